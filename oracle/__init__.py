@@ -1,0 +1,44 @@
+"""FP64 CPU oracle for constrained-least-squares radio image formation.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously correct
+NumPy (complex128 / float64) implementation of the method of Mouri
+Sardarabadi, Leshem and van der Veen, "Radio Astronomical Image Formation using
+Constrained Least Squares and Krylov Subspaces".  Only the test-suite, the
+smoke check and the benchmark's CPU-baseline leg may import it.  The HIP
+library never calls it and shares no code, table or constant with it.
+
+Modules
+-------
+imaging     steering vectors, the Khatri-Rao operators (correlation /
+            beamforming), matched-filter and MVDR dirty images, bounds and
+            detection threshold (Sec. II, Sec. IV-B, App. A)
+lsqr        Golub-Kahan bidiagonalisation with the LSQR updates (Sec. IV-A)
+active_set  the active-set solver of Table I with the detection threshold
+            (Sec. III)
+
+Pins (what the oracle is checked against, in tests/test_oracle_*.py): the
+Kronecker/Khatri-Rao identities of the Notation section against an explicitly
+built dense Psi, closed forms for a single source (MF and Sherman-Morrison
+MVDR), the MF >= MVDR ordering, the Jacobi-preconditioned-WLS identity for the
+MVDR image (Sec. II-C), LSQR against SVD minimum-norm least squares,
+the active-set solution against SciPy's BVLS and brute-force enumeration
+(objective and KKT conditions, eqs. gradFcond/etaL/etaU), exact recovery of
+on-grid sources from an exact covariance, and invariances (scale, antenna
+permutation, array translation, mirror).  The thresholded path with
+kappa_d > 0 beyond those pins is defined by this oracle ("parity unpinned" for
+the exact add/drop sequence).
+"""
+
+from .imaging import (  # noqa: F401
+    pixel_directions,
+    steering,
+    forward,
+    adjoint,
+    mf_image,
+    mvdr_inverse_power,
+    upper_bound,
+    detection_threshold,
+    NotPositiveDefinite,
+)
+from .lsqr import lsqr, LsqrResult  # noqa: F401
+from .active_set import solve, SolveResult, STATE_L, STATE_F, STATE_U  # noqa: F401

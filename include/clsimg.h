@@ -1,0 +1,180 @@
+/*
+ * clsimg.h - constrained least-squares radio image formation on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: A. Mouri Sardarabadi, A. Leshem, A.-J. van der Veen, "Radio
+ * Astronomical Image Formation using Constrained Least Squares and Krylov
+ * Subspaces".  One covariance snapshot (the paper's K = 1) per call.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Antenna p sits at (x_p, y_p) metres (planar array); `lambda` is the
+ *    wavelength in metres.  Pixel i = im*nl + il of the grid looks towards
+ *    direction cosines (l0 + il*dl, m0 + im*dm).
+ *  - Array response (Sec. II-A normalisation, Sec. III-E model with z = 0):
+ *        a_i[p] = P^-1/2 exp(-j 2 pi (x_p l_i + y_p m_i) / lambda).
+ *  - Covariances are P x P complex64 matrices, row-major, R[p*P + q] =
+ *    E{y_p conj(y_q)}; they must be Hermitian.  A transposed matrix mirrors
+ *    the image.
+ *  - Every large array is a DEVICE pointer on the context's device, owned by
+ *    the caller; it must stay valid until the work queued on `stream`
+ *    finishes.  Small descriptors (clsimg_array, clsimg_grid, clsimg_opts,
+ *    clsimg_stats and the positions they point to) are HOST memory, read or
+ *    written before the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is ordered on it.  Calls that return results to the host
+ *    (clsimg_solve's statistics, the active-set decisions) synchronise it.
+ *  - One context per host thread and stream: a context is not thread safe.
+ *  - Return value: CLSIMG_OK (0), a positive warning (results valid), or a
+ *    negative error (outputs not written).  No C++ exception crosses the ABI.
+ *  - Limits: 1 <= P <= CLSIMG_MAX_P, 1 <= nl*nm <= CLSIMG_MAX_Q.
+ */
+#ifndef CLSIMG_H
+#define CLSIMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLSIMG_MAX_P 288
+#define CLSIMG_MAX_Q (1 << 20)
+
+/* status codes */
+#define CLSIMG_OK 0
+#define CLSIMG_WMAXOUTER 1   /* active-set iteration limit reached; sigma is feasible   */
+#define CLSIMG_WITNLIM 2     /* some LSQR subproblem hit its iteration limit             */
+#define CLSIMG_WCYCLE 3      /* released pixel blocked again at zero step; state restored */
+#define CLSIMG_EINVAL (-1)   /* NULL pointer, bad size, bad grid or option                */
+#define CLSIMG_ENOTPD (-2)   /* covariance not positive definite or not finite           */
+#define CLSIMG_ENOMEM (-3)   /* workspace would exceed the context's HBM budget          */
+#define CLSIMG_EHIP (-4)     /* a HIP runtime call failed                                */
+
+/* bound kinds for clsimg_opts.bound */
+#define CLSIMG_BOUND_MVDR 0  /* gamma = C / (a^H R^-1 a) (+ kappa_b std), Sec. II-D  */
+#define CLSIMG_BOUND_MF 1    /* gamma = MF dirty image (+ kappa_b std), eq. mfupper  */
+#define CLSIMG_BOUND_NONE 2  /* gamma = +inf: lower bound only, eq. NNLS             */
+
+/* arithmetic of the Psi / Psi^H contractions */
+#define CLSIMG_FP32 0
+
+/* pixel states in clsimg_solve's `state` output */
+#define CLSIMG_STATE_L 0     /* sigma_i = 0        */
+#define CLSIMG_STATE_F 1     /* 0 < sigma_i < gamma_i (free)          */
+#define CLSIMG_STATE_U 2     /* sigma_i = gamma_i  */
+
+typedef struct clsimg_ctx clsimg_ctx;
+
+/* layout-compatible with torch.complex64 / std::complex<float> */
+typedef struct {
+  float re, im;
+} clsimg_c32;
+
+typedef struct {
+  int32_t P;              /* number of antennas                                */
+  const double* pos_xy;   /* HOST, P x 2 row-major (x_p, y_p), metres          */
+  double lambda;          /* wavelength, metres                                */
+} clsimg_array;
+
+typedef struct {
+  int32_t nl, nm;         /* pixels along l and m; Q = nl*nm                   */
+  double l0, dl, m0, dm;  /* first direction cosine and step along each axis   */
+} clsimg_grid;
+
+typedef struct {
+  int32_t bound;          /* CLSIMG_BOUND_*                          (MVDR)     */
+  double C;               /* MVDR bias factor, App. A gives N/(N-P)  (1.0)      */
+  double kappa_b;         /* bound inflation in std units, App. A    (0.0)      */
+  double kappa_d;         /* detection threshold in std units, Sec. III-C (6.0) */
+  int64_t nsamples;       /* N samples behind R, used by eps and kappa_b        */
+  double atol, btol;      /* LSQR tolerances                         (1e-6)     */
+  double conlim;          /* LSQR condition limit                    (1e8)      */
+  int32_t itnlim;         /* LSQR iterations per subproblem, -1 = 4|F|+100      */
+  int32_t max_outer;      /* subproblem solves, -1 = 4Q                         */
+  int32_t precision;      /* CLSIMG_FP32                                        */
+} clsimg_opts;
+
+typedef struct {
+  int32_t status;
+  int32_t outer_iters;    /* subproblem solves (Table I image index)            */
+  int32_t adds;           /* pixels released into the free set                  */
+  int32_t drops;          /* pixels blocked at a bound                          */
+  int32_t lsqr_iters_total;
+  int32_t lsqr_itnlim_hits;
+  int32_t nF, nU;         /* final set sizes                                    */
+  double rel_residual;    /* ||B0 - Psi sigma||_F / ||B0||_F                    */
+  double objective;       /* 1/2 ||B0 - Psi sigma||_F^2                         */
+  double min_margin_lambda; /* min |lambda_i + eps_i| / eps_i over detection tests */
+  double min_margin_z;      /* min over accepted subproblems of min(z, gamma-z)/gamma */
+  double psi_flops;         /* dense-count flops of every Psi / Psi^H applied: 8 P^2 per pixel
+                               and correlation term, + 8 P per beamformed pixel             */
+} clsimg_stats;
+
+/* Fill `opts` with the defaults listed above (nsamples = 0: must be set). */
+void clsimg_default_opts(clsimg_opts* opts);
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+ * workspace the context may allocate (0 = no cap).  The context owns that
+ * workspace and caches the steering tables of the last (array, grid). */
+int clsimg_create(clsimg_ctx** ctx, int32_t device, size_t hbm_budget_bytes);
+
+/* Release the context and its workspace (synchronises its device). */
+int clsimg_destroy(clsimg_ctx* ctx);
+
+/* Matched-filter dirty image, eq. mfdimg at K = 1:
+ *   mf[i] = a_i^H R a_i,  i = 0..Q-1.
+ * R: DEVICE complex64 P x P.  mf: DEVICE float[Q]. */
+int clsimg_dirty_image(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array,
+                       const clsimg_grid* grid, float* mf, void* stream);
+
+/* Upper bound gamma of the box constraint (eq. CLS):
+ *   MVDR (eq. wmvdr, Sec. II-D): h_i = a_i^H R^-1 a_i with R = L L^H factored in
+ *        FP64 on the device; gamma_i = C/h_i + kappa_b / (h_i sqrt(N-P-1));
+ *   MF:  gamma_i = mf_i (1 + kappa_b / sqrt(N))   (App. A variance, K = 1);
+ *   NONE: gamma_i = +inf.
+ * Fails with CLSIMG_ENOTPD when the Cholesky factorisation breaks down.
+ * R: DEVICE complex64 P x P.  gamma: DEVICE float[Q]. */
+int clsimg_mvdr_bound(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array,
+                      const clsimg_grid* grid, const clsimg_opts* opts, float* gamma,
+                      void* stream);
+
+/* Correlation (forward) operator of Sec. IV-B on a pixel subset S:
+ *   Y = sum_k v[k] a_{idx[k]} a_{idx[k]}^H     (= Psi_S v as a P x P matrix).
+ * idx: DEVICE int32[n] pixel indices in [0, Q) (NULL = pixels 0..n-1);
+ * v: DEVICE float[n]; Y: DEVICE complex64 P x P (overwritten; zero if n = 0). */
+int clsimg_forward(clsimg_ctx* ctx, const clsimg_array* array, const clsimg_grid* grid,
+                   const int32_t* idx, const float* v, int32_t n, clsimg_c32* Y, void* stream);
+
+/* Beamforming (adjoint) operator of Sec. IV-B on a pixel subset S:
+ *   g[k] = Re(a_{idx[k]}^H U a_{idx[k]})        (= Psi_S^H vect(U), real part).
+ * U: DEVICE complex64 P x P Hermitian; idx: DEVICE int32[n] in [0, Q)
+ * (NULL = pixels 0..n-1); g: DEVICE float[n]. */
+int clsimg_adjoint(clsimg_ctx* ctx, const clsimg_array* array, const clsimg_grid* grid,
+                   const clsimg_c32* U, const int32_t* idx, int32_t n, float* g, void* stream);
+
+/* Box-constrained LS image (eq. CLS with K = 1) by the active-set method of
+ * Sec. III-C / Table I, each equality-constrained subproblem (eqs.
+ * subproblemLS, bsubproblemLS) solved matrix-free by LSQR (Sec. IV).
+ *   data  B0 = R - diag(noise_diag)           (noise_diag NULL: no noise term)
+ *   bound gamma as clsimg_mvdr_bound; threshold eps_i = kappa_d mf_i / sqrt(N)
+ * R: DEVICE complex64 P x P.  noise_diag: DEVICE float[P] or NULL.
+ * sigma0 / state0: DEVICE float[Q] / uint8[Q] feasible starting image and its
+ *   sets (both NULL = start from sigma = 0, every pixel in L).
+ * sigma: DEVICE float[Q] out.  state: DEVICE uint8[Q] out (CLSIMG_STATE_*).
+ * mf, gamma: DEVICE float[Q] out, or NULL.  stats: HOST, always written.
+ * Synchronises `stream` (the active-set decisions are read on the host). */
+int clsimg_solve(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array,
+                 const clsimg_grid* grid, const float* noise_diag, const clsimg_opts* opts,
+                 const float* sigma0, const uint8_t* state0, float* sigma, uint8_t* state,
+                 float* mf, float* gamma, clsimg_stats* stats, void* stream);
+
+/* Static description of a status code. */
+const char* clsimg_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLSIMG_H */

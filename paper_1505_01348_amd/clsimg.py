@@ -1,0 +1,287 @@
+"""Python binding of the clsimg C ABI (include/clsimg.h).
+
+Argument marshalling only: every step of every call runs in the HIP library
+``libclsimg.so`` built next to this file.  PyTorch supplies device memory and
+the current HIP stream; nothing here computes on the host.  If the library is
+missing the import fails loudly (build it with ``python -m
+paper_1505_01348_amd.build``).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libclsimg.so")
+
+OK, WMAXOUTER, WITNLIM, WCYCLE = 0, 1, 2, 3
+EINVAL, ENOTPD, ENOMEM, EHIP = -1, -2, -3, -4
+BOUND_MVDR, BOUND_MF, BOUND_NONE = 0, 1, 2
+FP32 = 0
+STATE_L, STATE_F, STATE_U = 0, 1, 2
+MAX_P = 288
+
+EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
+            "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
+            "clsimg_strerror")
+
+
+class CArray(C.Structure):
+    _fields_ = [("P", C.c_int32), ("pos_xy", C.POINTER(C.c_double)), ("lam", C.c_double)]
+
+
+class CGrid(C.Structure):
+    _fields_ = [("nl", C.c_int32), ("nm", C.c_int32), ("l0", C.c_double), ("dl", C.c_double),
+                ("m0", C.c_double), ("dm", C.c_double)]
+
+
+class COpts(C.Structure):
+    _fields_ = [("bound", C.c_int32), ("C", C.c_double), ("kappa_b", C.c_double),
+                ("kappa_d", C.c_double), ("nsamples", C.c_int64), ("atol", C.c_double),
+                ("btol", C.c_double), ("conlim", C.c_double), ("itnlim", C.c_int32),
+                ("max_outer", C.c_int32), ("precision", C.c_int32)]
+
+
+class CStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer_iters", C.c_int32), ("adds", C.c_int32),
+                ("drops", C.c_int32), ("lsqr_iters_total", C.c_int32),
+                ("lsqr_itnlim_hits", C.c_int32), ("nF", C.c_int32), ("nU", C.c_int32),
+                ("rel_residual", C.c_double), ("objective", C.c_double),
+                ("min_margin_lambda", C.c_double), ("min_margin_z", C.c_double),
+                ("psi_flops", C.c_double)]
+
+
+class ClsimgError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libclsimg.so and declare its signatures; raises if it is absent."""
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run python -m paper_1505_01348_amd.build)")
+    lib = C.CDLL(path)
+    vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    lib.clsimg_default_opts.argtypes = [C.POINTER(COpts)]
+    lib.clsimg_default_opts.restype = None
+    lib.clsimg_create.argtypes = [C.POINTER(vp), i32, sz]
+    lib.clsimg_destroy.argtypes = [vp]
+    lib.clsimg_dirty_image.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp]
+    lib.clsimg_mvdr_bound.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), C.POINTER(COpts),
+                                      vp, vp]
+    lib.clsimg_forward.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp, i32, vp, vp]
+    lib.clsimg_adjoint.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp, i32, vp, vp]
+    lib.clsimg_solve.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, C.POINTER(COpts),
+                                 vp, vp, vp, vp, vp, vp, C.POINTER(CStats), vp]
+    lib.clsimg_strerror.argtypes = [C.c_int]
+    lib.clsimg_strerror.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("clsimg_default_opts", "clsimg_strerror"):
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def strerror(status: int) -> str:
+    return lib().clsimg_strerror(int(status)).decode()
+
+
+@dataclasses.dataclass
+class Options:
+    bound: int = BOUND_MVDR
+    C: float = 1.0
+    kappa_b: float = 0.0
+    kappa_d: float = 6.0
+    nsamples: int = 0
+    atol: float = 1e-6
+    btol: float = 1e-6
+    conlim: float = 1e8
+    itnlim: int = -1
+    max_outer: int = -1
+    precision: int = FP32
+
+    def to_c(self) -> COpts:
+        return COpts(self.bound, self.C, self.kappa_b, self.kappa_d, self.nsamples, self.atol,
+                     self.btol, self.conlim, self.itnlim, self.max_outer, self.precision)
+
+
+def default_options() -> Options:
+    o = COpts()
+    lib().clsimg_default_opts(C.byref(o))
+    return Options(o.bound, o.C, o.kappa_b, o.kappa_d, o.nsamples, o.atol, o.btol, o.conlim,
+                   o.itnlim, o.max_outer, o.precision)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, numel, name, device):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t
+
+
+class Geometry:
+    """Antenna positions (metres), wavelength and pixel grid of one problem."""
+
+    def __init__(self, pos_xy, lam, grid):
+        self.pos = np.ascontiguousarray(np.asarray(pos_xy, dtype=np.float64).reshape(-1, 2))
+        self.lam = float(lam)
+        nl, nm, l0, dl, m0, dm = grid
+        self.grid = (int(nl), int(nm), float(l0), float(dl), float(m0), float(dm))
+        self.c_array = CArray(self.pos.shape[0], self.pos.ctypes.data_as(C.POINTER(C.c_double)),
+                              self.lam)
+        self.c_grid = CGrid(*self.grid)
+
+    @property
+    def P(self):
+        return self.pos.shape[0]
+
+    @property
+    def Q(self):
+        return self.grid[0] * self.grid[1]
+
+
+class Context:
+    """One clsimg context on one device (not thread safe; one per stream)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self.device = int(device)
+        self._lib = lib()
+        h = C.c_void_p()
+        st = self._lib.clsimg_create(C.byref(h), self.device, int(hbm_budget))
+        if st != OK:
+            raise ClsimgError(st, "clsimg_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.clsimg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st, where, allow_warn=False):
+        if st < 0 or (st > 0 and not allow_warn):
+            raise ClsimgError(st, where)
+        return st
+
+    def dirty_image(self, R, geo: Geometry, mf=None):
+        dev = self.device
+        _need(R, torch.complex64, geo.P * geo.P, "R", dev)
+        mf = torch.empty(geo.Q, dtype=torch.float32, device=R.device) if mf is None else mf
+        _need(mf, torch.float32, geo.Q, "mf", dev)
+        self._check(self._lib.clsimg_dirty_image(self._h, _ptr(R), C.byref(geo.c_array),
+                                                 C.byref(geo.c_grid), _ptr(mf), _stream()),
+                    "clsimg_dirty_image")
+        return mf
+
+    def mvdr_bound(self, R, geo: Geometry, opts: Options | None = None, gamma=None):
+        dev = self.device
+        _need(R, torch.complex64, geo.P * geo.P, "R", dev)
+        opts = opts or default_options()
+        gamma = torch.empty(geo.Q, dtype=torch.float32, device=R.device) if gamma is None else gamma
+        _need(gamma, torch.float32, geo.Q, "gamma", dev)
+        co = opts.to_c()
+        self._check(self._lib.clsimg_mvdr_bound(self._h, _ptr(R), C.byref(geo.c_array),
+                                                C.byref(geo.c_grid), C.byref(co), _ptr(gamma),
+                                                _stream()), "clsimg_mvdr_bound")
+        return gamma
+
+    def forward(self, geo: Geometry, v, idx=None, Y=None):
+        dev = self.device
+        n = v.numel()
+        _need(v, torch.float32, None, "v", dev)
+        if idx is not None:
+            _need(idx, torch.int32, n, "idx", dev)
+        Y = torch.empty((geo.P, geo.P), dtype=torch.complex64, device=v.device) if Y is None else Y
+        _need(Y, torch.complex64, geo.P * geo.P, "Y", dev)
+        self._check(self._lib.clsimg_forward(self._h, C.byref(geo.c_array), C.byref(geo.c_grid),
+                                             _ptr(idx), _ptr(v), n, _ptr(Y), _stream()),
+                    "clsimg_forward")
+        return Y
+
+    def adjoint(self, geo: Geometry, U, idx=None, n=None, g=None):
+        dev = self.device
+        _need(U, torch.complex64, geo.P * geo.P, "U", dev)
+        if idx is not None:
+            _need(idx, torch.int32, None, "idx", dev)
+            n = idx.numel()
+        elif n is None:
+            n = geo.Q
+        g = torch.empty(n, dtype=torch.float32, device=U.device) if g is None else g
+        _need(g, torch.float32, n, "g", dev)
+        self._check(self._lib.clsimg_adjoint(self._h, C.byref(geo.c_array), C.byref(geo.c_grid),
+                                             _ptr(U), _ptr(idx), n, _ptr(g), _stream()),
+                    "clsimg_adjoint")
+        return g
+
+    def solve(self, R, geo: Geometry, opts: Options, noise_diag=None, sigma0=None, state0=None,
+              sigma=None, state=None, mf=None, gamma=None):
+        """Returns (sigma, state, mf, gamma, stats dict); warnings are in stats['status']."""
+        dev = self.device
+        _need(R, torch.complex64, geo.P * geo.P, "R", dev)
+        Q = geo.Q
+        if noise_diag is not None:
+            _need(noise_diag, torch.float32, geo.P, "noise_diag", dev)
+        if sigma0 is not None or state0 is not None:
+            _need(sigma0, torch.float32, Q, "sigma0", dev)
+            _need(state0, torch.uint8, Q, "state0", dev)
+        mk = lambda t, dt: torch.empty(Q, dtype=dt, device=R.device) if t is None else t  # noqa: E731
+        sigma, state = mk(sigma, torch.float32), mk(state, torch.uint8)
+        mf, gamma = mk(mf, torch.float32), mk(gamma, torch.float32)
+        for t, dt, name in ((sigma, torch.float32, "sigma"), (state, torch.uint8, "state"),
+                            (mf, torch.float32, "mf"), (gamma, torch.float32, "gamma")):
+            _need(t, dt, Q, name, dev)
+        co = opts.to_c()
+        stats = CStats()
+        st = self._lib.clsimg_solve(self._h, _ptr(R), C.byref(geo.c_array), C.byref(geo.c_grid),
+                                    _ptr(noise_diag), C.byref(co), _ptr(sigma0), _ptr(state0),
+                                    _ptr(sigma), _ptr(state), _ptr(mf), _ptr(gamma), C.byref(stats),
+                                    _stream())
+        self._check(st, "clsimg_solve", allow_warn=True)
+        out = {f: getattr(stats, f) for f, _ in CStats._fields_}
+        return sigma, state, mf, gamma, out
+
+
+def epsilon_scale(kappa_d: float, nsamples: int) -> float:
+    """Factor turning the MF image into the detection threshold (App. A, K = 1)."""
+    return kappa_d / math.sqrt(nsamples)

@@ -1,0 +1,642 @@
+// C ABI of the clsimg library: context, workspace, steering tables and the
+// host driver of the active-set solve (Table I of the paper) whose every
+// arithmetic step runs in the kernels of ops.hip / solve.hip.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <limits>
+#include <vector>
+
+#include "../../include/clsimg.h"
+#include "kernels.h"
+
+using namespace clsimg;
+
+namespace {
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct TableKey {
+  int P = -1;
+  double lambda = 0.0;
+  std::vector<double> pos;
+  clsimg_grid grid{};
+};
+
+}  // namespace
+
+struct clsimg_ctx {
+  int device = 0;
+  size_t budget = 0;  // 0 = unlimited
+  size_t used = 0;
+  // steering tables of the last (array, grid)
+  TableKey key;
+  bool tables_valid = false;
+  DevBuf El, Em, pos_d;
+  double* h_stage = nullptr;  // pinned staging for the antenna positions
+  size_t h_stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
+  // workspace
+  DevBuf frag_r, frag_u, part, beta_part, alpha_part, keys;
+  DevBuf B0, Bb, u, E, Rinv, W, Li;
+  DevBuf Flist, Ulist, v, w, x, eps, mf, gamma;
+  DevBuf lsqr, dec, status;
+  SolveDecision* h_dec = nullptr;
+  LsqrState* h_lsqr = nullptr;
+  int* h_status = nullptr;
+  double* h_norms = nullptr;
+  bool trace = false;  // CLSIMG_TRACE=1: one line per active-set step on stderr
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+#define HIP_TRY(expr)                               \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return CLSIMG_EHIP;       \
+  } while (0)
+
+#define ST_TRY(expr)                  \
+  do {                                \
+    int s_ = (expr);                  \
+    if (s_ != CLSIMG_OK) return s_;   \
+  } while (0)
+
+int ensure(clsimg_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (b.bytes >= bytes) return CLSIMG_OK;
+  if (c->budget && c->used - b.bytes + bytes > c->budget) return CLSIMG_ENOMEM;
+  if (b.ptr) {
+    (void)hipFree(b.ptr);
+    c->used -= b.bytes;
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.ptr, bytes) != hipSuccess) return CLSIMG_ENOMEM;
+  b.bytes = bytes;
+  c->used += bytes;
+  return CLSIMG_OK;
+}
+
+template <class T>
+T* P_(DevBuf& b) {
+  return reinterpret_cast<T*>(b.ptr);
+}
+
+int check_geometry(const clsimg_array* a, const clsimg_grid* g) {
+  if (!a || !g || !a->pos_xy) return CLSIMG_EINVAL;
+  if (a->P < 1 || a->P > CLSIMG_MAX_P) return CLSIMG_EINVAL;
+  if (!(a->lambda > 0.0) || !isfinite(a->lambda)) return CLSIMG_EINVAL;
+  if (g->nl < 1 || g->nm < 1) return CLSIMG_EINVAL;
+  if ((int64_t)g->nl * g->nm > CLSIMG_MAX_Q) return CLSIMG_EINVAL;
+  if (!isfinite(g->l0) || !isfinite(g->dl) || !isfinite(g->m0) || !isfinite(g->dm))
+    return CLSIMG_EINVAL;
+  for (int i = 0; i < 2 * a->P; ++i)
+    if (!isfinite(a->pos_xy[i])) return CLSIMG_EINVAL;
+  return CLSIMG_OK;
+}
+
+// Steering tables of (array, grid), rebuilt on the device only when either
+// changes: positions go up through a pinned buffer, the FP64 phases and their
+// complex64 rounding are computed by tables_kernel.
+int ensure_tables(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, hipStream_t st) {
+  const int P = a->P, Pp = pad_p(P);
+  if (c->tables_valid && c->key.P == P && c->key.lambda == a->lambda &&
+      memcmp(&c->key.grid, g, sizeof(*g)) == 0 &&
+      memcmp(c->key.pos.data(), a->pos_xy, sizeof(double) * 2 * P) == 0)
+    return CLSIMG_OK;
+  ST_TRY(ensure(c, c->El, (size_t)Pp * g->nl * sizeof(float2)));
+  ST_TRY(ensure(c, c->Em, (size_t)Pp * g->nm * sizeof(float2)));
+  ST_TRY(ensure(c, c->pos_d, (size_t)2 * CLSIMG_MAX_P * sizeof(double)));
+  if (!c->h_stage) {
+    HIP_TRY(hipHostMalloc((void**)&c->h_stage, 2 * CLSIMG_MAX_P * sizeof(double), hipHostMallocDefault));
+  } else {
+    HIP_TRY(hipEventSynchronize(c->stage_done));  // the previous upload has left the buffer
+  }
+  memcpy(c->h_stage, a->pos_xy, sizeof(double) * 2 * P);
+  HIP_TRY(hipMemcpyAsync(c->pos_d.ptr, c->h_stage, sizeof(double) * 2 * P, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(c->stage_done, st));
+  HIP_TRY(launch_tables(P_<const double>(c->pos_d), P, a->lambda, g->nl, g->nm, g->l0, g->dl, g->m0,
+                        g->dm, P_<float2>(c->El), P_<float2>(c->Em), st));
+  c->key.P = P;
+  c->key.lambda = a->lambda;
+  c->key.grid = *g;
+  c->key.pos.assign(a->pos_xy, a->pos_xy + 2 * P);
+  c->tables_valid = true;
+  return CLSIMG_OK;
+}
+
+Tables tables_of(clsimg_ctx* c, const clsimg_grid* g, int P) {
+  Tables t;
+  t.El = P_<const float2>(c->El);
+  t.Em = P_<const float2>(c->Em);
+  t.nl = g->nl;
+  t.nm = g->nm;
+  t.Pp = pad_p(P);
+  t.Q = g->nl * g->nm;
+  return t;
+}
+
+AdjParams adj_params(clsimg_ctx* c, const clsimg_grid* g, int P, const float* frag, const int* idx,
+                     int n, const int* stop, const float2* U = nullptr) {
+  AdjParams pr;
+  pr.frag = frag;
+  pr.U = U;
+  pr.P = P;
+  pr.MT = pad_p(P) / 8;
+  pr.KS = pad_p(P) / 2;
+  pr.tab = tables_of(c, g, P);
+  pr.idx = idx;
+  pr.n = n;
+  pr.stop_flag = stop;
+  return pr;
+}
+
+size_t part_floats_max(int P) {
+  const int MT = pad_p(P) / 8;
+  const int tw = MT <= 3 ? 3 : 6;
+  const int nb = (MT + tw - 1) / tw;
+  int waves = 512 / (nb * nb);
+  if (waves < 1) waves = 1;
+  const int nc = std::min(256, waves + 2);
+  return (size_t)nc * MT * MT * 256;
+}
+
+int ntiles_adj(int P, int n) {
+  const int T = adjoint_tile_width(pad_p(P) / 8);
+  return (n + T - 1) / T;
+}
+
+// Common workspace for every operation on a problem of size (P, Q).
+int ensure_workspace(clsimg_ctx* c, int P, int Q) {
+  const int Pp = pad_p(P);
+  const size_t fr = (size_t)4 * Pp * Pp * sizeof(float);
+  const size_t cx = (size_t)P * P * sizeof(float2);
+  ST_TRY(ensure(c, c->frag_r, fr));
+  ST_TRY(ensure(c, c->frag_u, fr));
+  ST_TRY(ensure(c, c->part, part_floats_max(P) * sizeof(float)));
+  ST_TRY(ensure(c, c->beta_part, (size_t)reduce_blocks(P) * sizeof(double)));
+  ST_TRY(ensure(c, c->alpha_part, (size_t)(ntiles_adj(P, Q) + 1) * sizeof(double)));
+  ST_TRY(ensure(c, c->keys, (size_t)(ntiles_adj(P, Q) + 1) * sizeof(uint64_t)));
+  ST_TRY(ensure(c, c->B0, cx));
+  ST_TRY(ensure(c, c->Bb, cx));
+  ST_TRY(ensure(c, c->u, cx));
+  ST_TRY(ensure(c, c->E, cx));
+  ST_TRY(ensure(c, c->Rinv, cx));
+  ST_TRY(ensure(c, c->W, (size_t)P * P * sizeof(double2)));
+  ST_TRY(ensure(c, c->Li, (size_t)P * P * sizeof(double2)));
+  ST_TRY(ensure(c, c->lsqr, sizeof(LsqrState)));
+  ST_TRY(ensure(c, c->dec, sizeof(SolveDecision)));
+  ST_TRY(ensure(c, c->status, 4 * sizeof(int)));
+  return CLSIMG_OK;
+}
+
+// Psi_S v as the complex P x P matrix out = cK * K + cB * B (see RedParams).
+int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const float* vals,
+              int gather, int n, float2* out, const float2* B, float cK, float cB,
+              const LsqrState* lsqr, float* frag, double* norm_part, const int* stop,
+              hipStream_t st) {
+  int chw = 8, nchunks = 0, nbm = 1;
+  forward_plan(P, n, &chw, &nchunks, &nbm);
+  const int MT = pad_p(P) / 8;
+  if ((size_t)nchunks * MT * MT * 256 > part_floats_max(P)) return CLSIMG_EINVAL;
+  if (n > 0) {
+    FwdParams f;
+    f.tab = tables_of(c, g, P);
+    f.MT = MT;
+    f.idx = idx;
+    f.vals = vals;
+    f.gather = gather;
+    f.n = n;
+    f.chw = chw;
+    f.nbm = nbm;
+    f.nbn = nbm;
+    f.part = P_<float>(c->part);
+    f.stop_flag = stop;
+    HIP_TRY(launch_forward(f, st));
+  }
+  RedParams r;
+  r.part = P_<const float>(c->part);
+  r.nchunks = n > 0 ? nchunks : 0;
+  r.MT = MT;
+  r.P = P;
+  r.out = out;
+  r.B = B;
+  r.cK = cK;
+  r.cB = cB;
+  r.lsqr = lsqr;
+  r.frag = frag;
+  r.norm_part = norm_part;
+  r.stop_flag = stop;
+  HIP_TRY(launch_reduce(r, st));
+  return CLSIMG_OK;
+}
+
+int read_back(clsimg_ctx* c, void* host, const void* dev, size_t bytes, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return CLSIMG_OK;
+}
+
+double sum_host(const double* p, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += p[i];
+  return s;
+}
+
+// MVDR / MF / NONE upper bound into `gamma`; MF image into `mf` if given.
+int compute_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
+                  const clsimg_opts* o, float* gamma, hipStream_t st) {
+  const int P = a->P, Q = g->nl * g->nm;
+  const float2* Rf = reinterpret_cast<const float2*>(R);
+  if (o->bound == CLSIMG_BOUND_NONE) {
+    HIP_TRY(launch_fill(gamma, std::numeric_limits<float>::infinity(), Q, st));
+    return CLSIMG_OK;
+  }
+  if (o->bound == CLSIMG_BOUND_MF) {
+    const double scale = 1.0 + (o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)o->nsamples) : 0.0);
+    HIP_TRY(launch_adjoint_store(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), gamma,
+                                 (float)scale, st));
+    return CLSIMG_OK;
+  }
+  HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
+                              P_<int>(c->status), st));
+  ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
+  if (*c->h_status != 0) return CLSIMG_ENOTPD;
+  const double kb = o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1)) : 0.0;
+  HIP_TRY(launch_adjoint_mvdr(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, P_<const float2>(c->Rinv)),
+                              gamma, o->C, kb, st));
+  return CLSIMG_OK;
+}
+
+// Dense-count flops: a correlation over n pixels costs 8 P^2 n, a beamforming
+// over n pixels 8 P^2 n + 8 P n (the complex GEMM and the column dot).
+double corr_flops(int P, int n) { return 8.0 * P * P * n; }
+double beam_flops(int P, int n) { return 8.0 * P * P * n + 8.0 * P * n; }
+
+int check_opts(const clsimg_opts* o, int P) {
+  if (!o) return CLSIMG_EINVAL;
+  if (o->bound < CLSIMG_BOUND_MVDR || o->bound > CLSIMG_BOUND_NONE) return CLSIMG_EINVAL;
+  if (o->precision != CLSIMG_FP32) return CLSIMG_EINVAL;
+  if (o->bound == CLSIMG_BOUND_MVDR && !(o->C > 0.0)) return CLSIMG_EINVAL;
+  if (o->kappa_b != 0.0) {
+    if (o->bound == CLSIMG_BOUND_MVDR && o->nsamples <= P + 1) return CLSIMG_EINVAL;
+    if (o->bound == CLSIMG_BOUND_MF && o->nsamples <= 0) return CLSIMG_EINVAL;
+  }
+  if (!(o->kappa_d >= 0.0) || !(o->kappa_b >= 0.0)) return CLSIMG_EINVAL;
+  if (!(o->atol >= 0.0) || !(o->btol >= 0.0) || !(o->conlim > 0.0)) return CLSIMG_EINVAL;
+  return CLSIMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void clsimg_default_opts(clsimg_opts* o) {
+  if (!o) return;
+  o->bound = CLSIMG_BOUND_MVDR;
+  o->C = 1.0;
+  o->kappa_b = 0.0;
+  o->kappa_d = 6.0;
+  o->nsamples = 0;
+  o->atol = 1e-6;
+  o->btol = 1e-6;
+  o->conlim = 1e8;
+  o->itnlim = -1;
+  o->max_outer = -1;
+  o->precision = CLSIMG_FP32;
+}
+
+int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
+  if (!out) return CLSIMG_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CLSIMG_EINVAL;
+  DeviceGuard guard(device);
+  clsimg_ctx* c = new (std::nothrow) clsimg_ctx();
+  if (!c) return CLSIMG_ENOMEM;
+  c->device = device;
+  c->budget = budget;
+  const char* tr = getenv("CLSIMG_TRACE");
+  c->trace = tr && tr[0] == '1';
+  void* hp = nullptr;
+  const size_t hbytes = sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + 64 * sizeof(double);
+  if (hipHostMalloc(&hp, hbytes, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+    if (hp) (void)hipHostFree(hp);
+    delete c;
+    return CLSIMG_EHIP;
+  }
+  char* b = static_cast<char*>(hp);
+  c->h_dec = reinterpret_cast<SolveDecision*>(b);
+  c->h_lsqr = reinterpret_cast<LsqrState*>(b + sizeof(SolveDecision));
+  c->h_status = reinterpret_cast<int*>(b + sizeof(SolveDecision) + sizeof(LsqrState));
+  c->h_norms = reinterpret_cast<double*>(b + sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int));
+  *out = c;
+  return CLSIMG_OK;
+}
+
+int clsimg_destroy(clsimg_ctx* c) {
+  if (!c) return CLSIMG_EINVAL;
+  DeviceGuard guard(c->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->part,  &c->beta_part,
+                    &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
+                    &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
+                    &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
+                    &c->dec,  &c->status};
+  for (DevBuf* d : bufs)
+    if (d->ptr) (void)hipFree(d->ptr);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->h_dec) (void)hipHostFree(c->h_dec);
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  delete c;
+  return CLSIMG_OK;
+}
+
+const char* clsimg_strerror(int s) {
+  switch (s) {
+    case CLSIMG_OK: return "ok";
+    case CLSIMG_WMAXOUTER: return "active-set iteration limit reached";
+    case CLSIMG_WITNLIM: return "an LSQR subproblem reached its iteration limit";
+    case CLSIMG_WCYCLE: return "released pixel blocked again at zero step (cycle)";
+    case CLSIMG_EINVAL: return "invalid argument";
+    case CLSIMG_ENOTPD: return "covariance is not positive definite or not finite";
+    case CLSIMG_ENOMEM: return "workspace exceeds the HBM budget or allocation failed";
+    case CLSIMG_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int clsimg_dirty_image(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a,
+                       const clsimg_grid* g, float* mf, void* stream) {
+  if (!c || !R || !mf) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int P = a->P, Q = g->nl * g->nm;
+  ST_TRY(ensure_workspace(c, P, Q));
+  ST_TRY(ensure_tables(c, a, g, st));
+  HIP_TRY(launch_adjoint_mf(
+      adj_params(c, g, P, nullptr, nullptr, Q, nullptr, reinterpret_cast<const float2*>(R)), mf, nullptr,
+      0.f, st));
+  return CLSIMG_OK;
+}
+
+int clsimg_mvdr_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a,
+                      const clsimg_grid* g, const clsimg_opts* o, float* gamma, void* stream) {
+  if (!c || !R || !gamma) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  ST_TRY(check_opts(o, a->P));
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  ST_TRY(ensure_workspace(c, a->P, g->nl * g->nm));
+  ST_TRY(ensure_tables(c, a, g, st));
+  return compute_bound(c, R, a, g, o, gamma, st);
+}
+
+int clsimg_forward(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, const int32_t* idx,
+                   const float* v, int32_t n, clsimg_c32* Y, void* stream) {
+  if (!c || !Y || n < 0 || (n > 0 && !v)) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  if (!idx && n > g->nl * g->nm) return CLSIMG_EINVAL;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  ST_TRY(ensure_workspace(c, a->P, g->nl * g->nm));
+  ST_TRY(ensure_tables(c, a, g, st));
+  return correlate(c, g, a->P, idx, v, 0, n, reinterpret_cast<float2*>(Y), nullptr, 1.f, 0.f, nullptr,
+                   nullptr, nullptr, nullptr, st);
+}
+
+int clsimg_adjoint(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, const clsimg_c32* U,
+                   const int32_t* idx, int32_t n, float* out, void* stream) {
+  if (!c || !U || n < 0 || (n > 0 && !out)) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  if (!idx && n > g->nl * g->nm) return CLSIMG_EINVAL;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int P = a->P;
+  ST_TRY(ensure_workspace(c, P, std::max(n, g->nl * g->nm)));
+  ST_TRY(ensure_tables(c, a, g, st));
+  if (n == 0) return CLSIMG_OK;
+  HIP_TRY(launch_adjoint_store(
+      adj_params(c, g, P, nullptr, idx, n, nullptr, reinterpret_cast<const float2*>(U)), out, 1.f, st));
+  return CLSIMG_OK;
+}
+
+int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
+                 const float* noise_diag, const clsimg_opts* o, const float* sigma0,
+                 const uint8_t* state0, float* sigma, uint8_t* state, float* mf_out,
+                 float* gamma_out, clsimg_stats* stats, void* stream) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (!c || !R || !sigma || !state || !stats) return CLSIMG_EINVAL;
+  if ((sigma0 == nullptr) != (state0 == nullptr)) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  ST_TRY(check_opts(o, a->P));
+  if (o->nsamples <= 0 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int P = a->P, Q = g->nl * g->nm;
+  ST_TRY(ensure_workspace(c, P, Q));
+  ST_TRY(ensure(c, c->Flist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->Ulist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->v, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->w, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->x, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
+  if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
+  if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure_tables(c, a, g, st));
+  float* mf = mf_out ? mf_out : P_<float>(c->mf);
+  float* gamma = gamma_out ? gamma_out : P_<float>(c->gamma);
+  float* eps = P_<float>(c->eps);
+  const float2* Rf = reinterpret_cast<const float2*>(R);
+  float2* B0 = P_<float2>(c->B0);
+  float2* Bb = P_<float2>(c->Bb);
+  float2* u = P_<float2>(c->u);
+  float2* E = P_<float2>(c->E);
+  int* Flist = P_<int>(c->Flist);
+  int* Ulist = P_<int>(c->Ulist);
+  float* v = P_<float>(c->v);
+  float* w = P_<float>(c->w);
+  float* x = P_<float>(c->x);
+  float* frag_r = P_<float>(c->frag_r);
+  float* frag_u = P_<float>(c->frag_u);
+  double* beta_part = P_<double>(c->beta_part);
+  double* alpha_part = P_<double>(c->alpha_part);
+  uint64_t* keys = P_<uint64_t>(c->keys);
+  LsqrState* ls = P_<LsqrState>(c->lsqr);
+  SolveDecision* dec = P_<SolveDecision>(c->dec);
+  const int* lsqr_stop = &ls->done;
+  const int* grad_stop = &dec->grad_done;
+  const int nbeta = reduce_blocks(P);
+
+  double flops = beam_flops(P, Q) + (o->bound != CLSIMG_BOUND_NONE ? beam_flops(P, Q) : 0.0);
+  // bounds and threshold (Sec. II-D, App. A)
+  const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
+  HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, eps, eps_scale,
+                            st));
+  ST_TRY(compute_bound(c, R, a, g, o, gamma, st));
+  // data B0 = R - diag(noise), its norm, the starting image and sets
+  HIP_TRY(launch_sub_diag(Rf, noise_diag, P, B0, st));
+  ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, E, B0, 0.f, 1.f, nullptr, nullptr, beta_part,
+                   nullptr, st));
+  HIP_TRY(hipMemcpyAsync(c->h_norms, beta_part, nbeta * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(launch_init_state(sigma0, state0, sigma, state, Q, st));
+  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+  const double b0norm = sqrt(sum_host(c->h_norms, nbeta));
+  int nF = c->h_dec->nF, nU = c->h_dec->nU;
+
+  const int max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
+  int status = CLSIMG_OK;
+  int outer = 0, adds = 0, drops = 0, lsqr_total = 0, itnlim_hits = 0, last_added = -1;
+  bool need_solve = true;
+  float lam_min = 0.f, eps_min = 0.f;
+  int i_min = -1, st_min = 0;
+  double margin_lambda = INFINITY, margin_z = INFINITY;
+  int batch = 4;
+  const int ntiles_Q = ntiles_adj(P, Q);
+  for (;;) {
+    if (need_solve) {
+      if (outer >= max_outer) {
+        status = CLSIMG_WMAXOUTER;
+        break;
+      }
+      HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+      // b = B0 - Psi_U gamma_U  (eq. bsubproblemLS)
+      ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr,
+                       nullptr, st));
+      flops += corr_flops(P, nU);
+      const int nalpha = ntiles_adj(P, nF);
+      if (nF > 0) {
+        const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
+        // beta_1 u_1 = b ; alpha_1 v_1 = Psi_F^H u_1  (eqs. initbeta, initu)
+        ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, u, Bb, 0.f, 1.f, nullptr, frag_u, beta_part,
+                         nullptr, st));
+        HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, nullptr), v, beta_part,
+                                    nbeta, alpha_part, 1, st));
+        HIP_TRY(launch_lsqr_init_scalars(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF,
+                                         o->atol, o->btol, o->conlim, itnlim, st));
+      }
+      for (;;) {
+        if (nF > 0) {
+          for (int it = 0; it < batch; ++it) {
+            // beta u <- Psi_F v - alpha u ; alpha v <- Psi_F^H u - beta v  (eq. lanczos)
+            ST_TRY(correlate(c, g, P, Flist, v, 0, nF, u, u, 1.f, 0.f, ls, frag_u, beta_part,
+                             lsqr_stop, st));
+            HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, lsqr_stop), v,
+                                        beta_part, nbeta, alpha_part, 0, st));
+            HIP_TRY(launch_lsqr_update(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF, st));
+          }
+        }
+        HIP_TRY(launch_step(ls, x, Flist, nF, sigma, gamma, state, dec, st));
+        // gradient on the active pixels, only after a feasible subproblem (eq. gls)
+        ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, Bb, 1.f, -1.f, nullptr, frag_r, nullptr,
+                         grad_stop, st));
+        HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys,
+                                      st));
+        HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
+        ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+        if (c->h_dec->lsqr_done) break;
+        batch = std::min(batch * 2, 64);
+      }
+      const SolveDecision d = *c->h_dec;
+      if (c->trace) {
+        ST_TRY(read_back(c, c->h_lsqr, ls, sizeof(LsqrState), st));
+        const LsqrState& L = *c->h_lsqr;
+        fprintf(stderr,
+                "clsimg: outer %d nF %d nU %d itn %d istop %d alpha %.3e beta %.3e rnorm %.3e "
+                "arnorm %.3e anorm %.3e acond %.3e xnorm %.3e bnorm %.3e feasible %d ib %d mu %.3e "
+                "i_min %d lam %.4e eps %.4e\n",
+                outer, nF, nU, L.itn, L.istop, L.alpha, L.beta, L.rnorm, L.arnorm, L.anorm, L.acond,
+                L.xnorm, L.bnorm, d.feasible, d.ib, (double)d.mu_max, d.i_min, (double)d.lam_min,
+                (double)d.eps_min);
+      }
+      batch = std::max(2, std::min(64, d.lsqr_itn + 1));
+      ++outer;
+      lsqr_total += d.lsqr_itn;
+      if (nF > 0) flops += beam_flops(P, nF) + d.lsqr_itn * (corr_flops(P, nF) + beam_flops(P, nF));
+      if (d.feasible) flops += corr_flops(P, nF) + beam_flops(P, Q);
+      if (nF > 0 && d.lsqr_istop == 7) ++itnlim_hits;
+      if (d.feasible) {
+        need_solve = false;
+        if (nF > 0) margin_z = std::min(margin_z, (double)d.margin_z);
+        if (d.i_min < 0) break;  // no active pixel left
+        lam_min = d.lam_min;
+        eps_min = d.eps_min;
+        i_min = d.i_min;
+        st_min = d.st_min;
+      } else {
+        ++drops;
+        --nF;
+        if (d.ib_to == CLSIMG_STATE_U) ++nU;
+        need_solve = true;
+        if (d.ib == last_added && d.mu_max == 0.0f) {
+          status = CLSIMG_WCYCLE;
+          break;
+        }
+      }
+      last_added = -1;
+    } else {
+      if (eps_min > 0.f)
+        margin_lambda = std::min(margin_lambda, fabs((double)lam_min + eps_min) / eps_min);
+      if (lam_min < -eps_min) {
+        HIP_TRY(launch_set_state(state, i_min, (uint8_t)CLSIMG_STATE_F, st));
+        ++adds;
+        ++nF;
+        if (st_min == CLSIMG_STATE_U) --nU;
+        last_added = i_min;
+        need_solve = true;
+      } else {
+        break;
+      }
+    }
+  }
+  if (status == CLSIMG_OK && itnlim_hits) status = CLSIMG_WITNLIM;
+  // final residual ||B0 - Psi sigma||_F
+  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+  nF = c->h_dec->nF;
+  nU = c->h_dec->nU;
+  ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr, nullptr,
+                   st));
+  ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, Bb, 1.f, -1.f, nullptr, nullptr, beta_part,
+                   nullptr, st));
+  ST_TRY(read_back(c, c->h_norms, beta_part, nbeta * sizeof(double), st));
+  const double rn = sqrt(sum_host(c->h_norms, nbeta));
+  stats->status = status;
+  stats->outer_iters = outer;
+  stats->adds = adds;
+  stats->drops = drops;
+  stats->lsqr_iters_total = lsqr_total;
+  stats->lsqr_itnlim_hits = itnlim_hits;
+  stats->nF = nF;
+  stats->nU = nU;
+  stats->rel_residual = b0norm > 0 ? rn / b0norm : 0.0;
+  stats->objective = 0.5 * rn * rn;
+  stats->min_margin_lambda = margin_lambda;
+  stats->min_margin_z = margin_z;
+  stats->psi_flops = flops + corr_flops(P, nU) + corr_flops(P, nF);
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Internal device/host helpers of the clsimg HIP library (gfx950 only).
+//
+// Data layout used by every kernel
+// --------------------------------
+//  * P is padded to Pp = ceil(P/8)*8.  Padding antennas have a zero response.
+//  * Complex steering vectors are handled in an interleaved real embedding:
+//    x_i = [Re a_i[0], Im a_i[0], Re a_i[1], Im a_i[1], ...]  (length 2Pp).
+//    For a Hermitian U, Re(a^H U a) = x^T Ut x with the real 2Pp x 2Pp matrix
+//        Ut[2p+s][2q+t] = { Re U_pq  (s,t)=(0,0),(1,1);  -Im U_pq (0,1);  Im U_pq (1,0) }
+//    and sum_i v_i a_i a_i^H is assembled from G = X diag(v) X^T as
+//        Re = G[2p][2q] + G[2p+1][2q+1],  Im = G[2p+1][2q] - G[2p][2q+1].
+//    Both products are plain real GEMMs with M = N or K = 2Pp (a multiple of
+//    16), which run on the fp32 MFMA v_mfma_f32_16x16x4f32.
+//  * Steering tables (complex64, built in FP64 on the host):
+//        El[p*nl + il] = P^-1/2 exp(-j 2pi x_p l_il / lambda)
+//        Em[p*nm + im] =        exp(-j 2pi y_p m_im / lambda)
+//    so a_i[p] = El[p][il] * Em[p][im] for pixel i = im*nl + il: one complex
+//    multiply per entry, no transcendental in any kernel, ~1 ulp of fp32.
+//  * MFMA 16x16x4 f32 lane layout (lane l, c16 = l%16, q = l/16):
+//        A operand: A[c16][q];  B operand: B[q][c16];
+//        D (4 regs r): D[4q + r][c16].
+//  * "Fragment" order of Ut for the beamforming product Y = Ut X:
+//        frag[(mt*KS + kc)*64 + l] = Ut[16 mt + c16][4 kc + q],
+//    MT = 2Pp/16 row tiles, KS = 2Pp/4 k-steps, so each MFMA A operand is
+//    one contiguous 256-byte load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clsimg {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;  // every multi-wave kernel: 4 waves of 64
+
+__host__ __device__ inline int pad_p(int P) { return (P + 7) & ~7; }
+
+__device__ __forceinline__ v4f mfma16x16x4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Steering-table view shared by the operator kernels.
+struct Tables {
+  const float2* El;  // Pp x nl
+  const float2* Em;  // Pp x nm
+  int nl, nm, Pp, Q;
+  __device__ __forceinline__ float2 a(int p, int il, int im) const {
+    return cmul(El[p * nl + il], Em[p * nm + im]);
+  }
+};
+
+// Monotone float -> uint32 map so that unsigned comparison orders floats;
+// NaN sorts above +inf.
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if (f != f) return 0xFFFFFFFFu;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float from_ordered_bits(uint32_t u) {
+  uint32_t v = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+  float f;
+  __builtin_memcpy(&f, &v, 4);
+  return f;
+}
+
+// Wave-level (64 lanes) reductions.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    uint64_t w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// Block-level reductions through an LDS scratch of NW slots (one per wave);
+// every thread gets the result.  The scratch is passed as an array reference
+// so that its size is known: slots beyond NW are never touched.
+template <int NW>
+__device__ inline double block_sum_d(double v, double (&sh)[NW]) {
+  v = wave_sum_d(v);
+  const int w = threadIdx.x >> 6;
+  const int nw = min((int)(blockDim.x >> 6), NW);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0 && w < NW) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  return s;
+}
+template <int NW>
+__device__ inline uint64_t block_min_u64(uint64_t v, uint64_t (&sh)[NW]) {
+  v = wave_min_u64(v);
+  const int w = threadIdx.x >> 6;
+  const int nw = min((int)(blockDim.x >> 6), NW);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0 && w < NW) sh[w] = v;
+  __syncthreads();
+  uint64_t m = ~0ull;
+  for (int i = 0; i < nw; ++i) m = sh[i] < m ? sh[i] : m;
+  return m;
+}
+
+}  // namespace clsimg

@@ -1,0 +1,189 @@
+// Parameter blocks, epilogues and host launchers of the clsimg kernels.
+#pragma once
+
+#include "common.h"
+
+namespace clsimg {
+
+// Device-resident LSQR scalars (FP64), Sec. IV-A with the LSQR updates.
+struct LsqrState {
+  double alpha, beta;        // current alpha_i, beta_i
+  double rhobar, phibar;     // rotation state
+  double bnorm, anorm2, ddnorm;
+  double rnorm, arnorm, anorm, acond, xnorm;
+  double atol, btol, conlim;
+  int itn, itnlim, istop, done;
+};
+
+struct AdjParams {
+  const float* frag;  // Ut fragments, 4 Pp^2 floats (used when U is NULL)
+  const float2* U;    // or: complex P x P matrix, staged into fragments by the kernel
+  int P, MT, KS;
+  Tables tab;
+  const int* idx;     // output column k looks at pixel idx[k] (NULL: pixel k)
+  int n;
+  const int* stop_flag;
+};
+
+struct FwdParams {
+  Tables tab;
+  int MT;
+  const int* idx;     // k-th term uses pixel idx[k] (NULL: pixel k)
+  const float* vals;  // weight of the k-th term: gather ? vals[pixel] : vals[k]
+  int gather;
+  int n;
+  int chw;            // pixels per wave (multiple of 4)
+  int nbm, nbn;       // output block grid
+  float* part;
+  const int* stop_flag;
+};
+
+struct RedParams {
+  const float* part;
+  int nchunks, MT, P;
+  float2* out;
+  const float2* B;
+  float cK, cB;
+  const LsqrState* lsqr;  // if set: cB = -alpha/beta
+  float* frag;            // optional Ut fragments of out
+  double* norm_part;      // optional per-block sum |out|^2
+  const int* stop_flag;
+};
+
+// ---- adjoint epilogues: called by every thread of the block once per tile --
+struct EpiStore {
+  float* out;
+  float scale;
+  __device__ void operator()(int, int col, int, float g, bool ok) const {
+    if (ok) out[col] = g * scale;
+  }
+};
+
+struct EpiMF {
+  float* mf;
+  float* eps;
+  float eps_scale;
+  __device__ void operator()(int, int col, int, float g, bool ok) const {
+    if (ok) {
+      mf[col] = g;
+      if (eps) eps[col] = g * eps_scale;
+    }
+  }
+};
+
+struct EpiMVDR {
+  float* gamma;
+  double C, kb_coef;
+  __device__ void operator()(int, int col, int, float g, bool ok) const {
+    if (ok) {
+      const double h = (double)g;
+      gamma[col] = (float)(C / h + kb_coef / h);
+    }
+  }
+};
+
+// Lagrange multipliers of the active pixels (eqs. etaL / etaU) and a per-tile
+// argmin key (ordered value << 32 | pixel): ties go to the lowest pixel.
+struct EpiLambda {
+  const uint8_t* state;
+  uint64_t* part;
+  __device__ void operator()(int tile, int, int pix, float g, bool ok) const {
+    __shared__ uint64_t sh[8];
+    uint64_t key = ~0ull;
+    if (ok) {
+      const uint8_t s = state[pix];
+      if (s != 1) {
+        const float lam = (s == 0) ? g : -g;
+        key = ((uint64_t)ordered_bits(lam) << 32) | (uint32_t)pix;
+      }
+    }
+    key = block_min_u64(key, sh);
+    if (threadIdx.x == 0) part[tile] = key;
+  }
+};
+
+// LSQR: v <- Psi_F^H u / beta - beta v   (or Psi_F^H u / beta at the start),
+// with u held unnormalised; per-tile partial sums of v^2.
+struct EpiLsqrV {
+  float* v;
+  const double* beta_part;
+  int nbeta;
+  double* alpha_part;
+  int init;
+  __device__ void operator()(int tile, int col, int, float g, bool ok) const {
+    __shared__ double sh[8];
+    __shared__ double sbeta;
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int i = 0; i < nbeta; ++i) s += beta_part[i];
+      sbeta = sqrt(s);
+    }
+    __syncthreads();
+    const double beta = sbeta;
+    double vr2 = 0.0;
+    if (ok) {
+      double vr = beta > 0.0 ? (double)g / beta : 0.0;
+      if (!init) vr -= beta * (double)v[col];
+      const float vf = (float)vr;
+      v[col] = vf;
+      vr2 = (double)vf * vf;
+    }
+    const double tot = block_sum_d(vr2, sh);
+    if (threadIdx.x == 0) alpha_part[tile] = tot;
+  }
+};
+
+// ---- launchers (ops.hip) ----
+int adjoint_tile_width(int MT);
+hipError_t launch_adjoint_store(const AdjParams& pr, float* out, float scale, hipStream_t st);
+hipError_t launch_adjoint_mf(const AdjParams& pr, float* mf, float* eps, float eps_scale,
+                             hipStream_t st);
+hipError_t launch_adjoint_mvdr(const AdjParams& pr, float* gamma, double C, double kb_coef,
+                               hipStream_t st);
+hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint64_t* part,
+                                 hipStream_t st);
+hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
+                               double* alpha_part, int init, hipStream_t st);
+void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm);
+hipError_t launch_forward(const FwdParams& pr, hipStream_t st);
+int reduce_blocks(int P);
+hipError_t launch_reduce(const RedParams& pr, hipStream_t st);
+hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, float2* Rinv,
+                               int* status, hipStream_t st);
+hipError_t launch_tables(const double* pos, int P, double lambda, int nl, int nm, double l0,
+                         double dl, double m0, double dm, float2* El, float2* Em, hipStream_t st);
+hipError_t launch_sub_diag(const float2* R, const float* noise, int P, float2* B0, hipStream_t st);
+hipError_t launch_fill(float* x, float v, int n, hipStream_t st);
+
+// ---- active-set / LSQR control kernels (solve.hip) ----
+struct SolveDecision {
+  int lsqr_done, lsqr_itn, lsqr_istop;
+  int feasible;          // subproblem solution inside the box
+  int ib, ib_to;         // blocking pixel and its new state (infeasible step)
+  float mu_max;
+  float margin_z;        // min over F of min(z, gamma - z)/gamma (feasible only)
+  int nF, nU;            // set sizes after the step
+  int i_min;             // most negative multiplier (feasible only; -1: none)
+  int st_min;            // set of i_min (0 = L, 2 = U)
+  float lam_min, eps_min;
+  int grad_done;
+};
+
+hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec,
+                          hipStream_t st);
+hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int nbeta,
+                                    const double* alpha_part, int nalpha, float* v, float* w,
+                                    float* x, int n, double atol, double btol, double conlim,
+                                    int itnlim, hipStream_t st);
+hipError_t launch_lsqr_update(LsqrState* s, const double* beta_part, int nbeta,
+                              const double* alpha_part, int nalpha, float* v, float* w, float* x,
+                              int n, hipStream_t st);
+hipError_t launch_step(const LsqrState* s, const float* x, const int* Flist, int nF, float* sigma,
+                       const float* gamma, uint8_t* state, SolveDecision* dec, hipStream_t st);
+hipError_t launch_argmin_final(const uint64_t* part, int nparts, const float* eps,
+                               const uint8_t* state, SolveDecision* dec, hipStream_t st);
+hipError_t launch_set_state(uint8_t* state, int i, uint8_t v, hipStream_t st);
+hipError_t launch_init_state(const float* sigma0, const uint8_t* state0, float* sigma,
+                             uint8_t* state, int Q, hipStream_t st);
+
+}  // namespace clsimg

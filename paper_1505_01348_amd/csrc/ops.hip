@@ -1,0 +1,541 @@
+// Khatri-Rao operator kernels: beamforming (Psi^H), correlation (Psi), their
+// reduction, the real-embedding fragments, and the FP64 Cholesky inverse.
+//
+// Sec. IV-B of the paper observes that Psi v is a correlation matrix
+// sum_i v_i a_i a_i^H and Psi^H u a set of beamformer outputs a_i^H U a_i, so
+// that the Khatri-Rao matrix never has to be stored.  Here both become dense
+// real GEMMs on the fp32 MFMA with the steering vectors generated on the fly
+// from FP64-built separable tables (layout notes in common.h).
+#include "kernels.h"
+
+namespace clsimg {
+
+// ---------------------------------------------------------------------------
+// Beamforming: g_k = x_k^T Ut x_k for the pixels of a list (or 0..n-1).
+// Y = Ut X on MFMA (A operand = Ut fragments staged through LDS, B operand =
+// steering entries generated in registers), then a column dot product with X.
+constexpr int kLdsFloats = 16384;  // 64 KiB of Ut fragments per workgroup
+
+template <int MTW, int NTW, int WM, class Epi>
+__global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi) {
+  if (pr.stop_flag && *pr.stop_flag) return;
+  constexpr int WN = 4 / WM;
+  constexpr int T = WN * NTW * 16;
+  static_assert(T <= kThreads, "tile wider than the block");
+  __shared__ float lds[kLdsFloats];
+  __shared__ float gsh[WM][T];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w % WM, wn = w / WM;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int MT = pr.MT, KS = pr.KS;
+  const int kch = min(KS, kLdsFloats / (MT * 64));
+  const bool resident = (kch == KS);
+  const int ntiles = (pr.n + T - 1) / T;
+  const Tables tab = pr.tab;
+  bool loaded = false;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int il[NTW], im[NTW];
+    bool valid[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      const int col = tile * T + (wn * NTW + t) * 16 + c16;
+      int pix = col < pr.n ? (pr.idx ? pr.idx[col] : col) : 0;
+      valid[t] = col < pr.n && (unsigned)pix < (unsigned)tab.Q;
+      if (!valid[t]) pix = 0;
+      il[t] = pix % tab.nl;
+      im[t] = pix / tab.nl;
+    }
+    v4f acc[MTW][NTW];
+#pragma unroll
+    for (int mi = 0; mi < MTW; ++mi)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) acc[mi][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int kc0 = 0; kc0 < KS; kc0 += kch) {
+      const int kn = min(kch, KS - kc0);
+      if (!(resident && loaded)) {
+        __syncthreads();
+        if (pr.U) {
+          // stage Ut straight from the complex matrix: Ut[2p+s][2q+u]
+          const int ne = MT * kn * 64;
+          for (int e = threadIdx.x; e < ne; e += kThreads) {
+            const int mt = e / (kn * 64);
+            const int r = e - mt * kn * 64;
+            const int j = r >> 6, l = r & 63;
+            const int row = 16 * mt + (l & 15), col = 4 * (kc0 + j) + (l >> 4);
+            const int p = row >> 1, s = row & 1, qq = col >> 1, u = col & 1;
+            const float2 v = (p < pr.P && qq < pr.P) ? pr.U[p * pr.P + qq] : make_float2(0.f, 0.f);
+            lds[(mt * kch + j) * 64 + l] = (s == u) ? v.x : (s == 0 ? -v.y : v.y);
+          }
+        } else {
+          const int n4 = MT * kn * 16;
+          for (int e = threadIdx.x; e < n4; e += kThreads) {
+            const int mt = e / (kn * 16);
+            const int r = e - mt * kn * 16;
+            const int j = r >> 4, l4 = r & 15;
+            const float4 val = *reinterpret_cast<const float4*>(
+                pr.frag + ((size_t)(mt * KS + kc0 + j) * 64 + l4 * 4));
+            *reinterpret_cast<float4*>(lds + ((mt * kch + j) * 64 + l4 * 4)) = val;
+          }
+        }
+        __syncthreads();
+        loaded = true;
+      }
+      for (int j = 0; j < kn; ++j) {
+        const int p = 2 * (kc0 + j) + (q >> 1);
+        float b[NTW];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+          const float2 a = tab.a(p, il[t], im[t]);
+          b[t] = valid[t] ? ((q & 1) ? a.y : a.x) : 0.f;
+        }
+#pragma unroll
+        for (int mi = 0; mi < MTW; ++mi) {
+          const int mt = wm * MTW + mi;
+          if (mt < MT) {
+            const float av = lds[(mt * kch + j) * 64 + lane];
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) acc[mi][t] = mfma16x16x4(av, b[t], acc[mi][t]);
+          }
+        }
+      }
+    }
+    // column dot product: rows 16mt + 4q + r hold antenna 8mt + 2q + r/2, part r%2
+    float gp[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) gp[t] = 0.f;
+#pragma unroll
+    for (int mi = 0; mi < MTW; ++mi) {
+      const int mt = wm * MTW + mi;
+      if (mt < MT) {
+        const int p0 = 8 * mt + 2 * q;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+          const float2 a0 = tab.a(p0, il[t], im[t]);
+          const float2 a1 = tab.a(p0 + 1, il[t], im[t]);
+          gp[t] += a0.x * acc[mi][t][0] + a0.y * acc[mi][t][1] + a1.x * acc[mi][t][2] +
+                   a1.y * acc[mi][t][3];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      gp[t] += __shfl_xor(gp[t], 16, 64);
+      gp[t] += __shfl_xor(gp[t], 32, 64);
+    }
+    __syncthreads();
+    if (q == 0) {
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) gsh[wm][(wn * NTW + t) * 16 + c16] = gp[t];
+    }
+    __syncthreads();
+    const int c = threadIdx.x;
+    const int col = tile * T + c;
+    float g = 0.f;
+    bool ok = false;
+    int pix = 0;
+    if (c < T) {
+#pragma unroll
+      for (int k = 0; k < WM; ++k) g += gsh[k][c];
+      ok = col < pr.n;
+      if (ok) {
+        pix = pr.idx ? pr.idx[col] : col;
+        if ((unsigned)pix >= (unsigned)tab.Q) {  // invalid pixel index: NaN output
+          pix = 0;
+          g = __builtin_nanf("");
+        }
+      }
+    }
+    epi(tile, col, pix, g, ok);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Correlation: partial G = X_S diag(v) X_S^T over a chunk of pixels per wave.
+// Partial tile layout: part[((chunk*MT + mt)*MT + nt)*256 + lane*4 + r]
+//                      = G[16mt + 4q + r][16nt + c16].
+template <int MTW, int NTW>
+__global__ __launch_bounds__(kThreads) void forward_kernel(FwdParams pr) {
+  if (pr.stop_flag && *pr.stop_flag) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int MT = pr.MT;
+  const int bm = blockIdx.y % pr.nbm, bn = blockIdx.y / pr.nbm;
+  const int chunk = blockIdx.x * 4 + w;
+  const int k0 = chunk * pr.chw;
+  if (k0 >= pr.n) return;
+  const int k1 = min(k0 + pr.chw, pr.n);
+  const Tables tab = pr.tab;
+  v4f acc[MTW][NTW];
+#pragma unroll
+  for (int mi = 0; mi < MTW; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NTW; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int part_bit = c16 & 1;
+  for (int kk = k0; kk < k1; kk += 4) {
+    const int k = kk + q;
+    int pix = k < k1 ? (pr.idx ? pr.idx[k] : k) : 0;
+    const bool ok = k < k1 && (unsigned)pix < (unsigned)tab.Q;  // invalid index: term dropped
+    if (!ok) pix = 0;
+    const float val = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
+    const int il = pix % tab.nl, im = pix / tab.nl;
+    float am[MTW], bv[NTW];
+#pragma unroll
+    for (int mi = 0; mi < MTW; ++mi) {
+      const int mt = bm * MTW + mi;
+      float x = 0.f;
+      if (mt < MT) {
+        const float2 a = tab.a(8 * mt + (c16 >> 1), il, im);
+        x = part_bit ? a.y : a.x;
+      }
+      am[mi] = ok ? x * val : 0.f;
+    }
+#pragma unroll
+    for (int ni = 0; ni < NTW; ++ni) {
+      const int nt = bn * NTW + ni;
+      float x = 0.f;
+      if (nt < MT) {
+        const float2 a = tab.a(8 * nt + (c16 >> 1), il, im);
+        x = part_bit ? a.y : a.x;
+      }
+      bv[ni] = ok ? x : 0.f;
+    }
+#pragma unroll
+    for (int mi = 0; mi < MTW; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NTW; ++ni) acc[mi][ni] = mfma16x16x4(am[mi], bv[ni], acc[mi][ni]);
+  }
+#pragma unroll
+  for (int mi = 0; mi < MTW; ++mi) {
+    const int mt = bm * MTW + mi;
+#pragma unroll
+    for (int ni = 0; ni < NTW; ++ni) {
+      const int nt = bn * NTW + ni;
+      if (mt < MT && nt < MT) {
+        float4 o = make_float4(acc[mi][ni][0], acc[mi][ni][1], acc[mi][ni][2], acc[mi][ni][3]);
+        *reinterpret_cast<float4*>(pr.part + (((size_t)chunk * MT + mt) * MT + nt) * 256 + lane * 4) = o;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Second stage of the correlation: fixed-order sum of the wave partials, then
+//   out = cK * K + cB * B  (complex P x P), optional Ut fragments of `out`,
+//   optional per-block sum |out|^2.  cB may come from the LSQR state
+//   (-alpha/beta) when `lsqr` is set.  out may alias B.
+__global__ __launch_bounds__(kThreads) void reduce_kernel(RedParams pr) {
+  __shared__ double sh[8];
+  if (pr.stop_flag && *pr.stop_flag) return;
+  const int MT = pr.MT, P = pr.P;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  const int tile = t >> 6, lane = t & 63;
+  const bool live = tile < MT * MT;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  int mt = 0, nt = 0;
+  if (live) {
+    mt = tile / MT;
+    nt = tile - mt * MT;
+    for (int c = 0; c < pr.nchunks; ++c) {
+      const float4 v =
+          *reinterpret_cast<const float4*>(pr.part + (((size_t)c * MT + mt) * MT + nt) * 256 + lane * 4);
+      s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    }
+  }
+  float4 o;
+  o.x = __shfl_xor(s.x, 1, 64);
+  o.y = __shfl_xor(s.y, 1, 64);
+  o.z = __shfl_xor(s.z, 1, 64);
+  o.w = __shfl_xor(s.w, 1, 64);
+  float cB = pr.cB;
+  if (pr.lsqr) cB = (float)(-pr.lsqr->alpha / pr.lsqr->beta);
+  double nrm = 0.0;
+  const int c16 = lane & 15, q = lane >> 4;
+  if (live && (c16 & 1) == 0) {
+    const int p0 = 8 * mt + 2 * q, qq = 8 * nt + (c16 >> 1);
+    const float2 K0 = make_float2(s.x + o.y, s.y - o.x);
+    const float2 K1 = make_float2(s.z + o.w, s.w - o.z);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int p = p0 + h;
+      const float2 K = h ? K1 : K0;
+      float2 r = make_float2(0.f, 0.f);
+      if (p < P && qq < P) {
+        r.x = pr.cK * K.x;
+        r.y = pr.cK * K.y;
+        if (pr.B) {
+          const float2 b = pr.B[p * P + qq];
+          r.x += cB * b.x;
+          r.y += cB * b.y;
+        }
+        pr.out[p * P + qq] = r;
+        nrm += (double)r.x * r.x + (double)r.y * r.y;
+      }
+      if (pr.frag) {
+        const int KS = MT * 4;
+        // Ut[2p+s][2qq+u]
+#pragma unroll
+        for (int su = 0; su < 4; ++su) {
+          const int s_ = su >> 1, u_ = su & 1;
+          const int row = 2 * p + s_, col = 2 * qq + u_;
+          const float v = (s_ == u_) ? r.x : (s_ == 0 ? -r.y : r.y);
+          const int fi = ((row >> 4) * KS + (col >> 2)) * 64 + (col & 3) * 16 + (row & 15);
+          pr.frag[fi] = v;
+        }
+      }
+    }
+  }
+  if (pr.norm_part) {
+    const double tot = block_sum_d(nrm, sh);
+    if (threadIdx.x == 0) pr.norm_part[blockIdx.x] = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Cholesky R = L L^H (lower triangle of R is read), then
+// R^-1 = L^-H L^-1 written as complex64.  One workgroup.  status: 0 ok,
+// 1 not positive definite, 2 non-finite entry.
+__global__ __launch_bounds__(1024) void chol_inverse_kernel(const float2* __restrict__ R, int P,
+                                                            double2* __restrict__ W,
+                                                            double2* __restrict__ Li,
+                                                            float2* __restrict__ Rinv,
+                                                            int* __restrict__ status) {
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int e = tid; e < P * P; e += nt) {
+    const float2 v = R[e];
+    if (!isfinite(v.x) || !isfinite(v.y)) bad = 2;
+    W[e] = make_double2((double)v.x, (double)v.y);
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) *status = bad;
+    return;
+  }
+  for (int j = 0; j < P; ++j) {
+    if (tid == 0) {
+      const double d = W[j * P + j].x;
+      if (!(d > 0.0)) bad = 1;
+      else W[j * P + j] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) *status = 1;
+      return;
+    }
+    const double ljj = W[j * P + j].x;
+    for (int i = j + 1 + tid; i < P; i += nt) {
+      const double2 v = W[i * P + j];
+      W[i * P + j] = make_double2(v.x / ljj, v.y / ljj);
+    }
+    __syncthreads();
+    const int m = P - j - 1;
+    for (int e = tid; e < m * m; e += nt) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) {
+        const double2 a = W[i * P + j], b = W[k * P + j];
+        // W[i][k] -= a * conj(b)
+        double2 w = W[i * P + k];
+        w.x -= a.x * b.x + a.y * b.y;
+        w.y -= a.y * b.x - a.x * b.y;
+        W[i * P + k] = w;
+      }
+    }
+    __syncthreads();
+  }
+  // Li = L^-1 by forward substitution, one column per thread
+  for (int c = tid; c < P; c += nt) {
+    for (int i = 0; i < c; ++i) Li[i * P + c] = make_double2(0.0, 0.0);
+    Li[c * P + c] = make_double2(1.0 / W[c * P + c].x, 0.0);
+    for (int i = c + 1; i < P; ++i) {
+      double sr = 0.0, si = 0.0;
+      for (int k = c; k < i; ++k) {
+        const double2 l = W[i * P + k], y = Li[k * P + c];
+        sr += l.x * y.x - l.y * y.y;
+        si += l.x * y.y + l.y * y.x;
+      }
+      const double lii = W[i * P + i].x;
+      Li[i * P + c] = make_double2(-sr / lii, -si / lii);
+    }
+  }
+  __syncthreads();
+  // R^-1[i][k] = sum_{m >= max(i,k)} conj(Li[m][i]) Li[m][k]
+  for (int e = tid; e < P * P; e += nt) {
+    const int i = e / P, k = e % P;
+    double sr = 0.0, si = 0.0;
+    for (int m = (i > k ? i : k); m < P; ++m) {
+      const double2 a = Li[m * P + i], b = Li[m * P + k];
+      sr += a.x * b.x + a.y * b.y;
+      si += a.x * b.y - a.y * b.x;
+    }
+    Rinv[e] = make_float2((float)sr, (float)si);
+  }
+  if (tid == 0) *status = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Separable steering tables, FP64 phases rounded once to complex64:
+//   El[p][il] = P^-1/2 exp(-j 2pi x_p l_il / lambda),  Em[p][im] = exp(-j 2pi y_p m_im / lambda),
+// zero rows for the padding antennas p >= P.
+__global__ void tables_kernel(const double* __restrict__ pos, int P, int Pp, double lambda, int nl,
+                              int nm, double l0, double dl, double m0, double dm,
+                              float2* __restrict__ El, float2* __restrict__ Em) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const double norm = 1.0 / sqrt((double)P);
+  const int nEl = Pp * nl, total = nEl + Pp * nm;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const bool is_l = t < nEl;
+    const int e = is_l ? t : t - nEl;
+    const int n = is_l ? nl : nm;
+    const int p = e / n, i = e - p * n;
+    float2 v = make_float2(0.f, 0.f);
+    if (p < P) {
+      const double dir = is_l ? l0 + i * dl : m0 + i * dm;
+      const double coord = pos[2 * p + (is_l ? 0 : 1)];
+      double sn, cs;
+      sincos(-two_pi * coord * dir / lambda, &sn, &cs);
+      const double sc = is_l ? norm : 1.0;
+      v = make_float2((float)(sc * cs), (float)(sc * sn));
+    }
+    if (is_l) El[e] = v;
+    else Em[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small elementwise helpers.
+__global__ void sub_diag_kernel(const float2* __restrict__ R, const float* __restrict__ noise, int P,
+                                float2* __restrict__ B0) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P * P; e += gridDim.x * blockDim.x) {
+    float2 v = R[e];
+    const int p = e / P, q = e - p * P;
+    if (noise && p == q) v.x -= noise[p];
+    B0[e] = v;
+  }
+}
+
+__global__ void fill_kernel(float* __restrict__ x, float v, int n) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) x[e] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+namespace {
+
+template <class Epi>
+hipError_t launch_adjoint_epi(const AdjParams& pr, const Epi& epi, hipStream_t st) {
+  if (pr.n <= 0) return hipSuccess;
+  int T;
+  auto go = [&](auto kern, int T_) {
+    const int ntiles = (pr.n + T_ - 1) / T_;
+    const int grid = ntiles < 4096 ? ntiles : 4096;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, pr, epi);
+    return hipGetLastError();
+  };
+  if (pr.MT <= 3) return go(adjoint_kernel<3, 1, 1, Epi>, T = 64);
+  if (pr.MT <= 6) return go(adjoint_kernel<6, 1, 1, Epi>, T = 64);
+  if (pr.MT <= 12) return go(adjoint_kernel<12, 1, 1, Epi>, T = 64);
+  if (pr.MT <= 24) return go(adjoint_kernel<6, 2, 4, Epi>, T = 32);
+  return go(adjoint_kernel<9, 4, 4, Epi>, T = 64);
+}
+
+}  // namespace
+
+int adjoint_tile_width(int MT) { return (MT > 12 && MT <= 24) ? 32 : 64; }
+
+hipError_t launch_adjoint_store(const AdjParams& pr, float* out, float scale, hipStream_t st) {
+  return launch_adjoint_epi(pr, EpiStore{out, scale}, st);
+}
+hipError_t launch_adjoint_mf(const AdjParams& pr, float* mf, float* eps, float eps_scale,
+                             hipStream_t st) {
+  return launch_adjoint_epi(pr, EpiMF{mf, eps, eps_scale}, st);
+}
+hipError_t launch_adjoint_mvdr(const AdjParams& pr, float* gamma, double C, double kb_coef,
+                               hipStream_t st) {
+  return launch_adjoint_epi(pr, EpiMVDR{gamma, C, kb_coef}, st);
+}
+hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint64_t* part,
+                                 hipStream_t st) {
+  return launch_adjoint_epi(pr, EpiLambda{state, part}, st);
+}
+hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
+                               double* alpha_part, int init, hipStream_t st) {
+  return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init}, st);
+}
+
+void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm) {
+  const int MT = pad_p(P) / 8;
+  const int tw = MT <= 3 ? 3 : 6;
+  const int nb = (MT + tw - 1) / tw;
+  *nbm = nb;
+  // about 512 waves in flight, at least 8 pixels per wave, at most 256 partials
+  int waves = 512 / (nb * nb);
+  if (waves < 1) waves = 1;
+  int c = (n + waves - 1) / waves;
+  c = (c + 3) & ~3;
+  if (c < 8) c = 8;
+  int nc = (n + c - 1) / c;
+  if (nc > 256) {
+    c = ((n + 255) / 256 + 3) & ~3;
+    nc = (n + c - 1) / c;
+  }
+  *chw = c;
+  *nchunks = n > 0 ? nc : 0;
+}
+
+hipError_t launch_forward(const FwdParams& pr, hipStream_t st) {
+  if (pr.n <= 0) return hipSuccess;
+  const int nchunks = (pr.n + pr.chw - 1) / pr.chw;
+  dim3 grid((nchunks + 3) / 4, pr.nbm * pr.nbn);
+  if (pr.MT <= 3)
+    hipLaunchKernelGGL((forward_kernel<3, 3>), grid, dim3(kThreads), 0, st, pr);
+  else
+    hipLaunchKernelGGL((forward_kernel<6, 6>), grid, dim3(kThreads), 0, st, pr);
+  return hipGetLastError();
+}
+
+int reduce_blocks(int P) {
+  const int MT = pad_p(P) / 8;
+  return (MT * MT * 64 + kThreads - 1) / kThreads;
+}
+
+hipError_t launch_reduce(const RedParams& pr, hipStream_t st) {
+  const int blocks = reduce_blocks(pr.P);
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(kThreads), 0, st, pr);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, float2* Rinv,
+                               int* status, hipStream_t st) {
+  hipLaunchKernelGGL(chol_inverse_kernel, dim3(1), dim3(1024), 0, st, R, P, W, Li, Rinv, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_tables(const double* pos, int P, double lambda, int nl, int nm, double l0,
+                         double dl, double m0, double dm, float2* El, float2* Em, hipStream_t st) {
+  const int Pp = pad_p(P);
+  const int total = Pp * (nl + nm);
+  int grid = (total + kThreads - 1) / kThreads;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(tables_kernel, dim3(grid), dim3(kThreads), 0, st, pos, P, Pp, lambda, nl, nm,
+                     l0, dl, m0, dm, El, Em);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_diag(const float2* R, const float* noise, int P, float2* B0, hipStream_t st) {
+  const int grid = (P * P + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(sub_diag_kernel, dim3(grid), dim3(kThreads), 0, st, R, noise, P, B0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* x, float v, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int grid = (n + kThreads - 1) / kThreads;
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(kThreads), 0, st, x, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace clsimg

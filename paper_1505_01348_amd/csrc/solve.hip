@@ -1,0 +1,381 @@
+// Control kernels of the active-set solve: free/upper set compaction, the
+// LSQR scalar recurrences in FP64, the feasibility test and bounded step of
+// Table I, and the final argmin of the Lagrange multipliers.
+#include "kernels.h"
+
+namespace clsimg {
+
+constexpr int kCtl = 1024;  // single-workgroup control kernels
+
+// ---------------------------------------------------------------------------
+// Sorted index lists of F (state 1) and U (state 2); one workgroup.
+__global__ __launch_bounds__(kCtl) void compact_kernel(const uint8_t* __restrict__ state, int Q,
+                                                       int* __restrict__ Flist,
+                                                       int* __restrict__ Ulist,
+                                                       SolveDecision* dec) {
+  __shared__ int sF[kCtl], sU[kCtl];
+  const int tid = threadIdx.x;
+  const int per = (Q + kCtl - 1) / kCtl;
+  const int b = tid * per, e = min(Q, b + per);
+  int cf = 0, cu = 0;
+  for (int i = b; i < e; ++i) {
+    const uint8_t s = state[i];
+    cf += (s == 1);
+    cu += (s == 2);
+  }
+  sF[tid] = cf;
+  sU[tid] = cu;
+  __syncthreads();
+  // inclusive Hillis-Steele scan
+  for (int o = 1; o < kCtl; o <<= 1) {
+    const int af = tid >= o ? sF[tid - o] : 0;
+    const int au = tid >= o ? sU[tid - o] : 0;
+    __syncthreads();
+    sF[tid] += af;
+    sU[tid] += au;
+    __syncthreads();
+  }
+  int of = sF[tid] - cf, ou = sU[tid] - cu;
+  for (int i = b; i < e; ++i) {
+    const uint8_t s = state[i];
+    if (s == 1) Flist[of++] = i;
+    else if (s == 2) Ulist[ou++] = i;
+  }
+  if (tid == kCtl - 1) {
+    dec->nF = sF[tid];
+    dec->nU = sU[tid];
+  }
+}
+
+__device__ inline double sum_parts(const double* p, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += p[i];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// LSQR start: beta_1 = ||b||, alpha_1 = ||M^H u_1||, v_1, w_1 = v_1, x = 0.
+__global__ __launch_bounds__(kCtl) void lsqr_init_kernel(LsqrState* s, const double* beta_part,
+                                                         int nbeta, const double* alpha_part,
+                                                         int nalpha, float* v, float* w, float* x,
+                                                         int n, double atol, double btol,
+                                                         double conlim, int itnlim) {
+  __shared__ double sab[2];
+  if (threadIdx.x == 0) {
+    sab[0] = sqrt(sum_parts(alpha_part, nalpha));
+    sab[1] = sqrt(sum_parts(beta_part, nbeta));
+  }
+  __syncthreads();
+  const double alpha = sab[0], beta = sab[1];
+  const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  for (int k = threadIdx.x; k < n; k += kCtl) {
+    const float vk = (float)((double)v[k] * ia);
+    v[k] = vk;
+    w[k] = vk;
+    x[k] = 0.f;
+  }
+  if (threadIdx.x == 0) {
+    s->alpha = alpha;
+    s->beta = beta;
+    s->rhobar = alpha;
+    s->phibar = beta;
+    s->bnorm = beta;
+    s->anorm2 = 0.0;
+    s->ddnorm = 0.0;
+    s->rnorm = beta;
+    s->arnorm = alpha * beta;
+    s->anorm = 0.0;
+    s->acond = 0.0;
+    s->xnorm = 0.0;
+    s->atol = atol;
+    s->btol = btol;
+    s->conlim = conlim;
+    s->itn = 0;
+    s->itnlim = itnlim;
+    const bool stop = (n == 0) || (beta == 0.0) || (alpha == 0.0);
+    s->istop = stop ? 4 : 0;
+    s->done = stop ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One LSQR update after the bidiagonalisation step has produced beta_{i+1}
+// (partials of ||u||^2) and the unnormalised v (partials of ||v||^2).
+__global__ __launch_bounds__(kCtl) void lsqr_update_kernel(LsqrState* s, const double* beta_part,
+                                                           int nbeta, const double* alpha_part,
+                                                           int nalpha, float* v, float* w,
+                                                           float* x, int n) {
+  __shared__ double sc[8];
+  __shared__ double red_d[kCtl / 64], red_x[kCtl / 64];
+  if (s->done) return;
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(sum_parts(beta_part, nbeta));
+    const double alpha = sqrt(sum_parts(alpha_part, nalpha));
+    const double alpha_old = s->alpha;
+    s->anorm2 += alpha_old * alpha_old + beta * beta;
+    const double rho = hypot(s->rhobar, beta);
+    const double c = s->rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    s->rhobar = -c * alpha;
+    const double phi = c * s->phibar;
+    s->phibar = sn * s->phibar;
+    s->alpha = alpha;
+    s->beta = beta;
+    sc[0] = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v scale
+    sc[1] = 1.0 / rho;                         // dk = w / rho
+    sc[2] = phi;                               // x += phi dk
+    sc[3] = theta / rho;                       // w = v - (theta/rho) w
+    sc[4] = c;
+  }
+  __syncthreads();
+  const double iv = sc[0], ir = sc[1], phi = sc[2], tr = sc[3];
+  double dd = 0.0, xx = 0.0;
+  for (int k = threadIdx.x; k < n; k += kCtl) {
+    const double vk = (double)v[k] * iv;
+    const double wk = (double)w[k];
+    const double dk = wk * ir;
+    dd += dk * dk;
+    const float xk = (float)((double)x[k] + phi * dk);
+    x[k] = xk;
+    xx += (double)xk * xk;
+    const float vf = (float)vk;
+    v[k] = vf;
+    w[k] = (float)((double)vf - tr * wk);
+  }
+  dd = block_sum_d(dd, red_d);
+  xx = block_sum_d(xx, red_x);
+  if (threadIdx.x == 0) {
+    s->ddnorm += dd;
+    const double c = sc[4];
+    s->rnorm = s->phibar;
+    s->arnorm = s->phibar * s->alpha * fabs(c);
+    s->anorm = sqrt(s->anorm2);
+    s->acond = s->anorm * sqrt(s->ddnorm);
+    s->xnorm = sqrt(xx);
+    s->itn += 1;
+    int istop = 0;
+    if (s->rnorm <= s->btol * s->bnorm + s->atol * s->anorm * s->xnorm) istop = 1;
+    else if (s->arnorm <= s->atol * s->anorm * s->rnorm) istop = 2;
+    else if (s->acond >= s->conlim) istop = 3;
+    else if (s->alpha == 0.0 || s->beta == 0.0) istop = 4;
+    else if (s->itn >= s->itnlim) istop = 7;
+    s->istop = istop;
+    s->done = istop != 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Table I, after the subproblem: accept z if 0 <= z <= gamma on F, otherwise
+// move along p = z - sigma_F by the largest feasible step (eq. mumax) and move
+// the first blocking pixel to its bound.  Sets dec->grad_done = 0 only when a
+// feasible z was accepted (the gradient kernels run only then).
+__global__ __launch_bounds__(kCtl) void step_kernel(const LsqrState* s, const float* __restrict__ x,
+                                                    const int* __restrict__ Flist, int nF,
+                                                    float* __restrict__ sigma,
+                                                    const float* __restrict__ gamma,
+                                                    uint8_t* __restrict__ state,
+                                                    SolveDecision* dec) {
+  __shared__ int s_ok[kCtl / 64];
+  __shared__ double s_mu[kCtl / 64];
+  __shared__ int s_k[kCtl / 64];
+  __shared__ float s_mz[kCtl / 64];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  if (nF > 0 && !s->done) {
+    if (tid == 0) {
+      dec->lsqr_done = 0;
+      dec->grad_done = 1;
+    }
+    return;
+  }
+  // feasibility (non-strict, no tolerance)
+  int ok = 1;
+  float mz = 3.0e38f;
+  for (int k = tid; k < nF; k += kCtl) {
+    const float z = x[k], g = gamma[Flist[k]];
+    ok &= (z >= 0.f) && (z <= g);
+    mz = fminf(mz, fminf(z, g - z) / g);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    ok &= __shfl_xor(ok, o, 64);
+    mz = fminf(mz, __shfl_xor(mz, o, 64));
+  }
+  if (lane == 0) {
+    s_ok[wv] = ok;
+    s_mz[wv] = mz;
+  }
+  __syncthreads();
+  ok = 1;
+  mz = 3.0e38f;
+  for (int i = 0; i < kCtl / 64; ++i) {
+    ok &= s_ok[i];
+    mz = fminf(mz, s_mz[i]);
+  }
+  if (ok) {
+    for (int k = tid; k < nF; k += kCtl) sigma[Flist[k]] = x[k];
+    if (tid == 0) {
+      dec->lsqr_done = 1;
+      dec->lsqr_itn = nF > 0 ? s->itn : 0;
+      dec->lsqr_istop = nF > 0 ? s->istop : 0;
+      dec->feasible = 1;
+      dec->margin_z = mz;
+      dec->ib = -1;
+      dec->grad_done = 0;
+    }
+    return;
+  }
+  // largest feasible step; ties to the lowest list position (= lowest pixel)
+  double best = INFINITY;
+  int bk = 0x7fffffff;
+  for (int k = tid; k < nF; k += kCtl) {
+    const int i = Flist[k];
+    const double sg = sigma[i], p = (double)x[k] - sg;
+    if (p != 0.0) {
+      const double mu = fmax(-sg / p, ((double)gamma[i] - sg) / p);
+      if (mu < best || (mu == best && k < bk)) {
+        best = mu;
+        bk = k;
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int ok2 = __shfl_xor(bk, o, 64);
+    if (ob < best || (ob == best && ok2 < bk)) {
+      best = ob;
+      bk = ok2;
+    }
+  }
+  if (lane == 0) {
+    s_mu[wv] = best;
+    s_k[wv] = bk;
+  }
+  __syncthreads();
+  best = INFINITY;
+  bk = 0x7fffffff;
+  for (int i = 0; i < kCtl / 64; ++i) {
+    if (s_mu[i] < best || (s_mu[i] == best && s_k[i] < bk)) {
+      best = s_mu[i];
+      bk = s_k[i];
+    }
+  }
+  if (bk >= nF) {  // no finite step (non-finite z): stop moving, block the first pixel
+    bk = 0;
+    best = 0.0;
+  }
+  const double mu = best;
+  // sign of the step at the blocking pixel, read before any sigma changes
+  __shared__ double s_pb;
+  if (tid == 0) s_pb = (double)x[bk] - (double)sigma[Flist[bk]];
+  __syncthreads();
+  // every list entry is owned by one thread: read-modify-write is race free
+  for (int k = tid; k < nF; k += kCtl) {
+    const int i = Flist[k];
+    const double sg = sigma[i], p = (double)x[k] - sg;
+    sigma[i] = (float)fmin(fmax(sg + mu * p, 0.0), (double)gamma[i]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int ib = Flist[bk];
+    const bool to_upper = !(s_pb < 0.0);
+    sigma[ib] = to_upper ? gamma[ib] : 0.f;
+    state[ib] = to_upper ? (uint8_t)2 : (uint8_t)0;
+    dec->lsqr_done = 1;
+    dec->lsqr_itn = s->itn;
+    dec->lsqr_istop = s->istop;
+    dec->feasible = 0;
+    dec->ib = ib;
+    dec->ib_to = to_upper ? 2 : 0;
+    dec->mu_max = (float)mu;
+    dec->grad_done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kCtl) void argmin_final_kernel(const uint64_t* __restrict__ part,
+                                                            int nparts,
+                                                            const float* __restrict__ eps,
+                                                            const uint8_t* __restrict__ state,
+                                                            SolveDecision* dec) {
+  __shared__ uint64_t sh[kCtl / 64];
+  if (dec->grad_done) return;
+  uint64_t m = ~0ull;
+  for (int i = threadIdx.x; i < nparts; i += kCtl) m = part[i] < m ? part[i] : m;
+  m = block_min_u64(m, sh);
+  if (threadIdx.x == 0) {
+    if (m == ~0ull) {
+      dec->i_min = -1;
+      dec->lam_min = 0.f;
+      dec->eps_min = 0.f;
+    } else {
+      const int i = (int)(m & 0xffffffffu);
+      dec->i_min = i;
+      dec->st_min = state[i];
+      dec->lam_min = from_ordered_bits((uint32_t)(m >> 32));
+      dec->eps_min = eps[i];
+    }
+    dec->grad_done = 1;
+  }
+}
+
+__global__ void set_state_kernel(uint8_t* state, int i, uint8_t v) { state[i] = v; }
+
+__global__ void init_state_kernel(const float* __restrict__ sigma0, const uint8_t* __restrict__ state0,
+                                  float* __restrict__ sigma, uint8_t* __restrict__ state, int Q) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < Q; e += gridDim.x * blockDim.x) {
+    sigma[e] = sigma0 ? sigma0[e] : 0.f;
+    state[e] = state0 ? state0[e] : (uint8_t)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kCtl), 0, st, state, Q, Flist, Ulist, dec);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int nbeta,
+                                    const double* alpha_part, int nalpha, float* v, float* w,
+                                    float* x, int n, double atol, double btol, double conlim,
+                                    int itnlim, hipStream_t st) {
+  hipLaunchKernelGGL(lsqr_init_kernel, dim3(1), dim3(kCtl), 0, st, s, beta_part, nbeta, alpha_part,
+                     nalpha, v, w, x, n, atol, btol, conlim, itnlim);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsqr_update(LsqrState* s, const double* beta_part, int nbeta,
+                              const double* alpha_part, int nalpha, float* v, float* w, float* x,
+                              int n, hipStream_t st) {
+  hipLaunchKernelGGL(lsqr_update_kernel, dim3(1), dim3(kCtl), 0, st, s, beta_part, nbeta,
+                     alpha_part, nalpha, v, w, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const LsqrState* s, const float* x, const int* Flist, int nF, float* sigma,
+                       const float* gamma, uint8_t* state, SolveDecision* dec, hipStream_t st) {
+  hipLaunchKernelGGL(step_kernel, dim3(1), dim3(kCtl), 0, st, s, x, Flist, nF, sigma, gamma, state,
+                     dec);
+  return hipGetLastError();
+}
+
+hipError_t launch_argmin_final(const uint64_t* part, int nparts, const float* eps,
+                               const uint8_t* state, SolveDecision* dec, hipStream_t st) {
+  hipLaunchKernelGGL(argmin_final_kernel, dim3(1), dim3(kCtl), 0, st, part, nparts, eps, state, dec);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(uint8_t* state, int i, uint8_t v, hipStream_t st) {
+  hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, st, state, i, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const float* sigma0, const uint8_t* state0, float* sigma,
+                             uint8_t* state, int Q, hipStream_t st) {
+  int grid = (Q + 255) / 256;
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL(init_state_kernel, dim3(grid), dim3(256), 0, st, sigma0, state0, sigma, state,
+                     Q);
+  return hipGetLastError();
+}
+
+}  // namespace clsimg

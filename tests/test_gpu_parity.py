@@ -1,0 +1,246 @@
+"""GPU (HIP library through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances (FP32 contractions with FP32 steering entries of ~1 ulp):
+* images and operator outputs: normwise relative error <= 1e-5 and every entry
+  within 1e-5 * max|reference| (per-pixel relative error is no valid gate:
+  sidelobe pixels cancel);
+* the active-set solve: identical final sets on the 24-antenna workload and a
+  relative image error <= 1e-5.
+The oracle always sees the complex64-rounded covariance upcast to complex128,
+i.e. exactly the bits the GPU receives.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _rel(got, ref):
+    got = np.asarray(got).astype(np.complex128 if np.iscomplexobj(got) else np.float64)
+    ref = np.asarray(ref)
+    d = np.linalg.norm((got - ref).ravel())
+    n = np.linalg.norm(np.asarray(ref).ravel())
+    return d / n if n > 0 else d
+
+
+def _assert_close(got, ref, tol=TOL, what=""):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    rel = _rel(got, ref)
+    mx = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30) if ref.size else 0.0
+    print(f"{what}: normwise rel {rel:.3e}, max rel-to-peak {mx:.3e}", flush=True)
+    assert rel <= tol, (what, rel)
+    assert mx <= tol, (what, mx)
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    return {name: synth.make_scene(name) for name in ("c0", "c1")}
+
+
+def _geo(gpu_lib, sc):
+    return gpu_lib.Geometry(sc.pos, sc.lam, sc.grid)
+
+
+def _dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _rand_geometry(rng, P, nl, nm, radius=10.0, L=0.6):
+    r = radius * np.sqrt(rng.random(P))
+    t = 2 * np.pi * rng.random(P)
+    pos = np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+    grid = (nl, nm, -L, 2 * L / nl, -L * 0.9, 1.8 * L / nm)
+    return pos, 1.3, grid
+
+
+def _rand_hermitian(rng, P, pd=False):
+    X = rng.standard_normal((P, P)) + 1j * rng.standard_normal((P, P))
+    H = X @ X.conj().T / P + 0.5 * np.eye(P) if pd else 0.5 * (X + X.conj().T)
+    return H.astype(np.complex64)
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_dirty_image_matches_oracle(gpu_lib, ctx, scenes, name):
+    sc = scenes[name]
+    print(f"case dirty_image {name} P={sc.P} Q={sc.Q}", flush=True)
+    A = oracle.steering(sc.pos, sc.lam, sc.grid)
+    ref = oracle.mf_image(A, sc.R_hat32_c128)
+    got = ctx.dirty_image(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc)).cpu().numpy()
+    _assert_close(got, ref, what=f"mf {name}")
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+@pytest.mark.parametrize("bound", ["mvdr", "mf", "mvdr_opts"])
+def test_upper_bound_matches_oracle(gpu_lib, ctx, scenes, name, bound):
+    sc = scenes[name]
+    print(f"case bound {bound} {name}", flush=True)
+    A = oracle.steering(sc.pos, sc.lam, sc.grid)
+    R = sc.R_hat32_c128
+    opts = gpu_lib.default_options()
+    opts.nsamples = sc.N
+    if bound == "mvdr":
+        ref = oracle.upper_bound(A, R, "mvdr")
+    elif bound == "mf":
+        opts.bound = gpu_lib.BOUND_MF
+        opts.kappa_b = 6.0
+        ref = oracle.upper_bound(A, R, "mf", kappa_b=6.0, nsamples=sc.N)
+    else:
+        opts.C = sc.N / (sc.N - sc.P)
+        opts.kappa_b = 6.0
+        ref = oracle.upper_bound(A, R, "mvdr", C=opts.C, kappa_b=6.0, nsamples=sc.N)
+    got = ctx.mvdr_bound(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts).cpu().numpy()
+    _assert_close(got, ref, what=f"gamma {bound} {name}")
+
+
+def test_bound_none_is_infinite(gpu_lib, ctx, scenes):
+    sc = scenes["c0"]
+    opts = gpu_lib.default_options()
+    opts.bound = gpu_lib.BOUND_NONE
+    got = ctx.mvdr_bound(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts).cpu().numpy()
+    assert np.all(np.isinf(got)) and np.all(got > 0)
+
+
+@pytest.mark.parametrize("P,nl,nm", [(24, 32, 32), (48, 33, 17), (5, 7, 3), (13, 40, 9), (96, 20, 20),
+                                     (288, 16, 12), (1, 4, 4)])
+@pytest.mark.parametrize("n", [0, 1, 17, 64, 65, 300])
+def test_adjoint_subset_matches_oracle(gpu_lib, ctx, P, nl, nm, n):
+    rng = np.random.default_rng(1000 * P + n)
+    pos, lam, grid = _rand_geometry(rng, P, nl, nm)
+    Q = nl * nm
+    n = min(n, Q)
+    print(f"case adjoint P={P} grid={nl}x{nm} n={n}", flush=True)
+    idx = np.sort(rng.choice(Q, size=n, replace=False)).astype(np.int32)
+    U = _rand_hermitian(rng, P)
+    A = oracle.steering(pos, lam, grid, pixels=idx)
+    ref = oracle.adjoint(A, U.astype(np.complex128))
+    geo = gpu_lib.Geometry(pos, lam, grid)
+    got = ctx.adjoint(geo, _dev(U, torch.complex64), idx=_dev(idx, torch.int32)).cpu().numpy()
+    if n:
+        _assert_close(got, ref, what=f"adjoint P={P} n={n}")
+    # the whole grid, no index list
+    refQ = oracle.adjoint(oracle.steering(pos, lam, grid), U.astype(np.complex128))
+    gotQ = ctx.adjoint(geo, _dev(U, torch.complex64)).cpu().numpy()
+    _assert_close(gotQ, refQ, what=f"adjoint all P={P}")
+
+
+@pytest.mark.parametrize("P,nl,nm", [(24, 32, 32), (48, 33, 17), (5, 7, 3), (13, 40, 9), (96, 20, 20),
+                                     (288, 16, 12), (1, 4, 4)])
+@pytest.mark.parametrize("n", [0, 1, 17, 64, 65, 300])
+def test_forward_subset_matches_oracle(gpu_lib, ctx, P, nl, nm, n):
+    rng = np.random.default_rng(2000 * P + n)
+    pos, lam, grid = _rand_geometry(rng, P, nl, nm)
+    Q = nl * nm
+    n = min(n, Q)
+    print(f"case forward P={P} grid={nl}x{nm} n={n}", flush=True)
+    idx = rng.choice(Q, size=n, replace=False).astype(np.int32)
+    v = rng.standard_normal(n).astype(np.float32)
+    A = oracle.steering(pos, lam, grid, pixels=idx)
+    ref = oracle.forward(A, v.astype(np.float64))
+    geo = gpu_lib.Geometry(pos, lam, grid)
+    got = ctx.forward(geo, _dev(v, torch.float32), idx=_dev(idx, torch.int32)).cpu().numpy()
+    if n == 0:
+        assert np.all(got == 0)
+    else:
+        _assert_close(got, ref, what=f"forward P={P} n={n}")
+
+
+def test_gpu_adjointness(gpu_lib, ctx, scenes):
+    sc = scenes["c1"]
+    rng = np.random.default_rng(7)
+    geo = _geo(gpu_lib, sc)
+    idx = np.sort(rng.choice(sc.Q, size=500, replace=False)).astype(np.int32)
+    x = rng.standard_normal(500).astype(np.float32)
+    Y = _rand_hermitian(rng, sc.P)
+    Fx = ctx.forward(geo, _dev(x, torch.float32), idx=_dev(idx, torch.int32)).cpu().numpy()
+    AY = ctx.adjoint(geo, _dev(Y, torch.complex64), idx=_dev(idx, torch.int32)).cpu().numpy()
+    lhs = float(np.real(np.vdot(Fx.astype(np.complex128), Y.astype(np.complex128))))
+    rhs = float(x.astype(np.float64) @ AY.astype(np.float64))
+    scale = np.linalg.norm(Fx) * np.linalg.norm(Y)
+    print(f"adjointness: {lhs} vs {rhs}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_not_positive_definite_is_reported(gpu_lib, ctx):
+    rng = np.random.default_rng(3)
+    pos, lam, grid = _rand_geometry(rng, 8, 8, 8)
+    R = _rand_hermitian(rng, 8)
+    R = (R - (np.abs(np.linalg.eigvalsh(R)).max() + 1) * np.eye(8)).astype(np.complex64)
+    geo = gpu_lib.Geometry(pos, lam, grid)
+    with pytest.raises(gpu_lib.ClsimgError) as ei:
+        ctx.mvdr_bound(_dev(R, torch.complex64), geo)
+    assert ei.value.status == gpu_lib.ENOTPD
+    Rn = np.eye(8, dtype=np.complex64)
+    Rn[2, 3] = np.nan
+    with pytest.raises(gpu_lib.ClsimgError) as ei:
+        ctx.mvdr_bound(_dev(Rn, torch.complex64), geo)
+    assert ei.value.status == gpu_lib.ENOTPD
+
+
+def _oracle_solve(sc, atol=1e-8, btol=1e-8, noise=True, kappa_d=6.0):
+    R = sc.R_hat32_c128
+    A = oracle.steering(sc.pos, sc.lam, sc.grid)
+    mf = oracle.mf_image(A, R)
+    gamma = oracle.upper_bound(A, R)
+    eps = oracle.detection_threshold(mf, kappa_d, sc.N)
+    nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64) if noise else np.zeros(sc.P)
+    res = oracle.solve(A, R - np.diag(nd), gamma, eps, atol=atol, btol=btol)
+    return res, mf, gamma
+
+
+def _gpu_solve(gpu_lib, ctx, sc, atol=1e-7, btol=1e-7, noise=True, kappa_d=6.0):
+    opts = gpu_lib.default_options()
+    opts.nsamples = sc.N
+    opts.atol, opts.btol = atol, btol
+    opts.kappa_d = kappa_d
+    nd = _dev(sc.noise_diag, torch.float32) if noise else None
+    sigma, state, mf, gamma, stats = ctx.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc),
+                                               opts, noise_diag=nd)
+    return sigma.cpu().numpy(), state.cpu().numpy(), mf.cpu().numpy(), gamma.cpu().numpy(), stats
+
+
+@pytest.mark.parametrize("noise", [True, False])
+def test_solve_c0_identical_sets(gpu_lib, ctx, scenes, noise):
+    sc = scenes["c0"]
+    print(f"case solve c0 noise={noise}", flush=True)
+    ref, mf_ref, gamma_ref = _oracle_solve(sc, noise=noise)
+    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc, noise=noise)
+    print("gpu stats", stats, flush=True)
+    print("oracle outer", ref.outer_iters, "adds", ref.adds, "drops", ref.drops, "lsqr", ref.lsqr_iters_total,
+          flush=True)
+    _assert_close(mf, mf_ref, what="solve mf")
+    _assert_close(gamma, gamma_ref, what="solve gamma")
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what="solve sigma c0")
+    assert stats["status"] == ref.status
+    assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
+    assert abs(stats["rel_residual"] - ref.rel_residual) <= 1e-5 * max(ref.rel_residual, 1e-12) + 1e-7
+
+
+def test_solve_c1_image_error(gpu_lib, ctx, scenes):
+    sc = scenes["c1"]
+    print("case solve c1", flush=True)
+    ref, _, _ = _oracle_solve(sc)
+    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc)
+    print("gpu stats", stats, flush=True)
+    print("oracle outer", ref.outer_iters, "adds", ref.adds, "drops", ref.drops, "lsqr",
+          ref.lsqr_iters_total, flush=True)
+    print("state mismatches", int(np.sum(state != ref.state)), flush=True)
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what="solve sigma c1")

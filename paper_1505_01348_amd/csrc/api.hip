@@ -47,11 +47,14 @@ struct clsimg_ctx {
   DevBuf B0, Bb, u, E, Rinv, W, Li;
   DevBuf Flist, Ulist, v, w, x, eps, mf, gamma;
   DevBuf lsqr, dec, status;
+  DevBuf lsqr2, done, x1, w1, vraw, bpart0, bpart1, xf, bar;  // fused LSQR step
   SolveDecision* h_dec = nullptr;
   LsqrState* h_lsqr = nullptr;
   int* h_status = nullptr;
   double* h_norms = nullptr;
   bool trace = false;  // CLSIMG_TRACE=1: one line per active-set step on stderr
+  bool coop = false;   // cooperative launches available (multi-workgroup LSQR kernel)
+  int lsqr_path = 0;   // CLSIMG_LSQR_PATH: 0 auto, 1 one workgroup, 2 cooperative, 3 two kernels/step
 };
 
 namespace {
@@ -160,6 +163,7 @@ AdjParams adj_params(clsimg_ctx* c, const clsimg_grid* g, int P, const float* fr
   AdjParams pr;
   pr.frag = frag;
   pr.U = U;
+  pr.xf = nullptr;
   pr.P = P;
   pr.MT = pad_p(P) / 8;
   pr.KS = pad_p(P) / 2;
@@ -337,6 +341,11 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   c->budget = budget;
   const char* tr = getenv("CLSIMG_TRACE");
   c->trace = tr && tr[0] == '1';
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess)
+    c->coop = coop != 0;
+  const char* lp = getenv("CLSIMG_LSQR_PATH");
+  if (lp) c->lsqr_path = atoi(lp);
   void* hp = nullptr;
   const size_t hbytes = sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + 64 * sizeof(double);
   if (hipHostMalloc(&hp, hbytes, hipHostMallocDefault) != hipSuccess ||
@@ -362,7 +371,8 @@ int clsimg_destroy(clsimg_ctx* c) {
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
-                    &c->dec,  &c->status};
+                    &c->dec,  &c->status, &c->lsqr2, &c->done, &c->x1, &c->w1, &c->vraw,
+                    &c->bpart0, &c->bpart1, &c->xf, &c->bar};
   for (DevBuf* d : bufs)
     if (d->ptr) (void)hipFree(d->ptr);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -461,6 +471,20 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   ST_TRY(ensure(c, c->v, (size_t)Q * sizeof(float)));
   ST_TRY(ensure(c, c->w, (size_t)Q * sizeof(float)));
   ST_TRY(ensure(c, c->x, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->x1, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->w1, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->vraw, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->lsqr2, 3 * sizeof(LsqrState)));
+  ST_TRY(ensure(c, c->done, sizeof(int)));
+  ST_TRY(ensure(c, c->bar, 2 * sizeof(unsigned)));
+  {
+    const int nparts = std::max(std::max(reduce_blocks(P), lsqr_fwd_waves(P)), Q / 32 + 64);
+    const size_t nb = (size_t)nparts * sizeof(double);
+    ST_TRY(ensure(c, c->bpart0, nb));
+    ST_TRY(ensure(c, c->bpart1, nb));
+  }
+  ST_TRY(ensure(c, c->alpha_part, (size_t)(Q / 32 + 64) * sizeof(double)));
+
   ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
   if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
   if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
@@ -488,6 +512,20 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   const int* lsqr_stop = &ls->done;
   const int* grad_stop = &dec->grad_done;
   const int nbeta = reduce_blocks(P);
+  // fused two-kernel LSQR step for up to 12 row tiles (P <= 96)
+  const int MT = pad_p(P) / 8;
+  const bool fused = MT <= 12;
+  const int nfw = lsqr_fwd_waves(P);
+  LsqrState* S2 = P_<LsqrState>(c->lsqr2);
+  LsqrState* Sfin = S2 + 2;
+  int* done = P_<int>(c->done);
+  float* x1 = P_<float>(c->x1);
+  float* w1 = P_<float>(c->w1);
+  float* vraw = P_<float>(c->vraw);
+  double* bparts[2] = {P_<double>(c->bpart0), P_<double>(c->bpart1)};
+  unsigned* bar = P_<unsigned>(c->bar);
+  int* lerr = reinterpret_cast<int*>(bar + 1);
+  float* xf = P_<float>(c->xf);
 
   double flops = beam_flops(P, Q) + (o->bound != CLSIMG_BOUND_NONE ? beam_flops(P, Q) : 0.0);
   // bounds and threshold (Sec. II-D, App. A)
@@ -505,6 +543,11 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
   const double b0norm = sqrt(sum_host(c->h_norms, nbeta));
   int nF = c->h_dec->nF, nU = c->h_dec->nU;
+  auto lsqr_adj = [&](const int* stop) {
+    AdjParams a = adj_params(c, g, P, frag_u, Flist, nF, stop);
+    a.xf = xf;
+    return a;
+  };
 
   const int max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
   int status = CLSIMG_OK;
@@ -522,46 +565,174 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
         break;
       }
       HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
-      // b = B0 - Psi_U gamma_U  (eq. bsubproblemLS)
-      ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr,
-                       nullptr, st));
+      // b = B0 - Psi_U gamma_U  (eq. bsubproblemLS); b = B0 while U is empty
+      const float2* bsub = B0;
+      if (nU > 0) {
+        ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr,
+                         nullptr, st));
+        bsub = Bb;
+      }
       flops += corr_flops(P, nU);
+      if (fused) {
+        // the cache grows geometrically with |F| (a reallocation synchronises the device)
+        size_t cap = 256;
+        while (cap < (size_t)nF) cap *= 2;
+        ST_TRY(ensure(c, c->xf, cap * 2 * pad_p(P) * sizeof(float)));
+        xf = P_<float>(c->xf);
+        HIP_TRY(launch_xf(tables_of(c, g, P), Flist, nF, xf, st));
+      }
       const int nalpha = ntiles_adj(P, nF);
+      const int nalpha2 = (nF + adjoint_lsqr2_tile_width(MT, nF) - 1) / adjoint_lsqr2_tile_width(MT, nF);
+      int it = 1;
+      auto fwd_params = [&](int iter) {
+        LsqrFwdParams f;
+        f.tab = tables_of(c, g, P);
+        f.MT = MT;
+        f.P = P;
+        f.Flist = Flist;
+        f.n = nF;
+        f.S = S2;
+        f.Sfinal = Sfin;
+        f.done = done;
+        f.it = iter;
+        f.vraw = vraw;
+        f.vnorm = v;
+        f.alpha_part = alpha_part;
+        f.nalpha = nalpha2;
+        f.beta_in = bparts[iter & 1];
+        f.nbeta_in = iter == 1 ? nbeta : nfw;
+        f.beta_out = bparts[(iter + 1) & 1];
+        f.x0 = x;
+        f.x1 = x1;
+        f.w0 = w;
+        f.w1 = w1;
+        f.xf = xf;
+        f.u = u;
+        f.frag = frag_u;
+        f.ntp = MT * (MT + 1) / 2;
+        return f;
+      };
+      // LSQR engine: one cooperative kernel, else one workgroup when everything
+      // fits in its LDS, else two kernels per step (P <= 96), else the split-K
+      // correlation with separate reductions
+      const int want = c->lsqr_path;
+      const bool persist = fused && c->coop && (want == 0 || want == 2) && persist_fits(P, nF);
+      const bool one_cu = !persist && fused && (want == 0 || want == 1) && lsqr_cu_fits(P, nF);
       if (nF > 0) {
         const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
-        // beta_1 u_1 = b ; alpha_1 v_1 = Psi_F^H u_1  (eqs. initbeta, initu)
-        ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, u, Bb, 0.f, 1.f, nullptr, frag_u, beta_part,
-                         nullptr, st));
-        HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, nullptr), v, beta_part,
-                                    nbeta, alpha_part, 1, st));
-        HIP_TRY(launch_lsqr_init_scalars(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF,
-                                         o->atol, o->btol, o->conlim, itnlim, st));
+        if (one_cu) {
+          HIP_TRY(launch_lsqr_setup2(S2, done, bar, lerr, o->atol, o->btol, o->conlim, itnlim, st));
+          LsqrCuParams lc;
+          lc.P = P;
+          lc.n = nF;
+          lc.xf = xf;
+          lc.B = bsub;
+          lc.x_out = x;
+          lc.Sfinal = Sfin;
+          lc.done = done;
+          lc.atol = o->atol;
+          lc.btol = o->btol;
+          lc.conlim = o->conlim;
+          lc.itnlim = itnlim;
+          HIP_TRY(launch_lsqr_cu(lc, st));
+        } else if (persist) {
+          // the whole LSQR solve in one cooperative kernel
+          HIP_TRY(launch_lsqr_setup2(S2, done, bar, lerr, o->atol, o->btol, o->conlim, itnlim, st));
+          LsqrPersistParams lp;
+          lp.MT = MT;
+          lp.P = P;
+          lp.n = nF;
+          lp.ntp = MT * (MT + 1) / 2;
+          lp.xf = xf;
+          lp.B = bsub;
+          lp.frag = frag_u;
+          lp.pbeta = bparts[0];
+          lp.palpha = alpha_part;
+          lp.vraw = vraw;
+          lp.x_out = x;
+          lp.Sfinal = Sfin;
+          lp.done = done;
+          lp.bar = bar;
+          lp.err = lerr;
+          lp.atol = o->atol;
+          lp.btol = o->btol;
+          lp.conlim = o->conlim;
+          lp.itnlim = itnlim;
+          HIP_TRY(launch_lsqr_persist(lp, st));
+        } else if (fused) {
+          // beta_1 u_1 = b ; alpha_1 v_1 = Psi_F^H u_1  (eqs. initbeta, initu); then step 1
+          HIP_TRY(launch_lsqr_setup(S2, done, o->atol, o->btol, o->conlim, itnlim, st));
+          ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, u, bsub, 0.f, 1.f, nullptr, frag_u,
+                           bparts[1], nullptr, st));
+          HIP_TRY(launch_adjoint_lsqr2(lsqr_adj(done), EpiLsqrV2{vraw, v, bparts[1], nbeta, alpha_part, 1},
+                                       st));
+          HIP_TRY(launch_lsqr_fwd(fwd_params(1), st));
+        } else {
+          ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, u, bsub, 0.f, 1.f, nullptr, frag_u, beta_part,
+                           nullptr, st));
+          HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, nullptr), v, beta_part,
+                                      nbeta, alpha_part, 1, st));
+          HIP_TRY(launch_lsqr_init_scalars(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF,
+                                           o->atol, o->btol, o->conlim, itnlim, st));
+        }
       }
       for (;;) {
-        if (nF > 0) {
-          for (int it = 0; it < batch; ++it) {
+        if (nF > 0 && !persist && !one_cu) {
+          for (int b = 0; b < batch; ++b) {
             // beta u <- Psi_F v - alpha u ; alpha v <- Psi_F^H u - beta v  (eq. lanczos)
-            ST_TRY(correlate(c, g, P, Flist, v, 0, nF, u, u, 1.f, 0.f, ls, frag_u, beta_part,
-                             lsqr_stop, st));
-            HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, lsqr_stop), v,
-                                        beta_part, nbeta, alpha_part, 0, st));
-            HIP_TRY(launch_lsqr_update(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF, st));
+            if (fused) {
+              HIP_TRY(launch_adjoint_lsqr2(lsqr_adj(done),
+                                           EpiLsqrV2{vraw, v, bparts[(it + 1) & 1], nfw, alpha_part, 0},
+                                           st));
+              ++it;
+              HIP_TRY(launch_lsqr_fwd(fwd_params(it), st));
+            } else {
+              ST_TRY(correlate(c, g, P, Flist, v, 0, nF, u, u, 1.f, 0.f, ls, frag_u, beta_part,
+                               lsqr_stop, st));
+              HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, lsqr_stop), v,
+                                          beta_part, nbeta, alpha_part, 0, st));
+              HIP_TRY(launch_lsqr_update(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF, st));
+            }
           }
         }
-        HIP_TRY(launch_step(ls, x, Flist, nF, sigma, gamma, state, dec, st));
-        // gradient on the active pixels, only after a feasible subproblem (eq. gls)
-        ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, Bb, 1.f, -1.f, nullptr, frag_r, nullptr,
-                         grad_stop, st));
+        if (persist || one_cu)
+          HIP_TRY(launch_step(done, lerr, Sfin, x, x, Flist, nF, sigma, gamma, state, dec, st));
+        else if (fused)
+          HIP_TRY(launch_step(done, nullptr, Sfin, x, x1, Flist, nF, sigma, gamma, state, dec, st));
+        else
+          HIP_TRY(launch_step(lsqr_stop, nullptr, ls, x, x, Flist, nF, sigma, gamma, state, dec, st));
+        // gradient on the active pixels, only after a feasible subproblem (eq. gls):
+        // E = Psi_F sigma_F - b, then g = Psi^H E on every pixel
+        if (fused) {
+          CorrOsParams cp;
+          cp.MT = MT;
+          cp.P = P;
+          cp.xf = xf;
+          cp.n = nF;
+          cp.vals = sigma;
+          cp.gidx = Flist;
+          cp.out = E;
+          cp.B = bsub;
+          cp.cK = 1.f;
+          cp.cB = -1.f;
+          cp.frag = frag_r;
+          cp.stop_flag = grad_stop;
+          HIP_TRY(launch_corr_os(cp, st));
+        } else {
+          ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, bsub, 1.f, -1.f, nullptr, frag_r, nullptr,
+                           grad_stop, st));
+        }
         HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys,
                                       st));
         HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
         ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
         if (c->h_dec->lsqr_done) break;
+        if (persist || one_cu || c->h_dec->lsqr_err) return CLSIMG_EHIP;  // LSQR kernel did not finish
         batch = std::min(batch * 2, 64);
       }
       const SolveDecision d = *c->h_dec;
       if (c->trace) {
-        ST_TRY(read_back(c, c->h_lsqr, ls, sizeof(LsqrState), st));
+        ST_TRY(read_back(c, c->h_lsqr, fused ? Sfin : ls, sizeof(LsqrState), st));
         const LsqrState& L = *c->h_lsqr;
         fprintf(stderr,
                 "clsimg: outer %d nF %d nU %d itn %d istop %d alpha %.3e beta %.3e rnorm %.3e "

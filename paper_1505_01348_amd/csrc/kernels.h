@@ -18,6 +18,8 @@ struct LsqrState {
 struct AdjParams {
   const float* frag;  // Ut fragments, 4 Pp^2 floats (used when U is NULL)
   const float2* U;    // or: complex P x P matrix, staged into fragments by the kernel
+  const float* xf;    // optional: real-embedded steering vectors of the listed pixels,
+                      // 2Pp floats per list position (else generated from the tables)
   int P, MT, KS;
   Tables tab;
   const int* idx;     // output column k looks at pixel idx[k] (NULL: pixel k)
@@ -50,11 +52,40 @@ struct RedParams {
   const int* stop_flag;
 };
 
+struct LsqrFwdParams {
+  Tables tab;
+  int MT, P;
+  const int* Flist;
+  int n;
+  LsqrState* S;            // two slots, by iteration parity
+  LsqrState* Sfinal;       // the state of the last step, written when it stops
+  int* done;               // set once the stopping tests pass
+  int it;                  // this launch finishes step it-1 and starts step it
+  const float* vraw;       // unnormalised v from the beamforming of step it-1
+  float* vnorm;            // v_it (written by workgroup 0)
+  const double* alpha_part;
+  int nalpha;
+  const double* beta_in;   // ||u_it||^2 partials
+  int nbeta_in;
+  double* beta_out;        // ||u_{it+1}||^2 partials, one per wave
+  float *x0, *x1, *w0, *w1;
+  const float* xf;         // steering vectors of the free set
+  float2* u;               // unnormalised u, updated in place
+  float* frag;             // Ut fragments of the new u
+  int ntp;                 // upper-triangle tiles MT(MT+1)/2
+};
+
 // ---- adjoint epilogues: called by every thread of the block once per tile --
+struct NoCtx {};
+
 struct EpiStore {
   float* out;
   float scale;
-  __device__ void operator()(int, int col, int, float g, bool ok) const {
+  using Ctx = NoCtx;
+  using Pre = NoCtx;
+  __device__ Ctx init() const { return {}; }
+  __device__ Pre prefetch(int, bool) const { return {}; }
+  __device__ void operator()(int, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
     if (ok) out[col] = g * scale;
   }
 };
@@ -63,7 +94,11 @@ struct EpiMF {
   float* mf;
   float* eps;
   float eps_scale;
-  __device__ void operator()(int, int col, int, float g, bool ok) const {
+  using Ctx = NoCtx;
+  using Pre = NoCtx;
+  __device__ Ctx init() const { return {}; }
+  __device__ Pre prefetch(int, bool) const { return {}; }
+  __device__ void operator()(int, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
     if (ok) {
       mf[col] = g;
       if (eps) eps[col] = g * eps_scale;
@@ -74,7 +109,11 @@ struct EpiMF {
 struct EpiMVDR {
   float* gamma;
   double C, kb_coef;
-  __device__ void operator()(int, int col, int, float g, bool ok) const {
+  using Ctx = NoCtx;
+  using Pre = NoCtx;
+  __device__ Ctx init() const { return {}; }
+  __device__ Pre prefetch(int, bool) const { return {}; }
+  __device__ void operator()(int, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
     if (ok) {
       const double h = (double)g;
       gamma[col] = (float)(C / h + kb_coef / h);
@@ -87,7 +126,11 @@ struct EpiMVDR {
 struct EpiLambda {
   const uint8_t* state;
   uint64_t* part;
-  __device__ void operator()(int tile, int, int pix, float g, bool ok) const {
+  using Ctx = NoCtx;
+  using Pre = NoCtx;
+  __device__ Ctx init() const { return {}; }
+  __device__ Pre prefetch(int, bool) const { return {}; }
+  __device__ void operator()(int tile, int, int pix, float g, bool ok, const Ctx&, const Pre&) const {
     __shared__ uint64_t sh[8];
     uint64_t key = ~0ull;
     if (ok) {
@@ -109,8 +152,12 @@ struct EpiLsqrV {
   const double* beta_part;
   int nbeta;
   double* alpha_part;
-  int init;
-  __device__ void operator()(int tile, int col, int, float g, bool ok) const {
+  int first;
+  using Ctx = NoCtx;
+  using Pre = NoCtx;
+  __device__ Ctx init() const { return {}; }
+  __device__ Pre prefetch(int, bool) const { return {}; }
+  __device__ void operator()(int tile, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
     __shared__ double sh[8];
     __shared__ double sbeta;
     if (threadIdx.x == 0) {
@@ -123,7 +170,7 @@ struct EpiLsqrV {
     double vr2 = 0.0;
     if (ok) {
       double vr = beta > 0.0 ? (double)g / beta : 0.0;
-      if (!init) vr -= beta * (double)v[col];
+      if (!first) vr -= beta * (double)v[col];
       const float vf = (float)vr;
       v[col] = vf;
       vr2 = (double)vf * vf;
@@ -131,6 +178,87 @@ struct EpiLsqrV {
     const double tot = block_sum_d(vr2, sh);
     if (threadIdx.x == 0) alpha_part[tile] = tot;
   }
+};
+
+// LSQR (fused form): v_raw <- Psi_F^H u / beta - beta v_it (or Psi_F^H u / beta
+// at the start); beta from the per-wave partials of the correlation kernel.
+struct EpiLsqrV2 {
+  float* vraw;
+  const float* vnorm;
+  const double* beta_part;
+  int nbeta;
+  double* alpha_part;
+  int first;
+  struct Ctx {
+    double beta;
+  };
+  struct Pre {
+    float v;
+  };
+  // beta_{it+1} from the correlation's per-wave partials, once per block
+  __device__ Ctx init() const {
+    __shared__ double sh[4];
+    double b2 = 0.0;
+    for (int i = threadIdx.x; i < nbeta; i += blockDim.x) b2 += beta_part[i];
+    return {sqrt(block_sum_d(b2, sh))};
+  }
+  __device__ Pre prefetch(int col, bool ok) const { return {(ok && !first) ? vnorm[col] : 0.f}; }
+  __device__ void operator()(int tile, int col, int, float g, bool ok, const Ctx& cx,
+                             const Pre& pf) const {
+    __shared__ double sh2[4];
+    const double beta = cx.beta;
+    double vr2 = 0.0;
+    if (ok) {
+      double vr = beta > 0.0 ? (double)g / beta : 0.0;
+      if (!first) vr -= beta * (double)pf.v;
+      const float vf = (float)vr;
+      vraw[col] = vf;
+      vr2 = (double)vf * vf;
+    }
+    const double tot = block_sum_d(vr2, sh2);
+    if (threadIdx.x == 0) alpha_part[tile] = tot;
+  }
+};
+
+struct LsqrPersistParams {
+  int MT, P, n, ntp;
+  const float* xf;     // steering vectors of the free set (xf_kernel layout)
+  const float2* B;     // right-hand side b (P x P)
+  float* frag;         // Ut fragments of u, exchanged between workgroups
+  double* pbeta;       // per-workgroup ||u||^2 partials
+  double* palpha;      // per-workgroup ||v_raw||^2 partials
+  float* vraw;         // v_raw of every free pixel
+  float* x_out;        // final iterate
+  LsqrState* Sfinal;   // final state
+  int* done;           // set when x_out and Sfinal are written
+  unsigned* bar;       // grid-barrier counter (zeroed before the launch)
+  int* err;            // set if a grid barrier does not complete
+  double atol, btol, conlim;
+  int itnlim;
+};
+
+struct LsqrCuParams {
+  int P, n;
+  const float* xf;     // steering vectors of the free set (xf_kernel layout)
+  const float2* B;     // right-hand side b (P x P, Hermitian)
+  float* x_out;        // final iterate
+  LsqrState* Sfinal;   // final state
+  int* done;           // set when x_out and Sfinal are written
+  double atol, btol, conlim;
+  int itnlim;
+};
+
+struct CorrOsParams {
+  int MT, P;
+  const float* xf;   // steering vectors of the free set (xf_kernel layout)
+  int n;
+  const float* vals; // weight of term k: vals[gidx ? gidx[k] : k]
+  const int* gidx;
+  float2* out;
+  const float2* B;
+  float cK, cB;
+  float* frag;
+  const int* stop_flag;
 };
 
 // ---- launchers (ops.hip) ----
@@ -144,6 +272,22 @@ hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint
                                  hipStream_t st);
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
                                double* alpha_part, int init, hipStream_t st);
+hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st);
+int adjoint_lsqr2_tile_width(int MT, int n);
+// lsqr_cu.hip
+bool lsqr_cu_fits(int P, int n);
+hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st);
+// lsqr_persist.hip
+bool persist_fits(int P, int n);
+int persist_grid(int P, int n);
+hipError_t launch_lsqr_persist(const LsqrPersistParams& pr, hipStream_t st);
+// lsqr.hip
+int lsqr_fwd_waves(int P);
+hipError_t launch_corr_os(const CorrOsParams& pr, hipStream_t st);
+hipError_t launch_xf(const Tables& tab, const int* Flist, int n, float* xf, hipStream_t st);
+hipError_t launch_lsqr_fwd(const LsqrFwdParams& pr, hipStream_t st);
+hipError_t launch_lsqr_setup(LsqrState* S0, int* done, double atol, double btol, double conlim,
+                             int itnlim, hipStream_t st);
 void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm);
 hipError_t launch_forward(const FwdParams& pr, hipStream_t st);
 int reduce_blocks(int P);
@@ -167,6 +311,7 @@ struct SolveDecision {
   int st_min;            // set of i_min (0 = L, 2 = U)
   float lam_min, eps_min;
   int grad_done;
+  int lsqr_err;          // a grid barrier of the LSQR kernel did not complete
 };
 
 hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec,
@@ -178,8 +323,11 @@ hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int n
 hipError_t launch_lsqr_update(LsqrState* s, const double* beta_part, int nbeta,
                               const double* alpha_part, int nalpha, float* v, float* w, float* x,
                               int n, hipStream_t st);
-hipError_t launch_step(const LsqrState* s, const float* x, const int* Flist, int nF, float* sigma,
-                       const float* gamma, uint8_t* state, SolveDecision* dec, hipStream_t st);
+hipError_t launch_step(const int* done, const int* err, const LsqrState* s, const float* x0,
+                       const float* x1, const int* Flist, int nF, float* sigma, const float* gamma,
+                       uint8_t* state, SolveDecision* dec, hipStream_t st);
+hipError_t launch_lsqr_setup2(LsqrState* S0, int* done, unsigned* bar, int* err, double atol,
+                              double btol, double conlim, int itnlim, hipStream_t st);
 hipError_t launch_argmin_final(const uint64_t* part, int nparts, const float* eps,
                                const uint8_t* state, SolveDecision* dec, hipStream_t st);
 hipError_t launch_set_state(uint8_t* state, int i, uint8_t v, hipStream_t st);

@@ -1,0 +1,325 @@
+// Free-set kernels of the active-set solve: the steering vectors of the free
+// pixels, the output-stationary correlation over them, and the fused LSQR step
+// (Sec. IV-A / IV-B).
+//
+// One LSQR step is two kernels:
+//   lsqr_fwd_kernel(it):  finish step it-1 (FP64 rotation scalars, v, w, x and
+//                         the stopping tests) and compute
+//                         u_{it+1} = Psi_F v_it - (alpha_it/beta_it) u_it
+//                         with its Ut fragments and ||u||^2 partials;
+//   adjoint_kernel<EpiLsqrV2>(it):
+//                         v_raw = Psi_F^H u_{it+1} / beta_{it+1} - beta_{it+1} v_it
+//                         with ||v_raw||^2 partials.
+// Every workgroup of lsqr_fwd_kernel evaluates the scalar recurrence and the
+// stopping tests itself from the same inputs in the same order, so all of them
+// agree bit for bit without a grid barrier; workgroup 0 alone writes the
+// vectors and the state.  Scalars and vectors whose old and new values are
+// both live are double-buffered by iteration parity: x_j lives in x[j & 1],
+// w_j in w[j & 1], the state after step j in S[(j + 1) & 1].
+//
+// The correlation is output-stationary: one wave owns one 16 x 16 tile
+// (mt <= nt) of G = X_F diag(v) X_F^T, the workgroup stages the real-embedded
+// steering vectors of a chunk of free pixels in LDS, and the Hermitian mirror
+// of each off-diagonal tile is written by the same wave.  No partial sums, no
+// reduction kernel.  The steering vectors of the free set are generated once
+// per subproblem (xf_kernel, 2Pp x |F| floats) and read by every LSQR step.
+#include "os_tiles.h"
+
+namespace clsimg {
+
+constexpr int kXs = 12288;  // LDS floats of staged steering entries
+
+__host__ __device__ inline int os_row_stride(int Pp) { return 2 * Pp + 16; }
+__host__ __device__ inline int os_chunk(int Pp) { return (kXs / os_row_stride(Pp)) & ~15; }
+
+// X_F[k][2p + s] = Re/Im a_{Flist[k]}[p]  (pixel-major, 2Pp floats per pixel)
+__global__ void xf_kernel(Tables tab, const int* __restrict__ Flist, int n, float* __restrict__ xf) {
+  const int Pp = tab.Pp;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * Pp; e += gridDim.x * blockDim.x) {
+    const int k = e / Pp, p = e - k * Pp;
+    const int pix = Flist[k];
+    *reinterpret_cast<float2*>(xf + (size_t)k * 2 * Pp + 2 * p) = tab.a(p, pix % tab.nl, pix / tab.nl);
+  }
+}
+
+// Stage a chunk of X_F rows and weights in LDS and accumulate the tile.
+__device__ inline v4f os_accumulate(const float* __restrict__ xf, int n, int Pp, const float* vals,
+                                    const int* gidx, double scale, bool active, int mt, int nt,
+                                    float* xs, float* vs) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int RS = os_row_stride(Pp), CH = os_chunk(Pp);
+  const int r4 = Pp / 2;  // float4s per pixel row
+  v4f acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < n; c0 += CH) {
+    const int cn = min(CH, n - c0);
+    const int cn16 = (cn + 15) & ~15;
+    __syncthreads();
+    for (int e = tid; e < cn16 * r4; e += kThreads) {
+      const int k = e / r4, j = e - k * r4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (k < cn) v = *reinterpret_cast<const float4*>(xf + (size_t)(c0 + k) * 2 * Pp + 4 * j);
+      *reinterpret_cast<float4*>(xs + k * RS + 4 * j) = v;
+    }
+    for (int k = tid; k < cn16; k += kThreads) {
+      float wv = 0.f;
+      if (k < cn) wv = (float)((double)(gidx ? vals[gidx[c0 + k]] : vals[c0 + k]) * scale);
+      vs[k] = wv;
+    }
+    __syncthreads();
+    if (active) {
+      for (int kk = 0; kk < cn16; kk += 16) {
+        float a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = kk + 4 * u + q;
+          a[u] = xs[k * RS + 16 * mt + c16] * vs[k];
+          b[u] = xs[k * RS + 16 * nt + c16];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = mfma16x16x4(a[u], b[u], acc[u]);
+      }
+    }
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// out = cK K + cB Bold (Bold preloaded), Ut fragments, sum |out|^2 of the lane.
+__device__ inline double os_write(v4f acc, const OsSlots& sl, const float2* Bold, int P, int Pp,
+                                  float cK, float cB, float2* out, float* frag) {
+  float2 K[4], r[4];
+  os_assemble(acc, sl, K);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = make_float2(cK * K[i].x + cB * Bold[i].x, cK * K[i].y + cB * Bold[i].y);
+  return os_store(sl, r, P, Pp, out, frag);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
+  __shared__ float xs[kXs];
+  __shared__ float vs[kXs / 16];
+  __shared__ double red_a[4], red_b[4], red_d[4], red_x[4];
+  __shared__ double sc[8];
+  __shared__ LsqrState sS;
+  __shared__ int s_done;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int it = pr.it, n = pr.n;
+  const bool first = (it == 1);
+  const bool wg0 = (blockIdx.x == 0);
+  LsqrState* Sprev = pr.S + ((it - 1) & 1);
+  LsqrState* Scur = pr.S + (it & 1);
+  float* x_prev = (it & 1) ? pr.x1 : pr.x0;  // x_{it-2}
+  float* x_cur = (it & 1) ? pr.x0 : pr.x1;   // x_{it-1}
+  float* w_prev = (it & 1) ? pr.w0 : pr.w1;  // w_{it-1}
+  float* w_cur = (it & 1) ? pr.w1 : pr.w0;   // w_it
+  const int MT = pr.MT, P = pr.P, Pp = 8 * MT;
+  const int tp = blockIdx.x * 4 + w;
+  const bool active = tp < pr.ntp;
+  int mt = 0, nt = 0;
+  if (active) tri_tile(tp, MT, mt, nt);
+  const OsSlots sl = os_slots(mt, nt, c16, q, P, active);
+
+  // ---- every independent load first: flag, state, partials, old u, vectors ----
+  const int was_done = *pr.done;
+  if (tid == 0) sS = *Sprev;
+  double a2 = 0.0, b2 = 0.0;
+  for (int i = tid; i < pr.nalpha; i += kThreads) a2 += pr.alpha_part[i];
+  for (int i = tid; i < pr.nbeta_in; i += kThreads) b2 += pr.beta_in[i];
+  float2 uold[4];
+  os_prefetch(sl, pr.u, P, uold);
+  float vr0 = 0.f, wp0 = 0.f, xp0 = 0.f;
+  if (tid < n) {
+    vr0 = pr.vraw[tid];
+    if (!first) {
+      wp0 = w_prev[tid];
+      xp0 = x_prev[tid];
+    }
+  }
+  if (was_done) return;  // uniform: a finished solve
+
+  // ---- finish LSQR step it-1 (every workgroup, identical arithmetic) ----
+  a2 = block_sum_d(a2, red_a);
+  b2 = block_sum_d(b2, red_b);
+  if (tid == 0) {
+    const double alpha = sqrt(a2), beta = sqrt(b2);
+    sc[0] = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v = v_raw / alpha
+    if (first) {
+      sc[1] = sc[2] = sc[3] = 0.0;
+    } else {
+      const double rho = hypot(sS.rhobar, beta);
+      const double c = sS.rhobar / rho, sn = beta / rho;
+      sc[1] = 1.0 / rho;          // d = w / rho
+      sc[2] = c * sS.phibar;      // phi
+      sc[3] = sn * alpha / rho;   // theta / rho
+      sc[4] = c;
+      sc[5] = sn;
+    }
+  }
+  __syncthreads();
+  const double iv = sc[0], ir = sc[1], phi = sc[2], tr = sc[3];
+  double dd = 0.0, xx = 0.0;
+  for (int k = tid; k < n; k += kThreads) {
+    const bool pre = k == tid;
+    const float vf = (float)((double)(pre ? vr0 : pr.vraw[k]) * iv);
+    if (first) {
+      if (wg0) {
+        pr.vnorm[k] = vf;
+        w_cur[k] = vf;
+        x_cur[k] = 0.f;
+      }
+    } else {
+      const double wk = (double)(pre ? wp0 : w_prev[k]);
+      const double dk = wk * ir;
+      dd += dk * dk;
+      const float xk = (float)((double)(pre ? xp0 : x_prev[k]) + phi * dk);
+      xx += (double)xk * xk;
+      if (wg0) {
+        pr.vnorm[k] = vf;
+        x_cur[k] = xk;
+        w_cur[k] = (float)((double)vf - tr * wk);
+      }
+    }
+  }
+  dd = block_sum_d(dd, red_d);
+  xx = block_sum_d(xx, red_x);
+  if (tid == 0) {
+    LsqrState S = sS;  // tolerances and limits travel with the state
+    const double alpha = sqrt(a2), beta = sqrt(b2);
+    if (first) {
+      S.alpha = alpha;
+      S.beta = beta;
+      S.rhobar = alpha;
+      S.phibar = beta;
+      S.bnorm = beta;
+      S.anorm2 = 0.0;
+      S.ddnorm = 0.0;
+      S.rnorm = beta;
+      S.arnorm = alpha * beta;
+      S.anorm = S.acond = S.xnorm = 0.0;
+      S.itn = 0;
+      S.istop = (n == 0 || alpha == 0.0 || beta == 0.0) ? 4 : 0;
+    } else {
+      const double c = sc[4], sn = sc[5];
+      S.anorm2 += S.alpha * S.alpha + beta * beta;
+      S.rhobar = -c * alpha;
+      S.phibar = sn * S.phibar;
+      S.alpha = alpha;
+      S.beta = beta;
+      S.ddnorm += dd;
+      S.rnorm = S.phibar;
+      S.arnorm = S.phibar * alpha * fabs(c);
+      S.anorm = sqrt(S.anorm2);
+      S.acond = S.anorm * sqrt(S.ddnorm);
+      S.xnorm = sqrt(xx);
+      S.itn = it - 1;
+      int istop = 0;
+      if (S.rnorm <= S.btol * S.bnorm + S.atol * S.anorm * S.xnorm) istop = 1;
+      else if (S.arnorm <= S.atol * S.anorm * S.rnorm) istop = 2;
+      else if (S.acond >= S.conlim) istop = 3;
+      else if (alpha == 0.0 || beta == 0.0) istop = 4;
+      else if (S.itn >= S.itnlim) istop = 7;
+      S.istop = istop;
+    }
+    S.done = S.istop != 0;
+    s_done = S.done;
+    if (wg0) {
+      *Scur = S;
+      if (S.done) *pr.Sfinal = S;
+    }
+    sc[7] = alpha > 0.0 && beta > 0.0 ? -alpha / beta : 0.0;
+  }
+  __syncthreads();
+  if (s_done) {
+    // the final iterate x_{itn} stays in x[itn & 1]; the state went to Sfinal
+    if (wg0 && tid == 0) *pr.done = 1;
+    return;
+  }
+
+  // ---- u_{it+1} = Psi_F v_it - (alpha/beta) u_it ----
+  const v4f acc = os_accumulate(pr.xf, n, Pp, pr.vraw, nullptr, iv, active, mt, nt, xs, vs);
+  double nrm = os_write(acc, sl, uold, P, Pp, 1.f, (float)sc[7], pr.u, pr.frag);
+  nrm = wave_sum_d(nrm);
+  if (lane == 0) pr.beta_out[tp] = nrm;
+}
+
+// Plain output-stationary correlation over the free set:
+//   out = cK * sum_k vals[gidx ? gidx[k] : k] a_k a_k^H + cB * B,  Ut fragments of out.
+__global__ __launch_bounds__(kThreads) void corr_os_kernel(CorrOsParams pr) {
+  __shared__ float xs[kXs];
+  __shared__ float vs[kXs / 16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int MT = pr.MT, P = pr.P, Pp = 8 * MT;
+  const int tp = blockIdx.x * 4 + w;
+  const bool active = tp < MT * (MT + 1) / 2;
+  int mt = 0, nt = 0;
+  if (active) tri_tile(tp, MT, mt, nt);
+  const OsSlots sl = os_slots(mt, nt, c16, q, P, active);
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
+  float2 bold[4];
+  os_prefetch(sl, pr.B, P, bold);
+  if (stop) return;
+  const v4f acc = os_accumulate(pr.xf, pr.n, Pp, pr.vals, pr.gidx, 1.0, active, mt, nt, xs, vs);
+  (void)os_write(acc, sl, bold, P, Pp, pr.cK, pr.cB, pr.out, pr.frag);
+}
+
+__global__ void lsqr_setup_kernel(LsqrState* S0, int* done, double atol, double btol,
+                                  double conlim, int itnlim) {
+  LsqrState S = {};
+  S.atol = atol;
+  S.btol = btol;
+  S.conlim = conlim;
+  S.itnlim = itnlim;
+  *S0 = S;
+  *done = 0;
+}
+
+__global__ void lsqr_setup2_kernel(int* done, unsigned* bar, int* err) {
+  *done = 0;
+  *bar = 0u;
+  *err = 0;
+}
+
+hipError_t launch_lsqr_setup2(LsqrState* S0, int* done, unsigned* bar, int* err, double atol,
+                              double btol, double conlim, int itnlim, hipStream_t st) {
+  (void)S0; (void)atol; (void)btol; (void)conlim; (void)itnlim;
+  hipLaunchKernelGGL(lsqr_setup2_kernel, dim3(1), dim3(1), 0, st, done, bar, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsqr_setup(LsqrState* S0, int* done, double atol, double btol, double conlim,
+                             int itnlim, hipStream_t st) {
+  hipLaunchKernelGGL(lsqr_setup_kernel, dim3(1), dim3(1), 0, st, S0, done, atol, btol, conlim, itnlim);
+  return hipGetLastError();
+}
+
+int lsqr_fwd_waves(int P) {
+  const int MT = pad_p(P) / 8;
+  const int ntp = MT * (MT + 1) / 2;
+  return 4 * ((ntp + 3) / 4);
+}
+
+hipError_t launch_lsqr_fwd(const LsqrFwdParams& pr, hipStream_t st) {
+  const int blocks = (pr.ntp + 3) / 4;
+  hipLaunchKernelGGL(lsqr_fwd_kernel, dim3(blocks), dim3(kThreads), 0, st, pr);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_os(const CorrOsParams& pr, hipStream_t st) {
+  const int ntp = pr.MT * (pr.MT + 1) / 2;
+  hipLaunchKernelGGL(corr_os_kernel, dim3((ntp + 3) / 4), dim3(kThreads), 0, st, pr);
+  return hipGetLastError();
+}
+
+hipError_t launch_xf(const Tables& tab, const int* Flist, int n, float* xf, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int grid = (n * tab.Pp + kThreads - 1) / kThreads;
+  if (grid > 2048) grid = 2048;
+  hipLaunchKernelGGL(xf_kernel, dim3(grid), dim3(kThreads), 0, st, tab, Flist, n, xf);
+  return hipGetLastError();
+}
+
+}  // namespace clsimg

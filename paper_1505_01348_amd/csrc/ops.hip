@@ -12,39 +12,64 @@ namespace clsimg {
 
 // ---------------------------------------------------------------------------
 // Beamforming: g_k = x_k^T Ut x_k for the pixels of a list (or 0..n-1).
-// Y = Ut X on MFMA (A operand = Ut fragments staged through LDS, B operand =
-// steering entries generated in registers), then a column dot product with X.
-constexpr int kLdsFloats = 16384;  // 64 KiB of Ut fragments per workgroup
+// Y = Ut X on MFMA.  Per K-chunk the workgroup stages Ut (A operands, kept
+// resident across tiles when it fits) and the steering entries of its T
+// pixels (B operands) in LDS, so that every global load of a chunk is in
+// flight at once; then a column dot product of Y with X.
+constexpr int kLdsU = 12288;     // 48 KiB of Ut per workgroup
+constexpr int kMaxKch = 24;      // k-steps per chunk (96 real rows of X)
+constexpr int kXsRows = 4 * kMaxKch;
+
+__host__ __device__ inline int adjoint_kch(int MT, int KS) {
+  int k = kLdsU / (MT * 64);
+  k = k < KS ? k : KS;
+  return k < kMaxKch ? k : kMaxKch;
+}
 
 template <int MTW, int NTW, int WM, class Epi>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi) {
-  if (pr.stop_flag && *pr.stop_flag) return;
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
+  const typename Epi::Ctx cx = epi.init();  // per-block constants of the epilogue
+  if (stop) return;
   constexpr int WN = 4 / WM;
   constexpr int T = WN * NTW * 16;
+  constexpr int TS = T + 16;  // padded row stride of the staged X (bank spread)
   static_assert(T <= kThreads, "tile wider than the block");
-  __shared__ float lds[kLdsFloats];
+  __shared__ float lds[kLdsU];
+  __shared__ float xs[kXsRows * TS];
   __shared__ float gsh[WM][T];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ int spix[T];
+  __shared__ int sil[T], sim[T];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
   const int wm = w % WM, wn = w / WM;
   const int c16 = lane & 15, q = lane >> 4;
+  // row tiles held in LDS: MTA = WM*MTW >= MT, the ones past MT are zero so
+  // that the MFMA loop carries no branch
+  constexpr int MTA = WM * MTW;
   const int MT = pr.MT, KS = pr.KS;
-  const int kch = min(KS, kLdsFloats / (MT * 64));
+  const int kch = adjoint_kch(MTA, KS);
   const bool resident = (kch == KS);
   const int ntiles = (pr.n + T - 1) / T;
   const Tables tab = pr.tab;
   bool loaded = false;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    int il[NTW], im[NTW];
-    bool valid[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) {
-      const int col = tile * T + (wn * NTW + t) * 16 + c16;
-      int pix = col < pr.n ? (pr.idx ? pr.idx[col] : col) : 0;
-      valid[t] = col < pr.n && (unsigned)pix < (unsigned)tab.Q;
-      if (!valid[t]) pix = 0;
-      il[t] = pix % tab.nl;
-      im[t] = pix / tab.nl;
+    __syncthreads();
+    if (tid < T) {
+      const int col = tile * T + tid;
+      int pix = -1;
+      if (col < pr.n) {
+        pix = pr.idx ? pr.idx[col] : col;
+        if ((unsigned)pix >= (unsigned)tab.Q) pix = -1;
+      }
+      spix[tid] = pix;
+      const int pp = pix < 0 ? 0 : pix;
+      const int im = pp / tab.nl;
+      sil[tid] = pp - im * tab.nl;
+      sim[tid] = im;
     }
+    const int ecol = tile * T + tid;
+    const typename Epi::Pre pf = epi.prefetch(ecol, tid < T && ecol < pr.n);
     v4f acc[MTW][NTW];
 #pragma unroll
     for (int mi = 0; mi < MTW; ++mi)
@@ -53,54 +78,76 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
 
     for (int kc0 = 0; kc0 < KS; kc0 += kch) {
       const int kn = min(kch, KS - kc0);
+      __syncthreads();
       if (!(resident && loaded)) {
-        __syncthreads();
         if (pr.U) {
           // stage Ut straight from the complex matrix: Ut[2p+s][2q+u]
-          const int ne = MT * kn * 64;
-          for (int e = threadIdx.x; e < ne; e += kThreads) {
-            const int mt = e / (kn * 64);
-            const int r = e - mt * kn * 64;
-            const int j = r >> 6, l = r & 63;
-            const int row = 16 * mt + (l & 15), col = 4 * (kc0 + j) + (l >> 4);
-            const int p = row >> 1, s = row & 1, qq = col >> 1, u = col & 1;
-            const float2 v = (p < pr.P && qq < pr.P) ? pr.U[p * pr.P + qq] : make_float2(0.f, 0.f);
+          // wave w fills blocks (mt, j) = w, w+4, ...; the lane is the fragment slot
+          const int l = lane, s = l & 1, u = (l >> 4) & 1;
+          int mt = 0, j = w;
+          while (j >= kn) {
+            j -= kn;
+            ++mt;
+          }
+          for (; mt < MTA;) {
+            const int p = 8 * mt + ((l & 15) >> 1), qq = 2 * (kc0 + j) + (l >> 5);
+            const float2 v = (mt < MT && p < pr.P && qq < pr.P) ? pr.U[p * pr.P + qq]
+                                                                 : make_float2(0.f, 0.f);
             lds[(mt * kch + j) * 64 + l] = (s == u) ? v.x : (s == 0 ? -v.y : v.y);
+            j += 4;
+            while (j >= kn) {
+              j -= kn;
+              ++mt;
+            }
           }
         } else {
-          const int n4 = MT * kn * 16;
-          for (int e = threadIdx.x; e < n4; e += kThreads) {
+          const int n4 = MTA * kn * 16;
+          for (int e = tid; e < n4; e += kThreads) {
             const int mt = e / (kn * 16);
             const int r = e - mt * kn * 16;
             const int j = r >> 4, l4 = r & 15;
-            const float4 val = *reinterpret_cast<const float4*>(
-                pr.frag + ((size_t)(mt * KS + kc0 + j) * 64 + l4 * 4));
+            float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (mt < MT)
+              val = *reinterpret_cast<const float4*>(pr.frag + ((size_t)(mt * KS + kc0 + j) * 64 + l4 * 4));
             *reinterpret_cast<float4*>(lds + ((mt * kch + j) * 64 + l4 * 4)) = val;
           }
         }
-        __syncthreads();
         loaded = true;
       }
-      for (int j = 0; j < kn; ++j) {
-        const int p = 2 * (kc0 + j) + (q >> 1);
-        float b[NTW];
-#pragma unroll
-        for (int t = 0; t < NTW; ++t) {
-          const float2 a = tab.a(p, il[t], im[t]);
-          b[t] = valid[t] ? ((q & 1) ? a.y : a.x) : 0.f;
+      // steering entries of antennas 2kc0 .. 2(kc0+kn)-1 for the T pixels
+      const int na = 2 * kn;
+      if (pr.xf) {
+        const int nr = 2 * na, ldx = 2 * tab.Pp;
+        for (int e = tid; e < nr * T; e += kThreads) {
+          const int c = e / nr, row = e - c * nr;
+          const int col = tile * T + c;
+          xs[row * TS + c] = (spix[c] >= 0) ? pr.xf[(size_t)col * ldx + 4 * kc0 + row] : 0.f;
         }
-#pragma unroll
-        for (int mi = 0; mi < MTW; ++mi) {
-          const int mt = wm * MTW + mi;
-          if (mt < MT) {
-            const float av = lds[(mt * kch + j) * 64 + lane];
-#pragma unroll
-            for (int t = 0; t < NTW; ++t) acc[mi][t] = mfma16x16x4(av, b[t], acc[mi][t]);
-          }
+      } else {
+        for (int e = tid; e < na * T; e += kThreads) {
+          const int pl = e / T, c = e - pl * T;  // T is a power of two
+          float2 a = make_float2(0.f, 0.f);
+          if (spix[c] >= 0) a = tab.a(2 * kc0 + pl, sil[c], sim[c]);
+          xs[(2 * pl) * TS + c] = a.x;
+          xs[(2 * pl + 1) * TS + c] = a.y;
         }
       }
+      __syncthreads();
+#pragma unroll 2
+      for (int j = 0; j < kn; ++j) {
+        float b[NTW];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) b[t] = xs[(4 * j + q) * TS + (wn * NTW + t) * 16 + c16];
+        float av[MTW];
+#pragma unroll
+        for (int mi = 0; mi < MTW; ++mi) av[mi] = lds[((wm * MTW + mi) * kch + j) * 64 + lane];
+#pragma unroll
+        for (int mi = 0; mi < MTW; ++mi)
+#pragma unroll
+          for (int t = 0; t < NTW; ++t) acc[mi][t] = mfma16x16x4(av[mi], b[t], acc[mi][t]);
+      }
     }
-    // column dot product: rows 16mt + 4q + r hold antenna 8mt + 2q + r/2, part r%2
+    // column dot product: row 16mt + 4q + r of X against the same row of Y
     float gp[NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) gp[t] = 0.f;
@@ -108,13 +155,34 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
     for (int mi = 0; mi < MTW; ++mi) {
       const int mt = wm * MTW + mi;
       if (mt < MT) {
-        const int p0 = 8 * mt + 2 * q;
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
-          const float2 a0 = tab.a(p0, il[t], im[t]);
-          const float2 a1 = tab.a(p0 + 1, il[t], im[t]);
-          gp[t] += a0.x * acc[mi][t][0] + a0.y * acc[mi][t][1] + a1.x * acc[mi][t][2] +
-                   a1.y * acc[mi][t][3];
+          const int cl = (wn * NTW + t) * 16 + c16;
+          float x0, x1, x2, x3;
+          if (resident) {
+            const int r0 = 16 * mt + 4 * q;
+            x0 = xs[(r0 + 0) * TS + cl];
+            x1 = xs[(r0 + 1) * TS + cl];
+            x2 = xs[(r0 + 2) * TS + cl];
+            x3 = xs[(r0 + 3) * TS + cl];
+          } else if (pr.xf) {
+            const float* xr = pr.xf + (size_t)(tile * T + cl) * 2 * tab.Pp + 16 * mt + 4 * q;
+            const bool v = spix[cl] >= 0;
+            x0 = v ? xr[0] : 0.f;
+            x1 = v ? xr[1] : 0.f;
+            x2 = v ? xr[2] : 0.f;
+            x3 = v ? xr[3] : 0.f;
+          } else {
+            const int pix = spix[cl];
+            float2 a0 = make_float2(0.f, 0.f), a1 = a0;
+            if (pix >= 0) {
+              const int il = pix % tab.nl, im = pix / tab.nl;
+              a0 = tab.a(8 * mt + 2 * q, il, im);
+              a1 = tab.a(8 * mt + 2 * q + 1, il, im);
+            }
+            x0 = a0.x; x1 = a0.y; x2 = a1.x; x3 = a1.y;
+          }
+          gp[t] += x0 * acc[mi][t][0] + x1 * acc[mi][t][1] + x2 * acc[mi][t][2] + x3 * acc[mi][t][3];
         }
       }
     }
@@ -129,24 +197,23 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
       for (int t = 0; t < NTW; ++t) gsh[wm][(wn * NTW + t) * 16 + c16] = gp[t];
     }
     __syncthreads();
-    const int c = threadIdx.x;
-    const int col = tile * T + c;
+    const int col = tile * T + tid;
     float g = 0.f;
     bool ok = false;
     int pix = 0;
-    if (c < T) {
+    if (tid < T) {
 #pragma unroll
-      for (int k = 0; k < WM; ++k) g += gsh[k][c];
+      for (int k = 0; k < WM; ++k) g += gsh[k][tid];
       ok = col < pr.n;
       if (ok) {
-        pix = pr.idx ? pr.idx[col] : col;
-        if ((unsigned)pix >= (unsigned)tab.Q) {  // invalid pixel index: NaN output
+        pix = spix[tid];
+        if (pix < 0) {  // invalid pixel index: NaN output
           pix = 0;
           g = __builtin_nanf("");
         }
       }
     }
-    epi(tile, col, pix, g, ok);
+    epi(tile, col, pix, g, ok, cx, pf);
   }
 }
 
@@ -444,6 +511,25 @@ hipError_t launch_adjoint_epi(const AdjParams& pr, const Epi& epi, hipStream_t s
 }  // namespace
 
 int adjoint_tile_width(int MT) { return (MT > 12 && MT <= 24) ? 32 : 64; }
+
+// Narrow tiles (two waves split the rows, T = 32) for the small free sets of
+// the LSQR subproblems when the row tiles divide evenly.
+int adjoint_lsqr2_tile_width(int MT, int n) {
+  return (MT <= 6 && n <= 1024) ? 32 : adjoint_tile_width(MT);
+}
+
+hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st) {
+  if (pr.n <= 0) return hipSuccess;
+  if (adjoint_lsqr2_tile_width(pr.MT, pr.n) == 32 && pr.MT <= 6) {
+    const int ntiles = (pr.n + 31) / 32;
+    if (pr.MT <= 3)
+      hipLaunchKernelGGL((adjoint_kernel<2, 1, 2, EpiLsqrV2>), dim3(ntiles), dim3(kThreads), 0, st, pr, epi);
+    else
+      hipLaunchKernelGGL((adjoint_kernel<3, 1, 2, EpiLsqrV2>), dim3(ntiles), dim3(kThreads), 0, st, pr, epi);
+    return hipGetLastError();
+  }
+  return launch_adjoint_epi(pr, epi, st);
+}
 
 hipError_t launch_adjoint_store(const AdjParams& pr, float* out, float scale, hipStream_t st) {
   return launch_adjoint_epi(pr, EpiStore{out, scale}, st);

@@ -8,20 +8,37 @@ namespace clsimg {
 constexpr int kCtl = 1024;  // single-workgroup control kernels
 
 // ---------------------------------------------------------------------------
-// Sorted index lists of F (state 1) and U (state 2); one workgroup.
+// Sorted index lists of F (state 1) and U (state 2); one workgroup.  Each
+// thread owns a contiguous run of 16-byte words of the state array.
 __global__ __launch_bounds__(kCtl) void compact_kernel(const uint8_t* __restrict__ state, int Q,
                                                        int* __restrict__ Flist,
                                                        int* __restrict__ Ulist,
                                                        SolveDecision* dec) {
   __shared__ int sF[kCtl], sU[kCtl];
   const int tid = threadIdx.x;
-  const int per = (Q + kCtl - 1) / kCtl;
+  const bool vec = (reinterpret_cast<uintptr_t>(state) & 15) == 0;
+  const int per = 16 * ((Q + 16 * kCtl - 1) / (16 * kCtl));
   const int b = tid * per, e = min(Q, b + per);
   int cf = 0, cu = 0;
-  for (int i = b; i < e; ++i) {
-    const uint8_t s = state[i];
-    cf += (s == 1);
-    cu += (s == 2);
+  for (int i = b; i < e; i += 16) {
+    if (vec && i + 16 <= e) {
+      const uint4 wv = *reinterpret_cast<const uint4*>(state + i);
+      const uint32_t ws[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t sv = (ws[j] >> (8 * k)) & 0xFFu;
+          cf += (sv == 1);
+          cu += (sv == 2);
+        }
+    } else {
+      for (int k = i; k < min(e, i + 16); ++k) {
+        const uint8_t sv = state[k];
+        cf += (sv == 1);
+        cu += (sv == 2);
+      }
+    }
   }
   sF[tid] = cf;
   sU[tid] = cu;
@@ -36,10 +53,12 @@ __global__ __launch_bounds__(kCtl) void compact_kernel(const uint8_t* __restrict
     __syncthreads();
   }
   int of = sF[tid] - cf, ou = sU[tid] - cu;
-  for (int i = b; i < e; ++i) {
-    const uint8_t s = state[i];
-    if (s == 1) Flist[of++] = i;
-    else if (s == 2) Ulist[ou++] = i;
+  if (cf + cu > 0) {
+    for (int i = b; i < e; ++i) {
+      const uint8_t sv = state[i];
+      if (sv == 1) Flist[of++] = i;
+      else if (sv == 2) Ulist[ou++] = i;
+    }
   }
   if (tid == kCtl - 1) {
     dec->nF = sF[tid];
@@ -169,7 +188,9 @@ __global__ __launch_bounds__(kCtl) void lsqr_update_kernel(LsqrState* s, const d
 // move along p = z - sigma_F by the largest feasible step (eq. mumax) and move
 // the first blocking pixel to its bound.  Sets dec->grad_done = 0 only when a
 // feasible z was accepted (the gradient kernels run only then).
-__global__ __launch_bounds__(kCtl) void step_kernel(const LsqrState* s, const float* __restrict__ x,
+__global__ __launch_bounds__(kCtl) void step_kernel(const int* done, const int* err, const LsqrState* s,
+                                                    const float* __restrict__ x0,
+                                                    const float* __restrict__ x1,
                                                     const int* __restrict__ Flist, int nF,
                                                     float* __restrict__ sigma,
                                                     const float* __restrict__ gamma,
@@ -180,13 +201,16 @@ __global__ __launch_bounds__(kCtl) void step_kernel(const LsqrState* s, const fl
   __shared__ int s_k[kCtl / 64];
   __shared__ float s_mz[kCtl / 64];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  if (nF > 0 && !s->done) {
+  if (nF > 0 && !*done) {
     if (tid == 0) {
       dec->lsqr_done = 0;
       dec->grad_done = 1;
+      dec->lsqr_err = err ? *err : 0;
     }
     return;
   }
+  // the final LSQR iterate x_itn is kept in buffer itn & 1
+  const float* __restrict__ x = (nF > 0 && (s->itn & 1)) ? x1 : x0;
   // feasibility (non-strict, no tolerance)
   int ok = 1;
   float mz = 3.0e38f;
@@ -217,6 +241,7 @@ __global__ __launch_bounds__(kCtl) void step_kernel(const LsqrState* s, const fl
       dec->lsqr_itn = nF > 0 ? s->itn : 0;
       dec->lsqr_istop = nF > 0 ? s->istop : 0;
       dec->feasible = 1;
+      dec->lsqr_err = 0;
       dec->margin_z = mz;
       dec->ib = -1;
       dec->grad_done = 0;
@@ -283,6 +308,7 @@ __global__ __launch_bounds__(kCtl) void step_kernel(const LsqrState* s, const fl
     dec->lsqr_itn = s->itn;
     dec->lsqr_istop = s->istop;
     dec->feasible = 0;
+    dec->lsqr_err = 0;
     dec->ib = ib;
     dec->ib_to = to_upper ? 2 : 0;
     dec->mu_max = (float)mu;
@@ -351,10 +377,11 @@ hipError_t launch_lsqr_update(LsqrState* s, const double* beta_part, int nbeta,
   return hipGetLastError();
 }
 
-hipError_t launch_step(const LsqrState* s, const float* x, const int* Flist, int nF, float* sigma,
-                       const float* gamma, uint8_t* state, SolveDecision* dec, hipStream_t st) {
-  hipLaunchKernelGGL(step_kernel, dim3(1), dim3(kCtl), 0, st, s, x, Flist, nF, sigma, gamma, state,
-                     dec);
+hipError_t launch_step(const int* done, const int* err, const LsqrState* s, const float* x0,
+                       const float* x1, const int* Flist, int nF, float* sigma, const float* gamma,
+                       uint8_t* state, SolveDecision* dec, hipStream_t st) {
+  hipLaunchKernelGGL(step_kernel, dim3(1), dim3(kCtl), 0, st, done, err, s, x0, x1, Flist, nF, sigma,
+                     gamma, state, dec);
   return hipGetLastError();
 }
 

@@ -244,3 +244,22 @@ def test_solve_c1_image_error(gpu_lib, ctx, scenes):
     print("state mismatches", int(np.sum(state != ref.state)), flush=True)
     np.testing.assert_array_equal(state, ref.state)
     _assert_close(sigma, ref.sigma, what="solve sigma c1")
+
+
+@pytest.mark.parametrize("path", ["1", "2", "3"])
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_solve_each_lsqr_engine_matches_oracle(gpu_lib, scenes, name, path, monkeypatch):
+    # every LSQR engine (one workgroup, one cooperative kernel, two kernels per
+    # step) must reproduce the oracle's solve
+    monkeypatch.setenv("CLSIMG_LSQR_PATH", path)
+    sc = scenes[name]
+    print(f"case solve {name} LSQR engine {path}", flush=True)
+    ctx2 = gpu_lib.Context(0)
+    try:
+        ref, _, _ = _oracle_solve(sc)
+        sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx2, sc)
+    finally:
+        ctx2.close()
+    print("gpu stats", stats, flush=True)
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what=f"solve sigma {name} engine {path}")

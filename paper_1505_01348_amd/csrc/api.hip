@@ -43,7 +43,7 @@ struct clsimg_ctx {
   size_t h_stage_bytes = 0;
   hipEvent_t stage_done = nullptr;
   // workspace
-  DevBuf frag_r, frag_u, part, beta_part, alpha_part, keys;
+  DevBuf frag_r, frag_u, frag_b, part, beta_part, alpha_part, keys;
   DevBuf B0, Bb, u, E, Rinv, W, Li;
   DevBuf Flist, Ulist, v, w, x, eps, mf, gamma;
   DevBuf lsqr, dec, status;
@@ -55,6 +55,8 @@ struct clsimg_ctx {
   bool trace = false;  // CLSIMG_TRACE=1: one line per active-set step on stderr
   bool coop = false;   // cooperative launches available (multi-workgroup LSQR kernel)
   int lsqr_path = 0;   // CLSIMG_LSQR_PATH: 0 auto, 1 one workgroup, 2 cooperative, 3 two kernels/step
+  bool old_beam = false;   // CLSIMG_LDS_BEAM=1: LDS-staged beamformer for the gradient
+  bool beam_prep = false;  // CLSIMG_BEAM_PREP=1: beamformer fragments from a separate pass
 };
 
 namespace {
@@ -199,7 +201,8 @@ int ensure_workspace(clsimg_ctx* c, int P, int Q) {
   ST_TRY(ensure(c, c->part, part_floats_max(P) * sizeof(float)));
   ST_TRY(ensure(c, c->beta_part, (size_t)reduce_blocks(P) * sizeof(double)));
   ST_TRY(ensure(c, c->alpha_part, (size_t)(ntiles_adj(P, Q) + 1) * sizeof(double)));
-  ST_TRY(ensure(c, c->keys, (size_t)(ntiles_adj(P, Q) + 1) * sizeof(uint64_t)));
+  ST_TRY(ensure(c, c->keys, (size_t)(std::max(ntiles_adj(P, Q), beam_grid(Q)) + 1) * sizeof(uint64_t)));
+  ST_TRY(ensure(c, c->frag_b, (size_t)2 * (Pp / 8) * (Pp / 8 + 1) * 64 * sizeof(float)));
   ST_TRY(ensure(c, c->B0, cx));
   ST_TRY(ensure(c, c->Bb, cx));
   ST_TRY(ensure(c, c->u, cx));
@@ -254,6 +257,24 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
   return CLSIMG_OK;
 }
 
+// Full-grid beamformer for P <= 48: fragments of U, then one pass over all
+// pixels with them held in registers.
+enum BeamKind { BEAM_MF, BEAM_MVDR, BEAM_STORE };
+int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamKind kind, float* out,
+              float* eps, float eps_scale, double C, double kb, float scale, hipStream_t st) {
+  const Tables tab = tables_of(c, g, P);
+  // fragments built inside the kernel, or prepared by a separate pass
+  const float* fb = c->beam_prep ? P_<float>(c->frag_b) : nullptr;
+  const float2* Uk = c->beam_prep ? nullptr : U;
+  if (c->beam_prep) HIP_TRY(launch_beam_prep(U, P, P_<float>(c->frag_b), st));
+  switch (kind) {
+    case BEAM_MF: HIP_TRY(launch_beam_mf(fb, Uk, P, tab, out, eps, eps_scale, st)); break;
+    case BEAM_MVDR: HIP_TRY(launch_beam_mvdr(fb, Uk, P, tab, out, C, kb, st)); break;
+    default: HIP_TRY(launch_beam_store(fb, Uk, P, tab, out, scale, st)); break;
+  }
+  return CLSIMG_OK;
+}
+
 int read_back(clsimg_ctx* c, void* host, const void* dev, size_t bytes, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -277,6 +298,7 @@ int compute_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, con
   }
   if (o->bound == CLSIMG_BOUND_MF) {
     const double scale = 1.0 + (o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)o->nsamples) : 0.0);
+    if (beam_fits(P)) return beam_full(c, g, P, Rf, BEAM_STORE, gamma, nullptr, 0.f, 0, 0, (float)scale, st);
     HIP_TRY(launch_adjoint_store(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), gamma,
                                  (float)scale, st));
     return CLSIMG_OK;
@@ -286,6 +308,8 @@ int compute_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, con
   ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
   if (*c->h_status != 0) return CLSIMG_ENOTPD;
   const double kb = o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1)) : 0.0;
+  if (beam_fits(P))
+    return beam_full(c, g, P, P_<const float2>(c->Rinv), BEAM_MVDR, gamma, nullptr, 0.f, o->C, kb, 1.f, st);
   HIP_TRY(launch_adjoint_mvdr(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, P_<const float2>(c->Rinv)),
                               gamma, o->C, kb, st));
   return CLSIMG_OK;
@@ -346,6 +370,10 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
     c->coop = coop != 0;
   const char* lp = getenv("CLSIMG_LSQR_PATH");
   if (lp) c->lsqr_path = atoi(lp);
+  const char* ob = getenv("CLSIMG_LDS_BEAM");
+  c->old_beam = ob && ob[0] == '1';
+  const char* bp = getenv("CLSIMG_BEAM_PREP");
+  c->beam_prep = bp && bp[0] == '1';
   void* hp = nullptr;
   const size_t hbytes = sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + 64 * sizeof(double);
   if (hipHostMalloc(&hp, hbytes, hipHostMallocDefault) != hipSuccess ||
@@ -367,7 +395,7 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (!c) return CLSIMG_EINVAL;
   DeviceGuard guard(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->part,  &c->beta_part,
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->part,  &c->beta_part,
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
@@ -405,9 +433,9 @@ int clsimg_dirty_image(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a
   const int P = a->P, Q = g->nl * g->nm;
   ST_TRY(ensure_workspace(c, P, Q));
   ST_TRY(ensure_tables(c, a, g, st));
-  HIP_TRY(launch_adjoint_mf(
-      adj_params(c, g, P, nullptr, nullptr, Q, nullptr, reinterpret_cast<const float2*>(R)), mf, nullptr,
-      0.f, st));
+  const float2* Rf = reinterpret_cast<const float2*>(R);
+  if (beam_fits(P)) return beam_full(c, g, P, Rf, BEAM_MF, mf, nullptr, 0.f, 0, 0, 1.f, st);
+  HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, nullptr, 0.f, st));
   return CLSIMG_OK;
 }
 
@@ -447,6 +475,9 @@ int clsimg_adjoint(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, c
   ST_TRY(ensure_workspace(c, P, std::max(n, g->nl * g->nm)));
   ST_TRY(ensure_tables(c, a, g, st));
   if (n == 0) return CLSIMG_OK;
+  if (!idx && n == g->nl * g->nm && beam_fits(P))
+    return beam_full(c, g, P, reinterpret_cast<const float2*>(U), BEAM_STORE, out, nullptr, 0.f, 0, 0, 1.f,
+                     st);
   HIP_TRY(launch_adjoint_store(
       adj_params(c, g, P, nullptr, idx, n, nullptr, reinterpret_cast<const float2*>(U)), out, 1.f, st));
   return CLSIMG_OK;
@@ -530,8 +561,12 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   double flops = beam_flops(P, Q) + (o->bound != CLSIMG_BOUND_NONE ? beam_flops(P, Q) : 0.0);
   // bounds and threshold (Sec. II-D, App. A)
   const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
-  HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, eps, eps_scale,
-                            st));
+  if (beam_fits(P)) {
+    ST_TRY(beam_full(c, g, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
+  } else {
+    HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, eps, eps_scale,
+                              st));
+  }
   ST_TRY(compute_bound(c, R, a, g, o, gamma, st));
   // data B0 = R - diag(noise), its norm, the starting image and sets
   HIP_TRY(launch_sub_diag(Rf, noise_diag, P, B0, st));
@@ -558,6 +593,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   double margin_lambda = INFINITY, margin_z = INFINITY;
   int batch = 4;
   const int ntiles_Q = ntiles_adj(P, Q);
+  const bool beam_full_grid = beam_fits(P) && !c->old_beam;
   for (;;) {
     if (need_solve) {
       if (outer >= max_outer) {
@@ -612,12 +648,12 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
         f.ntp = MT * (MT + 1) / 2;
         return f;
       };
-      // LSQR engine: one cooperative kernel, else one workgroup when everything
-      // fits in its LDS, else two kernels per step (P <= 96), else the split-K
-      // correlation with separate reductions
+      // LSQR engine: one workgroup when the subproblem fits in its LDS (no grid
+      // barriers at all), else one cooperative kernel, else two kernels per
+      // step (P <= 96), else the split-K correlation with separate reductions
       const int want = c->lsqr_path;
-      const bool persist = fused && c->coop && (want == 0 || want == 2) && persist_fits(P, nF);
-      const bool one_cu = !persist && fused && (want == 0 || want == 1) && lsqr_cu_fits(P, nF);
+      const bool one_cu = fused && (want == 0 || want == 1) && lsqr_cu_fits(P, nF);
+      const bool persist = !one_cu && fused && c->coop && (want == 0 || want == 2) && persist_fits(P, nF);
       if (nF > 0) {
         const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
         if (one_cu) {
@@ -722,9 +758,17 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, bsub, 1.f, -1.f, nullptr, frag_r, nullptr,
                            grad_stop, st));
         }
-        HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys,
-                                      st));
-        HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
+        if (beam_full_grid) {
+          if (c->beam_prep) HIP_TRY(launch_beam_prep(E, P, P_<float>(c->frag_b), st));
+          HIP_TRY(launch_beam_lambda(c->beam_prep ? P_<const float>(c->frag_b) : nullptr,
+                                     c->beam_prep ? nullptr : E, P, tables_of(c, g, P), grad_stop, state,
+                                     keys, st));
+          HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
+        } else {
+          HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys,
+                                        st));
+          HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
+        }
         ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
         if (c->h_dec->lsqr_done) break;
         if (persist || one_cu || c->h_dec->lsqr_err) return CLSIMG_EHIP;  // LSQR kernel did not finish

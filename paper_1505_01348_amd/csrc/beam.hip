@@ -1,0 +1,291 @@
+// Register-resident beamformer g_i = Re(a_i^H U a_i) over a whole pixel grid
+// (the adjoint of Sec. IV-C, eq. psiH, on all pixels: the dirty image of
+// eq. mfdimg, the MVDR power of eq. wmvdr and the gradient of eq. gls).
+//
+// With x_i the real embedding of a_i, g_i = x_i^T Ut x_i.  The embedding is
+// ordered so that one MFMA lane generates whole complex entries: position
+// 4 kc + q (kc = 0 .. 2Pp/4 - 1, q = 0 .. 3) holds component (kc & 1) of
+// antenna 4 (kc >> 1) + q.  In that order Ut is split into 16 x 16 tiles and
+// only the lower block triangle is kept, off-diagonal tiles doubled:
+//   x^T Ut x = sum_m x_m^T Ut_mm x_m + 2 sum_{k<m} x_m^T Ut_mk x_k.
+// Inside each row tile the rows are stored transposed in (q, r) (row
+// 16m + 4q + r holds tile row 16m + 4r + q), so that after the MFMAs the
+// accumulator element r of lane (c16, q) multiplies exactly the B operand
+// that lane loaded for chunk kc = 4m + r: the column dot needs no exchange
+// between lanes beyond the final sum over q.
+//
+// Each wave holds all 2 MT (MT + 1) fragment registers of Ut for the whole
+// launch (built once per workgroup from U through LDS, or loaded prepared) and
+// walks 16-pixel tiles; it generates the steering entries of its tile from the
+// separable tables (one complex product per entry).  After the fragments are
+// in registers there is no LDS traffic and no barrier on the path.
+#include "kernels.h"
+
+namespace clsimg {
+
+constexpr int kBeamWaves = 4;
+constexpr int kBeamMaxMT = 6;
+
+// embedding position -> (antenna, component)
+__device__ __forceinline__ void beam_pos(int idx, int& p, int& s) {
+  const int kc = idx >> 2, q = idx & 3;
+  p = 4 * (kc >> 1) + q;
+  s = kc & 1;
+}
+
+// Fragment f = 2 m (m + 1) + kc (kc < 4 (m + 1)) for lane l holds
+// Ut[rowpos][4 kc + (l >> 4)] with rowpos = 16 m + 4 ((l & 15) & 3) + ((l & 15) >> 2),
+// Ut built from the Hermitian part of U (which leaves Re(a^H U a) unchanged).
+__global__ void beam_prep_kernel(const float2* __restrict__ U, int P, int MT, float* __restrict__ frag) {
+  const int nfr = 2 * MT * (MT + 1);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nfr * 64; e += gridDim.x * blockDim.x) {
+    const int f = e >> 6, l = e & 63;
+    int m = 0;
+    while (2 * (m + 1) * (m + 2) <= f) ++m;
+    const int kc = f - 2 * m * (m + 1);
+    const int c16 = l & 15, qq = l >> 4;
+    int p, s, p2, t;
+    beam_pos(16 * m + 4 * (c16 & 3) + (c16 >> 2), p, s);
+    beam_pos(4 * kc + qq, p2, t);
+    float v = 0.f;
+    if (p < P && p2 < P) {
+      const float2 x = U[p * P + p2], y = U[p2 * P + p];
+      const float hr = 0.5f * (x.x + y.x), hi = 0.5f * (x.y - y.y);
+      v = (s == t) ? hr : (s == 0 ? -hi : hi);
+      if ((kc >> 2) < m) v *= 2.f;
+    }
+    frag[e] = v;
+  }
+}
+
+struct BeamMF {
+  float* mf;
+  float* eps;
+  float eps_scale;
+  __device__ void init() {}
+  __device__ void operator()(int pix, float g, bool ok) {
+    if (ok) {
+      mf[pix] = g;
+      if (eps) eps[pix] = g * eps_scale;
+    }
+  }
+  __device__ void finish() {}
+};
+
+struct BeamMVDR {
+  float* gamma;
+  double C, kb_coef;
+  __device__ void init() {}
+  __device__ void operator()(int pix, float g, bool ok) {
+    if (ok) {
+      const double h = (double)g;
+      gamma[pix] = (float)(C / h + kb_coef / h);
+    }
+  }
+  __device__ void finish() {}
+};
+
+struct BeamStore {
+  float* out;
+  float scale;
+  __device__ void init() {}
+  __device__ void operator()(int pix, float g, bool ok) {
+    if (ok) out[pix] = g * scale;
+  }
+  __device__ void finish() {}
+};
+
+// Lagrange multipliers of the active pixels (eqs. etaL, etaU): lambda = g on
+// L, -g on U; the block's smallest key (ordered lambda << 32 | pixel, so ties
+// go to the lowest pixel) is written to part[blockIdx.x].
+struct BeamLambda {
+  const uint8_t* state;
+  uint64_t* part;
+  uint64_t best;
+  __device__ void init() { best = ~0ull; }
+  __device__ void operator()(int pix, float g, bool ok) {
+    if (ok) {
+      const uint8_t s = state[pix];
+      if (s != 1) {  // not free
+        const float lam = (s == 0) ? g : -g;  // L : U
+        const uint64_t key = ((uint64_t)ordered_bits(lam) << 32) | (uint32_t)pix;
+        best = key < best ? key : best;
+      }
+    }
+  }
+  __device__ void finish() {
+    __shared__ uint64_t sh[kBeamWaves];
+    const uint64_t m = block_min_u64(best, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+  }
+};
+
+// Fragments built from U by the whole workgroup: the (m, j) pairs of chunks
+// 2j, 2j + 1 of row tile m (same values as beam_prep_kernel) are dealt round
+// robin to the waves, written to LDS and then read back by every wave.  For
+// row tile m the lane's row is antenna 8m + 4((c16 >> 1) & 1) + (c16 >> 2),
+// component c16 & 1; the pair shares column antenna 4j + q and takes the two
+// components of the same Hermitian-part entry.
+template <int MT>
+__device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, int P, float* sfr, float* fa) {
+  constexpr int NPAIR = MT * (MT + 1);
+  constexpr int NFR = 2 * NPAIR;
+  constexpr int PPW = (NPAIR + kBeamWaves - 1) / kBeamWaves;
+  const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int pr0 = 4 * ((c16 >> 1) & 1) + (c16 >> 2);
+  const bool s1 = c16 & 1;
+  float2 xv[PPW], yv[PPW];
+  int mm[PPW], jj[PPW];
+#pragma unroll
+  for (int i = 0; i < PPW; ++i) {
+    const int t = min(w + kBeamWaves * i, NPAIR - 1);
+    int m = 0;
+    while ((m + 1) * (m + 2) <= t) ++m;
+    mm[i] = m;
+    jj[i] = t - m * (m + 1);
+    // clamped (valid) indices, padding masked afterwards: no branch around a
+    // load, so all of them are in flight together
+    const int p = min(8 * m + pr0, P - 1), p2 = min(4 * jj[i] + q, P - 1);
+    xv[i] = U[p * P + p2];
+    yv[i] = U[p2 * P + p];
+  }
+#pragma unroll
+  for (int i = 0; i < PPW; ++i) {
+    if (w + kBeamWaves * i < NPAIR) {
+      const int m = mm[i], j = jj[i];
+      const bool live = 8 * m + pr0 < P && 4 * j + q < P;
+      const float d = (j >> 1) < m ? 2.f : 1.f;  // chunks 2j, 2j+1 lie in column tile j >> 1
+      const float hr = live ? 0.5f * d * (xv[i].x + yv[i].x) : 0.f;
+      const float hi = live ? 0.5f * d * (xv[i].y - yv[i].y) : 0.f;
+      const int f = 2 * m * (m + 1) + 2 * j;
+      sfr[f * 64 + lane] = s1 ? hi : hr;
+      sfr[(f + 1) * 64 + lane] = s1 ? hr : -hi;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < NFR; ++f) fa[f] = sfr[f * 64 + lane];
+}
+
+// (at most two waves per SIMD: the fragments, the tile's operands and the
+// accumulators all stay in registers)
+template <int MT, class Epi>
+__global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu(1, 2))) void beam_kernel(const float* __restrict__ frag,
+                                                               const float2* __restrict__ U, int P,
+                                                               Tables tab, const int* skip, Epi epi) {
+  constexpr int KS = 4 * MT;             // 4-row chunks of the embedding
+  constexpr int NFR = 2 * MT * (MT + 1);  // fragments of the lower block triangle
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  const int Q = tab.Q, nl = tab.nl, nm = tab.nm;
+  const int ntiles = (Q + 15) >> 4;
+  const int nwav = gridDim.x * kBeamWaves;
+  // table entries of antennas 4 j + q for this lane's pixel of a tile; the
+  // loads of the next tile are issued before the current one is multiplied
+  float2 te[KS / 2], tm[KS / 2];
+  auto load_tables = [&](int tile) {
+    const int pix = min(16 * tile + c16, Q - 1);
+    const int im = pix / nl, il = pix - im * nl;
+    const float2* el = tab.El + (size_t)q * nl + il;
+    const float2* em = tab.Em + (size_t)q * nm + im;
+#pragma unroll
+    for (int j = 0; j < KS / 2; ++j) {
+      te[j] = el[(size_t)4 * j * nl];
+      tm[j] = em[(size_t)4 * j * nm];
+    }
+  };
+  int tile = blockIdx.x * kBeamWaves + (threadIdx.x >> 6);
+  if (tile < ntiles) load_tables(tile);
+  float fa[NFR];
+  if (U) {
+    __shared__ float sfr[NFR * 64];
+    beam_frags_from_u<MT>(U, P, sfr, fa);
+  } else {
+#pragma unroll
+    for (int f = 0; f < NFR; ++f) fa[f] = frag[f * 64 + lane];
+  }
+  epi.init();
+  for (; tile < ntiles; tile += nwav) {
+    const int pix = 16 * tile + c16;
+    float b[KS];
+#pragma unroll
+    for (int j = 0; j < KS / 2; ++j) {
+      const float2 a = cmul(te[j], tm[j]);
+      b[2 * j] = a.x;
+      b[2 * j + 1] = a.y;
+    }
+    if (tile + nwav < ntiles) load_tables(tile + nwav);
+    v4f acc[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KS; ++kc) {
+#pragma unroll
+      for (int m = kc >> 2; m < MT; ++m) acc[m] = mfma16x16x4(fa[2 * m * (m + 1) + kc], b[kc], acc[m]);
+    }
+    float g = 0.f;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) g += acc[m][r] * b[4 * m + r];
+    }
+    g += __shfl_xor(g, 16, 64);
+    g += __shfl_xor(g, 32, 64);
+    epi(pix, g, pix < Q && q == 0);
+  }
+  epi.finish();
+}
+
+bool beam_fits(int P) { return pad_p(P) / 8 <= kBeamMaxMT; }
+
+int beam_grid(int Q) {
+  const int ntiles = (Q + 15) / 16;
+  int g = (ntiles + kBeamWaves - 1) / kBeamWaves;
+  return g < 1 ? 1 : (g > 2048 ? 2048 : g);
+}
+
+hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st) {
+  const int MT = pad_p(P) / 8;
+  const int n = 2 * MT * (MT + 1) * 64;
+  hipLaunchKernelGGL(beam_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, U, P, MT, frag);
+  return hipGetLastError();
+}
+
+template <class Epi>
+static hipError_t launch_beam(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
+                              Epi epi, hipStream_t st) {
+  const dim3 g(beam_grid(tab.Q)), b(64 * kBeamWaves);
+  switch (tab.Pp / 8) {
+    case 1: hipLaunchKernelGGL((beam_kernel<1, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
+    case 2: hipLaunchKernelGGL((beam_kernel<2, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
+    case 3: hipLaunchKernelGGL((beam_kernel<3, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
+    case 4: hipLaunchKernelGGL((beam_kernel<4, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
+    case 5: hipLaunchKernelGGL((beam_kernel<5, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
+    case 6: hipLaunchKernelGGL((beam_kernel<6, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,
+                          float eps_scale, hipStream_t st) {
+  return launch_beam(frag, U, P, tab, nullptr, BeamMF{mf, eps, eps_scale}, st);
+}
+
+hipError_t launch_beam_mvdr(const float* frag, const float2* U, int P, const Tables& tab, float* gamma, double C,
+                            double kb_coef, hipStream_t st) {
+  return launch_beam(frag, U, P, tab, nullptr, BeamMVDR{gamma, C, kb_coef}, st);
+}
+
+hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Tables& tab, float* out,
+                             float scale, hipStream_t st) {
+  return launch_beam(frag, U, P, tab, nullptr, BeamStore{out, scale}, st);
+}
+
+hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
+                              const uint8_t* state, uint64_t* part, hipStream_t st) {
+  return launch_beam(frag, U, P, tab, skip, BeamLambda{state, part, 0}, st);
+}
+
+}  // namespace clsimg

@@ -73,6 +73,27 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+// DPP move of a double: both 32-bit halves with the same lane pattern; lanes
+// whose source is outside the pattern (or whose row is masked off) get 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_move_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, kRowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, kRowMask, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Wave sum on the VALU: row_shr 1, 2, 4, 8 leave each 16-lane row's total in
+// its lane 15; row_bcast 15 and 31 carry the row totals up to lane 63, which
+// every lane then reads.
+__device__ __forceinline__ double wave_sum_dpp_d(double v) {
+  v += dpp_move_d<0x111, 0xF>(v);
+  v += dpp_move_d<0x112, 0xF>(v);
+  v += dpp_move_d<0x114, 0xF>(v);
+  v += dpp_move_d<0x118, 0xF>(v);
+  v += dpp_move_d<0x142, 0xA>(v);
+  v += dpp_move_d<0x143, 0xC>(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
 __device__ __forceinline__ float wave_sum_f(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

@@ -274,6 +274,19 @@ hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta
                                double* alpha_part, int init, hipStream_t st);
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st);
 int adjoint_lsqr2_tile_width(int MT, int n);
+// beam.hip (register-resident full-grid beamformer, P <= 48)
+bool beam_fits(int P);
+int beam_grid(int Q);  // workgroups of a full-grid launch (= partial keys of the lambda variant)
+hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st);
+// the fragments come from frag (beam_prep layout) when U is null, else are built from U
+hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,
+                          float eps_scale, hipStream_t st);
+hipError_t launch_beam_mvdr(const float* frag, const float2* U, int P, const Tables& tab, float* gamma, double C,
+                            double kb_coef, hipStream_t st);
+hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Tables& tab, float* out,
+                             float scale, hipStream_t st);
+hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
+                              const uint8_t* state, uint64_t* part, hipStream_t st);
 // lsqr_cu.hip
 bool lsqr_cu_fits(int P, int n);
 hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st);

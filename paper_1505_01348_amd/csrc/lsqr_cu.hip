@@ -1,26 +1,29 @@
 // One LSQR solve of the free-set subproblem on one compute unit (Sec. IV-A,
-// eqs. initbeta, initu, lanczos, with the LSQR updates), for P <= 64.
+// eqs. initbeta, initu, lanczos, with the LSQR updates), for P <= 48.
 //
 // A single workgroup keeps everything in LDS for the whole solve: the
 // real-embedded steering vectors of the free pixels, the Ut fragments of u,
 // and the vectors v, w, x; each lane keeps the u elements it owns in
 // registers.  One step is, with only workgroup barriers:
 //   F  u <- Psi_F v - (alpha/beta) u over the upper-triangle 16 x 16 tiles of
-//      G = X_F diag(v) X_F^T (tiles spread over the four waves), fragments
+//      G = X_F diag(v) X_F^T (tiles spread over the 16 waves), fragments
 //      of Ut written to LDS, ||u||^2;
 //   A  g = x^T Ut x for every free pixel with the block-triangular form
 //      x^T Ut x = sum_m x_m^T Ut_mm x_m + 2 sum_{k<m} x_m^T Ut_mk x_k, so only
 //      the row tiles m >= k of each k tile are multiplied;
 //      v_raw = g / beta - beta v, ||v_raw||^2;
 //   S  FP64 rotation, vector updates and the stopping tests.
-// The first pass sets u = b.  Tile indices are compile-time constants (the
-// kernel is instantiated per row-tile count MT), so the register arrays of the
-// row slices are never indexed dynamically.
+// Each phase ends in one block sum (one barrier), two per step.
+// The first pass sets u = b.  Operands are read from LDS at run-time tile
+// offsets; only the per-tile accumulators and owned u elements sit in
+// register arrays, always at compile-time indices.
 #include "os_tiles.h"
 
 namespace clsimg {
 
 constexpr int kCuLds = 36864;  // floats of LDS (144 KiB)
+constexpr int kCuThreads = 1024;
+constexpr int kCuWaves = kCuThreads / 64;
 
 __host__ __device__ constexpr int cu_row_stride(int Pp) { return 2 * Pp + ((18 - (2 * Pp) % 32) + 32) % 32; }
 
@@ -29,46 +32,29 @@ __host__ __device__ inline int cu_lds_floats(int MT, int n) {
   return n16 * cu_row_stride(8 * MT) + 256 * MT * MT + 4 * n16;
 }
 
-// triangle tile t -> (mt, nt), mt <= nt, row by row (compile-time when t is)
-__host__ __device__ constexpr int tri_row(int t, int MT) {
-  int mt = 0;
-  while (t >= MT - mt) {
-    t -= MT - mt;
-    ++mt;
-  }
-  return mt;
-}
-__host__ __device__ constexpr int tri_col(int t, int MT) {
-  int mt = 0;
-  while (t >= MT - mt) {
-    t -= MT - mt;
-    ++mt;
-  }
-  return mt + t;
-}
-
-template <int MT, int W>
-__device__ inline void cu_forward(const float* xr, const float* vv, int n16, int RS, v4f* acc) {
-  constexpr int NTP = MT * (MT + 1) / 2;
-  constexpr int TPW = (NTP + 3) / 4;
+// G tile (mt, nt) = sum_k x_k[16mt + .] (vs v_k) x_k[16nt + .]^T over the n16 LDS
+// rows: sixteen rows per step, all operands loaded before the four MFMAs
+// (four accumulators)
+__device__ inline v4f cu_forward_tile(const float* xr, const float* vv, float vs, int n16, int RS, int mt,
+                                      int nt) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  v4f acc[4];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int kk = 0; kk < n16; kk += 4) {
-    const int k = kk + q;
-    const float vk = vv[k];
-    float xm[MT];
+  for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+  const float* xa = xr + q * RS + 16 * mt + c16;
+  const float* xb = xr + q * RS + 16 * nt + c16;
+  for (int kk = 0; kk < n16; kk += 16) {
+    float a[4], b[4];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) xm[m] = xr[k * RS + 16 * m + c16];
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-      const int t = W + 4 * i;
-      if (t < NTP) {
-        const int mt = tri_row(t, MT), nt = tri_col(t, MT);
-        acc[i] = mfma16x16x4(xm[mt] * vk, xm[nt], acc[i]);
-      }
+    for (int u = 0; u < 4; ++u) {
+      const int o = (kk + 4 * u) * RS;
+      a[u] = xa[o] * (vv[kk + 4 * u + q] * vs);
+      b[u] = xb[o];
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = mfma16x16x4(a[u], b[u], acc[u]);
   }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // Ut fragment entry (row, col), kept only for col tile <= row tile, off-diagonal
@@ -79,283 +65,298 @@ __device__ inline void cu_put_frag(float* fr, int KS, int row, int col, float v)
   fr[((rt * KS + (col >> 2)) * 64) + (col & 3) * 16 + (row & 15)] = (kt < rt) ? 2.f * v : v;
 }
 
-template <int MT, int W>
-__device__ inline double cu_store_u(const v4f* acc, float2 (*uown)[4], float cu, bool first, int P,
-                                    float* fr) {
-  constexpr int NTP = MT * (MT + 1) / 2;
-  constexpr int TPW = (NTP + 3) / 4;
-  constexpr int KS = 4 * MT;
+// u <- K + cu * u on the owned elements (u kept when first), fragments of Ut;
+// returns the owned part of ||u||^2
+__device__ inline double cu_store_u(v4f acc, float2* uown, float cu, bool first, int P, int mt, int nt,
+                                    int KS, float* fr) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  const OsSlots sl = os_slots(mt, nt, c16, q, P, true);
+  float2 K[4];
+  os_assemble(acc, sl, K);
   double nrm = 0.0;
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    const int t = W + 4 * i;
-    if (t >= NTP) continue;
-    const int mt = tri_row(t, MT), nt = tri_col(t, MT);
-    const OsSlots sl = os_slots(mt, nt, c16, q, P, true);
-    float2 K[4];
-    os_assemble(first ? v4f{0.f, 0.f, 0.f, 0.f} : acc[i], sl, K);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if (!sl.live[s]) continue;
-      const int pa = sl.pa[s], pb = sl.pb[s];
-      float2 r = make_float2(0.f, 0.f);
-      if (pa < P && pb < P) {
-        if (!first) {
-          uown[i][s].x = K[s].x + cu * uown[i][s].x;
-          uown[i][s].y = K[s].y + cu * uown[i][s].y;
-        }
-        r = uown[i][s];
-        nrm += (double)r.x * r.x + (double)r.y * r.y;
+  for (int s = 0; s < 4; ++s) {
+    if (!sl.live[s]) continue;
+    const int pa = sl.pa[s], pb = sl.pb[s];
+    float2 r = make_float2(0.f, 0.f);
+    if (pa < P && pb < P) {
+      if (!first) {
+        uown[s].x = K[s].x + cu * uown[s].x;
+        uown[s].y = K[s].y + cu * uown[s].y;
       }
-      cu_put_frag(fr, KS, 2 * pa, 2 * pb, r.x);
-      cu_put_frag(fr, KS, 2 * pa, 2 * pb + 1, -r.y);
-      cu_put_frag(fr, KS, 2 * pa + 1, 2 * pb, r.y);
-      cu_put_frag(fr, KS, 2 * pa + 1, 2 * pb + 1, r.x);
+      r = uown[s];
+      nrm += (double)r.x * r.x + (double)r.y * r.y;
     }
+    cu_put_frag(fr, KS, 2 * pa, 2 * pb, r.x);
+    cu_put_frag(fr, KS, 2 * pa, 2 * pb + 1, -r.y);
+    cu_put_frag(fr, KS, 2 * pa + 1, 2 * pb, r.y);
+    cu_put_frag(fr, KS, 2 * pa + 1, 2 * pb + 1, r.x);
   }
   return nrm;
 }
 
-template <int MT, int W>
-__device__ inline void cu_load_u(float2 (*uown)[4], const float2* B, int P) {
-  constexpr int NTP = MT * (MT + 1) / 2;
-  constexpr int TPW = (NTP + 3) / 4;
+// Hermitian part of the owned elements of b, so that u and Ut stay exactly
+// Hermitian / symmetric
+__device__ inline void cu_load_u(float2* uown, const float2* B, int P, int mt, int nt) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  const OsSlots sl = os_slots(mt, nt, c16, q, P, true);
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    const int t = W + 4 * i;
-    const bool act = t < NTP;
-    const OsSlots sl = os_slots(act ? tri_row(t, MT) : 0, act ? tri_col(t, MT) : 0, c16, q, P, act);
-    // Hermitian part of b, so that u and Ut stay exactly Hermitian / symmetric
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      uown[i][s] = make_float2(0.f, 0.f);
-      if (sl.live[s] && sl.pa[s] < P && sl.pb[s] < P) {
-        const float2 x = B[sl.pa[s] * P + sl.pb[s]], y = B[sl.pb[s] * P + sl.pa[s]];
-        uown[i][s] = make_float2(0.5f * (x.x + y.x), 0.5f * (x.y - y.y));
-      }
+  for (int s = 0; s < 4; ++s) {
+    uown[s] = make_float2(0.f, 0.f);
+    if (sl.live[s] && sl.pa[s] < P && sl.pb[s] < P) {
+      const float2 x = B[sl.pa[s] * P + sl.pb[s]], y = B[sl.pb[s] * P + sl.pa[s]];
+      uown[s] = make_float2(0.5f * (x.x + y.x), 0.5f * (x.y - y.y));
     }
   }
 }
 
-// g for the free pixels of 16-column tile j (all four row-halves in this wave)
+// g for the 16 pixels of column tile col - c16 (all four row-quarters in this
+// wave); rows beyond n are zero in LDS, so every load is unconditional.
 template <int MT>
-__device__ inline float cu_beam_tile(const float* xr, const float* fr, int RS, int col, bool valid) {
+__device__ inline float cu_beam_tile(const float* xr, const float* fr, int RS, int col) {
   constexpr int KS = 4 * MT;
   const int lane = threadIdx.x & 63, q = lane >> 4;
+  const float* xc = xr + col * RS;
+  float b[KS];
+#pragma unroll
+  for (int kc = 0; kc < KS; ++kc) b[kc] = xc[4 * kc + q];
   v4f acc[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
-  const float* xc = xr + col * RS;
 #pragma unroll
   for (int kt = 0; kt < MT; ++kt) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int kc = 4 * kt + j;
-      const float b = valid ? xc[4 * kc + q] : 0.f;
 #pragma unroll
-      for (int m = kt; m < MT; ++m) acc[m] = mfma16x16x4(fr[(m * KS + kc) * 64 + lane], b, acc[m]);
+      for (int m = kt; m < MT; ++m) acc[m] = mfma16x16x4(fr[(m * KS + kc) * 64 + lane], b[kc], acc[m]);
     }
   }
   float gp = 0.f;
-  if (valid) {
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const float* xm = xc + 16 * m + 4 * q;
-      gp += xm[0] * acc[m][0] + xm[1] * acc[m][1] + xm[2] * acc[m][2] + xm[3] * acc[m][3];
-    }
+  for (int m = 0; m < MT; ++m) {
+    const float* xm = xc + 16 * m + 4 * q;
+    gp += xm[0] * acc[m][0] + xm[1] * acc[m][1] + xm[2] * acc[m][2] + xm[3] * acc[m][3];
   }
   gp += __shfl_xor(gp, 16, 64);
   gp += __shfl_xor(gp, 32, 64);
   return gp;
 }
 
+// Block sum of NV doubles: DPP wave sums, one slot per wave in sh, one
+// barrier.  Two reductions that alternate between two sh buffers never race:
+// every reader of one buffer has passed the other buffer's barrier before
+// that buffer is written again.
+template <int NV>
+__device__ inline void cu_block_sum(double (&v)[NV], double (*sh)[kCuWaves]) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum_dpp_d(v[i]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCuWaves; ++k) t += sh[i][k];
+    v[i] = t;
+  }
+}
+
+// One pass of the F phase over this wave's triangle tiles (v = vs * vsrc);
+// returns this thread's part of ||u||^2.
+template <int TPW, int NTP>
+__device__ inline double cu_phase_f(const float* xr, const float* vsrc, float vs, int n16, int RS, int P,
+                                    int KS, const int* tmt, const int* tnt, float2 (*uown)[4], float cu,
+                                    bool first, float* fr) {
+  const int w = threadIdx.x >> 6;
+  double nb = 0.0;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    if (w + kCuWaves * i < NTP) {
+      v4f acc = {0.f, 0.f, 0.f, 0.f};
+      if (!first) acc = cu_forward_tile(xr, vsrc, vs, n16, RS, tmt[i], tnt[i]);
+      nb += cu_store_u(acc, uown[i], cu, first, P, tmt[i], tnt[i], KS, fr);
+    }
+  }
+  return nb;
+}
+
+// The step order is the usual one; the only change is where the stopping
+// tests of step k are evaluated: ||d_k||^2 and ||x_k||^2 are summed together
+// with ||u_{k+1}||^2, so the F phase of step k+1 runs before the tests of step
+// k and is discarded when they stop the iteration (x_k is untouched by it).
+// Every thread keeps its own copy of the FP64 scalars; they are computed from
+// the same block sums in the same order, so the copies agree bit for bit.
 template <int MT>
-__global__ __launch_bounds__(kThreads) void lsqr_cu_kernel(LsqrCuParams pr) {
+__global__ __launch_bounds__(kCuThreads) void lsqr_cu_kernel(LsqrCuParams pr) {
   constexpr int Pp = 8 * MT;
+  constexpr int KS = 4 * MT;
   constexpr int RS = cu_row_stride(Pp);
   constexpr int NTP = MT * (MT + 1) / 2;
-  constexpr int TPW = (NTP + 3) / 4;
+  constexpr int TPW = (NTP + kCuWaves - 1) / kCuWaves;  // triangle tiles per wave (at most)
   __shared__ float lds[kCuLds];
-  __shared__ double red[4];
-  __shared__ double sc[8];
-  __shared__ int s_done;
-  __shared__ LsqrState sS;
+  __shared__ double redF[3][kCuWaves], redA[1][kCuWaves];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c16 = lane & 15;
   const int P = pr.P, n = pr.n;
   const int n16 = (n + 15) & ~15;
   float* xr = lds;
   float* fr = xr + n16 * RS;
-  float* vv = fr + 256 * MT * MT;
-  float* ww = vv + n16;
-  float* xv = ww + n16;
-  float* vr = xv + n16;
+  float* vv = fr + 256 * MT * MT;  // v
+  float* ww = vv + n16;            // w
+  float* xv = ww + n16;            // x
+  float* vr = xv + n16;            // alpha * next v (zero beyond n)
 
-  for (int e = tid; e < n16 * 2 * Pp; e += kThreads) {
+  for (int e = tid; e < n16 * 2 * Pp; e += kCuThreads) {
     const int k = e / (2 * Pp), r = e - k * (2 * Pp);
     xr[k * RS + r] = k < n ? pr.xf[(size_t)k * 2 * Pp + r] : 0.f;
   }
-  for (int e = tid; e < 4 * n16; e += kThreads) vv[e] = 0.f;
-  for (int e = tid; e < 256 * MT * MT; e += kThreads) fr[e] = 0.f;
+  for (int e = tid; e < 4 * n16; e += kCuThreads) vv[e] = 0.f;
+  for (int e = tid; e < 256 * MT * MT; e += kCuThreads) fr[e] = 0.f;
+  // this wave's triangle tiles t = w + kCuWaves * i and the u elements it owns
+  int tmt[TPW], tnt[TPW];
   float2 uown[TPW][4];
-  switch (w) {
-    case 0: cu_load_u<MT, 0>(uown, pr.B, P); break;
-    case 1: cu_load_u<MT, 1>(uown, pr.B, P); break;
-    case 2: cu_load_u<MT, 2>(uown, pr.B, P); break;
-    default: cu_load_u<MT, 3>(uown, pr.B, P); break;
-  }
-  if (tid == 0) {
-    LsqrState S = {};
-    S.atol = pr.atol;
-    S.btol = pr.btol;
-    S.conlim = pr.conlim;
-    S.itnlim = pr.itnlim;
-    sS = S;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = w + kCuWaves * i;
+    tri_tile(t < NTP ? t : 0, MT, tmt[i], tnt[i]);
+    if (t < NTP) cu_load_u(uown[i], pr.B, P, tmt[i], tnt[i]);
   }
   __syncthreads();
-  float cu = 0.f;
-  bool first = true;
-  for (int it = 0;; ++it) {
-    // ---- F: u <- Psi_F v - (alpha/beta) u (u = b on the first pass) ----
-    double nb;
-    {
-      v4f acc[TPW];
-      switch (w) {
-        case 0:
-          if (!first) cu_forward<MT, 0>(xr, vv, n16, RS, acc);
-          nb = cu_store_u<MT, 0>(acc, uown, cu, first, P, fr);
-          break;
-        case 1:
-          if (!first) cu_forward<MT, 1>(xr, vv, n16, RS, acc);
-          nb = cu_store_u<MT, 1>(acc, uown, cu, first, P, fr);
-          break;
-        case 2:
-          if (!first) cu_forward<MT, 2>(xr, vv, n16, RS, acc);
-          nb = cu_store_u<MT, 2>(acc, uown, cu, first, P, fr);
-          break;
-        default:
-          if (!first) cu_forward<MT, 3>(xr, vv, n16, RS, acc);
-          nb = cu_store_u<MT, 3>(acc, uown, cu, first, P, fr);
-          break;
-      }
-    }
-    const double beta = sqrt(block_sum_d(nb, red));  // barrier inside: fragments complete
-    // ---- A: v_raw = Psi_F^H u / beta - beta v ----
+
+  // A phase: vr = Psi_F^H u / bet - bet v; returns ||vr||
+  auto phase_a = [&](double bet) {
     double a2 = 0.0;
-    for (int j = w; 16 * j < n; j += 4) {
+    for (int j = w; 16 * j < n; j += kCuWaves) {
       const int col = 16 * j + c16;
-      const bool valid = col < n;
-      const float g = cu_beam_tile<MT>(xr, fr, RS, col, valid);
-      if (lane < 16 && valid) {
-        double v = beta > 0.0 ? (double)g / beta : 0.0;
-        if (!first) v -= beta * (double)vv[col];
-        const float vf = (float)v;
+      const float g = cu_beam_tile<MT>(xr, fr, RS, col);
+      if (lane < 16 && col < n) {
+        const float vf = (float)((bet > 0.0 ? (double)g / bet : 0.0) - bet * (double)vv[col]);
         vr[col] = vf;
         a2 += (double)vf * vf;
       }
     }
-    const double alpha = sqrt(block_sum_d(a2, red));
-    // ---- S: rotation, vector updates and stopping tests ----
-    if (tid == 0) {
-      sc[0] = alpha > 0.0 ? 1.0 / alpha : 0.0;
-      if (!first) {
-        const double rho = hypot(sS.rhobar, beta);
-        const double c = sS.rhobar / rho, sn = beta / rho;
-        sc[1] = 1.0 / rho;         // d = w / rho
-        sc[2] = c * sS.phibar;     // phi
-        sc[3] = sn * alpha / rho;  // theta / rho
-        sc[4] = c;
-        sc[5] = sn;
-      }
-    }
-    __syncthreads();
-    const double iv = sc[0];
-    double dd = 0.0, xx = 0.0;
-    if (first) {
-      for (int k = tid; k < n; k += kThreads) {
-        const float vf = (float)((double)vr[k] * iv);
-        vv[k] = vf;
-        ww[k] = vf;
-        xv[k] = 0.f;
-      }
-    } else {
-      const double ir = sc[1], phi = sc[2], tr = sc[3];
-      for (int k = tid; k < n; k += kThreads) {
-        const float vf = (float)((double)vr[k] * iv);
-        const double wk = (double)ww[k];
-        const double dk = wk * ir;
-        dd += dk * dk;
-        const float xk = (float)((double)xv[k] + phi * dk);
-        xx += (double)xk * xk;
-        vv[k] = vf;
-        xv[k] = xk;
-        ww[k] = (float)((double)vf - tr * wk);
-      }
-    }
-    dd = block_sum_d(dd, red);
-    xx = block_sum_d(xx, red);
-    if (tid == 0) {
-      LsqrState S = sS;
-      if (first) {
-        S.alpha = alpha;
-        S.beta = beta;
-        S.rhobar = alpha;
-        S.phibar = beta;
-        S.bnorm = beta;
-        S.anorm2 = 0.0;
-        S.ddnorm = 0.0;
-        S.rnorm = beta;
-        S.arnorm = alpha * beta;
-        S.itn = 0;
-        S.istop = (alpha == 0.0 || beta == 0.0) ? 4 : 0;
-      } else {
-        const double c = sc[4], sn = sc[5];
-        S.anorm2 += S.alpha * S.alpha + beta * beta;
-        S.rhobar = -c * alpha;
-        S.phibar = sn * S.phibar;
-        S.alpha = alpha;
-        S.beta = beta;
-        S.ddnorm += dd;
-        S.rnorm = S.phibar;
-        S.arnorm = S.phibar * alpha * fabs(c);
-        S.anorm = sqrt(S.anorm2);
-        S.acond = S.anorm * sqrt(S.ddnorm);
-        S.xnorm = sqrt(xx);
-        S.itn = it;
-        int istop = 0;
-        if (S.rnorm <= S.btol * S.bnorm + S.atol * S.anorm * S.xnorm) istop = 1;
-        else if (S.arnorm <= S.atol * S.anorm * S.rnorm) istop = 2;
-        else if (S.acond >= S.conlim) istop = 3;
-        else if (alpha == 0.0 || beta == 0.0) istop = 4;
-        else if (S.itn >= S.itnlim) istop = 7;
-        S.istop = istop;
-      }
-      S.done = S.istop != 0;
-      sS = S;
-      s_done = S.done;
-    }
-    __syncthreads();
-    if (s_done) break;
-    cu = (float)(-alpha / beta);
-    first = false;
+    double r[1] = {a2};
+    cu_block_sum<1>(r, redA);
+    return sqrt(r[0]);
+  };
+
+  double alpha, beta, rhobar, phibar, bnorm, rnorm, arnorm;
+  double anorm2 = 0.0, ddnorm = 0.0, anorm = 0.0, acond = 0.0, xnorm = 0.0;
+  const double atol = pr.atol, btol = pr.btol, conlim = pr.conlim;
+  int istop, itn = 0;
+
+  // beta u = b, alpha v = Psi_F^H u
+  {
+    double r[3] = {cu_phase_f<TPW, NTP>(xr, vr, 0.f, n16, RS, P, KS, tmt, tnt, uown, 0.f, true, fr), 0.0,
+                   0.0};
+    cu_block_sum<3>(r, redF);
+    beta = sqrt(r[0]);
   }
-  for (int k = tid; k < n; k += kThreads) pr.x_out[k] = xv[k];
+  alpha = phase_a(beta);
+  rhobar = alpha;
+  phibar = beta;
+  bnorm = beta;
+  rnorm = beta;
+  arnorm = alpha * beta;
+  istop = (alpha == 0.0 || beta == 0.0) ? 4 : 0;
+  float ivf = alpha > 0.0 ? (float)(1.0 / alpha) : 0.f;
+  for (int k = tid; k < n; k += kCuThreads) {
+    const float vf = vr[k] * ivf;
+    vv[k] = vf;
+    ww[k] = vf;
+    xv[k] = 0.f;
+  }
+  double dd = 0.0, xx = 0.0;  // this thread's part of ||d||^2 and ||x||^2 of the last step
+  for (int it = 1; istop == 0; ++it) {
+    // F: u <- Psi_F v - (alpha/beta) u, with v taken as vr * (1/alpha), the
+    // same FP32 product the vector update stores in vv
+    const float cu = beta > 0.0 ? (float)(-alpha / beta) : 0.f;
+    double r[3] = {cu_phase_f<TPW, NTP>(xr, vr, ivf, n16, RS, P, KS, tmt, tnt, uown, cu, false, fr), dd, xx};
+    cu_block_sum<3>(r, redF);
+    if (it > 1) {  // stopping tests of step it - 1
+      ddnorm += r[1];
+      xnorm = sqrt(r[2]);
+      anorm = sqrt(anorm2);
+      acond = anorm * sqrt(ddnorm);
+      if (rnorm <= btol * bnorm + atol * anorm * xnorm) istop = 1;
+      else if (arnorm <= atol * anorm * rnorm) istop = 2;
+      else if (acond >= conlim) istop = 3;
+      else if (alpha == 0.0 || beta == 0.0) istop = 4;
+      else if (itn >= pr.itnlim) istop = 7;
+      if (istop) break;
+    }
+    const double beta_n = sqrt(r[0]);
+    const double alpha_n = phase_a(beta_n);
+    // plane rotation and the updates of w and x
+    anorm2 += alpha * alpha + beta_n * beta_n;
+    const double rho = hypot(rhobar, beta_n);
+    const double c = rhobar / rho, sn = beta_n / rho;
+    const double phi = c * phibar;
+    const double ir = 1.0 / rho, tr = sn * alpha_n / rho;
+    rhobar = -c * alpha_n;
+    phibar = sn * phibar;
+    alpha = alpha_n;
+    beta = beta_n;
+    rnorm = phibar;
+    arnorm = phibar * alpha * fabs(c);
+    itn = it;
+    ivf = alpha > 0.0 ? (float)(1.0 / alpha) : 0.f;
+    dd = 0.0;
+    xx = 0.0;
+    for (int k = tid; k < n; k += kCuThreads) {
+      const float vf = vr[k] * ivf;
+      const double wk = (double)ww[k];
+      const double dk = wk * ir;
+      dd += dk * dk;
+      const float xk = (float)((double)xv[k] + phi * dk);
+      xx += (double)xk * xk;
+      vv[k] = vf;
+      xv[k] = xk;
+      ww[k] = (float)((double)vf - tr * wk);
+    }
+  }
+  for (int k = tid; k < n; k += kCuThreads) pr.x_out[k] = xv[k];
   __syncthreads();
   if (tid == 0) {
-    *pr.Sfinal = sS;
+    LsqrState S = {};
+    S.alpha = alpha;
+    S.beta = beta;
+    S.rhobar = rhobar;
+    S.phibar = phibar;
+    S.bnorm = bnorm;
+    S.anorm2 = anorm2;
+    S.ddnorm = ddnorm;
+    S.rnorm = rnorm;
+    S.arnorm = arnorm;
+    S.anorm = anorm;
+    S.acond = acond;
+    S.xnorm = xnorm;
+    S.atol = atol;
+    S.btol = btol;
+    S.conlim = conlim;
+    S.itn = itn;
+    S.itnlim = pr.itnlim;
+    S.istop = istop;
+    S.done = 1;
+    *pr.Sfinal = S;
     *pr.done = 1;
   }
 }
 
 bool lsqr_cu_fits(int P, int n) {
   const int MT = pad_p(P) / 8;
-  return MT <= 8 && n > 0 && cu_lds_floats(MT, n) <= kCuLds;
+  // up to P = 48: beyond that the per-lane operand arrays no longer fit the
+  // 128 registers a 1024-thread workgroup leaves each lane
+  return MT <= 6 && n > 0 && cu_lds_floats(MT, n) <= kCuLds;
 }
 
 hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st) {
-  const dim3 g(1), b(kThreads);
+  const dim3 g(1), b(kCuThreads);
   switch (pad_p(pr.P) / 8) {
     case 1: hipLaunchKernelGGL(lsqr_cu_kernel<1>, g, b, 0, st, pr); break;
     case 2: hipLaunchKernelGGL(lsqr_cu_kernel<2>, g, b, 0, st, pr); break;
@@ -363,8 +364,6 @@ hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st) {
     case 4: hipLaunchKernelGGL(lsqr_cu_kernel<4>, g, b, 0, st, pr); break;
     case 5: hipLaunchKernelGGL(lsqr_cu_kernel<5>, g, b, 0, st, pr); break;
     case 6: hipLaunchKernelGGL(lsqr_cu_kernel<6>, g, b, 0, st, pr); break;
-    case 7: hipLaunchKernelGGL(lsqr_cu_kernel<7>, g, b, 0, st, pr); break;
-    case 8: hipLaunchKernelGGL(lsqr_cu_kernel<8>, g, b, 0, st, pr); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

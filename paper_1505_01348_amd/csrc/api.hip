@@ -48,7 +48,9 @@ struct clsimg_ctx {
   DevBuf Flist, Ulist, v, w, x, eps, mf, gamma;
   DevBuf lsqr, dec, status;
   DevBuf lsqr2, done, x1, w1, vraw, bpart0, bpart1, xf, bar;  // fused LSQR step
+  DevBuf ostate;                                                // device-resident outer loop
   SolveDecision* h_dec = nullptr;
+  OuterState* h_outer = nullptr;
   LsqrState* h_lsqr = nullptr;
   int* h_status = nullptr;
   double* h_norms = nullptr;
@@ -57,6 +59,8 @@ struct clsimg_ctx {
   int lsqr_path = 0;   // CLSIMG_LSQR_PATH: 0 auto, 1 one workgroup, 2 cooperative, 3 two kernels/step
   bool old_beam = false;   // CLSIMG_LDS_BEAM=1: LDS-staged beamformer for the gradient
   bool beam_prep = false;  // CLSIMG_BEAM_PREP=1: beamformer fragments from a separate pass
+  bool host_loop = false;  // CLSIMG_HOST_LOOP=1: active-set loop driven from the host
+  int outer_max_f = 1 << 30;  // CLSIMG_OUTER_MAXF: hand over to the host loop beyond this |F|
 };
 
 namespace {
@@ -374,8 +378,13 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   c->old_beam = ob && ob[0] == '1';
   const char* bp = getenv("CLSIMG_BEAM_PREP");
   c->beam_prep = bp && bp[0] == '1';
+  const char* hl = getenv("CLSIMG_HOST_LOOP");
+  c->host_loop = hl && hl[0] == '1';
+  const char* mf_ = getenv("CLSIMG_OUTER_MAXF");
+  if (mf_) c->outer_max_f = atoi(mf_);
   void* hp = nullptr;
-  const size_t hbytes = sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + 64 * sizeof(double);
+  const size_t hbytes =
+      sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + 64 * sizeof(double) + sizeof(OuterState);
   if (hipHostMalloc(&hp, hbytes, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
     if (hp) (void)hipHostFree(hp);
@@ -387,6 +396,8 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   c->h_lsqr = reinterpret_cast<LsqrState*>(b + sizeof(SolveDecision));
   c->h_status = reinterpret_cast<int*>(b + sizeof(SolveDecision) + sizeof(LsqrState));
   c->h_norms = reinterpret_cast<double*>(b + sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int));
+  c->h_outer = reinterpret_cast<OuterState*>(b + sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) +
+                                             64 * sizeof(double));
   *out = c;
   return CLSIMG_OK;
 }
@@ -395,7 +406,7 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (!c) return CLSIMG_EINVAL;
   DeviceGuard guard(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->part,  &c->beta_part,
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->part,  &c->beta_part,
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
@@ -498,7 +509,8 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   const int P = a->P, Q = g->nl * g->nm;
   ST_TRY(ensure_workspace(c, P, Q));
   ST_TRY(ensure(c, c->Flist, (size_t)Q * sizeof(int)));
-  ST_TRY(ensure(c, c->Ulist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->Ulist, (size_t)2 * Q * sizeof(int)));  // two buffers for the device loop
+  ST_TRY(ensure(c, c->ostate, sizeof(OuterState)));
   ST_TRY(ensure(c, c->v, (size_t)Q * sizeof(float)));
   ST_TRY(ensure(c, c->w, (size_t)Q * sizeof(float)));
   ST_TRY(ensure(c, c->x, (size_t)Q * sizeof(float)));
@@ -594,7 +606,61 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   int batch = 4;
   const int ntiles_Q = ntiles_adj(P, Q);
   const bool beam_full_grid = beam_fits(P) && !c->old_beam;
-  for (;;) {
+  bool host_loop = true;
+  if (beam_full_grid && outer_fits(P) && !c->host_loop && !c->trace) {
+    // Table I on the device: one workgroup per outer step, the full-grid
+    // multiplier kernel between steps; the host only checks for the end
+    OuterState* ost = P_<OuterState>(c->ostate);
+    HIP_TRY(launch_outer_init(ost, dec, st));
+    OuterParams op;
+    op.st = ost;
+    op.Flist = Flist;
+    op.Ulist = Ulist;
+    op.sigma = sigma;
+    op.gamma = gamma;
+    op.eps = eps;
+    op.state = state;
+    op.B0 = B0;
+    op.Bb = Bb;
+    op.E = E;
+    op.keys = keys;
+    op.nkeys = beam_grid(Q);
+    op.tab = tables_of(c, g, P);
+    op.P = P;
+    op.Q = Q;
+    op.atol = o->atol;
+    op.btol = o->btol;
+    op.conlim = o->conlim;
+    op.itnlim = o->itnlim;
+    op.max_outer = max_outer;
+    op.max_f = c->outer_max_f;
+    int nb = 8;
+    for (;;) {
+      for (int b = 0; b < nb; ++b) {
+        HIP_TRY(launch_outer_step(op, st));
+        HIP_TRY(launch_beam_lambda(nullptr, E, P, op.tab, &ost->lam_skip, state, keys, st));
+      }
+      ST_TRY(read_back(c, c->h_outer, ost, sizeof(OuterState), st));
+      if (c->h_outer->done) break;
+      nb = std::min(2 * nb, 128);
+    }
+    const OuterState& S = *c->h_outer;
+    status = S.status == kStatusMaxOuter ? CLSIMG_WMAXOUTER : (S.status == kStatusCycle ? CLSIMG_WCYCLE : CLSIMG_OK);
+    outer = S.outer;
+    adds = S.adds;
+    drops = S.drops;
+    lsqr_total = S.lsqr_total;
+    itnlim_hits = S.itnlim_hits;
+    last_added = S.last_added;
+    margin_lambda = S.margin_lambda;
+    margin_z = S.margin_z;
+    nF = S.nF;
+    nU = S.nU;
+    flops += S.psi_flops;
+    // a free set too large for one workgroup: continue on the host from here
+    host_loop = S.fallback != 0;
+  }
+  for (; host_loop;) {
     if (need_solve) {
       if (outer >= max_outer) {
         status = CLSIMG_WMAXOUTER;

@@ -329,6 +329,50 @@ struct SolveDecision {
 
 hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec,
                           hipStream_t st);
+
+// ---- device-resident outer iteration (outer.hip) ----
+// pixel states and stop codes as in the public header
+constexpr int kStateL = 0, kStateF = 1, kStateU = 2;
+constexpr int kStatusMaxOuter = 1, kStatusCycle = 3;
+
+struct OuterState {
+  int done;          // the iteration has stopped (or handed over: fallback)
+  int status;        // 0, kStatusMaxOuter or kStatusCycle
+  int fallback;      // stopped because the next free set does not fit one workgroup
+  int await_lambda;  // a feasible step left E; the multiplier keys decide the next move
+  int lam_skip;      // the multiplier kernel has nothing to do
+  int nF, nU;
+  int ucur;          // which half of the two-buffer U list is current
+  int outer, adds, drops, lsqr_total, itnlim_hits, last_added;
+  int bb_dirty;      // U changed since b was formed
+  int last_itn, last_istop, last_feasible, last_ib, last_ib_to, last_imin;
+  float last_mu, last_lam, last_eps;
+  double margin_lambda, margin_z, psi_flops;
+};
+
+struct OuterParams {
+  OuterState* st;
+  int* Flist;  // sorted free pixels (capacity Q)
+  int* Ulist;  // sorted pixels at the upper bound, two buffers of Q entries
+  float* sigma;
+  const float* gamma;
+  const float* eps;
+  uint8_t* state;
+  const float2* B0;
+  float2* Bb;
+  float2* E;
+  const uint64_t* keys;  // per-block argmin keys of the multiplier kernel
+  int nkeys;
+  Tables tab;
+  int P, Q;
+  double atol, btol, conlim;
+  int itnlim, max_outer;
+  int max_f;  // largest free set kept on the device (at most the LDS capacity)
+};
+
+bool outer_fits(int P);
+hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s);
+hipError_t launch_outer_step(const OuterParams& pr, hipStream_t s);
 hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int nbeta,
                                     const double* alpha_part, int nalpha, float* v, float* w,
                                     float* x, int n, double atol, double btol, double conlim,

@@ -1,0 +1,417 @@
+// Device-resident outer iteration of the active-set method (Table I) for
+// P <= 48 and free sets that fit in one workgroup's LDS.
+//
+// Every outer step changes the free set by one pixel (an add after a feasible
+// step, a block after an infeasible one), so one workgroup can carry the whole
+// step: it keeps the sorted lists of F and U, applies the decision taken from
+// the Lagrange multipliers of the previous feasible step, forms
+// b = B0 - Psi_U gamma_U (eq. bsubproblemLS) when U changed, generates the
+// steering vectors of F from the separable tables, runs LSQR (Sec. IV-A), and
+// takes the feasible step (sigma_F = z, then E = Psi_F sigma_F - b for the
+// gradient, eq. gls) or the infeasible one (eq. mumax).  The multipliers of a
+// feasible step (eqs. etaL, etaU) come from the full-grid beamformer, which
+// runs between two outer steps and leaves one partial argmin key per block.
+//
+// The host enqueues (outer step, multipliers) pairs in batches and reads the
+// state once per batch; steps enqueued after the iteration stopped return at
+// once.  When a free set outgrows the LDS, the outer step stops with
+// `fallback` set and the host continues with its own loop from the current
+// sigma and state.
+#include "lsqr_cu.h"
+
+namespace clsimg {
+
+constexpr int kOuterMaxF = 1024;  // entries of the LDS copy of the free list
+
+__device__ inline int cu_block_sum_i(int v, int (&sh)[kCuWaves]) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kCuWaves; ++i) s += sh[i];
+  return s;
+}
+
+__device__ inline int cu_block_min_i(int v, int (&sh)[kCuWaves]) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int s = sh[0];
+#pragma unroll
+  for (int i = 1; i < kCuWaves; ++i) s = min(s, sh[i]);
+  return s;
+}
+
+__device__ inline float cu_block_min_f(float v, float (&sh)[kCuWaves]) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float s = sh[0];
+#pragma unroll
+  for (int i = 1; i < kCuWaves; ++i) s = fminf(s, sh[i]);
+  return s;
+}
+
+// order-preserving map of a double to uint64 (no NaN arrives here)
+__device__ inline uint64_t ordered_bits_d(double d) {
+  const uint64_t u = (uint64_t)__double_as_longlong(d);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ inline double from_ordered_bits_d(uint64_t u) {
+  const uint64_t v = (u & 0x8000000000000000ull) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+  return __longlong_as_double((long long)v);
+}
+
+// Real-embedded steering vectors of pixels list[0 .. n) into LDS rows
+// (x[2p] = Re a_p, x[2p+1] = Im a_p, rows n .. n16 - 1 zero), optionally with
+// the row weights w[k] = wsrc[list[k]].
+template <int MT>
+__device__ inline void cu_gen_rows(const Tables& tab, const int* list, int n, float* xr, const float* wsrc,
+                                   float* w) {
+  constexpr int Pp = 8 * MT;
+  constexpr int RS = cu_row_stride(Pp);
+  const int n16 = (n + 15) & ~15;
+  for (int e = threadIdx.x; e < n16 * Pp; e += kCuThreads) {
+    const int k = e / Pp, p = e - k * Pp;
+    float2 a = make_float2(0.f, 0.f);
+    if (k < n) {
+      const int i = list[k];
+      const int im = i / tab.nl, il = i - im * tab.nl;
+      a = tab.a(p, il, im);
+    }
+    xr[k * RS + 2 * p] = a.x;
+    xr[k * RS + 2 * p + 1] = a.y;
+  }
+  if (w)
+    for (int k = threadIdx.x; k < n16; k += kCuThreads) w[k] = k < n ? wsrc[list[k]] : 0.f;
+}
+
+// out = sK K + sB herm(B) over this wave's owned elements, K from a forward tile
+__device__ inline void cu_store_c(v4f acc, int mt, int nt, int P, float sK, float sB,
+                                  const float2* __restrict__ B, float2* out) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  const OsSlots sl = os_slots(mt, nt, c16, q, P, true);
+  float2 K[4];
+  os_assemble(acc, sl, K);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (!sl.live[s] || sl.pa[s] >= P || sl.pb[s] >= P) continue;
+    const float2 x = B[sl.pa[s] * P + sl.pb[s]], y = B[sl.pb[s] * P + sl.pa[s]];
+    out[sl.pa[s] * P + sl.pb[s]] =
+        make_float2(sK * K[s].x + sB * (0.5f * (x.x + y.x)), sK * K[s].y + sB * (0.5f * (x.y - y.y)));
+  }
+}
+
+__device__ inline const int* ulist_cur(const OuterParams& pr, const OuterState& S) {
+  return pr.Ulist + (size_t)S.ucur * pr.Q;
+}
+
+template <int MT>
+__global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) {
+  constexpr int Pp = 8 * MT;
+  constexpr int RS = cu_row_stride(Pp);
+  constexpr int NTP = MT * (MT + 1) / 2;
+  constexpr int TPW = (NTP + kCuWaves - 1) / kCuWaves;
+  __shared__ float lds[kCuLds];
+  __shared__ int sF[kOuterMaxF];
+  __shared__ OuterState S;
+  __shared__ int shi[kCuWaves];
+  __shared__ float shf[kCuWaves];
+  __shared__ uint64_t shk[kCuWaves];
+  __shared__ int s_add, s_from_u;
+  const int tid = threadIdx.x, w = tid >> 6;
+  const int P = pr.P, Q = pr.Q;
+  if (tid == 0) S = *pr.st;
+  __syncthreads();
+  if (S.done) return;
+  for (int k = tid; k < S.nF && k < kOuterMaxF; k += kCuThreads) sF[k] = pr.Flist[k];
+
+  // ---- decision from the multipliers of the last feasible step ----
+  if (S.await_lambda) {
+    uint64_t m = ~0ull;
+    for (int i = tid; i < pr.nkeys; i += kCuThreads) m = pr.keys[i] < m ? pr.keys[i] : m;
+    m = block_min_u64(m, shk);
+    if (tid == 0) {
+      s_add = -1;
+      s_from_u = 0;
+      S.await_lambda = 0;
+      if (m == ~0ull) {
+        S.done = 1;  // no active pixel left
+      } else {
+        const float lam = from_ordered_bits((uint32_t)(m >> 32));
+        const int i = (int)(m & 0xFFFFFFFFull);
+        const float thr = pr.eps[i];
+        S.last_imin = i;
+        S.last_lam = lam;
+        S.last_eps = thr;
+        if (thr > 0.f) S.margin_lambda = fmin(S.margin_lambda, fabs((double)lam + thr) / thr);
+        if (lam < -thr) {
+          s_add = i;
+          s_from_u = pr.state[i] == kStateU;
+          pr.state[i] = kStateF;
+          ++S.adds;
+          S.last_added = i;
+        } else {
+          S.done = 1;
+        }
+      }
+    }
+    __syncthreads();
+    const int add = s_add;
+    if (add >= 0) {
+      // insert into the sorted free list (LDS) ...
+      const int n = S.nF;
+      int cnt = 0;
+      for (int k = tid; k < n && k < kOuterMaxF; k += kCuThreads) cnt += sF[k] < add;
+      const int pos = cu_block_sum_i(cnt, shi);
+      if (n < kOuterMaxF) {
+        const int v = tid < n ? sF[tid] : 0;
+        __syncthreads();
+        if (tid < n && tid >= pos) sF[tid + 1] = v;
+        if (tid == pos) sF[pos] = add;
+      }
+      // ... and take it out of the upper-bound list (global, two buffers)
+      if (s_from_u) {
+        const int* Uo = ulist_cur(pr, S);
+        int* Un = pr.Ulist + (size_t)(1 - S.ucur) * Q;
+        int kp = 0x7fffffff;
+        for (int k = tid; k < S.nU; k += kCuThreads)
+          if (Uo[k] == add) kp = k;
+        kp = cu_block_min_i(kp, shi);
+        for (int k = tid; k < S.nU - 1; k += kCuThreads) Un[k] = k < kp ? Uo[k] : Uo[k + 1];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        ++S.nF;
+        if (s_from_u) {
+          --S.nU;
+          S.ucur = 1 - S.ucur;
+          S.bb_dirty = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- guards ----
+  if (tid == 0 && !S.done) {
+    if (S.outer >= pr.max_outer) {
+      S.status = kStatusMaxOuter;
+      S.done = 1;
+    } else if (S.nF > kOuterMaxF || S.nF > pr.max_f || cu_lds_floats(MT, S.nF) > kCuLds) {
+      S.fallback = 1;
+      S.done = 1;
+    }
+  }
+  __syncthreads();
+  const int n = S.nF, n16 = (n + 15) & ~15;
+  auto finish = [&]() {
+    __syncthreads();
+    for (int k = tid; k < S.nF && k < kOuterMaxF; k += kCuThreads) pr.Flist[k] = sF[k];
+    if (tid == 0) {
+      S.lam_skip = !(S.await_lambda && !S.done);
+      *pr.st = S;
+    }
+  };
+  if (S.done) {
+    finish();
+    return;
+  }
+
+  // this wave's triangle tiles
+  int tmt[TPW], tnt[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = w + kCuWaves * i;
+    tri_tile(t < NTP ? t : 0, MT, tmt[i], tnt[i]);
+  }
+
+  // ---- b = B0 - Psi_U gamma_U, recomputed when U changed ----
+  if (S.bb_dirty) {
+    if (S.nU > 0) {
+      const int* U = ulist_cur(pr, S);
+      constexpr int CH = ((kCuLds - 64) / (RS + 1)) & ~15;  // rows per chunk
+      float* xr = lds;
+      float* wg = lds + CH * RS;
+      v4f acc[TPW];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int c0 = 0; c0 < S.nU; c0 += CH) {
+        const int nc = min(CH, S.nU - c0), nc16 = (nc + 15) & ~15;
+        cu_gen_rows<MT>(pr.tab, U + c0, nc, xr, pr.gamma, wg);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+          if (w + kCuWaves * i < NTP) acc[i] = acc[i] + cu_forward_tile(xr, wg, 1.f, nc16, RS, tmt[i], tnt[i]);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < TPW; ++i)
+        if (w + kCuWaves * i < NTP) cu_store_c(acc[i], tmt[i], tnt[i], P, -1.f, 1.f, pr.B0, pr.Bb);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      S.psi_flops += 8.0 * P * P * S.nU;
+      S.bb_dirty = 0;
+    }
+  }
+  const float2* bsub = S.nU > 0 ? pr.Bb : pr.B0;
+
+  // ---- LSQR on the free set ----
+  cu_gen_rows<MT>(pr.tab, sF, n, lds, nullptr, nullptr);
+  __syncthreads();
+  const int itnlim = pr.itnlim < 0 ? 4 * n + 100 : pr.itnlim;
+  const LsqrState L = cu_lsqr<MT>(lds, n, P, bsub, pr.atol, pr.btol, pr.conlim, itnlim);
+  float* z = cu_x(lds, MT, n);
+  __syncthreads();
+
+  // ---- step (Table I) ----
+  int ok = 1;
+  float mz = 3.0e38f;
+  for (int k = tid; k < n; k += kCuThreads) {
+    const float zk = z[k], g = pr.gamma[sF[k]];
+    ok &= (zk >= 0.f) && (zk <= g);
+    mz = fminf(mz, fminf(zk, g - zk) / g);
+  }
+  ok = cu_block_min_i(ok, shi);
+  mz = cu_block_min_f(mz, shf);
+  if (ok) {
+    // feasible: sigma_F = z, then E = Psi_F sigma_F - b on the owned elements
+    for (int k = tid; k < n; k += kCuThreads) pr.sigma[sF[k]] = z[k];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+      if (w + kCuWaves * i < NTP) {
+        const v4f acc = cu_forward_tile(lds, z, 1.f, n16, RS, tmt[i], tnt[i]);
+        cu_store_c(acc, tmt[i], tnt[i], P, 1.f, -1.f, bsub, pr.E);
+      }
+    __syncthreads();
+    if (tid == 0) {
+      if (n > 0) S.margin_z = fmin(S.margin_z, (double)mz);
+      S.last_feasible = 1;
+      S.last_ib = -1;
+      if (n >= Q) S.done = 1;  // no active pixel
+      else S.await_lambda = 1;
+      S.psi_flops += 8.0 * P * P * n + 8.0 * P * P * Q + 8.0 * P * Q;
+    }
+  } else {
+    // infeasible: largest step along p = z - sigma_F, ties to the lowest pixel
+    double best = INFINITY;
+    for (int k = tid; k < n; k += kCuThreads) {
+      const int i = sF[k];
+      const double sg = pr.sigma[i], p = (double)z[k] - sg;
+      if (p != 0.0) best = fmin(best, fmax(-sg / p, ((double)pr.gamma[i] - sg) / p));
+    }
+    const uint64_t kb = block_min_u64(ordered_bits_d(best), shk);
+    best = from_ordered_bits_d(kb);
+    int bk = 0x7fffffff;
+    for (int k = tid; k < n; k += kCuThreads) {
+      const int i = sF[k];
+      const double sg = pr.sigma[i], p = (double)z[k] - sg;
+      if (p != 0.0 && fmax(-sg / p, ((double)pr.gamma[i] - sg) / p) == best) bk = min(bk, k);
+    }
+    bk = cu_block_min_i(bk, shi);
+    if (bk >= n) {  // no finite step (non-finite z): stop moving, block the first pixel
+      bk = 0;
+      best = 0.0;
+    }
+    const int ib = sF[bk];
+    const double pb = (double)z[bk] - (double)pr.sigma[ib];  // read before sigma changes
+    __syncthreads();
+    for (int k = tid; k < n; k += kCuThreads) {
+      const int i = sF[k];
+      const double sg = pr.sigma[i], p = (double)z[k] - sg;
+      pr.sigma[i] = (float)fmin(fmax(sg + best * p, 0.0), (double)pr.gamma[i]);
+    }
+    __syncthreads();
+    const bool to_upper = !(pb < 0.0);
+    if (tid == 0) {
+      pr.sigma[ib] = to_upper ? pr.gamma[ib] : 0.f;
+      pr.state[ib] = to_upper ? (uint8_t)kStateU : (uint8_t)kStateL;
+      ++S.drops;
+      S.last_feasible = 0;
+      S.last_ib = ib;
+      S.last_ib_to = to_upper ? kStateU : kStateL;
+      S.last_mu = (float)best;
+      if (ib == S.last_added && (float)best == 0.0f) {
+        S.status = kStatusCycle;
+        S.done = 1;
+      }
+    }
+    // take ib out of the free list
+    {
+      const int v = (tid < n && tid > bk) ? sF[tid] : 0;
+      __syncthreads();
+      if (tid < n && tid > bk) sF[tid - 1] = v;
+    }
+    // and into the upper-bound list
+    if (to_upper) {
+      const int* Uo = ulist_cur(pr, S);
+      int* Un = pr.Ulist + (size_t)(1 - S.ucur) * Q;
+      int cnt = 0;
+      for (int k = tid; k < S.nU; k += kCuThreads) cnt += Uo[k] < ib;
+      const int pos = cu_block_sum_i(cnt, shi);
+      for (int k = tid; k <= S.nU; k += kCuThreads) Un[k] = k < pos ? Uo[k] : (k == pos ? ib : Uo[k - 1]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      --S.nF;
+      if (to_upper) {
+        ++S.nU;
+        S.ucur = 1 - S.ucur;
+        S.bb_dirty = 1;
+      }
+    }
+  }
+  if (tid == 0) {
+    S.last_added = -1;
+    ++S.outer;
+    S.lsqr_total += L.itn;
+    S.last_itn = L.itn;
+    S.last_istop = L.istop;
+    if (L.istop == 7) ++S.itnlim_hits;
+    if (n > 0) S.psi_flops += (8.0 * P * P * n + 8.0 * P * n) + L.itn * (16.0 * P * P * n + 8.0 * P * n);
+  }
+  finish();
+}
+
+__global__ void outer_init_kernel(OuterState* st, const SolveDecision* dec) {
+  if (threadIdx.x != 0) return;
+  OuterState S = {};
+  S.nF = dec->nF;
+  S.nU = dec->nU;
+  S.last_added = -1;
+  S.bb_dirty = S.nU > 0;
+  S.margin_lambda = INFINITY;
+  S.margin_z = INFINITY;
+  S.lam_skip = 1;
+  S.last_ib = -1;
+  S.last_imin = -1;
+  *st = S;
+}
+
+bool outer_fits(int P) { return pad_p(P) / 8 <= 6; }
+
+hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s) {
+  hipLaunchKernelGGL(outer_init_kernel, dim3(1), dim3(64), 0, s, st, dec);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_step(const OuterParams& pr, hipStream_t s) {
+  const dim3 g(1), b(kCuThreads);
+  switch (pad_p(pr.P) / 8) {
+    case 1: hipLaunchKernelGGL(outer_step_kernel<1>, g, b, 0, s, pr); break;
+    case 2: hipLaunchKernelGGL(outer_step_kernel<2>, g, b, 0, s, pr); break;
+    case 3: hipLaunchKernelGGL(outer_step_kernel<3>, g, b, 0, s, pr); break;
+    case 4: hipLaunchKernelGGL(outer_step_kernel<4>, g, b, 0, s, pr); break;
+    case 5: hipLaunchKernelGGL(outer_step_kernel<5>, g, b, 0, s, pr); break;
+    case 6: hipLaunchKernelGGL(outer_step_kernel<6>, g, b, 0, s, pr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace clsimg

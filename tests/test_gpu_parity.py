@@ -252,6 +252,7 @@ def test_solve_each_lsqr_engine_matches_oracle(gpu_lib, scenes, name, path, monk
     # every LSQR engine (one workgroup, one cooperative kernel, two kernels per
     # step) must reproduce the oracle's solve
     monkeypatch.setenv("CLSIMG_LSQR_PATH", path)
+    monkeypatch.setenv("CLSIMG_HOST_LOOP", "1")
     sc = scenes[name]
     print(f"case solve {name} LSQR engine {path}", flush=True)
     ctx2 = gpu_lib.Context(0)
@@ -263,3 +264,58 @@ def test_solve_each_lsqr_engine_matches_oracle(gpu_lib, scenes, name, path, monk
     print("gpu stats", stats, flush=True)
     np.testing.assert_array_equal(state, ref.state)
     _assert_close(sigma, ref.sigma, what=f"solve sigma {name} engine {path}")
+
+
+@pytest.mark.parametrize("name,maxf", [("c0", 3), ("c1", 40)])
+def test_solve_device_loop_hands_over_to_host(gpu_lib, scenes, name, maxf, monkeypatch):
+    # the device-resident loop stops when |F| passes maxf and the host loop
+    # continues from the same sigma and state; the result must not change
+    monkeypatch.setenv("CLSIMG_OUTER_MAXF", str(maxf))
+    sc = scenes[name]
+    print(f"case solve {name} device loop handover at |F| > {maxf}", flush=True)
+    ctx2 = gpu_lib.Context(0)
+    try:
+        ref, _, _ = _oracle_solve(sc)
+        sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx2, sc)
+    finally:
+        ctx2.close()
+    print("gpu stats", stats, flush=True)
+    assert int(np.sum(ref.state == 1)) > maxf  # the handover really happens
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what=f"solve sigma {name} handover")
+    assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
+
+
+@pytest.mark.parametrize("host", ["0", "1"])
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_solve_tight_bound_uses_upper_set(gpu_lib, scenes, name, host, monkeypatch):
+    # a bias factor C < 1 lowers the MVDR bound until pixels stop at it: the
+    # upper set U, b = B0 - Psi_U gamma_U and the moves into and out of U are
+    # exercised on the device loop (host=0) and on the host loop (host=1)
+    monkeypatch.setenv("CLSIMG_HOST_LOOP", host)
+    sc = scenes[name]
+    C = 0.25
+    print(f"case solve {name} C={C} host loop {host}", flush=True)
+    R = sc.R_hat32_c128
+    A = oracle.steering(sc.pos, sc.lam, sc.grid)
+    mf_ref = oracle.mf_image(A, R)
+    gamma_ref = oracle.upper_bound(A, R, C=C)
+    eps = oracle.detection_threshold(mf_ref, 6.0, sc.N)
+    nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
+    ref = oracle.solve(A, R - np.diag(nd), gamma_ref, eps, atol=1e-8, btol=1e-8)
+    ctx2 = gpu_lib.Context(0)
+    try:
+        opts = gpu_lib.default_options()
+        opts.nsamples = sc.N
+        opts.atol = opts.btol = 1e-7
+        opts.C = C
+        sigma, state, mf, gamma, stats = ctx2.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts,
+                                                    noise_diag=_dev(sc.noise_diag, torch.float32))
+    finally:
+        ctx2.close()
+    sigma, state = sigma.cpu().numpy(), state.cpu().numpy()
+    print("gpu stats", stats, "oracle U", int(np.sum(ref.state == 2)), flush=True)
+    assert int(np.sum(ref.state == 2)) > 0
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what=f"solve sigma {name} C={C}")
+    assert stats["adds"] == ref.adds and stats["drops"] == ref.drops

@@ -6,7 +6,7 @@
 // and the vectors v, w, x; each lane keeps the u elements it owns in
 // registers.  One step is, with only workgroup barriers:
 //   F  u <- Psi_F v - (alpha/beta) u over the upper-triangle 16 x 16 tiles of
-//      G = X_F diag(v) X_F^T (tiles spread over the 16 waves), fragments
+//      G = X_F diag(v) X_F^T (tiles spread over the 8 waves), fragments
 //      of Ut written to LDS, ||u||^2;
 //   A  g = x^T Ut x for every free pixel with the block-triangular form
 //      x^T Ut x = sum_m x_m^T Ut_mm x_m + 2 sum_{k<m} x_m^T Ut_mk x_k, so only
@@ -25,7 +25,7 @@
 namespace clsimg {
 
 constexpr int kCuLds = 36864;  // floats of LDS (144 KiB)
-constexpr int kCuThreads = 1024;
+constexpr int kCuThreads = 512;
 constexpr int kCuWaves = kCuThreads / 64;
 
 __host__ __device__ constexpr int cu_row_stride(int Pp) { return 2 * Pp + ((18 - (2 * Pp) % 32) + 32) % 32; }
@@ -58,6 +58,32 @@ __device__ inline v4f cu_forward_tile(const float* xr, const float* vv, float vs
     for (int u = 0; u < 4; ++u) acc[u] = mfma16x16x4(a[u], b[u], acc[u]);
   }
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+
+// All NT triangle tiles of this wave in one pass over the rows (two
+// accumulators each), so each step has 2 NT independent MFMAs.
+template <int NT>
+__device__ inline void cu_forward_tiles(const float* xr, const float* vv, float vs, int n16, int RS, const int* mt,
+                                        const int* nt, v4f* out) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  v4f acc[NT][2];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) acc[i][0] = acc[i][1] = v4f{0.f, 0.f, 0.f, 0.f};
+  const float* x0 = xr + q * RS + c16;
+  for (int kk = 0; kk < n16; kk += 8) {
+    const int o0 = kk * RS, o1 = (kk + 4) * RS;
+    const float v0 = vv[kk + q] * vs, v1 = vv[kk + 4 + q] * vs;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const float* xa = x0 + 16 * mt[i];
+      const float* xb = x0 + 16 * nt[i];
+      acc[i][0] = mfma16x16x4(xa[o0] * v0, xb[o0], acc[i][0]);
+      acc[i][1] = mfma16x16x4(xa[o1] * v1, xb[o1], acc[i][1]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NT; ++i) out[i] = acc[i][0] + acc[i][1];
 }
 
 // Ut fragment entry (row, col), kept only for col tile <= row tile, off-diagonal
@@ -177,14 +203,17 @@ __device__ inline double cu_phase_f(const float* xr, const float* vsrc, float vs
                                     bool first, float* fr) {
   const int w = threadIdx.x >> 6;
   double nb = 0.0;
+  v4f acc[TPW];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    if (w + kCuWaves * i < NTP) {
-      v4f acc = {0.f, 0.f, 0.f, 0.f};
-      if (!first) acc = cu_forward_tile(xr, vsrc, vs, n16, RS, tmt[i], tnt[i]);
-      nb += cu_store_u(acc, uown[i], cu, first, P, tmt[i], tnt[i], KS, fr);
-    }
+  for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int ntw = (NTP - w + kCuWaves - 1) / kCuWaves;  // tiles of this wave
+  if (!first) {
+    if (ntw == TPW) cu_forward_tiles<TPW>(xr, vsrc, vs, n16, RS, tmt, tnt, acc);
+    else if (TPW > 1 && ntw == TPW - 1) cu_forward_tiles<(TPW > 1 ? TPW - 1 : 1)>(xr, vsrc, vs, n16, RS, tmt, tnt, acc);
   }
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+    if (w + kCuWaves * i < NTP) nb += cu_store_u(acc[i], uown[i], cu, first, P, tmt[i], tnt[i], KS, fr);
   return nb;
 }
 
@@ -251,7 +280,7 @@ __device__ LsqrState cu_lsqr(float* lds, int n, int P, const float2* __restrict_
     }
     double r[1] = {a2};
     cu_block_sum<1>(r, redA);
-    return sqrt(r[0]);
+    return (sqrt(r[0]));
   };
 
   double alpha, beta, rhobar, phibar, bnorm, rnorm, arnorm;
@@ -287,10 +316,10 @@ __device__ LsqrState cu_lsqr(float* lds, int n, int P, const float2* __restrict_
     double r[3] = {cu_phase_f<TPW, NTP>(xr, vr, ivf, n16, RS, P, KS, tmt, tnt, uown, cu, false, fr), dd, xx};
     cu_block_sum<3>(r, redF);
     if (it > 1) {  // stopping tests of step it - 1
-      ddnorm += r[1];
+      ddnorm = (ddnorm + r[1]);
       xnorm = sqrt(r[2]);
       anorm = sqrt(anorm2);
-      acond = anorm * sqrt(ddnorm);
+      acond = (anorm * sqrt(ddnorm));
       if (rnorm <= btol * bnorm + atol * anorm * xnorm) istop = 1;
       else if (arnorm <= atol * anorm * rnorm) istop = 2;
       else if (acond >= conlim) istop = 3;
@@ -303,15 +332,15 @@ __device__ LsqrState cu_lsqr(float* lds, int n, int P, const float2* __restrict_
     // plane rotation and the updates of w and x
     anorm2 += alpha * alpha + beta_n * beta_n;
     const double rho = hypot(rhobar, beta_n);
-    const double c = rhobar / rho, sn = beta_n / rho;
-    const double phi = c * phibar;
-    const double ir = 1.0 / rho, tr = sn * alpha_n / rho;
-    rhobar = -c * alpha_n;
-    phibar = sn * phibar;
+    const double c = (rhobar / rho), sn = (beta_n / rho);
+    const double phi = (c * phibar);
+    const double ir = (1.0 / rho), tr = (sn * alpha_n / rho);
+    rhobar = (-c * alpha_n);
+    phibar = (sn * phibar);
     alpha = alpha_n;
     beta = beta_n;
     rnorm = phibar;
-    arnorm = phibar * alpha * fabs(c);
+    arnorm = (phibar * alpha * fabs(c));
     itn = it;
     ivf = alpha > 0.0 ? (float)(1.0 / alpha) : 0.f;
     dd = 0.0;

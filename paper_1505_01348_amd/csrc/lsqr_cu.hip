@@ -27,8 +27,8 @@ __global__ __launch_bounds__(kCuThreads) void lsqr_cu_kernel(LsqrCuParams pr) {
 
 bool lsqr_cu_fits(int P, int n) {
   const int MT = pad_p(P) / 8;
-  // up to P = 48: beyond that the per-lane operand arrays no longer fit the
-  // 128 registers a 1024-thread workgroup leaves each lane
+  // up to P = 48 (eight row tiles of the real embedding would not leave room
+  // for the steering vectors of a useful free set in LDS)
   return MT <= 6 && n > 0 && cu_lds_floats(MT, n) <= kCuLds;
 }
 

@@ -22,6 +22,8 @@
 namespace clsimg {
 
 constexpr int kOuterMaxF = 1024;  // entries of the LDS copy of the free list
+constexpr int kPerThread = kOuterMaxF / kCuThreads;  // list entries each thread moves in a shift
+static_assert(kOuterMaxF % kCuThreads == 0, "list shifts assume whole entries per thread");
 
 __device__ inline int cu_block_sum_i(int v, int (&sh)[kCuWaves]) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -169,10 +171,19 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
       for (int k = tid; k < n && k < kOuterMaxF; k += kCuThreads) cnt += sF[k] < add;
       const int pos = cu_block_sum_i(cnt, shi);
       if (n < kOuterMaxF) {
-        const int v = tid < n ? sF[tid] : 0;
+        int v[kPerThread];
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+          const int k = tid + j * kCuThreads;
+          v[j] = k < n ? sF[k] : 0;
+        }
         __syncthreads();
-        if (tid < n && tid >= pos) sF[tid + 1] = v;
-        if (tid == pos) sF[pos] = add;
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+          const int k = tid + j * kCuThreads;
+          if (k < n && k >= pos) sF[k + 1] = v[j];
+        }
+        if (tid == 0) sF[pos] = add;
       }
       // ... and take it out of the upper-bound list (global, two buffers)
       if (s_from_u) {
@@ -343,9 +354,18 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
     }
     // take ib out of the free list
     {
-      const int v = (tid < n && tid > bk) ? sF[tid] : 0;
+      int v[kPerThread];
+#pragma unroll
+      for (int j = 0; j < kPerThread; ++j) {
+        const int k = tid + j * kCuThreads;
+        v[j] = (k < n && k > bk) ? sF[k] : 0;
+      }
       __syncthreads();
-      if (tid < n && tid > bk) sF[tid - 1] = v;
+#pragma unroll
+      for (int j = 0; j < kPerThread; ++j) {
+        const int k = tid + j * kCuThreads;
+        if (k < n && k > bk) sF[k - 1] = v[j];
+      }
     }
     // and into the upper-bound list
     if (to_upper) {

@@ -53,7 +53,32 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-7, help="LSQR atol = btol")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only launch the beamformer (20 times) and a plain copy of --copy-mib MiB "
+                         "(3 times): the program the HBM traffic counters are read on")
+    ap.add_argument("--copy-mib", type=int, default=256)
     return ap.parse_args()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "beam_kernel_mf_c1_traffic.md")
+BEAM_SOURCE = os.path.join(ROOT, "paper_1505_01348_amd", "csrc", "beam.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the beamformer from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(BEAM_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_json: "):
+            rec = json.loads(line[len("traffic_json: "):])
+            if rec.get("beam_hip_sha256") == src:
+                return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def cpu_baseline(sc, tol_oracle, budget_s=25.0):
@@ -75,7 +100,7 @@ def cpu_baseline(sc, tol_oracle, budget_s=25.0):
         t_total += time.perf_counter() - t0
         runs += 1
         log(f"cpu baseline: oracle solve {runs} done, {t_total:.1f} s")
-        if t_total >= budget_s * 0.4 or runs >= 3:
+        if t_total >= budget_s * 0.4 or runs >= 30:
             break
     threads = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
     cores = max(threads) if threads else 1
@@ -102,6 +127,22 @@ def main():
         sys.exit(1)
     sc = synth.make_scene(args.config)
     log(f"bench: workload {args.config} P={sc.P} Q={sc.Q} N={sc.N}")
+    if args.kernel_only:
+        geo = clsimg.Geometry(sc.pos, sc.lam, sc.grid)
+        ctx = clsimg.Context(0)
+        R = torch.as_tensor(sc.R_hat32).cuda()
+        out = torch.empty(sc.Q, dtype=torch.float32, device="cuda")
+        for _ in range(20):
+            ctx.dirty_image(R, geo, mf=out)
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        ctx.close()
+        log(f"bench: kernel-only run done (20 beamformer launches, 3 copies of {args.copy_mib} MiB)")
+        return
     geo = clsimg.Geometry(sc.pos, sc.lam, sc.grid)
     opts = clsimg.default_options()
     opts.nsamples = sc.N
@@ -201,7 +242,7 @@ def main():
         "roofline": {"kernel": "beam_kernel<MF> (dirty image, full grid)",
                      "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 5),
-                     "traffic": None, "us_per_launch": round(t_kernel * 1e6, 3), "timing": timing,
+                     "traffic": measured_traffic(), "us_per_launch": round(t_kernel * 1e6, 3), "timing": timing,
                      "flops_per_launch": kflops, "mfma_issued_flops_per_launch": exec_flops,
                      "mfma_issued_frac": round(exec_flops / t_kernel / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5)},
     }

@@ -205,8 +205,12 @@ int ensure_workspace(clsimg_ctx* c, int P, int Q) {
   ST_TRY(ensure(c, c->part, part_floats_max(P) * sizeof(float)));
   ST_TRY(ensure(c, c->beta_part, (size_t)reduce_blocks(P) * sizeof(double)));
   ST_TRY(ensure(c, c->alpha_part, (size_t)(ntiles_adj(P, Q) + 1) * sizeof(double)));
-  ST_TRY(ensure(c, c->keys, (size_t)(std::max(ntiles_adj(P, Q), beam_grid(Q)) + 1) * sizeof(uint64_t)));
-  ST_TRY(ensure(c, c->frag_b, (size_t)2 * (Pp / 8) * (Pp / 8 + 1) * 64 * sizeof(float)));
+  ST_TRY(ensure(c, c->keys,
+                (size_t)(std::max(ntiles_adj(P, Q), std::max(beam_grid(Q), beam_big_grid(Q))) + 1) *
+                    sizeof(uint64_t)));
+  const size_t fb = beam_fits(P) ? (size_t)2 * (Pp / 8) * (Pp / 8 + 1) * 64
+                                 : (beam_big_fits(P) ? beam_big_frag_floats(P) : 64);
+  ST_TRY(ensure(c, c->frag_b, fb * sizeof(float)));
   ST_TRY(ensure(c, c->B0, cx));
   ST_TRY(ensure(c, c->Bb, cx));
   ST_TRY(ensure(c, c->u, cx));
@@ -261,12 +265,22 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
   return CLSIMG_OK;
 }
 
-// Full-grid beamformer for P <= 48: fragments of U, then one pass over all
-// pixels with them held in registers.
+bool beam_any(int P) { return beam_fits(P) || beam_big_fits(P); }
+
+// Full-grid beamformer: for P <= 48 the block-triangular fragments of U stay
+// in registers for the whole pass; for larger arrays (up to 288) the
+// fragments are prepared once and streamed by the GEMM-shaped kernel.
 enum BeamKind { BEAM_MF, BEAM_MVDR, BEAM_STORE };
 int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamKind kind, float* out,
               float* eps, float eps_scale, double C, double kb, float scale, hipStream_t st) {
   const Tables tab = tables_of(c, g, P);
+  if (!beam_fits(P)) {  // larger arrays: fragments of the whole Ut, GEMM-shaped kernel
+    HIP_TRY(launch_beam_prep_full(U, P, P_<float>(c->frag_b), st));
+    const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
+    HIP_TRY(launch_beam_big(k, P_<const float>(c->frag_b), tab, nullptr, out, eps, eps_scale, C, kb, scale,
+                            nullptr, nullptr, st));
+    return CLSIMG_OK;
+  }
   // fragments built inside the kernel, or prepared by a separate pass
   const float* fb = c->beam_prep ? P_<float>(c->frag_b) : nullptr;
   const float2* Uk = c->beam_prep ? nullptr : U;
@@ -302,7 +316,7 @@ int compute_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, con
   }
   if (o->bound == CLSIMG_BOUND_MF) {
     const double scale = 1.0 + (o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)o->nsamples) : 0.0);
-    if (beam_fits(P)) return beam_full(c, g, P, Rf, BEAM_STORE, gamma, nullptr, 0.f, 0, 0, (float)scale, st);
+    if (beam_any(P)) return beam_full(c, g, P, Rf, BEAM_STORE, gamma, nullptr, 0.f, 0, 0, (float)scale, st);
     HIP_TRY(launch_adjoint_store(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), gamma,
                                  (float)scale, st));
     return CLSIMG_OK;
@@ -312,7 +326,7 @@ int compute_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, con
   ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
   if (*c->h_status != 0) return CLSIMG_ENOTPD;
   const double kb = o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1)) : 0.0;
-  if (beam_fits(P))
+  if (beam_any(P))
     return beam_full(c, g, P, P_<const float2>(c->Rinv), BEAM_MVDR, gamma, nullptr, 0.f, o->C, kb, 1.f, st);
   HIP_TRY(launch_adjoint_mvdr(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, P_<const float2>(c->Rinv)),
                               gamma, o->C, kb, st));
@@ -445,7 +459,7 @@ int clsimg_dirty_image(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a
   ST_TRY(ensure_workspace(c, P, Q));
   ST_TRY(ensure_tables(c, a, g, st));
   const float2* Rf = reinterpret_cast<const float2*>(R);
-  if (beam_fits(P)) return beam_full(c, g, P, Rf, BEAM_MF, mf, nullptr, 0.f, 0, 0, 1.f, st);
+  if (beam_any(P)) return beam_full(c, g, P, Rf, BEAM_MF, mf, nullptr, 0.f, 0, 0, 1.f, st);
   HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, nullptr, 0.f, st));
   return CLSIMG_OK;
 }
@@ -486,7 +500,7 @@ int clsimg_adjoint(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, c
   ST_TRY(ensure_workspace(c, P, std::max(n, g->nl * g->nm)));
   ST_TRY(ensure_tables(c, a, g, st));
   if (n == 0) return CLSIMG_OK;
-  if (!idx && n == g->nl * g->nm && beam_fits(P))
+  if (!idx && n == g->nl * g->nm && beam_any(P))
     return beam_full(c, g, P, reinterpret_cast<const float2*>(U), BEAM_STORE, out, nullptr, 0.f, 0, 0, 1.f,
                      st);
   HIP_TRY(launch_adjoint_store(
@@ -573,7 +587,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   double flops = beam_flops(P, Q) + (o->bound != CLSIMG_BOUND_NONE ? beam_flops(P, Q) : 0.0);
   // bounds and threshold (Sec. II-D, App. A)
   const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
-  if (beam_fits(P)) {
+  if (beam_any(P)) {
     ST_TRY(beam_full(c, g, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
   } else {
     HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, eps, eps_scale,
@@ -606,6 +620,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   int batch = 4;
   const int ntiles_Q = ntiles_adj(P, Q);
   const bool beam_full_grid = beam_fits(P) && !c->old_beam;
+  const bool beam_big_grid_ok = !beam_fits(P) && beam_big_fits(P) && !c->old_beam;
   bool host_loop = true;
   if (beam_full_grid && outer_fits(P) && !c->host_loop && !c->trace) {
     // Table I on the device: one workgroup per outer step, the full-grid
@@ -824,7 +839,12 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, bsub, 1.f, -1.f, nullptr, frag_r, nullptr,
                            grad_stop, st));
         }
-        if (beam_full_grid) {
+        if (!beam_full_grid && beam_big_grid_ok) {
+          HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
+          HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr, 0.f,
+                                  0, 0, 1.f, state, keys, st));
+          HIP_TRY(launch_argmin_final(keys, beam_big_grid(Q), eps, state, dec, st));
+        } else if (beam_full_grid) {
           if (c->beam_prep) HIP_TRY(launch_beam_prep(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_lambda(c->beam_prep ? P_<const float>(c->frag_b) : nullptr,
                                      c->beam_prep ? nullptr : E, P, tables_of(c, g, P), grad_stop, state,

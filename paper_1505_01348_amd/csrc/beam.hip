@@ -237,7 +237,141 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
   epi.finish();
 }
 
+// ---------------------------------------------------------------------------
+// Larger arrays (P > 48): the fragments of the whole Ut no longer fit in
+// registers, so the product is organised like a GEMM.  A workgroup takes 64
+// pixels (four 16-pixel tiles); wave w owns the row tiles m = w, w + 4, ...
+// (RPW of them, padded rows are zero) and streams their fragments from L2
+// (prepared once per call by beam_prep_full_kernel, same row permutation as
+// above, full matrix, no doubling) while it generates the B operands of the
+// four pixel tiles from the tables, one complex product per two 4-row
+// chunks.  After the K loop the column dot needs the lane's entries of its own
+// row tiles again: they are recomputed from the tables (two complex products
+// per row tile and pixel tile).  The four waves' partial sums meet in LDS.
+constexpr int kBigTiles = 4;  // 16-pixel tiles per workgroup
+
+__host__ __device__ inline int big_rpw(int MT) { return (MT + 3) / 4; }
+
+__global__ void beam_prep_full_kernel(const float2* __restrict__ U, int P, int MT, float* __restrict__ frag) {
+  const int KS = 4 * MT, rows = 4 * big_rpw(MT);
+  const int total = rows * KS * 64;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int f = e >> 6, l = e & 63;
+    const int m = f / KS, kc = f - m * KS;
+    const int c16 = l & 15, qq = l >> 4;
+    int p, s, p2, t;
+    beam_pos(16 * m + 4 * (c16 & 3) + (c16 >> 2), p, s);
+    beam_pos(4 * kc + qq, p2, t);
+    float v = 0.f;
+    if (m < MT && p < P && p2 < P) {
+      const float2 x = U[p * P + p2], y = U[p2 * P + p];
+      const float hr = 0.5f * (x.x + y.x), hi = 0.5f * (x.y - y.y);
+      v = (s == t) ? hr : (s == 0 ? -hi : hi);
+    }
+    frag[e] = v;
+  }
+}
+
+template <int RPW, class Epi>
+__global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__ frag, int MT, Tables tab,
+                                                       const int* skip, Epi epi) {
+  constexpr int NT = kBigTiles;
+  if (skip && *skip) return;
+  __shared__ float gsum[4][NT * 16];
+  const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  const int w = threadIdx.x >> 6;
+  const int KS = 4 * MT;
+  const int Q = tab.Q, nl = tab.nl, nm = tab.nm;
+  const int ntiles = (Q + 15) >> 4;
+  epi.init();
+  for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
+    // this lane's pixel in each of the block's tiles (clamped; masked at the end)
+    const float2* el[NT];
+    const float2* em[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
+      const int im = pix / nl, il = pix - im * nl;
+      el[t] = tab.El + (size_t)q * nl + il;
+      em[t] = tab.Em + (size_t)q * nm + im;
+    }
+    v4f acc[RPW][NT];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const float* fw = frag + (size_t)w * KS * 64 + lane;  // row tile w, chunk 0
+    const size_t rstep = (size_t)4 * KS * 64;             // next row tile of this wave
+    for (int j = 0; j < KS / 2; ++j) {                    // chunk pair 2j, 2j + 1: antenna 4j + q
+      float b0[NT], b1[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float2 a = cmul(el[t][(size_t)4 * j * nl], em[t][(size_t)4 * j * nm]);
+        b0[t] = a.x;
+        b1[t] = a.y;
+      }
+      float f0[RPW], f1[RPW];
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        f0[i] = fw[i * rstep + (size_t)(2 * j) * 64];
+        f1[i] = fw[i * rstep + (size_t)(2 * j + 1) * 64];
+      }
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          acc[i][t] = mfma16x16x4(f0[i], b0[t], acc[i][t]);
+          acc[i][t] = mfma16x16x4(f1[i], b1[t], acc[i][t]);
+        }
+    }
+    // column dot over this wave's row tiles: accumulator element r of row tile m
+    // pairs with chunk 4m + r, i.e. antenna 8m + 4(r >> 1) + q, component r & 1
+    float gp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      gp[t] = 0.f;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int m = w + 4 * i;
+        if (m < MT) {
+          const float2 a0 = cmul(el[t][(size_t)(8 * m) * nl], em[t][(size_t)(8 * m) * nm]);
+          const float2 a1 = cmul(el[t][(size_t)(8 * m + 4) * nl], em[t][(size_t)(8 * m + 4) * nm]);
+          gp[t] += acc[i][t][0] * a0.x + acc[i][t][1] * a0.y + acc[i][t][2] * a1.x + acc[i][t][3] * a1.y;
+        }
+      }
+      gp[t] += __shfl_xor(gp[t], 16, 64);
+      gp[t] += __shfl_xor(gp[t], 32, 64);
+    }
+    if (q == 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) gsum[w][16 * t + c16] = gp[t];
+    }
+    __syncthreads();
+    if (threadIdx.x < NT * 16) {
+      const int t = threadIdx.x >> 4;
+      const int pix = 16 * (blk * NT + t) + (threadIdx.x & 15);
+      const float g = (gsum[0][threadIdx.x] + gsum[1][threadIdx.x]) + (gsum[2][threadIdx.x] + gsum[3][threadIdx.x]);
+      epi(pix, g, pix < Q);
+    }
+    __syncthreads();
+  }
+  epi.finish();
+}
+
 bool beam_fits(int P) { return pad_p(P) / 8 <= kBeamMaxMT; }
+
+constexpr int kBigMaxRPW = 9;  // up to 36 row tiles: P <= 288
+bool beam_big_fits(int P) { return big_rpw(pad_p(P) / 8) <= kBigMaxRPW; }
+
+size_t beam_big_frag_floats(int P) {
+  const int MT = pad_p(P) / 8;
+  return (size_t)4 * big_rpw(MT) * 4 * MT * 64;
+}
+
+int beam_big_grid(int Q) {
+  const int nblk = ((Q + 15) / 16 + kBigTiles - 1) / kBigTiles;
+  return nblk < 1 ? 1 : (nblk > 8192 ? 8192 : nblk);
+}
 
 int beam_grid(int Q) {
   const int ntiles = (Q + 15) / 16;
@@ -266,6 +400,45 @@ static hipError_t launch_beam(const float* frag, const float2* U, int P, const T
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st) {
+  const int MT = pad_p(P) / 8;
+  const size_t n = beam_big_frag_floats(P);
+  int g = (int)((n + 255) / 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(beam_prep_full_kernel, dim3(g), dim3(256), 0, st, U, P, MT, frag);
+  return hipGetLastError();
+}
+
+template <class Epi>
+static hipError_t launch_big(const float* frag, const Tables& tab, const int* skip, Epi epi, hipStream_t st) {
+  const int MT = tab.Pp / 8;
+  const dim3 g(beam_big_grid(tab.Q)), b(256);
+  switch (big_rpw(MT)) {
+    case 1: hipLaunchKernelGGL((beam_big_kernel<1, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 2: hipLaunchKernelGGL((beam_big_kernel<2, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 3: hipLaunchKernelGGL((beam_big_kernel<3, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 4: hipLaunchKernelGGL((beam_big_kernel<4, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 5: hipLaunchKernelGGL((beam_big_kernel<5, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 6: hipLaunchKernelGGL((beam_big_kernel<6, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 7: hipLaunchKernelGGL((beam_big_kernel<7, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 8: hipLaunchKernelGGL((beam_big_kernel<8, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 9: hipLaunchKernelGGL((beam_big_kernel<9, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
+                           float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
+                           hipStream_t st) {
+  switch (kind) {
+    case 0: return launch_big(frag, tab, skip, BeamMF{out, eps, eps_scale}, st);
+    case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st);
+    case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st);
+    default: return launch_big(frag, tab, skip, BeamLambda{state, part, 0}, st);
+  }
 }
 
 hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,

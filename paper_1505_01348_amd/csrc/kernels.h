@@ -287,6 +287,15 @@ hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Ta
                              float scale, hipStream_t st);
 hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
                               const uint8_t* state, uint64_t* part, hipStream_t st);
+// GEMM-shaped full-grid beamformer for larger arrays (P <= 288)
+bool beam_big_fits(int P);
+size_t beam_big_frag_floats(int P);
+int beam_big_grid(int Q);  // workgroups (= partial keys of the lambda variant)
+hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st);
+// kind: 0 MF (+ threshold), 1 MVDR bound, 2 store (scaled), 3 multipliers with argmin keys
+hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
+                           float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
+                           hipStream_t st);
 // lsqr_cu.hip
 bool lsqr_cu_fits(int P, int n);
 hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st);

@@ -206,7 +206,7 @@ int ensure_workspace(clsimg_ctx* c, int P, int Q) {
   ST_TRY(ensure(c, c->beta_part, (size_t)reduce_blocks(P) * sizeof(double)));
   ST_TRY(ensure(c, c->alpha_part, (size_t)(ntiles_adj(P, Q) + 1) * sizeof(double)));
   ST_TRY(ensure(c, c->keys,
-                (size_t)(std::max(ntiles_adj(P, Q), std::max(beam_grid(Q), beam_big_grid(Q))) + 1) *
+                (size_t)(std::max(ntiles_adj(P, Q), std::max(beam_grid(Q), beam_big_grid(P, Q))) + 1) *
                     sizeof(uint64_t)));
   const size_t fb = beam_fits(P) ? (size_t)2 * (Pp / 8) * (Pp / 8 + 1) * 64
                                  : (beam_big_fits(P) ? beam_big_frag_floats(P) : 64);
@@ -843,7 +843,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr, 0.f,
                                   0, 0, 1.f, state, keys, st));
-          HIP_TRY(launch_argmin_final(keys, beam_big_grid(Q), eps, state, dec, st));
+          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q), eps, state, dec, st));
         } else if (beam_full_grid) {
           if (c->beam_prep) HIP_TRY(launch_beam_prep(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_lambda(c->beam_prep ? P_<const float>(c->frag_b) : nullptr,

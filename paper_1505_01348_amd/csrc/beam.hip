@@ -239,8 +239,8 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
 
 // ---------------------------------------------------------------------------
 // Larger arrays (P > 48): the fragments of the whole Ut no longer fit in
-// registers, so the product is organised like a GEMM.  A workgroup takes 64
-// pixels (four 16-pixel tiles); wave w owns the row tiles m = w, w + 4, ...
+// registers, so the product is organised like a GEMM.  A workgroup takes NT
+// 16-pixel tiles (two or four); wave w owns the row tiles m = w, w + 4, ...
 // (RPW of them, padded rows are zero) and streams their fragments from L2
 // (prepared once per call by beam_prep_full_kernel, same row permutation as
 // above, full matrix, no doubling) while it generates the B operands of the
@@ -248,9 +248,14 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
 // chunks.  After the K loop the column dot needs the lane's entries of its own
 // row tiles again: they are recomputed from the tables (two complex products
 // per row tile and pixel tile).  The four waves' partial sums meet in LDS.
-constexpr int kBigTiles = 4;  // 16-pixel tiles per workgroup
-
 __host__ __device__ inline int big_rpw(int MT) { return (MT + 3) / 4; }
+// 16-pixel tiles per workgroup (measured: two for up to 16 row tiles, where
+// more workgroups hide the load latency, four for longer K loops, where the
+// fragment loads are shared by more MFMAs)
+__host__ __device__ constexpr int big_nt(int rpw) { return rpw <= 4 ? 2 : 4; }
+// loads of the next chunk pair issued before the current pair's MFMAs while
+// the registers allow it (short K loops, i.e. up to 16 row tiles)
+__host__ __device__ constexpr bool big_prefetch(int rpw) { return rpw <= 4; }
 
 __global__ void beam_prep_full_kernel(const float2* __restrict__ U, int P, int MT, float* __restrict__ frag) {
   const int KS = 4 * MT, rows = 4 * big_rpw(MT);
@@ -275,7 +280,8 @@ __global__ void beam_prep_full_kernel(const float2* __restrict__ U, int P, int M
 template <int RPW, class Epi>
 __global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__ frag, int MT, Tables tab,
                                                        const int* skip, Epi epi) {
-  constexpr int NT = kBigTiles;
+  constexpr int NT = big_nt(RPW);
+  constexpr bool kPrefetch = big_prefetch(RPW);
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
@@ -302,27 +308,75 @@ __global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__
       for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
     const float* fw = frag + (size_t)w * KS * 64 + lane;  // row tile w, chunk 0
     const size_t rstep = (size_t)4 * KS * 64;             // next row tile of this wave
-    for (int j = 0; j < KS / 2; ++j) {                    // chunk pair 2j, 2j + 1: antenna 4j + q
-      float b0[NT], b1[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const float2 a = cmul(el[t][(size_t)4 * j * nl], em[t][(size_t)4 * j * nm]);
-        b0[t] = a.x;
-        b1[t] = a.y;
-      }
+    if constexpr (kPrefetch) {
+      float2 te[NT], tm[NT];
       float f0[RPW], f1[RPW];
-#pragma unroll
-      for (int i = 0; i < RPW; ++i) {
-        f0[i] = fw[i * rstep + (size_t)(2 * j) * 64];
-        f1[i] = fw[i * rstep + (size_t)(2 * j + 1) * 64];
+  #pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        te[t] = el[t][0];
+        tm[t] = em[t][0];
       }
-#pragma unroll
-      for (int i = 0; i < RPW; ++i)
-#pragma unroll
+  #pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        f0[i] = fw[i * rstep];
+        f1[i] = fw[i * rstep + 64];
+      }
+      for (int j = 0; j < KS / 2; ++j) {                    // chunk pair 2j, 2j + 1: antenna 4j + q
+        float b0[NT], b1[NT];
+  #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          acc[i][t] = mfma16x16x4(f0[i], b0[t], acc[i][t]);
-          acc[i][t] = mfma16x16x4(f1[i], b1[t], acc[i][t]);
+          const float2 a = cmul(te[t], tm[t]);
+          b0[t] = a.x;
+          b1[t] = a.y;
         }
+        float g0[RPW], g1[RPW];
+  #pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          g0[i] = f0[i];
+          g1[i] = f1[i];
+        }
+        const int jn = j + 1 < KS / 2 ? j + 1 : j;  // loads of the next pair
+  #pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          te[t] = el[t][(size_t)4 * jn * nl];
+          tm[t] = em[t][(size_t)4 * jn * nm];
+        }
+  #pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          f0[i] = fw[i * rstep + (size_t)(2 * jn) * 64];
+          f1[i] = fw[i * rstep + (size_t)(2 * jn + 1) * 64];
+        }
+  #pragma unroll
+        for (int i = 0; i < RPW; ++i)
+  #pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            acc[i][t] = mfma16x16x4(g0[i], b0[t], acc[i][t]);
+            acc[i][t] = mfma16x16x4(g1[i], b1[t], acc[i][t]);
+          }
+      }
+    } else {
+      for (int j = 0; j < KS / 2; ++j) {                    // chunk pair 2j, 2j + 1: antenna 4j + q
+        float b0[NT], b1[NT];
+  #pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const float2 a = cmul(el[t][(size_t)4 * j * nl], em[t][(size_t)4 * j * nm]);
+          b0[t] = a.x;
+          b1[t] = a.y;
+        }
+        float f0[RPW], f1[RPW];
+  #pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          f0[i] = fw[i * rstep + (size_t)(2 * j) * 64];
+          f1[i] = fw[i * rstep + (size_t)(2 * j + 1) * 64];
+        }
+  #pragma unroll
+        for (int i = 0; i < RPW; ++i)
+  #pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            acc[i][t] = mfma16x16x4(f0[i], b0[t], acc[i][t]);
+            acc[i][t] = mfma16x16x4(f1[i], b1[t], acc[i][t]);
+          }
+      }
     }
     // column dot over this wave's row tiles: accumulator element r of row tile m
     // pairs with chunk 4m + r, i.e. antenna 8m + 4(r >> 1) + q, component r & 1
@@ -368,8 +422,9 @@ size_t beam_big_frag_floats(int P) {
   return (size_t)4 * big_rpw(MT) * 4 * MT * 64;
 }
 
-int beam_big_grid(int Q) {
-  const int nblk = ((Q + 15) / 16 + kBigTiles - 1) / kBigTiles;
+int beam_big_grid(int P, int Q) {
+  const int nt = big_nt(big_rpw(pad_p(P) / 8));
+  const int nblk = ((Q + 15) / 16 + nt - 1) / nt;
   return nblk < 1 ? 1 : (nblk > 8192 ? 8192 : nblk);
 }
 
@@ -414,7 +469,7 @@ hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_
 template <class Epi>
 static hipError_t launch_big(const float* frag, const Tables& tab, const int* skip, Epi epi, hipStream_t st) {
   const int MT = tab.Pp / 8;
-  const dim3 g(beam_big_grid(tab.Q)), b(256);
+  const dim3 g(beam_big_grid(tab.Pp, tab.Q)), b(256);
   switch (big_rpw(MT)) {
     case 1: hipLaunchKernelGGL((beam_big_kernel<1, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
     case 2: hipLaunchKernelGGL((beam_big_kernel<2, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;

@@ -290,7 +290,7 @@ hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const T
 // GEMM-shaped full-grid beamformer for larger arrays (P <= 288)
 bool beam_big_fits(int P);
 size_t beam_big_frag_floats(int P);
-int beam_big_grid(int Q);  // workgroups (= partial keys of the lambda variant)
+int beam_big_grid(int P, int Q);  // workgroups (= partial keys of the lambda variant)
 hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st);
 // kind: 0 MF (+ threshold), 1 MVDR bound, 2 store (scaled), 3 multipliers with argmin keys
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,

@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-7, help="LSQR atol = btol")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 288-antenna full-grid beamformer timing")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only launch the beamformer (20 times) and a plain copy of --copy-mib MiB "
                          "(3 times): the program the HBM traffic counters are read on")
@@ -214,6 +216,34 @@ def main():
     log(f"bench: beam kernel {t_kernel * 1e6:.2f} us/launch ({timing}), {achieved:.2f} TFLOP/s dense count, "
         f"{exec_flops / t_kernel / 1e12:.2f} TFLOP/s issued MFMA")
 
+    # the same operation at the largest workload's full size (288 antennas,
+    # 512 x 512 pixels), where the GEMM-shaped beamformer runs
+    big = None
+    if not args.no_large:
+        sb = synth.make_scene("c4")
+        gb = clsimg.Geometry(sb.pos, sb.lam, sb.grid)
+        Rb = torch.as_tensor(sb.R_hat32).cuda()
+        ob = torch.empty(sb.Q, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            ctx.dirty_image(Rb, gb, mf=ob)
+        torch.cuda.synchronize()
+        reps_b = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps_b):
+            ctx.dirty_image(Rb, gb, mf=ob)
+        e1.record()
+        torch.cuda.synchronize()
+        tb = e0.elapsed_time(e1) / 1e3 / reps_b
+        fb = 8.0 * sb.P * sb.P * sb.Q + 8.0 * sb.P * sb.Q
+        big = {"kernel": "beam_prep_full + beam_big_kernel<9, BeamMF> (dirty image, full grid)",
+               "workload": "P=288, 512x512 pixels (the 288-antenna workload's size)", "bound": "mfma",
+               "achieved": round(fb / tb / 1e12, 4), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+               "frac": round(fb / tb / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5), "us_per_launch": round(tb * 1e6, 2),
+               "flops_per_launch": fb, "timing": "eager (each call is milliseconds long)"}
+        log(f"bench: 288-antenna dirty image {tb * 1e6:.1f} us, {fb / tb / 1e12:.1f} TFLOP/s")
+        del Rb, ob
+
     lat_ms = np.array(lat) * 1e3
     solves_per_s = args.steps / total
     psi_tflops = flops / total / 1e12
@@ -246,6 +276,8 @@ def main():
                      "flops_per_launch": kflops, "mfma_issued_flops_per_launch": exec_flops,
                      "mfma_issued_frac": round(exec_flops / t_kernel / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5)},
     }
+    if big is not None:
+        result["roofline_full_size"] = big
     if not args.no_cpu:
         base, ref = cpu_baseline(sc, tol_oracle=1e-8)
         result["cpu_baseline"] = base

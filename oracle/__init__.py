@@ -15,6 +15,8 @@ imaging     steering vectors, the Khatri-Rao operators (correlation /
 lsqr        Golub-Kahan bidiagonalisation with the LSQR updates (Sec. IV-A)
 active_set  the active-set solver of Table I with the detection threshold
             (Sec. III)
+pwls        the constrained preconditioned weighted LS problem (eq. preWLS)
+            as the LS problem on whitened, D-scaled inputs
 
 Pins (what the oracle is checked against, in tests/test_oracle_*.py): the
 Kronecker/Khatri-Rao identities of the Notation section against an explicitly
@@ -26,7 +28,12 @@ the active-set solution against SciPy's BVLS and brute-force enumeration
 on-grid sources from an exact covariance, and invariances (scale, antenna
 permutation, array translation, mirror).  The thresholded path with
 kappa_d > 0 beyond those pins is defined by this oracle ("parity unpinned" for
-the exact add/drop sequence).
+the exact add/drop sequence).  PWLS (tests/test_oracle_pwls.py): Cholesky
+whitening against the R^-1/2 weighting from an eigendecomposition, the
+transformed operators against the dense weighted Khatri-Rao matrix, the
+gradient at zero against the unbiased MVDR image from R^-1, the box solution
+against BVLS with KKT, bound pixels at gamma in image units, and the
+threshold's MVDR standard deviation against a Monte Carlo.
 """
 
 from .imaging import (  # noqa: F401
@@ -42,3 +49,4 @@ from .imaging import (  # noqa: F401
 )
 from .lsqr import lsqr, LsqrResult  # noqa: F401
 from .active_set import solve, SolveResult, STATE_L, STATE_F, STATE_U  # noqa: F401
+from .pwls import pwls_problem, pwls_scaling, pwls_threshold, solve_pwls, whitening_factor  # noqa: F401

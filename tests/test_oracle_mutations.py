@@ -17,7 +17,9 @@ import oracle
 oas = importlib.import_module("oracle.active_set")
 oim = importlib.import_module("oracle.imaging")
 olsqr = importlib.import_module("oracle.lsqr")  # the package re-exports a function of that name
+opw = importlib.import_module("oracle.pwls")
 from tests import test_oracle_pins as pins
+from tests import test_oracle_pwls as ppins
 
 PINS = [
     pins.test_steering_matches_entrywise_model_and_is_unit_norm,
@@ -41,6 +43,12 @@ PINS = [
     pins.test_first_release_is_dirty_image_peak,
     lambda: pins.test_exact_recovery_from_exact_covariance([(200, 5.0), (615, 2.0)]),
     pins.test_solution_respects_bounds_and_kkt_with_threshold,
+    ppins.test_cholesky_whitening_has_the_paper_cost,
+    ppins.test_transformed_operators_equal_dense_weighted_psi,
+    lambda: ppins.test_gradient_at_zero_is_minus_unbiased_mvdr_image(0.8),
+    lambda: ppins.test_box_pwls_matches_bvls_and_kkt("mvdr"),
+    ppins.test_threshold_std_matches_monte_carlo_of_mvdr_image,
+    ppins.test_upper_set_pixels_sit_at_the_image_bound,
 ]
 
 MUTATIONS = [
@@ -69,6 +77,14 @@ MUTATIONS = [
     (oas, "k = int(np.argmin(lam))", "k = int(np.argmax(lam))"),
     (oas, "E = forward(A[:, S], sigma[S]) - B0", "E = B0 - forward(A[:, S], sigma[S])"),
     (oas, "if lam_min < -thr:", "if lam_min < thr:"),
+    (opw, "return h * h / C, h", "return h / C, h"),
+    (opw, "Ahat = (Linv @ A) / np.sqrt(D)[None, :]", "Ahat = (Linv @ A) / D[None, :]"),
+    (opw, "Bhat = Linv @ np.asarray(B0, dtype=np.complex128) @ Linv.conj().T",
+     "Bhat = Linv @ np.asarray(B0, dtype=np.complex128) @ Linv.T"),
+    (opw, "return kappa_d / (np.asarray(h, dtype=np.float64) * math.sqrt(nsamples - P - 1))",
+     "return kappa_d / (np.sqrt(np.asarray(h, dtype=np.float64)) * math.sqrt(nsamples - P - 1))"),
+    (opw, "res.sigma = res.sigma / D", "res.sigma = res.sigma * D"),
+    (opw, "gamma_pw = D * np.asarray(gamma, dtype=np.float64)", "gamma_pw = np.asarray(gamma, dtype=np.float64)"),
 ]
 
 

@@ -51,6 +51,7 @@ extern "C" {
 #define CLSIMG_ENOTPD (-2)   /* covariance not positive definite or not finite           */
 #define CLSIMG_ENOMEM (-3)   /* workspace would exceed the context's HBM budget          */
 #define CLSIMG_EHIP (-4)     /* a HIP runtime call failed                                */
+#define CLSIMG_ENOTSUP (-5)  /* option not available for this problem (see cost below)   */
 
 /* bound kinds for clsimg_opts.bound */
 #define CLSIMG_BOUND_MVDR 0  /* gamma = C / (a^H R^-1 a) (+ kappa_b std), Sec. II-D  */
@@ -59,6 +60,14 @@ extern "C" {
 
 /* arithmetic of the Psi / Psi^H contractions */
 #define CLSIMG_FP32 0
+
+/* cost function for clsimg_opts.cost */
+#define CLSIMG_COST_LS 0     /* 1/2 ||B0 - Psi sigma||^2, eq. CLS                         */
+#define CLSIMG_COST_PWLS 1   /* preconditioned weighted LS, eq. preWLS: R^-1/2 weighting  */
+                             /* on both sides, variable D sigma with D_i = h_i^2 / C,     */
+                             /* h_i = a_i^H R^-1 a_i; threshold kappa_d std of the MVDR   */
+                             /* image (App. A).  Needs P <= 48 and free sets that fit one */
+                             /* workgroup (CLSIMG_ENOTSUP otherwise).                     */
 
 /* pixel states in clsimg_solve's `state` output */
 #define CLSIMG_STATE_L 0     /* sigma_i = 0        */
@@ -94,6 +103,7 @@ typedef struct {
   int32_t itnlim;         /* LSQR iterations per subproblem, -1 = 4|F|+100      */
   int32_t max_outer;      /* subproblem solves, -1 = 4Q                         */
   int32_t precision;      /* CLSIMG_FP32                                        */
+  int32_t cost;           /* CLSIMG_COST_*                           (LS)       */
 } clsimg_opts;
 
 typedef struct {

@@ -20,9 +20,10 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libclsimg.so")
 
 OK, WMAXOUTER, WITNLIM, WCYCLE = 0, 1, 2, 3
-EINVAL, ENOTPD, ENOMEM, EHIP = -1, -2, -3, -4
+EINVAL, ENOTPD, ENOMEM, EHIP, ENOTSUP = -1, -2, -3, -4, -5
 BOUND_MVDR, BOUND_MF, BOUND_NONE = 0, 1, 2
 FP32 = 0
+COST_LS, COST_PWLS = 0, 1
 STATE_L, STATE_F, STATE_U = 0, 1, 2
 MAX_P = 288
 
@@ -44,7 +45,7 @@ class COpts(C.Structure):
     _fields_ = [("bound", C.c_int32), ("C", C.c_double), ("kappa_b", C.c_double),
                 ("kappa_d", C.c_double), ("nsamples", C.c_int64), ("atol", C.c_double),
                 ("btol", C.c_double), ("conlim", C.c_double), ("itnlim", C.c_int32),
-                ("max_outer", C.c_int32), ("precision", C.c_int32)]
+                ("max_outer", C.c_int32), ("precision", C.c_int32), ("cost", C.c_int32)]
 
 
 class CStats(C.Structure):
@@ -114,17 +115,18 @@ class Options:
     itnlim: int = -1
     max_outer: int = -1
     precision: int = FP32
+    cost: int = COST_LS
 
     def to_c(self) -> COpts:
         return COpts(self.bound, self.C, self.kappa_b, self.kappa_d, self.nsamples, self.atol,
-                     self.btol, self.conlim, self.itnlim, self.max_outer, self.precision)
+                     self.btol, self.conlim, self.itnlim, self.max_outer, self.precision, self.cost)
 
 
 def default_options() -> Options:
     o = COpts()
     lib().clsimg_default_opts(C.byref(o))
     return Options(o.bound, o.C, o.kappa_b, o.kappa_d, o.nsamples, o.atol, o.btol, o.conlim,
-                   o.itnlim, o.max_outer, o.precision)
+                   o.itnlim, o.max_outer, o.precision, o.cost)
 
 
 def _ptr(t):

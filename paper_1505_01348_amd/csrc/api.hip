@@ -49,6 +49,7 @@ struct clsimg_ctx {
   DevBuf lsqr, dec, status;
   DevBuf lsqr2, done, x1, w1, vraw, bpart0, bpart1, xf, bar;  // fused LSQR step
   DevBuf ostate;                                                // device-resident outer loop
+  DevBuf pw_h, pw_rs, pw_g, pw_eps, pw_dinv, pw_Lw, pw_B0w;      // PWLS inputs
   SolveDecision* h_dec = nullptr;
   OuterState* h_outer = nullptr;
   LsqrState* h_lsqr = nullptr;
@@ -342,6 +343,8 @@ int check_opts(const clsimg_opts* o, int P) {
   if (!o) return CLSIMG_EINVAL;
   if (o->bound < CLSIMG_BOUND_MVDR || o->bound > CLSIMG_BOUND_NONE) return CLSIMG_EINVAL;
   if (o->precision != CLSIMG_FP32) return CLSIMG_EINVAL;
+  if (o->cost != CLSIMG_COST_LS && o->cost != CLSIMG_COST_PWLS) return CLSIMG_EINVAL;
+  if (o->cost == CLSIMG_COST_PWLS && !(o->C > 0.0)) return CLSIMG_EINVAL;
   if (o->bound == CLSIMG_BOUND_MVDR && !(o->C > 0.0)) return CLSIMG_EINVAL;
   if (o->kappa_b != 0.0) {
     if (o->bound == CLSIMG_BOUND_MVDR && o->nsamples <= P + 1) return CLSIMG_EINVAL;
@@ -369,6 +372,7 @@ void clsimg_default_opts(clsimg_opts* o) {
   o->itnlim = -1;
   o->max_outer = -1;
   o->precision = CLSIMG_FP32;
+  o->cost = CLSIMG_COST_LS;
 }
 
 int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
@@ -420,7 +424,7 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (!c) return CLSIMG_EINVAL;
   DeviceGuard guard(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->part,  &c->beta_part,
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->part,  &c->beta_part,
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
@@ -445,6 +449,7 @@ const char* clsimg_strerror(int s) {
     case CLSIMG_ENOTPD: return "covariance is not positive definite or not finite";
     case CLSIMG_ENOMEM: return "workspace exceeds the HBM budget or allocation failed";
     case CLSIMG_EHIP: return "HIP runtime error";
+    case CLSIMG_ENOTSUP: return "option not available for this problem size";
     default: return "unknown status";
   }
 }
@@ -542,6 +547,17 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   }
   ST_TRY(ensure(c, c->alpha_part, (size_t)(Q / 32 + 64) * sizeof(double)));
 
+  // PWLS runs on the device-resident loop only (P <= 48)
+  const bool pwls = o->cost == CLSIMG_COST_PWLS;
+  const bool device_loop = beam_fits(P) && outer_fits(P) && !c->old_beam && !c->host_loop && !c->trace;
+  if (pwls && !device_loop) return CLSIMG_ENOTSUP;
+  if (pwls && o->nsamples <= P + 1 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
+  if (pwls) {
+    for (DevBuf* b : {&c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv})
+      ST_TRY(ensure(c, *b, (size_t)Q * sizeof(float)));
+    ST_TRY(ensure(c, c->pw_Lw, (size_t)P * P * sizeof(float2)));
+    ST_TRY(ensure(c, c->pw_B0w, (size_t)P * P * sizeof(float2)));
+  }
   ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
   if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
   if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
@@ -622,7 +638,33 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   const bool beam_full_grid = beam_fits(P) && !c->old_beam;
   const bool beam_big_grid_ok = !beam_fits(P) && beam_big_fits(P) && !c->old_beam;
   bool host_loop = true;
-  if (beam_full_grid && outer_fits(P) && !c->host_loop && !c->trace) {
+  // PWLS inputs (eq. preWLS): Cholesky of R, h = a^H R^-1 a, D = h^2 / C, the
+  // whitened data, bound D gamma and the MVDR-image threshold; the loop then
+  // solves for D sigma
+  const float* lam_scale = nullptr;
+  const float* op_gamma = gamma;
+  const float* op_eps = eps;
+  const float2* op_B0 = B0;
+  if (pwls) {
+    if (o->bound != CLSIMG_BOUND_MVDR) {  // the MVDR bound has factorised R already
+      HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
+                                  P_<int>(c->status), st));
+      ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
+      if (*c->h_status != 0) return CLSIMG_ENOTPD;
+    }
+    float* h = P_<float>(c->pw_h);
+    ST_TRY(beam_full(c, g, P, P_<const float2>(c->Rinv), BEAM_STORE, h, nullptr, 0.f, 0, 0, 1.f, st));
+    const double kd = o->kappa_d != 0.0 ? o->kappa_d / sqrt((double)(o->nsamples - P - 1)) : 0.0;
+    HIP_TRY(launch_pwls_setup(h, gamma, o->C, kd, Q, P_<float>(c->pw_rs), P_<float>(c->pw_g),
+                              P_<float>(c->pw_eps), P_<float>(c->pw_dinv), st));
+    HIP_TRY(launch_pwls_whiten(P_<const double2>(c->Li), B0, P, P_<float2>(c->pw_Lw), P_<float2>(c->pw_B0w), st));
+    if (sigma0) HIP_TRY(launch_pwls_scale(sigma, P_<const float>(c->pw_dinv), Q, true, st));  // D sigma0
+    lam_scale = P_<const float>(c->pw_dinv);
+    op_gamma = P_<const float>(c->pw_g);
+    op_eps = P_<const float>(c->pw_eps);
+    op_B0 = P_<const float2>(c->pw_B0w);
+  }
+  if (device_loop) {
     // Table I on the device: one workgroup per outer step, the full-grid
     // multiplier kernel between steps; the host only checks for the end
     OuterState* ost = P_<OuterState>(c->ostate);
@@ -632,10 +674,10 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
     op.Flist = Flist;
     op.Ulist = Ulist;
     op.sigma = sigma;
-    op.gamma = gamma;
-    op.eps = eps;
+    op.gamma = op_gamma;
+    op.eps = op_eps;
     op.state = state;
-    op.B0 = B0;
+    op.B0 = op_B0;
     op.Bb = Bb;
     op.E = E;
     op.keys = keys;
@@ -649,11 +691,13 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
     op.itnlim = o->itnlim;
     op.max_outer = max_outer;
     op.max_f = c->outer_max_f;
+    op.Lw = pwls ? P_<const float2>(c->pw_Lw) : nullptr;
+    op.rowscale = pwls ? P_<const float>(c->pw_rs) : nullptr;
     int nb = 8;
     for (;;) {
       for (int b = 0; b < nb; ++b) {
         HIP_TRY(launch_outer_step(op, st));
-        HIP_TRY(launch_beam_lambda(nullptr, E, P, op.tab, &ost->lam_skip, state, keys, st));
+        HIP_TRY(launch_beam_lambda(nullptr, E, P, op.tab, &ost->lam_skip, state, keys, lam_scale, st));
       }
       ST_TRY(read_back(c, c->h_outer, ost, sizeof(OuterState), st));
       if (c->h_outer->done) break;
@@ -674,6 +718,10 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
     flops += S.psi_flops;
     // a free set too large for one workgroup: continue on the host from here
     host_loop = S.fallback != 0;
+    if (pwls) {
+      if (host_loop) return CLSIMG_ENOTSUP;  // the host loop has no PWLS path
+      HIP_TRY(launch_pwls_scale(sigma, P_<const float>(c->pw_dinv), Q, false, st));  // sigma = D^-1 (D sigma)
+    }
   }
   for (; host_loop;) {
     if (need_solve) {
@@ -848,7 +896,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           if (c->beam_prep) HIP_TRY(launch_beam_prep(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_lambda(c->beam_prep ? P_<const float>(c->frag_b) : nullptr,
                                      c->beam_prep ? nullptr : E, P, tables_of(c, g, P), grad_stop, state,
-                                     keys, st));
+                                     keys, nullptr, st));
           HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
         } else {
           HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys,

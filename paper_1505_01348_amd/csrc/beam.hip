@@ -101,12 +101,14 @@ struct BeamStore {
 struct BeamLambda {
   const uint8_t* state;
   uint64_t* part;
+  const float* scale;  // optional positive per-pixel factor (PWLS: 1 / D_i)
   uint64_t best;
   __device__ void init() { best = ~0ull; }
   __device__ void operator()(int pix, float g, bool ok) {
     if (ok) {
       const uint8_t s = state[pix];
       if (s != 1) {  // not free
+        if (scale) g *= scale[pix];
         const float lam = (s == 0) ? g : -g;  // L : U
         const uint64_t key = ((uint64_t)ordered_bits(lam) << 32) | (uint32_t)pix;
         best = key < best ? key : best;
@@ -492,7 +494,7 @@ hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const
     case 0: return launch_big(frag, tab, skip, BeamMF{out, eps, eps_scale}, st);
     case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st);
     case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st);
-    default: return launch_big(frag, tab, skip, BeamLambda{state, part, 0}, st);
+    default: return launch_big(frag, tab, skip, BeamLambda{state, part, nullptr, 0}, st);
   }
 }
 
@@ -512,8 +514,8 @@ hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Ta
 }
 
 hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
-                              const uint8_t* state, uint64_t* part, hipStream_t st) {
-  return launch_beam(frag, U, P, tab, skip, BeamLambda{state, part, 0}, st);
+                              const uint8_t* state, uint64_t* part, const float* scale, hipStream_t st) {
+  return launch_beam(frag, U, P, tab, skip, BeamLambda{state, part, scale, 0}, st);
 }
 
 }  // namespace clsimg

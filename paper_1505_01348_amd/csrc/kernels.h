@@ -285,8 +285,9 @@ hipError_t launch_beam_mvdr(const float* frag, const float2* U, int P, const Tab
                             double kb_coef, hipStream_t st);
 hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Tables& tab, float* out,
                              float scale, hipStream_t st);
+// scale (may be null): per-pixel positive factor applied to g before the multiplier
 hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
-                              const uint8_t* state, uint64_t* part, hipStream_t st);
+                              const uint8_t* state, uint64_t* part, const float* scale, hipStream_t st);
 // GEMM-shaped full-grid beamformer for larger arrays (P <= 288)
 bool beam_big_fits(int P);
 size_t beam_big_frag_floats(int P);
@@ -377,9 +378,17 @@ struct OuterParams {
   double atol, btol, conlim;
   int itnlim, max_outer;
   int max_f;  // largest free set kept on the device (at most the LDS capacity)
+  // PWLS (eq. preWLS), both null for LS: steering rows are L^-1 a_i * rowscale_i,
+  // and the gradient matrix handed to the multiplier kernel is L^-H E L^-1
+  const float2* Lw;       // L^-1, P x P row-major (lower triangular)
+  const float* rowscale;  // 1 / sqrt(D_i)
 };
 
 bool outer_fits(int P);
+hipError_t launch_pwls_setup(const float* h, const float* gamma, double C, double kd_coef, int Q, float* rowscale,
+                             float* gamma_pw, float* eps_pw, float* dinv, hipStream_t st);
+hipError_t launch_pwls_whiten(const double2* Li, const float2* B0, int P, float2* Lw, float2* B0w, hipStream_t st);
+hipError_t launch_pwls_scale(float* x, const float* s, int n, bool divide, hipStream_t st);
 hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s);
 hipError_t launch_outer_step(const OuterParams& pr, hipStream_t s);
 hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int nbeta,

@@ -17,6 +17,13 @@
 // once.  When a free set outgrows the LDS, the outer step stops with
 // `fallback` set and the host continues with its own loop from the current
 // sigma and state.
+//
+// PWLS (eq. preWLS) runs the same step on the transformed problem: steering
+// rows L^-1 a_i / sqrt(D_i) (R = L L^H, D_i = h_i^2 / C), data L^-1 B0 L^-H,
+// bound D gamma; the gradient matrix E of the whitened problem is handed to
+// the multiplier kernel as L^-H E L^-1 with a per-pixel factor 1 / D_i.
+#include <algorithm>
+
 #include "lsqr_cu.h"
 
 namespace clsimg {
@@ -90,6 +97,46 @@ __device__ inline void cu_gen_rows(const Tables& tab, const int* list, int n, fl
   }
   if (w)
     for (int k = threadIdx.x; k < n16; k += kCuThreads) w[k] = k < n ? wsrc[list[k]] : 0.f;
+}
+
+// PWLS rows: x_k <- rowscale[list[k]] * L^-1 x_k for the n LDS rows, in
+// chunks of kWhChunk rows through the LDS scratch tmp (kWhChunk * 2Pp floats);
+// Lw (LDS) holds L^-1 row-major as complex pairs.  Entries of padding antennas
+// stay zero.
+constexpr int kWhChunk = 16;
+template <int MT>
+__device__ inline void cu_whiten_rows(float* xr, const int* list, int n, const float2* Lw, float* tmp,
+                                      const float* rowscale, int P) {
+  constexpr int Pp = 8 * MT;
+  constexpr int RS = cu_row_stride(Pp);
+  for (int k0 = 0; k0 < n; k0 += kWhChunk) {
+    const int nc = min(kWhChunk, n - k0);
+    for (int e = threadIdx.x; e < nc * P; e += kCuThreads) {
+      const int kk = e / P, p = e - kk * P;
+      const float* row = xr + (k0 + kk) * RS;
+      float re = 0.f, im = 0.f;
+      for (int r = 0; r <= p; ++r) {  // L^-1 is lower triangular
+        const float2 l = Lw[p * P + r];
+        const float ar = row[2 * r], ai = row[2 * r + 1];
+        re += l.x * ar - l.y * ai;
+        im += l.x * ai + l.y * ar;
+      }
+      const float sc = rowscale[list[k0 + kk]];
+      tmp[kk * 2 * Pp + 2 * p] = sc * re;
+      tmp[kk * 2 * Pp + 2 * p + 1] = sc * im;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * 2 * P; e += kCuThreads) {
+      const int kk = e / (2 * P), c = e - kk * 2 * P;
+      xr[(k0 + kk) * RS + c] = tmp[kk * 2 * Pp + c];
+    }
+    __syncthreads();
+  }
+}
+
+// L^-1 into LDS (P x P complex, row-major)
+__device__ inline void cu_load_lw(const float2* __restrict__ Lw, int P, float2* dst) {
+  for (int e = threadIdx.x; e < P * P; e += kCuThreads) dst[e] = Lw[e];
 }
 
 // out = sK K + sB herm(B) over this wave's owned elements, K from a forward tile
@@ -213,7 +260,8 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
     if (S.outer >= pr.max_outer) {
       S.status = kStatusMaxOuter;
       S.done = 1;
-    } else if (S.nF > kOuterMaxF || S.nF > pr.max_f || cu_lds_floats(MT, S.nF) > kCuLds) {
+    } else if (S.nF > kOuterMaxF || S.nF > pr.max_f ||
+               cu_lds_floats(MT, S.nF) + (pr.Lw ? kWhChunk * 2 * Pp : 0) > kCuLds) {
       S.fallback = 1;
       S.done = 1;
     }
@@ -245,9 +293,13 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
   if (S.bb_dirty) {
     if (S.nU > 0) {
       const int* U = ulist_cur(pr, S);
-      constexpr int CH = ((kCuLds - 64) / (RS + 1)) & ~15;  // rows per chunk
+      // rows per chunk, leaving room for L^-1 and the whitening scratch
+      constexpr int CH = ((kCuLds - 64 - 2 * Pp * Pp - kWhChunk * 2 * Pp) / (RS + 1)) & ~15;
       float* xr = lds;
       float* wg = lds + CH * RS;
+      float2* lw = reinterpret_cast<float2*>(wg + CH);
+      float* wtmp = reinterpret_cast<float*>(lw + Pp * Pp);
+      if (pr.Lw) cu_load_lw(pr.Lw, P, lw);
       v4f acc[TPW];
 #pragma unroll
       for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -255,6 +307,7 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
         const int nc = min(CH, S.nU - c0), nc16 = (nc + 15) & ~15;
         cu_gen_rows<MT>(pr.tab, U + c0, nc, xr, pr.gamma, wg);
         __syncthreads();
+        if (pr.Lw) cu_whiten_rows<MT>(xr, U + c0, nc, lw, wtmp, pr.rowscale, P);
 #pragma unroll
         for (int i = 0; i < TPW; ++i)
           if (w + kCuWaves * i < NTP) acc[i] = acc[i] + cu_forward_tile(xr, wg, 1.f, nc16, RS, tmt[i], tnt[i]);
@@ -274,6 +327,12 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
 
   // ---- LSQR on the free set ----
   cu_gen_rows<MT>(pr.tab, sF, n, lds, nullptr, nullptr);
+  if (pr.Lw) {  // PWLS: L^-1 in the (not yet used) fragment area, scratch after the vectors
+    float2* lw = reinterpret_cast<float2*>(lds + n16 * RS);
+    cu_load_lw(pr.Lw, P, lw);
+    __syncthreads();
+    cu_whiten_rows<MT>(lds, sF, n, lw, lds + cu_lds_floats(MT, n), pr.rowscale, P);
+  }
   __syncthreads();
   const int itnlim = pr.itnlim < 0 ? 4 * n + 100 : pr.itnlim;
   const LsqrState L = cu_lsqr<MT>(lds, n, P, bsub, pr.atol, pr.btol, pr.conlim, itnlim);
@@ -300,6 +359,39 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
         cu_store_c(acc, tmt[i], tnt[i], P, 1.f, -1.f, bsub, pr.E);
       }
     __syncthreads();
+    if (pr.Lw) {
+      // PWLS: the multiplier kernel beamforms L^-H E L^-1 (and scales by 1/D)
+      float2* Ed = reinterpret_cast<float2*>(lds);
+      float2* lw = Ed + P * P;
+      float2* T = lw + P * P;
+      for (int e = tid; e < P * P; e += kCuThreads) {
+        Ed[e] = pr.E[e];
+        lw[e] = pr.Lw[e];
+      }
+      __syncthreads();
+      for (int e = tid; e < P * P; e += kCuThreads) {  // T = E L^-1
+        const int p = e / P, q = e - p * P;
+        float re = 0.f, im = 0.f;
+        for (int r = q; r < P; ++r) {
+          const float2 a = Ed[p * P + r], l = lw[r * P + q];
+          re += a.x * l.x - a.y * l.y;
+          im += a.x * l.y + a.y * l.x;
+        }
+        T[e] = make_float2(re, im);
+      }
+      __syncthreads();
+      for (int e = tid; e < P * P; e += kCuThreads) {  // E' = L^-H T
+        const int p = e / P, q = e - p * P;
+        float re = 0.f, im = 0.f;
+        for (int r = p; r < P; ++r) {
+          const float2 l = lw[r * P + p], t = T[r * P + q];  // conj(l) * t
+          re += l.x * t.x + l.y * t.y;
+          im += l.x * t.y - l.y * t.x;
+        }
+        pr.E[e] = make_float2(re, im);
+      }
+      __syncthreads();
+    }
     if (tid == 0) {
       if (n > 0) S.margin_z = fmin(S.margin_z, (double)mz);
       S.last_feasible = 1;
@@ -411,6 +503,79 @@ __global__ void outer_init_kernel(OuterState* st, const SolveDecision* dec) {
   S.last_ib = -1;
   S.last_imin = -1;
   *st = S;
+}
+
+// ---- PWLS set-up (eq. preWLS, eq. D at K = 1) ----
+// D_i = h_i^2 / C; rowscale = 1 / sqrt(D); bound D gamma; threshold
+// kd_coef / h_i (kd_coef = kappa_d / sqrt(N - P - 1), App. A); dinv = 1 / D.
+__global__ void pwls_setup_kernel(const float* __restrict__ h, const float* __restrict__ gamma, double C,
+                                  double kd_coef, int Q, float* __restrict__ rowscale, float* __restrict__ gamma_pw,
+                                  float* __restrict__ eps_pw, float* __restrict__ dinv) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
+    const double hh = (double)h[i];
+    const double D = hh * hh / C;
+    rowscale[i] = (float)(sqrt(C) / hh);
+    gamma_pw[i] = (float)(D * (double)gamma[i]);
+    eps_pw[i] = (float)(kd_coef / hh);
+    dinv[i] = (float)(1.0 / D);
+  }
+}
+
+// L^-1 to FP32, and the whitened data L^-1 herm(B0) L^-H in FP64 (one workgroup)
+__global__ __launch_bounds__(1024) void pwls_whiten_kernel(const double2* __restrict__ Li,
+                                                           const float2* __restrict__ B0, int P,
+                                                           float2* __restrict__ Lw, float2* __restrict__ B0w) {
+  __shared__ double2 T[48 * 48];
+  for (int e = threadIdx.x; e < P * P; e += blockDim.x) Lw[e] = make_float2((float)Li[e].x, (float)Li[e].y);
+  for (int e = threadIdx.x; e < P * P; e += blockDim.x) {  // T = L^-1 herm(B0)
+    const int p = e / P, q = e - p * P;
+    double re = 0.0, im = 0.0;
+    for (int r = 0; r <= p; ++r) {
+      const double2 l = Li[p * P + r];
+      const float2 x = B0[r * P + q], y = B0[q * P + r];
+      const double br = 0.5 * ((double)x.x + y.x), bi = 0.5 * ((double)x.y - y.y);
+      re += l.x * br - l.y * bi;
+      im += l.x * bi + l.y * br;
+    }
+    T[e] = make_double2(re, im);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < P * P; e += blockDim.x) {  // B0w = T L^-H
+    const int p = e / P, q = e - p * P;
+    double re = 0.0, im = 0.0;
+    for (int r = 0; r <= q; ++r) {
+      const double2 t = T[p * P + r], l = Li[q * P + r];  // t * conj(l)
+      re += t.x * l.x + t.y * l.y;
+      im += t.y * l.x - t.x * l.y;
+    }
+    B0w[e] = make_float2((float)re, (float)im);
+  }
+}
+
+// x[i] *= s[i] (mul) or x[i] /= s[i]
+__global__ void pwls_scale_kernel(float* __restrict__ x, const float* __restrict__ s, int n, int divide) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    x[i] = divide ? x[i] / s[i] : x[i] * s[i];
+}
+
+hipError_t launch_pwls_setup(const float* h, const float* gamma, double C, double kd_coef, int Q, float* rowscale,
+                             float* gamma_pw, float* eps_pw, float* dinv, hipStream_t st) {
+  const int g = std::min((Q + 255) / 256, 2048);
+  hipLaunchKernelGGL(pwls_setup_kernel, dim3(g), dim3(256), 0, st, h, gamma, C, kd_coef, Q, rowscale, gamma_pw,
+                     eps_pw, dinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_pwls_whiten(const double2* Li, const float2* B0, int P, float2* Lw, float2* B0w, hipStream_t st) {
+  if (P > 48) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pwls_whiten_kernel, dim3(1), dim3(1024), 0, st, Li, B0, P, Lw, B0w);
+  return hipGetLastError();
+}
+
+hipError_t launch_pwls_scale(float* x, const float* s, int n, bool divide, hipStream_t st) {
+  const int g = std::min((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(pwls_scale_kernel, dim3(g), dim3(256), 0, st, x, s, n, divide ? 1 : 0);
+  return hipGetLastError();
 }
 
 bool outer_fits(int P) { return pad_p(P) / 8 <= 6; }

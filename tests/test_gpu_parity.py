@@ -319,3 +319,46 @@ def test_solve_tight_bound_uses_upper_set(gpu_lib, scenes, name, host, monkeypat
     np.testing.assert_array_equal(state, ref.state)
     _assert_close(sigma, ref.sigma, what=f"solve sigma {name} C={C}")
     assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_solve_pwls_matches_oracle(gpu_lib, ctx, scenes, name):
+    # preconditioned weighted LS (eq. preWLS) with the MVDR bound and the
+    # MVDR-image threshold, against the oracle's PWLS solve
+    sc = scenes[name]
+    print(f"case PWLS solve {name}", flush=True)
+    R = sc.R_hat32_c128
+    A = oracle.steering(sc.pos, sc.lam, sc.grid)
+    gamma = oracle.upper_bound(A, R)
+    _, h = oracle.pwls_scaling(A, R)
+    eps = oracle.pwls_threshold(h, 6.0, sc.N, sc.P)
+    nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
+    ref = oracle.solve_pwls(A, R, R - np.diag(nd), gamma, eps, atol=1e-8, btol=1e-8)
+    opts = gpu_lib.default_options()
+    opts.nsamples = sc.N
+    opts.atol = opts.btol = 1e-7
+    opts.cost = gpu_lib.COST_PWLS
+    sigma, state, mf, gam, stats = ctx.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts,
+                                             noise_diag=_dev(sc.noise_diag, torch.float32))
+    print("gpu stats", stats, "oracle outer", ref.outer_iters, "adds", ref.adds, "drops", ref.drops, flush=True)
+    state, sigma = state.cpu().numpy(), sigma.cpu().numpy()
+    print("state mismatches", int(np.sum(state != ref.state)), flush=True)
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what=f"PWLS sigma {name}")
+    _assert_close(gam.cpu().numpy(), gamma, what=f"PWLS gamma {name}")
+    assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
+
+
+def test_pwls_without_the_device_loop_is_not_supported(gpu_lib, scenes, monkeypatch):
+    monkeypatch.setenv("CLSIMG_HOST_LOOP", "1")
+    sc = scenes["c0"]
+    ctx2 = gpu_lib.Context(0)
+    try:
+        opts = gpu_lib.default_options()
+        opts.nsamples = sc.N
+        opts.cost = gpu_lib.COST_PWLS
+        with pytest.raises(gpu_lib.ClsimgError) as ei:
+            ctx2.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts)
+        assert ei.value.status == gpu_lib.ENOTSUP
+    finally:
+        ctx2.close()

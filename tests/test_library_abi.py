@@ -36,7 +36,9 @@ def test_default_options_and_strerror():
     o = clsimg.default_options()
     assert o.bound == clsimg.BOUND_MVDR and o.C == 1.0 and o.kappa_b == 0.0 and o.kappa_d == 6.0
     assert o.itnlim == -1 and o.max_outer == -1 and o.precision == clsimg.FP32
+    assert o.cost == clsimg.COST_LS
     assert clsimg.strerror(clsimg.ENOTPD).startswith("covariance")
+    assert "not available" in clsimg.strerror(clsimg.ENOTSUP)
     assert clsimg.strerror(12345) == "unknown status"
 
 

@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-7, help="LSQR atol = btol")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cost", default="ls", choices=["ls", "pwls"],
+                    help="cost function: LS (eq. CLS) or preconditioned weighted LS (eq. preWLS)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 288-antenna full-grid beamformer timing")
     ap.add_argument("--kernel-only", action="store_true",
@@ -83,7 +85,7 @@ def measured_traffic():
     return None
 
 
-def cpu_baseline(sc, tol_oracle, budget_s=25.0):
+def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls"):
     """Time full oracle solves of the same workload on the host (bounded sample)."""
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -97,8 +99,13 @@ def cpu_baseline(sc, tol_oracle, budget_s=25.0):
         A = oracle.steering(sc.pos, sc.lam, sc.grid)
         mf = oracle.mf_image(A, R)
         gamma = oracle.upper_bound(A, R)
-        eps = oracle.detection_threshold(mf, 6.0, sc.N)
-        res = oracle.solve(A, R - np.diag(nd), gamma, eps, atol=tol_oracle, btol=tol_oracle)
+        if cost == "pwls":
+            _, h = oracle.pwls_scaling(A, R)
+            eps = oracle.pwls_threshold(h, 6.0, sc.N, sc.P)
+            res = oracle.solve_pwls(A, R, R - np.diag(nd), gamma, eps, atol=tol_oracle, btol=tol_oracle)
+        else:
+            eps = oracle.detection_threshold(mf, 6.0, sc.N)
+            res = oracle.solve(A, R - np.diag(nd), gamma, eps, atol=tol_oracle, btol=tol_oracle)
         t_total += time.perf_counter() - t0
         runs += 1
         log(f"cpu baseline: oracle solve {runs} done, {t_total:.1f} s")
@@ -149,6 +156,7 @@ def main():
     opts = clsimg.default_options()
     opts.nsamples = sc.N
     opts.atol = opts.btol = args.tol
+    opts.cost = clsimg.COST_PWLS if args.cost == "pwls" else clsimg.COST_LS
     R = torch.as_tensor(sc.R_hat32).cuda()
     nd = torch.as_tensor(sc.noise_diag.astype(np.float32)).cuda()
     Q = sc.Q
@@ -260,7 +268,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "P": P, "Q": Q,
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "cost": args.cost, "P": P, "Q": Q,
                    "nsamples": sc.N, "n_sources": int(len(sc.src_pix)), "lsqr_tol": args.tol,
                    "contractions": "fp32 MFMA 16x16x4, fp64 Cholesky and LSQR scalars"},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
@@ -279,7 +287,7 @@ def main():
     if big is not None:
         result["roofline_full_size"] = big
     if not args.no_cpu:
-        base, ref = cpu_baseline(sc, tol_oracle=1e-8)
+        base, ref = cpu_baseline(sc, tol_oracle=1e-8, cost=args.cost)
         result["cpu_baseline"] = base
         s = sigma.cpu().numpy().astype(np.float64)
         st = state.cpu().numpy()

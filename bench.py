@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-7, help="LSQR atol = btol")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--bound", default="mvdr", choices=["mvdr", "mf", "none"],
+                    help="upper bound of the box (Sec. II-D)")
+    ap.add_argument("--kappa-b", type=float, default=0.0, help="bound inflation in std units (App. A)")
     ap.add_argument("--cost", default="ls", choices=["ls", "pwls"],
                     help="cost function: LS (eq. CLS) or preconditioned weighted LS (eq. preWLS)")
     ap.add_argument("--no-large", action="store_true",
@@ -85,7 +88,7 @@ def measured_traffic():
     return None
 
 
-def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls"):
+def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls", bound="mvdr", kappa_b=0.0):
     """Time full oracle solves of the same workload on the host (bounded sample)."""
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -98,7 +101,7 @@ def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls"):
         t0 = time.perf_counter()
         A = oracle.steering(sc.pos, sc.lam, sc.grid)
         mf = oracle.mf_image(A, R)
-        gamma = oracle.upper_bound(A, R)
+        gamma = oracle.upper_bound(A, R, kind=bound, kappa_b=kappa_b, nsamples=sc.N)
         if cost == "pwls":
             _, h = oracle.pwls_scaling(A, R)
             eps = oracle.pwls_threshold(h, 6.0, sc.N, sc.P)
@@ -157,6 +160,8 @@ def main():
     opts.nsamples = sc.N
     opts.atol = opts.btol = args.tol
     opts.cost = clsimg.COST_PWLS if args.cost == "pwls" else clsimg.COST_LS
+    opts.bound = {"mvdr": clsimg.BOUND_MVDR, "mf": clsimg.BOUND_MF, "none": clsimg.BOUND_NONE}[args.bound]
+    opts.kappa_b = args.kappa_b
     R = torch.as_tensor(sc.R_hat32).cuda()
     nd = torch.as_tensor(sc.noise_diag.astype(np.float32)).cuda()
     Q = sc.Q
@@ -268,7 +273,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "cost": args.cost, "P": P, "Q": Q,
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "cost": args.cost, "bound": args.bound,
+                   "kappa_b": args.kappa_b, "P": P, "Q": Q,
                    "nsamples": sc.N, "n_sources": int(len(sc.src_pix)), "lsqr_tol": args.tol,
                    "contractions": "fp32 MFMA 16x16x4, fp64 Cholesky and LSQR scalars"},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
@@ -287,7 +293,7 @@ def main():
     if big is not None:
         result["roofline_full_size"] = big
     if not args.no_cpu:
-        base, ref = cpu_baseline(sc, tol_oracle=1e-8, cost=args.cost)
+        base, ref = cpu_baseline(sc, tol_oracle=1e-8, cost=args.cost, bound=args.bound, kappa_b=args.kappa_b)
         result["cpu_baseline"] = base
         s = sigma.cpu().numpy().astype(np.float64)
         st = state.cpu().numpy()

@@ -362,3 +362,20 @@ def test_pwls_without_the_device_loop_is_not_supported(gpu_lib, scenes, monkeypa
         assert ei.value.status == gpu_lib.ENOTSUP
     finally:
         ctx2.close()
+
+
+def test_noise_only_solves_raise_no_false_alarm(gpu_lib, ctx, scenes):
+    # Sec. III-C: with the 6-sigma threshold a noise-only covariance (noise
+    # known and removed from b) must not release any pixel
+    sc = scenes["c0"]
+    rng = np.random.default_rng(17)
+    opts = gpu_lib.default_options()
+    opts.nsamples = sc.N
+    opts.atol = opts.btol = 1e-7
+    nd = _dev(np.ones(sc.P, np.float32), torch.float32)
+    for t in range(20):
+        Y = np.sqrt(0.5) * (rng.standard_normal((sc.P, sc.N)) + 1j * rng.standard_normal((sc.P, sc.N)))
+        Rh = (Y @ Y.conj().T / sc.N).astype(np.complex64)
+        sigma, state, _, _, stats = ctx.solve(_dev(Rh, torch.complex64), _geo(gpu_lib, sc), opts, noise_diag=nd)
+        assert stats["adds"] == 0, (t, stats)
+        assert int((state.cpu().numpy() == 1).sum()) == 0

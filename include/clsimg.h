@@ -181,6 +181,35 @@ int clsimg_solve(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array
                  float* mf, float* gamma, clsimg_stats* stats, void* stream);
 
 /* Static description of a status code. */
+/* One request of a batched solve. */
+typedef struct {
+  const clsimg_c32* R;      /* DEVICE, P x P sample covariance of this request       */
+  clsimg_array array;       /* antenna positions and wavelength (P equal in a batch) */
+  clsimg_grid grid;         /* pixel grid of this request                           */
+  const float* noise_diag;  /* DEVICE, P, or NULL                                    */
+  float* sigma;             /* DEVICE, Q: image (output)                             */
+  uint8_t* state;           /* DEVICE, Q: CLSIMG_STATE_* (output)                    */
+  float* mf;                /* DEVICE, Q, or NULL: MF dirty image (output)           */
+  float* gamma;             /* DEVICE, Q, or NULL: upper bound (output)              */
+  clsimg_stats stats;       /* HOST: statistics of this request (output); status is  */
+                            /* the request's own code.  rel_residual and objective   */
+                            /* are taken at the last feasible step (PWLS: weighted)  */
+} clsimg_request;
+
+/* Batched solve (Sec. III, Table I, with LSQR of Sec. IV-A) of n independent
+ * imaging problems -- frequency channels, time slices, observations -- with
+ * the same antenna count P <= 48 and the same options.  Every outer step of
+ * all requests runs in one kernel launch (one workgroup per request) and the
+ * Lagrange multipliers of all requests in another, so the requests share the
+ * GPU instead of queueing; each request's result is identical to what
+ * clsimg_solve returns for it alone.  Each request may have its own array,
+ * wavelength and grid.  Returns CLSIMG_OK when every request ended with
+ * CLSIMG_OK, its first negative code if a request failed, CLSIMG_ENOTSUP if a
+ * free set outgrew one workgroup (no host fallback in a batch), else the
+ * largest warning code; per-request codes are in reqs[i].stats.status.
+ * `reqs` is host memory (n entries); n >= 1. */
+int clsimg_solve_batch(clsimg_ctx* ctx, int32_t n, clsimg_request* reqs, const clsimg_opts* opts, void* stream);
+
 const char* clsimg_strerror(int status);
 
 #ifdef __cplusplus

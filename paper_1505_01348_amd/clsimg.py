@@ -29,7 +29,7 @@ MAX_P = 288
 
 EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
             "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
-            "clsimg_strerror")
+            "clsimg_solve_batch", "clsimg_strerror")
 
 
 class CArray(C.Structure):
@@ -57,6 +57,12 @@ class CStats(C.Structure):
                 ("psi_flops", C.c_double)]
 
 
+class CRequest(C.Structure):
+    _fields_ = [("R", C.c_void_p), ("array", CArray), ("grid", CGrid), ("noise_diag", C.c_void_p),
+                ("sigma", C.c_void_p), ("state", C.c_void_p), ("mf", C.c_void_p), ("gamma", C.c_void_p),
+                ("stats", CStats)]
+
+
 class ClsimgError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -78,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                       vp, vp]
     lib.clsimg_forward.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp, i32, vp, vp]
     lib.clsimg_adjoint.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp, i32, vp, vp]
+    lib.clsimg_solve_batch.argtypes = [vp, i32, C.POINTER(CRequest), C.POINTER(COpts), vp]
     lib.clsimg_solve.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, C.POINTER(COpts),
                                  vp, vp, vp, vp, vp, vp, C.POINTER(CStats), vp]
     lib.clsimg_strerror.argtypes = [C.c_int]
@@ -282,6 +289,46 @@ class Context:
         self._check(st, "clsimg_solve", allow_warn=True)
         out = {f: getattr(stats, f) for f, _ in CStats._fields_}
         return sigma, state, mf, gamma, out
+
+
+    def solve_batch(self, requests, opts: Options):
+        """Batched solve of independent problems with the same P (each a dict with
+        R, geo and optional noise_diag / sigma / state / mf / gamma tensors).
+        Returns (overall status, list of (sigma, state, mf, gamma, stats dict))."""
+        dev = self.device
+        n = len(requests)
+        arr = (CRequest * n)()
+        keep, outs = [], []
+        for i, rq in enumerate(requests):
+            R, geo = rq["R"], rq["geo"]
+            _need(R, torch.complex64, geo.P * geo.P, "R", dev)
+            Q = geo.Q
+            nd = rq.get("noise_diag")
+            if nd is not None:
+                _need(nd, torch.float32, geo.P, "noise_diag", dev)
+            mk = lambda t, dt: torch.empty(Q, dtype=dt, device=R.device) if t is None else t  # noqa: E731
+            sigma, state = mk(rq.get("sigma"), torch.float32), mk(rq.get("state"), torch.uint8)
+            mf, gamma = mk(rq.get("mf"), torch.float32), mk(rq.get("gamma"), torch.float32)
+            for t, dt, name in ((sigma, torch.float32, "sigma"), (state, torch.uint8, "state"),
+                                (mf, torch.float32, "mf"), (gamma, torch.float32, "gamma")):
+                _need(t, dt, Q, name, dev)
+            arr[i].R = R.data_ptr()
+            arr[i].array = geo.c_array
+            arr[i].grid = geo.c_grid
+            arr[i].noise_diag = None if nd is None else nd.data_ptr()
+            arr[i].sigma, arr[i].state = sigma.data_ptr(), state.data_ptr()
+            arr[i].mf, arr[i].gamma = mf.data_ptr(), gamma.data_ptr()
+            keep.append(geo)
+            outs.append((sigma, state, mf, gamma))
+        co = opts.to_c()
+        st = self._lib.clsimg_solve_batch(self._h, n, arr, C.byref(co), _stream())
+        if st < 0 and st != ENOTSUP:
+            self._check(st, "clsimg_solve_batch")
+        res = []
+        for i in range(n):
+            stats = {f: getattr(arr[i].stats, f) for f, _ in CStats._fields_}
+            res.append(outs[i] + (stats,))
+        return st, res
 
 
 def epsilon_scale(kappa_d: float, nsamples: int) -> float:

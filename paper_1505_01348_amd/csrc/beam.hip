@@ -69,7 +69,7 @@ struct BeamMF {
       if (eps) eps[pix] = g * eps_scale;
     }
   }
-  __device__ void finish() {}
+  __device__ void finish(int) {}
 };
 
 struct BeamMVDR {
@@ -82,7 +82,7 @@ struct BeamMVDR {
       gamma[pix] = (float)(C / h + kb_coef / h);
     }
   }
-  __device__ void finish() {}
+  __device__ void finish(int) {}
 };
 
 struct BeamStore {
@@ -92,7 +92,7 @@ struct BeamStore {
   __device__ void operator()(int pix, float g, bool ok) {
     if (ok) out[pix] = g * scale;
   }
-  __device__ void finish() {}
+  __device__ void finish(int) {}
 };
 
 // Lagrange multipliers of the active pixels (eqs. etaL, etaU): lambda = g on
@@ -115,10 +115,10 @@ struct BeamLambda {
       }
     }
   }
-  __device__ void finish() {
+  __device__ void finish(int blk) {
     __shared__ uint64_t sh[kBeamWaves];
     const uint64_t m = block_min_u64(best, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = m;
+    if (threadIdx.x == 0) part[blk] = m;
   }
 };
 
@@ -170,19 +170,16 @@ __device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, 
   for (int f = 0; f < NFR; ++f) fa[f] = sfr[f * 64 + lane];
 }
 
-// (at most two waves per SIMD: the fragments, the tile's operands and the
-// accumulators all stay in registers)
 template <int MT, class Epi>
-__global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu(1, 2))) void beam_kernel(const float* __restrict__ frag,
-                                                               const float2* __restrict__ U, int P,
-                                                               Tables tab, const int* skip, Epi epi) {
+__device__ __forceinline__ void beam_body(const float* __restrict__ frag, const float2* __restrict__ U, int P,
+                                          const Tables& tab, const int* skip, Epi& epi, int blk, int nblk) {
   constexpr int KS = 4 * MT;             // 4-row chunks of the embedding
   constexpr int NFR = 2 * MT * (MT + 1);  // fragments of the lower block triangle
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
   const int Q = tab.Q, nl = tab.nl, nm = tab.nm;
   const int ntiles = (Q + 15) >> 4;
-  const int nwav = gridDim.x * kBeamWaves;
+  const int nwav = nblk * kBeamWaves;
   // table entries of antennas 4 j + q for this lane's pixel of a tile; the
   // loads of the next tile are issued before the current one is multiplied
   float2 te[KS / 2], tm[KS / 2];
@@ -197,7 +194,7 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
       tm[j] = em[(size_t)4 * j * nm];
     }
   };
-  int tile = blockIdx.x * kBeamWaves + (threadIdx.x >> 6);
+  int tile = blk * kBeamWaves + (threadIdx.x >> 6);
   if (tile < ntiles) load_tables(tile);
   float fa[NFR];
   if (U) {
@@ -236,7 +233,25 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
     g += __shfl_xor(g, 32, 64);
     epi(pix, g, pix < Q && q == 0);
   }
-  epi.finish();
+  epi.finish(blk);
+}
+
+// (at most two waves per SIMD: the fragments, the tile's operands and the
+// accumulators all stay in registers)
+template <int MT, class Epi>
+__global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu(1, 2))) void beam_kernel(
+    const float* __restrict__ frag, const float2* __restrict__ U, int P, Tables tab, const int* skip, Epi epi) {
+  beam_body<MT>(frag, U, P, tab, skip, epi, blockIdx.x, gridDim.x);
+}
+
+// Multipliers of a batch of requests in one launch: bpr blocks per request.
+template <int MT>
+__global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu(1, 2))) void beam_lambda_batch_kernel(
+    const BeamLamItem* __restrict__ items, int bpr) {
+  const int r = blockIdx.x / bpr, lb = blockIdx.x - r * bpr;
+  const BeamLamItem it = items[r];
+  BeamLambda epi{it.state, it.part, it.scale, 0};
+  beam_body<MT>(nullptr, it.U, it.P, it.tab, it.skip, epi, lb, bpr);
 }
 
 // ---------------------------------------------------------------------------
@@ -411,7 +426,7 @@ __global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__
     }
     __syncthreads();
   }
-  epi.finish();
+  epi.finish(blockIdx.x);
 }
 
 bool beam_fits(int P) { return pad_p(P) / 8 <= kBeamMaxMT; }
@@ -511,6 +526,20 @@ hipError_t launch_beam_mvdr(const float* frag, const float2* U, int P, const Tab
 hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Tables& tab, float* out,
                              float scale, hipStream_t st) {
   return launch_beam(frag, U, P, tab, nullptr, BeamStore{out, scale}, st);
+}
+
+hipError_t launch_beam_lambda_batch(const BeamLamItem* items, int nreq, int bpr, int P, hipStream_t st) {
+  const dim3 g(nreq * bpr), b(64 * kBeamWaves);
+  switch (pad_p(P) / 8) {
+    case 1: hipLaunchKernelGGL(beam_lambda_batch_kernel<1>, g, b, 0, st, items, bpr); break;
+    case 2: hipLaunchKernelGGL(beam_lambda_batch_kernel<2>, g, b, 0, st, items, bpr); break;
+    case 3: hipLaunchKernelGGL(beam_lambda_batch_kernel<3>, g, b, 0, st, items, bpr); break;
+    case 4: hipLaunchKernelGGL(beam_lambda_batch_kernel<4>, g, b, 0, st, items, bpr); break;
+    case 5: hipLaunchKernelGGL(beam_lambda_batch_kernel<5>, g, b, 0, st, items, bpr); break;
+    case 6: hipLaunchKernelGGL(beam_lambda_batch_kernel<6>, g, b, 0, st, items, bpr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,

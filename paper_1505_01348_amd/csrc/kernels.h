@@ -288,6 +288,18 @@ hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Ta
 // scale (may be null): per-pixel positive factor applied to g before the multiplier
 hipError_t launch_beam_lambda(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
                               const uint8_t* state, uint64_t* part, const float* scale, hipStream_t st);
+// one request of a batched multiplier launch
+struct BeamLamItem {
+  const float2* U;  // gradient matrix E (P x P)
+  Tables tab;
+  const int* skip;
+  const uint8_t* state;
+  uint64_t* part;      // bpr argmin keys
+  const float* scale;  // optional per-pixel factor
+  int P;
+};
+hipError_t launch_beam_lambda_batch(const BeamLamItem* items, int nreq, int bpr, int P, hipStream_t st);
+
 // GEMM-shaped full-grid beamformer for larger arrays (P <= 288)
 bool beam_big_fits(int P);
 size_t beam_big_frag_floats(int P);
@@ -358,6 +370,8 @@ struct OuterState {
   int last_itn, last_istop, last_feasible, last_ib, last_ib_to, last_imin;
   float last_mu, last_lam, last_eps;
   double margin_lambda, margin_z, psi_flops;
+  double b0n2;  // ||B0||^2 (data of the problem solved: whitened for PWLS)
+  double res2;  // ||Psi sigma - b||^2 at the last feasible step
 };
 
 struct OuterParams {
@@ -391,6 +405,8 @@ hipError_t launch_pwls_whiten(const double2* Li, const float2* B0, int P, float2
 hipError_t launch_pwls_scale(float* x, const float* s, int n, bool divide, hipStream_t st);
 hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s);
 hipError_t launch_outer_step(const OuterParams& pr, hipStream_t s);
+// prs: device array of nreq parameter sets with the same P
+hipError_t launch_outer_step_batch(const OuterParams* prs, int nreq, int P, hipStream_t s);
 hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int nbeta,
                                     const double* alpha_part, int nalpha, float* v, float* w,
                                     float* x, int n, double atol, double btol, double conlim,

@@ -139,20 +139,25 @@ __device__ inline void cu_load_lw(const float2* __restrict__ Lw, int P, float2* 
   for (int e = threadIdx.x; e < P * P; e += kCuThreads) dst[e] = Lw[e];
 }
 
-// out = sK K + sB herm(B) over this wave's owned elements, K from a forward tile
-__device__ inline void cu_store_c(v4f acc, int mt, int nt, int P, float sK, float sB,
-                                  const float2* __restrict__ B, float2* out) {
+// out = sK K + sB herm(B) over this wave's owned elements, K from a forward
+// tile; returns the sum of |out|^2 over them
+__device__ inline double cu_store_c(v4f acc, int mt, int nt, int P, float sK, float sB,
+                                    const float2* __restrict__ B, float2* out) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
   const OsSlots sl = os_slots(mt, nt, c16, q, P, true);
   float2 K[4];
   os_assemble(acc, sl, K);
+  double nrm = 0.0;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     if (!sl.live[s] || sl.pa[s] >= P || sl.pb[s] >= P) continue;
     const float2 x = B[sl.pa[s] * P + sl.pb[s]], y = B[sl.pb[s] * P + sl.pa[s]];
-    out[sl.pa[s] * P + sl.pb[s]] =
+    const float2 o =
         make_float2(sK * K[s].x + sB * (0.5f * (x.x + y.x)), sK * K[s].y + sB * (0.5f * (x.y - y.y)));
+    out[sl.pa[s] * P + sl.pb[s]] = o;
+    nrm += (double)o.x * o.x + (double)o.y * o.y;
   }
+  return nrm;
 }
 
 __device__ inline const int* ulist_cur(const OuterParams& pr, const OuterState& S) {
@@ -160,7 +165,7 @@ __device__ inline const int* ulist_cur(const OuterParams& pr, const OuterState& 
 }
 
 template <int MT>
-__global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) {
+__device__ void outer_step_body(const OuterParams& pr) {
   constexpr int Pp = 8 * MT;
   constexpr int RS = cu_row_stride(Pp);
   constexpr int NTP = MT * (MT + 1) / 2;
@@ -171,6 +176,7 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
   __shared__ int shi[kCuWaves];
   __shared__ float shf[kCuWaves];
   __shared__ uint64_t shk[kCuWaves];
+  __shared__ double shd[1][kCuWaves];
   __shared__ int s_add, s_from_u;
   const int tid = threadIdx.x, w = tid >> 6;
   const int P = pr.P, Q = pr.Q;
@@ -252,6 +258,19 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
         }
       }
     }
+    __syncthreads();
+  }
+
+  // ||B0||^2 once (for the relative residual reported at the end)
+  if (S.outer == 0 && !S.done) {
+    double b2 = 0.0;
+    for (int e = tid; e < P * P; e += kCuThreads) {
+      const float2 v = pr.B0[e];
+      b2 += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    double r[1] = {b2};
+    cu_block_sum<1>(r, shd);
+    if (tid == 0) S.b0n2 = r[0];
     __syncthreads();
   }
 
@@ -350,14 +369,21 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
   ok = cu_block_min_i(ok, shi);
   mz = cu_block_min_f(mz, shf);
   if (ok) {
-    // feasible: sigma_F = z, then E = Psi_F sigma_F - b on the owned elements
+    // feasible: sigma_F = z, then E = Psi_F sigma_F - b on the owned elements;
+    // ||E|| is the residual of this image
     for (int k = tid; k < n; k += kCuThreads) pr.sigma[sF[k]] = z[k];
+    double e2 = 0.0;
 #pragma unroll
     for (int i = 0; i < TPW; ++i)
       if (w + kCuWaves * i < NTP) {
         const v4f acc = cu_forward_tile(lds, z, 1.f, n16, RS, tmt[i], tnt[i]);
-        cu_store_c(acc, tmt[i], tnt[i], P, 1.f, -1.f, bsub, pr.E);
+        e2 += cu_store_c(acc, tmt[i], tnt[i], P, 1.f, -1.f, bsub, pr.E);
       }
+    {
+      double r[1] = {e2};
+      cu_block_sum<1>(r, shd);  // (its barrier also completes E)
+      if (tid == 0) S.res2 = r[0];
+    }
     __syncthreads();
     if (pr.Lw) {
       // PWLS: the multiplier kernel beamforms L^-H E L^-1 (and scales by 1/D)
@@ -490,11 +516,23 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) 
   finish();
 }
 
+template <int MT>
+__global__ __launch_bounds__(kCuThreads) void outer_step_kernel(OuterParams pr) {
+  outer_step_body<MT>(pr);
+}
+
+// one workgroup per request of a batch (all with the same P)
+template <int MT>
+__global__ __launch_bounds__(kCuThreads) void outer_step_batch_kernel(const OuterParams* __restrict__ prs) {
+  const OuterParams pr = prs[blockIdx.x];
+  outer_step_body<MT>(pr);
+}
+
 __global__ void outer_init_kernel(OuterState* st, const SolveDecision* dec) {
   if (threadIdx.x != 0) return;
   OuterState S = {};
-  S.nF = dec->nF;
-  S.nU = dec->nU;
+  S.nF = dec ? dec->nF : 0;
+  S.nU = dec ? dec->nU : 0;
   S.last_added = -1;
   S.bb_dirty = S.nU > 0;
   S.margin_lambda = INFINITY;
@@ -582,6 +620,20 @@ bool outer_fits(int P) { return pad_p(P) / 8 <= 6; }
 
 hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s) {
   hipLaunchKernelGGL(outer_init_kernel, dim3(1), dim3(64), 0, s, st, dec);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_step_batch(const OuterParams* prs, int nreq, int P, hipStream_t s) {
+  const dim3 g(nreq), b(kCuThreads);
+  switch (pad_p(P) / 8) {
+    case 1: hipLaunchKernelGGL(outer_step_batch_kernel<1>, g, b, 0, s, prs); break;
+    case 2: hipLaunchKernelGGL(outer_step_batch_kernel<2>, g, b, 0, s, prs); break;
+    case 3: hipLaunchKernelGGL(outer_step_batch_kernel<3>, g, b, 0, s, prs); break;
+    case 4: hipLaunchKernelGGL(outer_step_batch_kernel<4>, g, b, 0, s, prs); break;
+    case 5: hipLaunchKernelGGL(outer_step_batch_kernel<5>, g, b, 0, s, prs); break;
+    case 6: hipLaunchKernelGGL(outer_step_batch_kernel<6>, g, b, 0, s, prs); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,107 @@
+"""Batched solves (clsimg_solve_batch): every request of a batch must give
+exactly what the same request gives alone, and match the oracle.
+
+Requests differ in data (seed), wavelength and grid size, as frequency
+channels or separate observations would; the batch shares the GPU between
+them (one outer-step workgroup per request, one multiplier launch for all).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _req(gpu_lib, sc):
+    return {"R": _dev(sc.R_hat32, torch.complex64), "geo": gpu_lib.Geometry(sc.pos, sc.lam, sc.grid),
+            "noise_diag": _dev(sc.noise_diag, torch.float32)}
+
+
+def _opts(gpu_lib, sc, cost=0):
+    o = gpu_lib.default_options()
+    o.nsamples = sc.N
+    o.atol = o.btol = 1e-7
+    o.cost = cost
+    return o
+
+
+def _scenes(kind):
+    if kind == "p24":
+        return [synth.make_scene("c0", seed=100 + i, lam=lam, n=n)
+                for i, (lam, n) in enumerate([(1.0, 32), (1.3, 24), (1.7, 40), (1.15, 32), (1.9, 16)])]
+    return [synth.make_scene("c1", seed=200 + i, lam=lam, n=n)
+            for i, (lam, n) in enumerate([(1.0, 128), (1.4, 64), (1.8, 96)])]
+
+
+@pytest.mark.parametrize("cost", [0, 1])
+@pytest.mark.parametrize("kind", ["p24", "p48"])
+def test_each_request_in_a_batch_equals_its_solve_alone(gpu_lib, kind, cost):
+    scenes = _scenes(kind)
+    print(f"case batch of {len(scenes)} ({kind}, cost {cost})", flush=True)
+    ctx = gpu_lib.Context(0)
+    try:
+        opts = _opts(gpu_lib, scenes[0], cost)
+        st, res = ctx.solve_batch([_req(gpu_lib, sc) for sc in scenes], opts)
+        torch.cuda.synchronize()
+        assert st >= 0, st
+        for i, sc in enumerate(scenes):
+            r = _req(gpu_lib, sc)
+            sigma, state, mf, gamma, stats = ctx.solve(r["R"], r["geo"], opts, noise_diag=r["noise_diag"])
+            bs, bst, bmf, bg, bstats = res[i]
+            print(f"request {i}: alone {stats['adds']} adds {stats['lsqr_iters_total']} LSQR; "
+                  f"batch {bstats['adds']} adds {bstats['lsqr_iters_total']} LSQR", flush=True)
+            assert torch.equal(state, bst)
+            assert torch.equal(sigma, bs)
+            assert torch.equal(mf, bmf) and torch.equal(gamma, bg)
+            for k in ("status", "outer_iters", "adds", "drops", "lsqr_iters_total", "nF", "nU"):
+                assert stats[k] == bstats[k], (i, k)
+    finally:
+        ctx.close()
+
+
+def test_batch_matches_the_oracle(gpu_lib):
+    scenes = _scenes("p24")[:3]
+    print("case batch of 3 against the oracle", flush=True)
+    ctx = gpu_lib.Context(0)
+    try:
+        st, res = ctx.solve_batch([_req(gpu_lib, sc) for sc in scenes], _opts(gpu_lib, scenes[0]))
+        torch.cuda.synchronize()
+    finally:
+        ctx.close()
+    assert st >= 0
+    for i, sc in enumerate(scenes):
+        R = sc.R_hat32_c128
+        A = oracle.steering(sc.pos, sc.lam, sc.grid)
+        mf = oracle.mf_image(A, R)
+        nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
+        ref = oracle.solve(A, R - np.diag(nd), oracle.upper_bound(A, R),
+                           oracle.detection_threshold(mf, 6.0, sc.N))
+        sigma, state = res[i][0].cpu().numpy(), res[i][1].cpu().numpy()
+        np.testing.assert_array_equal(state, ref.state)
+        err = np.linalg.norm(sigma - ref.sigma) / max(np.linalg.norm(ref.sigma), 1e-30)
+        print(f"request {i}: rel image error {err:.2e}; residual {res[i][4]['rel_residual']:.6f} "
+              f"oracle {ref.rel_residual:.6f}", flush=True)
+        assert err <= 1e-5
+        assert abs(res[i][4]["rel_residual"] - ref.rel_residual) <= 1e-5 * ref.rel_residual + 1e-7
+
+
+def test_batch_rejects_mixed_or_large_arrays(gpu_lib):
+    a, b = synth.make_scene("c0"), synth.make_scene("c1", n=32)
+    big = synth.make_scene("c2", n=16)
+    ctx = gpu_lib.Context(0)
+    try:
+        with pytest.raises(gpu_lib.ClsimgError) as ei:
+            ctx.solve_batch([_req(gpu_lib, a), _req(gpu_lib, b)], _opts(gpu_lib, a))
+        assert ei.value.status == gpu_lib.EINVAL
+        st, _ = ctx.solve_batch([_req(gpu_lib, big)], _opts(gpu_lib, big))
+        assert st == gpu_lib.ENOTSUP
+    finally:
+        ctx.close()

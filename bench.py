@@ -14,6 +14,11 @@ Printed JSON line: solves/s (value), p50/p99 latency, the dense-count
 Psi / Psi^H TFLOP/s of the solves, the roofline of the matched-filter
 beamforming kernel timed with HIP events, the oracle timed on the host cores,
 and the solve's agreement with that oracle run.
+
+--batch B: one step is one batched call of B independent requests of the
+workload (request 0 is the workload itself; the others redraw sky and samples
+with other seeds), value = whole-job solves/s; the same requests solved one
+call after another are timed once for comparison.
 """
 
 import argparse
@@ -64,6 +69,9 @@ def parse():
                     help="only launch the beamformer (20 times) and a plain copy of --copy-mib MiB "
                          "(3 times): the program the HBM traffic counters are read on")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=1,
+                    help="solve B independent requests of the workload per step (one batched call); "
+                         "request 0 is the workload itself, the others redraw its sky and samples")
     return ap.parse_args()
 
 
@@ -170,9 +178,22 @@ def main():
     mf = torch.empty(Q, dtype=torch.float32, device="cuda")
     gamma = torch.empty(Q, dtype=torch.float32, device="cuda")
     ctx = clsimg.Context(0)
+    B = max(1, args.batch)
+    reqs = [{"R": R, "geo": geo, "noise_diag": nd, "sigma": sigma, "state": state, "mf": mf, "gamma": gamma}]
+    for k in range(1, B):
+        sk = synth.make_scene(args.config, seed=synth.scenes._SEED_BASE + 1000 * k)
+        reqs.append({"R": torch.as_tensor(sk.R_hat32).cuda(), "geo": clsimg.Geometry(sk.pos, sk.lam, sk.grid),
+                     "noise_diag": torch.as_tensor(sk.noise_diag.astype(np.float32)).cuda()})
 
     def step():
-        return ctx.solve(R, geo, opts, noise_diag=nd, sigma=sigma, state=state, mf=mf, gamma=gamma)[4]
+        if B == 1:
+            return ctx.solve(R, geo, opts, noise_diag=nd, sigma=sigma, state=state, mf=mf, gamma=gamma)[4]
+        st, res = ctx.solve_batch(reqs, opts)
+        if st < 0:
+            raise RuntimeError(f"batched solve returned {st}: {clsimg.strerror(st)}")
+        agg = dict(res[0][4])
+        agg["psi_flops"] = sum(r[4]["psi_flops"] for r in res)
+        return agg
 
     for i in range(args.warmup):
         step()
@@ -189,7 +210,16 @@ def main():
         flops += stats["psi_flops"]
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    log(f"bench: {args.steps} solves in {total:.3f} s; last stats {stats}")
+    log(f"bench: {args.steps} steps of {B} solve(s) in {total:.3f} s; last stats {stats}")
+    sequential = None
+    if B > 1:
+        # the same requests one clsimg_solve call after another, for comparison
+        t0 = time.perf_counter()
+        for rq in reqs:
+            ctx.solve(rq["R"], rq["geo"], opts, noise_diag=rq["noise_diag"])
+        torch.cuda.synchronize()
+        sequential = B / (time.perf_counter() - t0)
+        log(f"bench: the {B} requests solved one by one: {sequential:.2f} solves/s")
 
     # roofline of the full-grid beamforming kernel: the dirty image is one
     # launch of it.  The calls are captured into a graph and replayed, so the
@@ -258,7 +288,7 @@ def main():
         del Rb, ob
 
     lat_ms = np.array(lat) * 1e3
-    solves_per_s = args.steps / total
+    solves_per_s = B * args.steps / total
     psi_tflops = flops / total / 1e12
     result = {
         "metric": METRIC,
@@ -274,7 +304,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "cost": args.cost, "bound": args.bound,
-                   "kappa_b": args.kappa_b, "P": P, "Q": Q,
+                   "kappa_b": args.kappa_b, "P": P, "Q": Q, "batch": B,
                    "nsamples": sc.N, "n_sources": int(len(sc.src_pix)), "lsqr_tol": args.tol,
                    "contractions": "fp32 MFMA 16x16x4, fp64 Cholesky and LSQR scalars"},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
@@ -292,6 +322,10 @@ def main():
     }
     if big is not None:
         result["roofline_full_size"] = big
+    if sequential is not None:
+        result["batch"] = {"requests": B, "solves_per_s_one_by_one": round(sequential, 4),
+                           "latency": "p50/p99 are of one batched call (all B requests)",
+                           "solve": "request 0's statistics; psi_tflops counts all requests"}
     if not args.no_cpu:
         base, ref = cpu_baseline(sc, tol_oracle=1e-8, cost=args.cost, bound=args.bound, kappa_b=args.kappa_b)
         result["cpu_baseline"] = base

@@ -180,8 +180,7 @@ int clsimg_solve(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array
                  const float* sigma0, const uint8_t* state0, float* sigma, uint8_t* state,
                  float* mf, float* gamma, clsimg_stats* stats, void* stream);
 
-/* Static description of a status code. */
-/* One request of a batched solve. */
+/* One request of a batched solve or of a server. */
 typedef struct {
   const clsimg_c32* R;      /* DEVICE, P x P sample covariance of this request       */
   clsimg_array array;       /* antenna positions and wavelength (P equal in a batch) */
@@ -210,6 +209,60 @@ typedef struct {
  * `reqs` is host memory (n entries); n >= 1. */
 int clsimg_solve_batch(clsimg_ctx* ctx, int32_t n, clsimg_request* reqs, const clsimg_opts* opts, void* stream);
 
+/* ---- Serving: continuous batching of independent requests -------------
+ * A server solves a stream of imaging requests (Sec. III, Table I, LSQR of
+ * Sec. IV-A), each with its own array (any P <= CLSIMG_MAX_P), wavelength and
+ * grid, all with the server's options.  Requests with P <= 48 are admitted
+ * into device slots (at most max_slots, their device state in one arena of
+ * hbm_budget_bytes, 0 = 1 GiB) as slots and arena space free up; each poll
+ * runs steps_per_poll Table I steps of every admitted request, one kernel
+ * launch per array tile-count group and step, and retires finished requests.
+ * Other requests (larger P, or a free set beyond the device loop's on-chip
+ * capacity) are solved by a worker thread on a second stream of the same
+ * device, overlapping with the batch.  Every request's outputs equal those of
+ * clsimg_solve for it alone.  The server owns two contexts, two streams, the
+ * arena, and one thread; submit / poll / query / destroy must be called from
+ * one host thread.  Per-request PWLS (CLSIMG_COST_PWLS) requires P <= 48
+ * (otherwise the request completes at once with status CLSIMG_ENOTSUP). */
+typedef struct clsimg_server clsimg_server;
+
+typedef struct {
+  int32_t pending;        /* submitted, waiting for a slot / arena space        */
+  int32_t active;         /* in device slots                                    */
+  int32_t worker_queued;  /* queued for, or being solved by, the worker         */
+  int32_t ready;          /* finished, not yet returned by clsimg_server_poll   */
+  int64_t submitted, admitted, completed;  /* completed = returned by poll       */
+  int64_t step_rounds;    /* Table I steps launched for the device slots        */
+  size_t arena_bytes, arena_used, arena_peak;
+} clsimg_server_info;
+
+/* Create a server on `device`.  1 <= max_slots <= 1024; 1 <= steps_per_poll
+ * <= 1024 (steps between two looks at the requests' states: fewer give earlier
+ * admission and retirement, more give fewer host round trips).  opts is copied.
+ * Errors: CLSIMG_EINVAL, CLSIMG_ENOMEM (arena), CLSIMG_EHIP. */
+int clsimg_server_create(clsimg_server** srv, int32_t device, int32_t max_slots, size_t hbm_budget_bytes,
+                         int32_t steps_per_poll, const clsimg_opts* opts);
+
+/* Queue request *req (HOST struct; its device buffers and its host positions
+ * must stay valid, and unchanged, until poll returns its ticket).  Outputs and
+ * req->stats are written by the server; stats.status is the request's code as
+ * clsimg_solve would return it.  *ticket > 0 identifies it.  Does no GPU work. */
+int clsimg_server_submit(clsimg_server* srv, clsimg_request* req, int64_t* ticket);
+
+/* Admit, run one round of steps, retire; with wait != 0 repeat until at least
+ * one request is finished or the server holds no work.  Writes up to cap
+ * finished tickets (their outputs complete on the device) to tickets[] and the
+ * count to *n_done.  Returns CLSIMG_OK or an error of the server itself. */
+int clsimg_server_poll(clsimg_server* srv, int32_t wait, int64_t* tickets, int32_t cap, int32_t* n_done);
+
+/* Counters of the server (host struct). */
+int clsimg_server_query(clsimg_server* srv, clsimg_server_info* info);
+
+/* Stop the worker (after its current solve), wait for the streams and free
+ * everything; requests not yet returned are abandoned. */
+int clsimg_server_destroy(clsimg_server* srv);
+
+/* Static description of a status code. */
 const char* clsimg_strerror(int status);
 
 #ifdef __cplusplus

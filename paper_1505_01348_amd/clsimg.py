@@ -29,7 +29,8 @@ MAX_P = 288
 
 EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
             "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
-            "clsimg_solve_batch", "clsimg_strerror")
+            "clsimg_solve_batch", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
+            "clsimg_server_query", "clsimg_server_destroy", "clsimg_strerror")
 
 
 class CArray(C.Structure):
@@ -63,6 +64,13 @@ class CRequest(C.Structure):
                 ("stats", CStats)]
 
 
+class CServerInfo(C.Structure):
+    _fields_ = [("pending", C.c_int32), ("active", C.c_int32), ("worker_queued", C.c_int32),
+                ("ready", C.c_int32), ("submitted", C.c_int64), ("admitted", C.c_int64),
+                ("completed", C.c_int64), ("step_rounds", C.c_int64), ("arena_bytes", C.c_size_t),
+                ("arena_used", C.c_size_t), ("arena_peak", C.c_size_t)]
+
+
 class ClsimgError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -87,6 +95,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.clsimg_solve_batch.argtypes = [vp, i32, C.POINTER(CRequest), C.POINTER(COpts), vp]
     lib.clsimg_solve.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, C.POINTER(COpts),
                                  vp, vp, vp, vp, vp, vp, C.POINTER(CStats), vp]
+    lib.clsimg_server_create.argtypes = [C.POINTER(vp), i32, i32, sz, i32, C.POINTER(COpts)]
+    lib.clsimg_server_submit.argtypes = [vp, C.POINTER(CRequest), C.POINTER(C.c_int64)]
+    lib.clsimg_server_poll.argtypes = [vp, i32, C.POINTER(C.c_int64), i32, C.POINTER(i32)]
+    lib.clsimg_server_query.argtypes = [vp, C.POINTER(CServerInfo)]
+    lib.clsimg_server_destroy.argtypes = [vp]
     lib.clsimg_strerror.argtypes = [C.c_int]
     lib.clsimg_strerror.restype = C.c_char_p
     for name in EXPORTED:
@@ -334,3 +347,85 @@ class Context:
 def epsilon_scale(kappa_d: float, nsamples: int) -> float:
     """Factor turning the MF image into the detection threshold (App. A, K = 1)."""
     return kappa_d / math.sqrt(nsamples)
+
+
+class Server:
+    """Continuous-batching solver (clsimg_server_*): submit requests at any time,
+    poll for finished ones.  A request is a dict like those of
+    ``Context.solve_batch``; its tensors and geometry are kept alive here until
+    its ticket is returned.  Use from one thread."""
+
+    def __init__(self, opts: Options, device: int = 0, max_slots: int = 64, hbm_budget: int = 1 << 30,
+                 steps_per_poll: int = 16):
+        self.device = int(device)
+        self._lib = lib()
+        h = C.c_void_p()
+        co = opts.to_c()
+        st = self._lib.clsimg_server_create(C.byref(h), self.device, int(max_slots), int(hbm_budget),
+                                            int(steps_per_poll), C.byref(co))
+        if st != OK:
+            raise ClsimgError(st, "clsimg_server_create")
+        self._h = h
+        self._live = {}  # ticket -> (CRequest, tensors, geometry)
+
+    def submit(self, rq) -> int:
+        R, geo = rq["R"], rq["geo"]
+        dev = self.device
+        _need(R, torch.complex64, geo.P * geo.P, "R", dev)
+        Q = geo.Q
+        nd = rq.get("noise_diag")
+        if nd is not None:
+            _need(nd, torch.float32, geo.P, "noise_diag", dev)
+        mk = lambda t, dt: torch.empty(Q, dtype=dt, device=R.device) if t is None else t  # noqa: E731
+        sigma, state = mk(rq.get("sigma"), torch.float32), mk(rq.get("state"), torch.uint8)
+        mf, gamma = mk(rq.get("mf"), torch.float32), mk(rq.get("gamma"), torch.float32)
+        for t, dt, name in ((sigma, torch.float32, "sigma"), (state, torch.uint8, "state"),
+                            (mf, torch.float32, "mf"), (gamma, torch.float32, "gamma")):
+            _need(t, dt, Q, name, dev)
+        cr = CRequest()
+        cr.R = R.data_ptr()
+        cr.array = geo.c_array
+        cr.grid = geo.c_grid
+        cr.noise_diag = None if nd is None else nd.data_ptr()
+        cr.sigma, cr.state, cr.mf, cr.gamma = sigma.data_ptr(), state.data_ptr(), mf.data_ptr(), gamma.data_ptr()
+        # the server reads the inputs on its own streams: make the producer's work visible first
+        torch.cuda.current_stream(R.device).synchronize()
+        t = C.c_int64()
+        st = self._lib.clsimg_server_submit(self._h, C.byref(cr), C.byref(t))
+        if st != OK:
+            raise ClsimgError(st, "clsimg_server_submit")
+        self._live[t.value] = (cr, (R, nd, sigma, state, mf, gamma), geo)
+        return t.value
+
+    def poll(self, wait: bool = False, cap: int = 256):
+        """Finished requests: list of (ticket, (sigma, state, mf, gamma, stats dict))."""
+        arr = (C.c_int64 * cap)()
+        n = C.c_int32()
+        st = self._lib.clsimg_server_poll(self._h, 1 if wait else 0, arr, cap, C.byref(n))
+        if st != OK:
+            raise ClsimgError(st, "clsimg_server_poll")
+        out = []
+        for k in range(n.value):
+            cr, ts, _ = self._live.pop(arr[k])
+            stats = {f: getattr(cr.stats, f) for f, _ in CStats._fields_}
+            out.append((arr[k], ts[2:] + (stats,)))
+        return out
+
+    def info(self):
+        inf = CServerInfo()
+        st = self._lib.clsimg_server_query(self._h, C.byref(inf))
+        if st != OK:
+            raise ClsimgError(st, "clsimg_server_query")
+        return {f: getattr(inf, f) for f, _ in CServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.clsimg_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

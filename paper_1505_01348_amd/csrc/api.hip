@@ -12,6 +12,7 @@
 
 #include "../../include/clsimg.h"
 #include "kernels.h"
+#include "request.h"
 
 using namespace clsimg;
 
@@ -359,6 +360,161 @@ int check_opts(const clsimg_opts* o, int P) {
 }
 
 }  // namespace
+
+namespace clsimg {
+
+bool request_on_device(int P) { return beam_fits(P) && outer_fits(P); }
+
+ReqLayout request_layout(int P, int nl, int nm, bool pwls, int nkeys) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const int Pp = pad_p(P);
+  const size_t Q = (size_t)nl * nm;
+  ReqLayout L;
+  L.nkeys = nkeys;
+  L.El = 0;
+  L.Em = L.El + al((size_t)Pp * nl * sizeof(float2));
+  L.B0 = L.Em + al((size_t)Pp * nm * sizeof(float2));
+  L.Bb = L.B0 + al((size_t)P * P * sizeof(float2));
+  L.E = L.Bb + al((size_t)P * P * sizeof(float2));
+  L.eps = L.E + al((size_t)P * P * sizeof(float2));
+  L.gam = L.eps + al(Q * sizeof(float));
+  L.mf = L.gam + al(Q * sizeof(float));
+  L.F = L.mf + al(Q * sizeof(float));
+  L.U = L.F + al(Q * sizeof(int));
+  L.st = L.U + al(2 * Q * sizeof(int));
+  L.keys = L.st + al(sizeof(OuterState));
+  L.rs = L.keys + al((size_t)nkeys * sizeof(uint64_t));
+  L.gpw = L.rs + (pwls ? al(Q * sizeof(float)) : 0);
+  L.dinv = L.gpw + (pwls ? al(Q * sizeof(float)) : 0);
+  L.Lw = L.dinv + (pwls ? al(Q * sizeof(float)) : 0);
+  L.bytes = L.Lw + (pwls ? al((size_t)P * P * sizeof(float2)) : 0);
+  return L;
+}
+
+int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L,
+                  OuterParams& op, BeamLamItem& it, hipStream_t st) {
+  memset(&q.stats, 0, sizeof(clsimg_stats));
+  const int P = q.array.P, Pp = pad_p(P);
+  const int Q = q.grid.nl * q.grid.nm;
+  const bool pwls = o->cost == CLSIMG_COST_PWLS;
+  ST_TRY(ensure_workspace(c, P, Q));
+  ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
+  if (pwls) ST_TRY(ensure(c, c->pw_h, (size_t)Q * sizeof(float)));
+  const float2* Rf = reinterpret_cast<const float2*>(q.R);
+  // the steering tables: built in the context, then kept in the slice
+  ST_TRY(ensure_tables(c, &q.array, &q.grid, st));
+  float2* El = reinterpret_cast<float2*>(slice + L.El);
+  float2* Em = reinterpret_cast<float2*>(slice + L.Em);
+  HIP_TRY(hipMemcpyAsync(El, c->El.ptr, (size_t)Pp * q.grid.nl * sizeof(float2), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(Em, c->Em.ptr, (size_t)Pp * q.grid.nm * sizeof(float2), hipMemcpyDeviceToDevice, st));
+  Tables tab;
+  tab.El = El;
+  tab.Em = Em;
+  tab.nl = q.grid.nl;
+  tab.nm = q.grid.nm;
+  tab.Pp = Pp;
+  tab.Q = Q;
+  const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
+  float* eps = reinterpret_cast<float*>(slice + L.eps);
+  float* mf = q.mf ? q.mf : reinterpret_cast<float*>(slice + L.mf);
+  float* gamma = q.gamma ? q.gamma : reinterpret_cast<float*>(slice + L.gam);
+  float2* B0 = reinterpret_cast<float2*>(slice + L.B0);
+  ST_TRY(beam_full(c, &q.grid, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
+  ST_TRY(compute_bound(c, q.R, &q.array, &q.grid, o, gamma, st));
+  const float* op_gamma = gamma;
+  const float* rowscale = nullptr;
+  const float2* Lw = nullptr;
+  const float* dinv = nullptr;
+  if (!pwls) {
+    HIP_TRY(launch_sub_diag(Rf, q.noise_diag, P, B0, st));
+  } else {
+    if (o->bound != CLSIMG_BOUND_MVDR) {
+      HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
+                                  P_<int>(c->status), st));
+      ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
+      if (*c->h_status != 0) return CLSIMG_ENOTPD;
+    }
+    float* h = P_<float>(c->pw_h);
+    ST_TRY(beam_full(c, &q.grid, P, P_<const float2>(c->Rinv), BEAM_STORE, h, nullptr, 0.f, 0, 0, 1.f, st));
+    const double kd = o->kappa_d != 0.0 ? o->kappa_d / sqrt((double)(o->nsamples - P - 1)) : 0.0;
+    float* rs = reinterpret_cast<float*>(slice + L.rs);
+    float* gpw = reinterpret_cast<float*>(slice + L.gpw);
+    float* dv = reinterpret_cast<float*>(slice + L.dinv);
+    float2* lw = reinterpret_cast<float2*>(slice + L.Lw);
+    HIP_TRY(launch_pwls_setup(h, gamma, o->C, kd, Q, rs, gpw, eps, dv, st));
+    HIP_TRY(launch_sub_diag(Rf, q.noise_diag, P, P_<float2>(c->B0), st));
+    HIP_TRY(launch_pwls_whiten(P_<const double2>(c->Li), P_<const float2>(c->B0), P, lw, B0, st));
+    op_gamma = gpw;
+    rowscale = rs;
+    Lw = lw;
+    dinv = dv;
+  }
+  HIP_TRY(launch_init_state(nullptr, nullptr, q.sigma, q.state, Q, st));
+  OuterState* ost = reinterpret_cast<OuterState*>(slice + L.st);
+  HIP_TRY(launch_outer_init(ost, nullptr, st));
+  const int nblk = beam_grid(Q);
+  if (nblk > L.nkeys) return CLSIMG_EINVAL;
+  op.st = ost;
+  op.Flist = reinterpret_cast<int*>(slice + L.F);
+  op.Ulist = reinterpret_cast<int*>(slice + L.U);
+  op.sigma = q.sigma;
+  op.gamma = op_gamma;
+  op.eps = eps;
+  op.state = q.state;
+  op.B0 = B0;
+  op.Bb = reinterpret_cast<float2*>(slice + L.Bb);
+  op.E = reinterpret_cast<float2*>(slice + L.E);
+  op.keys = reinterpret_cast<const uint64_t*>(slice + L.keys);
+  op.nkeys = nblk;
+  op.tab = tab;
+  op.P = P;
+  op.Q = Q;
+  op.atol = o->atol;
+  op.btol = o->btol;
+  op.conlim = o->conlim;
+  op.itnlim = o->itnlim;
+  op.max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
+  op.max_f = c->outer_max_f;
+  op.Lw = Lw;
+  op.rowscale = rowscale;
+  it.U = op.E;
+  it.tab = tab;
+  it.skip = &ost->lam_skip;
+  it.state = q.state;
+  it.part = reinterpret_cast<uint64_t*>(slice + L.keys);
+  it.scale = dinv;
+  it.P = P;
+  it.nblk = nblk;
+  return CLSIMG_OK;
+}
+
+int request_finish(clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L, const OuterState& S,
+                   hipStream_t st) {
+  const int P = q.array.P;
+  const int Q = q.grid.nl * q.grid.nm;
+  int status = S.status == kStatusMaxOuter ? CLSIMG_WMAXOUTER : (S.status == kStatusCycle ? CLSIMG_WCYCLE : CLSIMG_OK);
+  if (status == CLSIMG_OK && S.itnlim_hits) status = CLSIMG_WITNLIM;
+  if (S.fallback) status = CLSIMG_ENOTSUP;
+  if (o->cost == CLSIMG_COST_PWLS && !S.fallback)
+    HIP_TRY(launch_pwls_scale(q.sigma, reinterpret_cast<const float*>(slice + L.dinv), Q, false, st));
+  clsimg_stats& t = q.stats;
+  t.status = status;
+  t.outer_iters = S.outer;
+  t.adds = S.adds;
+  t.drops = S.drops;
+  t.lsqr_iters_total = S.lsqr_total;
+  t.lsqr_itnlim_hits = S.itnlim_hits;
+  t.nF = S.nF;
+  t.nU = S.nU;
+  t.rel_residual = S.b0n2 > 0.0 ? sqrt(S.res2 / S.b0n2) : 0.0;
+  t.objective = 0.5 * S.res2;
+  t.min_margin_lambda = S.margin_lambda;
+  t.min_margin_z = S.margin_z;
+  t.psi_flops = S.psi_flops + 2.0 * beam_flops(P, Q);
+  return status;
+}
+
+}  // namespace clsimg
 
 extern "C" {
 
@@ -1009,34 +1165,17 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
     nlmax = std::max(nlmax, q.grid.nl);
     nmmax = std::max(nmmax, q.grid.nm);
   }
-  if (!beam_fits(P) || !outer_fits(P)) return CLSIMG_ENOTSUP;
+  if (!request_on_device(P)) return CLSIMG_ENOTSUP;
   DeviceGuard guard(c->device);
   hipStream_t st = (hipStream_t)stream;
-  const int Pp = pad_p(P);
   ST_TRY(ensure_workspace(c, P, Qmax));
   ST_TRY(ensure(c, c->eps, (size_t)Qmax * sizeof(float)));
   if (pwls) ST_TRY(ensure(c, c->pw_h, (size_t)Qmax * sizeof(float)));
 
-  // per-request slices of one workspace
-  const int bpr = beam_grid(Qmax);  // multiplier blocks (and argmin keys) per request
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t o_El = 0, o_Em = o_El + al((size_t)Pp * nlmax * sizeof(float2));
-  const size_t o_B0 = o_Em + al((size_t)Pp * nmmax * sizeof(float2));
-  const size_t o_Bb = o_B0 + al((size_t)P * P * sizeof(float2));
-  const size_t o_E = o_Bb + al((size_t)P * P * sizeof(float2));
-  const size_t o_eps = o_E + al((size_t)P * P * sizeof(float2));
-  const size_t o_gam = o_eps + al((size_t)Qmax * sizeof(float));
-  const size_t o_mf = o_gam + al((size_t)Qmax * sizeof(float));
-  const size_t o_F = o_mf + al((size_t)Qmax * sizeof(float));
-  const size_t o_U = o_F + al((size_t)Qmax * sizeof(int));
-  const size_t o_st = o_U + al((size_t)2 * Qmax * sizeof(int));
-  const size_t o_keys = o_st + al(sizeof(OuterState));
-  const size_t o_rs = o_keys + al((size_t)bpr * sizeof(uint64_t));
-  const size_t o_gpw = o_rs + (pwls ? al((size_t)Qmax * sizeof(float)) : 0);
-  const size_t o_dinv = o_gpw + (pwls ? al((size_t)Qmax * sizeof(float)) : 0);
-  const size_t o_Lw = o_dinv + (pwls ? al((size_t)Qmax * sizeof(float)) : 0);
-  const size_t per = o_Lw + (pwls ? al((size_t)P * P * sizeof(float2)) : 0);
-  ST_TRY(ensure(c, c->batch, per * n));
+  // per-request slices of one workspace, all laid out for the largest grid
+  const int bpr = beam_grid(Qmax);  // multiplier blocks per request in the launch
+  const ReqLayout L = request_layout(P, nlmax, nmmax, pwls, bpr);
+  ST_TRY(ensure(c, c->batch, L.bytes * n));
   const size_t pbytes = (size_t)n * (sizeof(OuterParams) + sizeof(BeamLamItem));
   ST_TRY(ensure(c, c->batch_params, pbytes));
   const size_t hbytes = std::max(pbytes, (size_t)n * sizeof(OuterState));
@@ -1053,99 +1192,10 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
     HIP_TRY(hipStreamSynchronize(st));  // the staging of a previous call has been consumed
   }
   char* base = P_<char>(c->batch);
-  auto slice = [&](int r, size_t off) { return base + (size_t)r * per + off; };
+  auto slice = [&](int r) { return base + (size_t)r * L.bytes; };
   OuterParams* hp = reinterpret_cast<OuterParams*>(c->h_batch);
   BeamLamItem* hi = reinterpret_cast<BeamLamItem*>(c->h_batch + (size_t)n * sizeof(OuterParams));
-  const int max_outer_default = o->max_outer;
-  const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
-
-  for (int r = 0; r < n; ++r) {
-    clsimg_request& q = reqs[r];
-    const int Q = q.grid.nl * q.grid.nm;
-    const float2* Rf = reinterpret_cast<const float2*>(q.R);
-    // this request's steering tables: built in the context, then kept in its slice
-    ST_TRY(ensure_tables(c, &q.array, &q.grid, st));
-    float2* El = reinterpret_cast<float2*>(slice(r, o_El));
-    float2* Em = reinterpret_cast<float2*>(slice(r, o_Em));
-    HIP_TRY(hipMemcpyAsync(El, c->El.ptr, (size_t)Pp * q.grid.nl * sizeof(float2), hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(Em, c->Em.ptr, (size_t)Pp * q.grid.nm * sizeof(float2), hipMemcpyDeviceToDevice, st));
-    Tables tab;
-    tab.El = El;
-    tab.Em = Em;
-    tab.nl = q.grid.nl;
-    tab.nm = q.grid.nm;
-    tab.Pp = Pp;
-    tab.Q = Q;
-    float* eps = reinterpret_cast<float*>(slice(r, o_eps));
-    float* mf = q.mf ? q.mf : reinterpret_cast<float*>(slice(r, o_mf));
-    float* gamma = q.gamma ? q.gamma : reinterpret_cast<float*>(slice(r, o_gam));
-    float2* B0 = reinterpret_cast<float2*>(slice(r, o_B0));
-    ST_TRY(beam_full(c, &q.grid, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
-    ST_TRY(compute_bound(c, q.R, &q.array, &q.grid, o, gamma, st));
-    const float* op_gamma = gamma;
-    const float* rowscale = nullptr;
-    const float2* Lw = nullptr;
-    const float* dinv = nullptr;
-    if (!pwls) {
-      HIP_TRY(launch_sub_diag(Rf, q.noise_diag, P, B0, st));
-    } else {
-      if (o->bound != CLSIMG_BOUND_MVDR) {
-        HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
-                                    P_<int>(c->status), st));
-        ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
-        if (*c->h_status != 0) return CLSIMG_ENOTPD;
-      }
-      float* h = P_<float>(c->pw_h);
-      ST_TRY(beam_full(c, &q.grid, P, P_<const float2>(c->Rinv), BEAM_STORE, h, nullptr, 0.f, 0, 0, 1.f, st));
-      const double kd = o->kappa_d != 0.0 ? o->kappa_d / sqrt((double)(o->nsamples - P - 1)) : 0.0;
-      float* rs = reinterpret_cast<float*>(slice(r, o_rs));
-      float* gpw = reinterpret_cast<float*>(slice(r, o_gpw));
-      float* di = reinterpret_cast<float*>(slice(r, o_dinv));
-      float2* lw = reinterpret_cast<float2*>(slice(r, o_Lw));
-      HIP_TRY(launch_pwls_setup(h, gamma, o->C, kd, Q, rs, gpw, eps, di, st));
-      HIP_TRY(launch_sub_diag(Rf, q.noise_diag, P, P_<float2>(c->B0), st));
-      HIP_TRY(launch_pwls_whiten(P_<const double2>(c->Li), P_<const float2>(c->B0), P, lw, B0, st));
-      op_gamma = gpw;
-      rowscale = rs;
-      Lw = lw;
-      dinv = di;
-    }
-    HIP_TRY(launch_init_state(nullptr, nullptr, q.sigma, q.state, Q, st));
-    OuterState* ost = reinterpret_cast<OuterState*>(slice(r, o_st));
-    HIP_TRY(launch_outer_init(ost, nullptr, st));
-    OuterParams& op = hp[r];
-    op.st = ost;
-    op.Flist = reinterpret_cast<int*>(slice(r, o_F));
-    op.Ulist = reinterpret_cast<int*>(slice(r, o_U));
-    op.sigma = q.sigma;
-    op.gamma = op_gamma;
-    op.eps = eps;
-    op.state = q.state;
-    op.B0 = B0;
-    op.Bb = reinterpret_cast<float2*>(slice(r, o_Bb));
-    op.E = reinterpret_cast<float2*>(slice(r, o_E));
-    op.keys = reinterpret_cast<const uint64_t*>(slice(r, o_keys));
-    op.nkeys = bpr;
-    op.tab = tab;
-    op.P = P;
-    op.Q = Q;
-    op.atol = o->atol;
-    op.btol = o->btol;
-    op.conlim = o->conlim;
-    op.itnlim = o->itnlim;
-    op.max_outer = max_outer_default < 0 ? 4 * Q : max_outer_default;
-    op.max_f = c->outer_max_f;
-    op.Lw = Lw;
-    op.rowscale = rowscale;
-    BeamLamItem& it = hi[r];
-    it.U = op.E;
-    it.tab = tab;
-    it.skip = &ost->lam_skip;
-    it.state = q.state;
-    it.part = reinterpret_cast<uint64_t*>(slice(r, o_keys));
-    it.scale = dinv;
-    it.P = P;
-  }
+  for (int r = 0; r < n; ++r) ST_TRY(request_setup(c, reqs[r], o, slice(r), L, hp[r], hi[r], st));
   OuterParams* dp = P_<OuterParams>(c->batch_params);
   BeamLamItem* di = reinterpret_cast<BeamLamItem*>(P_<char>(c->batch_params) + (size_t)n * sizeof(OuterParams));
   HIP_TRY(hipMemcpyAsync(dp, c->h_batch, pbytes, hipMemcpyHostToDevice, st));
@@ -1160,7 +1210,7 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
     }
     OuterState* hs = reinterpret_cast<OuterState*>(c->h_batch);
     for (int r = 0; r < n; ++r)
-      HIP_TRY(hipMemcpyAsync(hs + r, slice(r, o_st), sizeof(OuterState), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(hs + r, slice(r) + L.st, sizeof(OuterState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     bool all = true;
     for (int r = 0; r < n; ++r) all = all && hs[r].done;
@@ -1170,28 +1220,7 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   const OuterState* hs = reinterpret_cast<const OuterState*>(c->h_batch);
   int worst = CLSIMG_OK;
   for (int r = 0; r < n; ++r) {
-    clsimg_request& q = reqs[r];
-    const OuterState& S = hs[r];
-    const int Q = q.grid.nl * q.grid.nm;
-    int status = S.status == kStatusMaxOuter ? CLSIMG_WMAXOUTER : (S.status == kStatusCycle ? CLSIMG_WCYCLE : CLSIMG_OK);
-    if (status == CLSIMG_OK && S.itnlim_hits) status = CLSIMG_WITNLIM;
-    if (S.fallback) status = CLSIMG_ENOTSUP;
-    if (pwls && !S.fallback)
-      HIP_TRY(launch_pwls_scale(q.sigma, reinterpret_cast<const float*>(slice(r, o_dinv)), Q, false, st));
-    clsimg_stats& t = q.stats;
-    t.status = status;
-    t.outer_iters = S.outer;
-    t.adds = S.adds;
-    t.drops = S.drops;
-    t.lsqr_iters_total = S.lsqr_total;
-    t.lsqr_itnlim_hits = S.itnlim_hits;
-    t.nF = S.nF;
-    t.nU = S.nU;
-    t.rel_residual = S.b0n2 > 0.0 ? sqrt(S.res2 / S.b0n2) : 0.0;
-    t.objective = 0.5 * S.res2;
-    t.min_margin_lambda = S.margin_lambda;
-    t.min_margin_z = S.margin_z;
-    t.psi_flops = S.psi_flops + 2.0 * beam_flops(P, Q);
+    const int status = request_finish(reqs[r], o, slice(r), L, hs[r], st);
     if (status < 0) worst = (worst < 0) ? worst : status;
     else if (worst >= 0 && status > worst) worst = status;
   }

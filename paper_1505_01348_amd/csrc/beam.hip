@@ -250,8 +250,9 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
     const BeamLamItem* __restrict__ items, int bpr) {
   const int r = blockIdx.x / bpr, lb = blockIdx.x - r * bpr;
   const BeamLamItem it = items[r];
+  if (lb >= it.nblk) return;  // the whole block: this request has fewer pixels
   BeamLambda epi{it.state, it.part, it.scale, 0};
-  beam_body<MT>(nullptr, it.U, it.P, it.tab, it.skip, epi, lb, bpr);
+  beam_body<MT>(nullptr, it.U, it.P, it.tab, it.skip, epi, lb, it.nblk);
 }
 
 // ---------------------------------------------------------------------------

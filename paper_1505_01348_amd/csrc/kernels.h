@@ -294,10 +294,12 @@ struct BeamLamItem {
   Tables tab;
   const int* skip;
   const uint8_t* state;
-  uint64_t* part;      // bpr argmin keys
+  uint64_t* part;      // nblk argmin keys
   const float* scale;  // optional per-pixel factor
   int P;
+  int nblk;  // this request's blocks (beam_grid of its Q); blocks beyond it exit at once
 };
+// grid: nreq x bpr blocks, bpr >= every item's nblk; all items share P's tile count
 hipError_t launch_beam_lambda_batch(const BeamLamItem* items, int nreq, int bpr, int P, hipStream_t st);
 
 // GEMM-shaped full-grid beamformer for larger arrays (P <= 288)

@@ -1,0 +1,37 @@
+// Host-side pieces of a device-resident solve that the batched call and the
+// server share: the layout of one request's device state, its set-up (dirty
+// image, bound, data matrix, initial state: the same launches as a single
+// solve on the device loop) and its finish (PWLS rescaling, statistics).
+#pragma once
+
+#include <cstddef>
+
+#include "../../include/clsimg.h"
+#include "kernels.h"
+
+namespace clsimg {
+
+// Byte offsets inside one request's slice of device memory.
+struct ReqLayout {
+  size_t El, Em, B0, Bb, E, eps, gam, mf, F, U, st, keys, rs, gpw, dinv, Lw, bytes;
+  int nkeys;
+};
+
+// Layout for P antennas and an nl x nm grid; nkeys argmin keys.
+ReqLayout request_layout(int P, int nl, int nm, bool pwls, int nkeys);
+
+// Enqueue the set-up of request q on stream st into `slice` (laid out by L)
+// and fill its outer-step parameters and multiplier item.  Uses the context's
+// shared scratch (tables, Cholesky factors) only inside the stream order.
+int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L,
+                  OuterParams& op, BeamLamItem& it, hipStream_t st);
+
+// Status and statistics of a finished request from its final outer state;
+// enqueues the PWLS rescaling of sigma.  Returns the request's status.
+int request_finish(clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L, const OuterState& S,
+                   hipStream_t st);
+
+// The request can run on the device-resident loop (one workgroup per step).
+bool request_on_device(int P);
+
+}  // namespace clsimg

@@ -69,6 +69,12 @@ def parse():
                     help="only launch the beamformer (20 times) and a plain copy of --copy-mib MiB "
                          "(3 times): the program the HBM traffic counters are read on")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="serving benchmark instead: N mixed requests (24/48/96 antennas, 64^2..256^2 "
+                         "pixels) through the continuous-batching server, against one solve at a time")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=16, help="Table I steps per server poll")
+    ap.add_argument("--serve-workers", type=int, default=4, help="server threads for P > 48 requests")
     ap.add_argument("--batch", type=int, default=1,
                     help="solve B independent requests of the workload per step (one batched call); "
                          "request 0 is the workload itself, the others redraw its sky and samples")
@@ -128,6 +134,108 @@ def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls", bound="mvdr", kappa_b
             "sample": f"{runs} full FP64 oracle solves of the same workload ({t_total:.1f} s)"}, res
 
 
+def serve_bench(args, clsimg, synth, np, torch):
+    """Mixed requests (one frequency channel each): P uniform in {24, 48, 96}, grid
+    uniform in {64^2, 128^2, 256^2} over |l|,|m| <= 0.7, 10..200 point sources
+    log-uniform in [0.1, 100], lambda uniform in [1, 2), noise 10, N = 16384."""
+    n = args.serve
+    scenes = synth.make_request_scenes(n)
+    opts = clsimg.default_options()
+    opts.nsamples = 16384
+    opts.atol = opts.btol = args.tol
+    reqs = [{"R": torch.as_tensor(sc.R_hat32).cuda(), "geo": clsimg.Geometry(sc.pos, sc.lam, sc.grid),
+             "noise_diag": torch.as_tensor(sc.noise_diag.astype(np.float32)).cuda()} for sc in scenes]
+    torch.cuda.synchronize()
+    mix = {}
+    for sc in scenes:
+        key = f"P{sc.P}_{sc.nl}x{sc.nm}"
+        mix[key] = mix.get(key, 0) + 1
+    log(f"bench: {n} requests, mix {mix}")
+
+    # the plain per-solve path: one clsimg_solve after another
+    ctx = clsimg.Context(0)
+    for rq in reqs[:2]:  # warm-up (module load, first allocations)
+        ctx.solve(rq["R"], rq["geo"], opts, noise_diag=rq["noise_diag"])
+    torch.cuda.synchronize()
+    alone, lat1 = [], []
+    t0 = time.perf_counter()
+    for i, rq in enumerate(reqs):
+        ts = time.perf_counter()
+        alone.append(ctx.solve(rq["R"], rq["geo"], opts, noise_diag=rq["noise_diag"])[4])
+        torch.cuda.synchronize()
+        lat1.append(time.perf_counter() - ts)
+    t_seq = time.perf_counter() - t0
+    ctx.close()
+    rate1 = n / t_seq
+    log(f"bench: one solve at a time: {rate1:.2f} solves/s ({t_seq:.2f} s)")
+
+    def run(arrivals):
+        srv = clsimg.Server(opts, max_slots=args.serve_slots, hbm_budget=4 << 30, steps_per_poll=args.serve_steps,
+                            workers=args.serve_workers)
+        order = sorted(range(n), key=lambda i: arrivals[i])
+        ticket_of, done_at, stats = {}, {}, {}
+        k = 0
+        t_start = time.perf_counter()
+        while len(done_at) < n:
+            now = time.perf_counter() - t_start
+            while k < n and arrivals[order[k]] <= now:
+                i = order[k]
+                ticket_of[srv.submit(reqs[i])] = i
+                k += 1
+            info = srv.info()
+            busy = info["pending"] + info["active"] + info["worker_queued"] + info["ready"] > 0
+            if not busy:
+                if k < n:
+                    time.sleep(max(0.0, arrivals[order[k]] - (time.perf_counter() - t_start)))
+                continue
+            for t, r in srv.poll(wait=(k == n)):
+                i = ticket_of[t]
+                done_at[i] = time.perf_counter() - t_start
+                stats[i] = r[4]
+        total = time.perf_counter() - t_start
+        peak = srv.info()["arena_peak"]
+        srv.close()
+        lat = np.array([done_at[i] - arrivals[i] for i in range(n)]) * 1e3
+        same = all(stats[i]["rel_residual"] == alone[i]["rel_residual"] and
+                   stats[i]["lsqr_iters_total"] == alone[i]["lsqr_iters_total"] for i in range(n))
+        return {"solves_per_s": round(n / total, 3), "wall_s": round(total, 3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "arena_peak_bytes": int(peak), "same_result_as_alone": bool(same)}
+
+    closed = run([0.0] * n)
+    log(f"bench: server, all {n} at once: {closed}")
+    rng = np.random.default_rng(20150504)
+    sweep = {}
+    for f in (0.5, 1.0, 2.0):
+        qps = f * rate1
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=n))
+        arr -= arr[0]
+        sweep[f"{f}x"] = dict(run(list(arr)), qps=round(qps, 3))
+        log(f"bench: server, Poisson arrivals at {qps:.2f}/s: {sweep[f'{f}x']}")
+    lat1 = np.array(lat1) * 1e3
+    by_class = {}
+    for sc, t in zip(scenes, lat1):
+        by_class.setdefault(f"P{sc.P}_{sc.nl}x{sc.nm}", []).append(float(t))
+    by_class = {k: round(float(np.mean(v)), 2) for k, v in sorted(by_class.items())}
+    result = {
+        "metric": "imaging solves/s and p50/p99 latency, mixed requests (continuous batching)",
+        "value": closed["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n} requests: P in {{24,48,96}}, grid in {{64^2,128^2,256^2}} (L=0.7), "
+                               "10-200 points log-U[0.1,100], lambda U[1,2), noise 10, N=16384",
+                   "mix": mix, "slots": args.serve_slots, "steps_per_poll": args.serve_steps,
+                   "workers": args.serve_workers,
+                   "lsqr_tol": args.tol},
+        "one_solve_at_a_time": {"solves_per_s": round(rate1, 3), "p50_ms": round(float(np.percentile(lat1, 50)), 2),
+                                "p99_ms": round(float(np.percentile(lat1, 99)), 2),
+                                "mean_ms_by_class": by_class},
+        "server_all_at_once": closed,
+        "server_poisson": sweep,
+        "speedup_vs_one_at_a_time": round(closed["solves_per_s"] / rate1, 3),
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -145,6 +253,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serve:
+        serve_bench(args, clsimg, synth, np, torch)
+        return
     sc = synth.make_scene(args.config)
     log(f"bench: workload {args.config} P={sc.P} Q={sc.Q} N={sc.N}")
     if args.kernel_only:

@@ -114,8 +114,10 @@ typedef struct {
   int32_t lsqr_iters_total;
   int32_t lsqr_itnlim_hits;
   int32_t nF, nU;         /* final set sizes                                    */
-  double rel_residual;    /* ||B0 - Psi sigma||_F / ||B0||_F                    */
-  double objective;       /* 1/2 ||B0 - Psi sigma||_F^2                         */
+  double rel_residual;    /* ||B0 - Psi sigma||_F / ||B0||_F at the final image; with */
+                          /* CLSIMG_COST_PWLS the whitened residual of eq. preWLS,   */
+                          /* ||L^-1 (B0 - Psi sigma) L^-H||_F / ||L^-1 B0 L^-H||_F   */
+  double objective;       /* 1/2 the squared residual norm (numerator above)        */
   double min_margin_lambda; /* min |lambda_i + eps_i| / eps_i over detection tests */
   double min_margin_z;      /* min over accepted subproblems of min(z, gamma-z)/gamma */
   double psi_flops;         /* dense-count flops of every Psi / Psi^H applied: 8 P^2 per pixel
@@ -191,8 +193,7 @@ typedef struct {
   float* mf;                /* DEVICE, Q, or NULL: MF dirty image (output)           */
   float* gamma;             /* DEVICE, Q, or NULL: upper bound (output)              */
   clsimg_stats stats;       /* HOST: statistics of this request (output); status is  */
-                            /* the request's own code.  rel_residual and objective   */
-                            /* are taken at the last feasible step (PWLS: weighted)  */
+                            /* the request's own code                                */
 } clsimg_request;
 
 /* Batched solve (Sec. III, Table I, with LSQR of Sec. IV-A) of n independent
@@ -218,10 +219,10 @@ int clsimg_solve_batch(clsimg_ctx* ctx, int32_t n, clsimg_request* reqs, const c
  * runs steps_per_poll Table I steps of every admitted request, one kernel
  * launch per array tile-count group and step, and retires finished requests.
  * Other requests (larger P, or a free set beyond the device loop's on-chip
- * capacity) are solved by a worker thread on a second stream of the same
+ * capacity) are solved by worker threads on streams of their own on the same
  * device, overlapping with the batch.  Every request's outputs equal those of
- * clsimg_solve for it alone.  The server owns two contexts, two streams, the
- * arena, and one thread; submit / poll / query / destroy must be called from
+ * clsimg_solve for it alone.  The server owns one context and stream for the
+ * batch, one per worker, the arena and the worker threads; submit / poll / query / destroy must be called from
  * one host thread.  Per-request PWLS (CLSIMG_COST_PWLS) requires P <= 48
  * (otherwise the request completes at once with status CLSIMG_ENOTSUP). */
 typedef struct clsimg_server clsimg_server;
@@ -238,10 +239,12 @@ typedef struct {
 
 /* Create a server on `device`.  1 <= max_slots <= 1024; 1 <= steps_per_poll
  * <= 1024 (steps between two looks at the requests' states: fewer give earlier
- * admission and retirement, more give fewer host round trips).  opts is copied.
+ * admission and retirement, more give fewer host round trips); 1 <= workers
+ * <= 8 threads for the requests outside the device loop, each with its own
+ * context and stream.  opts is copied.
  * Errors: CLSIMG_EINVAL, CLSIMG_ENOMEM (arena), CLSIMG_EHIP. */
 int clsimg_server_create(clsimg_server** srv, int32_t device, int32_t max_slots, size_t hbm_budget_bytes,
-                         int32_t steps_per_poll, const clsimg_opts* opts);
+                         int32_t steps_per_poll, int32_t workers, const clsimg_opts* opts);
 
 /* Queue request *req (HOST struct; its device buffers and its host positions
  * must stay valid, and unchanged, until poll returns its ticket).  Outputs and
@@ -258,7 +261,7 @@ int clsimg_server_poll(clsimg_server* srv, int32_t wait, int64_t* tickets, int32
 /* Counters of the server (host struct). */
 int clsimg_server_query(clsimg_server* srv, clsimg_server_info* info);
 
-/* Stop the worker (after its current solve), wait for the streams and free
+/* Stop the workers (after their current solves), wait for the streams and free
  * everything; requests not yet returned are abandoned. */
 int clsimg_server_destroy(clsimg_server* srv);
 

@@ -95,7 +95,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.clsimg_solve_batch.argtypes = [vp, i32, C.POINTER(CRequest), C.POINTER(COpts), vp]
     lib.clsimg_solve.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, C.POINTER(COpts),
                                  vp, vp, vp, vp, vp, vp, C.POINTER(CStats), vp]
-    lib.clsimg_server_create.argtypes = [C.POINTER(vp), i32, i32, sz, i32, C.POINTER(COpts)]
+    lib.clsimg_server_create.argtypes = [C.POINTER(vp), i32, i32, sz, i32, i32, C.POINTER(COpts)]
     lib.clsimg_server_submit.argtypes = [vp, C.POINTER(CRequest), C.POINTER(C.c_int64)]
     lib.clsimg_server_poll.argtypes = [vp, i32, C.POINTER(C.c_int64), i32, C.POINTER(i32)]
     lib.clsimg_server_query.argtypes = [vp, C.POINTER(CServerInfo)]
@@ -356,13 +356,13 @@ class Server:
     its ticket is returned.  Use from one thread."""
 
     def __init__(self, opts: Options, device: int = 0, max_slots: int = 64, hbm_budget: int = 1 << 30,
-                 steps_per_poll: int = 16):
+                 steps_per_poll: int = 16, workers: int = 1):
         self.device = int(device)
         self._lib = lib()
         h = C.c_void_p()
         co = opts.to_c()
         st = self._lib.clsimg_server_create(C.byref(h), self.device, int(max_slots), int(hbm_budget),
-                                            int(steps_per_poll), C.byref(co))
+                                            int(steps_per_poll), int(workers), C.byref(co))
         if st != OK:
             raise ClsimgError(st, "clsimg_server_create")
         self._h = h

@@ -510,7 +510,7 @@ int request_finish(clsimg_request& q, const clsimg_opts* o, char* slice, const R
   t.objective = 0.5 * S.res2;
   t.min_margin_lambda = S.margin_lambda;
   t.min_margin_z = S.margin_z;
-  t.psi_flops = S.psi_flops + 2.0 * beam_flops(P, Q);
+  t.psi_flops = S.psi_flops + beam_flops(P, Q) + (o->bound != CLSIMG_BOUND_NONE ? beam_flops(P, Q) : 0.0);
   return status;
 }
 
@@ -798,6 +798,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   const bool beam_full_grid = beam_fits(P) && !c->old_beam;
   const bool beam_big_grid_ok = !beam_fits(P) && beam_big_fits(P) && !c->old_beam;
   bool host_loop = true;
+  double dev_res2 = 0.0, dev_b0n2 = 0.0;  // residual of the device loop's last feasible step
   // PWLS inputs (eq. preWLS): Cholesky of R, h = a^H R^-1 a, D = h^2 / C, the
   // whitened data, bound D gamma and the MVDR-image threshold; the loop then
   // solves for D sigma
@@ -878,6 +879,8 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
     flops += S.psi_flops;
     // a free set too large for one workgroup: continue on the host from here
     host_loop = S.fallback != 0;
+    dev_res2 = S.res2;
+    dev_b0n2 = S.b0n2;
     if (pwls) {
       if (host_loop) return CLSIMG_ENOTSUP;  // the host loop has no PWLS path
       HIP_TRY(launch_pwls_scale(sigma, P_<const float>(c->pw_dinv), Q, false, st));  // sigma = D^-1 (D sigma)
@@ -1121,6 +1124,24 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
     }
   }
   if (status == CLSIMG_OK && itnlim_hits) status = CLSIMG_WITNLIM;
+  if (!host_loop) {
+    // finished on the device: the residual of the last feasible step (the
+    // final image), as the batched and served solves report it
+    stats->status = status;
+    stats->outer_iters = outer;
+    stats->adds = adds;
+    stats->drops = drops;
+    stats->lsqr_iters_total = lsqr_total;
+    stats->lsqr_itnlim_hits = itnlim_hits;
+    stats->nF = nF;
+    stats->nU = nU;
+    stats->rel_residual = dev_b0n2 > 0.0 ? sqrt(dev_res2 / dev_b0n2) : 0.0;
+    stats->objective = 0.5 * dev_res2;
+    stats->min_margin_lambda = margin_lambda;
+    stats->min_margin_z = margin_z;
+    stats->psi_flops = flops;
+    return status;
+  }
   // final residual ||B0 - Psi sigma||_F
   HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
   ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));

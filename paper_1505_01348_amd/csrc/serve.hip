@@ -9,8 +9,8 @@
 // small outer states back, retires finished requests and admits waiting ones
 // into the freed slots and arena space, so new work joins work already on the
 // GPU.  Requests the device loop cannot hold (more antennas, or a free set
-// beyond its on-chip capacity) are solved by a worker thread with its own
-// context and stream, overlapping with the batch on the device.
+// beyond its on-chip capacity) are solved by worker threads, each with its own
+// context and stream, overlapping with the batch and each other on the device.
 //
 // Every request computes exactly what clsimg_solve computes for it alone: the
 // same set-up launches, the same outer-step and multiplier code, and the same
@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kMaxSlots = 1024;     // one workgroup per slot and step
 constexpr int kKeysPerReq = 2048;   // multiplier blocks of the largest grid
+constexpr int kMaxWorkers = 8;      // threads (contexts, streams) for the other requests
 constexpr size_t kAlign = 256;
 
 struct Job {
@@ -117,14 +118,14 @@ struct clsimg_server {
   };
   std::vector<Group> groups;
   int64_t next_ticket = 1, submitted = 0, admitted = 0, completed = 0, steps = 0;
-  // worker for requests outside the device loop
-  clsimg_ctx* wctx = nullptr;
-  hipStream_t wstream = nullptr;
-  std::thread worker;
+  // workers for requests outside the device loop: one context and stream each
+  std::vector<clsimg_ctx*> wctx;
+  std::vector<hipStream_t> wstream;
+  std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Job> large_q;  // guarded by mu
-  int large_active = 0;     // guarded by mu
+  int large_active = 0;     // guarded by mu: jobs being solved by workers
   bool stop = false;        // guarded by mu
   std::deque<int64_t> done;  // guarded by mu
 };
@@ -142,7 +143,7 @@ struct DeviceScope {
   }
 };
 
-void worker_main(clsimg_server* s) {
+void worker_main(clsimg_server* s, int w) {
   (void)hipSetDevice(s->device);
   for (;;) {
     Job j;
@@ -152,16 +153,16 @@ void worker_main(clsimg_server* s) {
       if (s->stop) return;
       j = s->large_q.front();
       s->large_q.pop_front();
-      s->large_active = 1;
+      ++s->large_active;
     }
     clsimg_request& q = *j.req;
-    int st = clsimg_solve(s->wctx, q.R, &q.array, &q.grid, q.noise_diag, &s->opts, nullptr, nullptr, q.sigma,
-                          q.state, q.mf, q.gamma, &q.stats, s->wstream);
-    if (hipStreamSynchronize(s->wstream) != hipSuccess && st >= 0) st = CLSIMG_EHIP;
+    int st = clsimg_solve(s->wctx[w], q.R, &q.array, &q.grid, q.noise_diag, &s->opts, nullptr, nullptr, q.sigma,
+                          q.state, q.mf, q.gamma, &q.stats, s->wstream[w]);
+    if (hipStreamSynchronize(s->wstream[w]) != hipSuccess && st >= 0) st = CLSIMG_EHIP;
     q.stats.status = st;
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      s->large_active = 0;
+      --s->large_active;
       s->done.push_back(j.ticket);
     }
     s->cv_done.notify_all();
@@ -309,10 +310,11 @@ int take_done(clsimg_server* s, int64_t* tickets, int32_t cap, int32_t* n_done) 
 extern "C" {
 
 int clsimg_server_create(clsimg_server** out, int32_t device, int32_t max_slots, size_t hbm_budget_bytes,
-                         int32_t steps_per_poll, const clsimg_opts* o) {
+                         int32_t steps_per_poll, int32_t workers, const clsimg_opts* o) {
   if (!out) return CLSIMG_EINVAL;
   *out = nullptr;
-  if (!o || max_slots < 1 || max_slots > kMaxSlots || steps_per_poll < 1 || steps_per_poll > 1024)
+  if (!o || max_slots < 1 || max_slots > kMaxSlots || steps_per_poll < 1 || steps_per_poll > 1024 ||
+      workers < 1 || workers > kMaxWorkers)
     return CLSIMG_EINVAL;
   if (o->cost != CLSIMG_COST_LS && o->cost != CLSIMG_COST_PWLS) return CLSIMG_EINVAL;
   if (o->nsamples <= 0 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
@@ -327,10 +329,15 @@ int clsimg_server_create(clsimg_server** out, int32_t device, int32_t max_slots,
   const size_t arena = hbm_budget_bytes ? hbm_budget_bytes : (size_t)1 << 30;
   void* base = nullptr;
   int st = clsimg_create(&s->ctx, device, 0);
-  if (st == CLSIMG_OK) st = clsimg_create(&s->wctx, device, 0);
-  if (st == CLSIMG_OK && (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-                          hipStreamCreateWithFlags(&s->wstream, hipStreamNonBlocking) != hipSuccess))
-    st = CLSIMG_EHIP;
+  if (st == CLSIMG_OK && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) st = CLSIMG_EHIP;
+  for (int w = 0; w < workers && st == CLSIMG_OK; ++w) {
+    clsimg_ctx* c = nullptr;
+    hipStream_t ws = nullptr;
+    st = clsimg_create(&c, device, 0);
+    if (st == CLSIMG_OK) s->wctx.push_back(c);
+    if (st == CLSIMG_OK && hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) st = CLSIMG_EHIP;
+    if (st == CLSIMG_OK) s->wstream.push_back(ws);
+  }
   if (st == CLSIMG_OK && hipMalloc(&base, arena) != hipSuccess) st = CLSIMG_ENOMEM;
   if (st == CLSIMG_OK) s->arena.reset(static_cast<char*>(base), arena);
   const size_t pbytes = (size_t)max_slots * (sizeof(OuterParams) + sizeof(BeamLamItem));
@@ -342,7 +349,7 @@ int clsimg_server_create(clsimg_server** out, int32_t device, int32_t max_slots,
     clsimg_server_destroy(s);
     return st;
   }
-  s->worker = std::thread(worker_main, s);
+  for (int w = 0; w < workers; ++w) s->workers.emplace_back(worker_main, s, w);
   *out = s;
   return CLSIMG_OK;
 }
@@ -350,23 +357,21 @@ int clsimg_server_create(clsimg_server** out, int32_t device, int32_t max_slots,
 int clsimg_server_destroy(clsimg_server* s) {
   if (!s) return CLSIMG_EINVAL;
   DeviceScope scope(s->device);
-  if (s->worker.joinable()) {
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->stop = true;
-    }
-    s->cv_work.notify_all();
-    s->worker.join();  // a solve in progress is finished first
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
   }
+  s->cv_work.notify_all();
+  for (auto& t : s->workers) t.join();  // solves in progress are finished first
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  if (s->wstream) (void)hipStreamSynchronize(s->wstream);
+  for (auto ws : s->wstream) (void)hipStreamSynchronize(ws);
   if (s->arena.base) (void)hipFree(s->arena.base);
   if (s->d_params) (void)hipFree(s->d_params);
   if (s->h_stage) (void)hipHostFree(s->h_stage);
   if (s->ctx) clsimg_destroy(s->ctx);
-  if (s->wctx) clsimg_destroy(s->wctx);
+  for (auto c : s->wctx) clsimg_destroy(c);
   if (s->stream) (void)hipStreamDestroy(s->stream);
-  if (s->wstream) (void)hipStreamDestroy(s->wstream);
+  for (auto ws : s->wstream) (void)hipStreamDestroy(ws);
   delete s;
   return CLSIMG_OK;
 }

@@ -4,7 +4,7 @@ same as the request solved alone with clsimg_solve.
 
 Arrivals are staggered (submit, run some steps, submit more) so that requests
 join slots freed by finished ones; a small HBM budget forces admission to wait
-for arena space; one request has 96 antennas and goes to the worker stream.
+for arena space; requests with 96 antennas go to the worker streams.
 """
 
 import numpy as np
@@ -37,8 +37,9 @@ def _opts(gpu_lib, cost=0):
 def _mixed_scenes(with_large=True):
     # P in {24, 48}, grids 32^2 / 64^2, lambda in [1, 2), 10..200 point sources
     out = synth.make_request_scenes(10, P_choices=(24, 48), n_choices=(32, 64))
-    if with_large:
-        out.insert(3, synth.make_scene("c2", n=32, seed=777))  # 96 antennas: the worker's
+    if with_large:  # 96 antennas: the workers'
+        out.insert(3, synth.make_scene("c2", n=32, seed=777))
+        out.insert(6, synth.make_scene("c2", n=48, seed=778))
     return out
 
 
@@ -97,12 +98,12 @@ def _serve(gpu_lib, scenes, opts, **kw):
 
 def test_mixed_requests_equal_their_solves_alone(gpu_lib):
     scenes = _mixed_scenes()
-    print("case server: mixed P 24/48 and one 96, staggered arrivals", flush=True)
+    print("case server: mixed P 24/48 and two 96, staggered arrivals, two workers", flush=True)
     opts = _opts(gpu_lib)
-    served, info = _serve(gpu_lib, scenes, opts, max_slots=8, steps_per_poll=8)
+    served, info = _serve(gpu_lib, scenes, opts, max_slots=8, steps_per_poll=8, workers=2)
     print("server info", info, flush=True)
     assert info["submitted"] == len(scenes) and info["completed"] == len(scenes)
-    assert info["admitted"] == len(scenes) - 1  # the 96-antenna request went to the worker
+    assert info["admitted"] == len(scenes) - 2  # the 96-antenna requests went to the workers
     alone = _alone(gpu_lib, scenes, opts)
     for i in range(len(scenes)):
         _same(alone[i], served[i], i)

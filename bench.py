@@ -35,6 +35,8 @@ if ROOT not in sys.path:
 METRIC = ("Ψ/Ψᴴ TFLOP/s + % MFMA peak; imaging solves/s and p50/p99 latency at "
           "fixed residual")
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HALF_MFMA_TFLOPS = 2516.6  # FP16 / BF16 dense
+PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2}
 WORKLOADS = {
     "c0": "P=24 random planar array (radius 20 lambda), Q=32x32 over |l|,|m|<=0.5, 5 point sources "
           "U[1,10], noise 1, N=4096 samples",
@@ -61,6 +63,9 @@ def parse():
     ap.add_argument("--bound", default="mvdr", choices=["mvdr", "mf", "none"],
                     help="upper bound of the box (Sec. II-D)")
     ap.add_argument("--kappa-b", type=float, default=0.0, help="bound inflation in std units (App. A)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="full-grid beamforming products: FP32, or split FP16 / BF16 halves on the "
+                         "half-precision MFMA (LSQR stays FP32)")
     ap.add_argument("--cost", default="ls", choices=["ls", "pwls"],
                     help="cost function: LS (eq. CLS) or preconditioned weighted LS (eq. preWLS)")
     ap.add_argument("--no-large", action="store_true",
@@ -281,6 +286,7 @@ def main():
     opts.cost = clsimg.COST_PWLS if args.cost == "pwls" else clsimg.COST_LS
     opts.bound = {"mvdr": clsimg.BOUND_MVDR, "mf": clsimg.BOUND_MF, "none": clsimg.BOUND_NONE}[args.bound]
     opts.kappa_b = args.kappa_b
+    opts.precision = PRECISIONS[args.precision]
     R = torch.as_tensor(sc.R_hat32).cuda()
     nd = torch.as_tensor(sc.noise_diag.astype(np.float32)).cuda()
     Q = sc.Q
@@ -378,24 +384,39 @@ def main():
         gb = clsimg.Geometry(sb.pos, sb.lam, sb.grid)
         Rb = torch.as_tensor(sb.R_hat32).cuda()
         ob = torch.empty(sb.Q, dtype=torch.float32, device="cuda")
-        for _ in range(3):
-            ctx.dirty_image(Rb, gb, mf=ob)
-        torch.cuda.synchronize()
-        reps_b = 20
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps_b):
-            ctx.dirty_image(Rb, gb, mf=ob)
-        e1.record()
-        torch.cuda.synchronize()
-        tb = e0.elapsed_time(e1) / 1e3 / reps_b
         fb = 8.0 * sb.P * sb.P * sb.Q + 8.0 * sb.P * sb.Q
-        big = {"kernel": "beam_prep_full + beam_big_kernel<9, BeamMF> (dirty image, full grid)",
-               "workload": "P=288, 512x512 pixels (the 288-antenna workload's size)", "bound": "mfma",
-               "achieved": round(fb / tb / 1e12, 4), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-               "frac": round(fb / tb / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5), "us_per_launch": round(tb * 1e6, 2),
-               "flops_per_launch": fb, "timing": "eager (each call is milliseconds long)"}
-        log(f"bench: 288-antenna dirty image {tb * 1e6:.1f} us, {fb / tb / 1e12:.1f} TFLOP/s")
+        Ppb = -(-sb.P // 8) * 8
+        by = {}
+        for name, prec in PRECISIONS.items():
+            for _ in range(3):
+                ctx.dirty_image(Rb, gb, mf=ob, precision=prec)
+            torch.cuda.synchronize()
+            reps_b = 20
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps_b):
+                ctx.dirty_image(Rb, gb, mf=ob, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            tb = e0.elapsed_time(e1) / 1e3 / reps_b
+            dense = fb / tb / 1e12
+            if prec == 0:
+                by[name] = {"kernel": "beam_prep_full + beam_big_kernel<9, BeamMF>", "bound": "mfma",
+                            "achieved": round(dense, 4), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(dense / PEAK_FP32_MFMA_TFLOPS, 5), "us_per_launch": round(tb * 1e6, 2)}
+            else:
+                # three half-precision products (hi.hi, hi.lo, lo.hi) of the full real 2P x 2P matrix
+                issued = 3 * 2.0 * (2 * Ppb) ** 2 * sb.Q
+                by[name] = {"kernel": f"scale + prep + beam_h16_kernel<9, {name}, BeamMF>", "bound": "mfma",
+                            "achieved_dense_count": round(dense, 4), "issued_half_mfma": round(issued / tb / 1e12, 4),
+                            "peak": PEAK_HALF_MFMA_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(issued / tb / 1e12 / PEAK_HALF_MFMA_TFLOPS, 5),
+                            "us_per_launch": round(tb * 1e6, 2), "speedup_vs_fp32": None}
+            log(f"bench: 288-antenna dirty image {name}: {tb * 1e6:.1f} us, {dense:.1f} TFLOP/s dense count")
+        for name in ("fp16", "bf16"):
+            by[name]["speedup_vs_fp32"] = round(by["fp32"]["us_per_launch"] / by[name]["us_per_launch"], 3)
+        big = dict(by["fp32"], workload="P=288, 512x512 pixels (the 288-antenna workload's size)",
+                   flops_per_launch=fb, timing="eager (each call is milliseconds long)", by_precision=by)
         del Rb, ob
 
     lat_ms = np.array(lat) * 1e3
@@ -412,9 +433,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "fp16": "f16 split halves + f32", "bf16": "bf16 split halves + f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "cost": args.cost, "bound": args.bound,
+                   "precision": args.precision,
                    "kappa_b": args.kappa_b, "P": P, "Q": Q, "batch": B,
                    "nsamples": sc.N, "n_sources": int(len(sc.src_pix)), "lsqr_tol": args.tol,
                    "contractions": "fp32 MFMA 16x16x4, fp64 Cholesky and LSQR scalars"},

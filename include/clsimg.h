@@ -58,8 +58,14 @@ extern "C" {
 #define CLSIMG_BOUND_MF 1    /* gamma = MF dirty image (+ kappa_b std), eq. mfupper  */
 #define CLSIMG_BOUND_NONE 2  /* gamma = +inf: lower bound only, eq. NNLS             */
 
-/* arithmetic of the Psi / Psi^H contractions */
-#define CLSIMG_FP32 0
+/* arithmetic of the full-grid beamforming products (dirty image, bound, and
+ * the Lagrange multipliers of the host-driven loop); the LSQR subproblems and
+ * the device-resident loop (P <= 48) compute in FP32 in every mode */
+#define CLSIMG_FP32 0  /* FP32 MFMA (16x16x4)                                         */
+#define CLSIMG_FP16 1  /* FP16 MFMA (16x16x32), each operand split into high and low  */
+                       /* halves, three products accumulated in FP32; power-of-two    */
+                       /* scaling keeps the operands in range; close to FP32 results  */
+#define CLSIMG_BF16 2  /* the same split with BF16 halves (about 2^-16 relative)      */
 
 /* cost function for clsimg_opts.cost */
 #define CLSIMG_COST_LS 0     /* 1/2 ||B0 - Psi sigma||^2, eq. CLS                         */
@@ -102,7 +108,7 @@ typedef struct {
   double conlim;          /* LSQR condition limit                    (1e8)      */
   int32_t itnlim;         /* LSQR iterations per subproblem, -1 = 4|F|+100      */
   int32_t max_outer;      /* subproblem solves, -1 = 4Q                         */
-  int32_t precision;      /* CLSIMG_FP32                                        */
+  int32_t precision;      /* CLSIMG_FP32 | CLSIMG_FP16 | CLSIMG_BF16            */
   int32_t cost;           /* CLSIMG_COST_*                           (LS)       */
 } clsimg_opts;
 
@@ -137,9 +143,10 @@ int clsimg_destroy(clsimg_ctx* ctx);
 
 /* Matched-filter dirty image, eq. mfdimg at K = 1:
  *   mf[i] = a_i^H R a_i,  i = 0..Q-1.
- * R: DEVICE complex64 P x P.  mf: DEVICE float[Q]. */
+ * R: DEVICE complex64 P x P.  precision: CLSIMG_FP32 / _FP16 / _BF16.
+ * mf: DEVICE float[Q]. */
 int clsimg_dirty_image(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array,
-                       const clsimg_grid* grid, float* mf, void* stream);
+                       const clsimg_grid* grid, int32_t precision, float* mf, void* stream);
 
 /* Upper bound gamma of the box constraint (eq. CLS):
  *   MVDR (eq. wmvdr, Sec. II-D): h_i = a_i^H R^-1 a_i with R = L L^H factored in

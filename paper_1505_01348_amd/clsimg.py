@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libclsimg.s
 OK, WMAXOUTER, WITNLIM, WCYCLE = 0, 1, 2, 3
 EINVAL, ENOTPD, ENOMEM, EHIP, ENOTSUP = -1, -2, -3, -4, -5
 BOUND_MVDR, BOUND_MF, BOUND_NONE = 0, 1, 2
-FP32 = 0
+FP32, FP16, BF16 = 0, 1, 2
 COST_LS, COST_PWLS = 0, 1
 STATE_L, STATE_F, STATE_U = 0, 1, 2
 MAX_P = 288
@@ -87,7 +87,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.clsimg_default_opts.restype = None
     lib.clsimg_create.argtypes = [C.POINTER(vp), i32, sz]
     lib.clsimg_destroy.argtypes = [vp]
-    lib.clsimg_dirty_image.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp]
+    lib.clsimg_dirty_image.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp]
     lib.clsimg_mvdr_bound.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), C.POINTER(COpts),
                                       vp, vp]
     lib.clsimg_forward.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp, i32, vp, vp]
@@ -226,13 +226,13 @@ class Context:
             raise ClsimgError(st, where)
         return st
 
-    def dirty_image(self, R, geo: Geometry, mf=None):
+    def dirty_image(self, R, geo: Geometry, mf=None, precision: int = FP32):
         dev = self.device
         _need(R, torch.complex64, geo.P * geo.P, "R", dev)
         mf = torch.empty(geo.Q, dtype=torch.float32, device=R.device) if mf is None else mf
         _need(mf, torch.float32, geo.Q, "mf", dev)
         self._check(self._lib.clsimg_dirty_image(self._h, _ptr(R), C.byref(geo.c_array),
-                                                 C.byref(geo.c_grid), _ptr(mf), _stream()),
+                                                 C.byref(geo.c_grid), int(precision), _ptr(mf), _stream()),
                     "clsimg_dirty_image")
         return mf
 

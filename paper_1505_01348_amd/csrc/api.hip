@@ -65,6 +65,8 @@ struct clsimg_ctx {
   bool old_beam = false;   // CLSIMG_LDS_BEAM=1: LDS-staged beamformer for the gradient
   bool beam_prep = false;  // CLSIMG_BEAM_PREP=1: beamformer fragments from a separate pass
   bool host_loop = false;  // CLSIMG_HOST_LOOP=1: active-set loop driven from the host
+  int prec = CLSIMG_FP32;  // arithmetic of the full-grid beamforming products of the current call
+  DevBuf frag_h, hscale;   // split half-precision fragments and their scale
   int outer_max_f = 1 << 30;  // CLSIMG_OUTER_MAXF: hand over to the host loop beyond this |F|
 };
 
@@ -279,6 +281,16 @@ enum BeamKind { BEAM_MF, BEAM_MVDR, BEAM_STORE };
 int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamKind kind, float* out,
               float* eps, float eps_scale, double C, double kb, float scale, hipStream_t st) {
   const Tables tab = tables_of(c, g, P);
+  if (c->prec != CLSIMG_FP32) {  // split half precision, GEMM-shaped kernel for every P
+    const bool bf = c->prec == CLSIMG_BF16;
+    ST_TRY(ensure(c, c->frag_h, beam_h16_frag_bytes(P)));
+    ST_TRY(ensure(c, c->hscale, sizeof(float)));
+    HIP_TRY(launch_beam_prep_h16(U, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st));
+    const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
+    HIP_TRY(launch_beam_h16(k, bf, c->frag_h.ptr, P_<const float>(c->hscale), tab, nullptr, out, eps, eps_scale, C,
+                            kb, scale, nullptr, nullptr, st));
+    return CLSIMG_OK;
+  }
   if (!beam_fits(P)) {  // larger arrays: fragments of the whole Ut, GEMM-shaped kernel
     HIP_TRY(launch_beam_prep_full(U, P, P_<float>(c->frag_b), st));
     const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
@@ -346,7 +358,8 @@ double beam_flops(int P, int n) { return 8.0 * P * P * n + 8.0 * P * n; }
 int check_opts(const clsimg_opts* o, int P) {
   if (!o) return CLSIMG_EINVAL;
   if (o->bound < CLSIMG_BOUND_MVDR || o->bound > CLSIMG_BOUND_NONE) return CLSIMG_EINVAL;
-  if (o->precision != CLSIMG_FP32) return CLSIMG_EINVAL;
+  if (o->precision != CLSIMG_FP32 && o->precision != CLSIMG_FP16 && o->precision != CLSIMG_BF16)
+    return CLSIMG_EINVAL;
   if (o->cost != CLSIMG_COST_LS && o->cost != CLSIMG_COST_PWLS) return CLSIMG_EINVAL;
   if (o->cost == CLSIMG_COST_PWLS && !(o->C > 0.0)) return CLSIMG_EINVAL;
   if (o->bound == CLSIMG_BOUND_MVDR && !(o->C > 0.0)) return CLSIMG_EINVAL;
@@ -394,6 +407,7 @@ ReqLayout request_layout(int P, int nl, int nm, bool pwls, int nkeys) {
 int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L,
                   OuterParams& op, BeamLamItem& it, hipStream_t st) {
   memset(&q.stats, 0, sizeof(clsimg_stats));
+  c->prec = o->precision;
   const int P = q.array.P, Pp = pad_p(P);
   const int Q = q.grid.nl * q.grid.nm;
   const bool pwls = o->cost == CLSIMG_COST_PWLS;
@@ -615,9 +629,11 @@ const char* clsimg_strerror(int s) {
 }
 
 int clsimg_dirty_image(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a,
-                       const clsimg_grid* g, float* mf, void* stream) {
+                       const clsimg_grid* g, int32_t precision, float* mf, void* stream) {
   if (!c || !R || !mf) return CLSIMG_EINVAL;
   ST_TRY(check_geometry(a, g));
+  if (precision != CLSIMG_FP32 && precision != CLSIMG_FP16 && precision != CLSIMG_BF16) return CLSIMG_EINVAL;
+  c->prec = precision;
   DeviceGuard guard(c->device);
   hipStream_t st = (hipStream_t)stream;
   const int P = a->P, Q = g->nl * g->nm;
@@ -634,6 +650,7 @@ int clsimg_mvdr_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a,
   if (!c || !R || !gamma) return CLSIMG_EINVAL;
   ST_TRY(check_geometry(a, g));
   ST_TRY(check_opts(o, a->P));
+  c->prec = o->precision;
   DeviceGuard guard(c->device);
   hipStream_t st = (hipStream_t)stream;
   ST_TRY(ensure_workspace(c, a->P, g->nl * g->nm));
@@ -646,6 +663,7 @@ int clsimg_forward(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, c
   if (!c || !Y || n < 0 || (n > 0 && !v)) return CLSIMG_EINVAL;
   ST_TRY(check_geometry(a, g));
   if (!idx && n > g->nl * g->nm) return CLSIMG_EINVAL;
+  c->prec = CLSIMG_FP32;
   DeviceGuard guard(c->device);
   hipStream_t st = (hipStream_t)stream;
   ST_TRY(ensure_workspace(c, a->P, g->nl * g->nm));
@@ -683,6 +701,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   ST_TRY(check_geometry(a, g));
   ST_TRY(check_opts(o, a->P));
   if (o->nsamples <= 0 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
+  c->prec = o->precision;
   DeviceGuard guard(c->device);
   hipStream_t st = (hipStream_t)stream;
   const int P = a->P, Q = g->nl * g->nm;
@@ -796,6 +815,11 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   int batch = 4;
   const int ntiles_Q = ntiles_adj(P, Q);
   const bool beam_full_grid = beam_fits(P) && !c->old_beam;
+  const bool beam_half = c->prec != CLSIMG_FP32;  // split half-precision multipliers
+  if (beam_half) {
+    ST_TRY(ensure(c, c->frag_h, beam_h16_frag_bytes(P)));
+    ST_TRY(ensure(c, c->hscale, sizeof(float)));
+  }
   const bool beam_big_grid_ok = !beam_fits(P) && beam_big_fits(P) && !c->old_beam;
   bool host_loop = true;
   double dev_res2 = 0.0, dev_b0n2 = 0.0;  // residual of the device loop's last feasible step
@@ -1050,7 +1074,13 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, bsub, 1.f, -1.f, nullptr, frag_r, nullptr,
                            grad_stop, st));
         }
-        if (!beam_full_grid && beam_big_grid_ok) {
+        if (beam_half) {
+          const bool bf = c->prec == CLSIMG_BF16;
+          HIP_TRY(launch_beam_prep_h16(E, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st));
+          HIP_TRY(launch_beam_h16(3, bf, c->frag_h.ptr, P_<const float>(c->hscale), tables_of(c, g, P), grad_stop,
+                                  nullptr, nullptr, 0.f, 0, 0, 1.f, state, keys, st));
+          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q), eps, state, dec, st));
+        } else if (!beam_full_grid && beam_big_grid_ok) {
           HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr, 0.f,
                                   0, 0, 1.f, state, keys, st));

@@ -430,6 +430,197 @@ __global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__
   epi.finish(blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Split half precision (CLSIMG_FP16, CLSIMG_BF16): the same product Y = Ut X
+// on the 16 x 16 x 32 half-precision MFMA with FP32 accumulation.  Each
+// operand is split into a high and a low half (v = hi + lo, lo = v - hi
+// rounded again), and three products are accumulated: hi.hi + hi.lo + lo.hi.
+// With FP16 (11-bit significands) the dropped lo.lo term is 2^-22 of the
+// product, so the result is close to the FP32 one; with BF16 (8 bits) it is
+// 2^-16.  FP16 needs the operands inside its range: Ut is scaled by a power of
+// two sU (largest entry below 2^14, computed on the device) and the steering
+// entries by a power of two sB (|a_p| = P^-1/2); the column dot in FP32 with
+// the unscaled steering entries is multiplied by 1 / (sU sB) (exact).
+//
+// Embedding: real position 2p + s = component s of antenna p (Ut[2p+s][2q+t]
+// = Re H_pq if s == t, -Im H_pq if (s, t) = (0, 1), Im H_pq if (1, 0), with H
+// the Hermitian part of U).  In K chunk c a lane of group g = lane >> 4
+// supplies positions 32c + 8g + i, i.e. antennas 16c + 4g + (i >> 1) with
+// both components; accumulator element r of row tile m is position
+// 16m + 4g + r, i.e. antenna 8m + 2g + (r >> 1), component r & 1.
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+
+template <bool BF>
+struct Half;
+template <>
+struct Half<false> {
+  typedef _Float16 T;
+  typedef v8h V;
+  __device__ static v4f mfma(V a, V b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Half<true> {
+  typedef __bf16 T;
+  typedef v8b V;
+  __device__ static v4f mfma(V a, V b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+
+// power-of-two scale putting the largest |U| component just below 2^14
+__global__ __launch_bounds__(1024) void beam_h16_scale_kernel(const float2* __restrict__ U, int n, float* scale) {
+  __shared__ float sm[16];
+  float m = 0.f;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const float2 v = U[e];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = fmaxf(t, sm[i]);
+    int ex = 0;
+    (void)frexpf(t, &ex);  // t < 2^ex
+    *scale = (t > 0.f && isfinite(t)) ? ldexpf(1.f, 14 - ex) : 1.f;
+  }
+}
+
+template <bool BF>
+__device__ __forceinline__ void split_half(float v, typename Half<BF>::T& hi, typename Half<BF>::T& lo) {
+  hi = (typename Half<BF>::T)v;
+  lo = (typename Half<BF>::T)(v - (float)hi);
+}
+
+// fragments: [row tile m][chunk c][hi, lo][lane][8]
+template <bool BF>
+__global__ void beam_prep_h16_kernel(const float2* __restrict__ U, int P, int MT, int KC, const float* __restrict__ scale,
+                                     typename Half<BF>::V* __restrict__ frag) {
+  typedef typename Half<BF>::V V;
+  const float sU = scale ? *scale : 1.f;
+  const int total = 4 * big_rpw(MT) * KC * 64;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int lane = e & 63, f = e >> 6;
+    const int m = f / KC, c = f - m * KC;
+    const int row = 16 * m + (lane & 15), col0 = 32 * c + 8 * (lane >> 4);
+    const int p = row >> 1, s = row & 1;
+    V hi, lo;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int p2 = (col0 + i) >> 1, t = i & 1;
+      float v = 0.f;
+      if (m < MT && p < P && p2 < P) {
+        const float2 x = U[p * P + p2], y = U[p2 * P + p];
+        const float hr = 0.5f * (x.x + y.x), hm = 0.5f * (x.y - y.y);
+        v = (s == t) ? hr : (s == 0 ? -hm : hm);
+      }
+      typename Half<BF>::T h, l;
+      split_half<BF>(v * sU, h, l);
+      hi[i] = h;
+      lo[i] = l;
+    }
+    frag[(size_t)(2 * f) * 64 + lane] = hi;
+    frag[(size_t)(2 * f + 1) * 64 + lane] = lo;
+  }
+}
+
+template <int RPW, bool BF, class Epi>
+__global__ __launch_bounds__(256) void beam_h16_kernel(const typename Half<BF>::V* __restrict__ frag, int MT, int KC,
+                                                       const float* __restrict__ scale, float sB, Tables tab,
+                                                       const int* skip, Epi epi) {
+  typedef typename Half<BF>::V V;
+  typedef typename Half<BF>::T T;
+  constexpr int NT = big_nt(RPW);
+  if (skip && *skip) return;
+  __shared__ float gsum[4][NT * 16];
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int w = threadIdx.x >> 6;
+  const int Q = tab.Q, nl = tab.nl, nm = tab.nm, Pp = tab.Pp;
+  const int ntiles = (Q + 15) >> 4;
+  const float inv = 1.f / ((scale ? *scale : 1.f) * sB);
+  epi.init();
+  for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
+    const float2* el[NT];
+    const float2* em[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
+      const int im = pix / nl, il = pix - im * nl;
+      el[t] = tab.El + il;
+      em[t] = tab.Em + im;
+    }
+    v4f acc[RPW][NT];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const V* fw = frag + (size_t)(2 * w * KC) * 64 + lane;  // row tile w, chunk 0, high half
+    const size_t rstep = (size_t)4 * KC * 2 * 64;          // next row tile of this wave
+    for (int c = 0; c < KC; ++c) {
+      V bh[NT], bl[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ant = min(16 * c + 4 * g + u, Pp - 1);  // beyond P: zero columns of Ut
+          const float2 a = cmul(el[t][(size_t)ant * nl], em[t][(size_t)ant * nm]);
+          T h, l;
+          split_half<BF>(a.x * sB, h, l);
+          bh[t][2 * u] = h;
+          bl[t][2 * u] = l;
+          split_half<BF>(a.y * sB, h, l);
+          bh[t][2 * u + 1] = h;
+          bl[t][2 * u + 1] = l;
+        }
+      }
+      V ah[RPW], al[RPW];
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        ah[i] = fw[i * rstep + (size_t)(2 * c) * 64];
+        al[i] = fw[i * rstep + (size_t)(2 * c + 1) * 64];
+      }
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          acc[i][t] = Half<BF>::mfma(ah[i], bh[t], acc[i][t]);
+          acc[i][t] = Half<BF>::mfma(ah[i], bl[t], acc[i][t]);
+          acc[i][t] = Half<BF>::mfma(al[i], bh[t], acc[i][t]);
+        }
+    }
+    float gp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      gp[t] = 0.f;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int m = w + 4 * i;
+        if (m < MT) {
+          const int a0i = 8 * m + 2 * g;
+          const float2 a0 = cmul(el[t][(size_t)a0i * nl], em[t][(size_t)a0i * nm]);
+          const float2 a1 = cmul(el[t][(size_t)(a0i + 1) * nl], em[t][(size_t)(a0i + 1) * nm]);
+          gp[t] += acc[i][t][0] * a0.x + acc[i][t][1] * a0.y + acc[i][t][2] * a1.x + acc[i][t][3] * a1.y;
+        }
+      }
+      gp[t] += __shfl_xor(gp[t], 16, 64);
+      gp[t] += __shfl_xor(gp[t], 32, 64);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) gsum[w][16 * t + c16] = gp[t];
+    }
+    __syncthreads();
+    if (threadIdx.x < NT * 16) {
+      const int t = threadIdx.x >> 4;
+      const int pix = 16 * (blk * NT + t) + (threadIdx.x & 15);
+      const float s4 = (gsum[0][threadIdx.x] + gsum[1][threadIdx.x]) + (gsum[2][threadIdx.x] + gsum[3][threadIdx.x]);
+      epi(pix, s4 * inv, pix < Q);
+    }
+    __syncthreads();
+  }
+  epi.finish(blockIdx.x);
+}
+
 bool beam_fits(int P) { return pad_p(P) / 8 <= kBeamMaxMT; }
 
 constexpr int kBigMaxRPW = 9;  // up to 36 row tiles: P <= 288
@@ -511,6 +702,79 @@ hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const
     case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st);
     case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st);
     default: return launch_big(frag, tab, skip, BeamLambda{state, part, nullptr, 0}, st);
+  }
+}
+
+// ---- split half precision ----
+int beam_h16_chunks(int P) { return (2 * pad_p(P) + 31) / 32; }
+
+size_t beam_h16_frag_bytes(int P) {
+  const int MT = pad_p(P) / 8;
+  return (size_t)4 * big_rpw(MT) * beam_h16_chunks(P) * 2 * 64 * 16;
+}
+
+template <bool BF, class Epi>
+static hipError_t launch_h16(const void* frag, const float* scale, const Tables& tab, const int* skip, Epi epi,
+                             hipStream_t st) {
+  typedef typename Half<BF>::V V;
+  const int MT = tab.Pp / 8, KC = beam_h16_chunks(tab.Pp);
+  // steering entries scaled towards unit magnitude (|a_p| = P^-1/2): a power of two
+  int ex = 0;
+  (void)frexpf(sqrtf((float)tab.Pp), &ex);
+  const float sB = BF ? 1.f : ldexpf(1.f, ex - 1);
+  const V* f = static_cast<const V*>(frag);
+  const dim3 g(beam_big_grid(tab.Pp, tab.Q)), b(256);
+  switch (big_rpw(MT)) {
+#define H16_CASE(R) \
+  case R: hipLaunchKernelGGL((beam_h16_kernel<R, BF, Epi>), g, b, 0, st, f, MT, KC, scale, sB, tab, skip, epi); break;
+    H16_CASE(1)
+    H16_CASE(2)
+    H16_CASE(3)
+    H16_CASE(4)
+    H16_CASE(5)
+    H16_CASE(6)
+    H16_CASE(7)
+    H16_CASE(8)
+    H16_CASE(9)
+#undef H16_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, float* scale, hipStream_t st) {
+  const int MT = pad_p(P) / 8, KC = beam_h16_chunks(P);
+  if (!bf16) {
+    hipLaunchKernelGGL(beam_h16_scale_kernel, dim3(1), dim3(1024), 0, st, U, P * P, scale);
+  }
+  const int total = 4 * big_rpw(MT) * KC * 64;
+  const int g = std::min((total + 255) / 256, 4096);
+  if (bf16)
+    hipLaunchKernelGGL(beam_prep_h16_kernel<true>, dim3(g), dim3(256), 0, st, U, P, MT, KC, (const float*)nullptr,
+                       static_cast<v8b*>(frag));
+  else
+    hipLaunchKernelGGL(beam_prep_h16_kernel<false>, dim3(g), dim3(256), 0, st, U, P, MT, KC, (const float*)scale,
+                       static_cast<v8h*>(frag));
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* scale, const Tables& tab,
+                           const int* skip, float* out, float* eps, float eps_scale, double C, double kb, float sc,
+                           const uint8_t* state, uint64_t* part, hipStream_t st) {
+  const float* s = bf16 ? nullptr : scale;
+  switch (kind) {
+    case 0:
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st)
+                  : launch_h16<false>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st);
+    case 1:
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st)
+                  : launch_h16<false>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st);
+    case 2:
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamStore{out, sc}, st)
+                  : launch_h16<false>(frag, s, tab, skip, BeamStore{out, sc}, st);
+    default:
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st)
+                  : launch_h16<false>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st);
   }
 }
 

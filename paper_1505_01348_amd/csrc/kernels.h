@@ -311,6 +311,14 @@ hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
                            hipStream_t st);
+// the same full-grid products in split half precision (FP16 with power-of-two
+// scaling, or BF16): fragments and scale prepared by launch_beam_prep_h16
+int beam_h16_chunks(int P);
+size_t beam_h16_frag_bytes(int P);
+hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, float* scale, hipStream_t st);
+hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* scale, const Tables& tab,
+                           const int* skip, float* out, float* eps, float eps_scale, double C, double kb, float sc,
+                           const uint8_t* state, uint64_t* part, hipStream_t st);
 // lsqr_cu.hip
 bool lsqr_cu_fits(int P, int n);
 hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st);

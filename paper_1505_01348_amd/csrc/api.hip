@@ -724,7 +724,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
     ST_TRY(ensure(c, c->bpart0, nb));
     ST_TRY(ensure(c, c->bpart1, nb));
   }
-  ST_TRY(ensure(c, c->alpha_part, (size_t)(Q / 32 + 64) * sizeof(double)));
+  ST_TRY(ensure(c, c->alpha_part, (size_t)(Q / 16 + 64) * sizeof(double)));  // one per 16-pixel tile
 
   // PWLS runs on the device-resident loop only (P <= 48)
   const bool pwls = o->cost == CLSIMG_COST_PWLS;

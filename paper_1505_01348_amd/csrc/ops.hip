@@ -514,12 +514,19 @@ int adjoint_tile_width(int MT) { return (MT > 12 && MT <= 24) ? 32 : 64; }
 
 // Narrow tiles (two waves split the rows, T = 32) for the small free sets of
 // the LSQR subproblems when the row tiles divide evenly.
+// For 7..12 row tiles the four waves split the rows (three tiles each) over
+// 16-pixel tiles, so that even small free sets spread over several CUs.
 int adjoint_lsqr2_tile_width(int MT, int n) {
+  if (MT > 6 && MT <= 12) return 16;
   return (MT <= 6 && n <= 1024) ? 32 : adjoint_tile_width(MT);
 }
 
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st) {
   if (pr.n <= 0) return hipSuccess;
+  if (pr.MT > 6 && pr.MT <= 12) {
+    hipLaunchKernelGGL((adjoint_kernel<3, 1, 4, EpiLsqrV2>), dim3((pr.n + 15) / 16), dim3(kThreads), 0, st, pr, epi);
+    return hipGetLastError();
+  }
   if (adjoint_lsqr2_tile_width(pr.MT, pr.n) == 32 && pr.MT <= 6) {
     const int ntiles = (pr.n + 31) / 32;
     if (pr.MT <= 3)

@@ -44,6 +44,8 @@ WORKLOADS = {
           "log-U[0.1,100] + 2 Gaussian blobs FWHM 6 px, noise 10, N=16384 samples",
     "c2": "P=96 random planar array (radius 150 lambda), Q=256x256 over |l|,|m|<=0.7, 200 point "
           "sources S^-1.5 on [0.5,500], noise 50, N=65536 samples",
+    "c4": "P=288 random planar array (radius 400 lambda), Q=512x512 over |l|,|m|<=0.7, 1000 point "
+          "sources S^-1.5 on [1,1000] + 10 Gaussian blobs FWHM 6 px, noise 100, N=262144 samples",
 }
 
 
@@ -57,6 +59,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--max-outer", type=int, default=-1,
+                    help="stop every solve (GPU and oracle) after this many Table I steps: the "
+                         "288-antenna workload is measured on its first steps")
     ap.add_argument("--tol", type=float, default=1e-7, help="LSQR atol = btol")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--kernel-reps", type=int, default=200)
@@ -107,8 +112,8 @@ def measured_traffic():
     return None
 
 
-def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls", bound="mvdr", kappa_b=0.0):
-    """Time full oracle solves of the same workload on the host (bounded sample)."""
+def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls", bound="mvdr", kappa_b=0.0, max_outer=-1):
+    """Time oracle solves of the same workload on the host (bounded sample)."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -124,10 +129,12 @@ def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls", bound="mvdr", kappa_b
         if cost == "pwls":
             _, h = oracle.pwls_scaling(A, R)
             eps = oracle.pwls_threshold(h, 6.0, sc.N, sc.P)
-            res = oracle.solve_pwls(A, R, R - np.diag(nd), gamma, eps, atol=tol_oracle, btol=tol_oracle)
+            res = oracle.solve_pwls(A, R, R - np.diag(nd), gamma, eps, atol=tol_oracle, btol=tol_oracle,
+                                    max_outer=max_outer)
         else:
             eps = oracle.detection_threshold(mf, 6.0, sc.N)
-            res = oracle.solve(A, R - np.diag(nd), gamma, eps, atol=tol_oracle, btol=tol_oracle)
+            res = oracle.solve(A, R - np.diag(nd), gamma, eps, atol=tol_oracle, btol=tol_oracle,
+                               max_outer=max_outer)
         t_total += time.perf_counter() - t0
         runs += 1
         log(f"cpu baseline: oracle solve {runs} done, {t_total:.1f} s")
@@ -135,8 +142,9 @@ def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls", bound="mvdr", kappa_b
             break
     threads = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
     cores = max(threads) if threads else 1
+    what = "full" if max_outer < 0 else f"first-{max_outer}-step"
     return {"value": runs / t_total, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{runs} full FP64 oracle solves of the same workload ({t_total:.1f} s)"}, res
+            "sample": f"{runs} {what} FP64 oracle solves of the same workload ({t_total:.1f} s)"}, res
 
 
 def serve_bench(args, clsimg, synth, np, torch):
@@ -287,6 +295,7 @@ def main():
     opts.bound = {"mvdr": clsimg.BOUND_MVDR, "mf": clsimg.BOUND_MF, "none": clsimg.BOUND_NONE}[args.bound]
     opts.kappa_b = args.kappa_b
     opts.precision = PRECISIONS[args.precision]
+    opts.max_outer = args.max_outer
     R = torch.as_tensor(sc.R_hat32).cuda()
     nd = torch.as_tensor(sc.noise_diag.astype(np.float32)).cuda()
     Q = sc.Q
@@ -371,7 +380,14 @@ def main():
     t_kernel = ev0.elapsed_time(ev1) / 1e3 / reps
     kflops = 8.0 * P * P * Q + 8.0 * P * Q  # dense count of one full-grid adjoint
     MT = -(-P // 8)
-    exec_flops = (-(-Q // 16)) * 2 * MT * (MT + 1) * 2048.0  # MFMAs the kernel issues (block triangle)
+    if MT <= 6:  # register-resident kernel: block triangle of Ut, each off-diagonal block used twice
+        kname = f"beam_kernel<{MT}, BeamMF> (dirty image, full grid)"
+        exec_flops = (-(-Q // 16)) * 2 * MT * (MT + 1) * 2048.0
+    else:  # GEMM-shaped kernel: every row tile (padded to 4 per wave group) against K = 2 Pp
+        rpw = -(-MT // 4)
+        nt = 2 if rpw <= 4 else 4
+        kname = f"beam_prep_full + beam_big_kernel<{rpw}, BeamMF> (dirty image, full grid)"
+        exec_flops = 2.0 * (64 * rpw) * (16 * MT) * (-(-Q // (16 * nt)) * 16 * nt)
     achieved = kflops / t_kernel / 1e12
     log(f"bench: beam kernel {t_kernel * 1e6:.2f} us/launch ({timing}), {achieved:.2f} TFLOP/s dense count, "
         f"{exec_flops / t_kernel / 1e12:.2f} TFLOP/s issued MFMA")
@@ -436,7 +452,7 @@ def main():
         "dtype": {"fp32": "f32", "fp16": "f16 split halves + f32", "bf16": "bf16 split halves + f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "cost": args.cost, "bound": args.bound,
-                   "precision": args.precision,
+                   "precision": args.precision, "max_outer": args.max_outer,
                    "kappa_b": args.kappa_b, "P": P, "Q": Q, "batch": B,
                    "nsamples": sc.N, "n_sources": int(len(sc.src_pix)), "lsqr_tol": args.tol,
                    "contractions": "fp32 MFMA 16x16x4, fp64 Cholesky and LSQR scalars"},
@@ -446,10 +462,11 @@ def main():
         "psi_mfma_frac": round(psi_tflops / PEAK_FP32_MFMA_TFLOPS, 5),
         "solve": {k: stats[k] for k in ("status", "outer_iters", "adds", "drops", "lsqr_iters_total",
                                         "nF", "nU", "rel_residual")},
-        "roofline": {"kernel": "beam_kernel<MF> (dirty image, full grid)",
+        "roofline": {"kernel": kname,
                      "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 5),
-                     "traffic": measured_traffic(), "us_per_launch": round(t_kernel * 1e6, 3), "timing": timing,
+                     "traffic": measured_traffic() if args.config == "c1" else None,
+                     "us_per_launch": round(t_kernel * 1e6, 3), "timing": timing,
                      "flops_per_launch": kflops, "mfma_issued_flops_per_launch": exec_flops,
                      "mfma_issued_frac": round(exec_flops / t_kernel / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5)},
     }
@@ -460,7 +477,8 @@ def main():
                            "latency": "p50/p99 are of one batched call (all B requests)",
                            "solve": "request 0's statistics; psi_tflops counts all requests"}
     if not args.no_cpu:
-        base, ref = cpu_baseline(sc, tol_oracle=1e-8, cost=args.cost, bound=args.bound, kappa_b=args.kappa_b)
+        base, ref = cpu_baseline(sc, tol_oracle=1e-8, cost=args.cost, bound=args.bound, kappa_b=args.kappa_b,
+                                 max_outer=args.max_outer)
         result["cpu_baseline"] = base
         s = sigma.cpu().numpy().astype(np.float64)
         st = state.cpu().numpy()

@@ -83,10 +83,20 @@ struct DeviceGuard {
   }
 };
 
-#define HIP_TRY(expr)                               \
-  do {                                              \
-    hipError_t e_ = (expr);                         \
-    if (e_ != hipSuccess) return CLSIMG_EHIP;       \
+// CLSIMG_VERBOSE=1: a failing HIP call names itself on stderr
+int hip_failed(hipError_t e, int line) {
+  static const bool verbose = [] {
+    const char* v = getenv("CLSIMG_VERBOSE");
+    return v && v[0] == '1';
+  }();
+  if (verbose) fprintf(stderr, "clsimg: %s (api.hip line %d)\n", hipGetErrorString(e), line);
+  return CLSIMG_EHIP;
+}
+
+#define HIP_TRY(expr)                                    \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_failed(e_, __LINE__); \
   } while (0)
 
 #define ST_TRY(expr)                  \
@@ -574,8 +584,10 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   const char* mf_ = getenv("CLSIMG_OUTER_MAXF");
   if (mf_) c->outer_max_f = atoi(mf_);
   void* hp = nullptr;
+  // room for the norm partials of the largest array (reduce_blocks grows as P^2)
+  const int nnorm = reduce_blocks(CLSIMG_MAX_P);
   const size_t hbytes =
-      sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + 64 * sizeof(double) + sizeof(OuterState);
+      sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + nnorm * sizeof(double) + sizeof(OuterState);
   if (hipHostMalloc(&hp, hbytes, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
     if (hp) (void)hipHostFree(hp);
@@ -588,7 +600,7 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   c->h_status = reinterpret_cast<int*>(b + sizeof(SolveDecision) + sizeof(LsqrState));
   c->h_norms = reinterpret_cast<double*>(b + sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int));
   c->h_outer = reinterpret_cast<OuterState*>(b + sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) +
-                                             64 * sizeof(double));
+                                             nnorm * sizeof(double));
   *out = c;
   return CLSIMG_OK;
 }

@@ -124,3 +124,29 @@ def test_solve_96_antennas_matches_oracle(gpu_lib, ctx, big):
     print("gpu stats", stats, "oracle outer", ref.outer_iters, flush=True)
     np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
     _assert_close(sigma.cpu().numpy(), ref.sigma, what="solve sigma c2")
+
+
+def test_solve_288_antennas_first_ten_steps(gpu_lib, ctx, big):
+    # the full 288-antenna solve takes about a thousand Table I steps (each a
+    # 174 GFLOP gradient in FP64 on the host); the state after the first ten
+    # is compared instead, at full size
+    sc = big["c4"]
+    print("case solve c4 (P=288, Q=512^2), first 10 Table I steps, against the oracle", flush=True)
+    A = oracle.steering(sc.pos, sc.lam, sc.grid)
+    R = sc.R_hat32_c128
+    nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
+    ref = oracle.solve(A, R - np.diag(nd), oracle.upper_bound(A, R),
+                       oracle.detection_threshold(oracle.mf_image(A, R), 6.0, sc.N),
+                       atol=1e-8, btol=1e-8, max_outer=10)
+    del A
+    opts = gpu_lib.default_options()
+    opts.nsamples = sc.N
+    opts.atol = opts.btol = 1e-7
+    opts.max_outer = 10
+    sigma, state, _, _, stats = ctx.solve(torch.as_tensor(sc.R_hat32).cuda(),
+                                          gpu_lib.Geometry(sc.pos, sc.lam, sc.grid), opts,
+                                          noise_diag=torch.as_tensor(nd.astype(np.float32)).cuda())
+    print("gpu stats", stats, "oracle outer", ref.outer_iters, "adds", ref.adds, flush=True)
+    assert stats["status"] == gpu_lib.WMAXOUTER and stats["outer_iters"] == ref.outer_iters == 10
+    np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
+    _assert_close(sigma.cpu().numpy(), ref.sigma, what="solve sigma c4, 10 steps")

@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=16, help="Table I steps per server poll")
     ap.add_argument("--serve-workers", type=int, default=4, help="server threads for P > 48 requests")
+    ap.add_argument("--batched-extra", type=int, default=16,
+                    help="after the timed solves, also time batched calls of this many requests of the "
+                         "workload (reported under 'batched'; 0 = skip)")
     ap.add_argument("--batch", type=int, default=1,
                     help="solve B independent requests of the workload per step (one batched call); "
                          "request 0 is the workload itself, the others redraw its sky and samples")
@@ -347,6 +350,36 @@ def main():
         sequential = B / (time.perf_counter() - t0)
         log(f"bench: the {B} requests solved one by one: {sequential:.2f} solves/s")
 
+    batched = None
+    if B == 1 and args.batched_extra > 1 and sc.P <= 48:
+        # the same workload served as batches (clsimg_solve_batch): request 0 is
+        # this covariance, the others redraw sky and samples with other seeds
+        nbx = args.batched_extra
+        breqs = [{"R": R, "geo": geo, "noise_diag": nd}]
+        for k in range(1, nbx):
+            sk = synth.make_scene(args.config, seed=synth.scenes._SEED_BASE + 1000 * k)
+            breqs.append({"R": torch.as_tensor(sk.R_hat32).cuda(), "geo": clsimg.Geometry(sk.pos, sk.lam, sk.grid),
+                          "noise_diag": torch.as_tensor(sk.noise_diag.astype(np.float32)).cuda()})
+        st0, res0 = ctx.solve_batch(breqs, opts)  # warm-up
+        torch.cuda.synchronize()
+        blat = []
+        tb0 = time.perf_counter()
+        for _ in range(3):
+            t0 = time.perf_counter()
+            stb, resb = ctx.solve_batch(breqs, opts)
+            torch.cuda.synchronize()
+            blat.append(time.perf_counter() - t0)
+        tbt = time.perf_counter() - tb0
+        same0 = (resb[0][4]["rel_residual"] == stats["rel_residual"] and
+                 resb[0][4]["lsqr_iters_total"] == stats["lsqr_iters_total"])
+        batched = {"requests_per_call": nbx, "solves_per_s": round(3 * nbx / tbt, 3),
+                   "ms_per_call_p50": round(float(np.percentile(np.array(blat) * 1e3, 50)), 3),
+                   "request0_same_as_alone": bool(same0 and stb >= 0),
+                   "note": "clsimg_solve_batch: one outer-step launch and one multiplier launch per Table I "
+                           "step for all requests; every result equals its solve alone"}
+        log(f"bench: batched {nbx} per call: {batched}")
+        del breqs
+
     # roofline of the full-grid beamforming kernel: the dirty image is one
     # launch of it.  The calls are captured into a graph and replayed, so the
     # events see back-to-back kernels rather than the host's call overhead.
@@ -472,6 +505,8 @@ def main():
     }
     if big is not None:
         result["roofline_full_size"] = big
+    if batched is not None:
+        result["batched"] = batched
     if sequential is not None:
         result["batch"] = {"requests": B, "solves_per_s_one_by_one": round(sequential, 4),
                            "latency": "p50/p99 are of one batched call (all B requests)",

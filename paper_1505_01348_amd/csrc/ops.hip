@@ -218,6 +218,75 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
 }
 
 // ---------------------------------------------------------------------------
+// Beamforming of a free list for 7..12 row tiles (LSQR adjoint): one 16-pixel
+// tile per workgroup; wave w takes row tiles w, w + 4, w + 8 over the whole K
+// and issues every fragment load (Ut fragments prepared by the correlation)
+// and every load of its pixel's column of X_F before the first MFMA, so that
+// the K loop costs one round trip to memory instead of staged LDS chunks.  The
+// waves' column dots meet in LDS.  Row tiles past MT are loaded clamped and
+// left out of the dot.
+template <int MT, class Epi>
+__global__ __launch_bounds__(kThreads) void adjoint_list_kernel(AdjParams pr, Epi epi) {
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
+  const typename Epi::Ctx cx = epi.init();
+  if (stop) return;
+  constexpr int KS = 4 * MT, RPW = (MT + 3) / 4, Pp = 8 * MT;
+  __shared__ float gsh[4][16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int tile = blockIdx.x, n = pr.n;
+  const float* xc = pr.xf + (size_t)min(16 * tile + c16, n - 1) * 2 * Pp;
+  float b[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) b[k] = xc[4 * k + q];
+  float a[RPW][KS];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const float* fm = pr.frag + (size_t)min(w + 4 * i, MT - 1) * KS * 64 + lane;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) a[i][k] = fm[k * 64];
+  }
+  v4f acc[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < KS; ++k) acc[i] = mfma16x16x4(a[i][k], b[k], acc[i]);
+  }
+  // column dot: accumulator element r of row tile m is row 16m + 4q + r
+  float gp = 0.f;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int m = w + 4 * i;
+    if (m < MT) {
+      const float4 x = *reinterpret_cast<const float4*>(xc + 16 * m + 4 * q);
+      gp += x.x * acc[i][0] + x.y * acc[i][1] + x.z * acc[i][2] + x.w * acc[i][3];
+    }
+  }
+  gp += __shfl_xor(gp, 16, 64);
+  gp += __shfl_xor(gp, 32, 64);
+  if (q == 0) gsh[w][c16] = gp;
+  __syncthreads();
+  const int col = 16 * tile + tid;
+  const typename Epi::Pre pf = epi.prefetch(col, tid < 16 && col < n);
+  float g = 0.f;
+  bool ok = false;
+  int pix = 0;
+  if (tid < 16) {
+    g = (gsh[0][tid] + gsh[1][tid]) + (gsh[2][tid] + gsh[3][tid]);
+    ok = col < n;
+    if (ok) {
+      pix = pr.idx ? pr.idx[col] : col;
+      if ((unsigned)pix >= (unsigned)pr.tab.Q) {  // invalid pixel index: NaN output
+        pix = 0;
+        g = __builtin_nanf("");
+      }
+    }
+  }
+  epi(tile, col, pix, g, ok, cx, pf);
+}
+
+// ---------------------------------------------------------------------------
 // Correlation: partial G = X_S diag(v) X_S^T over a chunk of pixels per wave.
 // Partial tile layout: part[((chunk*MT + mt)*MT + nt)*256 + lane*4 + r]
 //                      = G[16mt + 4q + r][16nt + c16].
@@ -524,7 +593,19 @@ int adjoint_lsqr2_tile_width(int MT, int n) {
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st) {
   if (pr.n <= 0) return hipSuccess;
   if (pr.MT > 6 && pr.MT <= 12) {
-    hipLaunchKernelGGL((adjoint_kernel<3, 1, 4, EpiLsqrV2>), dim3((pr.n + 15) / 16), dim3(kThreads), 0, st, pr, epi);
+    const dim3 g((pr.n + 15) / 16), b(kThreads);
+    if (pr.xf && pr.frag && !pr.U) {
+      switch (pr.MT) {
+        case 7: hipLaunchKernelGGL((adjoint_list_kernel<7, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
+        case 8: hipLaunchKernelGGL((adjoint_list_kernel<8, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
+        case 9: hipLaunchKernelGGL((adjoint_list_kernel<9, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
+        case 10: hipLaunchKernelGGL((adjoint_list_kernel<10, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
+        case 11: hipLaunchKernelGGL((adjoint_list_kernel<11, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
+        default: hipLaunchKernelGGL((adjoint_list_kernel<12, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
+      }
+    } else {
+      hipLaunchKernelGGL((adjoint_kernel<3, 1, 4, EpiLsqrV2>), g, b, 0, st, pr, epi);
+    }
     return hipGetLastError();
   }
   if (adjoint_lsqr2_tile_width(pr.MT, pr.n) == 32 && pr.MT <= 6) {

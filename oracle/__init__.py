@@ -17,6 +17,9 @@ active_set  the active-set solver of Table I with the detection threshold
             (Sec. III)
 pwls        the constrained preconditioned weighted LS problem (eq. preWLS)
             as the LS problem on whitened, D-scaled inputs
+multi       K covariance blocks over one grid (Earth-rotation snapshots or
+            frequency channels, eq. vectRtotal): MF / MVDR images, bounds,
+            thresholds and the stacked solve (eqs. mfdimg, wmvdr, App. A)
 
 Pins (what the oracle is checked against, in tests/test_oracle_*.py): the
 Kronecker/Khatri-Rao identities of the Notation section against an explicitly
@@ -33,7 +36,11 @@ whitening against the R^-1/2 weighting from an eigendecomposition, the
 transformed operators against the dense weighted Khatri-Rao matrix, the
 gradient at zero against the unbiased MVDR image from R^-1, the box solution
 against BVLS with KKT, bound pixels at gamma in image units, and the
-threshold's MVDR standard deviation against a Monte Carlo.
+threshold's MVDR standard deviation against a Monte Carlo.  K blocks
+(tests/test_oracle_multi.py): the stacked solve against BVLS on the dense
+stacked Psi with KKT, K identical blocks against the single-block problem,
+the MVDR <= MF ordering and the ASSC lower bound, both App. A variances
+against Monte Carlo, and adjointness of the stacked operators.
 """
 
 from .imaging import (  # noqa: F401
@@ -50,3 +57,12 @@ from .imaging import (  # noqa: F401
 from .lsqr import lsqr, LsqrResult  # noqa: F401
 from .active_set import solve, SolveResult, STATE_L, STATE_F, STATE_U  # noqa: F401
 from .pwls import pwls_problem, pwls_scaling, pwls_threshold, solve_pwls, whitening_factor  # noqa: F401
+from .multi import (  # noqa: F401
+    steering_blocks,
+    mf_image_multi,
+    mf_std_multi,
+    mvdr_powers,
+    upper_bound_multi,
+    detection_threshold_multi,
+    solve_multi,
+)

@@ -5,7 +5,10 @@ Test infrastructure only (see the package docstring).
 Problem (eq. CLS, K = 1):  ``min 1/2 ||B0 - sum_i sigma_i a_i a_i^H||_F^2``
 subject to ``0 <= sigma <= gamma``, where ``B0 = R_hat - diag(noise)`` (the
 data model of eq. vectRImg with the receiver-noise term moved to the data side;
-``noise = 0`` ignores it as in eq. UCLS).
+``noise = 0`` ignores it as in eq. UCLS).  With K blocks (``A`` and ``B0``
+given as lists, eq. vectRtotal) the cost is ``1/(2K) sum_k ||B0_k -
+A_k diag(sigma) A_k^H||_F^2`` (eq. UCLS): the subproblems are LSQR on the
+stacked blocks and the gradient is ``(1/K) sum_k vectdiag(A_k^H E_k A_k)``.
 
 The iteration follows the active-set template of Sec. III-C (Table I):
 
@@ -86,7 +89,28 @@ def solve(A, B0, gamma, eps, atol=1e-8, btol=1e-8, conlim=1e8, itnlim=-1, max_ou
     ``itnlim = -1`` means ``4 |F| + 100`` per subproblem, ``max_outer = -1``
     means ``4 Q`` subproblem solves.
     """
-    Q = A.shape[1]
+    if isinstance(A, (list, tuple)):  # K blocks over one pixel grid
+        As = list(A)
+        B0 = np.stack([np.asarray(b, dtype=np.complex128) for b in B0])
+        K = len(As)
+
+        def fwd(S, v):
+            return np.stack([forward(Ak[:, S], v) for Ak in As])
+
+        def adj(S, U):
+            return sum(adjoint(Ak[:, S], U[k]) for k, Ak in enumerate(As))
+
+        Q = As[0].shape[1]
+    else:
+        K = 1
+
+        def fwd(S, v):
+            return forward(A[:, S], v)
+
+        def adj(S, U):
+            return adjoint(A[:, S], U)
+
+        Q = A.shape[1]
     gamma = np.asarray(gamma, dtype=np.float64)
     eps = np.asarray(eps, dtype=np.float64)
     if max_outer < 0:
@@ -111,10 +135,9 @@ def solve(A, B0, gamma, eps, atol=1e-8, btol=1e-8, conlim=1e8, itnlim=-1, max_ou
                 break
             F = np.nonzero(state == STATE_F)[0]
             U = np.nonzero(state == STATE_U)[0]
-            A_F = A[:, F]
-            Bb = B0 - forward(A[:, U], gamma[U])
+            Bb = B0 - fwd(U, gamma[U])
             lim = 4 * F.size + 100 if itnlim < 0 else itnlim
-            res = lsqr(lambda v: forward(A_F, v), lambda u: adjoint(A_F, u), Bb, F.size,
+            res = lsqr(lambda v: fwd(F, v), lambda u: adj(F, u), Bb, F.size,
                        atol=atol, btol=btol, conlim=conlim, itnlim=lim)
             lsqr_total += res.itn
             if res.istop == 7:
@@ -131,8 +154,8 @@ def solve(A, B0, gamma, eps, atol=1e-8, btol=1e-8, conlim=1e8, itnlim=-1, max_ou
                 if act.size == 0:
                     break
                 S = np.nonzero(state != STATE_L)[0]
-                E = forward(A[:, S], sigma[S]) - B0
-                g = adjoint(A[:, act], E)
+                E = fwd(S, sigma[S]) - B0
+                g = adj(act, E) / K
                 lam = np.where(state[act] == STATE_L, g, -g)
                 k = int(np.argmin(lam))          # first occurrence = lowest index
                 lam_min, i_min = float(lam[k]), int(act[k])
@@ -171,7 +194,7 @@ def solve(A, B0, gamma, eps, atol=1e-8, btol=1e-8, conlim=1e8, itnlim=-1, max_ou
     if status == STATUS_OK and itnlim_hits:
         status = STATUS_ITNLIM
     S = np.nonzero(state != STATE_L)[0]
-    Rres = B0 - forward(A[:, S], sigma[S])
+    Rres = B0 - fwd(S, sigma[S])
     bn = math.sqrt(float(np.sum(np.abs(B0) ** 2)))
     rn = math.sqrt(float(np.sum(np.abs(Rres) ** 2)))
     return SolveResult(sigma=sigma, state=state, status=status, outer_iters=outer, adds=adds,

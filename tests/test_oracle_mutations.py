@@ -18,8 +18,10 @@ oas = importlib.import_module("oracle.active_set")
 oim = importlib.import_module("oracle.imaging")
 olsqr = importlib.import_module("oracle.lsqr")  # the package re-exports a function of that name
 opw = importlib.import_module("oracle.pwls")
+omu = importlib.import_module("oracle.multi")
 from tests import test_oracle_pins as pins
 from tests import test_oracle_pwls as ppins
+from tests import test_oracle_multi as mpins
 
 PINS = [
     pins.test_steering_matches_entrywise_model_and_is_unit_norm,
@@ -49,6 +51,11 @@ PINS = [
     lambda: ppins.test_box_pwls_matches_bvls_and_kkt("mvdr"),
     ppins.test_threshold_std_matches_monte_carlo_of_mvdr_image,
     ppins.test_upper_set_pixels_sit_at_the_image_bound,
+    mpins.test_identical_blocks_equal_the_single_block_problem,
+    mpins.test_stacked_solve_matches_bvls_and_kkt,
+    mpins.test_stacked_solve_matches_brute_force_on_a_tiny_grid,
+    mpins.test_mvdr_between_assc_and_mf,
+    mpins.test_app_a_variances_match_monte_carlo,
 ]
 
 MUTATIONS = [
@@ -73,9 +80,19 @@ MUTATIONS = [
      "v = np.asarray(rmatvec(u), dtype=np.float64) - alpha * v"),
     (oas, "lam = np.where(state[act] == STATE_L, g, -g)", "lam = np.where(state[act] == STATE_L, g, g)"),
     (oas, "sigma[ib], state[ib] = gamma[ib], STATE_U", "sigma[ib], state[ib] = 0.0, STATE_U"),
-    (oas, "Bb = B0 - forward(A[:, U], gamma[U])", "Bb = B0"),
+    (oas, "Bb = B0 - fwd(U, gamma[U])", "Bb = B0"),
     (oas, "k = int(np.argmin(lam))", "k = int(np.argmax(lam))"),
-    (oas, "E = forward(A[:, S], sigma[S]) - B0", "E = B0 - forward(A[:, S], sigma[S])"),
+    (oas, "E = fwd(S, sigma[S]) - B0", "E = B0 - fwd(S, sigma[S])"),
+    (oas, "g = adj(act, E) / K", "g = adj(act, E)"),
+    (oas, "return sum(adjoint(Ak[:, S], U[k]) for k, Ak in enumerate(As))",
+     "return sum(adjoint(Ak[:, S], U[0]) for k, Ak in enumerate(As))"),
+    (omu, "return sum(adjoint(A, np.asarray(R, np.complex128)) for A, R in zip(As, Rs)) / K",
+     "return sum(adjoint(A, np.asarray(R, np.complex128)) for A, R in zip(As, Rs))"),
+    (omu, "return np.sqrt(sq / nsamples) / K", "return np.sqrt(sq / nsamples) / math.sqrt(K)"),
+    (omu, "g = C * K / s1", "g = C / s1"),
+    (omu, "g = g + kappa_b * K * np.sqrt(s2) / (math.sqrt(nsamples - P - 1) * s1 * s1)",
+     "g = g + kappa_b * np.sqrt(s2) / (math.sqrt(nsamples - P - 1) * s1 * s1)"),
+    (omu, "return sum(hs), sum(h * h for h in hs)", "return sum(hs), sum(hs) ** 2"),
     (oas, "if lam_min < -thr:", "if lam_min < thr:"),
     (opw, "return h * h / C, h", "return h / C, h"),
     (opw, "Ahat = (Linv @ A) / np.sqrt(D)[None, :]", "Ahat = (Linv @ A) / D[None, :]"),
@@ -101,7 +118,8 @@ def _load_mutant(module, old, new):
 
 def _install(monkeypatch, module, mutant):
     names = [n for n in dir(module) if not n.startswith("__")]
-    targets = [oracle, oas] if module is not oas else [oracle]
+    # every module that imported the mutated functions by name
+    targets = [t for t in (oracle, oas, omu) if t is not module]
     for name in names:
         obj = getattr(mutant, name)
         if callable(obj) and getattr(obj, "__module__", None) == mutant.__name__:

@@ -217,6 +217,38 @@ typedef struct {
  * `reqs` is host memory (n entries); n >= 1. */
 int clsimg_solve_batch(clsimg_ctx* ctx, int32_t n, clsimg_request* reqs, const clsimg_opts* opts, void* stream);
 
+/* ---- K covariance blocks over one pixel grid ---------------------------
+ * Snapshots under the Earth's rotation (short-term integrations k whose
+ * antenna positions are rotated, Q_k in the data model of Sec. II) or
+ * frequency channels with the same sky (another wavelength): the stacked
+ * data model of eq. vectRtotal / eq. blockdiagtilde. */
+#define CLSIMG_MAX_BLOCKS 64
+
+typedef struct {
+  const clsimg_c32* R;      /* DEVICE, P x P sample covariance of this block     */
+  clsimg_array array;       /* antenna positions of this block and wavelength    */
+  const float* noise_diag;  /* DEVICE, P, or NULL                                 */
+} clsimg_block;
+
+/* Active-set solve (Sec. III, Table I, LSQR of Sec. IV-A) of the K-block
+ * problem  min 1/(2K) sum_k ||R_k - diag(noise_k) - A_k diag(sigma) A_k^H||^2
+ * s.t. 0 <= sigma <= gamma (eq. UCLS with the box of eq. CLS), all blocks
+ * with the same P and the same options, on one grid:
+ *   mf[i]    = (1/K) sum_k a_{i,k}^H R_k a_{i,k}                  (eq. mfdimg)
+ *   gamma[i] = C K / sum_k h_{i,k} (+ kappa_b std, App. A), h = a^H R^-1 a
+ *              (eq. wmvdr); CLSIMG_BOUND_MF: mf + kappa_b std; _NONE: inf
+ *   eps[i]   = kappa_d sqrt(sum_k (a_{i,k}^H R_k a_{i,k})^2) / (K sqrt N)
+ *   gradient (1/K) sum_k vectdiag(A_k^H E_k A_k) for the release test.
+ * 1 <= K <= CLSIMG_MAX_BLOCKS; blocks: HOST array of K.  LS cost only
+ * (CLSIMG_COST_PWLS: CLSIMG_ENOTSUP).  Outputs and stats as clsimg_solve
+ * (sigma0/state0 are not taken: the solve starts from sigma = 0); stats
+ * rel_residual is over all blocks and objective is the cost above.
+ * Synchronises `stream`.  With K = 1 it solves the clsimg_solve problem on
+ * the host-driven loop. */
+int clsimg_solve_multi(clsimg_ctx* ctx, int32_t K, const clsimg_block* blocks, const clsimg_grid* grid,
+                       const clsimg_opts* opts, float* sigma, uint8_t* state, float* mf, float* gamma,
+                       clsimg_stats* stats, void* stream);
+
 /* ---- Serving: continuous batching of independent requests -------------
  * A server solves a stream of imaging requests (Sec. III, Table I, LSQR of
  * Sec. IV-A), each with its own array (any P <= CLSIMG_MAX_P), wavelength and

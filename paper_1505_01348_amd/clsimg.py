@@ -29,7 +29,7 @@ MAX_P = 288
 
 EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
             "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
-            "clsimg_solve_batch", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
+            "clsimg_solve_batch", "clsimg_solve_multi", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
             "clsimg_server_query", "clsimg_server_destroy", "clsimg_strerror")
 
 
@@ -64,6 +64,10 @@ class CRequest(C.Structure):
                 ("stats", CStats)]
 
 
+class CBlock(C.Structure):
+    _fields_ = [("R", C.c_void_p), ("array", CArray), ("noise_diag", C.c_void_p)]
+
+
 class CServerInfo(C.Structure):
     _fields_ = [("pending", C.c_int32), ("active", C.c_int32), ("worker_queued", C.c_int32),
                 ("ready", C.c_int32), ("submitted", C.c_int64), ("admitted", C.c_int64),
@@ -95,6 +99,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.clsimg_solve_batch.argtypes = [vp, i32, C.POINTER(CRequest), C.POINTER(COpts), vp]
     lib.clsimg_solve.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, C.POINTER(COpts),
                                  vp, vp, vp, vp, vp, vp, C.POINTER(CStats), vp]
+    lib.clsimg_solve_multi.argtypes = [vp, i32, C.POINTER(CBlock), C.POINTER(CGrid), C.POINTER(COpts), vp, vp,
+                                       vp, vp, C.POINTER(CStats), vp]
     lib.clsimg_server_create.argtypes = [C.POINTER(vp), i32, i32, sz, i32, i32, C.POINTER(COpts)]
     lib.clsimg_server_submit.argtypes = [vp, C.POINTER(CRequest), C.POINTER(C.c_int64)]
     lib.clsimg_server_poll.argtypes = [vp, i32, C.POINTER(C.c_int64), i32, C.POINTER(i32)]
@@ -303,6 +309,41 @@ class Context:
         out = {f: getattr(stats, f) for f, _ in CStats._fields_}
         return sigma, state, mf, gamma, out
 
+
+    def solve_multi(self, blocks, opts: Options, sigma=None, state=None, mf=None, gamma=None):
+        """K covariance blocks over one grid: blocks is a list of dicts with R,
+        geo (positions and wavelength of the block; every geo has the same
+        grid) and optional noise_diag.  Returns (sigma, state, mf, gamma, stats)."""
+        dev = self.device
+        K = len(blocks)
+        geo0 = blocks[0]["geo"]
+        Q = geo0.Q
+        arr = (CBlock * K)()
+        for k, b in enumerate(blocks):
+            geo = b["geo"]
+            if geo.grid != geo0.grid:
+                raise ValueError("every block must use the same pixel grid")
+            _need(b["R"], torch.complex64, geo.P * geo.P, "R", dev)
+            nd = b.get("noise_diag")
+            if nd is not None:
+                _need(nd, torch.float32, geo.P, "noise_diag", dev)
+            arr[k].R = b["R"].data_ptr()
+            arr[k].array = geo.c_array
+            arr[k].noise_diag = None if nd is None else nd.data_ptr()
+        mk = lambda t, dt: torch.empty(Q, dtype=dt, device=f"cuda:{dev}") if t is None else t  # noqa: E731
+        sigma, state = mk(sigma, torch.float32), mk(state, torch.uint8)
+        mf, gamma = mk(mf, torch.float32), mk(gamma, torch.float32)
+        for t, dt, name in ((sigma, torch.float32, "sigma"), (state, torch.uint8, "state"),
+                            (mf, torch.float32, "mf"), (gamma, torch.float32, "gamma")):
+            _need(t, dt, Q, name, dev)
+        st_c = CStats()
+        co = opts.to_c()
+        st = self._lib.clsimg_solve_multi(self._h, K, arr, C.byref(geo0.c_grid), C.byref(co), _ptr(sigma),
+                                          _ptr(state), _ptr(mf), _ptr(gamma), C.byref(st_c), _stream())
+        if st < 0:
+            self._check(st, "clsimg_solve_multi")
+        stats = {f: getattr(st_c, f) for f, _ in CStats._fields_}
+        return sigma, state, mf, gamma, stats
 
     def solve_batch(self, requests, opts: Options):
         """Batched solve of independent problems with the same P (each a dict with

@@ -66,6 +66,13 @@ struct clsimg_ctx {
   bool beam_prep = false;  // CLSIMG_BEAM_PREP=1: beamformer fragments from a separate pass
   bool host_loop = false;  // CLSIMG_HOST_LOOP=1: active-set loop driven from the host
   int prec = CLSIMG_FP32;  // arithmetic of the full-grid beamforming products of the current call
+  // K covariance blocks: per-block tables and vectors; tables_of() reads the
+  // override while a block's operators run
+  DevBuf mb_tab, mb_B0, mb_Bb, mb_u, mb_E, mb_frag, mb_acc, mb_acc2;
+  const float2* tab_El = nullptr;
+  const float2* tab_Em = nullptr;
+  double* h_mnorm = nullptr;  // pinned: the blocks' norm partials
+  size_t h_mnorm_n = 0;
   DevBuf frag_h, hscale;   // split half-precision fragments and their scale
   int outer_max_f = 1 << 30;  // CLSIMG_OUTER_MAXF: hand over to the host loop beyond this |F|
 };
@@ -172,8 +179,8 @@ int ensure_tables(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, hi
 
 Tables tables_of(clsimg_ctx* c, const clsimg_grid* g, int P) {
   Tables t;
-  t.El = P_<const float2>(c->El);
-  t.Em = P_<const float2>(c->Em);
+  t.El = c->tab_El ? c->tab_El : P_<const float2>(c->El);
+  t.Em = c->tab_Em ? c->tab_Em : P_<const float2>(c->Em);
   t.nl = g->nl;
   t.nm = g->nm;
   t.Pp = pad_p(P);
@@ -614,12 +621,14 @@ int clsimg_destroy(clsimg_ctx* c) {
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
                     &c->dec,  &c->status, &c->lsqr2, &c->done, &c->x1, &c->w1, &c->vraw,
-                    &c->bpart0, &c->bpart1, &c->xf, &c->bar};
+                    &c->bpart0, &c->bpart1, &c->xf, &c->bar, &c->frag_h, &c->hscale,
+                    &c->mb_tab, &c->mb_B0, &c->mb_Bb, &c->mb_u, &c->mb_E, &c->mb_frag, &c->mb_acc, &c->mb_acc2};
   for (DevBuf* d : bufs)
     if (d->ptr) (void)hipFree(d->ptr);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->h_dec) (void)hipHostFree(c->h_dec);
   if (c->h_batch) (void)hipHostFree(c->h_batch);
+  if (c->h_mnorm) (void)hipHostFree(c->h_mnorm);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   delete c;
   return CLSIMG_OK;
@@ -1208,6 +1217,307 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   stats->min_margin_lambda = margin_lambda;
   stats->min_margin_z = margin_z;
   stats->psi_flops = flops + corr_flops(P, nU) + corr_flops(P, nF);
+  return status;
+}
+
+// K covariance blocks over one grid (eq. vectRtotal): the host-driven
+// active-set loop of clsimg_solve with every operator applied per block --
+// the correlations give one matrix per block, the beamformer outputs are
+// summed over the blocks (stacked Khatri-Rao operator), and the images, the
+// bound and the multipliers come from the block sums (eqs. mfdimg, wmvdr,
+// App. A; gradient (1/K) sum_k, eq. UCLS).  LSQR runs on the stacked blocks
+// with the split-K correlation and the LDS-staged adjoint.
+namespace {
+struct TableOverride {
+  clsimg_ctx* c;
+  ~TableOverride() {
+    c->tab_El = nullptr;
+    c->tab_Em = nullptr;
+  }
+};
+}  // namespace
+
+int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, const clsimg_grid* g,
+                       const clsimg_opts* o, float* sigma, uint8_t* state, float* mf_out, float* gamma_out,
+                       clsimg_stats* stats, void* stream) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (!c || !blocks || K < 1 || K > CLSIMG_MAX_BLOCKS || !g || !sigma || !state || !stats) return CLSIMG_EINVAL;
+  const int P = blocks[0].array.P;
+  for (int k = 0; k < K; ++k) {
+    if (!blocks[k].R || blocks[k].array.P != P) return CLSIMG_EINVAL;
+    ST_TRY(check_geometry(&blocks[k].array, g));
+  }
+  ST_TRY(check_opts(o, P));
+  if (o->nsamples <= 0 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
+  if (o->cost != CLSIMG_COST_LS) return CLSIMG_ENOTSUP;
+  c->prec = o->precision;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  TableOverride restore{c};
+  const int Q = g->nl * g->nm, Pp = pad_p(P), MT = Pp / 8;
+  const int nl = g->nl, nm = g->nm;
+  ST_TRY(ensure_workspace(c, P, Q));
+  const int nbeta = reduce_blocks(P);
+  const size_t cx = (size_t)P * P * sizeof(float2);
+  const size_t tab_b = (size_t)Pp * (nl + nm) * sizeof(float2);
+  const size_t fru = (size_t)4 * Pp * Pp;  // fragment floats of one block's u
+  ST_TRY(ensure(c, c->mb_tab, K * tab_b));
+  ST_TRY(ensure(c, c->mb_B0, K * cx));
+  ST_TRY(ensure(c, c->mb_Bb, K * cx));
+  ST_TRY(ensure(c, c->mb_u, K * cx));
+  ST_TRY(ensure(c, c->mb_E, K * cx));
+  ST_TRY(ensure(c, c->mb_frag, K * fru * sizeof(float)));
+  ST_TRY(ensure(c, c->mb_acc, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->mb_acc2, (size_t)Q * sizeof(float)));
+  // the lists and LSQR vectors of the host-driven loop (not part of the common workspace)
+  ST_TRY(ensure(c, c->Flist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->Ulist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->v, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->w, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->x, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->beta_part, (size_t)K * nbeta * sizeof(double)));
+  ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->alpha_part, (size_t)(Q / 16 + 64) * sizeof(double)));
+  if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
+  if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
+  if (c->prec != CLSIMG_FP32) {
+    ST_TRY(ensure(c, c->frag_h, beam_h16_frag_bytes(P)));
+    ST_TRY(ensure(c, c->hscale, sizeof(float)));
+  }
+  if ((size_t)K * nbeta > c->h_mnorm_n) {
+    HIP_TRY(hipStreamSynchronize(st));
+    if (c->h_mnorm) (void)hipHostFree(c->h_mnorm);
+    c->h_mnorm = nullptr;
+    c->h_mnorm_n = 0;
+    HIP_TRY(hipHostMalloc((void**)&c->h_mnorm, (size_t)K * nbeta * sizeof(double), hipHostMallocDefault));
+    c->h_mnorm_n = (size_t)K * nbeta;
+  }
+  float* mf = mf_out ? mf_out : P_<float>(c->mf);
+  float* gamma = gamma_out ? gamma_out : P_<float>(c->gamma);
+  float* eps = P_<float>(c->eps);
+  float* acc = P_<float>(c->mb_acc);
+  float* acc2 = P_<float>(c->mb_acc2);
+  double* beta_part = P_<double>(c->beta_part);
+  double* alpha_part = P_<double>(c->alpha_part);
+  uint64_t* keys = P_<uint64_t>(c->keys);
+  LsqrState* ls = P_<LsqrState>(c->lsqr);
+  SolveDecision* dec = P_<SolveDecision>(c->dec);
+  const int* lsqr_stop = &ls->done;
+  const int* grad_stop = &dec->grad_done;
+  int* Flist = P_<int>(c->Flist);
+  int* Ulist = P_<int>(c->Ulist);
+  float* v = P_<float>(c->v);
+  float* w = P_<float>(c->w);
+  float* x = P_<float>(c->x);
+  auto B0k = [&](int k) { return P_<float2>(c->mb_B0) + (size_t)k * P * P; };
+  auto Bbk = [&](int k) { return P_<float2>(c->mb_Bb) + (size_t)k * P * P; };
+  auto uk = [&](int k) { return P_<float2>(c->mb_u) + (size_t)k * P * P; };
+  auto Ek = [&](int k) { return P_<float2>(c->mb_E) + (size_t)k * P * P; };
+  auto fragk = [&](int k) { return P_<float>(c->mb_frag) + (size_t)k * fru; };
+  auto bpart = [&](int k) { return beta_part + (size_t)k * nbeta; };
+  // steering tables of every block, kept side by side
+  for (int k = 0; k < K; ++k) {
+    c->tab_El = nullptr;
+    c->tab_Em = nullptr;
+    ST_TRY(ensure_tables(c, &blocks[k].array, g, st));
+    char* tb = P_<char>(c->mb_tab) + (size_t)k * tab_b;
+    HIP_TRY(hipMemcpyAsync(tb, c->El.ptr, (size_t)Pp * nl * sizeof(float2), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tb + (size_t)Pp * nl * sizeof(float2), c->Em.ptr, (size_t)Pp * nm * sizeof(float2),
+                           hipMemcpyDeviceToDevice, st));
+  }
+  auto use = [&](int k) {
+    const float2* tb = reinterpret_cast<const float2*>(P_<char>(c->mb_tab) + (size_t)k * tab_b);
+    c->tab_El = tb;
+    c->tab_Em = tb + (size_t)Pp * nl;
+  };
+  auto beam_acc = [&](int k, const float2* U, const int* skip, float* sum, float* sumsq, float scale) {
+    use(k);
+    return launch_beam_accumulate(U, P, tables_of(c, g, P), skip, sum, sumsq, scale, k == 0, c->prec,
+                                  P_<float>(c->frag_b), c->frag_h.ptr, P_<float>(c->hscale), st);
+  };
+  const double Kd = K;
+  double flops = 0.0;
+  // MF image and threshold (eq. mfdimg, App. A)
+  for (int k = 0; k < K; ++k)
+    HIP_TRY(beam_acc(k, reinterpret_cast<const float2*>(blocks[k].R), nullptr, mf, acc2, (float)(1.0 / Kd)));
+  flops += K * beam_flops(P, Q);
+  const double sqn = o->nsamples > 0 ? sqrt((double)o->nsamples) : 1.0;
+  HIP_TRY(launch_multi_mf(acc2, Q, (float)(o->kappa_d / (Kd * sqn)), eps, st));
+  // bound (eq. wmvdr with the sqrt(K) normalisation, Sec. II-D, App. A)
+  if (o->bound == CLSIMG_BOUND_NONE) {
+    HIP_TRY(launch_fill(gamma, std::numeric_limits<float>::infinity(), Q, st));
+  } else if (o->bound == CLSIMG_BOUND_MF) {
+    HIP_TRY(launch_multi_bound(1, mf, acc2, Q, 0.0, Kd, o->kappa_b / (Kd * sqn), gamma, st));
+  } else {
+    for (int k = 0; k < K; ++k) {
+      HIP_TRY(launch_chol_inverse(reinterpret_cast<const float2*>(blocks[k].R), P, P_<double2>(c->W),
+                                  P_<double2>(c->Li), P_<float2>(c->Rinv), P_<int>(c->status), st));
+      ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
+      if (*c->h_status != 0) return CLSIMG_ENOTPD;
+      HIP_TRY(beam_acc(k, P_<const float2>(c->Rinv), nullptr, acc, acc2, 1.f));
+    }
+    flops += K * beam_flops(P, Q);
+    const double kb = o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1)) : 0.0;
+    HIP_TRY(launch_multi_bound(0, acc, acc2, Q, o->C, Kd, kb, gamma, st));
+  }
+  // data B0_k = R_k - diag(noise_k) and ||B0||
+  for (int k = 0; k < K; ++k) {
+    use(k);
+    HIP_TRY(launch_sub_diag(reinterpret_cast<const float2*>(blocks[k].R), blocks[k].noise_diag, P, B0k(k), st));
+    ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, Ek(k), B0k(k), 0.f, 1.f, nullptr, nullptr, bpart(k), nullptr,
+                     st));
+  }
+  ST_TRY(read_back(c, c->h_mnorm, beta_part, (size_t)K * nbeta * sizeof(double), st));
+  const double b0norm = sqrt(sum_host(c->h_mnorm, K * nbeta));
+  HIP_TRY(launch_init_state(nullptr, nullptr, sigma, state, Q, st));
+  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+  int nF = c->h_dec->nF, nU = c->h_dec->nU;
+
+  const int max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
+  const int nkeys = lambda_vec_blocks(Q);
+  int status = CLSIMG_OK;
+  int outer = 0, adds = 0, drops = 0, lsqr_total = 0, itnlim_hits = 0, last_added = -1;
+  bool need_solve = true;
+  float lam_min = 0.f, eps_min = 0.f;
+  int i_min = -1, st_min = 0;
+  double margin_lambda = INFINITY, margin_z = INFINITY;
+  int batch = 2;
+  for (;;) {
+    if (need_solve) {
+      if (outer >= max_outer) {
+        status = CLSIMG_WMAXOUTER;
+        break;
+      }
+      HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+      // b_k = B0_k - Psi_{U,k} gamma_U  (eq. bsubproblemLS per block)
+      for (int k = 0; k < K; ++k) {
+        use(k);
+        ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bbk(k), B0k(k), -1.f, 1.f, nullptr, nullptr, nullptr,
+                         nullptr, st));
+      }
+      flops += K * corr_flops(P, nU);
+      const int nalpha = ntiles_adj(P, nF);
+      const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
+      // Psi_F^H u summed over the blocks, then the LSQR epilogue on the last one
+      auto adjoint_all = [&](int init, const int* stop) -> int {
+        for (int k = 0; k + 1 < K; ++k) {
+          use(k);
+          HIP_TRY(launch_adjoint_acc(adj_params(c, g, P, fragk(k), Flist, nF, stop), acc, k == 0, st));
+        }
+        use(K - 1);
+        HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, fragk(K - 1), Flist, nF, stop), v, beta_part, K * nbeta,
+                                    alpha_part, init, st, K > 1 ? acc : nullptr));
+        return CLSIMG_OK;
+      };
+      if (nF > 0) {
+        // beta_1 u_1 = b ; alpha_1 v_1 = Psi_F^H u_1  (eqs. initbeta, initu)
+        for (int k = 0; k < K; ++k) {
+          use(k);
+          ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, uk(k), Bbk(k), 0.f, 1.f, nullptr, fragk(k), bpart(k),
+                           nullptr, st));
+        }
+        ST_TRY(adjoint_all(1, nullptr));
+        HIP_TRY(launch_lsqr_init_scalars(ls, beta_part, K * nbeta, alpha_part, nalpha, v, w, x, nF, o->atol,
+                                         o->btol, o->conlim, itnlim, st));
+      }
+      for (;;) {
+        if (nF > 0) {
+          for (int b = 0; b < batch; ++b) {
+            // beta u <- Psi_F v - alpha u ; alpha v <- Psi_F^H u - beta v  (eq. lanczos), all blocks
+            for (int k = 0; k < K; ++k) {
+              use(k);
+              ST_TRY(correlate(c, g, P, Flist, v, 0, nF, uk(k), uk(k), 1.f, 0.f, ls, fragk(k), bpart(k),
+                               lsqr_stop, st));
+            }
+            ST_TRY(adjoint_all(0, lsqr_stop));
+            HIP_TRY(launch_lsqr_update(ls, beta_part, K * nbeta, alpha_part, nalpha, v, w, x, nF, st));
+          }
+        }
+        HIP_TRY(launch_step(lsqr_stop, nullptr, ls, x, x, Flist, nF, sigma, gamma, state, dec, st));
+        // gradient after a feasible subproblem (eq. gls, cost of eq. UCLS):
+        // E_k = Psi_{F,k} sigma_F - b_k, g = (1/K) sum_k vectdiag(A_k^H E_k A_k)
+        for (int k = 0; k < K; ++k) {
+          use(k);
+          ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, Ek(k), Bbk(k), 1.f, -1.f, nullptr, nullptr, nullptr,
+                           grad_stop, st));
+        }
+        for (int k = 0; k < K; ++k) HIP_TRY(beam_acc(k, Ek(k), grad_stop, acc2, nullptr, (float)(1.0 / Kd)));
+        HIP_TRY(launch_lambda_vec(acc2, state, Q, grad_stop, keys, st));
+        HIP_TRY(launch_argmin_final(keys, nkeys, eps, state, dec, st));
+        ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+        if (c->h_dec->lsqr_done) break;
+        batch = std::min(batch * 2, 64);
+      }
+      const SolveDecision d = *c->h_dec;
+      batch = std::max(2, std::min(64, d.lsqr_itn + 1));
+      ++outer;
+      lsqr_total += d.lsqr_itn;
+      if (nF > 0) flops += K * (beam_flops(P, nF) + d.lsqr_itn * (corr_flops(P, nF) + beam_flops(P, nF)));
+      if (d.feasible) flops += K * (corr_flops(P, nF) + beam_flops(P, Q));
+      if (nF > 0 && d.lsqr_istop == 7) ++itnlim_hits;
+      if (d.feasible) {
+        need_solve = false;
+        if (nF > 0) margin_z = std::min(margin_z, (double)d.margin_z);
+        if (d.i_min < 0) break;  // no active pixel left
+        lam_min = d.lam_min;
+        eps_min = d.eps_min;
+        i_min = d.i_min;
+        st_min = d.st_min;
+      } else {
+        ++drops;
+        --nF;
+        if (d.ib_to == CLSIMG_STATE_U) ++nU;
+        need_solve = true;
+        if (d.ib == last_added && d.mu_max == 0.0f) {
+          status = CLSIMG_WCYCLE;
+          break;
+        }
+      }
+      last_added = -1;
+    } else {
+      if (eps_min > 0.f) margin_lambda = std::min(margin_lambda, fabs((double)lam_min + eps_min) / eps_min);
+      if (lam_min < -eps_min) {
+        HIP_TRY(launch_set_state(state, i_min, (uint8_t)CLSIMG_STATE_F, st));
+        ++adds;
+        ++nF;
+        if (st_min == CLSIMG_STATE_U) --nU;
+        last_added = i_min;
+        need_solve = true;
+      } else {
+        break;
+      }
+    }
+  }
+  if (status == CLSIMG_OK && itnlim_hits) status = CLSIMG_WITNLIM;
+  // final residual sum_k ||B0_k - Psi_k sigma||^2
+  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+  nF = c->h_dec->nF;
+  nU = c->h_dec->nU;
+  for (int k = 0; k < K; ++k) {
+    use(k);
+    ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bbk(k), B0k(k), -1.f, 1.f, nullptr, nullptr, nullptr, nullptr,
+                     st));
+    ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, Ek(k), Bbk(k), 1.f, -1.f, nullptr, nullptr, bpart(k), nullptr,
+                     st));
+  }
+  ST_TRY(read_back(c, c->h_mnorm, beta_part, (size_t)K * nbeta * sizeof(double), st));
+  const double rn = sqrt(sum_host(c->h_mnorm, K * nbeta));
+  stats->status = status;
+  stats->outer_iters = outer;
+  stats->adds = adds;
+  stats->drops = drops;
+  stats->lsqr_iters_total = lsqr_total;
+  stats->lsqr_itnlim_hits = itnlim_hits;
+  stats->nF = nF;
+  stats->nU = nU;
+  stats->rel_residual = b0norm > 0 ? rn / b0norm : 0.0;
+  stats->objective = 0.5 * rn * rn / Kd;
+  stats->min_margin_lambda = margin_lambda;
+  stats->min_margin_z = margin_z;
+  stats->psi_flops = flops + K * (corr_flops(P, nU) + corr_flops(P, nF));
+  (void)MT;
   return status;
 }
 

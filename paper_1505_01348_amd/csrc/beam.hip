@@ -95,6 +95,24 @@ struct BeamStore {
   __device__ void finish(int) {}
 };
 
+// Sums over covariance blocks: sum[i] (+)= scale * g_i and, if sumsq is
+// given, sumsq[i] (+)= g_i^2 (first block: =).  The blocks are added in order.
+struct BeamAcc {
+  float* sum;
+  float* sumsq;
+  float scale;
+  int first;
+  __device__ void init() {}
+  __device__ void operator()(int pix, float g, bool ok) {
+    if (ok) {
+      const float v = g * scale;
+      sum[pix] = first ? v : sum[pix] + v;
+      if (sumsq) sumsq[pix] = first ? g * g : sumsq[pix] + g * g;
+    }
+  }
+  __device__ void finish(int) {}
+};
+
 // Lagrange multipliers of the active pixels (eqs. etaL, etaU): lambda = g on
 // L, -g on U; the block's smallest key (ordered lambda << 32 | pixel, so ties
 // go to the lowest pixel) is written to part[blockIdx.x].
@@ -776,6 +794,23 @@ hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* s
       return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st)
                   : launch_h16<false>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st);
   }
+}
+
+hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
+                                  float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
+                                  float* hscale, hipStream_t st) {
+  const BeamAcc epi{sum, sumsq, scale, first};
+  if (prec != 0) {  // split half precision
+    const bool bf = prec == 2;
+    hipError_t e = launch_beam_prep_h16(U, P, bf, frag_half, hscale, st);
+    if (e != hipSuccess) return e;
+    return bf ? launch_h16<true>(frag_half, nullptr, tab, skip, epi, st)
+              : launch_h16<false>(frag_half, hscale, tab, skip, epi, st);
+  }
+  if (beam_fits(P)) return launch_beam(nullptr, U, P, tab, skip, epi, st);
+  hipError_t e = launch_beam_prep_full(U, P, frag_big, st);
+  if (e != hipSuccess) return e;
+  return launch_big(frag_big, tab, skip, epi, st);
 }
 
 hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,

@@ -153,6 +153,7 @@ struct EpiLsqrV {
   int nbeta;
   double* alpha_part;
   int first;
+  const float* acc = nullptr;  // optional: the other blocks' beamformer outputs, added to g
   using Ctx = NoCtx;
   using Pre = NoCtx;
   __device__ Ctx init() const { return {}; }
@@ -169,7 +170,8 @@ struct EpiLsqrV {
     const double beta = sbeta;
     double vr2 = 0.0;
     if (ok) {
-      double vr = beta > 0.0 ? (double)g / beta : 0.0;
+      const float gt = acc ? g + acc[col] : g;
+      double vr = beta > 0.0 ? (double)gt / beta : 0.0;
       if (!first) vr -= beta * (double)v[col];
       const float vf = (float)vr;
       v[col] = vf;
@@ -177,6 +179,19 @@ struct EpiLsqrV {
     }
     const double tot = block_sum_d(vr2, sh);
     if (threadIdx.x == 0) alpha_part[tile] = tot;
+  }
+};
+
+// Sum of beamformer outputs over covariance blocks (first block: =).
+struct EpiAcc {
+  float* out;
+  int first;
+  using Ctx = NoCtx;
+  using Pre = NoCtx;
+  __device__ Ctx init() const { return {}; }
+  __device__ Pre prefetch(int, bool) const { return {}; }
+  __device__ void operator()(int, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
+    if (ok) out[col] = first ? g : out[col] + g;
   }
 };
 
@@ -271,7 +286,8 @@ hipError_t launch_adjoint_mvdr(const AdjParams& pr, float* gamma, double C, doub
 hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint64_t* part,
                                  hipStream_t st);
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
-                               double* alpha_part, int init, hipStream_t st);
+                               double* alpha_part, int init, hipStream_t st, const float* acc = nullptr);
+hipError_t launch_adjoint_acc(const AdjParams& pr, float* out, int first, hipStream_t st);
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st);
 int adjoint_lsqr2_tile_width(int MT, int n);
 // beam.hip (register-resident full-grid beamformer, P <= 48)
@@ -319,6 +335,19 @@ hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, f
 hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* scale, const Tables& tab,
                            const int* skip, float* out, float* eps, float eps_scale, double C, double kb, float sc,
                            const uint8_t* state, uint64_t* part, hipStream_t st);
+// sums over covariance blocks of the full-grid beamformer (any P, any precision:
+// prec 0 FP32, 1 FP16 split, 2 BF16 split); frag_big / frag_half / hscale are
+// the scratch of the GEMM-shaped and half-precision kernels
+hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
+                                  float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
+                                  float* hscale, hipStream_t st);
+// K covariance blocks: images, bound and multipliers from the block sums
+hipError_t launch_multi_mf(const float* mfsq, int Q, float eps_coef, float* eps, hipStream_t st);
+hipError_t launch_multi_bound(int kind, const float* s1, const float* s2, int Q, double C, double K, double kb_coef,
+                              float* gamma, hipStream_t st);
+int lambda_vec_blocks(int Q);
+hipError_t launch_lambda_vec(const float* g, const uint8_t* state, int Q, const int* skip, uint64_t* part,
+                             hipStream_t st);
 // lsqr_cu.hip
 bool lsqr_cu_fits(int P, int n);
 hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st);

@@ -635,8 +635,12 @@ hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint
   return launch_adjoint_epi(pr, EpiLambda{state, part}, st);
 }
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
-                               double* alpha_part, int init, hipStream_t st) {
-  return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init}, st);
+                               double* alpha_part, int init, hipStream_t st, const float* acc) {
+  return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init, acc}, st);
+}
+
+hipError_t launch_adjoint_acc(const AdjParams& pr, float* out, int first, hipStream_t st) {
+  return launch_adjoint_epi(pr, EpiAcc{out, first}, st);
 }
 
 void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm) {

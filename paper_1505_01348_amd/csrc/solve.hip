@@ -405,4 +405,73 @@ hipError_t launch_init_state(const float* sigma0, const uint8_t* state0, float* 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// K covariance blocks (eq. vectRtotal).  The full-grid beamformer leaves the
+// block sums; these kernels turn them into the threshold, the bound and the
+// multiplier keys.
+//   MF:   mf = (1/K) sum_k m_k (summed by the beamformer), eps = kappa_d
+//         sqrt(sum_k m_k^2) / (K sqrt N)                       (App. A)
+//   MVDR: gamma = C K / sum_k h_k + kappa_b K sqrt(sum_k h_k^2) /
+//         (sqrt(N - p - 1) (sum_k h_k)^2)                 (eq. wmvdr, App. A)
+//   MF bound: gamma = mf + kappa_b sqrt(sum_k m_k^2) / (K sqrt N)
+__global__ void multi_mf_kernel(const float* __restrict__ mfsq, int Q, float eps_coef, float* __restrict__ eps) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x)
+    eps[i] = eps_coef * sqrtf(mfsq[i]);
+}
+
+__global__ void multi_bound_kernel(int kind, const float* __restrict__ s1, const float* __restrict__ s2, int Q,
+                                   double C, double K, double kb_coef, float* __restrict__ gamma) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
+    const double a = s1[i], b = s2[i];
+    double g;
+    if (kind == 0) {  // MVDR from the sums of h_k and h_k^2
+      g = C * K / a;
+      if (kb_coef != 0.0) g += kb_coef * K * sqrt(b) / (a * a);
+    } else {  // MF from the image and the sum of m_k^2
+      g = a + kb_coef * sqrt(b);
+    }
+    gamma[i] = (float)g;
+  }
+}
+
+// keys (ordered lambda << 32 | pixel) of the active pixels from a gradient
+// vector: lambda = g on L, -g on U; one key per block
+__global__ __launch_bounds__(256) void lambda_vec_kernel(const float* __restrict__ g,
+                                                         const uint8_t* __restrict__ state, int Q,
+                                                         const int* skip, uint64_t* __restrict__ part) {
+  __shared__ uint64_t sh[4];
+  if (skip && *skip) return;
+  uint64_t best = ~0ull;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
+    const uint8_t s = state[i];
+    if (s == 1) continue;
+    const float lam = s == 0 ? g[i] : -g[i];
+    const uint64_t key = ((uint64_t)ordered_bits(lam) << 32) | (uint32_t)i;
+    best = key < best ? key : best;
+  }
+  best = block_min_u64(best, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = best;
+}
+
+hipError_t launch_multi_mf(const float* mfsq, int Q, float eps_coef, float* eps, hipStream_t st) {
+  const int g = std::min((Q + 255) / 256, 2048);
+  hipLaunchKernelGGL(multi_mf_kernel, dim3(g), dim3(256), 0, st, mfsq, Q, eps_coef, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_bound(int kind, const float* s1, const float* s2, int Q, double C, double K, double kb_coef,
+                              float* gamma, hipStream_t st) {
+  const int g = std::min((Q + 255) / 256, 2048);
+  hipLaunchKernelGGL(multi_bound_kernel, dim3(g), dim3(256), 0, st, kind, s1, s2, Q, C, K, kb_coef, gamma);
+  return hipGetLastError();
+}
+
+int lambda_vec_blocks(int Q) { return std::max(1, std::min((Q + 255) / 256, 1024)); }
+
+hipError_t launch_lambda_vec(const float* g, const uint8_t* state, int Q, const int* skip, uint64_t* part,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(lambda_vec_kernel, dim3(lambda_vec_blocks(Q)), dim3(256), 0, st, g, state, Q, skip, part);
+  return hipGetLastError();
+}
+
 }  // namespace clsimg

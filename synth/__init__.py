@@ -12,5 +12,6 @@ from .scenes import (  # noqa: F401
     Scene,
     make_scene,
     make_request_scenes,
+    make_block_scenes,
     exact_covariance,
 )

@@ -219,3 +219,35 @@ def make_request_scenes(n_req: int, seed: int = _REQUEST_SEED, P_choices=(24, 48
                           N=16384, noise=10.0, points=(min(n_src, n * n), ("loguniform", 0.1, 100.0)),
                           blobs=(0, 6.0, 0.0), lam=lam))
     return out
+
+
+def make_block_scenes(config: str = "c0", K: int = 2, rotation: float = 0.05, lams=None, seed=None,
+                      **overrides):
+    """K covariance blocks of one sky on one grid (the stacked data model):
+    block k sees the array rotated by k * rotation radians about the origin
+    (Earth rotation between short-term integrations) and, if ``lams`` is
+    given, wavelength lams[k] (frequency channels with the same sky).  Each
+    block draws its own N samples.  Returns a list of K scenes."""
+    idx = {"c0": 0, "c1": 1, "c2": 2, "c4": 4}[config]
+    rec = dict(CONFIGS[config])
+    rec.update(overrides)
+    seed = _SEED_BASE + 100 + idx if seed is None else seed
+    ss = np.random.SeedSequence(seed)
+    s_pos, s_sky, s_smp = ss.spawn(3)
+    P, n = rec["P"], rec["n"]
+    pos0 = _disc_positions(np.random.default_rng(s_pos), P, rec["radius"])
+    l0, dl = _grid_axis(n, rec["L"])
+    n_pts, law = rec["points"]
+    n_blobs, fwhm, peak = rec["blobs"]
+    src_pix, src_pow = _sky(np.random.default_rng(s_sky), n, n, n_pts, law, n_blobs, fwhm, peak)
+    grid = (n, n, l0, dl, l0, dl)
+    out = []
+    for k, sk in enumerate(s_smp.spawn(K)):
+        c, sn = math.cos(k * rotation), math.sin(k * rotation)
+        pos = pos0 @ np.array([[c, -sn], [sn, c]]).T
+        lam = float(lams[k]) if lams is not None else rec.get("lam", 1.0)
+        R = exact_covariance(pos, lam, grid, src_pix, src_pow, rec["noise"])
+        Rh = _sample_covariance(np.random.default_rng(sk), R, rec["N"])
+        out.append(Scene(name=f"{config}-block{k}", P=P, pos=pos, lam=lam, nl=n, nm=n, l0=l0, dl=dl, m0=l0, dm=dl,
+                         N=rec["N"], noise_var=rec["noise"], src_pix=src_pix, src_pow=src_pow, R_hat=Rh))
+    return out

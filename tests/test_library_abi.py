@@ -46,7 +46,7 @@ def test_struct_layouts_match_c_abi(tmp_path):
     # compile the header with the host C compiler and compare every field offset
     structs = {"clsimg_array": clsimg.CArray, "clsimg_grid": clsimg.CGrid,
                "clsimg_opts": clsimg.COpts, "clsimg_stats": clsimg.CStats, "clsimg_request": clsimg.CRequest,
-               "clsimg_server_info": clsimg.CServerInfo}
+               "clsimg_server_info": clsimg.CServerInfo, "clsimg_block": clsimg.CBlock}
     cfields = {"clsimg_array": ["P", "pos_xy", "lambda"]}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
     for cname, cls in structs.items():

@@ -79,6 +79,10 @@ def parse():
                     help="only launch the beamformer (20 times) and a plain copy of --copy-mib MiB "
                          "(3 times): the program the HBM traffic counters are read on")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--blocks", type=int, default=1,
+                    help="snapshots per solve (array rotated 0.05 rad between them); with --channels, "
+                         "blocks x channels covariance blocks of one sky (clsimg_solve_multi)")
+    ap.add_argument("--channels", type=int, default=1, help="frequency channels (wavelength 1, 1.1, ...)")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="serving benchmark instead: N mixed requests (24/48/96 antennas, 64^2..256^2 "
                          "pixels) through the continuous-batching server, against one solve at a time")
@@ -148,6 +152,88 @@ def cpu_baseline(sc, tol_oracle, budget_s=25.0, cost="ls", bound="mvdr", kappa_b
     what = "full" if max_outer < 0 else f"first-{max_outer}-step"
     return {"value": runs / t_total, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{runs} {what} FP64 oracle solves of the same workload ({t_total:.1f} s)"}, res
+
+
+def multi_bench(args, clsimg, synth, np, torch):
+    """K = blocks x channels covariance blocks of one sky on the workload's grid
+    (eq. vectRtotal): snapshot k sees the array rotated by 0.05 k rad, channel c
+    the wavelength 1 + 0.1 c; each block has its own N samples."""
+    nb, nc = max(1, args.blocks), max(1, args.channels)
+    angles = [0.05 * k for c in range(nc) for k in range(nb)]
+    lams = [1.0 + 0.1 * c for c in range(nc) for k in range(nb)]
+    K = nb * nc
+    scs = synth.make_block_scenes(args.config, K=K, angles=angles, lams=lams)
+    sc0 = scs[0]
+    log(f"bench: {K} blocks ({nb} snapshots x {nc} channels) of {args.config} P={sc0.P} Q={sc0.Q}")
+    opts = clsimg.default_options()
+    opts.nsamples = sc0.N
+    opts.atol = opts.btol = args.tol
+    opts.bound = {"mvdr": clsimg.BOUND_MVDR, "mf": clsimg.BOUND_MF, "none": clsimg.BOUND_NONE}[args.bound]
+    opts.kappa_b = args.kappa_b
+    opts.precision = PRECISIONS[args.precision]
+    opts.max_outer = args.max_outer
+    blocks = [{"R": torch.as_tensor(sc.R_hat32).cuda(), "geo": clsimg.Geometry(sc.pos, sc.lam, sc.grid),
+               "noise_diag": torch.as_tensor(sc.noise_diag.astype(np.float32)).cuda()} for sc in scs]
+    ctx = clsimg.Context(0)
+    out = None
+    for i in range(args.warmup):
+        out = ctx.solve_multi(blocks, opts)
+        torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        out = ctx.solve_multi(blocks, opts)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    total = time.perf_counter() - t_start
+    stats = out[4]
+    log(f"bench: {args.steps} solves of {K} blocks in {total:.3f} s; stats {stats}")
+    lat_ms = np.array(lat) * 1e3
+    result = {
+        "metric": METRIC + " (K covariance blocks per solve)",
+        "value": round(args.steps / total, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16 split halves + f32", "bf16": "bf16 split halves + f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}; {nb} snapshots (array rotated 0.05 rad "
+                               f"apart) x {nc} channels (wavelength 1, 1.1, ...), own samples per block",
+                   "blocks": K, "bound": args.bound, "precision": args.precision, "lsqr_tol": args.tol,
+                   "max_outer": args.max_outer},
+        "p50_ms": round(float(np.percentile(lat_ms, 50)), 4), "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+        "psi_tflops": round(stats["psi_flops"] * args.steps / total / 1e12, 4),
+        "solve": {k: stats[k] for k in ("status", "outer_iters", "adds", "drops", "lsqr_iters_total", "nF", "nU",
+                                        "rel_residual")},
+    }
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_info
+
+        import oracle
+        As = oracle.steering_blocks([(sc.pos, sc.lam) for sc in scs], sc0.grid)
+        Rs = [sc.R_hat32_c128 for sc in scs]
+        runs, t_total, ref = 0, 0.0, None
+        while True:
+            t0 = time.perf_counter()
+            gamma = oracle.upper_bound_multi(As, Rs, kind=args.bound, kappa_b=args.kappa_b, nsamples=sc0.N)
+            eps = oracle.detection_threshold_multi(As, Rs, 6.0, sc0.N)
+            B0s = [R - np.diag(sc.noise_diag.astype(np.float32).astype(np.float64)) for R, sc in zip(Rs, scs)]
+            ref = oracle.solve_multi(As, B0s, gamma, eps, atol=1e-8, btol=1e-8, max_outer=args.max_outer)
+            t_total += time.perf_counter() - t0
+            runs += 1
+            log(f"cpu baseline: oracle solve {runs} done, {t_total:.1f} s")
+            if t_total >= 10.0 or runs >= 30:
+                break
+        threads = [i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"]
+        result["cpu_baseline"] = {"value": runs / t_total, "unit": "solves/s", "cores": int(max(threads) if threads else 1),
+                                  "kind": "oracle", "sample": f"{runs} FP64 oracle solves of the same {K} blocks "
+                                                              f"({t_total:.1f} s)"}
+        s = out[0].cpu().numpy().astype(np.float64)
+        result["parity"] = {"rel_image_err": float(np.linalg.norm(s - ref.sigma) / np.linalg.norm(ref.sigma)),
+                            "same_sets": bool(np.array_equal(out[1].cpu().numpy(), ref.state)),
+                            "oracle_rel_residual": ref.rel_residual}
+    ctx.close()
+    print(json.dumps(result), flush=True)
 
 
 def serve_bench(args, clsimg, synth, np, torch):
@@ -271,6 +357,9 @@ def main():
         sys.exit(1)
     if args.serve:
         serve_bench(args, clsimg, synth, np, torch)
+        return
+    if args.blocks > 1 or args.channels > 1:
+        multi_bench(args, clsimg, synth, np, torch)
         return
     sc = synth.make_scene(args.config)
     log(f"bench: workload {args.config} P={sc.P} Q={sc.Q} N={sc.N}")

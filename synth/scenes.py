@@ -222,12 +222,13 @@ def make_request_scenes(n_req: int, seed: int = _REQUEST_SEED, P_choices=(24, 48
 
 
 def make_block_scenes(config: str = "c0", K: int = 2, rotation: float = 0.05, lams=None, seed=None,
-                      **overrides):
+                      angles=None, **overrides):
     """K covariance blocks of one sky on one grid (the stacked data model):
     block k sees the array rotated by k * rotation radians about the origin
-    (Earth rotation between short-term integrations) and, if ``lams`` is
-    given, wavelength lams[k] (frequency channels with the same sky).  Each
-    block draws its own N samples.  Returns a list of K scenes."""
+    (Earth rotation between short-term integrations; ``angles`` gives the K
+    angles explicitly) and, if ``lams`` is given, wavelength lams[k]
+    (frequency channels with the same sky).  Each block draws its own N
+    samples.  Returns a list of K scenes."""
     idx = {"c0": 0, "c1": 1, "c2": 2, "c4": 4}[config]
     rec = dict(CONFIGS[config])
     rec.update(overrides)
@@ -243,7 +244,8 @@ def make_block_scenes(config: str = "c0", K: int = 2, rotation: float = 0.05, la
     grid = (n, n, l0, dl, l0, dl)
     out = []
     for k, sk in enumerate(s_smp.spawn(K)):
-        c, sn = math.cos(k * rotation), math.sin(k * rotation)
+        ang = float(angles[k]) if angles is not None else k * rotation
+        c, sn = math.cos(ang), math.sin(ang)
         pos = pos0 @ np.array([[c, -sn], [sn, c]]).T
         lam = float(lams[k]) if lams is not None else rec.get("lam", 1.0)
         R = exact_covariance(pos, lam, grid, src_pix, src_pow, rec["noise"])

@@ -134,3 +134,18 @@ def test_multi_rejects(gpu_lib, ctx):
     bad = blk[:1] + _blocks(gpu_lib, [other])
     with pytest.raises(ValueError):  # grids differ
         ctx.solve_multi(bad, _opts(gpu_lib, scs))
+
+
+def test_six_blocks_at_the_48_antenna_workload_size(gpu_lib, ctx):
+    # 2 snapshots x 3 channels of the 48-antenna, 128 x 128 workload
+    angles = [0.05 * k for c in range(3) for k in range(2)]
+    lams = [1.0 + 0.1 * c for c in range(3) for k in range(2)]
+    scs = synth.make_block_scenes("c1", K=6, angles=angles, lams=lams)
+    print(f"case multi 6 blocks P={scs[0].P} Q={scs[0].Q}", flush=True)
+    ref, mf_ref, gam_ref = _oracle(scs)
+    sigma, state, mf, gamma, stats = ctx.solve_multi(_blocks(gpu_lib, scs), _opts(gpu_lib, scs))
+    s = sigma.cpu().numpy()
+    print(f"  image {_rel(s, ref.sigma):.2e}; steps {stats['outer_iters']} oracle {ref.outer_iters}", flush=True)
+    assert _rel(mf.cpu().numpy(), mf_ref) <= TOL and _rel(gamma.cpu().numpy(), gam_ref) <= TOL
+    np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
+    assert _rel(s, ref.sigma) <= TOL

@@ -289,6 +289,59 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
   return CLSIMG_OK;
 }
 
+// correlate() over K covariance blocks in one forward and one reduction
+// launch: block k uses the tables at tables_of() + k * tab_stride (float2) and
+// reads / writes out, B, frag and norm_part at k times their strides.
+int correlate_blocks(clsimg_ctx* c, const clsimg_grid* g, int P, int K, size_t tab_stride, const int* idx,
+                     const float* vals, int gather, int n, float2* out, size_t out_stride, const float2* B,
+                     size_t B_stride, float cK, float cB, const LsqrState* lsqr, float* frag, size_t frag_stride,
+                     double* norm_part, size_t norm_stride, const int* stop, hipStream_t st) {
+  int chw = 8, nchunks = 0, nbm = 1;
+  forward_plan(P, n, &chw, &nchunks, &nbm);
+  const int MT = pad_p(P) / 8;
+  const size_t pstride = part_floats_max(P);
+  if ((size_t)nchunks * MT * MT * 256 > pstride) return CLSIMG_EINVAL;
+  if (n > 0) {
+    FwdParams f;
+    f.tab = tables_of(c, g, P);
+    f.MT = MT;
+    f.idx = idx;
+    f.vals = vals;
+    f.gather = gather;
+    f.n = n;
+    f.chw = chw;
+    f.nbm = nbm;
+    f.nbn = nbm;
+    f.part = P_<float>(c->part);
+    f.stop_flag = stop;
+    f.nblk = K;
+    f.tab_stride = tab_stride;
+    f.part_stride = pstride;
+    HIP_TRY(launch_forward(f, st));
+  }
+  RedParams r;
+  r.part = P_<const float>(c->part);
+  r.nchunks = n > 0 ? nchunks : 0;
+  r.MT = MT;
+  r.P = P;
+  r.out = out;
+  r.B = B;
+  r.cK = cK;
+  r.cB = cB;
+  r.lsqr = lsqr;
+  r.frag = frag;
+  r.norm_part = norm_part;
+  r.stop_flag = stop;
+  r.nblk = K;
+  r.part_stride = pstride;
+  r.out_stride = out_stride;
+  r.B_stride = B_stride;
+  r.frag_stride = frag_stride;
+  r.norm_stride = norm_stride;
+  HIP_TRY(launch_reduce(r, st));
+  return CLSIMG_OK;
+}
+
 bool beam_any(int P) { return beam_fits(P) || beam_big_fits(P); }
 
 // Full-grid beamformer: for P <= 48 the block-triangular fragments of U stay
@@ -1226,7 +1279,8 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
 // summed over the blocks (stacked Khatri-Rao operator), and the images, the
 // bound and the multipliers come from the block sums (eqs. mfdimg, wmvdr,
 // App. A; gradient (1/K) sum_k, eq. UCLS).  LSQR runs on the stacked blocks
-// with the split-K correlation and the LDS-staged adjoint.
+// with the split-K correlation and the LDS-staged adjoint, each launched
+// once for all blocks.
 namespace {
 struct TableOverride {
   clsimg_ctx* c;
@@ -1269,6 +1323,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   ST_TRY(ensure(c, c->mb_frag, K * fru * sizeof(float)));
   ST_TRY(ensure(c, c->mb_acc, (size_t)Q * sizeof(float)));
   ST_TRY(ensure(c, c->mb_acc2, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->part, (size_t)K * part_floats_max(P) * sizeof(float)));
   // the lists and LSQR vectors of the host-driven loop (not part of the common workspace)
   ST_TRY(ensure(c, c->Flist, (size_t)Q * sizeof(int)));
   ST_TRY(ensure(c, c->Ulist, (size_t)Q * sizeof(int)));
@@ -1314,7 +1369,6 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   auto uk = [&](int k) { return P_<float2>(c->mb_u) + (size_t)k * P * P; };
   auto Ek = [&](int k) { return P_<float2>(c->mb_E) + (size_t)k * P * P; };
   auto fragk = [&](int k) { return P_<float>(c->mb_frag) + (size_t)k * fru; };
-  auto bpart = [&](int k) { return beta_part + (size_t)k * nbeta; };
   // steering tables of every block, kept side by side
   for (int k = 0; k < K; ++k) {
     c->tab_El = nullptr;
@@ -1329,6 +1383,14 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
     const float2* tb = reinterpret_cast<const float2*>(P_<char>(c->mb_tab) + (size_t)k * tab_b);
     c->tab_El = tb;
     c->tab_Em = tb + (size_t)Pp * nl;
+  };
+  const size_t tstride = tab_b / sizeof(float2), pp2 = (size_t)P * P;
+  // one correlation launch pair for all blocks: block k at k * stride
+  auto corr = [&](const int* idx, const float* vals, int gather, int n, float2* out, const float2* B, float cK,
+                  float cB, const LsqrState* lsq, float* frag, double* norms, const int* stop) {
+    use(0);
+    return correlate_blocks(c, g, P, K, tstride, idx, vals, gather, n, out, pp2, B, pp2, cK, cB, lsq, frag,
+                            frag ? fru : 0, norms, norms ? (size_t)nbeta : 0, stop, st);
   };
   auto beam_acc = [&](int k, const float2* U, const int* skip, float* sum, float* sumsq, float scale) {
     use(k);
@@ -1361,12 +1423,9 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
     HIP_TRY(launch_multi_bound(0, acc, acc2, Q, o->C, Kd, kb, gamma, st));
   }
   // data B0_k = R_k - diag(noise_k) and ||B0||
-  for (int k = 0; k < K; ++k) {
-    use(k);
+  for (int k = 0; k < K; ++k)
     HIP_TRY(launch_sub_diag(reinterpret_cast<const float2*>(blocks[k].R), blocks[k].noise_diag, P, B0k(k), st));
-    ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, Ek(k), B0k(k), 0.f, 1.f, nullptr, nullptr, bpart(k), nullptr,
-                     st));
-  }
+  ST_TRY(corr(nullptr, nullptr, 0, 0, Ek(0), B0k(0), 0.f, 1.f, nullptr, nullptr, beta_part, nullptr));
   ST_TRY(read_back(c, c->h_mnorm, beta_part, (size_t)K * nbeta * sizeof(double), st));
   const double b0norm = sqrt(sum_host(c->h_mnorm, K * nbeta));
   HIP_TRY(launch_init_state(nullptr, nullptr, sigma, state, Q, st));
@@ -1391,32 +1450,23 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
       }
       HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
       // b_k = B0_k - Psi_{U,k} gamma_U  (eq. bsubproblemLS per block)
-      for (int k = 0; k < K; ++k) {
-        use(k);
-        ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bbk(k), B0k(k), -1.f, 1.f, nullptr, nullptr, nullptr,
-                         nullptr, st));
-      }
+      ST_TRY(corr(Ulist, gamma, 1, nU, Bbk(0), B0k(0), -1.f, 1.f, nullptr, nullptr, nullptr, nullptr));
       flops += K * corr_flops(P, nU);
       const int nalpha = ntiles_adj(P, nF);
       const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
-      // Psi_F^H u summed over the blocks, then the LSQR epilogue on the last one
+      // Psi_F^H u summed over the blocks in one launch, with the LSQR epilogue
       auto adjoint_all = [&](int init, const int* stop) -> int {
-        for (int k = 0; k + 1 < K; ++k) {
-          use(k);
-          HIP_TRY(launch_adjoint_acc(adj_params(c, g, P, fragk(k), Flist, nF, stop), acc, k == 0, st));
-        }
-        use(K - 1);
-        HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, fragk(K - 1), Flist, nF, stop), v, beta_part, K * nbeta,
-                                    alpha_part, init, st, K > 1 ? acc : nullptr));
+        use(0);
+        AdjParams ap = adj_params(c, g, P, fragk(0), Flist, nF, stop);
+        ap.nblk = K;
+        ap.frag_stride = fru;
+        ap.tab_stride = tstride;
+        HIP_TRY(launch_adjoint_lsqr(ap, v, beta_part, K * nbeta, alpha_part, init, st));
         return CLSIMG_OK;
       };
       if (nF > 0) {
         // beta_1 u_1 = b ; alpha_1 v_1 = Psi_F^H u_1  (eqs. initbeta, initu)
-        for (int k = 0; k < K; ++k) {
-          use(k);
-          ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, uk(k), Bbk(k), 0.f, 1.f, nullptr, fragk(k), bpart(k),
-                           nullptr, st));
-        }
+        ST_TRY(corr(nullptr, nullptr, 0, 0, uk(0), Bbk(0), 0.f, 1.f, nullptr, fragk(0), beta_part, nullptr));
         ST_TRY(adjoint_all(1, nullptr));
         HIP_TRY(launch_lsqr_init_scalars(ls, beta_part, K * nbeta, alpha_part, nalpha, v, w, x, nF, o->atol,
                                          o->btol, o->conlim, itnlim, st));
@@ -1425,11 +1475,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
         if (nF > 0) {
           for (int b = 0; b < batch; ++b) {
             // beta u <- Psi_F v - alpha u ; alpha v <- Psi_F^H u - beta v  (eq. lanczos), all blocks
-            for (int k = 0; k < K; ++k) {
-              use(k);
-              ST_TRY(correlate(c, g, P, Flist, v, 0, nF, uk(k), uk(k), 1.f, 0.f, ls, fragk(k), bpart(k),
-                               lsqr_stop, st));
-            }
+            ST_TRY(corr(Flist, v, 0, nF, uk(0), uk(0), 1.f, 0.f, ls, fragk(0), beta_part, lsqr_stop));
             ST_TRY(adjoint_all(0, lsqr_stop));
             HIP_TRY(launch_lsqr_update(ls, beta_part, K * nbeta, alpha_part, nalpha, v, w, x, nF, st));
           }
@@ -1437,11 +1483,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
         HIP_TRY(launch_step(lsqr_stop, nullptr, ls, x, x, Flist, nF, sigma, gamma, state, dec, st));
         // gradient after a feasible subproblem (eq. gls, cost of eq. UCLS):
         // E_k = Psi_{F,k} sigma_F - b_k, g = (1/K) sum_k vectdiag(A_k^H E_k A_k)
-        for (int k = 0; k < K; ++k) {
-          use(k);
-          ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, Ek(k), Bbk(k), 1.f, -1.f, nullptr, nullptr, nullptr,
-                           grad_stop, st));
-        }
+        ST_TRY(corr(Flist, sigma, 1, nF, Ek(0), Bbk(0), 1.f, -1.f, nullptr, nullptr, nullptr, grad_stop));
         for (int k = 0; k < K; ++k) HIP_TRY(beam_acc(k, Ek(k), grad_stop, acc2, nullptr, (float)(1.0 / Kd)));
         HIP_TRY(launch_lambda_vec(acc2, state, Q, grad_stop, keys, st));
         HIP_TRY(launch_argmin_final(keys, nkeys, eps, state, dec, st));
@@ -1495,13 +1537,8 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
   nF = c->h_dec->nF;
   nU = c->h_dec->nU;
-  for (int k = 0; k < K; ++k) {
-    use(k);
-    ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bbk(k), B0k(k), -1.f, 1.f, nullptr, nullptr, nullptr, nullptr,
-                     st));
-    ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, Ek(k), Bbk(k), 1.f, -1.f, nullptr, nullptr, bpart(k), nullptr,
-                     st));
-  }
+  ST_TRY(corr(Ulist, gamma, 1, nU, Bbk(0), B0k(0), -1.f, 1.f, nullptr, nullptr, nullptr, nullptr));
+  ST_TRY(corr(Flist, sigma, 1, nF, Ek(0), Bbk(0), 1.f, -1.f, nullptr, nullptr, beta_part, nullptr));
   ST_TRY(read_back(c, c->h_mnorm, beta_part, (size_t)K * nbeta * sizeof(double), st));
   const double rn = sqrt(sum_host(c->h_mnorm, K * nbeta));
   stats->status = status;

@@ -25,6 +25,10 @@ struct AdjParams {
   const int* idx;     // output column k looks at pixel idx[k] (NULL: pixel k)
   int n;
   const int* stop_flag;
+  // K covariance blocks summed in one launch: block k uses frag + k * frag_stride
+  // and the tables at El/Em + k * tab_stride (fragment input only)
+  int nblk = 1;
+  size_t frag_stride = 0, tab_stride = 0;
 };
 
 struct FwdParams {
@@ -38,6 +42,10 @@ struct FwdParams {
   int nbm, nbn;       // output block grid
   float* part;
   const int* stop_flag;
+  // K covariance blocks in one launch (blockIdx.z): block k reads the tables
+  // at El/Em + k * tab_stride and writes its partials at part + k * part_stride
+  int nblk = 1;
+  size_t tab_stride = 0, part_stride = 0;
 };
 
 struct RedParams {
@@ -50,6 +58,10 @@ struct RedParams {
   float* frag;            // optional Ut fragments of out
   double* norm_part;      // optional per-block sum |out|^2
   const int* stop_flag;
+  // K covariance blocks in one launch (blockIdx.y): block k adds k * stride to
+  // part, out, B, frag and norm_part
+  int nblk = 1;
+  size_t part_stride = 0, out_stride = 0, B_stride = 0, frag_stride = 0, norm_stride = 0;
 };
 
 struct LsqrFwdParams {
@@ -153,7 +165,6 @@ struct EpiLsqrV {
   int nbeta;
   double* alpha_part;
   int first;
-  const float* acc = nullptr;  // optional: the other blocks' beamformer outputs, added to g
   using Ctx = NoCtx;
   using Pre = NoCtx;
   __device__ Ctx init() const { return {}; }
@@ -170,8 +181,7 @@ struct EpiLsqrV {
     const double beta = sbeta;
     double vr2 = 0.0;
     if (ok) {
-      const float gt = acc ? g + acc[col] : g;
-      double vr = beta > 0.0 ? (double)gt / beta : 0.0;
+      double vr = beta > 0.0 ? (double)g / beta : 0.0;
       if (!first) vr -= beta * (double)v[col];
       const float vf = (float)vr;
       v[col] = vf;
@@ -182,18 +192,6 @@ struct EpiLsqrV {
   }
 };
 
-// Sum of beamformer outputs over covariance blocks (first block: =).
-struct EpiAcc {
-  float* out;
-  int first;
-  using Ctx = NoCtx;
-  using Pre = NoCtx;
-  __device__ Ctx init() const { return {}; }
-  __device__ Pre prefetch(int, bool) const { return {}; }
-  __device__ void operator()(int, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
-    if (ok) out[col] = first ? g : out[col] + g;
-  }
-};
 
 // LSQR (fused form): v_raw <- Psi_F^H u / beta - beta v_it (or Psi_F^H u / beta
 // at the start); beta from the per-wave partials of the correlation kernel.
@@ -286,8 +284,7 @@ hipError_t launch_adjoint_mvdr(const AdjParams& pr, float* gamma, double C, doub
 hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint64_t* part,
                                  hipStream_t st);
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
-                               double* alpha_part, int init, hipStream_t st, const float* acc = nullptr);
-hipError_t launch_adjoint_acc(const AdjParams& pr, float* out, int first, hipStream_t st);
+                               double* alpha_part, int init, hipStream_t st);
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st);
 int adjoint_lsqr2_tile_width(int MT, int n);
 // beam.hip (register-resident full-grid beamformer, P <= 48)

@@ -70,6 +70,17 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
     }
     const int ecol = tile * T + tid;
     const typename Epi::Pre pf = epi.prefetch(ecol, tid < T && ecol < pr.n);
+    float gp[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) gp[t] = 0.f;
+    // covariance blocks: the column dots of every block add up (one block
+    // unless the caller stacks several); Ut of each block is staged anew
+    for (int kb = 0; kb < pr.nblk; ++kb) {
+    const float* fragk = pr.frag ? pr.frag + kb * pr.frag_stride : nullptr;
+    Tables tabk = tab;
+    tabk.El += kb * pr.tab_stride;
+    tabk.Em += kb * pr.tab_stride;
+    if (pr.nblk > 1) loaded = false;
     v4f acc[MTW][NTW];
 #pragma unroll
     for (int mi = 0; mi < MTW; ++mi)
@@ -108,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
             const int j = r >> 4, l4 = r & 15;
             float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
             if (mt < MT)
-              val = *reinterpret_cast<const float4*>(pr.frag + ((size_t)(mt * KS + kc0 + j) * 64 + l4 * 4));
+              val = *reinterpret_cast<const float4*>(fragk + ((size_t)(mt * KS + kc0 + j) * 64 + l4 * 4));
             *reinterpret_cast<float4*>(lds + ((mt * kch + j) * 64 + l4 * 4)) = val;
           }
         }
@@ -127,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
         for (int e = tid; e < na * T; e += kThreads) {
           const int pl = e / T, c = e - pl * T;  // T is a power of two
           float2 a = make_float2(0.f, 0.f);
-          if (spix[c] >= 0) a = tab.a(2 * kc0 + pl, sil[c], sim[c]);
+          if (spix[c] >= 0) a = tabk.a(2 * kc0 + pl, sil[c], sim[c]);
           xs[(2 * pl) * TS + c] = a.x;
           xs[(2 * pl + 1) * TS + c] = a.y;
         }
@@ -148,9 +159,6 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
       }
     }
     // column dot product: row 16mt + 4q + r of X against the same row of Y
-    float gp[NTW];
-#pragma unroll
-    for (int t = 0; t < NTW; ++t) gp[t] = 0.f;
 #pragma unroll
     for (int mi = 0; mi < MTW; ++mi) {
       const int mt = wm * MTW + mi;
@@ -177,8 +185,8 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
             float2 a0 = make_float2(0.f, 0.f), a1 = a0;
             if (pix >= 0) {
               const int il = pix % tab.nl, im = pix / tab.nl;
-              a0 = tab.a(8 * mt + 2 * q, il, im);
-              a1 = tab.a(8 * mt + 2 * q + 1, il, im);
+              a0 = tabk.a(8 * mt + 2 * q, il, im);
+              a1 = tabk.a(8 * mt + 2 * q + 1, il, im);
             }
             x0 = a0.x; x1 = a0.y; x2 = a1.x; x3 = a1.y;
           }
@@ -186,6 +194,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
         }
       }
     }
+    }  // covariance blocks
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
       gp[t] += __shfl_xor(gp[t], 16, 64);
@@ -301,7 +310,11 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(FwdParams pr) {
   const int k0 = chunk * pr.chw;
   if (k0 >= pr.n) return;
   const int k1 = min(k0 + pr.chw, pr.n);
-  const Tables tab = pr.tab;
+  Tables tab = pr.tab;
+  const int kb = blockIdx.z;  // covariance block
+  tab.El += kb * pr.tab_stride;
+  tab.Em += kb * pr.tab_stride;
+  float* part = pr.part + kb * pr.part_stride;
   v4f acc[MTW][NTW];
 #pragma unroll
   for (int mi = 0; mi < MTW; ++mi)
@@ -349,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(FwdParams pr) {
       const int nt = bn * NTW + ni;
       if (mt < MT && nt < MT) {
         float4 o = make_float4(acc[mi][ni][0], acc[mi][ni][1], acc[mi][ni][2], acc[mi][ni][3]);
-        *reinterpret_cast<float4*>(pr.part + (((size_t)chunk * MT + mt) * MT + nt) * 256 + lane * 4) = o;
+        *reinterpret_cast<float4*>(part + (((size_t)chunk * MT + mt) * MT + nt) * 256 + lane * 4) = o;
       }
     }
   }
@@ -363,6 +376,14 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(FwdParams pr) {
 __global__ __launch_bounds__(kThreads) void reduce_kernel(RedParams pr) {
   __shared__ double sh[8];
   if (pr.stop_flag && *pr.stop_flag) return;
+  {  // covariance block blockIdx.y
+    const size_t kb = blockIdx.y;
+    pr.part += kb * pr.part_stride;
+    pr.out += kb * pr.out_stride;
+    if (pr.B) pr.B += kb * pr.B_stride;
+    if (pr.frag) pr.frag += kb * pr.frag_stride;
+    if (pr.norm_part) pr.norm_part += kb * pr.norm_stride;
+  }
   const int MT = pr.MT, P = pr.P;
   const int t = blockIdx.x * kThreads + threadIdx.x;
   const int tile = t >> 6, lane = t & 63;
@@ -635,12 +656,8 @@ hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint
   return launch_adjoint_epi(pr, EpiLambda{state, part}, st);
 }
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
-                               double* alpha_part, int init, hipStream_t st, const float* acc) {
-  return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init, acc}, st);
-}
-
-hipError_t launch_adjoint_acc(const AdjParams& pr, float* out, int first, hipStream_t st) {
-  return launch_adjoint_epi(pr, EpiAcc{out, first}, st);
+                               double* alpha_part, int init, hipStream_t st) {
+  return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init}, st);
 }
 
 void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm) {
@@ -666,7 +683,7 @@ void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm) {
 hipError_t launch_forward(const FwdParams& pr, hipStream_t st) {
   if (pr.n <= 0) return hipSuccess;
   const int nchunks = (pr.n + pr.chw - 1) / pr.chw;
-  dim3 grid((nchunks + 3) / 4, pr.nbm * pr.nbn);
+  dim3 grid((nchunks + 3) / 4, pr.nbm * pr.nbn, pr.nblk);
   if (pr.MT <= 3)
     hipLaunchKernelGGL((forward_kernel<3, 3>), grid, dim3(kThreads), 0, st, pr);
   else
@@ -681,7 +698,7 @@ int reduce_blocks(int P) {
 
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st) {
   const int blocks = reduce_blocks(pr.P);
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(kThreads), 0, st, pr);
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks, pr.nblk), dim3(kThreads), 0, st, pr);
   return hipGetLastError();
 }
 

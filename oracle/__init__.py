@@ -17,6 +17,8 @@ active_set  the active-set solver of Table I with the detection threshold
             (Sec. III)
 pwls        the constrained preconditioned weighted LS problem (eq. preWLS)
             as the LS problem on whitened, D-scaled inputs
+offgrid     strong off-grid sources (Sec. III-E, eq. doals): the free pixels'
+            offsets by Gauss-Newton rounds around the LSQR subproblem
 multi       K covariance blocks over one grid (Earth-rotation snapshots or
             frequency channels, eq. vectRtotal): MF / MVDR images, bounds,
             thresholds and the stacked solve (eqs. mfdimg, wmvdr, App. A)
@@ -66,3 +68,4 @@ from .multi import (  # noqa: F401
     detection_threshold_multi,
     solve_multi,
 )
+from .offgrid import gauss_newton_block, offset_gradient, solve_offgrid, steering_at  # noqa: F401

@@ -19,9 +19,11 @@ oim = importlib.import_module("oracle.imaging")
 olsqr = importlib.import_module("oracle.lsqr")  # the package re-exports a function of that name
 opw = importlib.import_module("oracle.pwls")
 omu = importlib.import_module("oracle.multi")
+oog = importlib.import_module("oracle.offgrid")
 from tests import test_oracle_pins as pins
 from tests import test_oracle_pwls as ppins
 from tests import test_oracle_multi as mpins
+from tests import test_oracle_offgrid as opins
 
 PINS = [
     pins.test_steering_matches_entrywise_model_and_is_unit_norm,
@@ -56,6 +58,10 @@ PINS = [
     mpins.test_stacked_solve_matches_brute_force_on_a_tiny_grid,
     mpins.test_mvdr_between_assc_and_mf,
     mpins.test_app_a_variances_match_monte_carlo,
+    opins.test_gradient_and_gauss_newton_block_against_finite_differences,
+    opins.test_one_pixel_shift_is_the_neighbour,
+    opins.test_zero_rounds_is_the_on_grid_solve,
+    opins.test_off_grid_sources_are_recovered,
 ]
 
 MUTATIONS = [
@@ -93,6 +99,13 @@ MUTATIONS = [
     (omu, "g = g + kappa_b * K * np.sqrt(s2) / (math.sqrt(nsamples - P - 1) * s1 * s1)",
      "g = g + kappa_b * np.sqrt(s2) / (math.sqrt(nsamples - P - 1) * s1 * s1)"),
     (omu, "return sum(hs), sum(h * h for h in hs)", "return sum(hs), sum(hs) ** 2"),
+    (oog, "d = a * (-1j * c * np.asarray(pos, np.float64)[:, j])", "d = a * (1j * c * np.asarray(pos, np.float64)[:, j])"),
+    (oog, "d = pos - pos.mean(axis=0)", "d = pos"),
+    (oog, "step = -np.linalg.solve(z[k] * z[k] * G, g)", "step = -np.linalg.solve(z[k] * G, g)"),
+    (oog, "phase = (-2.0 * math.pi / lam) * (np.outer(pos[:, 0], np.asarray(l, np.float64))",
+     "phase = (2.0 * math.pi / lam) * (np.outer(pos[:, 0], np.asarray(l, np.float64))"),
+    (oog, "gamma[F] = _bounds_at(pos, lam, lc[F] + delta[F, 0], mc[F] + delta[F, 1], R, Rinv, kind, C,",
+     "gamma[F] = _bounds_at(pos, lam, lc[F], mc[F], R, Rinv, kind, C,"),
     (oas, "if lam_min < -thr:", "if lam_min < thr:"),
     (opw, "return h * h / C, h", "return h / C, h"),
     (opw, "Ahat = (Linv @ A) / np.sqrt(D)[None, :]", "Ahat = (Linv @ A) / D[None, :]"),
@@ -119,7 +132,7 @@ def _load_mutant(module, old, new):
 def _install(monkeypatch, module, mutant):
     names = [n for n in dir(module) if not n.startswith("__")]
     # every module that imported the mutated functions by name
-    targets = [t for t in (oracle, oas, omu) if t is not module]
+    targets = [t for t in (oracle, oas, omu, oog) if t is not module]
     for name in names:
         obj = getattr(mutant, name)
         if callable(obj) and getattr(obj, "__module__", None) == mutant.__name__:

@@ -249,6 +249,29 @@ int clsimg_solve_multi(clsimg_ctx* ctx, int32_t K, const clsimg_block* blocks, c
                        const clsimg_opts* opts, float* sigma, uint8_t* state, float* mf, float* gamma,
                        clsimg_stats* stats, void* stream);
 
+/* ---- Strong off-grid sources (Sec. III-E, eq. doals) --------------------
+ * The subproblem on the free set F becomes
+ *   min over (delta_F, sigma_F)  1/2 || b - Psi(delta)_F sigma_F ||^2,
+ *   |delta_i,l| <= |dl|/2, |delta_i,m| <= |dm|/2,
+ * pixel i's steering vector taken at its centre shifted by delta_i (direction
+ * cosines).  Each subproblem runs `rounds` rounds of (LSQR for sigma_F at the
+ * current offsets, one Gauss-Newton step per free pixel's offset, inter-pixel
+ * coupling neglected, clipped to the pixel), then a final LSQR.  A pixel
+ * enters F at its centre and its offset is reset when it leaves F; free
+ * pixels' bounds are the bound formula at their shifted directions; the
+ * upper set keeps on-grid steering and bounds; release tests and the gradient
+ * on the active pixels stay on the grid.  offsets: DEVICE float[2Q] out,
+ * (delta_l, delta_m) per pixel, zero outside F; sigma holds the powers at the
+ * shifted positions.  0 <= rounds <= 16 (0: the plain subproblem, with the
+ * free steering vectors formed directly in FP64 rather than from the tables).
+ * P <= 48, LS cost, free sets within the one-workgroup LSQR (else
+ * CLSIMG_ENOTSUP).  Other arguments as clsimg_solve (no starting image);
+ * synchronises `stream`. */
+int clsimg_solve_offgrid(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array, const clsimg_grid* grid,
+                         const float* noise_diag, const clsimg_opts* opts, int32_t rounds, float* sigma,
+                         uint8_t* state, float* offsets, float* mf, float* gamma, clsimg_stats* stats,
+                         void* stream);
+
 /* ---- Serving: continuous batching of independent requests -------------
  * A server solves a stream of imaging requests (Sec. III, Table I, LSQR of
  * Sec. IV-A), each with its own array (any P <= CLSIMG_MAX_P), wavelength and

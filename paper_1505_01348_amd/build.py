@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libclsimg.so")
-SOURCES = ["ops.hip", "lsqr.hip", "lsqr_persist.hip", "lsqr_cu.hip", "beam.hip", "outer.hip", "solve.hip", "api.hip", "serve.hip"]
+SOURCES = ["ops.hip", "lsqr.hip", "lsqr_persist.hip", "lsqr_cu.hip", "beam.hip", "outer.hip", "solve.hip", "api.hip", "serve.hip", "offgrid.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -29,7 +29,7 @@ MAX_P = 288
 
 EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
             "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
-            "clsimg_solve_batch", "clsimg_solve_multi", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
+            "clsimg_solve_batch", "clsimg_solve_multi", "clsimg_solve_offgrid", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
             "clsimg_server_query", "clsimg_server_destroy", "clsimg_strerror")
 
 
@@ -101,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                  vp, vp, vp, vp, vp, vp, C.POINTER(CStats), vp]
     lib.clsimg_solve_multi.argtypes = [vp, i32, C.POINTER(CBlock), C.POINTER(CGrid), C.POINTER(COpts), vp, vp,
                                        vp, vp, C.POINTER(CStats), vp]
+    lib.clsimg_solve_offgrid.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), vp, C.POINTER(COpts), i32,
+                                         vp, vp, vp, vp, vp, C.POINTER(CStats), vp]
     lib.clsimg_server_create.argtypes = [C.POINTER(vp), i32, i32, sz, i32, i32, C.POINTER(COpts)]
     lib.clsimg_server_submit.argtypes = [vp, C.POINTER(CRequest), C.POINTER(C.c_int64)]
     lib.clsimg_server_poll.argtypes = [vp, i32, C.POINTER(C.c_int64), i32, C.POINTER(i32)]
@@ -344,6 +346,27 @@ class Context:
             self._check(st, "clsimg_solve_multi")
         stats = {f: getattr(st_c, f) for f, _ in CStats._fields_}
         return sigma, state, mf, gamma, stats
+
+    def solve_offgrid(self, R, geo: Geometry, opts: Options, rounds: int = 3, noise_diag=None):
+        """Solve with the off-grid correction of the free pixels.  Returns
+        (sigma, state, offsets (Q x 2: delta_l, delta_m), mf, gamma, stats)."""
+        dev = self.device
+        _need(R, torch.complex64, geo.P * geo.P, "R", dev)
+        if noise_diag is not None:
+            _need(noise_diag, torch.float32, geo.P, "noise_diag", dev)
+        Q = geo.Q
+        mk = lambda dt, n=Q: torch.empty(n, dtype=dt, device=R.device)  # noqa: E731
+        sigma, state, offsets = mk(torch.float32), mk(torch.uint8), mk(torch.float32, 2 * Q)
+        mf, gamma = mk(torch.float32), mk(torch.float32)
+        st_c = CStats()
+        co = opts.to_c()
+        st = self._lib.clsimg_solve_offgrid(self._h, _ptr(R), C.byref(geo.c_array), C.byref(geo.c_grid),
+                                            _ptr(noise_diag), C.byref(co), int(rounds), _ptr(sigma), _ptr(state),
+                                            _ptr(offsets), _ptr(mf), _ptr(gamma), C.byref(st_c), _stream())
+        if st < 0:
+            self._check(st, "clsimg_solve_offgrid")
+        stats = {f: getattr(st_c, f) for f, _ in CStats._fields_}
+        return sigma, state, offsets.view(Q, 2), mf, gamma, stats
 
     def solve_batch(self, requests, opts: Options):
         """Batched solve of independent problems with the same P (each a dict with

@@ -1558,6 +1558,225 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   return status;
 }
 
+// Strong off-grid sources (Sec. III-E, eq. doals): the host-driven active-set
+// loop with the subproblem replaced by rounds of (LSQR on the free pixels at
+// their shifted directions, one Gauss-Newton step per free pixel's offset),
+// then a final LSQR; the free pixels' bounds are taken at their shifted
+// directions; the upper set keeps on-grid steering and bounds; release tests
+// and the gradient on the active pixels stay on the grid.  P <= 48 and free
+// sets within the one-workgroup LSQR.
+int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
+                         const float* noise_diag, const clsimg_opts* o, int32_t rounds, float* sigma,
+                         uint8_t* state, float* offsets, float* mf_out, float* gamma_out, clsimg_stats* stats,
+                         void* stream) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (!c || !R || !sigma || !state || !offsets || !stats || rounds < 0 || rounds > 16) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  ST_TRY(check_opts(o, a->P));
+  if (o->nsamples <= 0 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
+  const int P = a->P, Q = g->nl * g->nm, Pp = pad_p(P), MT = Pp / 8;
+  if (o->cost != CLSIMG_COST_LS || !beam_fits(P)) return CLSIMG_ENOTSUP;
+  c->prec = o->precision;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  ST_TRY(ensure_workspace(c, P, Q));
+  ST_TRY(ensure(c, c->Flist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->Ulist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->x, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->lsqr2, 3 * sizeof(LsqrState)));
+  ST_TRY(ensure(c, c->done, sizeof(int)));
+  ST_TRY(ensure(c, c->bar, 2 * sizeof(unsigned)));
+  ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->mb_acc, (size_t)Q * sizeof(float)));  // on-grid bound gamma0
+  ST_TRY(ensure(c, c->mb_acc2, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->xf, (size_t)Q * 2 * Pp * sizeof(float)));
+  if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
+  if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure_tables(c, a, g, st));
+  float* mf = mf_out ? mf_out : P_<float>(c->mf);
+  float* gamma = gamma_out ? gamma_out : P_<float>(c->gamma);  // bounds in use (free pixels shifted)
+  float* gamma0 = P_<float>(c->mb_acc);
+  float* eps = P_<float>(c->eps);
+  float* xf = P_<float>(c->xf);
+  float* x = P_<float>(c->x);
+  int* Flist = P_<int>(c->Flist);
+  int* Ulist = P_<int>(c->Ulist);
+  float2* B0 = P_<float2>(c->B0);
+  float2* Bb = P_<float2>(c->Bb);
+  float2* E = P_<float2>(c->E);
+  uint64_t* keys = P_<uint64_t>(c->keys);
+  SolveDecision* dec = P_<SolveDecision>(c->dec);
+  LsqrState* S2 = P_<LsqrState>(c->lsqr2);
+  LsqrState* Sfin = S2 + 2;
+  int* done = P_<int>(c->done);
+  unsigned* bar = P_<unsigned>(c->bar);
+  int* lerr = reinterpret_cast<int*>(bar + 1);
+  const int* grad_stop = &dec->grad_done;
+  double* nrm = P_<double>(c->beta_part);
+  const Tables tab = tables_of(c, g, P);
+  const double* pos = P_<const double>(c->pos_d);
+  const float2* Rf = reinterpret_cast<const float2*>(R);
+  const float half_l = (float)(0.5 * fabs(g->dl)), half_m = (float)(0.5 * fabs(g->dm));
+  // images, on-grid bound and threshold (Sec. II-D, App. A)
+  const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
+  ST_TRY(beam_full(c, g, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
+  ST_TRY(compute_bound(c, R, a, g, o, gamma0, st));  // MVDR: leaves R^-1 in c->Rinv
+  const int bkind = o->bound == CLSIMG_BOUND_MVDR ? 0 : (o->bound == CLSIMG_BOUND_MF ? 1 : 2);
+  const double bkb = o->kappa_b == 0.0 ? 0.0
+                     : (bkind == 0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1))
+                                   : o->kappa_b / sqrt((double)o->nsamples));
+  const float2* bmat = bkind == 0 ? P_<const float2>(c->Rinv) : Rf;
+  HIP_TRY(hipMemcpyAsync(gamma, gamma0, (size_t)Q * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(launch_sub_diag(Rf, noise_diag, P, B0, st));
+  HIP_TRY(launch_frob2(B0, P * P, nrm, st));
+  ST_TRY(read_back(c, c->h_norms, nrm, sizeof(double), st));
+  const double b0norm = sqrt(c->h_norms[0]);
+  HIP_TRY(launch_init_state(nullptr, nullptr, sigma, state, Q, st));
+  HIP_TRY(launch_fill(offsets, 0.f, 2 * Q, st));
+  auto xf_off = [&](int n) {
+    return launch_xf_off(pos, P, a->lambda, g->nl, g->l0, g->dl, g->m0, g->dm, Flist, n, offsets, xf, st);
+  };
+  auto corr_xf = [&](int n, const float* vals, const int* gidx, const int* stop) {
+    CorrOsParams cp;
+    cp.MT = MT;
+    cp.P = P;
+    cp.xf = xf;
+    cp.n = n;
+    cp.vals = vals;
+    cp.gidx = gidx;
+    cp.out = E;
+    cp.B = Bb;
+    cp.cK = 1.f;
+    cp.cB = -1.f;
+    cp.frag = P_<float>(c->frag_r);
+    cp.stop_flag = stop;
+    return launch_corr_os(cp, st);
+  };
+
+  const int max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
+  int status = CLSIMG_OK;
+  int outer = 0, adds = 0, drops = 0, lsqr_total = 0, itnlim_hits = 0, last_added = -1, nF = 0, nU = 0;
+  bool need_solve = true;
+  float lam_min = 0.f, eps_min = 0.f;
+  int i_min = -1, st_min = 0;
+  double margin_lambda = INFINITY, margin_z = INFINITY, flops = 2.0 * beam_flops(P, Q);
+  for (;;) {
+    if (need_solve) {
+      if (outer >= max_outer) {
+        status = CLSIMG_WMAXOUTER;
+        break;
+      }
+      HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+      HIP_TRY(launch_offgrid_sets(state, Q, gamma0, offsets, sigma, st));
+      ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+      nF = c->h_dec->nF;
+      nU = c->h_dec->nU;
+      if (nF > 0 && !lsqr_cu_fits(P, nF)) return CLSIMG_ENOTSUP;  // beyond the one-workgroup LSQR
+      // b = B0 - Psi_U gamma0_U on the grid (eq. bsubproblemLS)
+      ST_TRY(correlate(c, g, P, Ulist, gamma0, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr, nullptr, st));
+      flops += corr_flops(P, nU);
+      const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
+      for (int t = 0; t <= rounds; ++t) {
+        HIP_TRY(xf_off(nF));
+        HIP_TRY(launch_lsqr_setup2(S2, done, bar, lerr, o->atol, o->btol, o->conlim, itnlim, st));
+        if (nF > 0) {
+          LsqrCuParams lc;
+          lc.P = P;
+          lc.n = nF;
+          lc.xf = xf;
+          lc.B = Bb;
+          lc.x_out = x;
+          lc.Sfinal = Sfin;
+          lc.done = done;
+          lc.atol = o->atol;
+          lc.btol = o->btol;
+          lc.conlim = o->conlim;
+          lc.itnlim = itnlim;
+          HIP_TRY(launch_lsqr_cu(lc, st));
+        }
+        if (t == rounds) break;
+        ST_TRY(read_back(c, c->h_lsqr, Sfin, sizeof(LsqrState), st));
+        lsqr_total += c->h_lsqr->itn;
+        if (c->h_lsqr->istop == 7) ++itnlim_hits;
+        flops += nF > 0 ? beam_flops(P, nF) + c->h_lsqr->itn * (corr_flops(P, nF) + beam_flops(P, nF)) : 0.0;
+        // E = Psi(delta)_F z - b, then one Gauss-Newton step per free pixel
+        HIP_TRY(corr_xf(nF, x, nullptr, nullptr));
+        HIP_TRY(launch_newton_offset(E, P, pos, a->lambda, Flist, nF, x, xf, offsets, half_l, half_m, st));
+      }
+      // bounds of the free pixels at their shifted directions
+      HIP_TRY(hipMemcpyAsync(gamma, gamma0, (size_t)Q * sizeof(float), hipMemcpyDeviceToDevice, st));
+      HIP_TRY(launch_gamma_off(bkind, bmat, P, Flist, nF, xf, o->C, bkb, gamma, st));
+      HIP_TRY(launch_step(done, lerr, Sfin, x, x, Flist, nF, sigma, gamma, state, dec, st));
+      // gradient after a feasible subproblem: E = Psi(delta)_F sigma_F - b, multipliers on the grid
+      HIP_TRY(corr_xf(nF, sigma, Flist, grad_stop));
+      HIP_TRY(launch_beam_lambda(nullptr, E, P, tab, grad_stop, state, keys, nullptr, st));
+      HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
+      ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+      const SolveDecision d = *c->h_dec;
+      if (nF > 0 && !d.lsqr_done) return CLSIMG_EHIP;  // the LSQR kernel did not finish
+      ++outer;
+      lsqr_total += d.lsqr_itn;
+      if (nF > 0) flops += beam_flops(P, nF) + d.lsqr_itn * (corr_flops(P, nF) + beam_flops(P, nF));
+      if (d.feasible) flops += corr_flops(P, nF) + beam_flops(P, Q);
+      if (nF > 0 && d.lsqr_istop == 7) ++itnlim_hits;
+      if (d.feasible) {
+        need_solve = false;
+        if (nF > 0) margin_z = std::min(margin_z, (double)d.margin_z);
+        if (d.i_min < 0) break;
+        lam_min = d.lam_min;
+        eps_min = d.eps_min;
+        i_min = d.i_min;
+        st_min = d.st_min;
+      } else {
+        ++drops;
+        need_solve = true;
+        if (d.ib == last_added && d.mu_max == 0.0f) {
+          status = CLSIMG_WCYCLE;
+          break;
+        }
+      }
+      last_added = -1;
+    } else {
+      if (eps_min > 0.f) margin_lambda = std::min(margin_lambda, fabs((double)lam_min + eps_min) / eps_min);
+      if (lam_min < -eps_min) {
+        HIP_TRY(launch_set_state(state, i_min, (uint8_t)CLSIMG_STATE_F, st));
+        ++adds;
+        last_added = i_min;
+        need_solve = true;
+      } else {
+        break;
+      }
+    }
+  }
+  if (status == CLSIMG_OK && itnlim_hits) status = CLSIMG_WITNLIM;
+  // final sets, upper-set powers and offsets; residual ||B0 - Psi_U gamma0_U - Psi(delta)_F sigma_F||
+  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  HIP_TRY(launch_offgrid_sets(state, Q, gamma0, offsets, sigma, st));
+  ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+  nF = c->h_dec->nF;
+  nU = c->h_dec->nU;
+  ST_TRY(correlate(c, g, P, Ulist, gamma0, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr, nullptr, st));
+  HIP_TRY(xf_off(nF));
+  HIP_TRY(corr_xf(nF, sigma, Flist, nullptr));
+  HIP_TRY(launch_frob2(E, P * P, nrm, st));
+  ST_TRY(read_back(c, c->h_norms, nrm, sizeof(double), st));
+  const double rn = sqrt(c->h_norms[0]);
+  stats->status = status;
+  stats->outer_iters = outer;
+  stats->adds = adds;
+  stats->drops = drops;
+  stats->lsqr_iters_total = lsqr_total;
+  stats->lsqr_itnlim_hits = itnlim_hits;
+  stats->nF = nF;
+  stats->nU = nU;
+  stats->rel_residual = b0norm > 0 ? rn / b0norm : 0.0;
+  stats->objective = 0.5 * rn * rn;
+  stats->min_margin_lambda = margin_lambda;
+  stats->min_margin_z = margin_z;
+  stats->psi_flops = flops;
+  return status;
+}
+
 int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const clsimg_opts* o, void* stream) {
   if (!c || !reqs || n < 1) return CLSIMG_EINVAL;
   for (int r = 0; r < n; ++r) memset(&reqs[r].stats, 0, sizeof(clsimg_stats));

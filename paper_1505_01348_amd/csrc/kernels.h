@@ -345,6 +345,17 @@ hipError_t launch_multi_bound(int kind, const float* s1, const float* s2, int Q,
 int lambda_vec_blocks(int Q);
 hipError_t launch_lambda_vec(const float* g, const uint8_t* state, int Q, const int* skip, uint64_t* part,
                              hipStream_t st);
+// offgrid.hip: strong off-grid correction of the free pixels (Sec. III-E)
+hipError_t launch_xf_off(const double* pos, int P, double lam, int nl, double l0, double dl, double m0, double dm,
+                         const int* Flist, int n, const float* delta, float* xf, hipStream_t st);
+hipError_t launch_newton_offset(const float2* E, int P, const double* pos, double lam, const int* Flist, int n,
+                                const float* z, const float* xf, float* delta, float half_l, float half_m,
+                                hipStream_t st);
+hipError_t launch_gamma_off(int kind, const float2* M, int P, const int* Flist, int n, const float* xf, double C,
+                            double kb, float* gamma, hipStream_t st);
+hipError_t launch_offgrid_sets(const uint8_t* state, int Q, const float* gamma0, float* delta, float* sigma,
+                               hipStream_t st);
+hipError_t launch_frob2(const float2* M, int n, double* out, hipStream_t st);
 // lsqr_cu.hip
 bool lsqr_cu_fits(int P, int n);
 hipError_t launch_lsqr_cu(const LsqrCuParams& pr, hipStream_t st);

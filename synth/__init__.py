@@ -13,5 +13,6 @@ from .scenes import (  # noqa: F401
     make_scene,
     make_request_scenes,
     make_block_scenes,
+    make_offgrid_scene,
     exact_covariance,
 )

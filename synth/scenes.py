@@ -253,3 +253,32 @@ def make_block_scenes(config: str = "c0", K: int = 2, rotation: float = 0.05, la
         out.append(Scene(name=f"{config}-block{k}", P=P, pos=pos, lam=lam, nl=n, nm=n, l0=l0, dl=dl, m0=l0, dm=dl,
                          N=rec["N"], noise_var=rec["noise"], src_pix=src_pix, src_pow=src_pow, R_hat=Rh))
     return out
+
+
+def make_offgrid_scene(config: str = "c0", max_offset: float = 0.45, seed=None, **overrides):
+    """The workload with every point source moved off its pixel centre by a
+    uniform offset of up to max_offset pixels in l and in m (the situation of
+    strong off-grid sources).  Returns (scene, offsets) with offsets an S x 2
+    array in direction cosines; scene.src_pix are the pixels that hold the
+    sources."""
+    idx = {"c0": 0, "c1": 1, "c2": 2, "c4": 4}[config]
+    rec = dict(CONFIGS[config])
+    rec.update(overrides)
+    seed = _SEED_BASE + 200 + idx if seed is None else seed
+    s_pos, s_sky, s_off, s_smp = np.random.SeedSequence(seed).spawn(4)
+    P, n = rec["P"], rec["n"]
+    pos = _disc_positions(np.random.default_rng(s_pos), P, rec["radius"])
+    l0, dl = _grid_axis(n, rec["L"])
+    n_pts, law = rec["points"]
+    src_pix, src_pow = _sky(np.random.default_rng(s_sky), n, n, n_pts, law, 0, 6.0, 0.0)
+    off = np.random.default_rng(s_off).uniform(-max_offset, max_offset, size=(len(src_pix), 2)) * dl
+    lam = rec.get("lam", 1.0)
+    l = l0 + (src_pix % n) * dl + off[:, 0]
+    m = l0 + (src_pix // n) * dl + off[:, 1]
+    A = _response(pos, lam, l, m)
+    R = (A * src_pow[None, :]) @ A.conj().T + rec["noise"] * np.eye(P)
+    R = 0.5 * (R + R.conj().T)
+    Rh = _sample_covariance(np.random.default_rng(s_smp), R, rec["N"])
+    sc = Scene(name=f"{config}-offgrid", P=P, pos=pos, lam=lam, nl=n, nm=n, l0=l0, dl=dl, m0=l0, dm=dl,
+               N=rec["N"], noise_var=rec["noise"], src_pix=src_pix, src_pow=src_pow, R_hat=Rh)
+    return sc, off

@@ -92,9 +92,9 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=16, help="Table I steps per server poll")
     ap.add_argument("--serve-workers", type=int, default=4, help="server threads for P > 48 requests")
-    ap.add_argument("--batched-extra", type=int, default=16,
-                    help="after the timed solves, also time batched calls of this many requests of the "
-                         "workload (reported under 'batched'; 0 = skip)")
+    ap.add_argument("--batched-extra", type=str, default="16,256",
+                    help="after the timed solves, also time batched calls of these numbers of requests of "
+                         "the workload, comma separated (reported under 'batched'; 0 = skip)")
     ap.add_argument("--batch", type=int, default=1,
                     help="solve B independent requests of the workload per step (one batched call); "
                          "request 0 is the workload itself, the others redraw its sky and samples")
@@ -103,6 +103,19 @@ def parse():
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "beam_kernel_mf_c1_traffic.md")
 BEAM_SOURCE = os.path.join(ROOT, "paper_1505_01348_amd", "csrc", "beam.hip")
+
+
+def stamped_seconds(call, reps):
+    """Mean device time of `call(start, stop)`, a library call that binds the two
+    timing events to its first and last kernel (the GPU's own timestamps)."""
+    import numpy as np
+    import torch
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        call(a, b)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
 
 
 def measured_traffic():
@@ -528,38 +541,53 @@ def main():
         log(f"bench: the {B} requests solved one by one: {sequential:.2f} solves/s")
 
     batched = None
-    if B == 1 and args.batched_extra > 1 and sc.P <= 48:
+    sizes = sorted({int(x) for x in str(args.batched_extra).split(",") if int(x) > 1})
+    if B == 1 and sizes and sc.P <= 48:
         # the same workload served as batches (clsimg_solve_batch): request 0 is
-        # this covariance, the others redraw sky and samples with other seeds
-        nbx = args.batched_extra
-        breqs = [{"R": R, "geo": geo, "noise_diag": nd}]
-        for k in range(1, nbx):
+        # this covariance, the others redraw sky and samples with other seeds;
+        # one workgroup per request, so up to one request per CU runs at once
+        pool = [{"R": R, "geo": geo, "noise_diag": nd}]
+        for k in range(1, sizes[-1]):
             sk = synth.make_scene(args.config, seed=synth.scenes._SEED_BASE + 1000 * k)
-            breqs.append({"R": torch.as_tensor(sk.R_hat32).cuda(), "geo": clsimg.Geometry(sk.pos, sk.lam, sk.grid),
-                          "noise_diag": torch.as_tensor(sk.noise_diag.astype(np.float32)).cuda()})
-        st0, res0 = ctx.solve_batch(breqs, opts)  # warm-up
-        torch.cuda.synchronize()
-        blat = []
-        tb0 = time.perf_counter()
-        for _ in range(3):
-            t0 = time.perf_counter()
-            stb, resb = ctx.solve_batch(breqs, opts)
+            pool.append({"R": torch.as_tensor(sk.R_hat32).cuda(), "geo": clsimg.Geometry(sk.pos, sk.lam, sk.grid),
+                         "noise_diag": torch.as_tensor(sk.noise_diag.astype(np.float32)).cuda()})
+        sweep = []
+        for nbx in sizes:
+            breqs = pool[:nbx]
+            st0, res0 = ctx.solve_batch(breqs, opts)  # warm-up
             torch.cuda.synchronize()
-            blat.append(time.perf_counter() - t0)
-        tbt = time.perf_counter() - tb0
-        same0 = (resb[0][4]["rel_residual"] == stats["rel_residual"] and
-                 resb[0][4]["lsqr_iters_total"] == stats["lsqr_iters_total"])
-        batched = {"requests_per_call": nbx, "solves_per_s": round(3 * nbx / tbt, 3),
-                   "ms_per_call_p50": round(float(np.percentile(np.array(blat) * 1e3, 50)), 3),
-                   "request0_same_as_alone": bool(same0 and stb >= 0),
-                   "note": "clsimg_solve_batch: one outer-step launch and one multiplier launch per Table I "
-                           "step for all requests; every result equals its solve alone"}
-        log(f"bench: batched {nbx} per call: {batched}")
-        del breqs
+            blat = []
+            bflops = 0.0
+            tb0 = time.perf_counter()
+            for _ in range(3):
+                t0 = time.perf_counter()
+                stb, resb = ctx.solve_batch(breqs, opts)
+                torch.cuda.synchronize()
+                blat.append(time.perf_counter() - t0)
+                bflops += sum(r[4]["psi_flops"] for r in resb)
+            tbt = time.perf_counter() - tb0
+            same0 = (resb[0][4]["rel_residual"] == stats["rel_residual"] and
+                     resb[0][4]["lsqr_iters_total"] == stats["lsqr_iters_total"])
+            sweep.append({"requests_per_call": nbx, "solves_per_s": round(3 * nbx / tbt, 3),
+                          "ms_per_call_p50": round(float(np.percentile(np.array(blat) * 1e3, 50)), 3),
+                          "psi_tflops": round(bflops / tbt / 1e12, 4),
+                          "psi_mfma_frac": round(bflops / tbt / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5),
+                          "request0_same_as_alone": bool(same0 and stb >= 0)})
+            log(f"bench: batched {nbx} per call: {sweep[-1]}")
+        batched = dict(sweep[-1])
+        batched["note"] = ("clsimg_solve_batch: one outer-step launch and one multiplier launch per Table I step "
+                           "for all requests; every result equals its solve alone; psi_tflops counts the "
+                           "dense-count Psi / Psi^H flops of all requests")
+        if len(sweep) > 1:
+            batched["sweep"] = sweep
+        del pool, breqs
 
     # roofline of the full-grid beamforming kernel: the dirty image is one
-    # launch of it.  The calls are captured into a graph and replayed, so the
-    # events see back-to-back kernels rather than the host's call overhead.
+    # launch of it.  Its time per launch is the span of a replayed graph of
+    # `reps` back-to-back launches divided by `reps` (it includes the dispatch
+    # gaps between the kernels, so the rate is a lower bound).  The kernel's
+    # own device timestamps (clsimg_dirty_image_timed: events bound to the
+    # launch itself) of `reps` separate launches are reported beside it.
     reps = args.kernel_reps
     P = sc.P
     out = torch.empty(Q, dtype=torch.float32, device="cuda")
@@ -588,6 +616,9 @@ def main():
         ev1.record()
     torch.cuda.synchronize()
     t_kernel = ev0.elapsed_time(ev1) / 1e3 / reps
+    t_alone = stamped_seconds(lambda a, b: ctx.dirty_image_timed(R, geo, a, b, mf=out), reps)
+    log(f"bench: dirty image {t_kernel * 1e6:.2f} us per launch over a {timing} of {reps}, "
+        f"{t_alone * 1e6:.2f} us device time of a launch alone")
     kflops = 8.0 * P * P * Q + 8.0 * P * Q  # dense count of one full-grid adjoint
     MT = -(-P // 8)
     if MT <= 6:  # register-resident kernel: block triangle of Ut, each off-diagonal block used twice
@@ -599,7 +630,7 @@ def main():
         kname = f"beam_prep_full + beam_big_kernel<{rpw}, BeamMF> (dirty image, full grid)"
         exec_flops = 2.0 * (64 * rpw) * (16 * MT) * (-(-Q // (16 * nt)) * 16 * nt)
     achieved = kflops / t_kernel / 1e12
-    log(f"bench: beam kernel {t_kernel * 1e6:.2f} us/launch ({timing}), {achieved:.2f} TFLOP/s dense count, "
+    log(f"bench: beam kernel {t_kernel * 1e6:.2f} us/launch, {achieved:.2f} TFLOP/s dense count, "
         f"{exec_flops / t_kernel / 1e12:.2f} TFLOP/s issued MFMA")
 
     # the same operation at the largest workload's full size (288 antennas,
@@ -617,14 +648,7 @@ def main():
             for _ in range(3):
                 ctx.dirty_image(Rb, gb, mf=ob, precision=prec)
             torch.cuda.synchronize()
-            reps_b = 20
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps_b):
-                ctx.dirty_image(Rb, gb, mf=ob, precision=prec)
-            e1.record()
-            torch.cuda.synchronize()
-            tb = e0.elapsed_time(e1) / 1e3 / reps_b
+            tb = stamped_seconds(lambda a, b: ctx.dirty_image_timed(Rb, gb, a, b, mf=ob, precision=prec), 20)
             dense = fb / tb / 1e12
             if prec == 0:
                 by[name] = {"kernel": "beam_prep_full + beam_big_kernel<9, BeamMF>", "bound": "mfma",
@@ -642,7 +666,9 @@ def main():
         for name in ("fp16", "bf16"):
             by[name]["speedup_vs_fp32"] = round(by["fp32"]["us_per_launch"] / by[name]["us_per_launch"], 3)
         big = dict(by["fp32"], workload="P=288, 512x512 pixels (the 288-antenna workload's size)",
-                   flops_per_launch=fb, timing="eager (each call is milliseconds long)", by_precision=by)
+                   flops_per_launch=fb, by_precision=by,
+                   timing="device timestamps from the start of the first kernel (fragment preparation) to the "
+                          "end of the beamformer, mean of 20 calls")
         del Rb, ob
 
     lat_ms = np.array(lat) * 1e3
@@ -676,7 +702,9 @@ def main():
                      "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 5),
                      "traffic": measured_traffic() if args.config == "c1" else None,
-                     "us_per_launch": round(t_kernel * 1e6, 3), "timing": timing,
+                     "us_per_launch": round(t_kernel * 1e6, 3),
+                     "timing": f"{timing} of {reps} back-to-back launches (span / {reps})",
+                     "us_device_launch_alone": round(t_alone * 1e6, 3),
                      "flops_per_launch": kflops, "mfma_issued_flops_per_launch": exec_flops,
                      "mfma_issued_frac": round(exec_flops / t_kernel / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5)},
     }

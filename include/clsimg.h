@@ -148,6 +148,17 @@ int clsimg_destroy(clsimg_ctx* ctx);
 int clsimg_dirty_image(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array,
                        const clsimg_grid* grid, int32_t precision, float* mf, void* stream);
 
+/* The same dirty image with the device's own timestamps of its kernels, for
+ * measuring the beamformer without the launch gaps around it: the start of the
+ * first kernel is recorded into `start_event` and the end of the last kernel
+ * into `stop_event` (hipEvent_t handles created by the caller with timing
+ * enabled, passed as void*), so that hipEventElapsedTime(start, stop) is the
+ * kernels' device time.  Both events must be non-null.  Arrays above
+ * CLSIMG_MAX_P antennas (no full-grid beamformer) return CLSIMG_ENOTSUP. */
+int clsimg_dirty_image_timed(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array,
+                             const clsimg_grid* grid, int32_t precision, float* mf, void* start_event,
+                             void* stop_event, void* stream);
+
 /* Upper bound gamma of the box constraint (eq. CLS):
  *   MVDR (eq. wmvdr, Sec. II-D): h_i = a_i^H R^-1 a_i with R = L L^H factored in
  *        FP64 on the device; gamma_i = C/h_i + kappa_b / (h_i sqrt(N-P-1));

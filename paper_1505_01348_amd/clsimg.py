@@ -28,7 +28,7 @@ STATE_L, STATE_F, STATE_U = 0, 1, 2
 MAX_P = 288
 
 EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
-            "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
+            "clsimg_dirty_image_timed", "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
             "clsimg_solve_batch", "clsimg_solve_multi", "clsimg_solve_offgrid", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
             "clsimg_server_query", "clsimg_server_destroy", "clsimg_strerror")
 
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.clsimg_create.argtypes = [C.POINTER(vp), i32, sz]
     lib.clsimg_destroy.argtypes = [vp]
     lib.clsimg_dirty_image.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp]
+    lib.clsimg_dirty_image_timed.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp, vp, vp]
     lib.clsimg_mvdr_bound.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), C.POINTER(COpts),
                                       vp, vp]
     lib.clsimg_forward.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp, i32, vp, vp]
@@ -242,6 +243,23 @@ class Context:
         self._check(self._lib.clsimg_dirty_image(self._h, _ptr(R), C.byref(geo.c_array),
                                                  C.byref(geo.c_grid), int(precision), _ptr(mf), _stream()),
                     "clsimg_dirty_image")
+        return mf
+
+    def dirty_image_timed(self, R, geo: Geometry, start, stop, mf=None, precision: int = FP32):
+        """dirty_image with the kernels' own device timestamps recorded into two
+        timing events (torch.cuda.Event(enable_timing=True)); start.elapsed_time(stop)
+        is then the kernels' device time in ms."""
+        dev = self.device
+        _need(R, torch.complex64, geo.P * geo.P, "R", dev)
+        mf = torch.empty(geo.Q, dtype=torch.float32, device=R.device) if mf is None else mf
+        _need(mf, torch.float32, geo.Q, "mf", dev)
+        for ev in (start, stop):  # torch creates the HIP event at its first record
+            if not ev.cuda_event:
+                ev.record()
+        self._check(self._lib.clsimg_dirty_image_timed(self._h, _ptr(R), C.byref(geo.c_array), C.byref(geo.c_grid),
+                                                       int(precision), _ptr(mf), C.c_void_p(start.cuda_event),
+                                                       C.c_void_p(stop.cuda_event), _stream()),
+                    "clsimg_dirty_image_timed")
         return mf
 
     def mvdr_bound(self, R, geo: Geometry, opts: Options | None = None, gamma=None):

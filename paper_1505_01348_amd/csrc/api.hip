@@ -51,7 +51,7 @@ struct clsimg_ctx {
   DevBuf lsqr2, done, x1, w1, vraw, bpart0, bpart1, xf, bar;  // fused LSQR step
   DevBuf ostate;                                                // device-resident outer loop
   DevBuf pw_h, pw_rs, pw_g, pw_eps, pw_dinv, pw_Lw, pw_B0w;      // PWLS inputs
-  DevBuf batch, batch_params;                                   // batched solve workspace
+  DevBuf batch, batch_params, batch_rinv;                       // batched solve workspace
   char* h_batch = nullptr;                                      // pinned staging of the batch
   size_t h_batch_bytes = 0;
   SolveDecision* h_dec = nullptr;
@@ -349,31 +349,35 @@ bool beam_any(int P) { return beam_fits(P) || beam_big_fits(P); }
 // fragments are prepared once and streamed by the GEMM-shaped kernel.
 enum BeamKind { BEAM_MF, BEAM_MVDR, BEAM_STORE };
 int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamKind kind, float* out,
-              float* eps, float eps_scale, double C, double kb, float scale, hipStream_t st) {
+              float* eps, float eps_scale, double C, double kb, float scale, hipStream_t st, Stamps ts = {}) {
   const Tables tab = tables_of(c, g, P);
+  const Stamps first{ts.start, nullptr}, last{nullptr, ts.stop};  // a preparation pass, then the beamformer
   if (c->prec != CLSIMG_FP32) {  // split half precision, GEMM-shaped kernel for every P
     const bool bf = c->prec == CLSIMG_BF16;
     ST_TRY(ensure(c, c->frag_h, beam_h16_frag_bytes(P)));
     ST_TRY(ensure(c, c->hscale, sizeof(float)));
-    HIP_TRY(launch_beam_prep_h16(U, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st));
+    HIP_TRY(launch_beam_prep_h16(U, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st, first));
     const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
     HIP_TRY(launch_beam_h16(k, bf, c->frag_h.ptr, P_<const float>(c->hscale), tab, nullptr, out, eps, eps_scale, C,
-                            kb, scale, nullptr, nullptr, st));
+                            kb, scale, nullptr, nullptr, st, last));
     return CLSIMG_OK;
   }
   if (!beam_fits(P)) {  // larger arrays: fragments of the whole Ut, GEMM-shaped kernel
-    HIP_TRY(launch_beam_prep_full(U, P, P_<float>(c->frag_b), st));
+    HIP_TRY(launch_beam_prep_full(U, P, P_<float>(c->frag_b), st, first));
     const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
     HIP_TRY(launch_beam_big(k, P_<const float>(c->frag_b), tab, nullptr, out, eps, eps_scale, C, kb, scale,
-                            nullptr, nullptr, st));
+                            nullptr, nullptr, st, last));
     return CLSIMG_OK;
   }
   // fragments built inside the kernel, or prepared by a separate pass
   const float* fb = c->beam_prep ? P_<float>(c->frag_b) : nullptr;
   const float2* Uk = c->beam_prep ? nullptr : U;
-  if (c->beam_prep) HIP_TRY(launch_beam_prep(U, P, P_<float>(c->frag_b), st));
+  if (c->beam_prep) {
+    HIP_TRY(launch_beam_prep(U, P, P_<float>(c->frag_b), st, first));
+    ts = last;
+  }
   switch (kind) {
-    case BEAM_MF: HIP_TRY(launch_beam_mf(fb, Uk, P, tab, out, eps, eps_scale, st)); break;
+    case BEAM_MF: HIP_TRY(launch_beam_mf(fb, Uk, P, tab, out, eps, eps_scale, st, ts)); break;
     case BEAM_MVDR: HIP_TRY(launch_beam_mvdr(fb, Uk, P, tab, out, C, kb, st)); break;
     default: HIP_TRY(launch_beam_store(fb, Uk, P, tab, out, scale, st)); break;
   }
@@ -394,7 +398,7 @@ double sum_host(const double* p, int n) {
 
 // MVDR / MF / NONE upper bound into `gamma`; MF image into `mf` if given.
 int compute_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
-                  const clsimg_opts* o, float* gamma, hipStream_t st) {
+                  const clsimg_opts* o, float* gamma, hipStream_t st, const float2* rinv = nullptr) {
   const int P = a->P, Q = g->nl * g->nm;
   const float2* Rf = reinterpret_cast<const float2*>(R);
   if (o->bound == CLSIMG_BOUND_NONE) {
@@ -408,15 +412,16 @@ int compute_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, con
                                  (float)scale, st));
     return CLSIMG_OK;
   }
-  HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
-                              P_<int>(c->status), st));
-  ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
-  if (*c->h_status != 0) return CLSIMG_ENOTPD;
+  if (!rinv) {  // else factored and checked beforehand (batched factorisation)
+    HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
+                                P_<int>(c->status), st));
+    ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
+    if (*c->h_status != 0) return CLSIMG_ENOTPD;
+    rinv = P_<const float2>(c->Rinv);
+  }
   const double kb = o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1)) : 0.0;
-  if (beam_any(P))
-    return beam_full(c, g, P, P_<const float2>(c->Rinv), BEAM_MVDR, gamma, nullptr, 0.f, o->C, kb, 1.f, st);
-  HIP_TRY(launch_adjoint_mvdr(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, P_<const float2>(c->Rinv)),
-                              gamma, o->C, kb, st));
+  if (beam_any(P)) return beam_full(c, g, P, rinv, BEAM_MVDR, gamma, nullptr, 0.f, o->C, kb, 1.f, st);
+  HIP_TRY(launch_adjoint_mvdr(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, rinv), gamma, o->C, kb, st));
   return CLSIMG_OK;
 }
 
@@ -475,7 +480,7 @@ ReqLayout request_layout(int P, int nl, int nm, bool pwls, int nkeys) {
 }
 
 int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L,
-                  OuterParams& op, BeamLamItem& it, hipStream_t st) {
+                  OuterParams& op, BeamLamItem& it, hipStream_t st, const float2* rinv) {
   memset(&q.stats, 0, sizeof(clsimg_stats));
   c->prec = o->precision;
   const int P = q.array.P, Pp = pad_p(P);
@@ -504,7 +509,7 @@ int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* 
   float* gamma = q.gamma ? q.gamma : reinterpret_cast<float*>(slice + L.gam);
   float2* B0 = reinterpret_cast<float2*>(slice + L.B0);
   ST_TRY(beam_full(c, &q.grid, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
-  ST_TRY(compute_bound(c, q.R, &q.array, &q.grid, o, gamma, st));
+  ST_TRY(compute_bound(c, q.R, &q.array, &q.grid, o, gamma, st, rinv));
   const float* op_gamma = gamma;
   const float* rowscale = nullptr;
   const float2* Lw = nullptr;
@@ -669,7 +674,7 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (!c) return CLSIMG_EINVAL;
   DeviceGuard guard(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->batch, &c->batch_params, &c->part,  &c->beta_part,
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->batch, &c->batch_params, &c->batch_rinv, &c->part,  &c->beta_part,
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
@@ -717,6 +722,22 @@ int clsimg_dirty_image(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a
   if (beam_any(P)) return beam_full(c, g, P, Rf, BEAM_MF, mf, nullptr, 0.f, 0, 0, 1.f, st);
   HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, nullptr, 0.f, st));
   return CLSIMG_OK;
+}
+
+int clsimg_dirty_image_timed(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
+                             int32_t precision, float* mf, void* start_event, void* stop_event, void* stream) {
+  if (!c || !R || !mf || !start_event || !stop_event) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  if (precision != CLSIMG_FP32 && precision != CLSIMG_FP16 && precision != CLSIMG_BF16) return CLSIMG_EINVAL;
+  if (!beam_any(a->P)) return CLSIMG_ENOTSUP;
+  c->prec = precision;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int P = a->P, Q = g->nl * g->nm;
+  ST_TRY(ensure_workspace(c, P, Q));
+  ST_TRY(ensure_tables(c, a, g, st));
+  const Stamps ts{(hipEvent_t)start_event, (hipEvent_t)stop_event};
+  return beam_full(c, g, P, reinterpret_cast<const float2*>(R), BEAM_MF, mf, nullptr, 0.f, 0, 0, 1.f, st, ts);
 }
 
 int clsimg_mvdr_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a,
@@ -1805,9 +1826,14 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   const int bpr = beam_grid(Qmax);  // multiplier blocks per request in the launch
   const ReqLayout L = request_layout(P, nlmax, nmmax, pwls, bpr);
   ST_TRY(ensure(c, c->batch, L.bytes * n));
+  // device parameters: outer-step parameters and multiplier items, then the
+  // gathered outer states, the factorisation items and their statuses
   const size_t pbytes = (size_t)n * (sizeof(OuterParams) + sizeof(BeamLamItem));
-  ST_TRY(ensure(c, c->batch_params, pbytes));
-  const size_t hbytes = std::max(pbytes, (size_t)n * sizeof(OuterState));
+  const size_t off_st = (pbytes + 255) & ~(size_t)255;
+  const size_t off_ci = (off_st + (size_t)n * sizeof(OuterState) + 255) & ~(size_t)255;
+  const size_t off_cs = (off_ci + (size_t)n * sizeof(CholItem) + 255) & ~(size_t)255;
+  ST_TRY(ensure(c, c->batch_params, off_cs + (size_t)n * sizeof(int)));
+  const size_t hbytes = std::max({pbytes, (size_t)n * sizeof(OuterState), (size_t)n * sizeof(CholItem)});
   if (c->h_batch_bytes < hbytes) {
     if (c->h_batch) {
       HIP_TRY(hipStreamSynchronize(st));
@@ -1822,9 +1848,30 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   }
   char* base = P_<char>(c->batch);
   auto slice = [&](int r) { return base + (size_t)r * L.bytes; };
+  char* dbase = P_<char>(c->batch_params);
+  // MVDR bound of the least-squares cost: every request's R^-1 from one
+  // factorisation launch (one workgroup each), checked with one read-back
+  const float2* rinv = nullptr;
+  if (!pwls && o->bound == CLSIMG_BOUND_MVDR && P <= kCholLdsMaxP) {
+    ST_TRY(ensure(c, c->batch_rinv, (size_t)n * P * P * sizeof(float2)));
+    CholItem* hc = reinterpret_cast<CholItem*>(c->h_batch);
+    int* dstat = reinterpret_cast<int*>(dbase + off_cs);
+    for (int r = 0; r < n; ++r)
+      hc[r] = CholItem{reinterpret_cast<const float2*>(reqs[r].R), nullptr,
+                       P_<float2>(c->batch_rinv) + (size_t)r * P * P, dstat + r};
+    CholItem* dc = reinterpret_cast<CholItem*>(dbase + off_ci);
+    HIP_TRY(hipMemcpyAsync(dc, hc, (size_t)n * sizeof(CholItem), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_chol_inverse_batch(dc, n, P, st));
+    int* hstat = reinterpret_cast<int*>(c->h_batch);  // the items' upload is done once this copy is
+    ST_TRY(read_back(c, hstat, dstat, (size_t)n * sizeof(int), st));
+    for (int r = 0; r < n; ++r)
+      if (hstat[r] != 0) return CLSIMG_ENOTPD;
+    rinv = P_<const float2>(c->batch_rinv);
+  }
   OuterParams* hp = reinterpret_cast<OuterParams*>(c->h_batch);
   BeamLamItem* hi = reinterpret_cast<BeamLamItem*>(c->h_batch + (size_t)n * sizeof(OuterParams));
-  for (int r = 0; r < n; ++r) ST_TRY(request_setup(c, reqs[r], o, slice(r), L, hp[r], hi[r], st));
+  for (int r = 0; r < n; ++r)
+    ST_TRY(request_setup(c, reqs[r], o, slice(r), L, hp[r], hi[r], st, rinv ? rinv + (size_t)r * P * P : nullptr));
   OuterParams* dp = P_<OuterParams>(c->batch_params);
   BeamLamItem* di = reinterpret_cast<BeamLamItem*>(P_<char>(c->batch_params) + (size_t)n * sizeof(OuterParams));
   HIP_TRY(hipMemcpyAsync(dp, c->h_batch, pbytes, hipMemcpyHostToDevice, st));
@@ -1838,8 +1885,9 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
       HIP_TRY(launch_beam_lambda_batch(di, n, bpr, P, st));
     }
     OuterState* hs = reinterpret_cast<OuterState*>(c->h_batch);
-    for (int r = 0; r < n; ++r)
-      HIP_TRY(hipMemcpyAsync(hs + r, slice(r) + L.st, sizeof(OuterState), hipMemcpyDeviceToHost, st));
+    OuterState* ds = reinterpret_cast<OuterState*>(dbase + off_st);
+    HIP_TRY(launch_gather_states(dp, n, ds, st));
+    HIP_TRY(hipMemcpyAsync(hs, ds, (size_t)n * sizeof(OuterState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     bool all = true;
     for (int r = 0; r < n; ++r) all = all && hs[r].done;

@@ -661,52 +661,54 @@ int beam_grid(int Q) {
   return g < 1 ? 1 : (g > 2048 ? 2048 : g);
 }
 
-hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st) {
+hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st, Stamps ts) {
   const int MT = pad_p(P) / 8;
   const int n = 2 * MT * (MT + 1) * 64;
-  hipLaunchKernelGGL(beam_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, U, P, MT, frag);
+  hipExtLaunchKernelGGL(beam_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, ts.start, ts.stop, 0, U, P, MT,
+                        frag);
   return hipGetLastError();
 }
 
 template <class Epi>
 static hipError_t launch_beam(const float* frag, const float2* U, int P, const Tables& tab, const int* skip,
-                              Epi epi, hipStream_t st) {
+                              Epi epi, hipStream_t st, Stamps ts = {}) {
   const dim3 g(beam_grid(tab.Q)), b(64 * kBeamWaves);
   switch (tab.Pp / 8) {
-    case 1: hipLaunchKernelGGL((beam_kernel<1, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
-    case 2: hipLaunchKernelGGL((beam_kernel<2, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
-    case 3: hipLaunchKernelGGL((beam_kernel<3, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
-    case 4: hipLaunchKernelGGL((beam_kernel<4, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
-    case 5: hipLaunchKernelGGL((beam_kernel<5, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
-    case 6: hipLaunchKernelGGL((beam_kernel<6, Epi>), g, b, 0, st, frag, U, P, tab, skip, epi); break;
+    case 1: hipExtLaunchKernelGGL((beam_kernel<1, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, U, P, tab, skip, epi); break;
+    case 2: hipExtLaunchKernelGGL((beam_kernel<2, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, U, P, tab, skip, epi); break;
+    case 3: hipExtLaunchKernelGGL((beam_kernel<3, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, U, P, tab, skip, epi); break;
+    case 4: hipExtLaunchKernelGGL((beam_kernel<4, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, U, P, tab, skip, epi); break;
+    case 5: hipExtLaunchKernelGGL((beam_kernel<5, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, U, P, tab, skip, epi); break;
+    case 6: hipExtLaunchKernelGGL((beam_kernel<6, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, U, P, tab, skip, epi); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st) {
+hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st, Stamps ts) {
   const int MT = pad_p(P) / 8;
   const size_t n = beam_big_frag_floats(P);
   int g = (int)((n + 255) / 256);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(beam_prep_full_kernel, dim3(g), dim3(256), 0, st, U, P, MT, frag);
+  hipExtLaunchKernelGGL(beam_prep_full_kernel, dim3(g), dim3(256), 0, st, ts.start, ts.stop, 0, U, P, MT, frag);
   return hipGetLastError();
 }
 
 template <class Epi>
-static hipError_t launch_big(const float* frag, const Tables& tab, const int* skip, Epi epi, hipStream_t st) {
+static hipError_t launch_big(const float* frag, const Tables& tab, const int* skip, Epi epi, hipStream_t st,
+                             Stamps ts = {}) {
   const int MT = tab.Pp / 8;
   const dim3 g(beam_big_grid(tab.Pp, tab.Q)), b(256);
   switch (big_rpw(MT)) {
-    case 1: hipLaunchKernelGGL((beam_big_kernel<1, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 2: hipLaunchKernelGGL((beam_big_kernel<2, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 3: hipLaunchKernelGGL((beam_big_kernel<3, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 4: hipLaunchKernelGGL((beam_big_kernel<4, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 5: hipLaunchKernelGGL((beam_big_kernel<5, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 6: hipLaunchKernelGGL((beam_big_kernel<6, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 7: hipLaunchKernelGGL((beam_big_kernel<7, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 8: hipLaunchKernelGGL((beam_big_kernel<8, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
-    case 9: hipLaunchKernelGGL((beam_big_kernel<9, Epi>), g, b, 0, st, frag, MT, tab, skip, epi); break;
+    case 1: hipExtLaunchKernelGGL((beam_big_kernel<1, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 2: hipExtLaunchKernelGGL((beam_big_kernel<2, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 3: hipExtLaunchKernelGGL((beam_big_kernel<3, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 4: hipExtLaunchKernelGGL((beam_big_kernel<4, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 5: hipExtLaunchKernelGGL((beam_big_kernel<5, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 6: hipExtLaunchKernelGGL((beam_big_kernel<6, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 7: hipExtLaunchKernelGGL((beam_big_kernel<7, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 8: hipExtLaunchKernelGGL((beam_big_kernel<8, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+    case 9: hipExtLaunchKernelGGL((beam_big_kernel<9, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -714,12 +716,12 @@ static hipError_t launch_big(const float* frag, const Tables& tab, const int* sk
 
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
-                           hipStream_t st) {
+                           hipStream_t st, Stamps ts) {
   switch (kind) {
-    case 0: return launch_big(frag, tab, skip, BeamMF{out, eps, eps_scale}, st);
-    case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st);
-    case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st);
-    default: return launch_big(frag, tab, skip, BeamLambda{state, part, nullptr, 0}, st);
+    case 0: return launch_big(frag, tab, skip, BeamMF{out, eps, eps_scale}, st, ts);
+    case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st, ts);
+    case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st, ts);
+    default: return launch_big(frag, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts);
   }
 }
 
@@ -733,7 +735,7 @@ size_t beam_h16_frag_bytes(int P) {
 
 template <bool BF, class Epi>
 static hipError_t launch_h16(const void* frag, const float* scale, const Tables& tab, const int* skip, Epi epi,
-                             hipStream_t st) {
+                             hipStream_t st, Stamps ts = {}) {
   typedef typename Half<BF>::V V;
   const int MT = tab.Pp / 8, KC = beam_h16_chunks(tab.Pp);
   // steering entries scaled towards unit magnitude (|a_p| = P^-1/2): a power of two
@@ -744,7 +746,10 @@ static hipError_t launch_h16(const void* frag, const float* scale, const Tables&
   const dim3 g(beam_big_grid(tab.Pp, tab.Q)), b(256);
   switch (big_rpw(MT)) {
 #define H16_CASE(R) \
-  case R: hipLaunchKernelGGL((beam_h16_kernel<R, BF, Epi>), g, b, 0, st, f, MT, KC, scale, sB, tab, skip, epi); break;
+  case R:                                                                                                    \
+    hipExtLaunchKernelGGL((beam_h16_kernel<R, BF, Epi>), g, b, 0, st, ts.start, ts.stop, 0, f, MT, KC, scale, sB, \
+                          tab, skip, epi);                                                                     \
+    break;
     H16_CASE(1)
     H16_CASE(2)
     H16_CASE(3)
@@ -760,39 +765,42 @@ static hipError_t launch_h16(const void* frag, const float* scale, const Tables&
   return hipGetLastError();
 }
 
-hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, float* scale, hipStream_t st) {
+hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, float* scale, hipStream_t st,
+                                Stamps ts) {
   const int MT = pad_p(P) / 8, KC = beam_h16_chunks(P);
-  if (!bf16) {
-    hipLaunchKernelGGL(beam_h16_scale_kernel, dim3(1), dim3(1024), 0, st, U, P * P, scale);
+  if (!bf16) {  // the scale pass comes first: it takes the start stamp
+    hipExtLaunchKernelGGL(beam_h16_scale_kernel, dim3(1), dim3(1024), 0, st, ts.start, (hipEvent_t) nullptr, 0, U,
+                          P * P, scale);
+    ts.start = nullptr;
   }
   const int total = 4 * big_rpw(MT) * KC * 64;
   const int g = std::min((total + 255) / 256, 4096);
   if (bf16)
-    hipLaunchKernelGGL(beam_prep_h16_kernel<true>, dim3(g), dim3(256), 0, st, U, P, MT, KC, (const float*)nullptr,
-                       static_cast<v8b*>(frag));
+    hipExtLaunchKernelGGL(beam_prep_h16_kernel<true>, dim3(g), dim3(256), 0, st, ts.start, ts.stop, 0, U, P, MT, KC,
+                          (const float*)nullptr, static_cast<v8b*>(frag));
   else
-    hipLaunchKernelGGL(beam_prep_h16_kernel<false>, dim3(g), dim3(256), 0, st, U, P, MT, KC, (const float*)scale,
-                       static_cast<v8h*>(frag));
+    hipExtLaunchKernelGGL(beam_prep_h16_kernel<false>, dim3(g), dim3(256), 0, st, ts.start, ts.stop, 0, U, P, MT, KC,
+                          (const float*)scale, static_cast<v8h*>(frag));
   return hipGetLastError();
 }
 
 hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* scale, const Tables& tab,
                            const int* skip, float* out, float* eps, float eps_scale, double C, double kb, float sc,
-                           const uint8_t* state, uint64_t* part, hipStream_t st) {
+                           const uint8_t* state, uint64_t* part, hipStream_t st, Stamps ts) {
   const float* s = bf16 ? nullptr : scale;
   switch (kind) {
     case 0:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st)
-                  : launch_h16<false>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st, ts)
+                  : launch_h16<false>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st, ts);
     case 1:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st)
-                  : launch_h16<false>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st, ts)
+                  : launch_h16<false>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st, ts);
     case 2:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamStore{out, sc}, st)
-                  : launch_h16<false>(frag, s, tab, skip, BeamStore{out, sc}, st);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamStore{out, sc}, st, ts)
+                  : launch_h16<false>(frag, s, tab, skip, BeamStore{out, sc}, st, ts);
     default:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st)
-                  : launch_h16<false>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts)
+                  : launch_h16<false>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts);
   }
 }
 
@@ -814,8 +822,8 @@ hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, con
 }
 
 hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,
-                          float eps_scale, hipStream_t st) {
-  return launch_beam(frag, U, P, tab, nullptr, BeamMF{mf, eps, eps_scale}, st);
+                          float eps_scale, hipStream_t st, Stamps ts) {
+  return launch_beam(frag, U, P, tab, nullptr, BeamMF{mf, eps, eps_scale}, st, ts);
 }
 
 hipError_t launch_beam_mvdr(const float* frag, const float2* U, int P, const Tables& tab, float* gamma, double C,

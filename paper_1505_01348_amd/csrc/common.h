@@ -25,6 +25,7 @@
 //    one contiguous 256-byte load.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

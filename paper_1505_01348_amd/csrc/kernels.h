@@ -287,13 +287,20 @@ hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta
                                double* alpha_part, int init, hipStream_t st);
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st);
 int adjoint_lsqr2_tile_width(int MT, int n);
+// optional device timestamps of a launch sequence (hipExtLaunchKernel): the
+// start of its first kernel goes to `start`, the end of its last kernel to
+// `stop`; null events record nothing
+struct Stamps {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
 // beam.hip (register-resident full-grid beamformer, P <= 48)
 bool beam_fits(int P);
 int beam_grid(int Q);  // workgroups of a full-grid launch (= partial keys of the lambda variant)
-hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st);
+hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st, Stamps ts = {});
 // the fragments come from frag (beam_prep layout) when U is null, else are built from U
 hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,
-                          float eps_scale, hipStream_t st);
+                          float eps_scale, hipStream_t st, Stamps ts = {});
 hipError_t launch_beam_mvdr(const float* frag, const float2* U, int P, const Tables& tab, float* gamma, double C,
                             double kb_coef, hipStream_t st);
 hipError_t launch_beam_store(const float* frag, const float2* U, int P, const Tables& tab, float* out,
@@ -319,19 +326,20 @@ hipError_t launch_beam_lambda_batch(const BeamLamItem* items, int nreq, int bpr,
 bool beam_big_fits(int P);
 size_t beam_big_frag_floats(int P);
 int beam_big_grid(int P, int Q);  // workgroups (= partial keys of the lambda variant)
-hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st);
+hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st, Stamps ts = {});
 // kind: 0 MF (+ threshold), 1 MVDR bound, 2 store (scaled), 3 multipliers with argmin keys
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
-                           hipStream_t st);
+                           hipStream_t st, Stamps ts = {});
 // the same full-grid products in split half precision (FP16 with power-of-two
 // scaling, or BF16): fragments and scale prepared by launch_beam_prep_h16
 int beam_h16_chunks(int P);
 size_t beam_h16_frag_bytes(int P);
-hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, float* scale, hipStream_t st);
+hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, float* scale, hipStream_t st,
+                                Stamps ts = {});
 hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* scale, const Tables& tab,
                            const int* skip, float* out, float* eps, float eps_scale, double C, double kb, float sc,
-                           const uint8_t* state, uint64_t* part, hipStream_t st);
+                           const uint8_t* state, uint64_t* part, hipStream_t st, Stamps ts = {});
 // sums over covariance blocks of the full-grid beamformer (any P, any precision:
 // prec 0 FP32, 1 FP16 split, 2 BF16 split); frag_big / frag_half / hscale are
 // the scratch of the GEMM-shaped and half-precision kernels
@@ -376,6 +384,16 @@ int reduce_blocks(int P);
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st);
 hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, float2* Rinv,
                                int* status, hipStream_t st);
+// one covariance of a batched factorisation (P <= kCholLdsMaxP, LDS-resident)
+constexpr int kCholLdsMaxP = 64;
+struct CholItem {
+  const float2* R;  // P x P complex64
+  double2* Li;      // L^-1 (P x P, FP64) or null
+  float2* Rinv;     // R^-1 as complex64
+  int* status;      // 0 ok, 1 not positive definite, 2 non-finite entry
+};
+// items: DEVICE array of n; one workgroup each
+hipError_t launch_chol_inverse_batch(const CholItem* items, int n, int P, hipStream_t st);
 hipError_t launch_tables(const double* pos, int P, double lambda, int nl, int nm, double l0,
                          double dl, double m0, double dm, float2* El, float2* Em, hipStream_t st);
 hipError_t launch_sub_diag(const float2* R, const float* noise, int P, float2* B0, hipStream_t st);
@@ -454,6 +472,8 @@ hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream
 hipError_t launch_outer_step(const OuterParams& pr, hipStream_t s);
 // prs: device array of nreq parameter sets with the same P
 hipError_t launch_outer_step_batch(const OuterParams* prs, int nreq, int P, hipStream_t s);
+// copies every request's outer state (prs[r].st) to out[r] (device)
+hipError_t launch_gather_states(const OuterParams* prs, int n, OuterState* out, hipStream_t s);
 hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int nbeta,
                                     const double* alpha_part, int nalpha, float* v, float* w,
                                     float* x, int n, double atol, double btol, double conlim,

@@ -532,6 +532,87 @@ __global__ __launch_bounds__(1024) void chol_inverse_kernel(const float2* __rest
   if (tid == 0) *status = 0;
 }
 
+// The same factorisation and inverse with both triangles resident in LDS
+// (P <= kCholLdsMaxP), one workgroup per item: identical arithmetic in the
+// same order, so the results are the same bits; the global-memory version
+// above serves larger arrays.  Per column: every thread reads the pivot and
+// scales its rows of the column, one barrier, the trailing update (and the
+// pivot's own store), one barrier.
+__global__ __launch_bounds__(256) void chol_inverse_lds_kernel(CholItem one, const CholItem* __restrict__ many,
+                                                               int P) {
+  __shared__ double2 W[kCholLdsMaxP * (kCholLdsMaxP + 1)];
+  __shared__ double2 Li[kCholLdsMaxP * (kCholLdsMaxP + 1)];
+  __shared__ int bad;
+  const CholItem it = many ? many[blockIdx.x] : one;
+  const int tid = threadIdx.x, nt = blockDim.x, LD = P + 1;  // padded rows: column walks spread over the banks
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int e = tid; e < P * P; e += nt) {
+    const float2 v = it.R[e];
+    if (!isfinite(v.x) || !isfinite(v.y)) bad = 2;
+    W[(e / P) * LD + e % P] = make_double2((double)v.x, (double)v.y);
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) *it.status = bad;
+    return;
+  }
+  for (int j = 0; j < P; ++j) {
+    const double d = W[j * LD + j].x;  // same value in every thread: the exit below is uniform
+    if (!(d > 0.0)) {
+      if (tid == 0) *it.status = 1;
+      return;
+    }
+    const double ljj = sqrt(d);
+    for (int i = j + 1 + tid; i < P; i += nt) {
+      const double2 v = W[i * LD + j];
+      W[i * LD + j] = make_double2(v.x / ljj, v.y / ljj);
+    }
+    __syncthreads();
+    if (tid == 0) W[j * LD + j] = make_double2(ljj, 0.0);  // nobody reads the pivot in this phase
+    const int m = P - j - 1;
+    for (int e = tid; e < m * m; e += nt) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) {
+        const double2 a = W[i * LD + j], b = W[k * LD + j];
+        double2 w = W[i * LD + k];
+        w.x -= a.x * b.x + a.y * b.y;
+        w.y -= a.y * b.x - a.x * b.y;
+        W[i * LD + k] = w;
+      }
+    }
+    __syncthreads();
+  }
+  // Li = L^-1 by forward substitution, one column per thread
+  for (int c = tid; c < P; c += nt) {
+    for (int i = 0; i < c; ++i) Li[i * LD + c] = make_double2(0.0, 0.0);
+    Li[c * LD + c] = make_double2(1.0 / W[c * LD + c].x, 0.0);
+    for (int i = c + 1; i < P; ++i) {
+      double sr = 0.0, si = 0.0;
+      for (int k = c; k < i; ++k) {
+        const double2 l = W[i * LD + k], y = Li[k * LD + c];
+        sr += l.x * y.x - l.y * y.y;
+        si += l.x * y.y + l.y * y.x;
+      }
+      const double lii = W[i * LD + i].x;
+      Li[i * LD + c] = make_double2(-sr / lii, -si / lii);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < P * P; e += nt) {
+    const int i = e / P, k = e % P;
+    double sr = 0.0, si = 0.0;
+    for (int m = (i > k ? i : k); m < P; ++m) {
+      const double2 a = Li[m * LD + i], b = Li[m * LD + k];
+      sr += a.x * b.x + a.y * b.y;
+      si += a.x * b.y - a.y * b.x;
+    }
+    it.Rinv[e] = make_float2((float)sr, (float)si);
+    if (it.Li) it.Li[e] = Li[i * LD + k];
+  }
+  if (tid == 0) *it.status = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Separable steering tables, FP64 phases rounded once to complex64:
 //   El[p][il] = P^-1/2 exp(-j 2pi x_p l_il / lambda),  Em[p][im] = exp(-j 2pi y_p m_im / lambda),
@@ -704,7 +785,18 @@ hipError_t launch_reduce(const RedParams& pr, hipStream_t st) {
 
 hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, float2* Rinv,
                                int* status, hipStream_t st) {
-  hipLaunchKernelGGL(chol_inverse_kernel, dim3(1), dim3(1024), 0, st, R, P, W, Li, Rinv, status);
+  if (P <= kCholLdsMaxP) {
+    const CholItem one{R, Li, Rinv, status};
+    hipLaunchKernelGGL(chol_inverse_lds_kernel, dim3(1), dim3(256), 0, st, one, (const CholItem*)nullptr, P);
+  } else {
+    hipLaunchKernelGGL(chol_inverse_kernel, dim3(1), dim3(1024), 0, st, R, P, W, Li, Rinv, status);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_inverse_batch(const CholItem* items, int n, int P, hipStream_t st) {
+  if (P > kCholLdsMaxP || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_inverse_lds_kernel, dim3(n), dim3(256), 0, st, CholItem{}, items, P);
   return hipGetLastError();
 }
 

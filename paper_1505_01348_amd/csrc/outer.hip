@@ -623,6 +623,24 @@ hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream
   return hipGetLastError();
 }
 
+// the outer states of a batch, each in its request's slice, into one array
+// (one read-back per poll)
+static_assert(sizeof(OuterState) % 4 == 0, "the state is copied as 32-bit words");
+__global__ void gather_states_kernel(const OuterParams* __restrict__ prs, int n, OuterState* __restrict__ out) {
+  constexpr int NW = sizeof(OuterState) / 4;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * NW; e += gridDim.x * blockDim.x) {
+    const int r = e / NW, k = e - r * NW;
+    reinterpret_cast<int*>(out + r)[k] = reinterpret_cast<const int*>(prs[r].st)[k];
+  }
+}
+
+hipError_t launch_gather_states(const OuterParams* prs, int n, OuterState* out, hipStream_t s) {
+  const int NW = (int)(sizeof(OuterState) / 4);
+  const int g = std::min((n * NW + 255) / 256, 1024);
+  hipLaunchKernelGGL(gather_states_kernel, dim3(g), dim3(256), 0, s, prs, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_outer_step_batch(const OuterParams* prs, int nreq, int P, hipStream_t s) {
   const dim3 g(nreq), b(kCuThreads);
   switch (pad_p(P) / 8) {

@@ -23,8 +23,10 @@ ReqLayout request_layout(int P, int nl, int nm, bool pwls, int nkeys);
 // Enqueue the set-up of request q on stream st into `slice` (laid out by L)
 // and fill its outer-step parameters and multiplier item.  Uses the context's
 // shared scratch (tables, Cholesky factors) only inside the stream order.
+// rinv: R^-1 of the request already factored and checked (MVDR bound of the
+// least-squares cost), or null to factor it here.
 int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L,
-                  OuterParams& op, BeamLamItem& it, hipStream_t st);
+                  OuterParams& op, BeamLamItem& it, hipStream_t st, const float2* rinv = nullptr);
 
 // Status and statistics of a finished request from its final outer state;
 // enqueues the PWLS rescaling of sigma.  Returns the request's status.

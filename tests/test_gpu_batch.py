@@ -105,3 +105,25 @@ def test_batch_rejects_mixed_or_large_arrays(gpu_lib):
         assert st == gpu_lib.ENOTSUP
     finally:
         ctx.close()
+
+
+def test_batch_reports_a_covariance_that_is_not_positive_definite(gpu_lib):
+    # the batched factorisation checks every request's covariance before any
+    # request is set up; a negative-definite one fails the call with ENOTPD
+    scs = [synth.make_scene("c0", seed=300 + i) for i in range(3)]
+    reqs = [_req(gpu_lib, sc) for sc in scs]
+    reqs[1]["R"] = -reqs[1]["R"]
+    ctx = gpu_lib.Context(0)
+    try:
+        print("case batch with a non-PD covariance", flush=True)
+        with pytest.raises(gpu_lib.ClsimgError) as ei:
+            ctx.solve_batch(reqs, _opts(gpu_lib, scs[0]))
+        assert ei.value.status == gpu_lib.ENOTPD
+        # the context stays usable: the valid requests solve, as alone
+        st, res = ctx.solve_batch([reqs[0], reqs[2]], _opts(gpu_lib, scs[0]))
+        assert st >= 0
+        s0, st0, _, _, _ = ctx.solve(reqs[0]["R"], reqs[0]["geo"], _opts(gpu_lib, scs[0]),
+                                     noise_diag=reqs[0]["noise_diag"])
+        assert torch.equal(res[0][1], st0) and torch.equal(res[0][0], s0)
+    finally:
+        ctx.close()

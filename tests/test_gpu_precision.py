@@ -117,3 +117,20 @@ def test_solve(gpu_lib, ctx, kind, prec):
         assert same
     assert err <= BAR[prec]
     assert abs(stats["rel_residual"] - ref.rel_residual) <= BAR[prec] * ref.rel_residual
+
+
+@pytest.mark.parametrize("kind,prec", [("p48", 0), ("p96", 0), ("p48", 1), ("p104", 2)])
+def test_timed_dirty_image_is_the_dirty_image(gpu_lib, ctx, kind, prec):
+    # clsimg_dirty_image_timed runs the same kernels (bit-identical image) and
+    # binds the two events to the first and last of them
+    sc = _scene(kind)
+    print(f"case timed dirty image {kind} precision {prec}", flush=True)
+    Rd = torch.as_tensor(sc.R_hat32).cuda()
+    plain = ctx.dirty_image(Rd, _geo(gpu_lib, sc), precision=prec)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    timed = ctx.dirty_image_timed(Rd, _geo(gpu_lib, sc), e0, e1, precision=prec)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    print(f"  {ms * 1e3:.2f} us", flush=True)
+    assert torch.equal(plain, timed)
+    assert 0.0 < ms < 1000.0

@@ -56,8 +56,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--max-outer", type=int, default=-1,
                     help="stop every solve (GPU and oracle) after this many Table I steps: the "
@@ -630,6 +630,43 @@ def main():
         kname = f"beam_prep_full + beam_big_kernel<{rpw}, BeamMF> (dirty image, full grid)"
         exec_flops = 2.0 * (64 * rpw) * (16 * MT) * (-(-Q // (16 * nt)) * 16 * nt)
     achieved = kflops / t_kernel / 1e12
+
+    # the forward operator on every pixel of the grid (Psi v, eq. correlation
+    # form): split-K correlation kernel + fixed-order reduction, same timing
+    vq = torch.rand(Q, dtype=torch.float32, device="cuda")
+    Yq = torch.empty((P, P), dtype=torch.complex64, device="cuda")
+    for _ in range(5):
+        ctx.forward(geo, vq, Y=Yq)
+    torch.cuda.synchronize()
+    fwd_timing = "graph"
+    try:
+        gf = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gf):
+            for _ in range(reps):
+                ctx.forward(geo, vq, Y=Yq)
+        gf.replay()
+        torch.cuda.synchronize()
+        ev0.record()
+        gf.replay()
+        ev1.record()
+    except Exception as e:
+        log(f"bench: graph capture of the forward failed ({e}); timing eager calls")
+        fwd_timing = "eager"
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            ctx.forward(geo, vq, Y=Yq)
+        ev1.record()
+    torch.cuda.synchronize()
+    t_fwd = ev0.elapsed_time(ev1) / 1e3 / reps
+    fwd_flops = 8.0 * P * P * Q
+    forward_full = {"kernels": "forward_kernel (split-K partial tiles) + reduce_kernel", "bound": "mfma",
+                    "achieved": round(fwd_flops / t_fwd / 1e12, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(fwd_flops / t_fwd / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5),
+                    "us_per_call": round(t_fwd * 1e6, 3), "flops_per_call": fwd_flops,
+                    "timing": f"{fwd_timing} of {reps} back-to-back calls"}
+    log(f"bench: forward over the whole grid {t_fwd * 1e6:.2f} us/call, {fwd_flops / t_fwd / 1e12:.2f} TFLOP/s")
+    del vq, Yq
     log(f"bench: beam kernel {t_kernel * 1e6:.2f} us/launch, {achieved:.2f} TFLOP/s dense count, "
         f"{exec_flops / t_kernel / 1e12:.2f} TFLOP/s issued MFMA")
 
@@ -645,30 +682,53 @@ def main():
         Ppb = -(-sb.P // 8) * 8
         by = {}
         for name, prec in PRECISIONS.items():
+            tiles, tune_us = ctx.autotune(gb, precision=prec)  # pixel tiles per workgroup, kept in the context
+            log(f"bench: autotuned {name}: {tiles} tiles per workgroup (us for 2/4/8: {tune_us})")
             for _ in range(3):
                 ctx.dirty_image(Rb, gb, mf=ob, precision=prec)
             torch.cuda.synchronize()
             tb = stamped_seconds(lambda a, b: ctx.dirty_image_timed(Rb, gb, a, b, mf=ob, precision=prec), 20)
             dense = fb / tb / 1e12
             if prec == 0:
-                by[name] = {"kernel": "beam_prep_full + beam_big_kernel<9, BeamMF>", "bound": "mfma",
+                by[name] = {"kernel": f"beam_prep_full + beam_big_kernel<9, {tiles}, BeamMF>", "bound": "mfma",
                             "achieved": round(dense, 4), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                             "frac": round(dense / PEAK_FP32_MFMA_TFLOPS, 5), "us_per_launch": round(tb * 1e6, 2)}
             else:
                 # three half-precision products (hi.hi, hi.lo, lo.hi) of the full real 2P x 2P matrix
                 issued = 3 * 2.0 * (2 * Ppb) ** 2 * sb.Q
-                by[name] = {"kernel": f"scale + prep + beam_h16_kernel<9, {name}, BeamMF>", "bound": "mfma",
+                by[name] = {"kernel": f"scale + prep + beam_h16_kernel<9, {tiles}, {name}, BeamMF>", "bound": "mfma",
                             "achieved_dense_count": round(dense, 4), "issued_half_mfma": round(issued / tb / 1e12, 4),
                             "peak": PEAK_HALF_MFMA_TFLOPS, "unit": "TFLOP/s",
                             "frac": round(issued / tb / 1e12 / PEAK_HALF_MFMA_TFLOPS, 5),
                             "us_per_launch": round(tb * 1e6, 2), "speedup_vs_fp32": None}
+            by[name]["autotune"] = {"tiles_per_workgroup": tiles, "us_for_2_4_8": [round(t, 2) for t in tune_us]}
             log(f"bench: 288-antenna dirty image {name}: {tb * 1e6:.1f} us, {dense:.1f} TFLOP/s dense count")
+        # the forward operator on every pixel at this size (FP32)
+        vb = torch.rand(sb.Q, dtype=torch.float32, device="cuda")
+        Yb = torch.empty((sb.P, sb.P), dtype=torch.complex64, device="cuda")
+        for _ in range(3):
+            ctx.forward(gb, vb, Y=Yb)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            ctx.forward(gb, vb, Y=Yb)
+        e1.record()
+        torch.cuda.synchronize()
+        tfb = e0.elapsed_time(e1) / 1e3 / 20
+        ffb = 8.0 * sb.P * sb.P * sb.Q
+        fwd_big = {"kernels": "forward_kernel + reduce_kernel", "us_per_call": round(tfb * 1e6, 2),
+                   "achieved": round(ffb / tfb / 1e12, 4), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(ffb / tfb / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5), "flops_per_call": ffb,
+                   "timing": "eager, 20 calls"}
+        log(f"bench: 288-antenna forward over the whole grid: {tfb * 1e6:.1f} us, {ffb / tfb / 1e12:.1f} TFLOP/s")
+        del vb, Yb
         for name in ("fp16", "bf16"):
             by[name]["speedup_vs_fp32"] = round(by["fp32"]["us_per_launch"] / by[name]["us_per_launch"], 3)
         big = dict(by["fp32"], workload="P=288, 512x512 pixels (the 288-antenna workload's size)",
                    flops_per_launch=fb, by_precision=by,
                    timing="device timestamps from the start of the first kernel (fragment preparation) to the "
-                          "end of the beamformer, mean of 20 calls")
+                          "end of the beamformer, mean of 20 calls", forward=fwd_big)
         del Rb, ob
 
     lat_ms = np.array(lat) * 1e3
@@ -698,6 +758,10 @@ def main():
         "psi_mfma_frac": round(psi_tflops / PEAK_FP32_MFMA_TFLOPS, 5),
         "solve": {k: stats[k] for k in ("status", "outer_iters", "adds", "drops", "lsqr_iters_total",
                                         "nF", "nU", "rel_residual")},
+        # one solve's time over its LSQR iterations: an upper bound of the latency of one
+        # iteration (the outer steps' other work and the multiplier kernels are included)
+        "us_per_lsqr_iteration_bound": round(total / (B * args.steps) * 1e6 / max(stats["lsqr_iters_total"], 1), 3),
+        "forward_full_grid": forward_full,
         "roofline": {"kernel": kname,
                      "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 5),

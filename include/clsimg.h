@@ -159,6 +159,28 @@ int clsimg_dirty_image_timed(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_
                              const clsimg_grid* grid, int32_t precision, float* mf, void* start_event,
                              void* stop_event, void* stream);
 
+/* Autotuner of the GEMM-shaped full-grid beamformers (the dirty image, bound
+ * and multipliers for P > 48 in FP32, and for every P in split FP16 / BF16):
+ * times one dirty image of this array and grid for each candidate number of
+ * 16-pixel tiles per workgroup (2, 4, 8) on `stream`, and keeps the fastest in
+ * the context for this precision and array size (by row tiles per wave,
+ * ceil(P / 32); the last tuning of a size applies to every grid).  Every
+ * candidate computes each pixel with the same operations in the same order,
+ * so results are bit-identical whichever is kept.  Eight tiles are offered up
+ * to P = 192 only (beyond, the accumulators would not fit in registers).  Not
+ * for use under stream capture: it synchronises the stream.  chosen (host, may
+ * be null): the tile count kept.  us (host float[3], may be null): microseconds
+ * per dirty image for 2, 4 and 8 tiles (-1: not offered).  CLSIMG_ENOTSUP for FP32 with P <= 48 (the
+ * register-resident beamformer has no tile choice) and for P > CLSIMG_MAX_P. */
+int clsimg_autotune(clsimg_ctx* ctx, const clsimg_array* array, const clsimg_grid* grid, int32_t precision,
+                    int32_t* chosen, float* us, void* stream);
+
+/* Sets the tiles per workgroup of the GEMM-shaped beamformers for arrays of P
+ * antennas at `precision` (tiles 2, 4, or 8 up to P = 192; 0 restores the
+ * built-in default), e.g. to reuse a choice tuned earlier.  CLSIMG_EINVAL for
+ * other values. */
+int clsimg_set_beam_tiles(clsimg_ctx* ctx, int32_t P, int32_t precision, int32_t tiles);
+
 /* Upper bound gamma of the box constraint (eq. CLS):
  *   MVDR (eq. wmvdr, Sec. II-D): h_i = a_i^H R^-1 a_i with R = L L^H factored in
  *        FP64 on the device; gamma_i = C/h_i + kappa_b / (h_i sqrt(N-P-1));

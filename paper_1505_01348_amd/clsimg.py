@@ -28,7 +28,7 @@ STATE_L, STATE_F, STATE_U = 0, 1, 2
 MAX_P = 288
 
 EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
-            "clsimg_dirty_image_timed", "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
+            "clsimg_dirty_image_timed", "clsimg_autotune", "clsimg_set_beam_tiles", "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
             "clsimg_solve_batch", "clsimg_solve_multi", "clsimg_solve_offgrid", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
             "clsimg_server_query", "clsimg_server_destroy", "clsimg_strerror")
 
@@ -93,6 +93,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.clsimg_destroy.argtypes = [vp]
     lib.clsimg_dirty_image.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp]
     lib.clsimg_dirty_image_timed.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp, vp, vp]
+    lib.clsimg_autotune.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), i32, C.POINTER(i32),
+                                    C.POINTER(C.c_float), vp]
+    lib.clsimg_set_beam_tiles.argtypes = [vp, i32, i32, i32]
     lib.clsimg_mvdr_bound.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), C.POINTER(COpts),
                                       vp, vp]
     lib.clsimg_forward.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), vp, vp, i32, vp, vp]
@@ -261,6 +264,20 @@ class Context:
                                                        C.c_void_p(stop.cuda_event), _stream()),
                     "clsimg_dirty_image_timed")
         return mf
+
+    def autotune(self, geo: Geometry, precision: int = FP32):
+        """Time 2, 4 and 8 pixel tiles per workgroup of the GEMM-shaped beamformer
+        for this array and grid; the fastest is kept in the context.
+        Returns (tiles kept, [us for 2, 4, 8])."""
+        chosen = C.c_int32(0)
+        us = (C.c_float * 3)()
+        self._check(self._lib.clsimg_autotune(self._h, C.byref(geo.c_array), C.byref(geo.c_grid), int(precision),
+                                              C.byref(chosen), us, _stream()), "clsimg_autotune")
+        return chosen.value, [float(x) for x in us]
+
+    def set_beam_tiles(self, P: int, precision: int, tiles: int):
+        self._check(self._lib.clsimg_set_beam_tiles(self._h, int(P), int(precision), int(tiles)),
+                    "clsimg_set_beam_tiles")
 
     def mvdr_bound(self, R, geo: Geometry, opts: Options | None = None, gamma=None):
         dev = self.device

@@ -52,6 +52,9 @@ struct clsimg_ctx {
   DevBuf ostate;                                                // device-resident outer loop
   DevBuf pw_h, pw_rs, pw_g, pw_eps, pw_dinv, pw_Lw, pw_B0w;      // PWLS inputs
   DevBuf batch, batch_params, batch_rinv;                       // batched solve workspace
+  // autotuned 16-pixel tiles per workgroup of the GEMM-shaped beamformers, by
+  // precision (FP32, FP16, BF16) and row tiles per wave; 0: the default
+  int tuned_nt[3][16] = {};
   char* h_batch = nullptr;                                      // pinned staging of the batch
   size_t h_batch_bytes = 0;
   SolveDecision* h_dec = nullptr;
@@ -63,6 +66,7 @@ struct clsimg_ctx {
   bool coop = false;   // cooperative launches available (multi-workgroup LSQR kernel)
   int lsqr_path = 0;   // CLSIMG_LSQR_PATH: 0 auto, 1 one workgroup, 2 cooperative, 3 two kernels/step
   bool old_beam = false;   // CLSIMG_LDS_BEAM=1: LDS-staged beamformer for the gradient
+  bool fwd_splitk = false; // CLSIMG_FWD_SPLITK=1: split-K correlation kernel (one partial per wave)
   bool beam_prep = false;  // CLSIMG_BEAM_PREP=1: beamformer fragments from a separate pass
   bool host_loop = false;  // CLSIMG_HOST_LOOP=1: active-set loop driven from the host
   int prec = CLSIMG_FP32;  // arithmetic of the full-grid beamforming products of the current call
@@ -204,13 +208,14 @@ AdjParams adj_params(clsimg_ctx* c, const clsimg_grid* g, int P, const float* fr
   return pr;
 }
 
+// partial tiles of either correlation kernel at its largest chunk count
 size_t part_floats_max(int P) {
   const int MT = pad_p(P) / 8;
   const int tw = MT <= 3 ? 3 : 6;
   const int nb = (MT + tw - 1) / tw;
   int waves = 512 / (nb * nb);
   if (waves < 1) waves = 1;
-  const int nc = std::min(256, waves + 2);
+  const int nc = std::max(std::min(256, waves + 2), forward_lds_chunks_max(P));
   return (size_t)nc * MT * MT * 256;
 }
 
@@ -230,7 +235,7 @@ int ensure_workspace(clsimg_ctx* c, int P, int Q) {
   ST_TRY(ensure(c, c->beta_part, (size_t)reduce_blocks(P) * sizeof(double)));
   ST_TRY(ensure(c, c->alpha_part, (size_t)(ntiles_adj(P, Q) + 1) * sizeof(double)));
   ST_TRY(ensure(c, c->keys,
-                (size_t)(std::max(ntiles_adj(P, Q), std::max(beam_grid(Q), beam_big_grid(P, Q))) + 1) *
+                (size_t)(std::max(ntiles_adj(P, Q), std::max(beam_grid(Q), beam_big_grid(P, Q, 2))) + 1) *
                     sizeof(uint64_t)));
   const size_t fb = beam_fits(P) ? (size_t)2 * (Pp / 8) * (Pp / 8 + 1) * 64
                                  : (beam_big_fits(P) ? beam_big_frag_floats(P) : 64);
@@ -254,7 +259,7 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
               const LsqrState* lsqr, float* frag, double* norm_part, const int* stop,
               hipStream_t st) {
   int chw = 8, nchunks = 0, nbm = 1;
-  forward_plan(P, n, &chw, &nchunks, &nbm);
+  forward_plan(P, n, &chw, &nchunks, &nbm, c->fwd_splitk);
   const int MT = pad_p(P) / 8;
   if ((size_t)nchunks * MT * MT * 256 > part_floats_max(P)) return CLSIMG_EINVAL;
   if (n > 0) {
@@ -268,6 +273,7 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
     f.chw = chw;
     f.nbm = nbm;
     f.nbn = nbm;
+    f.splitk = c->fwd_splitk;
     f.part = P_<float>(c->part);
     f.stop_flag = stop;
     HIP_TRY(launch_forward(f, st));
@@ -297,7 +303,7 @@ int correlate_blocks(clsimg_ctx* c, const clsimg_grid* g, int P, int K, size_t t
                      size_t B_stride, float cK, float cB, const LsqrState* lsqr, float* frag, size_t frag_stride,
                      double* norm_part, size_t norm_stride, const int* stop, hipStream_t st) {
   int chw = 8, nchunks = 0, nbm = 1;
-  forward_plan(P, n, &chw, &nchunks, &nbm);
+  forward_plan(P, n, &chw, &nchunks, &nbm, c->fwd_splitk);
   const int MT = pad_p(P) / 8;
   const size_t pstride = part_floats_max(P);
   if ((size_t)nchunks * MT * MT * 256 > pstride) return CLSIMG_EINVAL;
@@ -312,6 +318,7 @@ int correlate_blocks(clsimg_ctx* c, const clsimg_grid* g, int P, int K, size_t t
     f.chw = chw;
     f.nbm = nbm;
     f.nbn = nbm;
+    f.splitk = c->fwd_splitk;
     f.part = P_<float>(c->part);
     f.stop_flag = stop;
     f.nblk = K;
@@ -344,6 +351,13 @@ int correlate_blocks(clsimg_ctx* c, const clsimg_grid* g, int P, int K, size_t t
 
 bool beam_any(int P) { return beam_fits(P) || beam_big_fits(P); }
 
+// tiles per workgroup of the GEMM-shaped beamformer at the context's precision
+int big_tiles(const clsimg_ctx* c, int P) {
+  const int rpw = (pad_p(P) / 8 + 3) / 4;
+  const int pr = c->prec == CLSIMG_FP16 ? 1 : (c->prec == CLSIMG_BF16 ? 2 : 0);
+  return rpw < 16 ? c->tuned_nt[pr][rpw] : 0;
+}
+
 // Full-grid beamformer: for P <= 48 the block-triangular fragments of U stay
 // in registers for the whole pass; for larger arrays (up to 288) the
 // fragments are prepared once and streamed by the GEMM-shaped kernel.
@@ -359,14 +373,14 @@ int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamK
     HIP_TRY(launch_beam_prep_h16(U, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st, first));
     const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
     HIP_TRY(launch_beam_h16(k, bf, c->frag_h.ptr, P_<const float>(c->hscale), tab, nullptr, out, eps, eps_scale, C,
-                            kb, scale, nullptr, nullptr, st, last));
+                            kb, scale, nullptr, nullptr, st, last, big_tiles(c, P)));
     return CLSIMG_OK;
   }
   if (!beam_fits(P)) {  // larger arrays: fragments of the whole Ut, GEMM-shaped kernel
     HIP_TRY(launch_beam_prep_full(U, P, P_<float>(c->frag_b), st, first));
     const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
     HIP_TRY(launch_beam_big(k, P_<const float>(c->frag_b), tab, nullptr, out, eps, eps_scale, C, kb, scale,
-                            nullptr, nullptr, st, last));
+                            nullptr, nullptr, st, last, big_tiles(c, P)));
     return CLSIMG_OK;
   }
   // fragments built inside the kernel, or prepared by a separate pass
@@ -644,6 +658,8 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   c->old_beam = ob && ob[0] == '1';
   const char* bp = getenv("CLSIMG_BEAM_PREP");
   c->beam_prep = bp && bp[0] == '1';
+  const char* fs = getenv("CLSIMG_FWD_SPLITK");
+  c->fwd_splitk = fs && fs[0] == '1';
   const char* hl = getenv("CLSIMG_HOST_LOOP");
   c->host_loop = hl && hl[0] == '1';
   const char* mf_ = getenv("CLSIMG_OUTER_MAXF");
@@ -722,6 +738,75 @@ int clsimg_dirty_image(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a
   if (beam_any(P)) return beam_full(c, g, P, Rf, BEAM_MF, mf, nullptr, 0.f, 0, 0, 1.f, st);
   HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, nullptr, 0.f, st));
   return CLSIMG_OK;
+}
+
+int clsimg_set_beam_tiles(clsimg_ctx* c, int32_t P, int32_t precision, int32_t tiles) {
+  if (!c || P < 1 || P > CLSIMG_MAX_P) return CLSIMG_EINVAL;
+  if (precision != CLSIMG_FP32 && precision != CLSIMG_FP16 && precision != CLSIMG_BF16) return CLSIMG_EINVAL;
+  if (tiles != 0 && tiles != 2 && tiles != 4 && !(tiles == 8 && (pad_p(P) / 8 + 3) / 4 <= 6)) return CLSIMG_EINVAL;
+  const int pr = precision == CLSIMG_FP16 ? 1 : (precision == CLSIMG_BF16 ? 2 : 0);
+  c->tuned_nt[pr][(pad_p(P) / 8 + 3) / 4] = tiles;
+  return CLSIMG_OK;
+}
+
+int clsimg_autotune(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, int32_t precision, int32_t* chosen,
+                    float* us, void* stream) {
+  if (!c) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  if (precision != CLSIMG_FP32 && precision != CLSIMG_FP16 && precision != CLSIMG_BF16) return CLSIMG_EINVAL;
+  const int P = a->P, Q = g->nl * g->nm;
+  if (!beam_big_fits(P) || (precision == CLSIMG_FP32 && beam_fits(P))) return CLSIMG_ENOTSUP;
+  c->prec = precision;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  ST_TRY(ensure_workspace(c, P, Q));
+  ST_TRY(ensure_tables(c, a, g, st));
+  ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
+  // a synthetic covariance (the identity): the kernels' time does not depend on the values
+  std::vector<float2> eye((size_t)P * P, make_float2(0.f, 0.f));
+  for (int p = 0; p < P; ++p) eye[(size_t)p * P + p] = make_float2(1.f, 0.f);
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(c->B0.ptr, eye.data(), eye.size() * sizeof(float2), hipMemcpyHostToDevice));
+  const int pr = precision == CLSIMG_FP16 ? 1 : (precision == CLSIMG_BF16 ? 2 : 0);
+  const int rpw = (pad_p(P) / 8 + 3) / 4;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return CLSIMG_EHIP;
+  }
+  int status = CLSIMG_OK, best = 0;
+  float tbest = 0.f;
+  const int reps = 5;
+  for (int i = 0; i < 3 && status == CLSIMG_OK; ++i) {
+    const int nt = kBigTileChoices[i];
+    if (nt == 8 && rpw > 6) {  // not built: the accumulators would spill
+      if (us) us[i] = -1.f;
+      continue;
+    }
+    c->tuned_nt[pr][rpw] = nt;
+    float ms = 0.f;
+    for (int w = 0; w < 2 && status == CLSIMG_OK; ++w)
+      status = beam_full(c, g, P, P_<const float2>(c->B0), BEAM_MF, P_<float>(c->mf), nullptr, 0.f, 0, 0, 1.f, st);
+    if (status == CLSIMG_OK && hipEventRecord(e0, st) != hipSuccess) status = CLSIMG_EHIP;
+    for (int r = 0; r < reps && status == CLSIMG_OK; ++r)
+      status = beam_full(c, g, P, P_<const float2>(c->B0), BEAM_MF, P_<float>(c->mf), nullptr, 0.f, 0, 0, 1.f, st);
+    if (status == CLSIMG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      status = CLSIMG_EHIP;
+    if (status != CLSIMG_OK) break;
+    const float t = 1e3f * ms / reps;
+    if (us) us[i] = t;
+    if (best == 0 || t < tbest) {
+      best = nt;
+      tbest = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tuned_nt[pr][rpw] = status == CLSIMG_OK ? best : 0;
+  if (chosen) *chosen = c->tuned_nt[pr][rpw];
+  return status;
 }
 
 int clsimg_dirty_image_timed(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
@@ -1173,13 +1258,13 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           const bool bf = c->prec == CLSIMG_BF16;
           HIP_TRY(launch_beam_prep_h16(E, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st));
           HIP_TRY(launch_beam_h16(3, bf, c->frag_h.ptr, P_<const float>(c->hscale), tables_of(c, g, P), grad_stop,
-                                  nullptr, nullptr, 0.f, 0, 0, 1.f, state, keys, st));
-          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q), eps, state, dec, st));
+                                  nullptr, nullptr, 0.f, 0, 0, 1.f, state, keys, st, {}, big_tiles(c, P)));
+          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
         } else if (!beam_full_grid && beam_big_grid_ok) {
           HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr, 0.f,
-                                  0, 0, 1.f, state, keys, st));
-          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q), eps, state, dec, st));
+                                  0, 0, 1.f, state, keys, st, {}, big_tiles(c, P)));
+          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
         } else if (beam_full_grid) {
           if (c->beam_prep) HIP_TRY(launch_beam_prep(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_lambda(c->beam_prep ? P_<const float>(c->frag_b) : nullptr,
@@ -1416,7 +1501,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   auto beam_acc = [&](int k, const float2* U, const int* skip, float* sum, float* sumsq, float scale) {
     use(k);
     return launch_beam_accumulate(U, P, tables_of(c, g, P), skip, sum, sumsq, scale, k == 0, c->prec,
-                                  P_<float>(c->frag_b), c->frag_h.ptr, P_<float>(c->hscale), st);
+                                  P_<float>(c->frag_b), c->frag_h.ptr, P_<float>(c->hscale), st, big_tiles(c, P));
   };
   const double Kd = K;
   double flops = 0.0;

@@ -145,7 +145,9 @@ struct BeamLambda {
 // robin to the waves, written to LDS and then read back by every wave.  For
 // row tile m the lane's row is antenna 8m + 4((c16 >> 1) & 1) + (c16 >> 2),
 // component c16 & 1; the pair shares column antenna 4j + q and takes the two
-// components of the same Hermitian-part entry.
+// components of the same Hermitian-part entry.  In LDS fragment f of lane l
+// sits at (f >> 2) * 256 + 4 l + (f & 3): a pair is one 8-byte store and each
+// lane reads its fragments four at a time with 16-byte loads.
 template <int MT>
 __device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, int P, float* sfr, float* fa) {
   constexpr int NPAIR = MT * (MT + 1);
@@ -178,14 +180,21 @@ __device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, 
       const float d = (j >> 1) < m ? 2.f : 1.f;  // chunks 2j, 2j+1 lie in column tile j >> 1
       const float hr = live ? 0.5f * d * (xv[i].x + yv[i].x) : 0.f;
       const float hi = live ? 0.5f * d * (xv[i].y - yv[i].y) : 0.f;
-      const int f = 2 * m * (m + 1) + 2 * j;
-      sfr[f * 64 + lane] = s1 ? hi : hr;
-      sfr[(f + 1) * 64 + lane] = s1 ? hr : -hi;
+      const int f = 2 * m * (m + 1) + 2 * j;  // even
+      *reinterpret_cast<float2*>(sfr + (f >> 2) * 256 + 4 * lane + (f & 3)) =
+          make_float2(s1 ? hi : hr, s1 ? hr : -hi);
     }
   }
   __syncthreads();
+  static_assert(NFR % 4 == 0, "fragments are read four at a time");
 #pragma unroll
-  for (int f = 0; f < NFR; ++f) fa[f] = sfr[f * 64 + lane];
+  for (int f4 = 0; f4 < NFR / 4; ++f4) {
+    const float4 v = *reinterpret_cast<const float4*>(sfr + f4 * 256 + 4 * lane);
+    fa[4 * f4] = v.x;
+    fa[4 * f4 + 1] = v.y;
+    fa[4 * f4 + 2] = v.z;
+    fa[4 * f4 + 3] = v.w;
+  }
 }
 
 template <int MT, class Epi>
@@ -199,7 +208,9 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
   const int ntiles = (Q + 15) >> 4;
   const int nwav = nblk * kBeamWaves;
   // table entries of antennas 4 j + q for this lane's pixel of a tile; the
-  // loads of the next tile are issued before the current one is multiplied
+  // loads of the next tile are issued before the current one is multiplied.
+  // The first tile's loads follow the fragment loads (the fragments are built
+  // first, and loads complete in order).
   float2 te[KS / 2], tm[KS / 2];
   auto load_tables = [&](int tile) {
     const int pix = min(16 * tile + c16, Q - 1);
@@ -213,15 +224,15 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
     }
   };
   int tile = blk * kBeamWaves + (threadIdx.x >> 6);
-  if (tile < ntiles) load_tables(tile);
   float fa[NFR];
   if (U) {
-    __shared__ float sfr[NFR * 64];
+    __shared__ __align__(16) float sfr[NFR * 64];
     beam_frags_from_u<MT>(U, P, sfr, fa);
   } else {
 #pragma unroll
     for (int f = 0; f < NFR; ++f) fa[f] = frag[f * 64 + lane];
   }
+  if (tile < ntiles) load_tables(tile);
   epi.init();
   for (; tile < ntiles; tile += nwav) {
     const int pix = 16 * tile + c16;
@@ -285,10 +296,16 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
 // row tiles again: they are recomputed from the tables (two complex products
 // per row tile and pixel tile).  The four waves' partial sums meet in LDS.
 __host__ __device__ inline int big_rpw(int MT) { return (MT + 3) / 4; }
-// 16-pixel tiles per workgroup (measured: two for up to 16 row tiles, where
-// more workgroups hide the load latency, four for longer K loops, where the
-// fragment loads are shared by more MFMAs)
+// 16-pixel tiles per workgroup.  The default (measured: two for up to 16 row
+// tiles, where more workgroups hide the load latency, four for longer K
+// loops, where the fragment loads are shared by more MFMAs) can be replaced
+// by an autotuned choice among kBigNT; every choice computes each pixel with
+// the same operations in the same order.
 __host__ __device__ constexpr int big_nt(int rpw) { return rpw <= 4 ? 2 : 4; }
+// eight tiles only up to 6 row tiles per wave: beyond, the accumulators no
+// longer fit in the register file
+__host__ __device__ constexpr bool big_nt_ok(int nt, int rpw) { return nt == 2 || nt == 4 || (nt == 8 && rpw <= 6); }
+__host__ __device__ inline int big_nt_or(int nt, int rpw) { return big_nt_ok(nt, rpw) ? nt : big_nt(rpw); }
 // loads of the next chunk pair issued before the current pair's MFMAs while
 // the registers allow it (short K loops, i.e. up to 16 row tiles)
 __host__ __device__ constexpr bool big_prefetch(int rpw) { return rpw <= 4; }
@@ -313,10 +330,9 @@ __global__ void beam_prep_full_kernel(const float2* __restrict__ U, int P, int M
   }
 }
 
-template <int RPW, class Epi>
+template <int RPW, int NT, class Epi>
 __global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__ frag, int MT, Tables tab,
                                                        const int* skip, Epi epi) {
-  constexpr int NT = big_nt(RPW);
   constexpr bool kPrefetch = big_prefetch(RPW);
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
@@ -542,13 +558,12 @@ __global__ void beam_prep_h16_kernel(const float2* __restrict__ U, int P, int MT
   }
 }
 
-template <int RPW, bool BF, class Epi>
+template <int RPW, int NT, bool BF, class Epi>
 __global__ __launch_bounds__(256) void beam_h16_kernel(const typename Half<BF>::V* __restrict__ frag, int MT, int KC,
                                                        const float* __restrict__ scale, float sB, Tables tab,
                                                        const int* skip, Epi epi) {
   typedef typename Half<BF>::V V;
   typedef typename Half<BF>::T T;
-  constexpr int NT = big_nt(RPW);
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
@@ -649,8 +664,8 @@ size_t beam_big_frag_floats(int P) {
   return (size_t)4 * big_rpw(MT) * 4 * MT * 64;
 }
 
-int beam_big_grid(int P, int Q) {
-  const int nt = big_nt(big_rpw(pad_p(P) / 8));
+int beam_big_grid(int P, int Q, int nt) {
+  nt = big_nt_or(nt, big_rpw(pad_p(P) / 8));
   const int nblk = ((Q + 15) / 16 + nt - 1) / nt;
   return nblk < 1 ? 1 : (nblk > 8192 ? 8192 : nblk);
 }
@@ -696,19 +711,30 @@ hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_
 
 template <class Epi>
 static hipError_t launch_big(const float* frag, const Tables& tab, const int* skip, Epi epi, hipStream_t st,
-                             Stamps ts = {}) {
-  const int MT = tab.Pp / 8;
-  const dim3 g(beam_big_grid(tab.Pp, tab.Q)), b(256);
-  switch (big_rpw(MT)) {
-    case 1: hipExtLaunchKernelGGL((beam_big_kernel<1, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 2: hipExtLaunchKernelGGL((beam_big_kernel<2, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 3: hipExtLaunchKernelGGL((beam_big_kernel<3, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 4: hipExtLaunchKernelGGL((beam_big_kernel<4, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 5: hipExtLaunchKernelGGL((beam_big_kernel<5, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 6: hipExtLaunchKernelGGL((beam_big_kernel<6, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 7: hipExtLaunchKernelGGL((beam_big_kernel<7, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 8: hipExtLaunchKernelGGL((beam_big_kernel<8, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
-    case 9: hipExtLaunchKernelGGL((beam_big_kernel<9, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, epi); break;
+                             Stamps ts = {}, int nt = 0) {
+  const int MT = tab.Pp / 8, rpw = big_rpw(MT);
+  nt = big_nt_or(nt, rpw);
+  const dim3 g(beam_big_grid(tab.Pp, tab.Q, nt)), b(256);
+  switch (10 * rpw + nt / 4) {  // nt 2, 4, 8 -> 0, 1, 2
+#define BIG_CASE(R, N)                                                                                         \
+  case 10 * R + N / 4:                                                                                         \
+    hipExtLaunchKernelGGL((beam_big_kernel<R, N, Epi>), g, b, 0, st, ts.start, ts.stop, 0, frag, MT, tab, skip, \
+                          epi);                                                                                \
+    break;
+#define BIG_RPW(R) BIG_CASE(R, 2) BIG_CASE(R, 4) BIG_CASE(R, 8)
+#define BIG_RPW_LARGE(R) BIG_CASE(R, 2) BIG_CASE(R, 4)
+    BIG_RPW(1)
+    BIG_RPW(2)
+    BIG_RPW(3)
+    BIG_RPW(4)
+    BIG_RPW(5)
+    BIG_RPW(6)
+    BIG_RPW_LARGE(7)
+    BIG_RPW_LARGE(8)
+    BIG_RPW_LARGE(9)
+#undef BIG_RPW_LARGE
+#undef BIG_RPW
+#undef BIG_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -716,12 +742,12 @@ static hipError_t launch_big(const float* frag, const Tables& tab, const int* sk
 
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
-                           hipStream_t st, Stamps ts) {
+                           hipStream_t st, Stamps ts, int nt) {
   switch (kind) {
-    case 0: return launch_big(frag, tab, skip, BeamMF{out, eps, eps_scale}, st, ts);
-    case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st, ts);
-    case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st, ts);
-    default: return launch_big(frag, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts);
+    case 0: return launch_big(frag, tab, skip, BeamMF{out, eps, eps_scale}, st, ts, nt);
+    case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st, ts, nt);
+    case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st, ts, nt);
+    default: return launch_big(frag, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts, nt);
   }
 }
 
@@ -735,30 +761,35 @@ size_t beam_h16_frag_bytes(int P) {
 
 template <bool BF, class Epi>
 static hipError_t launch_h16(const void* frag, const float* scale, const Tables& tab, const int* skip, Epi epi,
-                             hipStream_t st, Stamps ts = {}) {
+                             hipStream_t st, Stamps ts = {}, int nt = 0) {
   typedef typename Half<BF>::V V;
-  const int MT = tab.Pp / 8, KC = beam_h16_chunks(tab.Pp);
+  const int MT = tab.Pp / 8, KC = beam_h16_chunks(tab.Pp), rpw = big_rpw(MT);
+  nt = big_nt_or(nt, rpw);
   // steering entries scaled towards unit magnitude (|a_p| = P^-1/2): a power of two
   int ex = 0;
   (void)frexpf(sqrtf((float)tab.Pp), &ex);
   const float sB = BF ? 1.f : ldexpf(1.f, ex - 1);
   const V* f = static_cast<const V*>(frag);
-  const dim3 g(beam_big_grid(tab.Pp, tab.Q)), b(256);
-  switch (big_rpw(MT)) {
-#define H16_CASE(R) \
-  case R:                                                                                                    \
-    hipExtLaunchKernelGGL((beam_h16_kernel<R, BF, Epi>), g, b, 0, st, ts.start, ts.stop, 0, f, MT, KC, scale, sB, \
-                          tab, skip, epi);                                                                     \
+  const dim3 g(beam_big_grid(tab.Pp, tab.Q, nt)), b(256);
+  switch (10 * rpw + nt / 4) {
+#define H16_CASE(R, N)                                                                                             \
+  case 10 * R + N / 4:                                                                                             \
+    hipExtLaunchKernelGGL((beam_h16_kernel<R, N, BF, Epi>), g, b, 0, st, ts.start, ts.stop, 0, f, MT, KC, scale, sB, \
+                          tab, skip, epi);                                                                         \
     break;
-    H16_CASE(1)
-    H16_CASE(2)
-    H16_CASE(3)
-    H16_CASE(4)
-    H16_CASE(5)
-    H16_CASE(6)
-    H16_CASE(7)
-    H16_CASE(8)
-    H16_CASE(9)
+#define H16_RPW(R) H16_CASE(R, 2) H16_CASE(R, 4) H16_CASE(R, 8)
+#define H16_RPW_LARGE(R) H16_CASE(R, 2) H16_CASE(R, 4)
+    H16_RPW(1)
+    H16_RPW(2)
+    H16_RPW(3)
+    H16_RPW(4)
+    H16_RPW(5)
+    H16_RPW(6)
+    H16_RPW_LARGE(7)
+    H16_RPW_LARGE(8)
+    H16_RPW_LARGE(9)
+#undef H16_RPW_LARGE
+#undef H16_RPW
 #undef H16_CASE
     default: return hipErrorInvalidValue;
   }
@@ -786,39 +817,39 @@ hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, f
 
 hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* scale, const Tables& tab,
                            const int* skip, float* out, float* eps, float eps_scale, double C, double kb, float sc,
-                           const uint8_t* state, uint64_t* part, hipStream_t st, Stamps ts) {
+                           const uint8_t* state, uint64_t* part, hipStream_t st, Stamps ts, int nt) {
   const float* s = bf16 ? nullptr : scale;
   switch (kind) {
     case 0:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st, ts)
-                  : launch_h16<false>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st, ts);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st, ts, nt)
+                  : launch_h16<false>(frag, s, tab, skip, BeamMF{out, eps, eps_scale}, st, ts, nt);
     case 1:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st, ts)
-                  : launch_h16<false>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st, ts);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st, ts, nt)
+                  : launch_h16<false>(frag, s, tab, skip, BeamMVDR{out, C, kb}, st, ts, nt);
     case 2:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamStore{out, sc}, st, ts)
-                  : launch_h16<false>(frag, s, tab, skip, BeamStore{out, sc}, st, ts);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamStore{out, sc}, st, ts, nt)
+                  : launch_h16<false>(frag, s, tab, skip, BeamStore{out, sc}, st, ts, nt);
     default:
-      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts)
-                  : launch_h16<false>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts);
+      return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts, nt)
+                  : launch_h16<false>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts, nt);
   }
 }
 
 hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
                                   float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
-                                  float* hscale, hipStream_t st) {
+                                  float* hscale, hipStream_t st, int nt) {
   const BeamAcc epi{sum, sumsq, scale, first};
   if (prec != 0) {  // split half precision
     const bool bf = prec == 2;
     hipError_t e = launch_beam_prep_h16(U, P, bf, frag_half, hscale, st);
     if (e != hipSuccess) return e;
-    return bf ? launch_h16<true>(frag_half, nullptr, tab, skip, epi, st)
-              : launch_h16<false>(frag_half, hscale, tab, skip, epi, st);
+    return bf ? launch_h16<true>(frag_half, nullptr, tab, skip, epi, st, {}, nt)
+              : launch_h16<false>(frag_half, hscale, tab, skip, epi, st, {}, nt);
   }
   if (beam_fits(P)) return launch_beam(nullptr, U, P, tab, skip, epi, st);
   hipError_t e = launch_beam_prep_full(U, P, frag_big, st);
   if (e != hipSuccess) return e;
-  return launch_big(frag_big, tab, skip, epi, st);
+  return launch_big(frag_big, tab, skip, epi, st, {}, nt);
 }
 
 hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,

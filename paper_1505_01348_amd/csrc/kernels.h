@@ -38,8 +38,9 @@ struct FwdParams {
   const float* vals;  // weight of the k-th term: gather ? vals[pixel] : vals[k]
   int gather;
   int n;
-  int chw;            // pixels per wave (multiple of 4)
+  int chw;            // pixels per workgroup (split-K kernel: per wave, a multiple of 4)
   int nbm, nbn;       // output block grid
+  int splitk = 0;     // the split-K kernel (one partial per wave) instead of the LDS-staged one
   float* part;
   const int* stop_flag;
   // K covariance blocks in one launch (blockIdx.z): block k reads the tables
@@ -325,12 +326,16 @@ hipError_t launch_beam_lambda_batch(const BeamLamItem* items, int nreq, int bpr,
 // GEMM-shaped full-grid beamformer for larger arrays (P <= 288)
 bool beam_big_fits(int P);
 size_t beam_big_frag_floats(int P);
-int beam_big_grid(int P, int Q);  // workgroups (= partial keys of the lambda variant)
+// workgroups (= partial keys of the lambda variant) with nt 16-pixel tiles per
+// workgroup (2, 4, or 8 up to P = 192; anything else: the default for P); nt = 2
+// gives the largest grid
+int beam_big_grid(int P, int Q, int nt = 0);
+constexpr int kBigTileChoices[3] = {2, 4, 8};
 hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st, Stamps ts = {});
 // kind: 0 MF (+ threshold), 1 MVDR bound, 2 store (scaled), 3 multipliers with argmin keys
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
-                           hipStream_t st, Stamps ts = {});
+                           hipStream_t st, Stamps ts = {}, int nt = 0);
 // the same full-grid products in split half precision (FP16 with power-of-two
 // scaling, or BF16): fragments and scale prepared by launch_beam_prep_h16
 int beam_h16_chunks(int P);
@@ -339,13 +344,13 @@ hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, f
                                 Stamps ts = {});
 hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* scale, const Tables& tab,
                            const int* skip, float* out, float* eps, float eps_scale, double C, double kb, float sc,
-                           const uint8_t* state, uint64_t* part, hipStream_t st, Stamps ts = {});
+                           const uint8_t* state, uint64_t* part, hipStream_t st, Stamps ts = {}, int nt = 0);
 // sums over covariance blocks of the full-grid beamformer (any P, any precision:
 // prec 0 FP32, 1 FP16 split, 2 BF16 split); frag_big / frag_half / hscale are
 // the scratch of the GEMM-shaped and half-precision kernels
 hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
                                   float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
-                                  float* hscale, hipStream_t st);
+                                  float* hscale, hipStream_t st, int nt = 0);
 // K covariance blocks: images, bound and multipliers from the block sums
 hipError_t launch_multi_mf(const float* mfsq, int Q, float eps_coef, float* eps, hipStream_t st);
 hipError_t launch_multi_bound(int kind, const float* s1, const float* s2, int Q, double C, double K, double kb_coef,
@@ -378,7 +383,8 @@ hipError_t launch_xf(const Tables& tab, const int* Flist, int n, float* xf, hipS
 hipError_t launch_lsqr_fwd(const LsqrFwdParams& pr, hipStream_t st);
 hipError_t launch_lsqr_setup(LsqrState* S0, int* done, double atol, double btol, double conlim,
                              int itnlim, hipStream_t st);
-void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm);
+void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm, bool splitk = false);
+int forward_lds_chunks_max(int P);  // most partials of the LDS-staged correlation
 hipError_t launch_forward(const FwdParams& pr, hipStream_t st);
 int reduce_blocks(int P);
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st);

@@ -6,6 +6,8 @@
 // that the Khatri-Rao matrix never has to be stored.  Here both become dense
 // real GEMMs on the fp32 MFMA with the steering vectors generated on the fly
 // from FP64-built separable tables (layout notes in common.h).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace clsimg {
@@ -369,12 +371,131 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(FwdParams pr) {
 }
 
 // ---------------------------------------------------------------------------
+// Correlation, LDS-staged: G = X_S diag(v) X_S^T with the output split into
+// blocks of MTB x MTB tiles and only block pairs bm >= bn computed (G is
+// symmetric).  A workgroup takes chw pixels of the list for one block pair
+// and writes one partial of every tile of it.  Per 64 pixels it stages their
+// steering entries for the rows of both blocks in LDS (coalesced table
+// loads: consecutive threads take consecutive pixels of the list) and the
+// weights; its four waves then split the pair's tiles (the lower triangle of
+// a diagonal pair), each MFMA taking A = v x[rows of bm] and B = x[rows of bn]
+// from LDS.  A tile off the diagonal is also stored transposed, so the
+// partials hold every tile in the layout of forward_kernel.
+template <int MTB>
+__global__ __launch_bounds__(kThreads) void forward_lds_kernel(FwdParams pr) {
+  constexpr int KCH = 64;        // pixels staged at a time (one per thread of a wave)
+  constexpr int ROW = 16 * MTB;  // embedding rows of one block
+  // LDS row stride: the four pixels of a k step read disjoint bank ranges
+  constexpr int RS = ROW + ((ROW % 64 == 0 || ROW % 64 == 32) ? 16 : 0);
+  constexpr int TPW = (MTB * MTB + 3) / 4;  // tiles per wave (at most)
+  __shared__ float xm[KCH * RS];
+  __shared__ float xn[KCH * RS];
+  __shared__ float vs[KCH];
+  if (pr.stop_flag && *pr.stop_flag) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c16 = lane & 15, q = lane >> 4;
+  const int MT = pr.MT;
+  int bm = 0, bn = blockIdx.y;  // the y-th pair of (0,0), (1,0), (1,1), (2,0), ...
+  while (bn > bm) {
+    bn -= bm + 1;
+    ++bm;
+  }
+  const bool diag = bm == bn;
+  const int ntt = diag ? MTB * (MTB + 1) / 2 : MTB * MTB;
+  const int chunk = blockIdx.x;
+  const int k0 = chunk * pr.chw;
+  const int k1 = min(k0 + pr.chw, pr.n);
+  Tables tab = pr.tab;
+  tab.El += blockIdx.z * pr.tab_stride;
+  tab.Em += blockIdx.z * pr.tab_stride;
+  float* part = pr.part + blockIdx.z * pr.part_stride;
+  int tmi[TPW], tni[TPW];  // this wave's tiles (local row / column tile; -1: none)
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = w + 4 * i;
+    int mi = -1, ni = -1;
+    if (t < ntt) {
+      if (diag) {
+        mi = 0;
+        while ((mi + 1) * (mi + 2) / 2 <= t) ++mi;
+        ni = t - mi * (mi + 1) / 2;
+      } else {
+        mi = t / MTB;
+        ni = t - mi * MTB;
+      }
+    }
+    tmi[i] = mi;
+    tni[i] = ni;
+  }
+  v4f acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+  const float* xb = diag ? xm : xn;
+  for (int kb = k0; kb < k1; kb += KCH) {
+    const int kn = min(KCH, k1 - kb);
+    __syncthreads();  // the previous pixels' operands have been read
+    {
+      const int kk = lane;  // pixel of the staged batch; the waves split the antennas
+      const bool live = kk < kn;
+      int pix = 0;
+      float val = 0.f;
+      if (live) {
+        const int k = kb + kk;
+        pix = pr.idx ? pr.idx[k] : k;
+        const bool ok = (unsigned)pix < (unsigned)tab.Q;  // invalid index: term dropped
+        if (!ok) pix = 0;
+        val = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
+      }
+      if (w == 0) vs[kk] = val;
+      const int il = pix % tab.nl, im = pix / tab.nl;
+      for (int j = w; j < 8 * MTB; j += 4) {  // local antenna j of each block
+        const int pm = 8 * MTB * bm + j, pn = 8 * MTB * bn + j;
+        float2 am = make_float2(0.f, 0.f), an = make_float2(0.f, 0.f);
+        if (live && pm < tab.Pp) am = cmul(tab.El[(size_t)pm * tab.nl + il], tab.Em[(size_t)pm * tab.nm + im]);
+        *reinterpret_cast<float2*>(xm + kk * RS + 2 * j) = am;
+        if (!diag) {
+          if (live && pn < tab.Pp) an = cmul(tab.El[(size_t)pn * tab.nl + il], tab.Em[(size_t)pn * tab.nm + im]);
+          *reinterpret_cast<float2*>(xn + kk * RS + 2 * j) = an;
+        }
+      }
+    }
+    __syncthreads();
+    for (int s = 0; s < kn; s += 4) {  // rows kn .. 63 are zero
+      const int r0 = (s + q) * RS + c16;
+      const float v = vs[s + q];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i)
+        if (tmi[i] >= 0)
+          acc[i] = mfma16x16x4(xm[r0 + 16 * tmi[i]] * v, xb[r0 + 16 * tni[i]], acc[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    if (tmi[i] < 0) continue;
+    const int mt = MTB * bm + tmi[i], nt = MTB * bn + tni[i];
+    if (mt >= MT || nt >= MT) continue;
+    *reinterpret_cast<float4*>(part + (((size_t)chunk * MT + mt) * MT + nt) * 256 + lane * 4) =
+        make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
+    if (mt != nt) {  // G[16nt + c16][16mt + 4q + r]: lane 4q + r + 16 (c16 >> 2), element c16 & 3
+      float* tt = part + (((size_t)chunk * MT + nt) * MT + mt) * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tt[((4 * q + r) + 16 * (c16 >> 2)) * 4 + (c16 & 3)] = acc[i][r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Second stage of the correlation: fixed-order sum of the wave partials, then
 //   out = cK * K + cB * B  (complex P x P), optional Ut fragments of `out`,
 //   optional per-block sum |out|^2.  cB may come from the LSQR state
 //   (-alpha/beta) when `lsqr` is set.  out may alias B.
-__global__ __launch_bounds__(kThreads) void reduce_kernel(RedParams pr) {
-  __shared__ double sh[8];
+// One workgroup per output tile (blockIdx.x): its G waves (G = min(16,
+// chunks), the launch's choice) sum every G-th partial each, in order, and
+// the G sums are then added in wave order: a fixed summation order for a given
+// chunk count.  Wave 0 finishes the tile.
+constexpr int kRedGroups = 16;
+__global__ __launch_bounds__(64 * kRedGroups) void reduce_kernel(RedParams pr) {
+  __shared__ float4 sp[kRedGroups][64];
   if (pr.stop_flag && *pr.stop_flag) return;
   {  // covariance block blockIdx.y
     const size_t kb = blockIdx.y;
@@ -385,19 +506,25 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(RedParams pr) {
     if (pr.norm_part) pr.norm_part += kb * pr.norm_stride;
   }
   const int MT = pr.MT, P = pr.P;
-  const int t = blockIdx.x * kThreads + threadIdx.x;
-  const int tile = t >> 6, lane = t & 63;
-  const bool live = tile < MT * MT;
-  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-  int mt = 0, nt = 0;
-  if (live) {
-    mt = tile / MT;
-    nt = tile - mt * MT;
-    for (int c = 0; c < pr.nchunks; ++c) {
+  const int tile = blockIdx.x, lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int ng = blockDim.x >> 6;  // <= kRedGroups
+  const int mt = tile / MT, nt = tile - (tile / MT) * MT;
+  {
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int c = grp; c < pr.nchunks; c += ng) {
       const float4 v =
           *reinterpret_cast<const float4*>(pr.part + (((size_t)c * MT + mt) * MT + nt) * 256 + lane * 4);
       s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
     }
+    sp[grp][lane] = s;
+  }
+  __syncthreads();
+  if (grp != 0) return;
+  const bool live = true;
+  float4 s = sp[0][lane];
+  for (int g = 1; g < ng; ++g) {
+    const float4 v = sp[g][lane];
+    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
   }
   float4 o;
   o.x = __shfl_xor(s.x, 1, 64);
@@ -443,8 +570,8 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(RedParams pr) {
     }
   }
   if (pr.norm_part) {
-    const double tot = block_sum_d(nrm, sh);
-    if (threadIdx.x == 0) pr.norm_part[blockIdx.x] = tot;
+    const double tot = wave_sum_d(nrm);
+    if (lane == 0) pr.norm_part[blockIdx.x] = tot;
   }
 }
 
@@ -741,11 +868,26 @@ hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta
   return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init}, st);
 }
 
-void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm) {
+int forward_lds_chunks_max(int P) {
+  const int MT = pad_p(P) / 8;
+  const int tw = MT <= 3 ? 3 : 6;
+  const int nb = (MT + tw - 1) / tw;
+  return std::max(1, 256 / (nb * (nb + 1) / 2));
+}
+
+void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm, bool splitk) {
   const int MT = pad_p(P) / 8;
   const int tw = MT <= 3 ? 3 : 6;
   const int nb = (MT + tw - 1) / tw;
   *nbm = nb;
+  if (!splitk) {  // LDS-staged: at least 64 pixels per workgroup, at most 256 workgroups over all block pairs
+    const int maxc = forward_lds_chunks_max(P);
+    int c = (n + maxc - 1) / maxc;
+    c = std::max(64, (c + 63) & ~63);
+    *chw = c;
+    *nchunks = n > 0 ? (n + c - 1) / c : 0;
+    return;
+  }
   // about 512 waves in flight, at least 8 pixels per wave, at most 256 partials
   int waves = 512 / (nb * nb);
   if (waves < 1) waves = 1;
@@ -764,6 +906,14 @@ void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm) {
 hipError_t launch_forward(const FwdParams& pr, hipStream_t st) {
   if (pr.n <= 0) return hipSuccess;
   const int nchunks = (pr.n + pr.chw - 1) / pr.chw;
+  if (!pr.splitk) {
+    const dim3 grid(nchunks, pr.nbm * (pr.nbm + 1) / 2, pr.nblk);
+    if (pr.MT <= 3)
+      hipLaunchKernelGGL(forward_lds_kernel<3>, grid, dim3(kThreads), 0, st, pr);
+    else
+      hipLaunchKernelGGL(forward_lds_kernel<6>, grid, dim3(kThreads), 0, st, pr);
+    return hipGetLastError();
+  }
   dim3 grid((nchunks + 3) / 4, pr.nbm * pr.nbn, pr.nblk);
   if (pr.MT <= 3)
     hipLaunchKernelGGL((forward_kernel<3, 3>), grid, dim3(kThreads), 0, st, pr);
@@ -774,12 +924,13 @@ hipError_t launch_forward(const FwdParams& pr, hipStream_t st) {
 
 int reduce_blocks(int P) {
   const int MT = pad_p(P) / 8;
-  return (MT * MT * 64 + kThreads - 1) / kThreads;
+  return MT * MT;  // one workgroup (and one norm partial) per tile
 }
 
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st) {
   const int blocks = reduce_blocks(pr.P);
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks, pr.nblk), dim3(kThreads), 0, st, pr);
+  const int ng = std::min(kRedGroups, std::max(1, pr.nchunks));
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks, pr.nblk), dim3(64 * ng), 0, st, pr);
   return hipGetLastError();
 }
 

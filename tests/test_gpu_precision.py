@@ -134,3 +134,55 @@ def test_timed_dirty_image_is_the_dirty_image(gpu_lib, ctx, kind, prec):
     print(f"  {ms * 1e3:.2f} us", flush=True)
     assert torch.equal(plain, timed)
     assert 0.0 < ms < 1000.0
+
+
+@pytest.mark.parametrize("kind,prec", [("p96", 0), ("p104", 1), ("p40_ragged", 2), ("p96", 2)])
+def test_every_tile_choice_gives_the_same_image(gpu_lib, ctx, kind, prec):
+    # the tile count per workgroup regroups pixels only: the same bits for each
+    # choice, and the autotuner keeps one of them
+    sc = _scene(kind)
+    geo = _geo(gpu_lib, sc)
+    print(f"case beamformer tiles {kind} precision {prec}", flush=True)
+    Rd = torch.as_tensor(sc.R_hat32).cuda()
+    ref = ctx.dirty_image(Rd, geo, precision=prec).clone()
+    for tiles in (2, 4, 8):
+        ctx.set_beam_tiles(sc.P, prec, tiles)
+        assert torch.equal(ctx.dirty_image(Rd, geo, precision=prec), ref), tiles
+    chosen, us = ctx.autotune(geo, precision=prec)
+    print(f"  kept {chosen} tiles; us per image {us}", flush=True)
+    assert chosen in (2, 4, 8) and all(t > 0 for t in us)
+    assert us[(2, 4, 8).index(chosen)] == min(us)
+    assert torch.equal(ctx.dirty_image(Rd, geo, precision=prec), ref)
+    ctx.set_beam_tiles(sc.P, prec, 0)
+
+
+def test_solve_is_the_same_for_every_tile_choice(gpu_lib, ctx):
+    # 96 antennas: the host-driven loop's multipliers use the GEMM-shaped
+    # beamformer, whose argmin partition changes with the tile count
+    sc = synth.make_scene("c2", n=40, points=(12, ("powerlaw", 0.5, 500.0)))
+    geo = _geo(gpu_lib, sc)
+    print(f"case solve P={sc.P} Q={sc.Q} for tiles 2 / 8", flush=True)
+    Rd = torch.as_tensor(sc.R_hat32).cuda()
+    nd = torch.as_tensor(sc.noise_diag.astype(np.float32)).cuda()
+    o = gpu_lib.default_options()
+    o.nsamples = sc.N
+    o.atol = o.btol = 1e-7
+    out = []
+    for tiles in (2, 8):
+        ctx.set_beam_tiles(sc.P, 0, tiles)
+        s, st, _, _, stats = ctx.solve(Rd, geo, o, noise_diag=nd)
+        out.append((s.clone(), st.clone(), stats))
+    ctx.set_beam_tiles(sc.P, 0, 0)
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert out[0][2]["outer_iters"] == out[1][2]["outer_iters"]
+
+
+def test_autotune_rejects(gpu_lib, ctx):
+    sc = _scene("p48")
+    with pytest.raises(gpu_lib.ClsimgError) as ei:  # register-resident kernel: nothing to tune
+        ctx.autotune(_geo(gpu_lib, sc), precision=0)
+    assert ei.value.status == gpu_lib.ENOTSUP
+    for P, tiles in ((96, 3), (288, 8), (0, 2)):
+        with pytest.raises(gpu_lib.ClsimgError) as ei:
+            ctx.set_beam_tiles(P, 0, tiles)
+        assert ei.value.status == gpu_lib.EINVAL

@@ -95,6 +95,15 @@ __device__ __forceinline__ double wave_sum_dpp_d(double v) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
                           __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
+// Sum of n doubles by one full wave in a fixed order: lane l adds p[l],
+// p[l + 64], ... in turn, then an xor butterfly (a + b == b + a, so every
+// lane ends with the same bits).  Call with all 64 lanes of a wave.
+__device__ inline double wave_sum_parts(const double* p, int n) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) s += p[i];
+  return wave_sum_d(s);
+}
 __device__ __forceinline__ float wave_sum_f(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

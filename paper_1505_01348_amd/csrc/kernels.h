@@ -173,10 +173,9 @@ struct EpiLsqrV {
   __device__ void operator()(int tile, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
     __shared__ double sh[8];
     __shared__ double sbeta;
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int i = 0; i < nbeta; ++i) s += beta_part[i];
-      sbeta = sqrt(s);
+    if (threadIdx.x < 64) {  // wave 0, the same order as the LSQR scalar kernels
+      const double s = wave_sum_parts(beta_part, nbeta);
+      if (threadIdx.x == 0) sbeta = sqrt(s);
     }
     __syncthreads();
     const double beta = sbeta;

@@ -880,10 +880,10 @@ void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm, bool splitk) {
   const int tw = MT <= 3 ? 3 : 6;
   const int nb = (MT + tw - 1) / tw;
   *nbm = nb;
-  if (!splitk) {  // LDS-staged: at least 64 pixels per workgroup, at most 256 workgroups over all block pairs
+  if (!splitk) {  // LDS-staged: at least 16 pixels per workgroup, at most 256 workgroups over all block pairs
     const int maxc = forward_lds_chunks_max(P);
     int c = (n + maxc - 1) / maxc;
-    c = std::max(64, (c + 63) & ~63);
+    c = std::max(16, (c + 15) & ~15);
     *chw = c;
     *nchunks = n > 0 ? (n + c - 1) / c : 0;
     return;

@@ -66,12 +66,6 @@ __global__ __launch_bounds__(kCtl) void compact_kernel(const uint8_t* __restrict
   }
 }
 
-__device__ inline double sum_parts(const double* p, int n) {
-  double s = 0.0;
-  for (int i = 0; i < n; ++i) s += p[i];
-  return s;
-}
-
 // ---------------------------------------------------------------------------
 // LSQR start: beta_1 = ||b||, alpha_1 = ||M^H u_1||, v_1, w_1 = v_1, x = 0.
 __global__ __launch_bounds__(kCtl) void lsqr_init_kernel(LsqrState* s, const double* beta_part,
@@ -80,9 +74,12 @@ __global__ __launch_bounds__(kCtl) void lsqr_init_kernel(LsqrState* s, const dou
                                                          int n, double atol, double btol,
                                                          double conlim, int itnlim) {
   __shared__ double sab[2];
-  if (threadIdx.x == 0) {
-    sab[0] = sqrt(sum_parts(alpha_part, nalpha));
-    sab[1] = sqrt(sum_parts(beta_part, nbeta));
+  if (threadIdx.x < 64) {  // wave 0: the norm partials in a fixed order
+    const double a2 = wave_sum_parts(alpha_part, nalpha), b2 = wave_sum_parts(beta_part, nbeta);
+    if (threadIdx.x == 0) {
+      sab[0] = sqrt(a2);
+      sab[1] = sqrt(b2);
+    }
   }
   __syncthreads();
   const double alpha = sab[0], beta = sab[1];
@@ -127,9 +124,14 @@ __global__ __launch_bounds__(kCtl) void lsqr_update_kernel(LsqrState* s, const d
   __shared__ double sc[8];
   __shared__ double red_d[kCtl / 64], red_x[kCtl / 64];
   if (s->done) return;
+  double b2 = 0.0, a2 = 0.0;
+  if (threadIdx.x < 64) {  // wave 0: the norm partials in a fixed order
+    b2 = wave_sum_parts(beta_part, nbeta);
+    a2 = wave_sum_parts(alpha_part, nalpha);
+  }
   if (threadIdx.x == 0) {
-    const double beta = sqrt(sum_parts(beta_part, nbeta));
-    const double alpha = sqrt(sum_parts(alpha_part, nalpha));
+    const double beta = sqrt(b2);
+    const double alpha = sqrt(a2);
     const double alpha_old = s->alpha;
     s->anorm2 += alpha_old * alpha_old + beta * beta;
     const double rho = hypot(s->rhobar, beta);

@@ -72,7 +72,7 @@ struct clsimg_ctx {
   int prec = CLSIMG_FP32;  // arithmetic of the full-grid beamforming products of the current call
   // K covariance blocks: per-block tables and vectors; tables_of() reads the
   // override while a block's operators run
-  DevBuf mb_tab, mb_B0, mb_Bb, mb_u, mb_E, mb_frag, mb_acc, mb_acc2;
+  DevBuf mb_tab, mb_B0, mb_Bb, mb_u, mb_E, mb_frag, mb_acc, mb_acc2, mb_gpart;
   const float2* tab_El = nullptr;
   const float2* tab_Em = nullptr;
   double* h_mnorm = nullptr;  // pinned: the blocks' norm partials
@@ -696,7 +696,8 @@ int clsimg_destroy(clsimg_ctx* c) {
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
                     &c->dec,  &c->status, &c->lsqr2, &c->done, &c->x1, &c->w1, &c->vraw,
                     &c->bpart0, &c->bpart1, &c->xf, &c->bar, &c->frag_h, &c->hscale,
-                    &c->mb_tab, &c->mb_B0, &c->mb_Bb, &c->mb_u, &c->mb_E, &c->mb_frag, &c->mb_acc, &c->mb_acc2};
+                    &c->mb_tab, &c->mb_B0, &c->mb_Bb, &c->mb_u, &c->mb_E, &c->mb_frag, &c->mb_acc, &c->mb_acc2,
+                    &c->mb_gpart};
   for (DevBuf* d : bufs)
     if (d->ptr) (void)hipFree(d->ptr);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -1558,16 +1559,21 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
       // b_k = B0_k - Psi_{U,k} gamma_U  (eq. bsubproblemLS per block)
       ST_TRY(corr(Ulist, gamma, 1, nU, Bbk(0), B0k(0), -1.f, 1.f, nullptr, nullptr, nullptr, nullptr));
       flops += K * corr_flops(P, nU);
-      const int nalpha = ntiles_adj(P, nF);
+      const int nalpha = (nF + 63) / 64;  // the 64-column tiles of launch_lsqr_v_blocks
       const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
-      // Psi_F^H u summed over the blocks in one launch, with the LSQR epilogue
+      // Psi_F^H u over the blocks: one launch whose workgroup rows are the
+      // blocks (column dots kept apart), then the LSQR v update adds them in
+      // block order
+      if (nF > 0) ST_TRY(ensure(c, c->mb_gpart, (size_t)K * nF * sizeof(float)));
       auto adjoint_all = [&](int init, const int* stop) -> int {
         use(0);
         AdjParams ap = adj_params(c, g, P, fragk(0), Flist, nF, stop);
         ap.nblk = K;
         ap.frag_stride = fru;
         ap.tab_stride = tstride;
-        HIP_TRY(launch_adjoint_lsqr(ap, v, beta_part, K * nbeta, alpha_part, init, st));
+        HIP_TRY(launch_adjoint_store_blocks(ap, P_<float>(c->mb_gpart), (size_t)nF, st));
+        HIP_TRY(launch_lsqr_v_blocks(P_<const float>(c->mb_gpart), K, (size_t)nF, nF, v, beta_part, K * nbeta,
+                                     alpha_part, init, stop, st));
         return CLSIMG_OK;
       };
       if (nF > 0) {

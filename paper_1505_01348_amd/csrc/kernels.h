@@ -29,6 +29,9 @@ struct AdjParams {
   // and the tables at El/Em + k * tab_stride (fragment input only)
   int nblk = 1;
   size_t frag_stride = 0, tab_stride = 0;
+  // 1: one block per workgroup (blockIdx.y = block), for epilogues that keep
+  // the blocks apart; 0: every workgroup adds the column dots of all blocks
+  int blk_grid = 0;
 };
 
 struct FwdParams {
@@ -100,6 +103,19 @@ struct EpiStore {
   __device__ Pre prefetch(int, bool) const { return {}; }
   __device__ void operator()(int, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
     if (ok) out[col] = g * scale;
+  }
+};
+
+// column dots of covariance block blockIdx.y at out + blockIdx.y * stride
+struct EpiStoreBlk {
+  float* out;
+  size_t stride;
+  using Ctx = NoCtx;
+  using Pre = NoCtx;
+  __device__ Ctx init() const { return {}; }
+  __device__ Pre prefetch(int, bool) const { return {}; }
+  __device__ void operator()(int, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
+    if (ok) out[blockIdx.y * stride + col] = g;
   }
 };
 
@@ -286,6 +302,8 @@ hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
                                double* alpha_part, int init, hipStream_t st);
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st);
+// the column dots of each of pr.nblk blocks apart: out[k * stride + col], one block per workgroup row
+hipError_t launch_adjoint_store_blocks(const AdjParams& pr, float* out, size_t stride, hipStream_t st);
 int adjoint_lsqr2_tile_width(int MT, int n);
 // optional device timestamps of a launch sequence (hipExtLaunchKernel): the
 // start of its first kernel goes to `start`, the end of its last kernel to
@@ -483,6 +501,9 @@ hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int n
                                     const double* alpha_part, int nalpha, float* v, float* w,
                                     float* x, int n, double atol, double btol, double conlim,
                                     int itnlim, hipStream_t st);
+// v from the per-block adjoint dots (launch_adjoint_store_blocks), 64-column alpha partials
+hipError_t launch_lsqr_v_blocks(const float* gpart, int K, size_t stride, int n, float* v, const double* beta_part,
+                                int nbeta, double* alpha_part, int first, const int* stop, hipStream_t st);
 hipError_t launch_lsqr_update(LsqrState* s, const double* beta_part, int nbeta,
                               const double* alpha_part, int nalpha, float* v, float* w, float* x,
                               int n, hipStream_t st);

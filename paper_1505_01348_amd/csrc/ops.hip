@@ -77,12 +77,13 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
     for (int t = 0; t < NTW; ++t) gp[t] = 0.f;
     // covariance blocks: the column dots of every block add up (one block
     // unless the caller stacks several); Ut of each block is staged anew
-    for (int kb = 0; kb < pr.nblk; ++kb) {
+    const int kb0 = pr.blk_grid ? (int)blockIdx.y : 0, kb1 = pr.blk_grid ? kb0 + 1 : pr.nblk;
+    for (int kb = kb0; kb < kb1; ++kb) {
     const float* fragk = pr.frag ? pr.frag + kb * pr.frag_stride : nullptr;
     Tables tabk = tab;
     tabk.El += kb * pr.tab_stride;
     tabk.Em += kb * pr.tab_stride;
-    if (pr.nblk > 1) loaded = false;
+    if (kb1 - kb0 > 1) loaded = false;
     v4f acc[MTW][NTW];
 #pragma unroll
     for (int mi = 0; mi < MTW; ++mi)
@@ -796,7 +797,7 @@ hipError_t launch_adjoint_epi(const AdjParams& pr, const Epi& epi, hipStream_t s
   auto go = [&](auto kern, int T_) {
     const int ntiles = (pr.n + T_ - 1) / T_;
     const int grid = ntiles < 4096 ? ntiles : 4096;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, pr, epi);
+    hipLaunchKernelGGL(kern, dim3(grid, pr.blk_grid ? pr.nblk : 1), dim3(kThreads), 0, st, pr, epi);
     return hipGetLastError();
   };
   if (pr.MT <= 3) return go(adjoint_kernel<3, 1, 1, Epi>, T = 64);
@@ -866,6 +867,11 @@ hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
                                double* alpha_part, int init, hipStream_t st) {
   return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init}, st);
+}
+hipError_t launch_adjoint_store_blocks(const AdjParams& pr, float* out, size_t stride, hipStream_t st) {
+  AdjParams p = pr;
+  p.blk_grid = 1;
+  return launch_adjoint_epi(p, EpiStoreBlk{out, stride}, st);
 }
 
 int forward_lds_chunks_max(int P) {

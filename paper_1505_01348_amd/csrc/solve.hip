@@ -371,6 +371,40 @@ hipError_t launch_lsqr_init_scalars(LsqrState* s, const double* beta_part, int n
   return hipGetLastError();
 }
 
+// LSQR over K covariance blocks: v <- (sum_k g_k) / beta - beta v (or the sum
+// / beta at the start), the block dots g_k = gpart[k * stride + col] added in
+// block order; one 64-column tile per workgroup, its sum of v^2 to
+// alpha_part[tile] (the tiles of the adjoint's own LSQR epilogue).
+__global__ __launch_bounds__(64) void lsqr_v_blocks_kernel(const float* __restrict__ gpart, int K, size_t stride,
+                                                           int n, float* __restrict__ v,
+                                                           const double* __restrict__ beta_part, int nbeta,
+                                                           double* __restrict__ alpha_part, int first,
+                                                           const int* stop) {
+  if (stop && *stop) return;
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  const double beta = sqrt(wave_sum_parts(beta_part, nbeta));
+  double vr2 = 0.0;
+  if (col < n) {
+    float g = 0.f;
+    for (int k = 0; k < K; ++k) g += gpart[k * stride + col];
+    double vr = beta > 0.0 ? (double)g / beta : 0.0;
+    if (!first) vr -= beta * (double)v[col];
+    const float vf = (float)vr;
+    v[col] = vf;
+    vr2 = (double)vf * vf;
+  }
+  vr2 = wave_sum_d(vr2);
+  if (threadIdx.x == 0) alpha_part[blockIdx.x] = vr2;
+}
+
+hipError_t launch_lsqr_v_blocks(const float* gpart, int K, size_t stride, int n, float* v, const double* beta_part,
+                                int nbeta, double* alpha_part, int first, const int* stop, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lsqr_v_blocks_kernel, dim3((n + 63) / 64), dim3(64), 0, st, gpart, K, stride, n, v, beta_part,
+                     nbeta, alpha_part, first, stop);
+  return hipGetLastError();
+}
+
 hipError_t launch_lsqr_update(LsqrState* s, const double* beta_part, int nbeta,
                               const double* alpha_part, int nalpha, float* v, float* w, float* x,
                               int n, hipStream_t st) {

@@ -386,8 +386,10 @@ template <int MTB>
 __global__ __launch_bounds__(kThreads) void forward_lds_kernel(FwdParams pr) {
   constexpr int KCH = 64;        // pixels staged at a time (one per thread of a wave)
   constexpr int ROW = 16 * MTB;  // embedding rows of one block
-  // LDS row stride: the four pixels of a k step read disjoint bank ranges
-  constexpr int RS = ROW + ((ROW % 64 == 0 || ROW % 64 == 32) ? 16 : 0);
+  // LDS row stride = 17 mod 32: the 16-column reads of consecutive pixels in a
+  // k step share at most one bank, and the staging stores (one row per lane)
+  // spread over the banks
+  constexpr int RS = ROW + ((17 - ROW % 32) + 32) % 32;
   constexpr int TPW = (MTB * MTB + 3) / 4;  // tiles per wave (at most)
   __shared__ float xm[KCH * RS];
   __shared__ float xn[KCH * RS];
@@ -432,35 +434,60 @@ __global__ __launch_bounds__(kThreads) void forward_lds_kernel(FwdParams pr) {
 #pragma unroll
   for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
   const float* xb = diag ? xm : xn;
+  // the table entries of the next batch are loaded into registers while the
+  // current batch is multiplied: lane = pixel, wave w = antennas w, w + 4, ...
+  constexpr int JW = 2 * MTB;  // antennas of one block per wave
+  float2 elm[JW], emm[JW], eln[JW], emn[JW];
+  float nval = 0.f;
+  auto fetch = [&](int kb) {
+    const int kn = min(KCH, k1 - kb);
+    const bool live = lane < kn;
+    int pix = 0;
+    float val = 0.f;
+    if (live) {
+      const int k = kb + lane;
+      pix = pr.idx ? pr.idx[k] : k;
+      const bool ok = (unsigned)pix < (unsigned)tab.Q;  // invalid index: term dropped
+      if (!ok) pix = 0;
+      val = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
+    }
+    nval = val;
+    const int il = pix % tab.nl, im = pix / tab.nl;
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) {
+      const int j = w + 4 * jj;
+      const int pm = min(8 * MTB * bm + j, tab.Pp - 1), pn = min(8 * MTB * bn + j, tab.Pp - 1);
+      elm[jj] = tab.El[(size_t)pm * tab.nl + il];
+      emm[jj] = tab.Em[(size_t)pm * tab.nm + im];
+      if (!diag) {
+        eln[jj] = tab.El[(size_t)pn * tab.nl + il];
+        emn[jj] = tab.Em[(size_t)pn * tab.nm + im];
+      }
+    }
+  };
+  if (k0 < k1) fetch(k0);
   for (int kb = k0; kb < k1; kb += KCH) {
     const int kn = min(KCH, k1 - kb);
     __syncthreads();  // the previous pixels' operands have been read
     {
-      const int kk = lane;  // pixel of the staged batch; the waves split the antennas
-      const bool live = kk < kn;
-      int pix = 0;
-      float val = 0.f;
-      if (live) {
-        const int k = kb + kk;
-        pix = pr.idx ? pr.idx[k] : k;
-        const bool ok = (unsigned)pix < (unsigned)tab.Q;  // invalid index: term dropped
-        if (!ok) pix = 0;
-        val = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
-      }
-      if (w == 0) vs[kk] = val;
-      const int il = pix % tab.nl, im = pix / tab.nl;
-      for (int j = w; j < 8 * MTB; j += 4) {  // local antenna j of each block
-        const int pm = 8 * MTB * bm + j, pn = 8 * MTB * bn + j;
-        float2 am = make_float2(0.f, 0.f), an = make_float2(0.f, 0.f);
-        if (live && pm < tab.Pp) am = cmul(tab.El[(size_t)pm * tab.nl + il], tab.Em[(size_t)pm * tab.nm + im]);
-        *reinterpret_cast<float2*>(xm + kk * RS + 2 * j) = am;
+      const bool live = lane < kn;
+      if (w == 0) vs[lane] = nval;
+#pragma unroll
+      for (int jj = 0; jj < JW; ++jj) {
+        const int j = w + 4 * jj;
+        const bool okm = live && 8 * MTB * bm + j < tab.Pp, okn = live && 8 * MTB * bn + j < tab.Pp;
+        const float2 am = okm ? cmul(elm[jj], emm[jj]) : make_float2(0.f, 0.f);
+        xm[lane * RS + 2 * j] = am.x;  // odd row stride: two 4-byte stores
+        xm[lane * RS + 2 * j + 1] = am.y;
         if (!diag) {
-          if (live && pn < tab.Pp) an = cmul(tab.El[(size_t)pn * tab.nl + il], tab.Em[(size_t)pn * tab.nm + im]);
-          *reinterpret_cast<float2*>(xn + kk * RS + 2 * j) = an;
+          const float2 an = okn ? cmul(eln[jj], emn[jj]) : make_float2(0.f, 0.f);
+          xn[lane * RS + 2 * j] = an.x;
+          xn[lane * RS + 2 * j + 1] = an.y;
         }
       }
     }
     __syncthreads();
+    if (kb + KCH < k1) fetch(kb + KCH);
     for (int s = 0; s < kn; s += 4) {  // rows kn .. 63 are zero
       const int r0 = (s + q) * RS + c16;
       const float v = vs[s + q];

@@ -37,6 +37,9 @@ CASES = {
     "p48_k3_chan": ("c1", 3, 0.0, [1.0, 1.2, 1.4], {"n": 48, "points": (15, ("loguniform", 0.5, 50.0)),
                                                     "blobs": (0, 6.0, 0.0)}),
     "p96_k2_rot": ("c2", 2, 0.03, None, {"n": 40, "points": (20, ("powerlaw", 0.5, 500.0))}),
+    # 13 row tiles: the adjoint's 32-pixel tiles with two waves per row group,
+    # one workgroup row per block
+    "p104_k2_chan": ("c2", 2, 0.0, [1.0, 1.15], {"P": 104, "n": 24, "points": (10, ("powerlaw", 0.5, 500.0))}),
 }
 
 

@@ -256,6 +256,31 @@ def test_solve_c0_identical_sets(gpu_lib, ctx, scenes, noise):
     assert abs(stats["rel_residual"] - ref.rel_residual) <= 1e-5 * max(ref.rel_residual, 1e-12) + 1e-7
 
 
+@pytest.mark.parametrize("host", [False, True])
+def test_solve_ragged_grid(gpu_lib, ctx, host, monkeypatch):
+    # 40 antennas (5 row tiles, padding antennas inside the last tile pair),
+    # 37 x 37 pixels: the last 16-pixel tile holds 9 pixels; device loop and
+    # host loop
+    sc = synth.make_scene("c1", P=40, n=37, seed=41, points=(30, ("loguniform", 0.5, 50.0)), blobs=(1, 5.0, 5.0))
+    print(f"case solve ragged P={sc.P} Q={sc.Q} host={host}", flush=True)
+    ref, mf_ref, gamma_ref = _oracle_solve(sc)
+    c = ctx
+    if host:
+        monkeypatch.setenv("CLSIMG_HOST_LOOP", "1")
+        c = gpu_lib.Context(0)
+    try:
+        sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, c, sc)
+    finally:
+        if host:
+            c.close()
+    print(f"  steps {stats['outer_iters']} / {ref.outer_iters}, nF {stats['nF']}", flush=True)
+    _assert_close(mf, mf_ref, what="ragged mf")
+    _assert_close(gamma, gamma_ref, what="ragged gamma")
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what="ragged sigma")
+    assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
+
+
 def test_solve_c1_image_error(gpu_lib, ctx, scenes):
     sc = scenes["c1"]
     print("case solve c1", flush=True)

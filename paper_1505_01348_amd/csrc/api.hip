@@ -555,7 +555,7 @@ int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* 
   HIP_TRY(launch_init_state(nullptr, nullptr, q.sigma, q.state, Q, st));
   OuterState* ost = reinterpret_cast<OuterState*>(slice + L.st);
   HIP_TRY(launch_outer_init(ost, nullptr, st));
-  const int nblk = beam_grid(Q);
+  const int nblk = beam_grid_batched(Q, L.tiles);
   if (nblk > L.nkeys) return CLSIMG_EINVAL;
   op.st = ost;
   op.Flist = reinterpret_cast<int*>(slice + L.F);
@@ -1914,8 +1914,10 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   if (pwls) ST_TRY(ensure(c, c->pw_h, (size_t)Qmax * sizeof(float)));
 
   // per-request slices of one workspace, all laid out for the largest grid
-  const int bpr = beam_grid(Qmax);  // multiplier blocks per request in the launch
-  const ReqLayout L = request_layout(P, nlmax, nmmax, pwls, bpr);
+  const int tiles = beam_batch_tiles(n, Qmax);
+  const int bpr = beam_grid_batched(Qmax, tiles);  // multiplier blocks per request in the launch
+  ReqLayout L = request_layout(P, nlmax, nmmax, pwls, bpr);
+  L.tiles = tiles;
   ST_TRY(ensure(c, c->batch, L.bytes * n));
   // device parameters: outer-step parameters and multiplier items, then the
   // gathered outer states, the factorisation items and their statuses

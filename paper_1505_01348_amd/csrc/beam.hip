@@ -676,6 +676,19 @@ int beam_grid(int Q) {
   return g < 1 ? 1 : (g > 2048 ? 2048 : g);
 }
 
+int beam_grid_batched(int Q, int tiles) {
+  const int ntiles = (Q + 15) / 16;
+  const int per = kBeamWaves * (tiles < 1 ? 1 : tiles);
+  int g = (ntiles + per - 1) / per;
+  return g < 1 ? 1 : (g > 2048 ? 2048 : g);
+}
+
+int beam_batch_tiles(int n, int Q) {
+  int t = 16;
+  while (t > 1 && (long long)n * beam_grid_batched(Q, t) < 1024) t >>= 1;
+  return t;
+}
+
 hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st, Stamps ts) {
   const int MT = pad_p(P) / 8;
   const int n = 2 * MT * (MT + 1) * 64;

@@ -315,6 +315,13 @@ struct Stamps {
 // beam.hip (register-resident full-grid beamformer, P <= 48)
 bool beam_fits(int P);
 int beam_grid(int Q);  // workgroups of a full-grid launch (= partial keys of the lambda variant)
+// workgroups of one request in a batched multiplier launch when each wave
+// walks `tiles` 16-pixel tiles: the fragments a workgroup builds then serve
+// more MFMAs, while the batch still has workgroups enough for the chip
+int beam_grid_batched(int Q, int tiles);
+// tiles per wave for n requests of Q pixels: the largest power of two up to 16
+// that leaves the launch at least 1024 workgroups (1 for small batches)
+int beam_batch_tiles(int n, int Q);
 hipError_t launch_beam_prep(const float2* U, int P, float* frag, hipStream_t st, Stamps ts = {});
 // the fragments come from frag (beam_prep layout) when U is null, else are built from U
 hipError_t launch_beam_mf(const float* frag, const float2* U, int P, const Tables& tab, float* mf, float* eps,

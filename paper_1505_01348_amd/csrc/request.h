@@ -15,6 +15,7 @@ namespace clsimg {
 struct ReqLayout {
   size_t El, Em, B0, Bb, E, eps, gam, mf, F, U, st, keys, rs, gpw, dinv, Lw, bytes;
   int nkeys;
+  int tiles = 1;  // 16-pixel tiles per wave of the request's multiplier blocks
 };
 
 // Layout for P antennas and an nl x nm grid; nkeys argmin keys.

@@ -186,7 +186,9 @@ void finish_now(clsimg_server* s, const Job& j, int status) {
 }
 
 ReqLayout layout_for(const clsimg_server* s, const clsimg_request& q) {
-  return request_layout(q.array.P, q.grid.nl, q.grid.nm, s->opts.cost == CLSIMG_COST_PWLS, kKeysPerReq);
+  ReqLayout L = request_layout(q.array.P, q.grid.nl, q.grid.nm, s->opts.cost == CLSIMG_COST_PWLS, kKeysPerReq);
+  L.tiles = beam_batch_tiles(s->max_slots, q.grid.nl * q.grid.nm);  // as if every slot were busy
+  return L;
 }
 
 // Admit waiting requests into free slots while the arena has room for them.

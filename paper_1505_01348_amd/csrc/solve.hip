@@ -8,61 +8,79 @@ namespace clsimg {
 constexpr int kCtl = 1024;  // single-workgroup control kernels
 
 // ---------------------------------------------------------------------------
-// Sorted index lists of F (state 1) and U (state 2); one workgroup.  Each
-// thread owns a contiguous run of 16-byte words of the state array.
+// Sorted index lists of F (state 1) and U (state 2); one workgroup.  The
+// state array is taken in rounds of 16 KiB: thread t holds the 16 states of
+// word t of the round (one coalesced 16-byte load), the counts are scanned
+// with wave shuffles plus one exchange of the wave totals, and each thread
+// writes its pixels in order.  Two barriers per round.
 __global__ __launch_bounds__(kCtl) void compact_kernel(const uint8_t* __restrict__ state, int Q,
                                                        int* __restrict__ Flist,
                                                        int* __restrict__ Ulist,
                                                        SolveDecision* dec) {
-  __shared__ int sF[kCtl], sU[kCtl];
-  const int tid = threadIdx.x;
+  constexpr int NW = kCtl / 64;
+  __shared__ int wf[NW], wu[NW];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool vec = (reinterpret_cast<uintptr_t>(state) & 15) == 0;
-  const int per = 16 * ((Q + 16 * kCtl - 1) / (16 * kCtl));
-  const int b = tid * per, e = min(Q, b + per);
-  int cf = 0, cu = 0;
-  for (int i = b; i < e; i += 16) {
-    if (vec && i + 16 <= e) {
-      const uint4 wv = *reinterpret_cast<const uint4*>(state + i);
-      const uint32_t ws[4] = {wv.x, wv.y, wv.z, wv.w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t sv = (ws[j] >> (8 * k)) & 0xFFu;
-          cf += (sv == 1);
-          cu += (sv == 2);
-        }
+  int baseF = 0, baseU = 0;  // pixels of F and U in the rounds before (the same in every thread)
+  for (int r0 = 0; r0 < Q; r0 += 16 * kCtl) {
+    const int i0 = r0 + 16 * tid;
+    uint32_t ws[4] = {0u, 0u, 0u, 0u};  // states past Q read as 0 (L)
+    if (vec && i0 + 16 <= Q) {
+      const uint4 v = *reinterpret_cast<const uint4*>(state + i0);
+      ws[0] = v.x;
+      ws[1] = v.y;
+      ws[2] = v.z;
+      ws[3] = v.w;
     } else {
-      for (int k = i; k < min(e, i + 16); ++k) {
-        const uint8_t sv = state[k];
-        cf += (sv == 1);
-        cu += (sv == 2);
+      for (int k = 0; k < 16 && i0 + k < Q; ++k) ws[k >> 2] |= (uint32_t)state[i0 + k] << (8 * (k & 3));
+    }
+    int cf = 0, cu = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t sv = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+      cf += (sv == 1);
+      cu += (sv == 2);
+    }
+    int sf = cf, su = cu;  // inclusive scan over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int tf = __shfl_up(sf, o, 64), tu = __shfl_up(su, o, 64);
+      if (lane >= o) {
+        sf += tf;
+        su += tu;
       }
     }
-  }
-  sF[tid] = cf;
-  sU[tid] = cu;
-  __syncthreads();
-  // inclusive Hillis-Steele scan
-  for (int o = 1; o < kCtl; o <<= 1) {
-    const int af = tid >= o ? sF[tid - o] : 0;
-    const int au = tid >= o ? sU[tid - o] : 0;
-    __syncthreads();
-    sF[tid] += af;
-    sU[tid] += au;
-    __syncthreads();
-  }
-  int of = sF[tid] - cf, ou = sU[tid] - cu;
-  if (cf + cu > 0) {
-    for (int i = b; i < e; ++i) {
-      const uint8_t sv = state[i];
-      if (sv == 1) Flist[of++] = i;
-      else if (sv == 2) Ulist[ou++] = i;
+    if (lane == 63) {
+      wf[w] = sf;
+      wu[w] = su;
     }
+    __syncthreads();
+    int pf = 0, pu = 0, tf = 0, tu = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      if (k < w) {
+        pf += wf[k];
+        pu += wu[k];
+      }
+      tf += wf[k];
+      tu += wu[k];
+    }
+    int of = baseF + pf + sf - cf, ou = baseU + pu + su - cu;
+    if (cf + cu > 0) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t sv = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+        if (sv == 1) Flist[of++] = i0 + k;
+        else if (sv == 2) Ulist[ou++] = i0 + k;
+      }
+    }
+    baseF += tf;
+    baseU += tu;
+    __syncthreads();  // the wave totals are rewritten in the next round
   }
-  if (tid == kCtl - 1) {
-    dec->nF = sF[tid];
-    dec->nU = sU[tid];
+  if (tid == 0) {
+    dec->nF = baseF;
+    dec->nU = baseU;
   }
 }
 

@@ -127,3 +127,38 @@ def test_batch_reports_a_covariance_that_is_not_positive_definite(gpu_lib):
         assert torch.equal(res[0][1], st0) and torch.equal(res[0][0], s0)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_half_precision_batch(gpu_lib, prec):
+    # the batch at FP16 / BF16 (the dirty images and bounds of the set-up in
+    # split half precision): each request equals its solve alone; FP16 also
+    # meets the FP32 bar against the oracle with the same sets
+    scenes = _scenes("p24")[:4] + _scenes("p48")[:1]
+    scenes = [sc for sc in scenes if sc.P == scenes[0].P]
+    print(f"case batch precision {prec}: {len(scenes)} requests", flush=True)
+    ctx = gpu_lib.Context(0)
+    try:
+        opts = _opts(gpu_lib, scenes[0])
+        opts.precision = prec
+        st, res = ctx.solve_batch([_req(gpu_lib, sc) for sc in scenes], opts)
+        torch.cuda.synchronize()
+        assert st >= 0, st
+        for i, sc in enumerate(scenes):
+            r = _req(gpu_lib, sc)
+            sigma, state, mf, gamma, stats = ctx.solve(r["R"], r["geo"], opts, noise_diag=r["noise_diag"])
+            bs, bst = res[i][0], res[i][1]
+            assert torch.equal(state, bst) and torch.equal(sigma, bs), i
+            if prec == 1:
+                R = sc.R_hat32_c128
+                A = oracle.steering(sc.pos, sc.lam, sc.grid)
+                nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
+                ref = oracle.solve(A, R - np.diag(nd), oracle.upper_bound(A, R),
+                                   oracle.detection_threshold(oracle.mf_image(A, R), 6.0, sc.N), atol=1e-8,
+                                   btol=1e-8)
+                err = float(np.linalg.norm(sigma.cpu().numpy() - ref.sigma) / np.linalg.norm(ref.sigma))
+                print(f"  request {i}: image error {err:.2e}", flush=True)
+                np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
+                assert err <= 1e-5
+    finally:
+        ctx.close()

@@ -93,7 +93,7 @@ def test_full_size_dirty_image_sampled(gpu_lib, ctx, prec):
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("kind", ["p24", "p96"])
+@pytest.mark.parametrize("kind", ["p24", "p40_ragged", "p48", "p96"])
 def test_solve(gpu_lib, ctx, kind, prec):
     sc = _scene(kind)
     print(f"case {NAME[prec]} solve {kind} P={sc.P} Q={sc.Q}", flush=True)

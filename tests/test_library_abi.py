@@ -76,3 +76,26 @@ def test_create_without_device_is_rejected():
     h = ctypes.c_void_p()
     assert lib.clsimg_create(ctypes.byref(h), 0, 0) == clsimg.EINVAL
     assert lib.clsimg_destroy(None) == clsimg.EINVAL
+
+
+def test_entry_points_reject_a_null_context():
+    # every call checks its handle and required pointers before any device
+    # work, so these run without a GPU
+    lib = clsimg.load_library()
+    E = clsimg.EINVAL
+    n = None
+    assert lib.clsimg_dirty_image(n, n, n, n, 0, n, n) == E
+    assert lib.clsimg_dirty_image_timed(n, n, n, n, 0, n, n, n, n) == E
+    assert lib.clsimg_mvdr_bound(n, n, n, n, n, n, n) == E
+    assert lib.clsimg_forward(n, n, n, n, n, 0, n, n) == E
+    assert lib.clsimg_adjoint(n, n, n, n, n, 0, n, n) == E
+    assert lib.clsimg_solve(n, n, n, n, n, n, n, n, n, n, n, n, n, n) == E
+    assert lib.clsimg_solve_batch(n, 1, n, n, n) == E
+    assert lib.clsimg_solve_multi(n, 1, n, n, n, n, n, n, n, n, n) == E
+    assert lib.clsimg_solve_offgrid(n, n, n, n, n, n, 3, n, n, n, n, n, n, n) == E
+    assert lib.clsimg_autotune(n, n, n, 0, n, n, n) == E
+    assert lib.clsimg_set_beam_tiles(n, 48, 0, 2) == E
+    assert lib.clsimg_server_submit(n, n, n) == E
+    assert lib.clsimg_server_poll(n, 0, n, 0, n) == E
+    assert lib.clsimg_server_query(n, n) == E
+    assert lib.clsimg_server_destroy(n) == E

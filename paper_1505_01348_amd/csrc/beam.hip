@@ -223,6 +223,10 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
       tm[j] = em[(size_t)4 * j * nm];
     }
   };
+  // workgroups are dealt round robin to the 8 XCDs: give each XCD a
+  // contiguous run of tiles (whole image rows), so that its L2 holds only its
+  // rows' part of the m table rather than every XCD fetching all of it
+  if (nblk % 8 == 0) blk = (blk % 8) * (nblk / 8) + blk / 8;
   int tile = blk * kBeamWaves + (threadIdx.x >> 6);
   float fa[NFR];
   if (U) {

@@ -91,7 +91,7 @@ def parse():
                          "pixels) through the continuous-batching server, against one solve at a time")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=16, help="Table I steps per server poll")
-    ap.add_argument("--serve-workers", type=int, default=4, help="server threads for P > 48 requests")
+    ap.add_argument("--serve-workers", type=int, default=8, help="server threads for P > 48 requests")
     ap.add_argument("--batched-extra", type=str, default="16,256",
                     help="after the timed solves, also time batched calls of these numbers of requests of "
                          "the workload, comma separated (reported under 'batched'; 0 = skip)")

@@ -27,7 +27,7 @@
 
 namespace clsimg {
 
-constexpr int kXs = 12288;  // LDS floats of staged steering entries
+constexpr int kXs = 24576;  // LDS floats of staged steering entries (96 KiB)
 
 __host__ __device__ inline int os_row_stride(int Pp) { return 2 * Pp + 16; }
 __host__ __device__ inline int os_chunk(int Pp) { return (kXs / os_row_stride(Pp)) & ~15; }

@@ -494,7 +494,7 @@ ReqLayout request_layout(int P, int nl, int nm, bool pwls, int nkeys) {
 }
 
 int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* slice, const ReqLayout& L,
-                  OuterParams& op, BeamLamItem& it, hipStream_t st, const float2* rinv) {
+                  OuterParams& op, BeamLamItem& it, hipStream_t st, const float2* rinv, const SetupItems* defer) {
   memset(&q.stats, 0, sizeof(clsimg_stats));
   c->prec = o->precision;
   const int P = q.array.P, Pp = pad_p(P);
@@ -505,11 +505,29 @@ int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* 
   if (pwls) ST_TRY(ensure(c, c->pw_h, (size_t)Q * sizeof(float)));
   const float2* Rf = reinterpret_cast<const float2*>(q.R);
   // the steering tables: built in the context, then kept in the slice
-  ST_TRY(ensure_tables(c, &q.array, &q.grid, st));
-  float2* El = reinterpret_cast<float2*>(slice + L.El);
-  float2* Em = reinterpret_cast<float2*>(slice + L.Em);
-  HIP_TRY(hipMemcpyAsync(El, c->El.ptr, (size_t)Pp * q.grid.nl * sizeof(float2), hipMemcpyDeviceToDevice, st));
-  HIP_TRY(hipMemcpyAsync(Em, c->Em.ptr, (size_t)Pp * q.grid.nm * sizeof(float2), hipMemcpyDeviceToDevice, st));
+  const float2* El;
+  const float2* Em;
+  if (defer && !defer->shared_tables) {  // built into the slice by the batched tables launch
+    float2* sl = reinterpret_cast<float2*>(slice + L.El);
+    float2* sm = reinterpret_cast<float2*>(slice + L.Em);
+    memcpy(defer->pos_host, q.array.pos_xy, sizeof(double) * 2 * P);
+    const clsimg_grid& g = q.grid;
+    *defer->table = TableItem{defer->pos_dev, q.array.lambda, g.l0, g.dl, g.m0, g.dm, P, g.nl, g.nm, sl, sm};
+    El = sl;
+    Em = sm;
+  } else {
+    ST_TRY(ensure_tables(c, &q.array, &q.grid, st));
+    El = P_<const float2>(c->El);
+    Em = P_<const float2>(c->Em);
+    if (!defer) {
+      float2* sl = reinterpret_cast<float2*>(slice + L.El);
+      float2* sm = reinterpret_cast<float2*>(slice + L.Em);
+      HIP_TRY(hipMemcpyAsync(sl, El, (size_t)Pp * q.grid.nl * sizeof(float2), hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(sm, Em, (size_t)Pp * q.grid.nm * sizeof(float2), hipMemcpyDeviceToDevice, st));
+      El = sl;
+      Em = sm;
+    }
+  }
   Tables tab;
   tab.El = El;
   tab.Em = Em;
@@ -522,14 +540,25 @@ int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* 
   float* mf = q.mf ? q.mf : reinterpret_cast<float*>(slice + L.mf);
   float* gamma = q.gamma ? q.gamma : reinterpret_cast<float*>(slice + L.gam);
   float2* B0 = reinterpret_cast<float2*>(slice + L.B0);
-  ST_TRY(beam_full(c, &q.grid, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
-  ST_TRY(compute_bound(c, q.R, &q.array, &q.grid, o, gamma, st, rinv));
+  OuterState* ost = reinterpret_cast<OuterState*>(slice + L.st);
+  const int nblk = beam_grid_batched(Q, L.tiles);
+  if (nblk > L.nkeys) return CLSIMG_EINVAL;
+  if (defer) {
+    if (pwls || !rinv || o->bound != CLSIMG_BOUND_MVDR || c->prec != CLSIMG_FP32 || !beam_fits(P) || c->beam_prep)
+      return CLSIMG_EINVAL;
+    const double kb = o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1)) : 0.0;
+    *defer->beam = BeamSetItem{Rf, rinv, tab, mf, eps, gamma, eps_scale, o->C, kb, P, nblk};
+    *defer->init = ReqInitItem{Rf, q.noise_diag, B0, q.sigma, q.state, ost, P, Q};
+  } else {
+    ST_TRY(beam_full(c, &q.grid, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
+    ST_TRY(compute_bound(c, q.R, &q.array, &q.grid, o, gamma, st, rinv));
+  }
   const float* op_gamma = gamma;
   const float* rowscale = nullptr;
   const float2* Lw = nullptr;
   const float* dinv = nullptr;
   if (!pwls) {
-    HIP_TRY(launch_sub_diag(Rf, q.noise_diag, P, B0, st));
+    if (!defer) HIP_TRY(launch_sub_diag(Rf, q.noise_diag, P, B0, st));
   } else {
     if (o->bound != CLSIMG_BOUND_MVDR) {
       HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
@@ -552,11 +581,10 @@ int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* 
     Lw = lw;
     dinv = dv;
   }
-  HIP_TRY(launch_init_state(nullptr, nullptr, q.sigma, q.state, Q, st));
-  OuterState* ost = reinterpret_cast<OuterState*>(slice + L.st);
-  HIP_TRY(launch_outer_init(ost, nullptr, st));
-  const int nblk = beam_grid_batched(Q, L.tiles);
-  if (nblk > L.nkeys) return CLSIMG_EINVAL;
+  if (!defer) {
+    HIP_TRY(launch_init_state(nullptr, nullptr, q.sigma, q.state, Q, st));
+    HIP_TRY(launch_outer_init(ost, nullptr, st));
+  }
   op.st = ost;
   op.Flist = reinterpret_cast<int*>(slice + L.F);
   op.Ulist = reinterpret_cast<int*>(slice + L.U);
@@ -1919,9 +1947,24 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   ReqLayout L = request_layout(P, nlmax, nmmax, pwls, bpr);
   L.tiles = tiles;
   ST_TRY(ensure(c, c->batch, L.bytes * n));
-  // device parameters: outer-step parameters and multiplier items, then the
-  // gathered outer states, the factorisation items and their statuses
-  const size_t pbytes = (size_t)n * (sizeof(OuterParams) + sizeof(BeamLamItem));
+  // the least-squares cost with the MVDR bound (factored below), FP32: the
+  // per-request set-up launches become two batched launches
+  const bool fused = !pwls && o->bound == CLSIMG_BOUND_MVDR && P <= kCholLdsMaxP &&
+                     o->precision == CLSIMG_FP32 && !c->beam_prep;
+  bool shared_tables = fused;
+  for (int r = 1; r < n && shared_tables; ++r) {
+    const clsimg_array &a0 = reqs[0].array, &a = reqs[r].array;
+    shared_tables = a.lambda == a0.lambda && memcmp(&reqs[r].grid, &reqs[0].grid, sizeof(clsimg_grid)) == 0 &&
+                    memcmp(a.pos_xy, a0.pos_xy, sizeof(double) * 2 * P) == 0;
+  }
+  // device parameters: outer-step parameters and multiplier items (then the
+  // set-up items), then the gathered outer states, the factorisation items
+  // and their statuses
+  const bool own_tables = fused && !shared_tables;
+  const size_t pbytes =
+      (size_t)n * (sizeof(OuterParams) + sizeof(BeamLamItem) +
+                   (fused ? sizeof(ReqInitItem) + sizeof(BeamSetItem) : 0) +
+                   (own_tables ? sizeof(TableItem) + sizeof(double) * 2 * P : 0));
   const size_t off_st = (pbytes + 255) & ~(size_t)255;
   const size_t off_ci = (off_st + (size_t)n * sizeof(OuterState) + 255) & ~(size_t)255;
   const size_t off_cs = (off_ci + (size_t)n * sizeof(CholItem) + 255) & ~(size_t)255;
@@ -1961,13 +2004,32 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
       if (hstat[r] != 0) return CLSIMG_ENOTPD;
     rinv = P_<const float2>(c->batch_rinv);
   }
+  const size_t off_ii = (size_t)n * (sizeof(OuterParams) + sizeof(BeamLamItem));
+  const size_t off_bi = off_ii + (size_t)n * sizeof(ReqInitItem);
+  const size_t off_ti = off_bi + (size_t)n * sizeof(BeamSetItem);
+  const size_t off_pos = off_ti + (size_t)n * sizeof(TableItem);
   OuterParams* hp = reinterpret_cast<OuterParams*>(c->h_batch);
   BeamLamItem* hi = reinterpret_cast<BeamLamItem*>(c->h_batch + (size_t)n * sizeof(OuterParams));
-  for (int r = 0; r < n; ++r)
-    ST_TRY(request_setup(c, reqs[r], o, slice(r), L, hp[r], hi[r], st, rinv ? rinv + (size_t)r * P * P : nullptr));
+  for (int r = 0; r < n; ++r) {
+    SetupItems items{reinterpret_cast<ReqInitItem*>(c->h_batch + off_ii) + r,
+                     reinterpret_cast<BeamSetItem*>(c->h_batch + off_bi) + r,
+                     shared_tables,
+                     own_tables ? reinterpret_cast<TableItem*>(c->h_batch + off_ti) + r : nullptr,
+                     own_tables ? reinterpret_cast<double*>(c->h_batch + off_pos) + (size_t)r * 2 * P : nullptr,
+                     own_tables ? reinterpret_cast<const double*>(dbase + off_pos) + (size_t)r * 2 * P : nullptr};
+    ST_TRY(request_setup(c, reqs[r], o, slice(r), L, hp[r], hi[r], st, rinv ? rinv + (size_t)r * P * P : nullptr,
+                         fused && rinv ? &items : nullptr));
+  }
   OuterParams* dp = P_<OuterParams>(c->batch_params);
   BeamLamItem* di = reinterpret_cast<BeamLamItem*>(P_<char>(c->batch_params) + (size_t)n * sizeof(OuterParams));
   HIP_TRY(hipMemcpyAsync(dp, c->h_batch, pbytes, hipMemcpyHostToDevice, st));
+  if (fused && rinv) {
+    if (own_tables)
+      HIP_TRY(launch_tables_batch(reinterpret_cast<const TableItem*>(dbase + off_ti), n, pad_p(P) * (nlmax + nmmax),
+                                  st));
+    HIP_TRY(launch_request_init_batch(reinterpret_cast<const ReqInitItem*>(dbase + off_ii), n, Qmax, st));
+    HIP_TRY(launch_beam_setup_batch(reinterpret_cast<const BeamSetItem*>(dbase + off_bi), n, bpr, P, st));
+  }
   // wait for the upload before the staging is reused for the state read-backs
   HIP_TRY(hipStreamSynchronize(st));
 

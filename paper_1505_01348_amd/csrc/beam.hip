@@ -288,6 +288,23 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
   beam_body<MT>(nullptr, it.U, it.P, it.tab, it.skip, epi, lb, it.nblk);
 }
 
+// Set-up beamformers of a batch of requests: grid.x runs over nreq x bpr
+// blocks, grid.y picks the dirty image (0) or the MVDR bound (1).
+template <int MT>
+__global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu(1, 2))) void beam_setup_batch_kernel(
+    const BeamSetItem* __restrict__ items, int bpr) {
+  const int r = blockIdx.x / bpr, lb = blockIdx.x - r * bpr;
+  const BeamSetItem it = items[r];
+  if (lb >= it.nblk) return;
+  if (blockIdx.y == 0) {
+    BeamMF epi{it.mf, it.eps, it.eps_scale};
+    beam_body<MT>(nullptr, it.R, it.P, it.tab, nullptr, epi, lb, it.nblk);
+  } else {
+    BeamMVDR epi{it.gamma, it.C, it.kb};
+    beam_body<MT>(nullptr, it.Rinv, it.P, it.tab, nullptr, epi, lb, it.nblk);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Larger arrays (P > 48): the fragments of the whole Ut no longer fit in
 // registers, so the product is organised like a GEMM.  A workgroup takes NT
@@ -893,6 +910,20 @@ hipError_t launch_beam_lambda_batch(const BeamLamItem* items, int nreq, int bpr,
     case 4: hipLaunchKernelGGL(beam_lambda_batch_kernel<4>, g, b, 0, st, items, bpr); break;
     case 5: hipLaunchKernelGGL(beam_lambda_batch_kernel<5>, g, b, 0, st, items, bpr); break;
     case 6: hipLaunchKernelGGL(beam_lambda_batch_kernel<6>, g, b, 0, st, items, bpr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_setup_batch(const BeamSetItem* items, int nreq, int bpr, int P, hipStream_t st) {
+  const dim3 g(nreq * bpr, 2), b(64 * kBeamWaves);
+  switch (pad_p(P) / 8) {
+    case 1: hipLaunchKernelGGL(beam_setup_batch_kernel<1>, g, b, 0, st, items, bpr); break;
+    case 2: hipLaunchKernelGGL(beam_setup_batch_kernel<2>, g, b, 0, st, items, bpr); break;
+    case 3: hipLaunchKernelGGL(beam_setup_batch_kernel<3>, g, b, 0, st, items, bpr); break;
+    case 4: hipLaunchKernelGGL(beam_setup_batch_kernel<4>, g, b, 0, st, items, bpr); break;
+    case 5: hipLaunchKernelGGL(beam_setup_batch_kernel<5>, g, b, 0, st, items, bpr); break;
+    case 6: hipLaunchKernelGGL(beam_setup_batch_kernel<6>, g, b, 0, st, items, bpr); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -346,6 +346,23 @@ struct BeamLamItem {
 };
 // grid: nreq x bpr blocks, bpr >= every item's nblk; all items share P's tile count
 hipError_t launch_beam_lambda_batch(const BeamLamItem* items, int nreq, int bpr, int P, hipStream_t st);
+// Set-up beamformers of a batch of requests in one launch (P <= 48): grid.y 0
+// gives each request's dirty image a^H R a and detection thresholds, grid.y 1
+// its MVDR bound from R^-1.  Per pixel the same arithmetic as the full-grid
+// launches, so each result is bit-identical to the request's own set-up.
+struct BeamSetItem {
+  const float2* R;
+  const float2* Rinv;
+  Tables tab;
+  float* mf;
+  float* eps;
+  float* gamma;
+  float eps_scale;
+  double C, kb;  // MVDR bound C / h + kb / h
+  int P;
+  int nblk;
+};
+hipError_t launch_beam_setup_batch(const BeamSetItem* items, int nreq, int bpr, int P, hipStream_t st);
 
 // GEMM-shaped full-grid beamformer for larger arrays (P <= 288)
 bool beam_big_fits(int P);
@@ -426,6 +443,16 @@ struct CholItem {
 hipError_t launch_chol_inverse_batch(const CholItem* items, int n, int P, hipStream_t st);
 hipError_t launch_tables(const double* pos, int P, double lambda, int nl, int nm, double l0,
                          double dl, double m0, double dm, float2* El, float2* Em, hipStream_t st);
+// Steering tables of a batch of geometries in one launch, every entry as
+// launch_tables computes it.  total_max: the largest Pp (nl + nm).
+struct TableItem {
+  const double* pos;  // 2P positions (x, y), device
+  double lambda, l0, dl, m0, dm;
+  int P, nl, nm;
+  float2* El;
+  float2* Em;
+};
+hipError_t launch_tables_batch(const TableItem* items, int nreq, int total_max, hipStream_t st);
 hipError_t launch_sub_diag(const float2* R, const float* noise, int P, float2* B0, hipStream_t st);
 hipError_t launch_fill(float* x, float v, int n, hipStream_t st);
 
@@ -499,6 +526,18 @@ hipError_t launch_pwls_setup(const float* h, const float* gamma, double C, doubl
 hipError_t launch_pwls_whiten(const double2* Li, const float2* B0, int P, float2* Lw, float2* B0w, hipStream_t st);
 hipError_t launch_pwls_scale(float* x, const float* s, int n, bool divide, hipStream_t st);
 hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s);
+// Fresh state of a batch of requests in one launch: B0 = R - diag(noise),
+// sigma = 0, every pixel at its lower bound, a fresh outer state.
+struct ReqInitItem {
+  const float2* R;
+  const float* noise;  // optional
+  float2* B0;
+  float* sigma;
+  uint8_t* state;
+  OuterState* st;
+  int P, Q;
+};
+hipError_t launch_request_init_batch(const ReqInitItem* items, int nreq, int Qmax, hipStream_t s);
 hipError_t launch_outer_step(const OuterParams& pr, hipStream_t s);
 // prs: device array of nreq parameter sets with the same P
 hipError_t launch_outer_step_batch(const OuterParams* prs, int nreq, int P, hipStream_t s);

@@ -772,29 +772,46 @@ __global__ __launch_bounds__(256) void chol_inverse_lds_kernel(CholItem one, con
 // Separable steering tables, FP64 phases rounded once to complex64:
 //   El[p][il] = P^-1/2 exp(-j 2pi x_p l_il / lambda),  Em[p][im] = exp(-j 2pi y_p m_im / lambda),
 // zero rows for the padding antennas p >= P.
+// Entry t of the tables of one geometry: the El entries (Pp x nl) first, then
+// the Em entries (Pp x nm).
+__device__ inline void table_entry(int t, const double* __restrict__ pos, int P, int Pp, double lambda, int nl,
+                                   int nm, double l0, double dl, double m0, double dm, float2* __restrict__ El,
+                                   float2* __restrict__ Em) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const double norm = 1.0 / sqrt((double)P);
+  const int nEl = Pp * nl;
+  const bool is_l = t < nEl;
+  const int e = is_l ? t : t - nEl;
+  const int n = is_l ? nl : nm;
+  const int p = e / n, i = e - p * n;
+  float2 v = make_float2(0.f, 0.f);
+  if (p < P) {
+    const double dir = is_l ? l0 + i * dl : m0 + i * dm;
+    const double coord = pos[2 * p + (is_l ? 0 : 1)];
+    double sn, cs;
+    sincos(-two_pi * coord * dir / lambda, &sn, &cs);
+    const double sc = is_l ? norm : 1.0;
+    v = make_float2((float)(sc * cs), (float)(sc * sn));
+  }
+  if (is_l) El[e] = v;
+  else Em[e] = v;
+}
+
 __global__ void tables_kernel(const double* __restrict__ pos, int P, int Pp, double lambda, int nl,
                               int nm, double l0, double dl, double m0, double dm,
                               float2* __restrict__ El, float2* __restrict__ Em) {
-  const double two_pi = 6.283185307179586476925286766559;
-  const double norm = 1.0 / sqrt((double)P);
-  const int nEl = Pp * nl, total = nEl + Pp * nm;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-    const bool is_l = t < nEl;
-    const int e = is_l ? t : t - nEl;
-    const int n = is_l ? nl : nm;
-    const int p = e / n, i = e - p * n;
-    float2 v = make_float2(0.f, 0.f);
-    if (p < P) {
-      const double dir = is_l ? l0 + i * dl : m0 + i * dm;
-      const double coord = pos[2 * p + (is_l ? 0 : 1)];
-      double sn, cs;
-      sincos(-two_pi * coord * dir / lambda, &sn, &cs);
-      const double sc = is_l ? norm : 1.0;
-      v = make_float2((float)(sc * cs), (float)(sc * sn));
-    }
-    if (is_l) El[e] = v;
-    else Em[e] = v;
-  }
+  const int total = Pp * (nl + nm);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x)
+    table_entry(t, pos, P, Pp, lambda, nl, nm, l0, dl, m0, dm, El, Em);
+}
+
+// per blocks per request
+__global__ void tables_batch_kernel(const TableItem* __restrict__ items, int per) {
+  const int r = blockIdx.x / per, b = blockIdx.x - r * per;
+  const TableItem it = items[r];
+  const int Pp = pad_p(it.P), total = Pp * (it.nl + it.nm);
+  for (int t = b * blockDim.x + threadIdx.x; t < total; t += per * blockDim.x)
+    table_entry(t, it.pos, it.P, Pp, it.lambda, it.nl, it.nm, it.l0, it.dl, it.m0, it.dm, it.El, it.Em);
 }
 
 // ---------------------------------------------------------------------------
@@ -981,6 +998,12 @@ hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, 
 hipError_t launch_chol_inverse_batch(const CholItem* items, int n, int P, hipStream_t st) {
   if (P > kCholLdsMaxP || n < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(chol_inverse_lds_kernel, dim3(n), dim3(256), 0, st, CholItem{}, items, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_tables_batch(const TableItem* items, int nreq, int total_max, hipStream_t st) {
+  const int per = std::max(1, std::min(16, (total_max + kThreads - 1) / kThreads));
+  hipLaunchKernelGGL(tables_batch_kernel, dim3(nreq * per), dim3(kThreads), 0, st, items, per);
   return hipGetLastError();
 }
 

@@ -528,8 +528,7 @@ __global__ __launch_bounds__(kCuThreads) void outer_step_batch_kernel(const Oute
   outer_step_body<MT>(pr);
 }
 
-__global__ void outer_init_kernel(OuterState* st, const SolveDecision* dec) {
-  if (threadIdx.x != 0) return;
+__device__ OuterState fresh_outer_state(const SolveDecision* dec) {
   OuterState S = {};
   S.nF = dec ? dec->nF : 0;
   S.nU = dec ? dec->nU : 0;
@@ -540,7 +539,30 @@ __global__ void outer_init_kernel(OuterState* st, const SolveDecision* dec) {
   S.lam_skip = 1;
   S.last_ib = -1;
   S.last_imin = -1;
-  *st = S;
+  return S;
+}
+
+__global__ void outer_init_kernel(OuterState* st, const SolveDecision* dec) {
+  if (threadIdx.x != 0) return;
+  *st = fresh_outer_state(dec);
+}
+
+// per blocks of 256 threads per request
+__global__ __launch_bounds__(256) void request_init_batch_kernel(const ReqInitItem* __restrict__ items, int per) {
+  const int r = blockIdx.x / per, b = blockIdx.x - r * per;
+  const ReqInitItem it = items[r];
+  const int t = b * 256 + threadIdx.x, nt = per * 256;
+  for (int e = t; e < it.Q; e += nt) {
+    it.sigma[e] = 0.f;
+    it.state[e] = 0;
+  }
+  for (int e = t; e < it.P * it.P; e += nt) {
+    float2 v = it.R[e];
+    const int p = e / it.P, q = e - p * it.P;
+    if (it.noise && p == q) v.x -= it.noise[p];
+    it.B0[e] = v;
+  }
+  if (t == 0) *it.st = fresh_outer_state(nullptr);
 }
 
 // ---- PWLS set-up (eq. preWLS, eq. D at K = 1) ----
@@ -617,6 +639,12 @@ hipError_t launch_pwls_scale(float* x, const float* s, int n, bool divide, hipSt
 }
 
 bool outer_fits(int P) { return pad_p(P) / 8 <= 6; }
+
+hipError_t launch_request_init_batch(const ReqInitItem* items, int nreq, int Qmax, hipStream_t s) {
+  const int per = std::max(1, std::min(16, (Qmax + 1023) / 1024));
+  hipLaunchKernelGGL(request_init_batch_kernel, dim3(nreq * per), dim3(256), 0, s, items, per);
+  return hipGetLastError();
+}
 
 hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s) {
   hipLaunchKernelGGL(outer_init_kernel, dim3(1), dim3(64), 0, s, st, dec);

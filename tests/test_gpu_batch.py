@@ -6,6 +6,8 @@ channels or separate observations would; the batch shares the GPU between
 them (one outer-step workgroup per request, one multiplier launch for all).
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -34,6 +36,15 @@ def _opts(gpu_lib, sc, cost=0):
 
 
 def _scenes(kind):
+    if kind == "p48same":
+        # one array and grid (snapshots of one observation): the batch reads the
+        # steering tables in place; each request has its own covariance
+        base = synth.make_scene("c1", seed=200, n=64)
+        R = synth.scenes.exact_covariance(base.pos, base.lam, base.grid, base.src_pix, base.src_pow,
+                                          base.noise_var)
+        return [dataclasses.replace(base, R_hat=synth.scenes._sample_covariance(np.random.default_rng(300 + i), R,
+                                                                                base.N))
+                for i in range(4)]
     if kind == "p24":
         return [synth.make_scene("c0", seed=100 + i, lam=lam, n=n)
                 for i, (lam, n) in enumerate([(1.0, 32), (1.3, 24), (1.7, 40), (1.15, 32), (1.9, 16)])]
@@ -42,7 +53,7 @@ def _scenes(kind):
 
 
 @pytest.mark.parametrize("cost", [0, 1])
-@pytest.mark.parametrize("kind", ["p24", "p48"])
+@pytest.mark.parametrize("kind", ["p24", "p48", "p48same"])
 def test_each_request_in_a_batch_equals_its_solve_alone(gpu_lib, kind, cost):
     scenes = _scenes(kind)
     print(f"case batch of {len(scenes)} ({kind}, cost {cost})", flush=True)

@@ -133,12 +133,57 @@ struct BeamLambda {
       }
     }
   }
+  // The register beamformer loads the state (and scale) of a tile's pixel
+  // together with the tile's table entries, one tile ahead, so the epilogue
+  // does not wait for them: prefetch(pix) for the next tile, begin_tile()
+  // when it becomes current, then apply() in place of operator().
+  uint8_t s_next, s_cur;
+  float sc_next, sc_cur;
+  __device__ void prefetch(int pix) {
+    s_next = ld_global(state + pix);
+    sc_next = scale ? ld_global(scale + pix) : 1.f;
+  }
+  __device__ void begin_tile() {
+    s_cur = s_next;
+    sc_cur = sc_next;
+  }
+  __device__ void apply(int pix, float g, bool ok) {
+    if (ok && s_cur != 1) {  // not free
+      if (scale) g *= sc_cur;
+      const float lam = (s_cur == 0) ? g : -g;  // L : U
+      const uint64_t key = ((uint64_t)ordered_bits(lam) << 32) | (uint32_t)pix;
+      best = key < best ? key : best;
+    }
+  }
   __device__ void finish(int blk) {
     __shared__ uint64_t sh[kBeamWaves];
     const uint64_t m = block_min_u64(best, sh);
     if (threadIdx.x == 0) part[blk] = m;
   }
 };
+
+// Epilogues with per-pixel inputs load them one tile ahead (prefetch /
+// begin_tile / apply); the others take the value at once.
+template <class E>
+__device__ __forceinline__ auto epi_prefetch(E& e, int pix, int) -> decltype(e.prefetch(pix), void()) {
+  e.prefetch(pix);
+}
+template <class E>
+__device__ __forceinline__ void epi_prefetch(E&, int, long) {}
+template <class E>
+__device__ __forceinline__ auto epi_begin(E& e, int) -> decltype(e.begin_tile(), void()) {
+  e.begin_tile();
+}
+template <class E>
+__device__ __forceinline__ void epi_begin(E&, long) {}
+template <class E>
+__device__ __forceinline__ auto epi_apply(E& e, int pix, float g, bool ok, int) -> decltype(e.apply(pix, g, ok), void()) {
+  e.apply(pix, g, ok);
+}
+template <class E>
+__device__ __forceinline__ void epi_apply(E& e, int pix, float g, bool ok, long) {
+  e(pix, g, ok);
+}
 
 // Fragments built from U by the whole workgroup: the (m, j) pairs of chunks
 // 2j, 2j + 1 of row tile m (same values as beam_prep_kernel) are dealt round
@@ -169,8 +214,8 @@ __device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, 
     // clamped (valid) indices, padding masked afterwards: no branch around a
     // load, so all of them are in flight together
     const int p = min(8 * m + pr0, P - 1), p2 = min(4 * jj[i] + q, P - 1);
-    xv[i] = U[p * P + p2];
-    yv[i] = U[p2 * P + p];
+    xv[i] = ld_global(U + p * P + p2);
+    yv[i] = ld_global(U + p2 * P + p);
   }
 #pragma unroll
   for (int i = 0; i < PPW; ++i) {
@@ -202,7 +247,7 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
                                           const Tables& tab, const int* skip, Epi& epi, int blk, int nblk) {
   constexpr int KS = 4 * MT;             // 4-row chunks of the embedding
   constexpr int NFR = 2 * MT * (MT + 1);  // fragments of the lower block triangle
-  if (skip && *skip) return;
+  if (skip && ld_global(skip)) return;
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
   const int Q = tab.Q, nl = tab.nl, nm = tab.nm;
   const int ntiles = (Q + 15) >> 4;
@@ -219,8 +264,8 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
     const float2* em = tab.Em + (size_t)q * nm + im;
 #pragma unroll
     for (int j = 0; j < KS / 2; ++j) {
-      te[j] = el[(size_t)4 * j * nl];
-      tm[j] = em[(size_t)4 * j * nm];
+      te[j] = ld_global(el + (size_t)4 * j * nl);
+      tm[j] = ld_global(em + (size_t)4 * j * nm);
     }
   };
   // workgroups are dealt round robin to the 8 XCDs: give each XCD a
@@ -236,10 +281,14 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
 #pragma unroll
     for (int f = 0; f < NFR; ++f) fa[f] = frag[f * 64 + lane];
   }
-  if (tile < ntiles) load_tables(tile);
+  if (tile < ntiles) {
+    load_tables(tile);
+    epi_prefetch(epi, min(16 * tile + c16, Q - 1), 0);
+  }
   epi.init();
   for (; tile < ntiles; tile += nwav) {
     const int pix = 16 * tile + c16;
+    epi_begin(epi, 0);
     float b[KS];
 #pragma unroll
     for (int j = 0; j < KS / 2; ++j) {
@@ -247,7 +296,10 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
       b[2 * j] = a.x;
       b[2 * j + 1] = a.y;
     }
-    if (tile + nwav < ntiles) load_tables(tile + nwav);
+    if (tile + nwav < ntiles) {
+      load_tables(tile + nwav);
+      epi_prefetch(epi, min(16 * (tile + nwav) + c16, Q - 1), 0);
+    }
     v4f acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -264,7 +316,7 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
     }
     g += __shfl_xor(g, 16, 64);
     g += __shfl_xor(g, 32, 64);
-    epi(pix, g, pix < Q && q == 0);
+    epi_apply(epi, pix, g, pix < Q && q == 0, 0);
   }
   epi.finish(blk);
 }

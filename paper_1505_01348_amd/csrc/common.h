@@ -41,6 +41,21 @@ __device__ __forceinline__ v4f mfma16x16x4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Loads through the global address space.  A pointer read from memory (an
+// item of a batched launch) is otherwise accessed with flat instructions,
+// which also count against the LDS wait counter, so every LDS or cross-lane
+// wait would wait for them too.
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_global(const float2* p) {
+  const v2f v = *(const __attribute__((address_space(1))) v2f*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float ld_global(const float* p) { return *(const __attribute__((address_space(1))) float*)p; }
+__device__ __forceinline__ int ld_global(const int* p) { return *(const __attribute__((address_space(1))) int*)p; }
+__device__ __forceinline__ uint8_t ld_global(const uint8_t* p) {
+  return *(const __attribute__((address_space(1))) uint8_t*)p;
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -78,6 +78,41 @@ def test_each_request_in_a_batch_equals_its_solve_alone(gpu_lib, kind, cost):
         ctx.close()
 
 
+@pytest.mark.parametrize("variant", ["mvdr_kappa_b", "mvdr_no_noise", "mf_bound", "no_bound"])
+def test_batch_bound_variants_equal_their_solves_alone(gpu_lib, variant):
+    # the MVDR bound of the least-squares cost takes the batched set-up (with
+    # the bound's inflation term, with and without a noise model); the MF
+    # bound and no bound keep the per-request set-up
+    scenes = _scenes("p24")[:3]
+    print(f"case batch bound variant {variant}", flush=True)
+    opts = _opts(gpu_lib, scenes[0])
+    if variant == "mvdr_kappa_b":
+        opts.kappa_b = 3.0
+    elif variant == "mf_bound":
+        opts.bound, opts.kappa_b = gpu_lib.BOUND_MF, 2.0
+    elif variant == "no_bound":
+        opts.bound = gpu_lib.BOUND_NONE
+    reqs = [_req(gpu_lib, sc) for sc in scenes]
+    if variant == "mvdr_no_noise":
+        for r in reqs:
+            r["noise_diag"] = None
+    ctx = gpu_lib.Context(0)
+    try:
+        st, res = ctx.solve_batch(reqs, opts)
+        torch.cuda.synchronize()
+        assert st >= 0, st
+        for i, r in enumerate(reqs):
+            sigma, state, mf, gamma, stats = ctx.solve(r["R"], r["geo"], opts, noise_diag=r["noise_diag"])
+            bs, bst, bmf, bg, bstats = res[i]
+            print(f"request {i}: alone {stats['adds']} adds, batch {bstats['adds']} adds", flush=True)
+            assert torch.equal(mf, bmf) and torch.equal(gamma, bg)
+            assert torch.equal(state, bst) and torch.equal(sigma, bs)
+            for k in ("status", "outer_iters", "adds", "drops", "lsqr_iters_total", "nF", "nU"):
+                assert stats[k] == bstats[k], (i, k)
+    finally:
+        ctx.close()
+
+
 def test_batch_matches_the_oracle(gpu_lib):
     scenes = _scenes("p24")[:3]
     print("case batch of 3 against the oracle", flush=True)

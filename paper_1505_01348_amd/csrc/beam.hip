@@ -193,8 +193,9 @@ __device__ __forceinline__ void epi_apply(E& e, int pix, float g, bool ok, long)
 // components of the same Hermitian-part entry.  In LDS fragment f of lane l
 // sits at (f >> 2) * 256 + 4 l + (f & 3): a pair is one 8-byte store and each
 // lane reads its fragments four at a time with 16-byte loads.
-template <int MT>
-__device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, int P, float* sfr, float* fa) {
+template <int MT, class Issue>
+__device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, int P, float* sfr, float* fa,
+                                                  Issue&& issue_next) {
   constexpr int NPAIR = MT * (MT + 1);
   constexpr int NFR = 2 * NPAIR;
   constexpr int PPW = (NPAIR + kBeamWaves - 1) / kBeamWaves;
@@ -217,6 +218,9 @@ __device__ __forceinline__ void beam_frags_from_u(const float2* __restrict__ U, 
     xv[i] = ld_global(U + p * P + p2);
     yv[i] = ld_global(U + p2 * P + p);
   }
+  // the caller's next loads go out behind these (loads complete in order, so
+  // waiting for the U entries does not wait for them)
+  issue_next();
 #pragma unroll
   for (int i = 0; i < PPW; ++i) {
     if (w + kBeamWaves * i < NPAIR) {
@@ -254,8 +258,8 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
   const int nwav = nblk * kBeamWaves;
   // table entries of antennas 4 j + q for this lane's pixel of a tile; the
   // loads of the next tile are issued before the current one is multiplied.
-  // The first tile's loads follow the fragment loads (the fragments are built
-  // first, and loads complete in order).
+  // The first tile's loads go out right behind the loads of U, so their
+  // latency overlaps the fragment build.
   float2 te[KS / 2], tm[KS / 2];
   auto load_tables = [&](int tile) {
     const int pix = min(16 * tile + c16, Q - 1);
@@ -273,17 +277,20 @@ __device__ __forceinline__ void beam_body(const float* __restrict__ frag, const 
   // rows' part of the m table rather than every XCD fetching all of it
   if (nblk % 8 == 0) blk = (blk % 8) * (nblk / 8) + blk / 8;
   int tile = blk * kBeamWaves + (threadIdx.x >> 6);
+  auto first_loads = [&]() {
+    if (tile < ntiles) {
+      load_tables(tile);
+      epi_prefetch(epi, min(16 * tile + c16, Q - 1), 0);
+    }
+  };
   float fa[NFR];
   if (U) {
     __shared__ __align__(16) float sfr[NFR * 64];
-    beam_frags_from_u<MT>(U, P, sfr, fa);
+    beam_frags_from_u<MT>(U, P, sfr, fa, first_loads);
   } else {
 #pragma unroll
     for (int f = 0; f < NFR; ++f) fa[f] = frag[f * 64 + lane];
-  }
-  if (tile < ntiles) {
-    load_tables(tile);
-    epi_prefetch(epi, min(16 * tile + c16, Q - 1), 0);
+    first_loads();
   }
   epi.init();
   for (; tile < ntiles; tile += nwav) {

@@ -243,7 +243,11 @@ typedef struct {
  * Lagrange multipliers of all requests in another, so the requests share the
  * GPU instead of queueing; each request's result is identical to what
  * clsimg_solve returns for it alone.  Each request may have its own array,
- * wavelength and grid.  Returns CLSIMG_OK when every request ended with
+ * wavelength and grid.  With the least-squares cost and the MVDR bound in
+ * FP32, the set-up of all requests (R^-1, steering tables, initial state,
+ * dirty images and bounds) also runs as a few batched launches.  When every
+ * request has the same array and grid, they all read one copy of the
+ * steering tables.  Returns CLSIMG_OK when every request ended with
  * CLSIMG_OK, its first negative code if a request failed, CLSIMG_ENOTSUP if a
  * free set outgrew one workgroup (no host fallback in a batch), else the
  * largest warning code; per-request codes are in reqs[i].stats.status.

@@ -27,7 +27,9 @@ Pins (what the oracle is checked against, in tests/test_oracle_*.py): the
 Kronecker/Khatri-Rao identities of the Notation section against an explicitly
 built dense Psi, closed forms for a single source (MF and Sherman-Morrison
 MVDR), the MF >= MVDR ordering, the Jacobi-preconditioned-WLS identity for the
-MVDR image (Sec. II-C), LSQR against SVD minimum-norm least squares,
+MVDR image (Sec. II-C), the bounds' kappa_b terms and the detection threshold
+against the Monte Carlo spread of the MF and MVDR images over sample
+covariances (App. A, K = 1), LSQR against SVD minimum-norm least squares,
 the active-set solution against SciPy's BVLS and brute-force enumeration
 (objective and KKT conditions, eqs. gradFcond/etaL/etaU), exact recovery of
 on-grid sources from an exact covariance, and invariances (scale, antenna

@@ -64,6 +64,17 @@ def test_identical_blocks_equal_the_single_block_problem():
         assert np.allclose(res.sigma, ref.sigma, rtol=1e-8, atol=1e-10 * np.abs(ref.sigma).max())
         assert abs(res.rel_residual - ref.rel_residual) <= 1e-9
     assert ref.adds >= 2 and np.any(ref.state == oracle.STATE_L)
+    # App. A with kappa_b > 0: K independent sample covariances of the same R
+    # average to an image whose standard deviation is 1/sqrt(K) of one block's,
+    # so the K-block bound (pinned by Monte Carlo below) equals the
+    # single-block bound with kappa_b / sqrt(K); K = 1 is the same problem.
+    N, C = 300, 300 / (300 - P)
+    for K in (1, 2, 3):
+        As, Rs = [A] * K, [R] * K
+        for kind, c in (("mvdr", C), ("mvdr", 1.0), ("mf", 1.0)):
+            np.testing.assert_allclose(
+                oracle.upper_bound_multi(As, Rs, kind, C=c, kappa_b=6.0, nsamples=N),
+                oracle.upper_bound(A, R, kind, C=c, kappa_b=6.0 / math.sqrt(K), nsamples=N), rtol=1e-12)
 
 
 def _dense_stacked(As, B0s):

@@ -199,6 +199,43 @@ def test_bound_options():
     np.testing.assert_allclose(oracle.detection_threshold(mf, 6.0, N), 6.0 * mf / math.sqrt(N))
 
 
+def test_single_block_bound_terms_are_app_a_std_by_monte_carlo():
+    # App. A at K = 1: the kappa_b term of each bound is one standard deviation
+    # of the image it inflates, per unit of kappa_b, and the detection
+    # threshold is kappa_d of the MF image's.  Reference: the spread of the
+    # images over many independent sample covariances of one R (complex
+    # Gaussian samples, N R_hat complex Wishart).  A small N (13 samples, 4
+    # antennas) makes the MVDR degrees of freedom visible: the first-order
+    # std 1/(h sqrt(N-P-1)) is within 0.7 % of the exact one, a neighbouring
+    # count (N-P, N-P+1) is 5-13 % off.
+    rng = np.random.default_rng(14)
+    P, N, trials = 4, 13, 60000
+    pos, lam, grid = _small_geometry(rng, P=P, n=3, radius=1.5)
+    A = oracle.steering(pos, lam, grid)
+    R = random_hermitian(rng, P, pd=True)
+    Lr = np.linalg.cholesky(R)
+    W = (rng.standard_normal((trials, P, N)) + 1j * rng.standard_normal((trials, P, N))) / math.sqrt(2)
+    Y = Lr[None] @ W
+    Rh = Y @ np.conj(np.swapaxes(Y, 1, 2)) / N
+    quad = lambda M: np.real(np.einsum("pi,tpq,qi->ti", A.conj(), M, A))  # noqa: E731
+    mf_mc = quad(Rh)
+    C = N / (N - P)  # the unbiased MVDR image (Sec. II-D)
+    mv_mc = C / quad(np.linalg.inv(Rh))
+    # MVDR: increment of the bound at kappa_b = 1 over the bound itself
+    d_mv = (oracle.upper_bound(A, R, "mvdr", C=C, kappa_b=1.0, nsamples=N)
+            - oracle.upper_bound(A, R, "mvdr", C=C))
+    np.testing.assert_allclose(mv_mc.std(axis=0), d_mv, rtol=0.025)
+    # MF: exact, N mf_hat / mf is Gamma(N) distributed
+    d_mf = (oracle.upper_bound(A, R, "mf", kappa_b=1.0, nsamples=N) - oracle.upper_bound(A, R, "mf"))
+    np.testing.assert_allclose(mf_mc.std(axis=0), d_mf, rtol=0.025)
+    np.testing.assert_allclose(mf_mc.std(axis=0), oracle.detection_threshold(oracle.mf_image(A, R), 1.0, N),
+                               rtol=0.025)
+    # kappa_b scales the increment linearly
+    d_mv3 = (oracle.upper_bound(A, R, "mvdr", C=C, kappa_b=3.0, nsamples=N)
+             - oracle.upper_bound(A, R, "mvdr", C=C))
+    np.testing.assert_allclose(d_mv3, 3.0 * mv_mc.std(axis=0), rtol=0.025)
+
+
 def test_inverse_wishart_bias_constant_monte_carlo():
     # App. A: E{R_hat^-1} = N/(N-P) R^-1, the origin of the constant C.
     rng = np.random.default_rng(12)

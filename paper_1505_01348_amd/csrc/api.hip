@@ -245,7 +245,7 @@ int ensure_workspace(clsimg_ctx* c, int P, int Q) {
   ST_TRY(ensure(c, c->u, cx));
   ST_TRY(ensure(c, c->E, cx));
   ST_TRY(ensure(c, c->Rinv, cx));
-  ST_TRY(ensure(c, c->W, (size_t)P * P * sizeof(double2)));
+  ST_TRY(ensure(c, c->W, (size_t)2 * P * P * sizeof(double2)));  // L and its transpose (Cholesky beyond 64)
   ST_TRY(ensure(c, c->Li, (size_t)P * P * sizeof(double2)));
   ST_TRY(ensure(c, c->lsqr, sizeof(LsqrState)));
   ST_TRY(ensure(c, c->dec, sizeof(SolveDecision)));
@@ -1013,6 +1013,15 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
     a.xf = xf;
     return a;
   };
+  // the LSQR adjoint of the split-K engine: for large arrays its rows are split
+  // over workgroups, with the correlation's partial buffer (free by then) as
+  // the workspace of the row groups' dots
+  auto lsqr_adj_rows = [&](const int* stop) {
+    AdjParams a = adj_params(c, g, P, frag_u, Flist, nF, stop);
+    a.rows_part = P_<float>(c->part);
+    a.rows_cap = c->part.bytes / sizeof(float);
+    return a;
+  };
 
   const int max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
   int status = CLSIMG_OK;
@@ -1231,8 +1240,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
         } else {
           ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, u, bsub, 0.f, 1.f, nullptr, frag_u, beta_part,
                            nullptr, st));
-          HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, nullptr), v, beta_part,
-                                      nbeta, alpha_part, 1, st));
+          HIP_TRY(launch_adjoint_lsqr(lsqr_adj_rows(nullptr), v, beta_part, nbeta, alpha_part, 1, st));
           HIP_TRY(launch_lsqr_init_scalars(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF,
                                            o->atol, o->btol, o->conlim, itnlim, st));
         }
@@ -1250,8 +1258,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
             } else {
               ST_TRY(correlate(c, g, P, Flist, v, 0, nF, u, u, 1.f, 0.f, ls, frag_u, beta_part,
                                lsqr_stop, st));
-              HIP_TRY(launch_adjoint_lsqr(adj_params(c, g, P, frag_u, Flist, nF, lsqr_stop), v,
-                                          beta_part, nbeta, alpha_part, 0, st));
+              HIP_TRY(launch_adjoint_lsqr(lsqr_adj_rows(lsqr_stop), v, beta_part, nbeta, alpha_part, 0, st));
               HIP_TRY(launch_lsqr_update(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF, st));
             }
           }

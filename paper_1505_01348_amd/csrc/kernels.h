@@ -32,6 +32,11 @@ struct AdjParams {
   // 1: one block per workgroup (blockIdx.y = block), for epilogues that keep
   // the blocks apart; 0: every workgroup adds the column dots of all blocks
   int blk_grid = 0;
+  // optional workspace (rows_cap floats) for the row-split beamformer of large
+  // arrays (LSQR adjoint beyond 12 row tiles, fragment input): one partial
+  // column dot per group of four row tiles and listed pixel
+  float* rows_part = nullptr;
+  size_t rows_cap = 0;
 };
 
 struct FwdParams {

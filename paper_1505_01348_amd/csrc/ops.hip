@@ -230,6 +230,122 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
 }
 
 // ---------------------------------------------------------------------------
+// Beamforming of a pixel list for arrays beyond 12 row tiles, rows split over
+// workgroups.  Workgroup (x, y) takes NT 16-pixel tiles of the list and the
+// row tiles 4y .. 4y + 3 of Ut (one per wave, fragments prepared by the
+// correlation), runs the whole K loop with the next chunk's fragment and
+// table loads issued before the current chunk's MFMA, and leaves the partial
+// column dot of its rows in part[y * n + k].  adjoint_rows_finish_kernel adds
+// the row groups in order and applies the epilogue.  Embedding as in the
+// reduction's fragments: real row 2p + s is component s of antenna p.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, float* __restrict__ part) {
+  if (pr.stop_flag && *pr.stop_flag) return;
+  __shared__ float gs[4][NT * 16];
+  const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
+  const int MT = pr.MT, KS = pr.KS, n = pr.n;
+  const int mt = 4 * blockIdx.y + w;
+  const bool live_row = mt < MT;
+  const int mtc = live_row ? mt : MT - 1;  // loads stay in bounds; the dot leaves it out
+  const Tables tab = pr.tab;
+  int il[NT], im[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = 16 * (blockIdx.x * NT + t) + c16;
+    int pix = col < n ? (pr.idx ? pr.idx[col] : col) : 0;
+    if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;
+    im[t] = pix / tab.nl;
+    il[t] = pix - im[t] * tab.nl;
+  }
+  // B operand of chunk kc: real row 4kc + q = component q & 1 of antenna 2kc + (q >> 1)
+  const float2* elp[NT];
+  const float2* emp[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    elp[t] = tab.El + (size_t)(q >> 1) * tab.nl + il[t];
+    emp[t] = tab.Em + (size_t)(q >> 1) * tab.nm + im[t];
+  }
+  const size_t sl = (size_t)2 * tab.nl, sm = (size_t)2 * tab.nm;  // two antennas per chunk
+  const float* fw = pr.frag + (size_t)mtc * KS * 64 + lane;
+  v4f acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  float fa = fw[0];
+  float2 te[NT], tm[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    te[t] = elp[t][0];
+    tm[t] = emp[t][0];
+  }
+  for (int kc = 0; kc < KS; ++kc) {
+    const float a = fa;
+    float b[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float2 x = cmul(te[t], tm[t]);
+      b[t] = (q & 1) ? x.y : x.x;
+    }
+    const int kn = kc + 1 < KS ? kc + 1 : kc;
+    fa = fw[(size_t)kn * 64];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      te[t] = elp[t][kn * sl];
+      tm[t] = emp[t][kn * sm];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(a, b[t], acc[t]);
+  }
+  // accumulator element r of lane (c16, q): real row 16mt + 4q + r, i.e.
+  // antenna 8mt + 2q + (r >> 1), component r & 1
+  float gp[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    gp[t] = 0.f;
+    if (live_row) {
+      const float2 a0 = tab.a(8 * mt + 2 * q, il[t], im[t]);
+      const float2 a1 = tab.a(8 * mt + 2 * q + 1, il[t], im[t]);
+      gp[t] = acc[t][0] * a0.x + acc[t][1] * a0.y + acc[t][2] * a1.x + acc[t][3] * a1.y;
+    }
+    gp[t] += __shfl_xor(gp[t], 16, 64);
+    gp[t] += __shfl_xor(gp[t], 32, 64);
+  }
+  if (q == 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) gs[w][16 * t + c16] = gp[t];
+  }
+  __syncthreads();
+  if (threadIdx.x < NT * 16) {
+    const int col = 16 * blockIdx.x * NT + threadIdx.x;
+    const float g = (gs[0][threadIdx.x] + gs[1][threadIdx.x]) + (gs[2][threadIdx.x] + gs[3][threadIdx.x]);
+    if (col < n) part[(size_t)blockIdx.y * n + col] = g;
+  }
+}
+
+// The row groups' partial dots added in group order, then the epilogue on
+// tiles of T <= 64 listed pixels (the tiles of adjoint_kernel), one wave each.
+template <class Epi>
+__global__ __launch_bounds__(64) void adjoint_rows_finish_kernel(AdjParams pr, const float* __restrict__ part,
+                                                                 int ngroups, int T, Epi epi) {
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
+  const typename Epi::Ctx cx = epi.init();
+  if (stop) return;
+  const int tile = blockIdx.x, col = tile * T + threadIdx.x;
+  const bool ok = (int)threadIdx.x < T && col < pr.n;
+  float g = 0.f;
+  int pix = 0;
+  if (ok) {
+    for (int y = 0; y < ngroups; ++y) g += part[(size_t)y * pr.n + col];
+    pix = pr.idx ? pr.idx[col] : col;
+    if ((unsigned)pix >= (unsigned)pr.tab.Q) {  // invalid pixel index: NaN output
+      pix = 0;
+      g = __builtin_nanf("");
+    }
+  }
+  const typename Epi::Pre pf = epi.prefetch(col, ok);
+  epi(tile, col, pix, g, ok, cx, pf);
+}
+
+// ---------------------------------------------------------------------------
 // Beamforming of a free list for 7..12 row tiles (LSQR adjoint): one 16-pixel
 // tile per workgroup; wave w takes row tiles w, w + 4, w + 8 over the whole K
 // and issues every fragment load (Ut fragments prepared by the correlation)
@@ -604,14 +720,31 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_kernel(RedParams pr) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 Cholesky R = L L^H (lower triangle of R is read), then
-// R^-1 = L^-H L^-1 written as complex64.  One workgroup.  status: 0 ok,
-// 1 not positive definite, 2 non-finite entry.
-__global__ __launch_bounds__(1024) void chol_inverse_kernel(const float2* __restrict__ R, int P,
-                                                            double2* __restrict__ W,
-                                                            double2* __restrict__ Li,
-                                                            float2* __restrict__ Rinv,
-                                                            int* __restrict__ status) {
+// FP64 Cholesky R = L L^H for arrays beyond the LDS-resident kernel below,
+// in two launches.
+//
+// chol_factor_kernel (one workgroup): blocked right-looking factorisation of
+// W (row-major, the lower triangle is read and overwritten by L), panels of
+// kCholNB columns.  A panel's rows are copied into LDS, factored there (one
+// column at a time: pivot, scale, update of the panel's later columns), and
+// written back; the trailing lower triangle then takes the panel's rank-nb
+// update with one global read and write per element.  The factor is also
+// stored transposed (LT[k][i] = L[i][k]) so that columns of L are contiguous
+// for the forward substitution.  status: 0 ok, 1 not positive definite,
+// 2 non-finite entry.
+//
+// chol_solve_kernel (one workgroup per column c of the identity): forward
+// substitution L y = e_c (y = column c of L^-1, stored when Li is given), then
+// backward substitution L^H x = y (x = column c of R^-1, rounded to complex64).
+// Each step reads one row of LT or of L, loaded one step ahead.
+constexpr int kCholNB = 16;
+constexpr int kCholMaxRows = 288;  // the largest array (CLSIMG_MAX_P)
+
+__global__ __launch_bounds__(1024) void chol_factor_kernel(const float2* __restrict__ R, int P,
+                                                           double2* __restrict__ W, double2* __restrict__ LT,
+                                                           int* __restrict__ status) {
+  constexpr int LDP = kCholNB + 1;  // padded panel rows
+  __shared__ double2 pan[kCholMaxRows * LDP];
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) bad = 0;
@@ -626,65 +759,174 @@ __global__ __launch_bounds__(1024) void chol_inverse_kernel(const float2* __rest
     if (tid == 0) *status = bad;
     return;
   }
-  for (int j = 0; j < P; ++j) {
-    if (tid == 0) {
-      const double d = W[j * P + j].x;
-      if (!(d > 0.0)) bad = 1;
-      else W[j * P + j] = make_double2(sqrt(d), 0.0);
+  for (int j0 = 0; j0 < P; j0 += kCholNB) {
+    const int nb = min(kCholNB, P - j0), rows = P - j0;
+    for (int e = tid; e < rows * nb; e += nt) {
+      const int r = e / nb, c = e - r * nb;
+      pan[r * LDP + c] = W[(size_t)(j0 + r) * P + j0 + c];
     }
     __syncthreads();
-    if (bad) {
-      if (tid == 0) *status = 1;
-      return;
+    for (int c = 0; c < nb; ++c) {
+      const double d = pan[c * LDP + c].x;  // the same value in every thread: the exit is uniform
+      if (!(d > 0.0)) {
+        if (tid == 0) *status = 1;
+        return;
+      }
+      const double ljj = sqrt(d);
+      for (int r = c + 1 + tid; r < rows; r += nt) {
+        const double2 v = pan[r * LDP + c];
+        pan[r * LDP + c] = make_double2(v.x / ljj, v.y / ljj);
+      }
+      __syncthreads();
+      if (tid == 0) pan[c * LDP + c] = make_double2(ljj, 0.0);
+      // later columns of the panel: pan[r][c2] -= pan[r][c] conj(pan[c2][c]), r >= c2 > c
+      const int w = nb - c - 1;
+      for (int e = tid; e < rows * w; e += nt) {
+        const int r = e / w, c2 = c + 1 + e - (e / w) * w;
+        if (r >= c2) {
+          const double2 a = pan[r * LDP + c], b = pan[c2 * LDP + c];
+          double2 x = pan[r * LDP + c2];
+          x.x -= a.x * b.x + a.y * b.y;
+          x.y -= a.y * b.x - a.x * b.y;
+          pan[r * LDP + c2] = x;
+        }
+      }
+      __syncthreads();
     }
-    const double ljj = W[j * P + j].x;
-    for (int i = j + 1 + tid; i < P; i += nt) {
-      const double2 v = W[i * P + j];
-      W[i * P + j] = make_double2(v.x / ljj, v.y / ljj);
-    }
-    __syncthreads();
-    const int m = P - j - 1;
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) {
-        const double2 a = W[i * P + j], b = W[k * P + j];
-        // W[i][k] -= a * conj(b)
-        double2 w = W[i * P + k];
-        w.x -= a.x * b.x + a.y * b.y;
-        w.y -= a.y * b.x - a.x * b.y;
-        W[i * P + k] = w;
+    // the panel's columns of L, in W and transposed in LT
+    for (int e = tid; e < rows * nb; e += nt) {
+      const int r = e / nb, c = e - r * nb;
+      if (r >= c) {
+        const double2 v = pan[r * LDP + c];
+        W[(size_t)(j0 + r) * P + j0 + c] = v;
+        LT[(size_t)(j0 + c) * P + j0 + r] = v;
       }
     }
-    __syncthreads();
-  }
-  // Li = L^-1 by forward substitution, one column per thread
-  for (int c = tid; c < P; c += nt) {
-    for (int i = 0; i < c; ++i) Li[i * P + c] = make_double2(0.0, 0.0);
-    Li[c * P + c] = make_double2(1.0 / W[c * P + c].x, 0.0);
-    for (int i = c + 1; i < P; ++i) {
-      double sr = 0.0, si = 0.0;
-      for (int k = c; k < i; ++k) {
-        const double2 l = W[i * P + k], y = Li[k * P + c];
-        sr += l.x * y.x - l.y * y.y;
-        si += l.x * y.y + l.y * y.x;
+    // trailing update W[i][k] -= sum_c L[i][c] conj(L[k][c]), j0 + nb <= k <= i;
+    // threads as 32 x 32 (row phase, column phase): consecutive threads take
+    // consecutive k of one row (coalesced), each thread four elements at a time
+    const int t0 = j0 + nb, m = P - t0;
+    const int ty = tid >> 5, tx = tid & 31;
+    for (int i = t0 + ty; i < P; i += 32) {
+      const int ri = i - j0;
+      for (int k0 = t0 + tx; k0 <= i; k0 += 128) {
+        double2 acc[4];
+        double2 wv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 32 * u;
+          wv[u] = k <= i ? W[(size_t)i * P + k] : make_double2(0.0, 0.0);
+          acc[u] = make_double2(0.0, 0.0);
+        }
+#pragma unroll 4
+        for (int c = 0; c < nb; ++c) {
+          const double2 a = pan[ri * LDP + c];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = min(k0 + 32 * u, P - 1);
+            const double2 b = pan[(k - j0) * LDP + c];
+            acc[u].x += a.x * b.x + a.y * b.y;
+            acc[u].y += a.y * b.x - a.x * b.y;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 32 * u;
+          if (k <= i) W[(size_t)i * P + k] = make_double2(wv[u].x - acc[u].x, wv[u].y - acc[u].y);
+        }
       }
-      const double lii = W[i * P + i].x;
-      Li[i * P + c] = make_double2(-sr / lii, -si / lii);
     }
-  }
-  __syncthreads();
-  // R^-1[i][k] = sum_{m >= max(i,k)} conj(Li[m][i]) Li[m][k]
-  for (int e = tid; e < P * P; e += nt) {
-    const int i = e / P, k = e % P;
-    double sr = 0.0, si = 0.0;
-    for (int m = (i > k ? i : k); m < P; ++m) {
-      const double2 a = Li[m * P + i], b = Li[m * P + k];
-      sr += a.x * b.x + a.y * b.y;
-      si += a.x * b.y - a.y * b.x;
-    }
-    Rinv[e] = make_float2((float)sr, (float)si);
+    (void)m;
+    __syncthreads();
   }
   if (tid == 0) *status = 0;
+}
+
+__global__ __launch_bounds__(256) void chol_solve_kernel(const double2* __restrict__ L, const double2* __restrict__ LT,
+                                                         int P, const int* __restrict__ status,
+                                                         double2* __restrict__ Li, float2* __restrict__ Rinv) {
+  __shared__ double2 y[kCholMaxRows];
+  if (*status != 0) return;
+  const int c = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < P; i += nt) y[i] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  // forward: for k = c .. P-1: y_k /= L_kk; y_i -= L_ik y_k (i > k), column k of L = row k of LT
+  double2 nxt[2];
+  double npiv = LT[(size_t)c * P + c].x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = c + tid + h * nt;
+    nxt[h] = i < P ? LT[(size_t)c * P + i] : make_double2(0.0, 0.0);
+  }
+  for (int k = c; k < P; ++k) {
+    // thread (tid, h) holds L[k + tid + h nt][k]
+    double2 col[2] = {nxt[0], nxt[1]};
+    const double lkk = npiv;
+    if (k + 1 < P) {
+      npiv = LT[(size_t)(k + 1) * P + k + 1].x;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = k + 1 + tid + h * nt;
+        nxt[h] = i < P ? LT[(size_t)(k + 1) * P + i] : make_double2(0.0, 0.0);
+      }
+    }
+    const double2 yk0 = y[k];
+    const double2 yk = make_double2(yk0.x / lkk, yk0.y / lkk);
+    __syncthreads();  // every thread has read y[k]
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = k + tid + h * nt;
+      if (i == k) {
+        y[k] = yk;
+      } else if (i < P) {
+        const double2 l = col[h];
+        double2 v = y[i];
+        v.x -= l.x * yk.x - l.y * yk.y;
+        v.y -= l.x * yk.y + l.y * yk.x;
+        y[i] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (Li)
+    for (int i = tid; i < P; i += nt) Li[(size_t)i * P + c] = y[i];
+  // backward: for k = P-1 .. 0: x_k = y_k / L_kk; y_i -= conj(L_ki) x_k (i < k), row k of L
+  npiv = L[(size_t)(P - 1) * P + P - 1].x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = tid + h * nt;
+    nxt[h] = i < P - 1 ? L[(size_t)(P - 1) * P + i] : make_double2(0.0, 0.0);
+  }
+  for (int k = P - 1; k >= 0; --k) {
+    double2 row[2] = {nxt[0], nxt[1]};
+    const double lkk = npiv;
+    if (k > 0) {
+      npiv = L[(size_t)(k - 1) * P + k - 1].x;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = tid + h * nt;
+        nxt[h] = i < k - 1 ? L[(size_t)(k - 1) * P + i] : make_double2(0.0, 0.0);
+      }
+    }
+    const double2 yk0 = y[k];
+    const double2 xk = make_double2(yk0.x / lkk, yk0.y / lkk);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = tid + h * nt;
+      if (i == k) {
+        y[k] = xk;
+      } else if (i < k) {
+        const double2 l = row[h];  // conj(L_ki) x_k
+        double2 v = y[i];
+        v.x -= l.x * xk.x + l.y * xk.y;
+        v.y -= l.x * xk.y - l.y * xk.x;
+        y[i] = v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < P; i += nt) Rinv[(size_t)i * P + c] = make_float2((float)y[i].x, (float)y[i].y);
 }
 
 // The same factorisation and inverse with both triangles resident in LDS
@@ -847,6 +1089,20 @@ hipError_t launch_adjoint_epi(const AdjParams& pr, const Epi& epi, hipStream_t s
   if (pr.MT <= 3) return go(adjoint_kernel<3, 1, 1, Epi>, T = 64);
   if (pr.MT <= 6) return go(adjoint_kernel<6, 1, 1, Epi>, T = 64);
   if (pr.MT <= 12) return go(adjoint_kernel<12, 1, 1, Epi>, T = 64);
+  const int ngroups = (pr.MT + 3) / 4;
+  if (pr.rows_part && pr.frag && !pr.U && !pr.xf && pr.nblk == 1 && (size_t)ngroups * pr.n <= pr.rows_cap) {
+    // rows split over workgroups, then the ordered sum and the epilogue on the
+    // same pixel tiles as adjoint_kernel
+    const int nt = pr.n <= 16 ? 1 : (pr.n <= 32 ? 2 : 4);
+    const int T_ = adjoint_tile_width(pr.MT);
+    const dim3 g1((pr.n + 16 * nt - 1) / (16 * nt), ngroups);
+    if (nt == 1) hipLaunchKernelGGL(adjoint_rows_kernel<1>, g1, dim3(kThreads), 0, st, pr, pr.rows_part);
+    else if (nt == 2) hipLaunchKernelGGL(adjoint_rows_kernel<2>, g1, dim3(kThreads), 0, st, pr, pr.rows_part);
+    else hipLaunchKernelGGL(adjoint_rows_kernel<4>, g1, dim3(kThreads), 0, st, pr, pr.rows_part);
+    hipLaunchKernelGGL(adjoint_rows_finish_kernel<Epi>, dim3((pr.n + T_ - 1) / T_), dim3(64), 0, st, pr,
+                       (const float*)pr.rows_part, ngroups, T_, epi);
+    return hipGetLastError();
+  }
   if (pr.MT <= 24) return go(adjoint_kernel<6, 2, 4, Epi>, T = 32);
   return go(adjoint_kernel<9, 4, 4, Epi>, T = 64);
 }
@@ -990,7 +1246,12 @@ hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, 
     const CholItem one{R, Li, Rinv, status};
     hipLaunchKernelGGL(chol_inverse_lds_kernel, dim3(1), dim3(256), 0, st, one, (const CholItem*)nullptr, P);
   } else {
-    hipLaunchKernelGGL(chol_inverse_kernel, dim3(1), dim3(1024), 0, st, R, P, W, Li, Rinv, status);
+    if (P > kCholMaxRows) return hipErrorInvalidValue;
+    // W holds two P x P FP64 matrices: L (row-major) and its transpose
+    double2* LT = W + (size_t)P * P;
+    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(1024), 0, st, R, P, W, LT, status);
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(P), dim3(256), 0, st, (const double2*)W, (const double2*)LT, P,
+                       (const int*)status, Li, Rinv);
   }
   return hipGetLastError();
 }

@@ -200,20 +200,48 @@ def test_gpu_adjointness(gpu_lib, ctx, scenes):
     assert abs(lhs - rhs) <= 1e-5 * scale
 
 
-def test_not_positive_definite_is_reported(gpu_lib, ctx):
+@pytest.mark.parametrize("P", [8, 100, 288])
+def test_not_positive_definite_is_reported(gpu_lib, ctx, P):
+    # P = 8: LDS-resident factorisation; 100 and 288: the blocked one (panels
+    # of 16), failing in the first column, in the last column, or on a NaN
+    print(f"case not positive definite P={P}", flush=True)
     rng = np.random.default_rng(3)
-    pos, lam, grid = _rand_geometry(rng, 8, 8, 8)
-    R = _rand_hermitian(rng, 8)
-    R = (R - (np.abs(np.linalg.eigvalsh(R)).max() + 1) * np.eye(8)).astype(np.complex64)
+    pos, lam, grid = _rand_geometry(rng, P, 8, 8)
+    R = _rand_hermitian(rng, P)
+    R = (R - (np.abs(np.linalg.eigvalsh(R)).max() + 1) * np.eye(P)).astype(np.complex64)
     geo = gpu_lib.Geometry(pos, lam, grid)
     with pytest.raises(gpu_lib.ClsimgError) as ei:
         ctx.mvdr_bound(_dev(R, torch.complex64), geo)
     assert ei.value.status == gpu_lib.ENOTPD
-    Rn = np.eye(8, dtype=np.complex64)
+    Rl = np.eye(P, dtype=np.complex64)
+    Rl[P - 1, P - 1] = -1.0
+    with pytest.raises(gpu_lib.ClsimgError) as ei:
+        ctx.mvdr_bound(_dev(Rl, torch.complex64), geo)
+    assert ei.value.status == gpu_lib.ENOTPD
+    Rn = np.eye(P, dtype=np.complex64)
     Rn[2, 3] = np.nan
     with pytest.raises(gpu_lib.ClsimgError) as ei:
         ctx.mvdr_bound(_dev(Rn, torch.complex64), geo)
     assert ei.value.status == gpu_lib.ENOTPD
+    # the context stays usable: a valid covariance of the same size afterwards
+    Rg = _rand_hermitian(rng, P, pd=True)
+    got = ctx.mvdr_bound(_dev(Rg, torch.complex64), geo).cpu().numpy()
+    _assert_close(got, oracle.upper_bound(oracle.steering(pos, lam, grid), Rg.astype(np.complex128)),
+                  what=f"mvdr after ENOTPD P={P}")
+
+
+@pytest.mark.parametrize("P", [65, 150, 288])
+def test_mvdr_bound_beyond_the_lds_factorisation(gpu_lib, ctx, P):
+    # FP64 Cholesky in panels of 16 columns (a ragged last panel at 65 and 150)
+    # and one substitution workgroup per column of R^-1
+    print(f"case mvdr bound P={P}", flush=True)
+    rng = np.random.default_rng(40 + P)
+    pos, lam, grid = _rand_geometry(rng, P, 24, 20)
+    R = _rand_hermitian(rng, P, pd=True)
+    geo = gpu_lib.Geometry(pos, lam, grid)
+    got = ctx.mvdr_bound(_dev(R, torch.complex64), geo).cpu().numpy()
+    _assert_close(got, oracle.upper_bound(oracle.steering(pos, lam, grid), R.astype(np.complex128)),
+                  what=f"mvdr P={P}")
 
 
 def _oracle_solve(sc, atol=1e-8, btol=1e-8, noise=True, kappa_d=6.0):
@@ -278,6 +306,23 @@ def test_solve_ragged_grid(gpu_lib, ctx, host, monkeypatch):
     _assert_close(gamma, gamma_ref, what="ragged gamma")
     np.testing.assert_array_equal(state, ref.state)
     _assert_close(sigma, ref.sigma, what="ragged sigma")
+    assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
+
+
+@pytest.mark.parametrize("P,n", [(104, 40), (150, 32)])
+def test_solve_large_arrays_split_rows(gpu_lib, ctx, P, n):
+    # beyond 96 antennas the LSQR subproblems run the split-K correlation and
+    # the row-split beamformer (groups of four row tiles, the last one ragged
+    # at 104 and 150 antennas); the FP64 factorisation runs in panels
+    sc = synth.make_scene("c2", P=P, n=n, seed=P, points=(15, ("powerlaw", 0.5, 500.0)))
+    print(f"case solve P={sc.P} Q={sc.Q} (row-split LSQR adjoint)", flush=True)
+    ref, mf_ref, gamma_ref = _oracle_solve(sc)
+    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc)
+    print(f"  steps {stats['outer_iters']} / {ref.outer_iters}, nF {stats['nF']}, lsqr "
+          f"{stats['lsqr_iters_total']} / {ref.lsqr_iters_total}", flush=True)
+    _assert_close(gamma, gamma_ref, what=f"gamma P={P}")
+    np.testing.assert_array_equal(state, ref.state)
+    _assert_close(sigma, ref.sigma, what=f"sigma P={P}")
     assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
 
 

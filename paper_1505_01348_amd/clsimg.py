@@ -11,7 +11,6 @@ from __future__ import annotations
 
 import ctypes as C
 import dataclasses
-import math
 import os
 
 import numpy as np
@@ -441,11 +440,6 @@ class Context:
             stats = {f: getattr(arr[i].stats, f) for f, _ in CStats._fields_}
             res.append(outs[i] + (stats,))
         return st, res
-
-
-def epsilon_scale(kappa_d: float, nsamples: int) -> float:
-    """Factor turning the MF image into the detection threshold (App. A, K = 1)."""
-    return kappa_d / math.sqrt(nsamples)
 
 
 class Server:

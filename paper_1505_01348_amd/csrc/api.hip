@@ -18,6 +18,12 @@ using namespace clsimg;
 
 namespace {
 
+// refined multipliers: at most Q / 8 (64 .. this many) FP32 candidates per
+// step (else the step's multipliers are all evaluated in FP32), and the |W|
+// partial count
+constexpr int kCandCap = 16384;
+constexpr int kCandAbsParts = 256;
+
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -66,7 +72,6 @@ struct clsimg_ctx {
   bool coop = false;   // cooperative launches available (multi-workgroup LSQR kernel)
   int lsqr_path = 0;   // CLSIMG_LSQR_PATH: 0 auto, 1 one workgroup, 2 cooperative, 3 two kernels/step
   bool old_beam = false;   // CLSIMG_LDS_BEAM=1: LDS-staged beamformer for the gradient
-  bool fwd_splitk = false; // CLSIMG_FWD_SPLITK=1: split-K correlation kernel (one partial per wave)
   bool beam_prep = false;  // CLSIMG_BEAM_PREP=1: beamformer fragments from a separate pass
   bool host_loop = false;  // CLSIMG_HOST_LOOP=1: active-set loop driven from the host
   int prec = CLSIMG_FP32;  // arithmetic of the full-grid beamforming products of the current call
@@ -77,7 +82,8 @@ struct clsimg_ctx {
   const float2* tab_Em = nullptr;
   double* h_mnorm = nullptr;  // pinned: the blocks' norm partials
   size_t h_mnorm_n = 0;
-  DevBuf frag_h, hscale;   // split half-precision fragments and their scale
+  DevBuf frag_h, hscale;   // half-precision fragments and their scale
+  DevBuf mx_abs, mx_lam, mx_cand, mx_count;  // refined multipliers: |W| partials, lam~, candidates
   int outer_max_f = 1 << 30;  // CLSIMG_OUTER_MAXF: hand over to the host loop beyond this |F|
 };
 
@@ -208,16 +214,8 @@ AdjParams adj_params(clsimg_ctx* c, const clsimg_grid* g, int P, const float* fr
   return pr;
 }
 
-// partial tiles of either correlation kernel at its largest chunk count
-size_t part_floats_max(int P) {
-  const int MT = pad_p(P) / 8;
-  const int tw = MT <= 3 ? 3 : 6;
-  const int nb = (MT + tw - 1) / tw;
-  int waves = 512 / (nb * nb);
-  if (waves < 1) waves = 1;
-  const int nc = std::max(std::min(256, waves + 2), forward_lds_chunks_max(P));
-  return (size_t)nc * MT * MT * 256;
-}
+// partials of the correlation at its largest chunk count
+size_t part_floats_max(int P) { return (size_t)forward_chunks_max(P) * forward_part_floats(P); }
 
 int ntiles_adj(int P, int n) {
   const int T = adjoint_tile_width(pad_p(P) / 8);
@@ -258,10 +256,10 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
               int gather, int n, float2* out, const float2* B, float cK, float cB,
               const LsqrState* lsqr, float* frag, double* norm_part, const int* stop,
               hipStream_t st) {
-  int chw = 8, nchunks = 0, nbm = 1;
-  forward_plan(P, n, &chw, &nchunks, &nbm, c->fwd_splitk);
+  int chw = 16, nchunks = 0;
+  forward_plan(P, n, &chw, &nchunks);
   const int MT = pad_p(P) / 8;
-  if ((size_t)nchunks * MT * MT * 256 > part_floats_max(P)) return CLSIMG_EINVAL;
+  if ((size_t)nchunks * forward_part_floats(P) > c->part.bytes / sizeof(float)) return CLSIMG_EINVAL;
   if (n > 0) {
     FwdParams f;
     f.tab = tables_of(c, g, P);
@@ -271,9 +269,6 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
     f.gather = gather;
     f.n = n;
     f.chw = chw;
-    f.nbm = nbm;
-    f.nbn = nbm;
-    f.splitk = c->fwd_splitk;
     f.part = P_<float>(c->part);
     f.stop_flag = stop;
     HIP_TRY(launch_forward(f, st));
@@ -302,11 +297,12 @@ int correlate_blocks(clsimg_ctx* c, const clsimg_grid* g, int P, int K, size_t t
                      const float* vals, int gather, int n, float2* out, size_t out_stride, const float2* B,
                      size_t B_stride, float cK, float cB, const LsqrState* lsqr, float* frag, size_t frag_stride,
                      double* norm_part, size_t norm_stride, const int* stop, hipStream_t st) {
-  int chw = 8, nchunks = 0, nbm = 1;
-  forward_plan(P, n, &chw, &nchunks, &nbm, c->fwd_splitk);
+  int chw = 16, nchunks = 0;
+  forward_plan(P, n, &chw, &nchunks);
   const int MT = pad_p(P) / 8;
   const size_t pstride = part_floats_max(P);
-  if ((size_t)nchunks * MT * MT * 256 > pstride) return CLSIMG_EINVAL;
+  if ((size_t)nchunks * forward_part_floats(P) > pstride || (size_t)K * pstride > c->part.bytes / sizeof(float))
+    return CLSIMG_EINVAL;
   if (n > 0) {
     FwdParams f;
     f.tab = tables_of(c, g, P);
@@ -316,9 +312,6 @@ int correlate_blocks(clsimg_ctx* c, const clsimg_grid* g, int P, int K, size_t t
     f.gather = gather;
     f.n = n;
     f.chw = chw;
-    f.nbm = nbm;
-    f.nbn = nbm;
-    f.splitk = c->fwd_splitk;
     f.part = P_<float>(c->part);
     f.stop_flag = stop;
     f.nblk = K;
@@ -686,8 +679,6 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   c->old_beam = ob && ob[0] == '1';
   const char* bp = getenv("CLSIMG_BEAM_PREP");
   c->beam_prep = bp && bp[0] == '1';
-  const char* fs = getenv("CLSIMG_FWD_SPLITK");
-  c->fwd_splitk = fs && fs[0] == '1';
   const char* hl = getenv("CLSIMG_HOST_LOOP");
   c->host_loop = hl && hl[0] == '1';
   const char* mf_ = getenv("CLSIMG_OUTER_MAXF");
@@ -724,6 +715,7 @@ int clsimg_destroy(clsimg_ctx* c) {
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
                     &c->dec,  &c->status, &c->lsqr2, &c->done, &c->x1, &c->w1, &c->vraw,
                     &c->bpart0, &c->bpart1, &c->xf, &c->bar, &c->frag_h, &c->hscale,
+                    &c->mx_abs, &c->mx_lam, &c->mx_cand, &c->mx_count,
                     &c->mb_tab, &c->mb_B0, &c->mb_Bb, &c->mb_u, &c->mb_E, &c->mb_frag, &c->mb_acc, &c->mb_acc2,
                     &c->mb_gpart};
   for (DevBuf* d : bufs)
@@ -1033,10 +1025,23 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   int batch = 4;
   const int ntiles_Q = ntiles_adj(P, Q);
   const bool beam_full_grid = beam_fits(P) && !c->old_beam;
-  const bool beam_half = c->prec != CLSIMG_FP32;  // split half-precision multipliers
+  // reduced precision: the multipliers from one half-precision product, the
+  // decision refined in FP32 over the candidates the rounding bound leaves
+  const bool beam_half = c->prec != CLSIMG_FP32;
+  const int cand_cap = std::max(64, std::min(Q / 8, kCandCap));
+  const int cand_tile = adjoint_tile_width(MT);
   if (beam_half) {
-    ST_TRY(ensure(c, c->frag_h, beam_h16_frag_bytes(P)));
+    ST_TRY(ensure(c, c->frag_h, std::max(beam_h16_frag_bytes(P), beam_h1_frag_bytes(P))));
     ST_TRY(ensure(c, c->hscale, sizeof(float)));
+    ST_TRY(ensure(c, c->mx_abs, kCandAbsParts * sizeof(double)));
+    ST_TRY(ensure(c, c->mx_lam, (size_t)Q * sizeof(float)));
+    ST_TRY(ensure(c, c->mx_cand, (size_t)cand_cap * sizeof(int)));
+    ST_TRY(ensure(c, c->mx_count, sizeof(int)));
+    const size_t nk = (size_t)std::max(beam_big_grid(P, Q, 2), (cand_cap + cand_tile - 1) / cand_tile) + 1;
+    if (c->keys.bytes < nk * sizeof(uint64_t)) ST_TRY(ensure(c, c->keys, nk * sizeof(uint64_t)));
+    keys = P_<uint64_t>(c->keys);
+    const size_t rows = (size_t)((MT + 3) / 4) * 8 * cand_cap;  // row groups x K slices x list
+    if (c->part.bytes < rows * sizeof(float)) ST_TRY(ensure(c, c->part, rows * sizeof(float)));
   }
   const bool beam_big_grid_ok = !beam_fits(P) && beam_big_fits(P) && !c->old_beam;
   bool host_loop = true;
@@ -1292,10 +1297,19 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
         }
         if (beam_half) {
           const bool bf = c->prec == CLSIMG_BF16;
-          HIP_TRY(launch_beam_prep_h16(E, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st));
-          HIP_TRY(launch_beam_h16(3, bf, c->frag_h.ptr, P_<const float>(c->hscale), tables_of(c, g, P), grad_stop,
-                                  nullptr, nullptr, 0.f, 0, 0, 1.f, state, keys, st, {}, big_tiles(c, P)));
-          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
+          int* count = P_<int>(c->mx_count);
+          HIP_TRY(launch_beam_lambda_refined(E, P, bf, tables_of(c, g, P), grad_stop, state, c->frag_h.ptr,
+                                             P_<float>(c->hscale), P_<double>(c->mx_abs), kCandAbsParts, keys,
+                                             P_<float>(c->mx_lam), P_<int>(c->mx_cand), cand_cap, count, st,
+                                             big_tiles(c, P)));
+          // the candidates in FP32: Ut fragments of E from the correlation
+          AdjParams ap = adj_params(c, g, P, frag_r, P_<const int>(c->mx_cand), cand_cap, grad_stop);
+          ap.rows_part = P_<float>(c->part);
+          ap.rows_cap = c->part.bytes / sizeof(float);
+          ap.n_dev = count;
+          HIP_TRY(launch_adjoint_lambda(ap, state, keys, st));
+          HIP_TRY(launch_argmin_final(keys, (cand_cap + cand_tile - 1) / cand_tile, eps, state, dec, st, count,
+                                      cand_cap));
         } else if (!beam_full_grid && beam_big_grid_ok) {
           HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr, 0.f,
@@ -1313,6 +1327,23 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
         }
         ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+        if (beam_half && c->h_dec->lsqr_done && c->h_dec->feasible && c->h_dec->cand_overflow) {
+          // more candidates than the list holds: this step's multipliers in FP32
+          if (beam_full_grid) {
+            HIP_TRY(launch_beam_lambda(nullptr, E, P, tables_of(c, g, P), grad_stop, state, keys, nullptr, st));
+            HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
+          } else if (beam_big_grid_ok) {
+            HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
+            HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr,
+                                    0.f, 0, 0, 1.f, state, keys, st, {}, big_tiles(c, P)));
+            HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
+          } else {
+            HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys, st));
+            HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
+          }
+          ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+          if (c->trace) fprintf(stderr, "clsimg: outer %d: candidate list full, multipliers in FP32\n", outer);
+        }
         if (c->h_dec->lsqr_done) break;
         if (persist || one_cu || c->h_dec->lsqr_err) return CLSIMG_EHIP;  // LSQR kernel did not finish
         batch = std::min(batch * 2, 64);

@@ -367,14 +367,18 @@ __global__ __launch_bounds__(64 * kBeamWaves) __attribute__((amdgpu_waves_per_eu
 // ---------------------------------------------------------------------------
 // Larger arrays (P > 48): the fragments of the whole Ut no longer fit in
 // registers, so the product is organised like a GEMM.  A workgroup takes NT
-// 16-pixel tiles (two or four); wave w owns the row tiles m = w, w + 4, ...
-// (RPW of them, padded rows are zero) and streams their fragments from L2
-// (prepared once per call by beam_prep_full_kernel, same row permutation as
-// above, full matrix, no doubling) while it generates the B operands of the
-// four pixel tiles from the tables, one complex product per two 4-row
-// chunks.  After the K loop the column dot needs the lane's entries of its own
-// row tiles again: they are recomputed from the tables (two complex products
-// per row tile and pixel tile).  The four waves' partial sums meet in LDS.
+// 16-pixel tiles (two, four or eight); wave w owns RPW row tiles, m = 4i + w
+// for even i and 4i + 3 - w for odd i (so that the four waves carry the same
+// work), and streams their fragments from L2 while it generates the B
+// operands of its pixel tiles from the tables, one complex product per two
+// 4-row chunks.  Ut is symmetric, so x^T Ut x = sum_m x_m^T Ut_mm x_m +
+// 2 sum_{c<m} x_m^T Ut_mc x_c over 16 x 16 blocks: row tile m runs the chunks
+// of column tiles 0..m only, with the fragments of c < m doubled by
+// beam_prep_full_kernel (same row permutation as above); that is 51 % of the
+// full product's MFMAs at 288 antennas.  After the K loop the column dot needs
+// the lane's entries of its own row tiles again: they are recomputed from the
+// tables (two complex products per row tile and pixel tile).  The four waves'
+// partial sums meet in LDS.
 __host__ __device__ inline int big_rpw(int MT) { return (MT + 3) / 4; }
 // 16-pixel tiles per workgroup.  The default (measured: two for up to 16 row
 // tiles, where more workgroups hide the load latency, four for longer K
@@ -386,9 +390,6 @@ __host__ __device__ constexpr int big_nt(int rpw) { return rpw <= 4 ? 2 : 4; }
 // longer fit in the register file
 __host__ __device__ constexpr bool big_nt_ok(int nt, int rpw) { return nt == 2 || nt == 4 || (nt == 8 && rpw <= 6); }
 __host__ __device__ inline int big_nt_or(int nt, int rpw) { return big_nt_ok(nt, rpw) ? nt : big_nt(rpw); }
-// loads of the next chunk pair issued before the current pair's MFMAs while
-// the registers allow it (short K loops, i.e. up to 16 row tiles)
-__host__ __device__ constexpr bool big_prefetch(int rpw) { return rpw <= 4; }
 
 __global__ void beam_prep_full_kernel(const float2* __restrict__ U, int P, int MT, float* __restrict__ frag) {
   const int KS = 4 * MT, rows = 4 * big_rpw(MT);
@@ -401,26 +402,36 @@ __global__ void beam_prep_full_kernel(const float2* __restrict__ U, int P, int M
     beam_pos(16 * m + 4 * (c16 & 3) + (c16 >> 2), p, s);
     beam_pos(4 * kc + qq, p2, t);
     float v = 0.f;
-    if (m < MT && p < P && p2 < P) {
+    const int ct = kc >> 2;  // column tile: below the diagonal doubled, above it unused (zero)
+    if (m < MT && p < P && p2 < P && ct <= m) {
       const float2 x = U[p * P + p2], y = U[p2 * P + p];
       const float hr = 0.5f * (x.x + y.x), hi = 0.5f * (x.y - y.y);
       v = (s == t) ? hr : (s == 0 ? -hi : hi);
+      if (ct < m) v *= 2.f;
     }
     frag[e] = v;
   }
 }
 
 template <int RPW, int NT, class Epi>
-__global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__ frag, int MT, Tables tab,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2 : 1))) void beam_big_kernel(const float* __restrict__ frag, int MT, Tables tab,
                                                        const int* skip, Epi epi) {
-  constexpr bool kPrefetch = big_prefetch(RPW);
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
-  const int w = threadIdx.x >> 6;
+  // wave index as a scalar: the row-tile tests below are wave-uniform branches
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int KS = 4 * MT;
   const int Q = tab.Q, nl = tab.nl, nm = tab.nm;
   const int ntiles = (Q + 15) >> 4;
+  int mrow[RPW];
+  int mlast = 0;  // this wave's last row tile: its K loop ends with that column tile
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
+    if (mrow[i] < MT) mlast = max(mlast, mrow[i]);
+  }
+  const int jend = 2 * mlast + 2;  // chunk pairs 0 .. 2 mlast + 1
   epi.init();
   for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
     // this lane's pixel in each of the block's tiles (clamped; masked at the end)
@@ -438,76 +449,60 @@ __global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__
     for (int i = 0; i < RPW; ++i)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    const float* fw = frag + (size_t)w * KS * 64 + lane;  // row tile w, chunk 0
-    const size_t rstep = (size_t)4 * KS * 64;             // next row tile of this wave
-    if constexpr (kPrefetch) {
-      float2 te[NT], tm[NT];
-      float f0[RPW], f1[RPW];
-  #pragma unroll
+    // the table entries and the fragments of the next chunk pair are loaded
+    // while the current pair multiplies
+    float2 te[NT], tm[NT];
+    float f0n[RPW], f1n[RPW];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      te[t] = el[t][0];
+      tm[t] = em[t][0];
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const float* fr = frag + (size_t)min(mrow[i], MT - 1) * KS * 64 + lane;
+      f0n[i] = fr[0];
+      f1n[i] = fr[64];
+    }
+    for (int j = 0; j < jend; ++j) {  // chunk pair 2j, 2j + 1: antenna 4j + q, column tile j >> 1
+      const int ct = j >> 1;
+      float b0[NT], b1[NT];
+#pragma unroll
       for (int t = 0; t < NT; ++t) {
-        te[t] = el[t][0];
-        tm[t] = em[t][0];
+        const float2 a = cmul(te[t], tm[t]);
+        b0[t] = a.x;
+        b1[t] = a.y;
       }
-  #pragma unroll
+      float f0[RPW], f1[RPW];
+#pragma unroll
       for (int i = 0; i < RPW; ++i) {
-        f0[i] = fw[i * rstep];
-        f1[i] = fw[i * rstep + 64];
+        f0[i] = f0n[i];
+        f1[i] = f1n[i];
       }
-      for (int j = 0; j < KS / 2; ++j) {                    // chunk pair 2j, 2j + 1: antenna 4j + q
-        float b0[NT], b1[NT];
-  #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const float2 a = cmul(te[t], tm[t]);
-          b0[t] = a.x;
-          b1[t] = a.y;
-        }
-        float g0[RPW], g1[RPW];
-  #pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-          g0[i] = f0[i];
-          g1[i] = f1[i];
-        }
-        const int jn = j + 1 < KS / 2 ? j + 1 : j;  // loads of the next pair
-  #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          te[t] = el[t][(size_t)4 * jn * nl];
-          tm[t] = em[t][(size_t)4 * jn * nm];
-        }
-  #pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-          f0[i] = fw[i * rstep + (size_t)(2 * jn) * 64];
-          f1[i] = fw[i * rstep + (size_t)(2 * jn + 1) * 64];
-        }
-  #pragma unroll
-        for (int i = 0; i < RPW; ++i)
-  #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            acc[i][t] = mfma16x16x4(g0[i], b0[t], acc[i][t]);
-            acc[i][t] = mfma16x16x4(g1[i], b1[t], acc[i][t]);
-          }
+      const int jn = j + 1 < jend ? j + 1 : j;
+      const int ctn = jn >> 1;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        te[t] = el[t][(size_t)4 * jn * nl];
+        tm[t] = em[t][(size_t)4 * jn * nm];
       }
-    } else {
-      for (int j = 0; j < KS / 2; ++j) {                    // chunk pair 2j, 2j + 1: antenna 4j + q
-        float b0[NT], b1[NT];
-  #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const float2 a = cmul(el[t][(size_t)4 * j * nl], em[t][(size_t)4 * j * nm]);
-          b0[t] = a.x;
-          b1[t] = a.y;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        if (mrow[i] >= ctn && mrow[i] < MT) {  // wave-uniform
+          const float* fr = frag + ((size_t)mrow[i] * KS + 2 * jn) * 64 + lane;
+          f0n[i] = fr[0];
+          f1n[i] = fr[64];
         }
-        float f0[RPW], f1[RPW];
-  #pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-          f0[i] = fw[i * rstep + (size_t)(2 * j) * 64];
-          f1[i] = fw[i * rstep + (size_t)(2 * j + 1) * 64];
-        }
-  #pragma unroll
-        for (int i = 0; i < RPW; ++i)
-  #pragma unroll
+      }
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        if (mrow[i] >= ct && mrow[i] < MT) {  // wave-uniform
+#pragma unroll
           for (int t = 0; t < NT; ++t) {
             acc[i][t] = mfma16x16x4(f0[i], b0[t], acc[i][t]);
             acc[i][t] = mfma16x16x4(f1[i], b1[t], acc[i][t]);
           }
+        }
       }
     }
     // column dot over this wave's row tiles: accumulator element r of row tile m
@@ -518,7 +513,7 @@ __global__ __launch_bounds__(256) void beam_big_kernel(const float* __restrict__
       gp[t] = 0.f;
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
-        const int m = w + 4 * i;
+        const int m = mrow[i];
         if (m < MT) {
           const float2 a0 = cmul(el[t][(size_t)(8 * m) * nl], em[t][(size_t)(8 * m) * nm]);
           const float2 a1 = cmul(el[t][(size_t)(8 * m + 4) * nl], em[t][(size_t)(8 * m + 4) * nm]);
@@ -734,6 +729,231 @@ __global__ __launch_bounds__(256) void beam_h16_kernel(const typename Half<BF>::
   epi.finish(blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Reduced precision with FP32 refinement of the decision (the multipliers of
+// the host-driven loop with CLSIMG_FP16 / CLSIMG_BF16): one half-precision
+// product Y = W X on the 16 x 16 x 32 MFMA with FP32 accumulation, W the
+// block triangle of Ut (blocks below the diagonal doubled, as in the FP32
+// kernel), gives approximate multipliers lam~_i, with a bound delta on
+// |lam~_i - lam_i| from the rounding of both operands:
+//   |x^T W x - x~^T W~ x| <= (2u + accumulation terms) sum_jk |x_j| |W_jk| |x_k|
+//                         <= (2u + ...) S / P,   S = sum |W| = sum |Ut|,
+// since every real steering component is at most P^-1/2 (u = 2^-11 for FP16,
+// 2^-8 for BF16).  The true minimum lies among the pixels with
+// lam~_i <= min lam~ + 2 delta; those candidates are beamformed again in FP32
+// and the argmin is taken over them, so the decision is the FP32 one.
+//
+// Fragments: [row tile m][chunk c][lane] (one 8-vector per lane), positions as
+// in the split kernel; chunk c of row tile m holds the 32 columns 32c ..
+// 32c + 31, zero above the diagonal block, doubled below it.  absum[b]:
+// workgroup b's sum of |W| (FP32 values, summed in double, fixed order).
+template <bool BF>
+__global__ __launch_bounds__(256) void beam_prep_h1_kernel(const float2* __restrict__ U, int P, int MT, int KC,
+                                                           const float* __restrict__ scale,
+                                                           typename Half<BF>::V* __restrict__ frag,
+                                                           double* __restrict__ absum, int* __restrict__ count) {
+  typedef typename Half<BF>::V V;
+  __shared__ double sh[4];
+  const float sU = scale ? *scale : 1.f;
+  const int total = 4 * big_rpw(MT) * KC * 64;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && count) *count = 0;  // candidates of the coming selection
+  double acc = 0.0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int lane = e & 63, f = e >> 6;
+    const int m = f / KC, c = f - m * KC;
+    const int row = 16 * m + (lane & 15), col0 = 32 * c + 8 * (lane >> 4);
+    const int p = row >> 1, s = row & 1;
+    V hv;
+    float a = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int col = col0 + i, p2 = col >> 1, t = i & 1;
+      const int ct = col >> 4;  // 16-column tile
+      float v = 0.f;
+      if (m < MT && p < P && p2 < P && ct <= m) {
+        const float2 x = U[p * P + p2], y = U[p2 * P + p];
+        const float hr = 0.5f * (x.x + y.x), hm = 0.5f * (x.y - y.y);
+        v = (s == t) ? hr : (s == 0 ? -hm : hm);
+        if (ct < m) v *= 2.f;
+      }
+      a += fabsf(v);
+      hv[i] = (typename Half<BF>::T)(v * sU);
+    }
+    acc += (double)a;
+    frag[(size_t)f * 64 + lane] = hv;
+  }
+  const double tot = block_sum_d(acc, sh);
+  if (threadIdx.x == 0) absum[blockIdx.x] = tot;
+}
+
+// The approximate multipliers: lam~ in lam[] (+inf for free pixels) and one
+// argmin key per workgroup in part[].
+struct BeamLambdaApprox {
+  const uint8_t* state;
+  uint64_t* part;
+  float* lam;
+  uint64_t best;
+  __device__ void init() { best = ~0ull; }
+  __device__ void operator()(int pix, float g, bool ok) {
+    if (ok) {
+      const uint8_t s = state[pix];
+      float l = __builtin_inff();
+      if (s != 1) {
+        l = (s == 0) ? g : -g;
+        const uint64_t key = ((uint64_t)ordered_bits(l) << 32) | (uint32_t)pix;
+        best = key < best ? key : best;
+      }
+      lam[pix] = l;
+    }
+  }
+  __device__ void finish(int blk) {
+    __shared__ uint64_t sh[4];
+    const uint64_t m = block_min_u64(best, sh);
+    if (threadIdx.x == 0) part[blk] = m;
+  }
+};
+
+// Single product on the half MFMA, block-triangular; waves own row tiles
+// m = 4i + w (even i) or 4i + 3 - w (odd i) as in the FP32 kernel, and row
+// tile m runs chunks 0 .. m / 2.  The B operands of a chunk (16 antennas of
+// the NT = 4 pixel tiles) are generated once per workgroup: wave w forms tile
+// w's operands from the tables (four complex products per lane) into a
+// double-buffered LDS slot while the waves multiply the previous chunk, and
+// every wave reads all four tiles' operands back (one barrier per chunk).
+template <int RPW, bool BF, class Epi>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void beam_h1_kernel(
+    const typename Half<BF>::V* __restrict__ frag, int MT, int KC, const float* __restrict__ scale, float sB,
+    Tables tab, const int* skip, Epi epi) {
+  typedef typename Half<BF>::V V;
+  typedef typename Half<BF>::T T;
+  constexpr int NT = 4;
+  if (skip && *skip) return;
+  __shared__ float gsum[4][NT * 16];
+  __shared__ V bsh[2][NT][64];
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row-tile tests
+  const int Q = tab.Q, nl = tab.nl, nm = tab.nm, Pp = tab.Pp;
+  const int ntiles = (Q + 15) >> 4;
+  const float inv = 1.f / ((scale ? *scale : 1.f) * sB);
+  int mrow[RPW];
+  int mlast = 0;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
+    if (mrow[i] < MT) mlast = max(mlast, mrow[i]);
+  }
+  // every wave runs the same chunks (the barriers are shared): up to the
+  // workgroup's last row tile
+  const int cend = min(KC, (MT - 1) / 2 + 1);
+  epi.init();
+  for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
+    // this lane's pixel in tile w (operand generation); the column dot below
+    // finds each tile's pixel again
+    const int pw = min(16 * (blk * NT + w) + c16, Q - 1);
+    const int imw = pw / nl;
+    const float2* elw = tab.El + (pw - imw * nl);
+    const float2* emw = tab.Em + imw;
+    auto gen = [&](int c, int slot) {
+      V bh;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ant = min(16 * c + 4 * g + u, Pp - 1);  // beyond P: zero columns of W
+        const float2 a = cmul(elw[(size_t)ant * nl], emw[(size_t)ant * nm]);
+        bh[2 * u] = (T)(a.x * sB);
+        bh[2 * u + 1] = (T)(a.y * sB);
+      }
+      bsh[slot][w][lane] = bh;
+    };
+    v4f acc[RPW][NT];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    gen(0, 0);
+    __syncthreads();
+    for (int c = 0; c < cend; ++c) {
+      if (c + 1 < cend) gen(c + 1, (c + 1) & 1);
+      V bh[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bh[t] = bsh[c & 1][t][lane];
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        if (mrow[i] < MT && 2 * c <= mrow[i]) {  // wave-uniform
+          const V ah = frag[((size_t)mrow[i] * KC + c) * 64 + lane];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[i][t] = Half<BF>::mfma(ah, bh[t], acc[i][t]);
+        }
+      }
+      __syncthreads();  // slot c & 1 is free again; slot (c + 1) & 1 is written
+    }
+    float gp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
+      const int im = pix / nl;
+      const float2* el = tab.El + (pix - im * nl);
+      const float2* em = tab.Em + im;
+      gp[t] = 0.f;
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int m = mrow[i];
+        if (m < MT) {
+          const int a0i = 8 * m + 2 * g;
+          const float2 a0 = cmul(el[(size_t)a0i * nl], em[(size_t)a0i * nm]);
+          const float2 a1 = cmul(el[(size_t)(a0i + 1) * nl], em[(size_t)(a0i + 1) * nm]);
+          gp[t] += acc[i][t][0] * a0.x + acc[i][t][1] * a0.y + acc[i][t][2] * a1.x + acc[i][t][3] * a1.y;
+        }
+      }
+      gp[t] += __shfl_xor(gp[t], 16, 64);
+      gp[t] += __shfl_xor(gp[t], 32, 64);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) gsum[w][16 * t + c16] = gp[t];
+    }
+    __syncthreads();
+    if (threadIdx.x < NT * 16) {
+      const int t = threadIdx.x >> 4;
+      const int pix = 16 * (blk * NT + t) + (threadIdx.x & 15);
+      const float s4 = (gsum[0][threadIdx.x] + gsum[1][threadIdx.x]) + (gsum[2][threadIdx.x] + gsum[3][threadIdx.x]);
+      epi(pix, s4 * inv, pix < Q);
+    }
+    __syncthreads();
+  }
+  epi.finish(blockIdx.x);
+}
+
+// Candidates of the FP32 refinement: every workgroup reduces the argmin keys
+// (min lam~) and the |W| partials (S) in a fixed order, forms
+//   delta = coef S + coef_abs S_abs,   threshold = min lam~ + 2 delta
+// (in double), and appends the pixels of its slice with lam~ <= threshold to
+// cand[] (order immaterial: the FP32 argmin key carries the pixel index).
+// *count ends as the number of candidates, possibly beyond cap.
+__global__ __launch_bounds__(256) void beam_cand_kernel(const uint64_t* __restrict__ keys, int nkeys,
+                                                        const double* __restrict__ absum, int nabs, double coef,
+                                                        const float* __restrict__ lam, int Q, const int* skip,
+                                                        int* __restrict__ cand, int cap, int* __restrict__ count) {
+  __shared__ uint64_t shk[4];
+  __shared__ double shs[4];
+  if (skip && *skip) return;
+  uint64_t m = ~0ull;
+  for (int i = threadIdx.x; i < nkeys; i += blockDim.x) m = keys[i] < m ? keys[i] : m;
+  m = block_min_u64(m, shk);
+  double sa = 0.0;
+  for (int i = threadIdx.x; i < nabs; i += blockDim.x) sa += absum[i];
+  const double S = block_sum_d(sa, shs);
+  if (m == ~0ull) return;  // no active pixel
+  const double lmin = (double)from_ordered_bits((uint32_t)(m >> 32));
+  const double thr = lmin + 2.0 * coef * S;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
+    const float l = lam[i];
+    if ((double)l <= thr) {
+      const int k = atomicAdd(count, 1);
+      if (k < cap) cand[k] = i;
+    }
+  }
+}
+
 bool beam_fits(int P) { return pad_p(P) / 8 <= kBeamMaxMT; }
 
 constexpr int kBigMaxRPW = 9;  // up to 36 row tiles: P <= 288
@@ -926,6 +1146,73 @@ hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* s
       return bf16 ? launch_h16<true>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts, nt)
                   : launch_h16<false>(frag, s, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts, nt);
   }
+}
+
+// ---- reduced precision with FP32 refinement of the decision ----
+size_t beam_h1_frag_bytes(int P) {
+  const int MT = pad_p(P) / 8;
+  return (size_t)4 * big_rpw(MT) * beam_h16_chunks(P) * 64 * 16;
+}
+
+double beam_h1_delta_coef(int P, bool bf16) {
+  // 2u for the two rounded operands, accumulation of up to 8 Pp + 64 FP32
+  // terms over the half and the FP32 evaluations (2^-24 each), FP16
+  // subnormals (at most 2^-25 absolute per scaled entry, far below u |v| for
+  // the entries that matter; covered by the factor 1.5 of the whole bound)
+  const double u = bf16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -11);
+  const int Pp = pad_p(P);
+  return 1.5 * (2.0 * u + (8.0 * Pp + 64.0) * std::ldexp(1.0, -24)) / (double)P;
+}
+
+hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,
+                                      const uint8_t* state, void* frag, float* scale, double* absum, int nabs,
+                                      uint64_t* keys, float* lam, int* cand, int cap, int* count, hipStream_t st,
+                                      int nt) {
+  const int MT = pad_p(P) / 8, KC = beam_h16_chunks(P), rpw = big_rpw(MT);
+  if (!bf16)
+    hipLaunchKernelGGL(beam_h16_scale_kernel, dim3(1), dim3(1024), 0, st, E, P * P, scale);
+  if (bf16)
+    hipLaunchKernelGGL(beam_prep_h1_kernel<true>, dim3(nabs), dim3(256), 0, st, E, P, MT, KC, (const float*)nullptr,
+                       static_cast<v8b*>(frag), absum, count);
+  else
+    hipLaunchKernelGGL(beam_prep_h1_kernel<false>, dim3(nabs), dim3(256), 0, st, E, P, MT, KC, (const float*)scale,
+                       static_cast<v8h*>(frag), absum, count);
+  // four 16-pixel tiles per workgroup (one per wave for the operand
+  // generation), two waves per SIMD
+  (void)nt;
+  nt = 4;
+  int ex = 0;
+  (void)frexpf(sqrtf((float)tab.Pp), &ex);
+  const float sB = bf16 ? 1.f : ldexpf(1.f, ex - 1);
+  const dim3 g(beam_big_grid(tab.Pp, tab.Q, nt)), b(256);
+  const BeamLambdaApprox epi{state, keys, lam, 0};
+  const float* sc = bf16 ? nullptr : scale;
+#define H1_RPW(R)                                                                                              \
+  case R:                                                                                                      \
+    if (bf16)                                                                                                  \
+      hipLaunchKernelGGL((beam_h1_kernel<R, true, BeamLambdaApprox>), g, b, 0, st,                             \
+                         static_cast<const v8b*>(frag), MT, KC, sc, sB, tab, skip, epi);                       \
+    else                                                                                                       \
+      hipLaunchKernelGGL((beam_h1_kernel<R, false, BeamLambdaApprox>), g, b, 0, st,                            \
+                         static_cast<const v8h*>(frag), MT, KC, sc, sB, tab, skip, epi);                       \
+    break;
+  switch (rpw) {
+    H1_RPW(1)
+    H1_RPW(2)
+    H1_RPW(3)
+    H1_RPW(4)
+    H1_RPW(5)
+    H1_RPW(6)
+    H1_RPW(7)
+    H1_RPW(8)
+    H1_RPW(9)
+    default: return hipErrorInvalidValue;
+  }
+#undef H1_RPW
+  hipLaunchKernelGGL(beam_cand_kernel, dim3(256), dim3(256), 0, st, (const uint64_t*)keys, (int)g.x,
+                     (const double*)absum, nabs, beam_h1_delta_coef(P, bf16), (const float*)lam, tab.Q, skip, cand,
+                     cap, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,

@@ -37,6 +37,9 @@ struct AdjParams {
   // column dot per group of four row tiles and listed pixel
   float* rows_part = nullptr;
   size_t rows_cap = 0;
+  // optional: the list length on the device (at most n), for lists built by a
+  // kernel; columns from *n_dev on are left out (row-split beamformer only)
+  const int* n_dev = nullptr;
 };
 
 struct FwdParams {
@@ -46,9 +49,7 @@ struct FwdParams {
   const float* vals;  // weight of the k-th term: gather ? vals[pixel] : vals[k]
   int gather;
   int n;
-  int chw;            // pixels per workgroup (split-K kernel: per wave, a multiple of 4)
-  int nbm, nbn;       // output block grid
-  int splitk = 0;     // the split-K kernel (one partial per wave) instead of the LDS-staged one
+  int chw;            // pixels per workgroup, a multiple of 16
   float* part;
   const int* stop_flag;
   // K covariance blocks in one launch (blockIdx.z): block k reads the tables
@@ -394,6 +395,19 @@ hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* s
 // sums over covariance blocks of the full-grid beamformer (any P, any precision:
 // prec 0 FP32, 1 FP16 split, 2 BF16 split); frag_big / frag_half / hscale are
 // the scratch of the GEMM-shaped and half-precision kernels
+// Reduced precision with FP32 refinement (host-driven loop, CLSIMG_FP16 /
+// CLSIMG_BF16): approximate multipliers of every pixel from one half-precision
+// product of the block-triangular Ut of E (lam[] and one argmin key per
+// workgroup in keys[]), then the pixels within twice the rounding bound of
+// the approximate minimum are listed in cand[] (*count of them, possibly more
+// than cap) for an FP32 evaluation.  frag: beam_h1_frag_bytes(P); scale: one
+// float (FP16); absum: nabs doubles; keys: beam_big_grid(P, Q, nt) entries.
+size_t beam_h1_frag_bytes(int P);
+double beam_h1_delta_coef(int P, bool bf16);
+hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,
+                                      const uint8_t* state, void* frag, float* scale, double* absum, int nabs,
+                                      uint64_t* keys, float* lam, int* cand, int cap, int* count, hipStream_t st,
+                                      int nt);
 hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
                                   float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
                                   float* hscale, hipStream_t st, int nt = 0);
@@ -429,8 +443,9 @@ hipError_t launch_xf(const Tables& tab, const int* Flist, int n, float* xf, hipS
 hipError_t launch_lsqr_fwd(const LsqrFwdParams& pr, hipStream_t st);
 hipError_t launch_lsqr_setup(LsqrState* S0, int* done, double atol, double btol, double conlim,
                              int itnlim, hipStream_t st);
-void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm, bool splitk = false);
-int forward_lds_chunks_max(int P);  // most partials of the LDS-staged correlation
+void forward_plan(int P, int n, int* chw, int* nchunks);
+int forward_chunks_max(int P);       // most chunks (partials per block pair) of the correlation
+size_t forward_part_floats(int P);   // floats of one chunk's partials
 hipError_t launch_forward(const FwdParams& pr, hipStream_t st);
 int reduce_blocks(int P);
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st);
@@ -474,6 +489,7 @@ struct SolveDecision {
   float lam_min, eps_min;
   int grad_done;
   int lsqr_err;          // a grid barrier of the LSQR kernel did not complete
+  int cand_overflow;     // refined multipliers: more candidates than the list holds
 };
 
 hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec,
@@ -564,7 +580,8 @@ hipError_t launch_step(const int* done, const int* err, const LsqrState* s, cons
 hipError_t launch_lsqr_setup2(LsqrState* S0, int* done, unsigned* bar, int* err, double atol,
                               double btol, double conlim, int itnlim, hipStream_t st);
 hipError_t launch_argmin_final(const uint64_t* part, int nparts, const float* eps,
-                               const uint8_t* state, SolveDecision* dec, hipStream_t st);
+                               const uint8_t* state, SolveDecision* dec, hipStream_t st,
+                               const int* cand_count = nullptr, int cand_cap = 0);
 hipError_t launch_set_state(uint8_t* state, int i, uint8_t v, hipStream_t st);
 hipError_t launch_init_state(const float* sigma0, const uint8_t* state0, float* sigma,
                              uint8_t* state, int Q, hipStream_t st);

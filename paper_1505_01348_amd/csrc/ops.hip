@@ -230,20 +230,25 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
 }
 
 // ---------------------------------------------------------------------------
-// Beamforming of a pixel list for arrays beyond 12 row tiles, rows split over
-// workgroups.  Workgroup (x, y) takes NT 16-pixel tiles of the list and the
-// row tiles 4y .. 4y + 3 of Ut (one per wave, fragments prepared by the
-// correlation), runs the whole K loop with the next chunk's fragment and
-// table loads issued before the current chunk's MFMA, and leaves the partial
-// column dot of its rows in part[y * n + k].  adjoint_rows_finish_kernel adds
-// the row groups in order and applies the epilogue.  Embedding as in the
+// Beamforming of a pixel list for arrays beyond 12 row tiles, rows and K
+// split over workgroups.  Workgroup (x, y, z) takes NT 16-pixel tiles of the
+// list, the row tiles 4y .. 4y + 3 of Ut (one per wave, fragments prepared by
+// the correlation) and the z-th of gridDim.z slices of the K chunks, with the
+// next chunk's fragment and table loads issued before the current chunk's
+// MFMA.  The column dot is linear in Y, so x_m^T (Ut_m,slice x_slice) summed
+// over slices and row tiles is the beamformer output: each workgroup leaves
+// its partial in part[(z * gridDim.y + y) * n + k], and
+// adjoint_rows_finish_kernel adds the partials in that order and applies the
+// epilogue.  Embedding as in the
 // reduction's fragments: real row 2p + s is component s of antenna p.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, float* __restrict__ part) {
   if (pr.stop_flag && *pr.stop_flag) return;
   __shared__ float gs[4][NT * 16];
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
-  const int MT = pr.MT, KS = pr.KS, n = pr.n;
+  const int MT = pr.MT, KS = pr.KS, stride = pr.n;  // partials: one row of pr.n per (slice, row group)
+  const int n = pr.n_dev ? min(*pr.n_dev, pr.n) : pr.n;
+  if (16 * (int)blockIdx.x * NT >= n) return;  // beyond a list built on the device
   const int mt = 4 * blockIdx.y + w;
   const bool live_row = mt < MT;
   const int mtc = live_row ? mt : MT - 1;  // loads stay in bounds; the dot leaves it out
@@ -266,18 +271,21 @@ __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, fl
     emp[t] = tab.Em + (size_t)(q >> 1) * tab.nm + im[t];
   }
   const size_t sl = (size_t)2 * tab.nl, sm = (size_t)2 * tab.nm;  // two antennas per chunk
+  const int per = (KS + gridDim.z - 1) / gridDim.z;
+  const int k0 = blockIdx.z * per, k1 = min(KS, k0 + per);
   const float* fw = pr.frag + (size_t)mtc * KS * 64 + lane;
   v4f acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-  float fa = fw[0];
+  const int kf = k0 < k1 ? k0 : 0;
+  float fa = fw[(size_t)kf * 64];
   float2 te[NT], tm[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    te[t] = elp[t][0];
-    tm[t] = emp[t][0];
+    te[t] = elp[t][kf * sl];
+    tm[t] = emp[t][kf * sm];
   }
-  for (int kc = 0; kc < KS; ++kc) {
+  for (int kc = k0; kc < k1; ++kc) {
     const float a = fa;
     float b[NT];
 #pragma unroll
@@ -285,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, fl
       const float2 x = cmul(te[t], tm[t]);
       b[t] = (q & 1) ? x.y : x.x;
     }
-    const int kn = kc + 1 < KS ? kc + 1 : kc;
+    const int kn = kc + 1 < k1 ? kc + 1 : kc;
     fa = fw[(size_t)kn * 64];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, fl
   if (threadIdx.x < NT * 16) {
     const int col = 16 * blockIdx.x * NT + threadIdx.x;
     const float g = (gs[0][threadIdx.x] + gs[1][threadIdx.x]) + (gs[2][threadIdx.x] + gs[3][threadIdx.x]);
-    if (col < n) part[(size_t)blockIdx.y * n + col] = g;
+    if (col < n) part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * stride + col] = g;
   }
 }
 
@@ -330,7 +338,8 @@ __global__ __launch_bounds__(64) void adjoint_rows_finish_kernel(AdjParams pr, c
   const typename Epi::Ctx cx = epi.init();
   if (stop) return;
   const int tile = blockIdx.x, col = tile * T + threadIdx.x;
-  const bool ok = (int)threadIdx.x < T && col < pr.n;
+  const int n = pr.n_dev ? min(*pr.n_dev, pr.n) : pr.n;
+  const bool ok = (int)threadIdx.x < T && col < n;
   float g = 0.f;
   int pix = 0;
   if (ok) {
@@ -415,231 +424,162 @@ __global__ __launch_bounds__(kThreads) void adjoint_list_kernel(AdjParams pr, Ep
 }
 
 // ---------------------------------------------------------------------------
-// Correlation: partial G = X_S diag(v) X_S^T over a chunk of pixels per wave.
-// Partial tile layout: part[((chunk*MT + mt)*MT + nt)*256 + lane*4 + r]
-//                      = G[16mt + 4q + r][16nt + c16].
-template <int MTW, int NTW>
-__global__ __launch_bounds__(kThreads) void forward_kernel(FwdParams pr) {
+// Correlation (forward operator, Sec. IV-B): Y = sum_k v_k a_k a_k^H over a
+// pixel list, computed in complex form on 16 x 16 antenna tiles.  For tiles
+// (bm, bn) of antennas, per four pixels (one MFMA k step, lane group q = one
+// pixel), with A = a[16bm + c16] and B = v a[16bn + c16]:
+//   Re Y += A_r B_r + A_i B_i,   Im Y += A_i B_r - A_r B_i,
+// four 16x16x4 FP32 MFMAs, exactly the dense complex count (8 flops per term
+// and antenna pair); Y is Hermitian, so only tile pairs bm >= bn are formed.
+// A wave owns a BT x BT block of tile pairs and generates its 2 BT steering
+// entries per pixel straight into registers from the tables (one complex
+// product each), with the next step's table entries, pixel indices and
+// weights loaded while the current step multiplies.  The four waves of a
+// workgroup split the workgroup's pixels (k steps w, w + 4, ...) and their
+// accumulators are added in LDS in a fixed order; each workgroup leaves one
+// partial of its block pair: part[(chunk * npairs + pair) * BT^2 * 512 +
+// tile * 512 + {0: Re, 256: Im} + lane * 4 + r] = Y[16 bm + 4q + r][16 bn + c16].
+__host__ __device__ inline int corr_tiles(int P) { return (pad_p(P) + 15) / 16; }
+__host__ __device__ inline int corr_bt(int P) { return corr_tiles(P) <= 2 ? 2 : 3; }
+__host__ __device__ inline int corr_nblocks(int P) { return (corr_tiles(P) + corr_bt(P) - 1) / corr_bt(P); }
+__host__ __device__ inline int corr_pairs(int P) { return corr_nblocks(P) * (corr_nblocks(P) + 1) / 2; }
+
+template <int BT>
+__global__ __launch_bounds__(kThreads) void corr_kernel(FwdParams pr) {
+  constexpr int NACC = BT * BT * 2;  // v4f accumulators per lane: Re and Im of each tile pair
+  __shared__ v4f red[2][NACC][64];
   if (pr.stop_flag && *pr.stop_flag) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c16 = lane & 15, q = lane >> 4;
-  const int MT = pr.MT;
-  const int bm = blockIdx.y % pr.nbm, bn = blockIdx.y / pr.nbm;
-  const int chunk = blockIdx.x * 4 + w;
-  const int k0 = chunk * pr.chw;
-  if (k0 >= pr.n) return;
-  const int k1 = min(k0 + pr.chw, pr.n);
-  Tables tab = pr.tab;
-  const int kb = blockIdx.z;  // covariance block
-  tab.El += kb * pr.tab_stride;
-  tab.Em += kb * pr.tab_stride;
-  float* part = pr.part + kb * pr.part_stride;
-  v4f acc[MTW][NTW];
-#pragma unroll
-  for (int mi = 0; mi < MTW; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < NTW; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int part_bit = c16 & 1;
-  for (int kk = k0; kk < k1; kk += 4) {
-    const int k = kk + q;
-    int pix = k < k1 ? (pr.idx ? pr.idx[k] : k) : 0;
-    const bool ok = k < k1 && (unsigned)pix < (unsigned)tab.Q;  // invalid index: term dropped
-    if (!ok) pix = 0;
-    const float val = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
-    const int il = pix % tab.nl, im = pix / tab.nl;
-    float am[MTW], bv[NTW];
-#pragma unroll
-    for (int mi = 0; mi < MTW; ++mi) {
-      const int mt = bm * MTW + mi;
-      float x = 0.f;
-      if (mt < MT) {
-        const float2 a = tab.a(8 * mt + (c16 >> 1), il, im);
-        x = part_bit ? a.y : a.x;
-      }
-      am[mi] = ok ? x * val : 0.f;
-    }
-#pragma unroll
-    for (int ni = 0; ni < NTW; ++ni) {
-      const int nt = bn * NTW + ni;
-      float x = 0.f;
-      if (nt < MT) {
-        const float2 a = tab.a(8 * nt + (c16 >> 1), il, im);
-        x = part_bit ? a.y : a.x;
-      }
-      bv[ni] = ok ? x : 0.f;
-    }
-#pragma unroll
-    for (int mi = 0; mi < MTW; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < NTW; ++ni) acc[mi][ni] = mfma16x16x4(am[mi], bv[ni], acc[mi][ni]);
+  int BM = 0, BN = blockIdx.y;  // the y-th block pair of (0,0), (1,0), (1,1), (2,0), ...
+  while (BN > BM) {
+    BN -= BM + 1;
+    ++BM;
   }
-#pragma unroll
-  for (int mi = 0; mi < MTW; ++mi) {
-    const int mt = bm * MTW + mi;
-#pragma unroll
-    for (int ni = 0; ni < NTW; ++ni) {
-      const int nt = bn * NTW + ni;
-      if (mt < MT && nt < MT) {
-        float4 o = make_float4(acc[mi][ni][0], acc[mi][ni][1], acc[mi][ni][2], acc[mi][ni][3]);
-        *reinterpret_cast<float4*>(part + (((size_t)chunk * MT + mt) * MT + nt) * 256 + lane * 4) = o;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Correlation, LDS-staged: G = X_S diag(v) X_S^T with the output split into
-// blocks of MTB x MTB tiles and only block pairs bm >= bn computed (G is
-// symmetric).  A workgroup takes chw pixels of the list for one block pair
-// and writes one partial of every tile of it.  Per 64 pixels it stages their
-// steering entries for the rows of both blocks in LDS (coalesced table
-// loads: consecutive threads take consecutive pixels of the list) and the
-// weights; its four waves then split the pair's tiles (the lower triangle of
-// a diagonal pair), each MFMA taking A = v x[rows of bm] and B = x[rows of bn]
-// from LDS.  A tile off the diagonal is also stored transposed, so the
-// partials hold every tile in the layout of forward_kernel.
-template <int MTB>
-__global__ __launch_bounds__(kThreads) void forward_lds_kernel(FwdParams pr) {
-  constexpr int KCH = 64;        // pixels staged at a time (one per thread of a wave)
-  constexpr int ROW = 16 * MTB;  // embedding rows of one block
-  // LDS row stride = 17 mod 32: the 16-column reads of consecutive pixels in a
-  // k step share at most one bank, and the staging stores (one row per lane)
-  // spread over the banks
-  constexpr int RS = ROW + ((17 - ROW % 32) + 32) % 32;
-  constexpr int TPW = (MTB * MTB + 3) / 4;  // tiles per wave (at most)
-  __shared__ float xm[KCH * RS];
-  __shared__ float xn[KCH * RS];
-  __shared__ float vs[KCH];
-  if (pr.stop_flag && *pr.stop_flag) return;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int c16 = lane & 15, q = lane >> 4;
-  const int MT = pr.MT;
-  int bm = 0, bn = blockIdx.y;  // the y-th pair of (0,0), (1,0), (1,1), (2,0), ...
-  while (bn > bm) {
-    bn -= bm + 1;
-    ++bm;
-  }
-  const bool diag = bm == bn;
-  const int ntt = diag ? MTB * (MTB + 1) / 2 : MTB * MTB;
-  const int chunk = blockIdx.x;
-  const int k0 = chunk * pr.chw;
-  const int k1 = min(k0 + pr.chw, pr.n);
+  const bool diag = BM == BN;
   Tables tab = pr.tab;
   tab.El += blockIdx.z * pr.tab_stride;
   tab.Em += blockIdx.z * pr.tab_stride;
-  float* part = pr.part + blockIdx.z * pr.part_stride;
-  int tmi[TPW], tni[TPW];  // this wave's tiles (local row / column tile; -1: none)
+  const int Pp = tab.Pp, nl = tab.nl, nm = tab.nm;
+  // this lane's antennas: rows 16 (BT BM + i) + c16, columns 16 (BT BN + j) + c16
+  int ar[BT], ac[BT];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    const int t = w + 4 * i;
-    int mi = -1, ni = -1;
-    if (t < ntt) {
-      if (diag) {
-        mi = 0;
-        while ((mi + 1) * (mi + 2) / 2 <= t) ++mi;
-        ni = t - mi * (mi + 1) / 2;
-      } else {
-        mi = t / MTB;
-        ni = t - mi * MTB;
-      }
-    }
-    tmi[i] = mi;
-    tni[i] = ni;
+  for (int i = 0; i < BT; ++i) {
+    ar[i] = 16 * (BT * BM + i) + c16;
+    ac[i] = 16 * (BT * BN + i) + c16;
   }
-  v4f acc[TPW];
+  const int k0 = blockIdx.x * pr.chw, k1 = min(k0 + pr.chw, pr.n);
+  v4f acc[NACC];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
-  const float* xb = diag ? xm : xn;
-  // the table entries of the next batch are loaded into registers while the
-  // current batch is multiplied: lane = pixel, wave w = antennas w, w + 4, ...
-  constexpr int JW = 2 * MTB;  // antennas of one block per wave
-  float2 elm[JW], emm[JW], eln[JW], emn[JW];
-  float nval = 0.f;
-  auto fetch = [&](int kb) {
-    const int kn = min(KCH, k1 - kb);
-    const bool live = lane < kn;
-    int pix = 0;
-    float val = 0.f;
-    if (live) {
-      const int k = kb + lane;
-      pix = pr.idx ? pr.idx[k] : k;
-      const bool ok = (unsigned)pix < (unsigned)tab.Q;  // invalid index: term dropped
-      if (!ok) pix = 0;
-      val = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
+  for (int a = 0; a < NACC; ++a) acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
+  // pixel of step s for this lane: k = k0 + 16 s + 4 w + q
+  auto pix_of = [&](int k, int& pix, float& v) {
+    pix = 0;
+    v = 0.f;
+    if (k < k1) {
+      int p = pr.idx ? pr.idx[k] : k;
+      const bool ok = (unsigned)p < (unsigned)tab.Q;  // invalid index: term dropped
+      pix = ok ? p : 0;
+      v = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
     }
-    nval = val;
-    const int il = pix % tab.nl, im = pix / tab.nl;
+  };
+  float2 elr[BT], emr[BT], elc[BT], emc[BT];
+  auto fetch = [&](int pix) {
+    const int im = pix / nl, il = pix - im * nl;
 #pragma unroll
-    for (int jj = 0; jj < JW; ++jj) {
-      const int j = w + 4 * jj;
-      const int pm = min(8 * MTB * bm + j, tab.Pp - 1), pn = min(8 * MTB * bn + j, tab.Pp - 1);
-      elm[jj] = tab.El[(size_t)pm * tab.nl + il];
-      emm[jj] = tab.Em[(size_t)pm * tab.nm + im];
+    for (int i = 0; i < BT; ++i) {
+      const bool okr = ar[i] < Pp, okc = ac[i] < Pp;
+      elr[i] = okr ? tab.El[(size_t)ar[i] * nl + il] : make_float2(0.f, 0.f);
+      emr[i] = okr ? tab.Em[(size_t)ar[i] * nm + im] : make_float2(0.f, 0.f);
       if (!diag) {
-        eln[jj] = tab.El[(size_t)pn * tab.nl + il];
-        emn[jj] = tab.Em[(size_t)pn * tab.nm + im];
+        elc[i] = okc ? tab.El[(size_t)ac[i] * nl + il] : make_float2(0.f, 0.f);
+        emc[i] = okc ? tab.Em[(size_t)ac[i] * nm + im] : make_float2(0.f, 0.f);
       }
     }
   };
-  if (k0 < k1) fetch(k0);
-  for (int kb = k0; kb < k1; kb += KCH) {
-    const int kn = min(KCH, k1 - kb);
-    __syncthreads();  // the previous pixels' operands have been read
-    {
-      const bool live = lane < kn;
-      if (w == 0) vs[lane] = nval;
+  int kk = k0 + 4 * w + q;
+  int pix;
+  float v;
+  pix_of(kk, pix, v);
+  fetch(pix);
+  for (int kb = k0 + 4 * w; kb < k1; kb += 16) {
+    float2 A[BT], C[BT];
 #pragma unroll
-      for (int jj = 0; jj < JW; ++jj) {
-        const int j = w + 4 * jj;
-        const bool okm = live && 8 * MTB * bm + j < tab.Pp, okn = live && 8 * MTB * bn + j < tab.Pp;
-        const float2 am = okm ? cmul(elm[jj], emm[jj]) : make_float2(0.f, 0.f);
-        xm[lane * RS + 2 * j] = am.x;  // odd row stride: two 4-byte stores
-        xm[lane * RS + 2 * j + 1] = am.y;
-        if (!diag) {
-          const float2 an = okn ? cmul(eln[jj], emn[jj]) : make_float2(0.f, 0.f);
-          xn[lane * RS + 2 * j] = an.x;
-          xn[lane * RS + 2 * j + 1] = an.y;
-        }
-      }
+    for (int i = 0; i < BT; ++i) {
+      A[i] = cmul(elr[i], emr[i]);
+      C[i] = diag ? A[i] : cmul(elc[i], emc[i]);
     }
-    __syncthreads();
-    if (kb + KCH < k1) fetch(kb + KCH);
-    for (int s = 0; s < kn; s += 4) {  // rows kn .. 63 are zero
-      const int r0 = (s + q) * RS + c16;
-      const float v = vs[s + q];
+    const float vc = v;
+    // the next step's pixel and table entries
+    kk += 16;
+    pix_of(kk, pix, v);
+    fetch(pix);
+    float br[BT], bi[BT], bn[BT];
 #pragma unroll
-      for (int i = 0; i < TPW; ++i)
-        if (tmi[i] >= 0)
-          acc[i] = mfma16x16x4(xm[r0 + 16 * tmi[i]] * v, xb[r0 + 16 * tni[i]], acc[i]);
+    for (int j = 0; j < BT; ++j) {
+      br[j] = vc * C[j].x;
+      bi[j] = vc * C[j].y;
+      bn[j] = -bi[j];
+    }
+#pragma unroll
+    for (int i = 0; i < BT; ++i)
+#pragma unroll
+      for (int j = 0; j < BT; ++j) {
+        if (diag && j > i) continue;  // upper tiles of a diagonal block: mirrors
+        v4f& re = acc[2 * (i * BT + j)];
+        v4f& im = acc[2 * (i * BT + j) + 1];
+        re = mfma16x16x4(A[i].x, br[j], re);
+        re = mfma16x16x4(A[i].y, bi[j], re);
+        im = mfma16x16x4(A[i].y, br[j], im);
+        im = mfma16x16x4(A[i].x, bn[j], im);
+      }
+  }
+  // the four waves' accumulators: (w0 + w2) + (w1 + w3)
+  if (w >= 2) {
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) red[w - 2][a][lane] = acc[a];
+  }
+  __syncthreads();
+  if (w < 2) {
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) {
+      const v4f o = red[w][a][lane];
+      acc[a] = v4f{acc[a][0] + o[0], acc[a][1] + o[1], acc[a][2] + o[2], acc[a][3] + o[3]};
     }
   }
+  __syncthreads();
+  if (w == 1) {
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    if (tmi[i] < 0) continue;
-    const int mt = MTB * bm + tmi[i], nt = MTB * bn + tni[i];
-    if (mt >= MT || nt >= MT) continue;
-    *reinterpret_cast<float4*>(part + (((size_t)chunk * MT + mt) * MT + nt) * 256 + lane * 4) =
-        make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
-    if (mt != nt) {  // G[16nt + c16][16mt + 4q + r]: lane 4q + r + 16 (c16 >> 2), element c16 & 3
-      float* tt = part + (((size_t)chunk * MT + nt) * MT + mt) * 256;
+    for (int a = 0; a < NACC; ++a) red[0][a][lane] = acc[a];
+  }
+  __syncthreads();
+  if (w == 0) {
+    float* part = pr.part + blockIdx.z * pr.part_stride +
+                  ((size_t)blockIdx.x * gridDim.y + blockIdx.y) * (size_t)(BT * BT * 512);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) tt[((4 * q + r) + 16 * (c16 >> 2)) * 4 + (c16 & 3)] = acc[i][r];
+    for (int a = 0; a < NACC; ++a) {
+      const v4f o = red[0][a][lane];
+      const float4 r = make_float4(acc[a][0] + o[0], acc[a][1] + o[1], acc[a][2] + o[2], acc[a][3] + o[3]);
+      // pair t = a / 2, component a & 1
+      *reinterpret_cast<float4*>(part + (size_t)(a >> 1) * 512 + (a & 1) * 256 + lane * 4) = r;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Second stage of the correlation: fixed-order sum of the wave partials, then
-//   out = cK * K + cB * B  (complex P x P), optional Ut fragments of `out`,
-//   optional per-block sum |out|^2.  cB may come from the LSQR state
-//   (-alpha/beta) when `lsqr` is set.  out may alias B.
-// One workgroup per output tile (blockIdx.x): its G waves (G = min(16,
-// chunks), the launch's choice) sum every G-th partial each, in order, and
-// the G sums are then added in wave order: a fixed summation order for a given
-// chunk count.  Wave 0 finishes the tile.
-constexpr int kRedGroups = 16;
-__global__ __launch_bounds__(64 * kRedGroups) void reduce_kernel(RedParams pr) {
-  __shared__ float4 sp[kRedGroups][64];
+// Second stage of the correlation: one workgroup per antenna tile pair
+// (bm >= bn) sums the chunks' partials in chunk order (each thread one entry,
+// a fixed order), then writes
+//   out = cK * Y + cB * B  (complex P x P; cB may come from the LSQR state,
+//   -alpha/beta), at (p, q) and, off the diagonal tile, at (q, p) with
+//   Y_qp = conj(Y_pq);
+// optionally the Ut fragments of out (interleaved embedding, layout of
+// common.h) and the workgroup's sum |out|^2 in norm_part[blockIdx.x].  out may
+// alias B.  Partials are read at the block pair and tile of the correlation.
+constexpr int kRedGroups = 4;  // thread groups summing interleaved chunks
+__global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) {
+  __shared__ double sh[4 * kRedGroups];
+  __shared__ float2 gsum[kRedGroups - 1][256];
   if (pr.stop_flag && *pr.stop_flag) return;
   {  // covariance block blockIdx.y
     const size_t kb = blockIdx.y;
@@ -649,73 +589,69 @@ __global__ __launch_bounds__(64 * kRedGroups) void reduce_kernel(RedParams pr) {
     if (pr.frag) pr.frag += kb * pr.frag_stride;
     if (pr.norm_part) pr.norm_part += kb * pr.norm_stride;
   }
-  const int MT = pr.MT, P = pr.P;
-  const int tile = blockIdx.x, lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int ng = blockDim.x >> 6;  // <= kRedGroups
-  const int mt = tile / MT, nt = tile - (tile / MT) * MT;
-  {
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int c = grp; c < pr.nchunks; c += ng) {
-      const float4 v =
-          *reinterpret_cast<const float4*>(pr.part + (((size_t)c * MT + mt) * MT + nt) * 256 + lane * 4);
-      s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
-    }
-    sp[grp][lane] = s;
+  const int P = pr.P, Pp = pad_p(P), BT = corr_bt(P), npairs = corr_pairs(P);
+  int bm = 0, bn = blockIdx.x;  // tile pair (bm >= bn)
+  while (bn > bm) {
+    bn -= bm + 1;
+    ++bm;
   }
+  const int BM = bm / BT, BN = bn / BT;
+  const int pair = BM * (BM + 1) / 2 + BN, tile = (bm - BT * BM) * BT + (bn - BT * BN);
+  const int t = threadIdx.x & 255, grp = threadIdx.x >> 8, lane = t >> 2, r = t & 3;
+  const int row = 4 * (lane >> 4) + r, col = lane & 15;
+  const int p = 16 * bm + row, qq = 16 * bn + col;
+  // group g sums chunks g, g + G, ...; the group sums are added in group order
+  float yr = 0.f, yi = 0.f;
+  for (int c = grp; c < pr.nchunks; c += kRedGroups) {
+    const float* src = pr.part + ((size_t)c * npairs + pair) * (size_t)(BT * BT * 512) + (size_t)tile * 512;
+    yr += src[t];
+    yi += src[256 + t];
+  }
+  if (grp > 0) gsum[grp - 1][t] = make_float2(yr, yi);
   __syncthreads();
-  if (grp != 0) return;
-  const bool live = true;
-  float4 s = sp[0][lane];
-  for (int g = 1; g < ng; ++g) {
-    const float4 v = sp[g][lane];
-    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+  if (grp == 0) {
+#pragma unroll
+    for (int g = 0; g < kRedGroups - 1; ++g) {
+      yr += gsum[g][t].x;
+      yi += gsum[g][t].y;
+    }
   }
-  float4 o;
-  o.x = __shfl_xor(s.x, 1, 64);
-  o.y = __shfl_xor(s.y, 1, 64);
-  o.z = __shfl_xor(s.z, 1, 64);
-  o.w = __shfl_xor(s.w, 1, 64);
   float cB = pr.cB;
   if (pr.lsqr) cB = (float)(-pr.lsqr->alpha / pr.lsqr->beta);
+  // group 0 writes; the diagonal tile: its lower triangle, mirrored
+  const bool lower = grp == 0 && (bm != bn || row >= col);
   double nrm = 0.0;
-  const int c16 = lane & 15, q = lane >> 4;
-  if (live && (c16 & 1) == 0) {
-    const int p0 = 8 * mt + 2 * q, qq = 8 * nt + (c16 >> 1);
-    const float2 K0 = make_float2(s.x + o.y, s.y - o.x);
-    const float2 K1 = make_float2(s.z + o.w, s.w - o.z);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int p = p0 + h;
-      const float2 K = h ? K1 : K0;
-      float2 r = make_float2(0.f, 0.f);
-      if (p < P && qq < P) {
-        r.x = pr.cK * K.x;
-        r.y = pr.cK * K.y;
-        if (pr.B) {
-          const float2 b = pr.B[p * P + qq];
-          r.x += cB * b.x;
-          r.y += cB * b.y;
-        }
-        pr.out[p * P + qq] = r;
-        nrm += (double)r.x * r.x + (double)r.y * r.y;
+  const int KS = pad_p(P) / 2;
+  auto put = [&](int a, int b, float2 y) {  // out[a][b] from Y_ab = y
+    float2 o = make_float2(0.f, 0.f);
+    if (a < P && b < P) {
+      o = make_float2(pr.cK * y.x, pr.cK * y.y);
+      if (pr.B) {
+        const float2 bv = pr.B[(size_t)a * P + b];
+        o.x += cB * bv.x;
+        o.y += cB * bv.y;
       }
-      if (pr.frag) {
-        const int KS = MT * 4;
-        // Ut[2p+s][2qq+u]
+      pr.out[(size_t)a * P + b] = o;
+      nrm += (double)o.x * o.x + (double)o.y * o.y;
+    }
+    if (pr.frag && a < Pp && b < Pp) {
 #pragma unroll
-        for (int su = 0; su < 4; ++su) {
-          const int s_ = su >> 1, u_ = su & 1;
-          const int row = 2 * p + s_, col = 2 * qq + u_;
-          const float v = (s_ == u_) ? r.x : (s_ == 0 ? -r.y : r.y);
-          const int fi = ((row >> 4) * KS + (col >> 2)) * 64 + (col & 3) * 16 + (row & 15);
-          pr.frag[fi] = v;
-        }
+      for (int su = 0; su < 4; ++su) {
+        const int s_ = su >> 1, u_ = su & 1;
+        const int rr = 2 * a + s_, cc = 2 * b + u_;
+        const float fv = (s_ == u_) ? o.x : (s_ == 0 ? -o.y : o.y);
+        pr.frag[((size_t)(rr >> 4) * KS + (cc >> 2)) * 64 + (cc & 3) * 16 + (rr & 15)] = fv;
       }
     }
+  };
+  if (lower) {
+    if (p == qq) yi = 0.f;  // the diagonal of a Hermitian matrix is real
+    put(p, qq, make_float2(yr, yi));
+    if (p != qq) put(qq, p, make_float2(yr, -yi));
   }
   if (pr.norm_part) {
-    const double tot = wave_sum_d(nrm);
-    if (lane == 0) pr.norm_part[blockIdx.x] = tot;
+    const double tot = block_sum_d(nrm, sh);
+    if (threadIdx.x == 0) pr.norm_part[blockIdx.x] = tot;
   }
 }
 
@@ -1086,23 +1022,31 @@ hipError_t launch_adjoint_epi(const AdjParams& pr, const Epi& epi, hipStream_t s
     hipLaunchKernelGGL(kern, dim3(grid, pr.blk_grid ? pr.nblk : 1), dim3(kThreads), 0, st, pr, epi);
     return hipGetLastError();
   };
-  if (pr.MT <= 3) return go(adjoint_kernel<3, 1, 1, Epi>, T = 64);
-  if (pr.MT <= 6) return go(adjoint_kernel<6, 1, 1, Epi>, T = 64);
-  if (pr.MT <= 12) return go(adjoint_kernel<12, 1, 1, Epi>, T = 64);
+  if (!pr.n_dev) {
+    if (pr.MT <= 3) return go(adjoint_kernel<3, 1, 1, Epi>, T = 64);
+    if (pr.MT <= 6) return go(adjoint_kernel<6, 1, 1, Epi>, T = 64);
+    if (pr.MT <= 12) return go(adjoint_kernel<12, 1, 1, Epi>, T = 64);
+  }
   const int ngroups = (pr.MT + 3) / 4;
-  if (pr.rows_part && pr.frag && !pr.U && !pr.xf && pr.nblk == 1 && (size_t)ngroups * pr.n <= pr.rows_cap) {
-    // rows split over workgroups, then the ordered sum and the epilogue on the
-    // same pixel tiles as adjoint_kernel
-    const int nt = pr.n <= 16 ? 1 : (pr.n <= 32 ? 2 : 4);
+  const int nt = pr.n <= 16 ? 1 : (pr.n <= 32 ? 2 : 4);
+  const int xt = (pr.n + 16 * nt - 1) / (16 * nt);
+  // K slices: about 256 workgroups in all, at least 16 chunks per slice
+  int ksl = (256 + xt * ngroups - 1) / (xt * ngroups);
+  ksl = std::max(1, std::min(ksl, std::min(8, pr.KS / 16)));
+  if (pr.rows_part && pr.frag && !pr.U && !pr.xf && pr.nblk == 1 &&
+      (size_t)ngroups * ksl * pr.n <= pr.rows_cap) {
+    // rows and K split over workgroups, then the ordered sum and the epilogue
+    // on the same pixel tiles as adjoint_kernel
     const int T_ = adjoint_tile_width(pr.MT);
-    const dim3 g1((pr.n + 16 * nt - 1) / (16 * nt), ngroups);
+    const dim3 g1(xt, ngroups, ksl);
     if (nt == 1) hipLaunchKernelGGL(adjoint_rows_kernel<1>, g1, dim3(kThreads), 0, st, pr, pr.rows_part);
     else if (nt == 2) hipLaunchKernelGGL(adjoint_rows_kernel<2>, g1, dim3(kThreads), 0, st, pr, pr.rows_part);
     else hipLaunchKernelGGL(adjoint_rows_kernel<4>, g1, dim3(kThreads), 0, st, pr, pr.rows_part);
     hipLaunchKernelGGL(adjoint_rows_finish_kernel<Epi>, dim3((pr.n + T_ - 1) / T_), dim3(64), 0, st, pr,
-                       (const float*)pr.rows_part, ngroups, T_, epi);
+                       (const float*)pr.rows_part, ngroups * ksl, T_, epi);
     return hipGetLastError();
   }
+  if (pr.n_dev) return hipErrorInvalidValue;  // a device-length list needs the row-split kernel
   if (pr.MT <= 24) return go(adjoint_kernel<6, 2, 4, Epi>, T = 32);
   return go(adjoint_kernel<9, 4, 4, Epi>, T = 64);
 }
@@ -1174,69 +1118,44 @@ hipError_t launch_adjoint_store_blocks(const AdjParams& pr, float* out, size_t s
   return launch_adjoint_epi(p, EpiStoreBlk{out, stride}, st);
 }
 
-int forward_lds_chunks_max(int P) {
-  const int MT = pad_p(P) / 8;
-  const int tw = MT <= 3 ? 3 : 6;
-  const int nb = (MT + tw - 1) / tw;
-  return std::max(1, 256 / (nb * (nb + 1) / 2));
+// Partials of the correlation: at most this many chunks (workgroups along
+// the list) per block pair.
+int forward_chunks_max(int P) {
+  return std::max(1, 2048 / corr_pairs(P));
 }
+size_t forward_part_floats(int P) { return (size_t)corr_pairs(P) * corr_bt(P) * corr_bt(P) * 512; }
 
-void forward_plan(int P, int n, int* chw, int* nchunks, int* nbm, bool splitk) {
-  const int MT = pad_p(P) / 8;
-  const int tw = MT <= 3 ? 3 : 6;
-  const int nb = (MT + tw - 1) / tw;
-  *nbm = nb;
-  if (!splitk) {  // LDS-staged: at least 16 pixels per workgroup, at most 256 workgroups over all block pairs
-    const int maxc = forward_lds_chunks_max(P);
-    int c = (n + maxc - 1) / maxc;
-    c = std::max(16, (c + 15) & ~15);
-    *chw = c;
-    *nchunks = n > 0 ? (n + c - 1) / c : 0;
-    return;
-  }
-  // about 512 waves in flight, at least 8 pixels per wave, at most 256 partials
-  int waves = 512 / (nb * nb);
-  if (waves < 1) waves = 1;
-  int c = (n + waves - 1) / waves;
-  c = (c + 3) & ~3;
-  if (c < 8) c = 8;
-  int nc = (n + c - 1) / c;
-  if (nc > 256) {
-    c = ((n + 255) / 256 + 3) & ~3;
-    nc = (n + c - 1) / c;
-  }
+// Up to about 2048 workgroups over all block pairs, at least 256 pixels
+// (16 k steps per wave) per workgroup unless the list is shorter: fewer,
+// longer chunks keep the partials (and the reduction's serial sums) small.
+void forward_plan(int P, int n, int* chw, int* nchunks) {
+  const int maxc = forward_chunks_max(P);
+  int c = (n + maxc - 1) / maxc;
+  c = std::max(std::min(256, (n + 15) & ~15), (c + 15) & ~15);
+  c = std::max(16, c);
   *chw = c;
-  *nchunks = n > 0 ? nc : 0;
+  *nchunks = n > 0 ? (n + c - 1) / c : 0;
 }
 
 hipError_t launch_forward(const FwdParams& pr, hipStream_t st) {
   if (pr.n <= 0) return hipSuccess;
+  const int P = pr.tab.Pp;  // corr_* depend on Pp only
   const int nchunks = (pr.n + pr.chw - 1) / pr.chw;
-  if (!pr.splitk) {
-    const dim3 grid(nchunks, pr.nbm * (pr.nbm + 1) / 2, pr.nblk);
-    if (pr.MT <= 3)
-      hipLaunchKernelGGL(forward_lds_kernel<3>, grid, dim3(kThreads), 0, st, pr);
-    else
-      hipLaunchKernelGGL(forward_lds_kernel<6>, grid, dim3(kThreads), 0, st, pr);
-    return hipGetLastError();
-  }
-  dim3 grid((nchunks + 3) / 4, pr.nbm * pr.nbn, pr.nblk);
-  if (pr.MT <= 3)
-    hipLaunchKernelGGL((forward_kernel<3, 3>), grid, dim3(kThreads), 0, st, pr);
+  const dim3 grid(nchunks, corr_pairs(P), pr.nblk);
+  if (corr_bt(P) == 2)
+    hipLaunchKernelGGL(corr_kernel<2>, grid, dim3(kThreads), 0, st, pr);
   else
-    hipLaunchKernelGGL((forward_kernel<6, 6>), grid, dim3(kThreads), 0, st, pr);
+    hipLaunchKernelGGL(corr_kernel<3>, grid, dim3(kThreads), 0, st, pr);
   return hipGetLastError();
 }
 
 int reduce_blocks(int P) {
-  const int MT = pad_p(P) / 8;
-  return MT * MT;  // one workgroup (and one norm partial) per tile
+  const int na = corr_tiles(P);
+  return na * (na + 1) / 2;  // one workgroup (and one norm partial) per antenna tile pair
 }
 
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st) {
-  const int blocks = reduce_blocks(pr.P);
-  const int ng = std::min(kRedGroups, std::max(1, pr.nchunks));
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks, pr.nblk), dim3(64 * ng), 0, st, pr);
+  hipLaunchKernelGGL(reduce_kernel, dim3(reduce_blocks(pr.P), pr.nblk), dim3(256 * kRedGroups), 0, st, pr);
   return hipGetLastError();
 }
 

@@ -337,13 +337,22 @@ __global__ __launch_bounds__(kCtl) void step_kernel(const int* done, const int* 
 }
 
 // ---------------------------------------------------------------------------
+// cand_count / cand_cap (optional): the refined multipliers' candidate list;
+// if it overflowed, the decision is left open (grad_done stays 0,
+// cand_overflow = 1) for a full FP32 evaluation.
 __global__ __launch_bounds__(kCtl) void argmin_final_kernel(const uint64_t* __restrict__ part,
                                                             int nparts,
                                                             const float* __restrict__ eps,
                                                             const uint8_t* __restrict__ state,
-                                                            SolveDecision* dec) {
+                                                            SolveDecision* dec, const int* cand_count,
+                                                            int cand_cap) {
   __shared__ uint64_t sh[kCtl / 64];
   if (dec->grad_done) return;
+  if (cand_count) {
+    const int over = *cand_count > cand_cap;
+    if (threadIdx.x == 0) dec->cand_overflow = over;
+    if (over) return;
+  }
   uint64_t m = ~0ull;
   for (int i = threadIdx.x; i < nparts; i += kCtl) m = part[i] < m ? part[i] : m;
   m = block_min_u64(m, sh);
@@ -440,8 +449,9 @@ hipError_t launch_step(const int* done, const int* err, const LsqrState* s, cons
 }
 
 hipError_t launch_argmin_final(const uint64_t* part, int nparts, const float* eps,
-                               const uint8_t* state, SolveDecision* dec, hipStream_t st) {
-  hipLaunchKernelGGL(argmin_final_kernel, dim3(1), dim3(kCtl), 0, st, part, nparts, eps, state, dec);
+                               const uint8_t* state, SolveDecision* dec, hipStream_t st, const int* cand_count, int cand_cap) {
+  hipLaunchKernelGGL(argmin_final_kernel, dim3(1), dim3(kCtl), 0, st, part, nparts, eps, state, dec, cand_count,
+                     cand_cap);
   return hipGetLastError();
 }
 

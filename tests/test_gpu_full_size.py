@@ -6,7 +6,9 @@ oracle computes only sampled outputs there (pixels drawn with a fixed seed,
 always including the first and the last pixel), each from its own steering
 vector in FP64; the forward product is checked entry by entry over a pixel
 subset.  For the 96-antenna workload the whole active-set solve is also run
-against the oracle (about half a minute of FP64 on the host).
+against the oracle (about half a minute of FP64 on the host), and for the
+288-antenna workload its first ten Table I steps; both in FP32 and with the
+FP16 / BF16 contractions.
 
 Tolerances as in test_gpu_parity: normwise 1e-5 and every entry within 1e-5
 of the peak (the covariances here are well conditioned, cond(R) ~ 11, so
@@ -104,49 +106,73 @@ def test_full_size_forward_and_adjoint(gpu_lib, ctx, big, name):
                   what=f"{name} adjoint (sampled)")
 
 
-def test_solve_96_antennas_matches_oracle(gpu_lib, ctx, big):
+@pytest.fixture(scope="module")
+def oracle_c2(big):
     sc = big["c2"]
-    print("case solve c2 (P=96, Q=65536) against the oracle", flush=True)
     A = oracle.steering(sc.pos, sc.lam, sc.grid)
     R = sc.R_hat32_c128
     mf = oracle.mf_image(A, R)
     gamma = oracle.upper_bound(A, R)
     eps = oracle.detection_threshold(mf, 6.0, sc.N)
     nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
-    ref = oracle.solve(A, R - np.diag(nd), gamma, eps, atol=1e-8, btol=1e-8)
-    del A
-    opts = gpu_lib.default_options()
-    opts.nsamples = sc.N
-    opts.atol = opts.btol = 1e-7
-    sigma, state, _, _, stats = ctx.solve(torch.as_tensor(sc.R_hat32).cuda(),
-                                          gpu_lib.Geometry(sc.pos, sc.lam, sc.grid), opts,
-                                          noise_diag=torch.as_tensor(nd.astype(np.float32)).cuda())
-    print("gpu stats", stats, "oracle outer", ref.outer_iters, flush=True)
-    np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
-    _assert_close(sigma.cpu().numpy(), ref.sigma, what="solve sigma c2")
+    return oracle.solve(A, R - np.diag(nd), gamma, eps, atol=1e-8, btol=1e-8)
 
 
-def test_solve_288_antennas_first_ten_steps(gpu_lib, ctx, big):
+@pytest.fixture(scope="module")
+def oracle_c4_ten(big):
     # the full 288-antenna solve takes about a thousand Table I steps (each a
     # 174 GFLOP gradient in FP64 on the host); the state after the first ten
     # is compared instead, at full size
     sc = big["c4"]
-    print("case solve c4 (P=288, Q=512^2), first 10 Table I steps, against the oracle", flush=True)
     A = oracle.steering(sc.pos, sc.lam, sc.grid)
     R = sc.R_hat32_c128
     nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
-    ref = oracle.solve(A, R - np.diag(nd), oracle.upper_bound(A, R),
-                       oracle.detection_threshold(oracle.mf_image(A, R), 6.0, sc.N),
-                       atol=1e-8, btol=1e-8, max_outer=10)
-    del A
+    return oracle.solve(A, R - np.diag(nd), oracle.upper_bound(A, R),
+                        oracle.detection_threshold(oracle.mf_image(A, R), 6.0, sc.N),
+                        atol=1e-8, btol=1e-8, max_outer=10)
+
+
+# FP32: the FP32 bar; FP16 / BF16 (reduced-precision contractions with FP32
+# refinement): the reduced-precision bar, and the same sets
+BAR = {0: 1e-5, 1: 1e-3, 2: 1e-3}
+PNAME = {0: "fp32", 1: "fp16", 2: "bf16"}
+
+
+def _solve(gpu_lib, ctx, sc, prec, max_outer=-1):
     opts = gpu_lib.default_options()
     opts.nsamples = sc.N
     opts.atol = opts.btol = 1e-7
-    opts.max_outer = 10
-    sigma, state, _, _, stats = ctx.solve(torch.as_tensor(sc.R_hat32).cuda(),
-                                          gpu_lib.Geometry(sc.pos, sc.lam, sc.grid), opts,
-                                          noise_diag=torch.as_tensor(nd.astype(np.float32)).cuda())
-    print("gpu stats", stats, "oracle outer", ref.outer_iters, "adds", ref.adds, flush=True)
+    opts.precision = prec
+    opts.max_outer = max_outer
+    nd = np.asarray(sc.noise_diag, np.float32)
+    return ctx.solve(torch.as_tensor(sc.R_hat32).cuda(), gpu_lib.Geometry(sc.pos, sc.lam, sc.grid), opts,
+                     noise_diag=torch.as_tensor(nd).cuda())
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_solve_96_antennas_matches_oracle(gpu_lib, ctx, big, oracle_c2, prec):
+    sc = big["c2"]
+    print(f"case solve c2 (P=96, Q=65536) {PNAME[prec]} against the oracle", flush=True)
+    ref = oracle_c2
+    sigma, state, _, _, stats = _solve(gpu_lib, ctx, sc, prec)
+    rel = _rel(sigma.cpu().numpy(), ref.sigma)
+    print(f"gpu stats {stats}; oracle outer {ref.outer_iters}; image error {rel:.3e}; residual "
+          f"{stats['rel_residual']:.9f} / {ref.rel_residual:.9f}", flush=True)
+    np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
+    _assert_close(sigma.cpu().numpy(), ref.sigma, tol=BAR[prec], what=f"solve sigma c2 {PNAME[prec]}")
+    assert abs(stats["rel_residual"] - ref.rel_residual) <= 1e-3 * ref.rel_residual
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_solve_288_antennas_first_ten_steps(gpu_lib, ctx, big, oracle_c4_ten, prec):
+    sc = big["c4"]
+    print(f"case solve c4 (P=288, Q=512^2) {PNAME[prec]}, first 10 Table I steps, against the oracle", flush=True)
+    ref = oracle_c4_ten
+    sigma, state, _, _, stats = _solve(gpu_lib, ctx, sc, prec, max_outer=10)
+    rel = _rel(sigma.cpu().numpy(), ref.sigma)
+    print(f"gpu stats {stats}; oracle outer {ref.outer_iters} adds {ref.adds}; image error {rel:.3e}; residual "
+          f"{stats['rel_residual']:.9f} / {ref.rel_residual:.9f}", flush=True)
     assert stats["status"] == gpu_lib.WMAXOUTER and stats["outer_iters"] == ref.outer_iters == 10
     np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
-    _assert_close(sigma.cpu().numpy(), ref.sigma, what="solve sigma c4, 10 steps")
+    _assert_close(sigma.cpu().numpy(), ref.sigma, tol=BAR[prec], what=f"solve sigma c4 {PNAME[prec]}, 10 steps")
+    assert abs(stats["rel_residual"] - ref.rel_residual) <= 1e-3 * ref.rel_residual

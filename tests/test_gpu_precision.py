@@ -186,3 +186,31 @@ def test_autotune_rejects(gpu_lib, ctx):
         with pytest.raises(gpu_lib.ClsimgError) as ei:
             ctx.set_beam_tiles(P, 0, tiles)
         assert ei.value.status == gpu_lib.EINVAL
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("P,n", [(64, 48), (104, 40), (150, 32)])
+def test_refined_multipliers_solve_matches_oracle(gpu_lib, ctx, P, n, prec):
+    # host-driven loop with half-precision multipliers: the single half
+    # product lists the candidates its rounding bound leaves, FP32 decides
+    # among them (or, when more than Q/8 are left, FP32 evaluates every pixel
+    # of that step): the decisions are the FP32 ones, so the sets are the
+    # oracle's and the image meets the FP32 bar
+    sc = synth.make_scene("c2", P=P, n=n, seed=300 + P, points=(15, ("powerlaw", 0.5, 500.0)))
+    print(f"case refined multipliers {NAME[prec]} P={sc.P} Q={sc.Q}", flush=True)
+    A = oracle.steering(sc.pos, sc.lam, sc.grid)
+    R = sc.R_hat32_c128
+    nd = sc.noise_diag.astype(np.float32).astype(np.float64)
+    ref = oracle.solve(A, R - np.diag(nd), oracle.upper_bound(A, R),
+                       oracle.detection_threshold(oracle.mf_image(A, R), 6.0, sc.N), atol=1e-8, btol=1e-8)
+    o = gpu_lib.default_options()
+    o.nsamples = sc.N
+    o.atol = o.btol = 1e-7
+    o.precision = prec
+    sigma, state, _, _, stats = ctx.solve(torch.as_tensor(sc.R_hat32).cuda(), _geo(gpu_lib, sc), o,
+                                          noise_diag=torch.as_tensor(nd.astype(np.float32)).cuda())
+    err = _rel(sigma.cpu().numpy(), ref.sigma)
+    print(f"  steps {stats['outer_iters']} / {ref.outer_iters}; image error {err:.3e}", flush=True)
+    np.testing.assert_array_equal(state.cpu().numpy(), ref.state)
+    assert err <= 1e-5
+    assert stats["adds"] == ref.adds and stats["drops"] == ref.drops

@@ -159,6 +159,23 @@ int clsimg_dirty_image_timed(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_
                              const clsimg_grid* grid, int32_t precision, float* mf, void* start_event,
                              void* stop_event, void* stream);
 
+/* The dirty image of clsimg_dirty_image (same kernels, same bits) without
+ * any allocation, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Its workspace (antenna positions, steering tables, fragments of R: at most
+ * 8 MiB) is a static array of the library that every GPU holds once, until
+ * the process ends; ctx (created beforehand, outside the caller's
+ * allocation-free region) holds this device's address of it.  The call
+ * allocates nothing and does not touch the context's own workspace; the
+ * positions are copied from host memory on `stream`.  Calls on one GPU share
+ * that array: calls that overlap on one GPU (other streams, other contexts
+ * or threads) race and must be ordered by the caller.  Arguments as
+ * clsimg_dirty_image; CLSIMG_ENOMEM when the geometry needs more than the
+ * 8 MiB (steering tables of Pp (nl + nm) entries, Pp = P rounded up to a
+ * multiple of 8, plus the fragments of R beyond 48 antennas). */
+int clsimg_dirty_image_noalloc(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array,
+                               const clsimg_grid* grid, int32_t precision, float* mf, void* stream);
+
 /* Autotuner of the GEMM-shaped full-grid beamformers (the dirty image, bound
  * and multipliers for P > 48 in FP32, and for every P in split FP16 / BF16):
  * times one dirty image of this array and grid for each candidate number of

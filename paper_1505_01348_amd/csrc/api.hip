@@ -85,6 +85,7 @@ struct clsimg_ctx {
   DevBuf frag_h, hscale;   // half-precision fragments and their scale
   DevBuf mx_abs, mx_lam, mx_cand, mx_count;  // refined multipliers: |W| partials, lam~, candidates
   int outer_max_f = 1 << 30;  // CLSIMG_OUTER_MAXF: hand over to the host loop beyond this |F|
+  void* scratch = nullptr;    // this device's copy of the static workspace (allocation-free calls)
 };
 
 namespace {
@@ -640,6 +641,17 @@ int request_finish(clsimg_request& q, const clsimg_opts* o, char* slice, const R
 
 }  // namespace clsimg
 
+namespace {
+
+// Static workspace of the allocation-free dirty image: every GPU the library
+// runs on holds one copy until the process ends.  Host code never uses the
+// array's name as an address: clsimg_create resolves this device's copy with
+// hipGetSymbolAddress and keeps it in the context.
+constexpr size_t kNoAllocBytes = (size_t)8 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+}  // namespace
+
 extern "C" {
 
 void clsimg_default_opts(clsimg_opts* o) {
@@ -701,6 +713,15 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   c->h_norms = reinterpret_cast<double*>(b + sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int));
   c->h_outer = reinterpret_cast<OuterState*>(b + sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) +
                                              nnorm * sizeof(double));
+  // this device's copy of the static workspace (the device is current here)
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+    (void)hipHostFree(hp);
+    (void)hipEventDestroy(c->stage_done);
+    delete c;
+    return CLSIMG_EHIP;
+  }
+  c->scratch = sp;
   *out = c;
   return CLSIMG_OK;
 }
@@ -844,6 +865,61 @@ int clsimg_dirty_image_timed(clsimg_ctx* c, const clsimg_c32* R, const clsimg_ar
   ST_TRY(ensure_tables(c, a, g, st));
   const Stamps ts{(hipEvent_t)start_event, (hipEvent_t)stop_event};
   return beam_full(c, g, P, reinterpret_cast<const float2*>(R), BEAM_MF, mf, nullptr, 0.f, 0, 0, 1.f, st, ts);
+}
+
+int clsimg_dirty_image_noalloc(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
+                               int32_t precision, float* mf, void* stream) {
+  if (!c || !R || !mf || !c->scratch) return CLSIMG_EINVAL;
+  ST_TRY(check_geometry(a, g));
+  if (precision != CLSIMG_FP32 && precision != CLSIMG_FP16 && precision != CLSIMG_BF16) return CLSIMG_EINVAL;
+  const int P = a->P, Pp = pad_p(P), Q = g->nl * g->nm;
+  if (!beam_any(P)) return CLSIMG_ENOTSUP;
+  // workspace layout: positions | El | Em | fragments | FP16 scale
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t o_pos = take((size_t)2 * P * sizeof(double));
+  const size_t o_el = take((size_t)Pp * g->nl * sizeof(float2));
+  const size_t o_em = take((size_t)Pp * g->nm * sizeof(float2));
+  size_t fb = 0;
+  if (precision != CLSIMG_FP32) fb = beam_h16_frag_bytes(P);
+  else if (!beam_fits(P)) fb = beam_big_frag_floats(P) * sizeof(float);
+  const size_t o_fr = take(fb), o_sc = take(sizeof(float));
+  if (off > kNoAllocBytes) return CLSIMG_ENOMEM;
+  c->prec = precision;
+  DeviceGuard guard(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char* base = static_cast<unsigned char*>(c->scratch);
+  double* pos = reinterpret_cast<double*>(base + o_pos);
+  Tables tab;
+  tab.El = reinterpret_cast<const float2*>(base + o_el);
+  tab.Em = reinterpret_cast<const float2*>(base + o_em);
+  tab.nl = g->nl;
+  tab.nm = g->nm;
+  tab.Pp = Pp;
+  tab.Q = Q;
+  HIP_TRY(hipMemcpyAsync(pos, a->pos_xy, (size_t)2 * P * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_tables(pos, P, a->lambda, g->nl, g->nm, g->l0, g->dl, g->m0, g->dm,
+                        reinterpret_cast<float2*>(base + o_el), reinterpret_cast<float2*>(base + o_em), st));
+  const float2* Rf = reinterpret_cast<const float2*>(R);
+  if (precision != CLSIMG_FP32) {
+    const bool bf = precision == CLSIMG_BF16;
+    float* sc = reinterpret_cast<float*>(base + o_sc);
+    HIP_TRY(launch_beam_prep_h16(Rf, P, bf, base + o_fr, sc, st));
+    HIP_TRY(launch_beam_h16(0, bf, base + o_fr, sc, tab, nullptr, mf, nullptr, 0.f, 0, 0, 1.f, nullptr, nullptr, st,
+                            {}, big_tiles(c, P)));
+  } else if (!beam_fits(P)) {
+    float* fr = reinterpret_cast<float*>(base + o_fr);
+    HIP_TRY(launch_beam_prep_full(Rf, P, fr, st));
+    HIP_TRY(launch_beam_big(0, fr, tab, nullptr, mf, nullptr, 0.f, 0, 0, 1.f, nullptr, nullptr, st, {},
+                            big_tiles(c, P)));
+  } else {
+    HIP_TRY(launch_beam_mf(nullptr, Rf, P, tab, mf, nullptr, 0.f, st));
+  }
+  return CLSIMG_OK;
 }
 
 int clsimg_mvdr_bound(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a,

@@ -488,7 +488,7 @@ def parity_of(sigma, state, ref):
             "oracle_rel_residual": ref.rel_residual}
 
 
-def time_solves(ctx, R, geo, opts, nd, steps, warmup, torch, what):
+def time_solves(ctx, R, geo, opts, nd, steps, warmup, torch, what, on_timed_start=None):
     """warmup + timed clsimg_solve calls; every call ends with a synchronisation."""
     Q = geo.Q
     sigma = torch.empty(Q, dtype=torch.float32, device="cuda")
@@ -500,6 +500,8 @@ def time_solves(ctx, R, geo, opts, nd, steps, warmup, torch, what):
         log(f"bench: {what}: warmup {i + 1}/{warmup}")
     lat, flops = [], 0.0
     torch.cuda.synchronize()
+    if on_timed_start is not None:
+        on_timed_start()
     t_start = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
@@ -523,6 +525,16 @@ def beam_executed_flops(P, Q, tiles):
     # block triangle: row tile m runs column tiles 0..m (4 chunks each), over
     # whole workgroups of `tiles` 16-pixel tiles
     return (-(-Q // (16 * tiles)) * tiles) * 2 * MT * (MT + 1) * 2048.0
+
+
+def h1_executed_flops(P, Q):
+    """MFMA flops of the single half-precision multiplier kernel: row tile m of
+    the block triangle runs 32-column chunks 0 .. m // 2, one 16x16x32 MFMA
+    (16384 flops) per chunk and 16-pixel tile, over workgroups of 4 tiles."""
+    MT = -(-P // 8)
+    KC = -(-2 * (-(-P // 8) * 8) // 32)
+    per_tile = sum(min(KC, m // 2 + 1) for m in range(MT))
+    return (-(-Q // 64) * 4) * per_tile * 16384.0
 
 
 def forward_executed_flops(P, Q):
@@ -740,7 +752,10 @@ def full_grid_ops(ctx, clsimg, np, torch, sc, reps=20):
                    "frac_dense_count": round(dense / t / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
                    "executed_flops_per_launch": ex}
         else:
-            ex = 3 * 2.0 * (2 * Pp) ** 2 * (-(-Q // (16 * tiles)) * 16 * tiles)
+            # three products on the block triangle (chunks 0 .. m // 2 of row tile m)
+            MT = Pp // 8
+            KC = -(-2 * Pp // 32)
+            ex = 3.0 * (-(-Q // (16 * tiles)) * tiles) * sum(min(KC, m // 2 + 1) for m in range(MT)) * 16384.0
             rec = {"kernel": f"beam_h16_kernel (split {name}: three 16x16x32 products)",
                    "us_per_launch": round(t * 1e6, 2), "dense_tflops": round(dense / t / 1e12, 3),
                    "executed_tflops": round(ex / t / 1e12, 3), "peak": PEAK_HALF_MFMA_TFLOPS,
@@ -780,7 +795,12 @@ def headline_bench(args, clsimg, synth, np, torch):
     ctx = clsimg.Context(0)
     if prec != 0:
         ctx.autotune(geo, precision=prec)
-    run = time_solves(ctx, R, geo, opts, nd, steps, warmup, torch, f"c4 first 10 steps, {args.precision}")
+    # the multiplier kernel of every feasible step (the steps' dominant kernel)
+    # is timed with HIP events bound to its launches inside the timed solves
+    ctx.kernel_timing(False)
+    run = time_solves(ctx, R, geo, opts, nd, steps, warmup, torch, f"c4 first 10 steps, {args.precision}",
+                      on_timed_start=lambda: ctx.kernel_timing(True))
+    mult_ms, mult_n = ctx.kernel_timing(False)
     total, stats = run["total"], run["stats"]
     lat_ms = np.array(run["lat"]) * 1e3
     plain = None
@@ -807,23 +827,29 @@ def headline_bench(args, clsimg, synth, np, torch):
     # gradient (the same GEMM as the dirty image and the bound), timed on the
     # dirty image with the device's own timestamps of its launches
     full4 = full_grid_ops(ctx, clsimg, np, torch, sc)
-    key = args.precision
-    bf = full4["beamformer"][key]
+    dense_beam = 8.0 * sc.P * sc.P * sc.Q + 8.0 * sc.P * sc.Q
+    t_mult = mult_ms / 1e3 / max(mult_n, 1)
     if prec == 0:
-        roof = {"kernel": "beam_big_kernel<9, 4, *> (full-grid beamformer: gradient, dirty image, bound)",
-                "bound": "mfma", "achieved": bf["executed_tflops"], "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": bf["frac"], "frac_dense_count": bf["frac_dense_count"],
-                "traffic": traffic_from("beam_big_kernel_c4_traffic.md", "beam_big_kernel<9, 4, BeamMF>", "beam.hip"),
-                "us_per_launch": bf["us_per_launch"], "executed_flops_per_launch": bf["executed_flops_per_launch"],
-                "dense_flops_per_launch": 8.0 * sc.P * sc.P * sc.Q + 8.0 * sc.P * sc.Q,
-                "timing": "device timestamps bound to the launch (clsimg_dirty_image_timed), mean of 20"}
+        ex = beam_executed_flops(sc.P, sc.Q, 4)
+        roof = {"kernel": "beam_big_kernel<9, 4, BeamLambda> (multipliers of each feasible step: the full-grid "
+                          "gradient, eq. gls)", "bound": "mfma", "peak": PEAK_FP32_MFMA_TFLOPS,
+                "traffic": traffic_from("beam_big_kernel_c4_traffic.md", "beam_big_kernel<9, 4, BeamMF>", "beam.hip")}
+        peak = PEAK_FP32_MFMA_TFLOPS
     else:
-        roof = {"kernel": bf["kernel"], "bound": "mfma", "achieved": bf["executed_tflops"],
-                "peak": PEAK_HALF_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": bf["frac"], "traffic": None,
-                "us_per_launch": bf["us_per_launch"], "executed_flops_per_launch": bf["executed_flops_per_launch"],
-                "timing": "device timestamps bound to the launch (clsimg_dirty_image_timed), mean of 20",
-                "note": "the split beamformer of the dirty image and bound; the steps' multipliers run the "
-                        "single-product kernel (beam_h1_kernel), timed in profiles/"}
+        ex = h1_executed_flops(sc.P, sc.Q)
+        roof = {"kernel": f"beam_h1_kernel<9, {args.precision}, BeamLambdaApprox> (multipliers of each feasible "
+                          "step: one half-precision product, decision refined in FP32)", "bound": "mfma",
+                "peak": PEAK_HALF_MFMA_TFLOPS,
+                "traffic": traffic_from("beam_h1_kernel_c4_traffic.md", "beam_h1_kernel<9, fp16, BeamLambdaApprox>",
+                                        "beam.hip")}
+        peak = PEAK_HALF_MFMA_TFLOPS
+    roof.update({"achieved": round(ex / t_mult / 1e12, 4), "unit": "TFLOP/s",
+                 "frac": round(ex / t_mult / 1e12 / peak, 5),
+                 "frac_dense_count": round(dense_beam / t_mult / 1e12 / peak, 5),
+                 "us_per_launch": round(t_mult * 1e6, 3), "launches_timed": mult_n,
+                 "executed_flops_per_launch": ex, "dense_flops_per_launch": dense_beam,
+                 "timing": "HIP events bound to every launch of the kernel inside the timed solves "
+                           "(clsimg_kernel_timing), mean"})
 
     psi_tflops = run["flops"] / total / 1e12
     model, ncores = cpu_info()

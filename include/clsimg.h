@@ -198,6 +198,16 @@ int clsimg_autotune(clsimg_ctx* ctx, const clsimg_array* array, const clsimg_gri
  * other values. */
 int clsimg_set_beam_tiles(clsimg_ctx* ctx, int32_t P, int32_t precision, int32_t tiles);
 
+/* Device time of the full-grid multiplier kernel of the host-driven active-set
+ * loop (the gradient of every feasible Table I step, eq. gls: beam_big_kernel
+ * in FP32, the single half-precision product beam_h1_kernel with FP16 / BF16),
+ * for measurement: while enabled, clsimg_solve binds two HIP events to each
+ * such launch and adds their elapsed time after the step's read-back.  Writes
+ * the milliseconds and launch count accumulated since the previous call
+ * (host pointers, may be null), resets them, and sets the mode (enable != 0)
+ * for later solves.  The device-resident loop (P <= 48) is not timed. */
+int clsimg_kernel_timing(clsimg_ctx* ctx, int32_t enable, double* ms, int32_t* launches);
+
 /* Upper bound gamma of the box constraint (eq. CLS):
  *   MVDR (eq. wmvdr, Sec. II-D): h_i = a_i^H R^-1 a_i with R = L L^H factored in
  *        FP64 on the device; gamma_i = C/h_i + kappa_b / (h_i sqrt(N-P-1));

@@ -27,7 +27,7 @@ STATE_L, STATE_F, STATE_U = 0, 1, 2
 MAX_P = 288
 
 EXPORTED = ("clsimg_default_opts", "clsimg_create", "clsimg_destroy", "clsimg_dirty_image",
-            "clsimg_dirty_image_timed", "clsimg_dirty_image_noalloc", "clsimg_autotune", "clsimg_set_beam_tiles", "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
+            "clsimg_dirty_image_timed", "clsimg_dirty_image_noalloc", "clsimg_kernel_timing", "clsimg_autotune", "clsimg_set_beam_tiles", "clsimg_mvdr_bound", "clsimg_forward", "clsimg_adjoint", "clsimg_solve",
             "clsimg_solve_batch", "clsimg_solve_multi", "clsimg_solve_offgrid", "clsimg_server_create", "clsimg_server_submit", "clsimg_server_poll",
             "clsimg_server_query", "clsimg_server_destroy", "clsimg_strerror")
 
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.clsimg_dirty_image.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp]
     lib.clsimg_dirty_image_timed.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp, vp, vp]
     lib.clsimg_dirty_image_noalloc.argtypes = [vp, vp, C.POINTER(CArray), C.POINTER(CGrid), i32, vp, vp]
+    lib.clsimg_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i32)]
     lib.clsimg_autotune.argtypes = [vp, C.POINTER(CArray), C.POINTER(CGrid), i32, C.POINTER(i32),
                                     C.POINTER(C.c_float), vp]
     lib.clsimg_set_beam_tiles.argtypes = [vp, i32, i32, i32]
@@ -247,6 +248,14 @@ class Context:
                                                  C.byref(geo.c_grid), int(precision), _ptr(mf), _stream()),
                     "clsimg_dirty_image")
         return mf
+
+    def kernel_timing(self, enable: bool):
+        """clsimg_kernel_timing: (ms, launches) of the multiplier kernel accumulated
+        since the previous call; `enable` sets the mode for later solves."""
+        ms, n = C.c_double(), C.c_int32()
+        self._check(self._lib.clsimg_kernel_timing(self._h, int(bool(enable)), C.byref(ms), C.byref(n)),
+                    "clsimg_kernel_timing")
+        return ms.value, n.value
 
     def dirty_image_noalloc(self, R, geo: Geometry, mf, precision: int = FP32):
         """clsimg_dirty_image_noalloc: the dirty image into the caller's `mf`

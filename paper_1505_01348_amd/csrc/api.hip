@@ -86,6 +86,11 @@ struct clsimg_ctx {
   DevBuf mx_abs, mx_lam, mx_cand, mx_count;  // refined multipliers: |W| partials, lam~, candidates
   int outer_max_f = 1 << 30;  // CLSIMG_OUTER_MAXF: hand over to the host loop beyond this |F|
   void* scratch = nullptr;    // this device's copy of the static workspace (allocation-free calls)
+  // device time of the host-driven loop's multiplier kernel (clsimg_kernel_timing)
+  bool time_mult = false;
+  hipEvent_t tm_ev[2] = {nullptr, nullptr};
+  double tm_ms = 0.0;
+  int tm_n = 0;
 };
 
 namespace {
@@ -746,6 +751,8 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (c->h_batch) (void)hipHostFree(c->h_batch);
   if (c->h_mnorm) (void)hipHostFree(c->h_mnorm);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  for (hipEvent_t e : c->tm_ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
   return CLSIMG_OK;
 }
@@ -788,6 +795,20 @@ int clsimg_set_beam_tiles(clsimg_ctx* c, int32_t P, int32_t precision, int32_t t
   if (tiles != 0 && tiles != 2 && tiles != 4 && !(tiles == 8 && (pad_p(P) / 8 + 3) / 4 <= 6)) return CLSIMG_EINVAL;
   const int pr = precision == CLSIMG_FP16 ? 1 : (precision == CLSIMG_BF16 ? 2 : 0);
   c->tuned_nt[pr][(pad_p(P) / 8 + 3) / 4] = tiles;
+  return CLSIMG_OK;
+}
+
+int clsimg_kernel_timing(clsimg_ctx* c, int32_t enable, double* ms, int32_t* launches) {
+  if (!c) return CLSIMG_EINVAL;
+  if (ms) *ms = c->tm_ms;
+  if (launches) *launches = c->tm_n;
+  c->tm_ms = 0.0;
+  c->tm_n = 0;
+  if (enable && !c->tm_ev[0]) {
+    DeviceGuard guard(c->device);
+    for (hipEvent_t& e : c->tm_ev) HIP_TRY(hipEventCreate(&e));
+  }
+  c->time_mult = enable != 0;
   return CLSIMG_OK;
 }
 
@@ -1101,6 +1122,8 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   int batch = 4;
   const int ntiles_Q = ntiles_adj(P, Q);
   const bool beam_full_grid = beam_fits(P) && !c->old_beam;
+  // timing of the multiplier kernel (clsimg_kernel_timing): events bound to its launches
+  const Stamps mult_stamps = c->time_mult ? Stamps{c->tm_ev[0], c->tm_ev[1]} : Stamps{};
   // reduced precision: the multipliers from one half-precision product, the
   // decision refined in FP32 over the candidates the rounding bound leaves
   const bool beam_half = c->prec != CLSIMG_FP32;
@@ -1377,7 +1400,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           HIP_TRY(launch_beam_lambda_refined(E, P, bf, tables_of(c, g, P), grad_stop, state, c->frag_h.ptr,
                                              P_<float>(c->hscale), P_<double>(c->mx_abs), kCandAbsParts, keys,
                                              P_<float>(c->mx_lam), P_<int>(c->mx_cand), cand_cap, count, st,
-                                             big_tiles(c, P)));
+                                             big_tiles(c, P), mult_stamps));
           // the candidates in FP32: Ut fragments of E from the correlation
           AdjParams ap = adj_params(c, g, P, frag_r, P_<const int>(c->mx_cand), cand_cap, grad_stop);
           ap.rows_part = P_<float>(c->part);
@@ -1389,7 +1412,7 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
         } else if (!beam_full_grid && beam_big_grid_ok) {
           HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
           HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr, 0.f,
-                                  0, 0, 1.f, state, keys, st, {}, big_tiles(c, P)));
+                                  0, 0, 1.f, state, keys, st, mult_stamps, big_tiles(c, P)));
           HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
         } else if (beam_full_grid) {
           if (c->beam_prep) HIP_TRY(launch_beam_prep(E, P, P_<float>(c->frag_b), st));
@@ -1403,6 +1426,12 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
           HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
         }
         ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
+        if (mult_stamps.start && c->h_dec->lsqr_done && c->h_dec->feasible && (beam_half || !beam_full_grid)) {
+          float ms = 0.f;
+          HIP_TRY(hipEventElapsedTime(&ms, c->tm_ev[0], c->tm_ev[1]));
+          c->tm_ms += ms;
+          ++c->tm_n;
+        }
         if (beam_half && c->h_dec->lsqr_done && c->h_dec->feasible && c->h_dec->cand_overflow) {
           // more candidates than the list holds: this step's multipliers in FP32
           if (beam_full_grid) {

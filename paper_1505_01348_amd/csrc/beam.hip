@@ -414,10 +414,11 @@ __global__ void beam_prep_full_kernel(const float2* __restrict__ U, int P, int M
 }
 
 template <int RPW, int NT, class Epi>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2 : 1))) void beam_big_kernel(const float* __restrict__ frag, int MT, Tables tab,
-                                                       const int* skip, Epi epi) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void beam_big_kernel(
+    const float* __restrict__ frag, int MT, Tables tab, const int* skip, Epi epi) {
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
+  __shared__ float2 bsh[2][NT][64];  // B operands of a chunk pair, per tile and lane (double buffer)
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
   // wave index as a scalar: the row-tile tests below are wave-uniform branches
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -425,53 +426,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2
   const int Q = tab.Q, nl = tab.nl, nm = tab.nm;
   const int ntiles = (Q + 15) >> 4;
   int mrow[RPW];
-  int mlast = 0;  // this wave's last row tile: its K loop ends with that column tile
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
-    if (mrow[i] < MT) mlast = max(mlast, mrow[i]);
-  }
-  const int jend = 2 * mlast + 2;  // chunk pairs 0 .. 2 mlast + 1
+  for (int i = 0; i < RPW; ++i) mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
+  // the waves share one barrier per chunk pair, so every wave runs all of them
+  const int jend = KS / 2;
+  constexpr int GT = (NT + 3) / 4;  // tiles whose operands this wave generates: w, w + 4
   epi.init();
   for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
-    // this lane's pixel in each of the block's tiles (clamped; masked at the end)
-    const float2* el[NT];
-    const float2* em[NT];
+    // operand generation: tile w + 4 tt, this lane's pixel, antennas 4j + q
+    const float2* elg[GT];
+    const float2* emg[GT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
+    for (int tt = 0; tt < GT; ++tt) {
+      const int t = min(w + 4 * tt, NT - 1);
       const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
       const int im = pix / nl, il = pix - im * nl;
-      el[t] = tab.El + (size_t)q * nl + il;
-      em[t] = tab.Em + (size_t)q * nm + im;
+      elg[tt] = tab.El + (size_t)q * nl + il;
+      emg[tt] = tab.Em + (size_t)q * nm + im;
     }
+    float2 te[GT], tm[GT];
+    auto issue = [&](int jj) {
+#pragma unroll
+      for (int tt = 0; tt < GT; ++tt) {
+        te[tt] = elg[tt][(size_t)4 * jj * nl];
+        tm[tt] = emg[tt][(size_t)4 * jj * nm];
+      }
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+      for (int tt = 0; tt < GT; ++tt)
+        if (w + 4 * tt < NT) bsh[slot][w + 4 * tt][lane] = cmul(te[tt], tm[tt]);
+    };
     v4f acc[RPW][NT];
 #pragma unroll
     for (int i = 0; i < RPW; ++i)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    // the table entries and the fragments of the next chunk pair are loaded
-    // while the current pair multiplies
-    float2 te[NT], tm[NT];
     float f0n[RPW], f1n[RPW];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      te[t] = el[t][0];
-      tm[t] = em[t][0];
-    }
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const float* fr = frag + (size_t)min(mrow[i], MT - 1) * KS * 64 + lane;
       f0n[i] = fr[0];
       f1n[i] = fr[64];
     }
+    issue(0);
+    store(0);
+    if (jend > 1) issue(1);
+    __syncthreads();
     for (int j = 0; j < jend; ++j) {  // chunk pair 2j, 2j + 1: antenna 4j + q, column tile j >> 1
       const int ct = j >> 1;
-      float b0[NT], b1[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const float2 a = cmul(te[t], tm[t]);
-        b0[t] = a.x;
-        b1[t] = a.y;
+      if (j + 1 < jend) {  // the next pair's operands into the other slot, loads for the one after
+        store((j + 1) & 1);
+        if (j + 2 < jend) issue(j + 2);
       }
       float f0[RPW], f1[RPW];
 #pragma unroll
@@ -482,17 +488,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2
       const int jn = j + 1 < jend ? j + 1 : j;
       const int ctn = jn >> 1;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        te[t] = el[t][(size_t)4 * jn * nl];
-        tm[t] = em[t][(size_t)4 * jn * nm];
-      }
-#pragma unroll
       for (int i = 0; i < RPW; ++i) {
         if (mrow[i] >= ctn && mrow[i] < MT) {  // wave-uniform
           const float* fr = frag + ((size_t)mrow[i] * KS + 2 * jn) * 64 + lane;
           f0n[i] = fr[0];
           f1n[i] = fr[64];
         }
+      }
+      float b0[NT], b1[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float2 a = bsh[j & 1][t][lane];
+        b0[t] = a.x;
+        b1[t] = a.y;
       }
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
@@ -504,6 +512,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2
           }
         }
       }
+      __syncthreads();  // slot j & 1 is free again; slot (j + 1) & 1 is complete
+    }
+    const float2* el[NT];
+    const float2* em[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
+      const int im = pix / nl, il = pix - im * nl;
+      el[t] = tab.El + (size_t)q * nl + il;
+      em[t] = tab.Em + (size_t)q * nm + im;
     }
     // column dot over this wave's row tiles: accumulator element r of row tile m
     // pairs with chunk 4m + r, i.e. antenna 8m + 4(r >> 1) + q, component r & 1
@@ -549,7 +567,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2
 // 2^-16.  FP16 needs the operands inside its range: Ut is scaled by a power of
 // two sU (largest entry below 2^14, computed on the device) and the steering
 // entries by a power of two sB (|a_p| = P^-1/2); the column dot in FP32 with
-// the unscaled steering entries is multiplied by 1 / (sU sB) (exact).
+// the unscaled steering entries is multiplied by 1 / (sU sB) (exact).  As in
+// the FP32 kernel the product runs on the block triangle of Ut (blocks below
+// the diagonal doubled by the preparation, zero above it; row tile m takes
+// chunks 0 .. m / 2), and the B operands of a chunk are generated once per
+// workgroup (wave w forms tiles w, w + 4 into a double-buffered LDS slot
+// while the previous chunk multiplies).
 //
 // Embedding: real position 2p + s = component s of antenna p (Ut[2p+s][2q+t]
 // = Re H_pq if s == t, -Im H_pq if (s, t) = (0, 1), Im H_pq if (1, 0), with H
@@ -617,11 +640,13 @@ __global__ void beam_prep_h16_kernel(const float2* __restrict__ U, int P, int MT
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int p2 = (col0 + i) >> 1, t = i & 1;
+      const int ct = (col0 + i) >> 4;  // 16-column tile: below the diagonal doubled, above it zero
       float v = 0.f;
-      if (m < MT && p < P && p2 < P) {
+      if (m < MT && p < P && p2 < P && ct <= m) {
         const float2 x = U[p * P + p2], y = U[p2 * P + p];
         const float hr = 0.5f * (x.x + y.x), hm = 0.5f * (x.y - y.y);
         v = (s == t) ? hr : (s == 0 ? -hm : hm);
+        if (ct < m) v *= 2.f;
       }
       typename Half<BF>::T h, l;
       split_half<BF>(v * sU, h, l);
@@ -634,79 +659,97 @@ __global__ void beam_prep_h16_kernel(const float2* __restrict__ U, int P, int MT
 }
 
 template <int RPW, int NT, bool BF, class Epi>
-__global__ __launch_bounds__(256) void beam_h16_kernel(const typename Half<BF>::V* __restrict__ frag, int MT, int KC,
-                                                       const float* __restrict__ scale, float sB, Tables tab,
-                                                       const int* skip, Epi epi) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void beam_h16_kernel(
+    const typename Half<BF>::V* __restrict__ frag, int MT, int KC, const float* __restrict__ scale, float sB,
+    Tables tab, const int* skip, Epi epi) {
   typedef typename Half<BF>::V V;
   typedef typename Half<BF>::T T;
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
+  __shared__ V bsh[2][NT][2][64];  // hi / lo B operands of a chunk, per tile and lane (double buffer)
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row-tile tests
   const int Q = tab.Q, nl = tab.nl, nm = tab.nm, Pp = tab.Pp;
   const int ntiles = (Q + 15) >> 4;
   const float inv = 1.f / ((scale ? *scale : 1.f) * sB);
+  int mrow[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
+  const int cend = min(KC, (MT - 1) / 2 + 1);  // the chunks of the last row tile (shared barriers)
+  constexpr int GT = (NT + 3) / 4;             // tiles whose operands this wave generates
   epi.init();
   for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
-    const float2* el[NT];
-    const float2* em[NT];
+    const float2* elg[GT];
+    const float2* emg[GT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
+    for (int tt = 0; tt < GT; ++tt) {
+      const int t = min(w + 4 * tt, NT - 1);
       const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
-      const int im = pix / nl, il = pix - im * nl;
-      el[t] = tab.El + il;
-      em[t] = tab.Em + im;
+      const int im = pix / nl;
+      elg[tt] = tab.El + (pix - im * nl);
+      emg[tt] = tab.Em + im;
     }
+    auto gen = [&](int c, int slot) {
+#pragma unroll
+      for (int tt = 0; tt < GT; ++tt) {
+        if (w + 4 * tt >= NT) continue;  // wave-uniform
+        V bh, bl;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ant = min(16 * c + 4 * g + u, Pp - 1);  // beyond P: zero columns of Ut
+          const float2 a = cmul(elg[tt][(size_t)ant * nl], emg[tt][(size_t)ant * nm]);
+          T h, l;
+          split_half<BF>(a.x * sB, h, l);
+          bh[2 * u] = h;
+          bl[2 * u] = l;
+          split_half<BF>(a.y * sB, h, l);
+          bh[2 * u + 1] = h;
+          bl[2 * u + 1] = l;
+        }
+        bsh[slot][w + 4 * tt][0][lane] = bh;
+        bsh[slot][w + 4 * tt][1][lane] = bl;
+      }
+    };
     v4f acc[RPW][NT];
 #pragma unroll
     for (int i = 0; i < RPW; ++i)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    const V* fw = frag + (size_t)(2 * w * KC) * 64 + lane;  // row tile w, chunk 0, high half
-    const size_t rstep = (size_t)4 * KC * 2 * 64;          // next row tile of this wave
-    for (int c = 0; c < KC; ++c) {
-      V bh[NT], bl[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int ant = min(16 * c + 4 * g + u, Pp - 1);  // beyond P: zero columns of Ut
-          const float2 a = cmul(el[t][(size_t)ant * nl], em[t][(size_t)ant * nm]);
-          T h, l;
-          split_half<BF>(a.x * sB, h, l);
-          bh[t][2 * u] = h;
-          bl[t][2 * u] = l;
-          split_half<BF>(a.y * sB, h, l);
-          bh[t][2 * u + 1] = h;
-          bl[t][2 * u + 1] = l;
-        }
-      }
-      V ah[RPW], al[RPW];
+    gen(0, 0);
+    __syncthreads();
+    for (int c = 0; c < cend; ++c) {
+      if (c + 1 < cend) gen(c + 1, (c + 1) & 1);
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
-        ah[i] = fw[i * rstep + (size_t)(2 * c) * 64];
-        al[i] = fw[i * rstep + (size_t)(2 * c + 1) * 64];
-      }
+        if (mrow[i] < MT && 2 * c <= mrow[i]) {  // wave-uniform
+          const V* fr = frag + ((size_t)(2 * ((size_t)mrow[i] * KC + c))) * 64 + lane;
+          const V ah = fr[0], al = fr[64];
 #pragma unroll
-      for (int i = 0; i < RPW; ++i)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          acc[i][t] = Half<BF>::mfma(ah[i], bh[t], acc[i][t]);
-          acc[i][t] = Half<BF>::mfma(ah[i], bl[t], acc[i][t]);
-          acc[i][t] = Half<BF>::mfma(al[i], bh[t], acc[i][t]);
+          for (int t = 0; t < NT; ++t) {
+            const V bh = bsh[c & 1][t][0][lane], bl = bsh[c & 1][t][1][lane];
+            acc[i][t] = Half<BF>::mfma(ah, bh, acc[i][t]);
+            acc[i][t] = Half<BF>::mfma(ah, bl, acc[i][t]);
+            acc[i][t] = Half<BF>::mfma(al, bh, acc[i][t]);
+          }
         }
+      }
+      __syncthreads();  // slot c & 1 is free again; slot (c + 1) & 1 is complete
     }
     float gp[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
+      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
+      const int im = pix / nl;
+      const float2* el = tab.El + (pix - im * nl);
+      const float2* em = tab.Em + im;
       gp[t] = 0.f;
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
-        const int m = w + 4 * i;
+        const int m = mrow[i];
         if (m < MT) {
           const int a0i = 8 * m + 2 * g;
-          const float2 a0 = cmul(el[t][(size_t)a0i * nl], em[t][(size_t)a0i * nm]);
-          const float2 a1 = cmul(el[t][(size_t)(a0i + 1) * nl], em[t][(size_t)(a0i + 1) * nm]);
+          const float2 a0 = cmul(el[(size_t)a0i * nl], em[(size_t)a0i * nm]);
+          const float2 a1 = cmul(el[(size_t)(a0i + 1) * nl], em[(size_t)(a0i + 1) * nm]);
           gp[t] += acc[i][t][0] * a0.x + acc[i][t][1] * a0.y + acc[i][t][2] * a1.x + acc[i][t][3] * a1.y;
         }
       }
@@ -1167,7 +1210,7 @@ double beam_h1_delta_coef(int P, bool bf16) {
 hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,
                                       const uint8_t* state, void* frag, float* scale, double* absum, int nabs,
                                       uint64_t* keys, float* lam, int* cand, int cap, int* count, hipStream_t st,
-                                      int nt) {
+                                      int nt, Stamps ts) {
   const int MT = pad_p(P) / 8, KC = beam_h16_chunks(P), rpw = big_rpw(MT);
   if (!bf16)
     hipLaunchKernelGGL(beam_h16_scale_kernel, dim3(1), dim3(1024), 0, st, E, P * P, scale);
@@ -1190,11 +1233,11 @@ hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const T
 #define H1_RPW(R)                                                                                              \
   case R:                                                                                                      \
     if (bf16)                                                                                                  \
-      hipLaunchKernelGGL((beam_h1_kernel<R, true, BeamLambdaApprox>), g, b, 0, st,                             \
-                         static_cast<const v8b*>(frag), MT, KC, sc, sB, tab, skip, epi);                       \
+      hipExtLaunchKernelGGL((beam_h1_kernel<R, true, BeamLambdaApprox>), g, b, 0, st, ts.start, ts.stop, 0,     \
+                            static_cast<const v8b*>(frag), MT, KC, sc, sB, tab, skip, epi);                    \
     else                                                                                                       \
-      hipLaunchKernelGGL((beam_h1_kernel<R, false, BeamLambdaApprox>), g, b, 0, st,                            \
-                         static_cast<const v8h*>(frag), MT, KC, sc, sB, tab, skip, epi);                       \
+      hipExtLaunchKernelGGL((beam_h1_kernel<R, false, BeamLambdaApprox>), g, b, 0, st, ts.start, ts.stop, 0,    \
+                            static_cast<const v8h*>(frag), MT, KC, sc, sB, tab, skip, epi);                    \
     break;
   switch (rpw) {
     H1_RPW(1)

@@ -407,7 +407,7 @@ double beam_h1_delta_coef(int P, bool bf16);
 hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,
                                       const uint8_t* state, void* frag, float* scale, double* absum, int nabs,
                                       uint64_t* keys, float* lam, int* cand, int cap, int* count, hipStream_t st,
-                                      int nt);
+                                      int nt, Stamps ts = {});
 hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
                                   float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
                                   float* hscale, hipStream_t st, int nt = 0);

@@ -248,84 +248,88 @@ __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, fl
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
   const int MT = pr.MT, KS = pr.KS, stride = pr.n;  // partials: one row of pr.n per (slice, row group)
   const int n = pr.n_dev ? min(*pr.n_dev, pr.n) : pr.n;
-  if (16 * (int)blockIdx.x * NT >= n) return;  // beyond a list built on the device
   const int mt = 4 * blockIdx.y + w;
   const bool live_row = mt < MT;
   const int mtc = live_row ? mt : MT - 1;  // loads stay in bounds; the dot leaves it out
   const Tables tab = pr.tab;
-  int il[NT], im[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int col = 16 * (blockIdx.x * NT + t) + c16;
-    int pix = col < n ? (pr.idx ? pr.idx[col] : col) : 0;
-    if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;
-    im[t] = pix / tab.nl;
-    il[t] = pix - im[t] * tab.nl;
-  }
-  // B operand of chunk kc: real row 4kc + q = component q & 1 of antenna 2kc + (q >> 1)
-  const float2* elp[NT];
-  const float2* emp[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    elp[t] = tab.El + (size_t)(q >> 1) * tab.nl + il[t];
-    emp[t] = tab.Em + (size_t)(q >> 1) * tab.nm + im[t];
-  }
   const size_t sl = (size_t)2 * tab.nl, sm = (size_t)2 * tab.nm;  // two antennas per chunk
   const int per = (KS + gridDim.z - 1) / gridDim.z;
   const int k0 = blockIdx.z * per, k1 = min(KS, k0 + per);
   const float* fw = pr.frag + (size_t)mtc * KS * 64 + lane;
-  v4f acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int kf = k0 < k1 ? k0 : 0;
-  float fa = fw[(size_t)kf * 64];
-  float2 te[NT], tm[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    te[t] = elp[t][kf * sl];
-    tm[t] = emp[t][kf * sm];
-  }
-  for (int kc = k0; kc < k1; ++kc) {
-    const float a = fa;
-    float b[NT];
+  // groups of NT 16-pixel tiles, strided over gridDim.x (a list built on the
+  // device may be shorter than the launch assumed)
+  for (int xb = blockIdx.x; 16 * xb * NT < n; xb += gridDim.x) {
+    int il[NT], im[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const float2 x = cmul(te[t], tm[t]);
-      b[t] = (q & 1) ? x.y : x.x;
+      const int col = 16 * (xb * NT + t) + c16;
+      int pix = col < n ? (pr.idx ? pr.idx[col] : col) : 0;
+      if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;
+      im[t] = pix / tab.nl;
+      il[t] = pix - im[t] * tab.nl;
     }
-    const int kn = kc + 1 < k1 ? kc + 1 : kc;
-    fa = fw[(size_t)kn * 64];
+    // B operand of chunk kc: real row 4kc + q = component q & 1 of antenna 2kc + (q >> 1)
+    const float2* elp[NT];
+    const float2* emp[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      te[t] = elp[t][kn * sl];
-      tm[t] = emp[t][kn * sm];
+      elp[t] = tab.El + (size_t)(q >> 1) * tab.nl + il[t];
+      emp[t] = tab.Em + (size_t)(q >> 1) * tab.nm + im[t];
     }
+    v4f acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(a, b[t], acc[t]);
-  }
-  // accumulator element r of lane (c16, q): real row 16mt + 4q + r, i.e.
-  // antenna 8mt + 2q + (r >> 1), component r & 1
-  float gp[NT];
+    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int kf = k0 < k1 ? k0 : 0;
+    float fa = fw[(size_t)kf * 64];
+    float2 te[NT], tm[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    gp[t] = 0.f;
-    if (live_row) {
-      const float2 a0 = tab.a(8 * mt + 2 * q, il[t], im[t]);
-      const float2 a1 = tab.a(8 * mt + 2 * q + 1, il[t], im[t]);
-      gp[t] = acc[t][0] * a0.x + acc[t][1] * a0.y + acc[t][2] * a1.x + acc[t][3] * a1.y;
+    for (int t = 0; t < NT; ++t) {
+      te[t] = elp[t][kf * sl];
+      tm[t] = emp[t][kf * sm];
     }
-    gp[t] += __shfl_xor(gp[t], 16, 64);
-    gp[t] += __shfl_xor(gp[t], 32, 64);
-  }
-  if (q == 0) {
+    for (int kc = k0; kc < k1; ++kc) {
+      const float a = fa;
+      float b[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) gs[w][16 * t + c16] = gp[t];
-  }
-  __syncthreads();
-  if (threadIdx.x < NT * 16) {
-    const int col = 16 * blockIdx.x * NT + threadIdx.x;
-    const float g = (gs[0][threadIdx.x] + gs[1][threadIdx.x]) + (gs[2][threadIdx.x] + gs[3][threadIdx.x]);
-    if (col < n) part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * stride + col] = g;
+      for (int t = 0; t < NT; ++t) {
+        const float2 x = cmul(te[t], tm[t]);
+        b[t] = (q & 1) ? x.y : x.x;
+      }
+      const int kn = kc + 1 < k1 ? kc + 1 : kc;
+      fa = fw[(size_t)kn * 64];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        te[t] = elp[t][kn * sl];
+        tm[t] = emp[t][kn * sm];
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(a, b[t], acc[t]);
+    }
+    // accumulator element r of lane (c16, q): real row 16mt + 4q + r, i.e.
+    // antenna 8mt + 2q + (r >> 1), component r & 1
+    float gp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      gp[t] = 0.f;
+      if (live_row) {
+        const float2 a0 = tab.a(8 * mt + 2 * q, il[t], im[t]);
+        const float2 a1 = tab.a(8 * mt + 2 * q + 1, il[t], im[t]);
+        gp[t] = acc[t][0] * a0.x + acc[t][1] * a0.y + acc[t][2] * a1.x + acc[t][3] * a1.y;
+      }
+      gp[t] += __shfl_xor(gp[t], 16, 64);
+      gp[t] += __shfl_xor(gp[t], 32, 64);
+    }
+    if (q == 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) gs[w][16 * t + c16] = gp[t];
+    }
+    __syncthreads();
+    if (threadIdx.x < NT * 16) {
+      const int col = 16 * xb * NT + threadIdx.x;
+      const float g = (gs[0][threadIdx.x] + gs[1][threadIdx.x]) + (gs[2][threadIdx.x] + gs[3][threadIdx.x]);
+      if (col < n) part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * stride + col] = g;
+    }
+    __syncthreads();
   }
 }
 
@@ -1028,10 +1032,13 @@ hipError_t launch_adjoint_epi(const AdjParams& pr, const Epi& epi, hipStream_t s
     if (pr.MT <= 12) return go(adjoint_kernel<12, 1, 1, Epi>, T = 64);
   }
   const int ngroups = (pr.MT + 3) / 4;
-  const int nt = pr.n <= 16 ? 1 : (pr.n <= 32 ? 2 : 4);
-  const int xt = (pr.n + 16 * nt - 1) / (16 * nt);
+  // a list built on the device (usually short): one tile per workgroup, at
+  // most 64 workgroups along the list, the most K slices
+  const int nt = pr.n_dev ? 1 : (pr.n <= 16 ? 1 : (pr.n <= 32 ? 2 : 4));
+  const int xt0 = (pr.n + 16 * nt - 1) / (16 * nt);
+  const int xt = pr.n_dev ? std::min(xt0, 64) : xt0;
   // K slices: about 256 workgroups in all, at least 16 chunks per slice
-  int ksl = (256 + xt * ngroups - 1) / (xt * ngroups);
+  int ksl = pr.n_dev ? 8 : (256 + xt * ngroups - 1) / (xt * ngroups);
   ksl = std::max(1, std::min(ksl, std::min(8, pr.KS / 16)));
   if (pr.rows_part && pr.frag && !pr.U && !pr.xf && pr.nblk == 1 &&
       (size_t)ngroups * ksl * pr.n <= pr.rows_cap) {

@@ -87,6 +87,7 @@ def test_entry_points_reject_a_null_context():
     assert lib.clsimg_dirty_image(n, n, n, n, 0, n, n) == E
     assert lib.clsimg_dirty_image_timed(n, n, n, n, 0, n, n, n, n) == E
     assert lib.clsimg_dirty_image_noalloc(n, n, n, n, 0, n, n) == E
+    assert lib.clsimg_kernel_timing(n, 1, n, n) == E
     assert lib.clsimg_mvdr_bound(n, n, n, n, n, n, n) == E
     assert lib.clsimg_forward(n, n, n, n, n, 0, n, n) == E
     assert lib.clsimg_adjoint(n, n, n, n, n, 0, n, n) == E

@@ -240,7 +240,8 @@ int clsimg_adjoint(clsimg_ctx* ctx, const clsimg_array* array, const clsimg_grid
  *   bound gamma as clsimg_mvdr_bound; threshold eps_i = kappa_d mf_i / sqrt(N)
  * R: DEVICE complex64 P x P.  noise_diag: DEVICE float[P] or NULL.
  * sigma0 / state0: DEVICE float[Q] / uint8[Q] feasible starting image and its
- *   sets (both NULL = start from sigma = 0, every pixel in L).
+ *   sets (both NULL = start from sigma = 0, every pixel in L; state0 values
+ *   other than CLSIMG_STATE_F and CLSIMG_STATE_U read as L).
  * sigma: DEVICE float[Q] out.  state: DEVICE uint8[Q] out (CLSIMG_STATE_*).
  * mf, gamma: DEVICE float[Q] out, or NULL.  stats: HOST, always written.
  * Synchronises `stream` (the active-set decisions are read on the host). */

@@ -19,6 +19,8 @@
 // walks 16-pixel tiles; it generates the steering entries of its tile from the
 // separable tables (one complex product per entry).  After the fragments are
 // in registers there is no LDS traffic and no barrier on the path.
+#include <utility>
+
 #include "kernels.h"
 
 namespace clsimg {
@@ -598,11 +600,21 @@ struct Half<true> {
   __device__ static v4f mfma(V a, V b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 
-// power-of-two scale putting the largest |U| component just below 2^14
+// power-of-two scale putting the largest |U| component just below 2^14;
+// one workgroup, eight loads in flight per thread
 __global__ __launch_bounds__(1024) void beam_h16_scale_kernel(const float2* __restrict__ U, int n, float* scale) {
   __shared__ float sm[16];
   float m = 0.f;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+  const int nt = blockDim.x;
+  int e = threadIdx.x;
+  for (; e + 7 * nt < n; e += 8 * nt) {
+    float2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = U[e + k * nt];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+  }
+  for (; e < n; e += nt) {
     const float2 v = U[e];
     m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
   }
@@ -777,10 +789,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 // the host-driven loop with CLSIMG_FP16 / CLSIMG_BF16): one half-precision
 // product Y = W X on the 16 x 16 x 32 MFMA with FP32 accumulation, W the
 // block triangle of Ut (blocks below the diagonal doubled, as in the FP32
-// kernel), gives approximate multipliers lam~_i, with a bound delta on
-// |lam~_i - lam_i| from the rounding of both operands:
-//   |x^T W x - x~^T W~ x| <= (2u + accumulation terms) sum_jk |x_j| |W_jk| |x_k|
-//                         <= (2u + ...) S / P,   S = sum |W| = sum |Ut|,
+// kernel), gives approximate multipliers lam~_i = x~^T W~ x~, with a bound
+// delta on |lam~_i - lam_i| from the rounding of the operands:
+//   |x^T W x - x~^T W~ x~| <= (3u + accumulation terms) sum_jk |x_j| |W_jk| |x_k|
+//                          <= (3u + ...) S / P,   S = sum |W| = sum |Ut|,
 // since every real steering component is at most P^-1/2 (u = 2^-11 for FP16,
 // 2^-8 for BF16).  The true minimum lies among the pixels with
 // lam~_i <= min lam~ + 2 delta; those candidates are beamformed again in FP32
@@ -856,95 +868,131 @@ struct BeamLambdaApprox {
   }
 };
 
+// Calls f(integral_constant<int, P>) for P = 0 .. N - 1 in order.
+template <class F, int... Ps>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, Ps...>) {
+  (f(std::integral_constant<int, Ps>{}), ...);
+}
+
 // Single product on the half MFMA, block-triangular; waves own row tiles
 // m = 4i + w (even i) or 4i + 3 - w (odd i) as in the FP32 kernel, and row
-// tile m runs chunks 0 .. m / 2.  The B operands of a chunk (16 antennas of
-// the NT = 4 pixel tiles) are generated once per workgroup: wave w forms tile
-// w's operands from the tables (four complex products per lane) into a
-// double-buffered LDS slot while the waves multiply the previous chunk, and
-// every wave reads all four tiles' operands back (one barrier per chunk).
+// tile m runs chunks 0 .. m / 2.  Per block of NT = 4 pixel tiles the B
+// operands of every chunk the triangle touches (at most 2 RPW chunks of 16
+// antennas) are formed once, wave w forming tile w's from the tables (the
+// block's column of the m table staged in LDS first when the block lies in
+// one image row), and stay in LDS for the whole block: the chunk loop has
+// no barrier.  The rows of a wave are sorted by m, so the chunks fall into
+// phases p = 0 .. RPW - 1 in which exactly rows p .. RPW - 1 are active;
+// each phase is its own loop with a fixed set of rows.  A fragments stream
+// from global memory one chunk ahead (row i's fragment of chunk c + 1, or of
+// chunk 0 of the next block behind its last chunk, is requested right behind
+// its MFMAs of chunk c, in a fixed order, so the waits count exactly), and
+// the column dot takes the same rounded steering components back from LDS:
+// lam~ = x~^T W~ x~, every operand rounded once.
 template <int RPW, bool BF, class Epi>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void beam_h1_kernel(
     const typename Half<BF>::V* __restrict__ frag, int MT, int KC, const float* __restrict__ scale, float sB,
     Tables tab, const int* skip, Epi epi) {
   typedef typename Half<BF>::V V;
   typedef typename Half<BF>::T T;
-  constexpr int NT = 4;
+  typedef T V4 __attribute__((ext_vector_type(4)));
+  constexpr int NT = 4, CMAX = 2 * RPW;
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
-  __shared__ V bsh[2][NT][64];
+  __shared__ V bsh[CMAX][NT][64];
+  __shared__ float2 emsh[16 * CMAX];
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row-tile tests
   const int Q = tab.Q, nl = tab.nl, nm = tab.nm, Pp = tab.Pp;
   const int ntiles = (Q + 15) >> 4;
-  const float inv = 1.f / ((scale ? *scale : 1.f) * sB);
+  const bool row_blocks = (nl & (16 * NT - 1)) == 0;  // every block inside one image row
+  const float inv = 1.f / ((scale ? *scale : 1.f) * sB * sB);
   int mrow[RPW];
-  int mlast = 0;
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
-    if (mrow[i] < MT) mlast = max(mlast, mrow[i]);
-  }
-  // every wave runs the same chunks (the barriers are shared): up to the
-  // workgroup's last row tile
+  for (int i = 0; i < RPW; ++i) mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
+  // chunks the triangle touches: 0 .. (MT - 1) / 2 (at most CMAX)
   const int cend = min(KC, (MT - 1) / 2 + 1);
+  // each row's last chunk: its diagonal chunk (rows from MT on are zero
+  // fragments, row tiles up to 4 RPW being allocated); behind it the row
+  // requests chunk 0 again, the first one of the next block
+  int last[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) last[i] = min(mrow[i] >> 1, cend - 1);
+  V a[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) a[i] = frag[(size_t)mrow[i] * KC * 64 + lane];
   epi.init();
   for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
-    // this lane's pixel in tile w (operand generation); the column dot below
-    // finds each tile's pixel again
-    const int pw = min(16 * (blk * NT + w) + c16, Q - 1);
-    const int imw = pw / nl;
-    const float2* elw = tab.El + (pw - imw * nl);
-    const float2* emw = tab.Em + imw;
-    auto gen = [&](int c, int slot) {
-      V bh;
+    if (row_blocks) {
+      const int im = (16 * blk * NT) / nl;
+      for (int k = threadIdx.x; k < 16 * cend; k += blockDim.x) emsh[k] = tab.Em[(size_t)min(k, Pp - 1) * nm + im];
+      __syncthreads();
+    }
+    {
+      const int pw = min(16 * (blk * NT + w) + c16, Q - 1);
+      const int imw = pw / nl;
+      const float2* elw = tab.El + (pw - imw * nl);
+      const float2* emw = tab.Em + imw;
+      // two chunks per round, all table reads issued before use
+      for (int c0 = 0; c0 < cend; c0 += 2) {
+        float2 el[8], em[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int ant = min(16 * c + 4 * g + u, Pp - 1);  // beyond P: zero columns of W
-        const float2 a = cmul(elw[(size_t)ant * nl], emw[(size_t)ant * nm]);
-        bh[2 * u] = (T)(a.x * sB);
-        bh[2 * u + 1] = (T)(a.y * sB);
+        for (int k = 0; k < 8; ++k) {
+          const int ant = min(16 * c0 + 16 * (k >> 2) + 4 * g + (k & 3), Pp - 1);  // beyond P: zero columns of W
+          el[k] = elw[(size_t)ant * nl];
+          em[k] = row_blocks ? emsh[ant] : emw[(size_t)ant * nm];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          V bh;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float2 x = cmul(el[4 * h + u], em[4 * h + u]);
+            bh[2 * u] = (T)(x.x * sB);
+            bh[2 * u + 1] = (T)(x.y * sB);
+          }
+          bsh[c0 + h][w][lane] = bh;  // c0 + 1 < CMAX also when cend is odd (CMAX is even)
+        }
       }
-      bsh[slot][w][lane] = bh;
-    };
+    }
+    __syncthreads();
     v4f acc[RPW][NT];
 #pragma unroll
     for (int i = 0; i < RPW; ++i)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    gen(0, 0);
-    __syncthreads();
-    for (int c = 0; c < cend; ++c) {
-      if (c + 1 < cend) gen(c + 1, (c + 1) & 1);
-      V bh[NT];
+    auto phase = [&](auto pc) {
+      constexpr int P0 = decltype(pc)::value;
+      const int lo = P0 == 0 ? 0 : (mrow[P0 > 0 ? P0 - 1 : 0] >> 1) + 1;
+      const int hi = min(mrow[P0] >> 1, cend - 1);
+      for (int c = lo; c <= hi; ++c) {
+        V bh[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) bh[t] = bsh[c & 1][t][lane];
+        for (int t = 0; t < NT; ++t) bh[t] = bsh[c][t][lane];
 #pragma unroll
-      for (int i = 0; i < RPW; ++i) {
-        if (mrow[i] < MT && 2 * c <= mrow[i]) {  // wave-uniform
-          const V ah = frag[((size_t)mrow[i] * KC + c) * 64 + lane];
+        for (int i = P0; i < RPW; ++i) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) acc[i][t] = Half<BF>::mfma(ah, bh[t], acc[i][t]);
+          for (int t = 0; t < NT; ++t) acc[i][t] = Half<BF>::mfma(a[i], bh[t], acc[i][t]);
+          a[i] = frag[((size_t)mrow[i] * KC + (c < last[i] ? c + 1 : 0)) * 64 + lane];
         }
       }
-      __syncthreads();  // slot c & 1 is free again; slot (c + 1) & 1 is written
-    }
+    };
+    for_each_index(phase, std::make_integer_sequence<int, RPW>{});
+    // lane (c16, g) holds rows 4g .. 4g + 3 of row tile m: antennas 8m + 2g
+    // and 8m + 2g + 1 (real, imaginary), which sit in chunk m / 2 at lane
+    // c16 + 16 (2 (m & 1) + g / 2), halves 4 (g & 1) .. 4 (g & 1) + 3
     float gp[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
-      const int im = pix / nl;
-      const float2* el = tab.El + (pix - im * nl);
-      const float2* em = tab.Em + im;
       gp[t] = 0.f;
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
         const int m = mrow[i];
         if (m < MT) {
-          const int a0i = 8 * m + 2 * g;
-          const float2 a0 = cmul(el[(size_t)a0i * nl], em[(size_t)a0i * nm]);
-          const float2 a1 = cmul(el[(size_t)(a0i + 1) * nl], em[(size_t)(a0i + 1) * nm]);
-          gp[t] += acc[i][t][0] * a0.x + acc[i][t][1] * a0.y + acc[i][t][2] * a1.x + acc[i][t][3] * a1.y;
+          const T* xs = reinterpret_cast<const T*>(&bsh[m >> 1][t][c16 + 16 * (2 * (m & 1) + (g >> 1))]);
+          const V4 x = *reinterpret_cast<const V4*>(xs + 4 * (g & 1));
+          gp[t] += acc[i][t][0] * (float)x[0] + acc[i][t][1] * (float)x[1] + acc[i][t][2] * (float)x[2] +
+                   acc[i][t][3] * (float)x[3];
         }
       }
       gp[t] += __shfl_xor(gp[t], 16, 64);
@@ -954,7 +1002,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
       for (int t = 0; t < NT; ++t) gsum[w][16 * t + c16] = gp[t];
     }
-    __syncthreads();
+    __syncthreads();  // every wave is done with bsh and emsh, and gsum is complete
     if (threadIdx.x < NT * 16) {
       const int t = threadIdx.x >> 4;
       const int pix = 16 * (blk * NT + t) + (threadIdx.x & 15);
@@ -1198,13 +1246,14 @@ size_t beam_h1_frag_bytes(int P) {
 }
 
 double beam_h1_delta_coef(int P, bool bf16) {
-  // 2u for the two rounded operands, accumulation of up to 8 Pp + 64 FP32
-  // terms over the half and the FP32 evaluations (2^-24 each), FP16
-  // subnormals (at most 2^-25 absolute per scaled entry, far below u |v| for
-  // the entries that matter; covered by the factor 1.5 of the whole bound)
+  // 3u for the three rounded operands (x~ on both sides, W~), accumulation
+  // of up to 8 Pp + 64 FP32 terms over the half and the FP32 evaluations
+  // (2^-24 each), FP16 subnormals (at most 2^-25 absolute per scaled entry,
+  // far below u |v| for the entries that matter; covered by the factor 1.5 of
+  // the whole bound)
   const double u = bf16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -11);
   const int Pp = pad_p(P);
-  return 1.5 * (2.0 * u + (8.0 * Pp + 64.0) * std::ldexp(1.0, -24)) / (double)P;
+  return 1.5 * (3.0 * u + (8.0 * Pp + 64.0) * std::ldexp(1.0, -24)) / (double)P;
 }
 
 hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,

@@ -9,37 +9,58 @@ constexpr int kCtl = 1024;  // single-workgroup control kernels
 
 // ---------------------------------------------------------------------------
 // Sorted index lists of F (state 1) and U (state 2); one workgroup.  The
-// state array is taken in rounds of 16 KiB: thread t holds the 16 states of
-// word t of the round (one coalesced 16-byte load), the counts are scanned
-// with wave shuffles plus one exchange of the wave totals, and each thread
-// writes its pixels in order.  Two barriers per round.
+// state array is taken in rounds of 64 KiB: thread t holds the 64 states of
+// bytes 64t .. 64t + 63 of the round (four coalesced 16-byte loads, issued
+// one round ahead), the counts are scanned with wave shuffles plus one
+// exchange of the wave totals, and each thread writes its pixels in order.
+// Two barriers per round.
 __global__ __launch_bounds__(kCtl) void compact_kernel(const uint8_t* __restrict__ state, int Q,
                                                        int* __restrict__ Flist,
                                                        int* __restrict__ Ulist,
                                                        SolveDecision* dec) {
-  constexpr int NW = kCtl / 64;
+  constexpr int NW = kCtl / 64, PER = 64, NV = PER / 16;
   __shared__ int wf[NW], wu[NW];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool vec = (reinterpret_cast<uintptr_t>(state) & 15) == 0;
-  int baseF = 0, baseU = 0;  // pixels of F and U in the rounds before (the same in every thread)
-  for (int r0 = 0; r0 < Q; r0 += 16 * kCtl) {
-    const int i0 = r0 + 16 * tid;
-    uint32_t ws[4] = {0u, 0u, 0u, 0u};  // states past Q read as 0 (L)
-    if (vec && i0 + 16 <= Q) {
-      const uint4 v = *reinterpret_cast<const uint4*>(state + i0);
-      ws[0] = v.x;
-      ws[1] = v.y;
-      ws[2] = v.z;
-      ws[3] = v.w;
+  // this thread's states of the round starting at r0; states past Q read as 0 (L)
+  auto fetch = [&](int r0, uint4* d) {
+    const int i0 = r0 + PER * tid;
+    if (vec && i0 + PER <= Q) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j) d[j] = reinterpret_cast<const uint4*>(state + i0)[j];
     } else {
-      for (int k = 0; k < 16 && i0 + k < Q; ++k) ws[k >> 2] |= (uint32_t)state[i0 + k] << (8 * (k & 3));
+      uint32_t ws[PER / 4] = {};
+      for (int k = 0; k < PER && i0 + k < Q; ++k) ws[k >> 2] |= (uint32_t)state[i0 + k] << (8 * (k & 3));
+#pragma unroll
+      for (int j = 0; j < NV; ++j) d[j] = make_uint4(ws[4 * j], ws[4 * j + 1], ws[4 * j + 2], ws[4 * j + 3]);
     }
+  };
+  auto byte_of = [](const uint4* v, int k) -> uint32_t {
+    const uint4 q = v[k >> 4];
+    const int wd = (k >> 2) & 3;
+    const uint32_t x = wd == 0 ? q.x : wd == 1 ? q.y : wd == 2 ? q.z : q.w;
+    return (x >> (8 * (k & 3))) & 0xFFu;
+  };
+  int baseF = 0, baseU = 0;  // pixels of F and U in the rounds before (the same in every thread)
+  uint4 nxt[NV];
+  fetch(0, nxt);
+  for (int r0 = 0; r0 < Q; r0 += PER * kCtl) {
+    uint4 cur[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) cur[j] = nxt[j];
+    if (r0 + PER * kCtl < Q) fetch(r0 + PER * kCtl, nxt);
+    const int i0 = r0 + PER * tid;
+    // states are 0, 1 or 2: byte b is 1 when its bit 0 is set and bit 1
+    // clear, 2 when bit 1 is set and bit 0 clear (four bytes per popcount)
     int cf = 0, cu = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const uint32_t sv = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-      cf += (sv == 1);
-      cu += (sv == 2);
+    for (int j = 0; j < NV; ++j) {
+      const uint32_t x[4] = {cur[j].x, cur[j].y, cur[j].z, cur[j].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cf += __popc(x[q] & ~(x[q] >> 1) & 0x01010101u);
+        cu += __popc((x[q] >> 1) & ~x[q] & 0x01010101u);
+      }
     }
     int sf = cf, su = cu;  // inclusive scan over the wave
 #pragma unroll
@@ -68,8 +89,8 @@ __global__ __launch_bounds__(kCtl) void compact_kernel(const uint8_t* __restrict
     int of = baseF + pf + sf - cf, ou = baseU + pu + su - cu;
     if (cf + cu > 0) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const uint32_t sv = (ws[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+      for (int k = 0; k < PER; ++k) {
+        const uint32_t sv = byte_of(cur, k);
         if (sv == 1) Flist[of++] = i0 + k;
         else if (sv == 2) Ulist[ou++] = i0 + k;
       }
@@ -378,7 +399,8 @@ __global__ void init_state_kernel(const float* __restrict__ sigma0, const uint8_
                                   float* __restrict__ sigma, uint8_t* __restrict__ state, int Q) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < Q; e += gridDim.x * blockDim.x) {
     sigma[e] = sigma0 ? sigma0[e] : 0.f;
-    state[e] = state0 ? state0[e] : (uint8_t)0;
+    const uint8_t v = state0 ? state0[e] : (uint8_t)0;
+    state[e] = v <= 2 ? v : (uint8_t)0;  // values other than F and U read as L
   }
 }
 

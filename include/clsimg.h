@@ -184,7 +184,9 @@ int clsimg_dirty_image_noalloc(clsimg_ctx* ctx, const clsimg_c32* R, const clsim
  * ceil(P / 32); the last tuning of a size applies to every grid).  Every
  * candidate computes each pixel with the same operations in the same order,
  * so results are bit-identical whichever is kept.  Eight tiles are offered up
- * to P = 192 only (beyond, the accumulators would not fit in registers).  Not
+ * to P = 192 in FP32 (beyond, the accumulators would not fit in registers) and
+ * up to P = 128 in split FP16 / BF16 (beyond, a block's operands would not fit
+ * in LDS).  Not
  * for use under stream capture: it synchronises the stream.  chosen (host, may
  * be null): the tile count kept.  us (host float[3], may be null): microseconds
  * per dirty image for 2, 4 and 8 tiles (-1: not offered).  CLSIMG_ENOTSUP for FP32 with P <= 48 (the
@@ -193,9 +195,9 @@ int clsimg_autotune(clsimg_ctx* ctx, const clsimg_array* array, const clsimg_gri
                     int32_t* chosen, float* us, void* stream);
 
 /* Sets the tiles per workgroup of the GEMM-shaped beamformers for arrays of P
- * antennas at `precision` (tiles 2, 4, or 8 up to P = 192; 0 restores the
- * built-in default), e.g. to reuse a choice tuned earlier.  CLSIMG_EINVAL for
- * other values. */
+ * antennas at `precision` (tiles 2, 4, or 8 up to P = 192 in FP32 and up to
+ * P = 128 in FP16 / BF16; 0 restores the built-in default), e.g. to reuse a
+ * choice tuned earlier.  CLSIMG_EINVAL for other values. */
 int clsimg_set_beam_tiles(clsimg_ctx* ctx, int32_t P, int32_t precision, int32_t tiles);
 
 /* Device time of the full-grid multiplier kernel of the host-driven active-set

@@ -792,7 +792,7 @@ int clsimg_dirty_image(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a
 int clsimg_set_beam_tiles(clsimg_ctx* c, int32_t P, int32_t precision, int32_t tiles) {
   if (!c || P < 1 || P > CLSIMG_MAX_P) return CLSIMG_EINVAL;
   if (precision != CLSIMG_FP32 && precision != CLSIMG_FP16 && precision != CLSIMG_BF16) return CLSIMG_EINVAL;
-  if (tiles != 0 && tiles != 2 && tiles != 4 && !(tiles == 8 && (pad_p(P) / 8 + 3) / 4 <= 6)) return CLSIMG_EINVAL;
+  if (tiles != 0 && !beam_tiles_offered(precision != CLSIMG_FP32, tiles, (pad_p(P) / 8 + 3) / 4)) return CLSIMG_EINVAL;
   const int pr = precision == CLSIMG_FP16 ? 1 : (precision == CLSIMG_BF16 ? 2 : 0);
   c->tuned_nt[pr][(pad_p(P) / 8 + 3) / 4] = tiles;
   return CLSIMG_OK;
@@ -843,7 +843,7 @@ int clsimg_autotune(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, 
   const int reps = 5;
   for (int i = 0; i < 3 && status == CLSIMG_OK; ++i) {
     const int nt = kBigTileChoices[i];
-    if (nt == 8 && rpw > 6) {  // not built: the accumulators would spill
+    if (!beam_tiles_offered(precision != CLSIMG_FP32, nt, rpw)) {  // not built
       if (us) us[i] = -1.f;
       continue;
     }

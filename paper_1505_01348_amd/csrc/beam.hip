@@ -569,12 +569,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 // 2^-16.  FP16 needs the operands inside its range: Ut is scaled by a power of
 // two sU (largest entry below 2^14, computed on the device) and the steering
 // entries by a power of two sB (|a_p| = P^-1/2); the column dot in FP32 with
-// the unscaled steering entries is multiplied by 1 / (sU sB) (exact).  As in
-// the FP32 kernel the product runs on the block triangle of Ut (blocks below
-// the diagonal doubled by the preparation, zero above it; row tile m takes
-// chunks 0 .. m / 2), and the B operands of a chunk are generated once per
-// workgroup (wave w forms tiles w, w + 4 into a double-buffered LDS slot
-// while the previous chunk multiplies).
+// the scaled steering entries xh + xl is multiplied by 1 / (sU sB^2) (exact).
+// As in the FP32 kernel the product runs on the block triangle of Ut (blocks
+// below the diagonal doubled by the preparation, zero above it; row tile m
+// takes chunks 0 .. m / 2), and the B operands of a block are generated once
+// per workgroup into LDS.
 //
 // Embedding: real position 2p + s = component s of antenna p (Ut[2p+s][2q+t]
 // = Re H_pq if s == t, -Im H_pq if (s, t) = (0, 1), Im H_pq if (1, 0), with H
@@ -630,6 +629,12 @@ __global__ __launch_bounds__(1024) void beam_h16_scale_kernel(const float2* __re
   }
 }
 
+// Calls f(integral_constant<int, P>) for P = 0 .. N - 1 in order.
+template <class F, int... Ps>
+__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, Ps...>) {
+  (f(std::integral_constant<int, Ps>{}), ...);
+}
+
 template <bool BF>
 __device__ __forceinline__ void split_half(float v, typename Half<BF>::T& hi, typename Half<BF>::T& lo) {
   hi = (typename Half<BF>::T)v;
@@ -670,99 +675,137 @@ __global__ void beam_prep_h16_kernel(const float2* __restrict__ U, int P, int MT
   }
 }
 
+// Split half precision: W x = Wh xh + Wh xl + Wl xh (the lo * lo product
+// dropped) on the 16 x 16 x 32 MFMA, FP32 accumulation.  Organised as the
+// single-product multiplier kernel: the hi / lo B operands of every chunk of
+// an NT-tile block are formed once into LDS (wave w forms tiles w, w + 4,
+// ... of each chunk from the tables), the rows of a wave run in triangle
+// phases with their hi / lo A fragments requested one chunk ahead (chunk 0
+// of the next block behind the last one), and the column dot takes
+// x = xh + xl back from LDS.
 template <int RPW, int NT, bool BF, class Epi>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void beam_h16_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4 * RPW * NT + 8 * RPW + 8 * NT > 224 ? 1 : 2))) void beam_h16_kernel(
     const typename Half<BF>::V* __restrict__ frag, int MT, int KC, const float* __restrict__ scale, float sB,
     Tables tab, const int* skip, Epi epi) {
   typedef typename Half<BF>::V V;
   typedef typename Half<BF>::T T;
+  typedef T V4 __attribute__((ext_vector_type(4)));
+  constexpr int CMAX = 2 * RPW;
   if (skip && *skip) return;
   __shared__ float gsum[4][NT * 16];
-  __shared__ V bsh[2][NT][2][64];  // hi / lo B operands of a chunk, per tile and lane (double buffer)
+  __shared__ V bsh[CMAX][NT][2][64];  // hi / lo B operands of every chunk, per tile and lane
+  __shared__ float2 emsh[16 * CMAX];
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row-tile tests
   const int Q = tab.Q, nl = tab.nl, nm = tab.nm, Pp = tab.Pp;
   const int ntiles = (Q + 15) >> 4;
-  const float inv = 1.f / ((scale ? *scale : 1.f) * sB);
+  const bool row_blocks = (nl & (16 * NT - 1)) == 0;  // every block inside one image row
+  const float inv = 1.f / ((scale ? *scale : 1.f) * sB * sB);
   int mrow[RPW];
 #pragma unroll
   for (int i = 0; i < RPW; ++i) mrow[i] = 4 * i + ((i & 1) ? 3 - w : w);
-  const int cend = min(KC, (MT - 1) / 2 + 1);  // the chunks of the last row tile (shared barriers)
-  constexpr int GT = (NT + 3) / 4;             // tiles whose operands this wave generates
+  const int cend = min(KC, (MT - 1) / 2 + 1);
+  int last[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) last[i] = min(mrow[i] >> 1, cend - 1);
+  // hi at fragment 2 f, lo at 2 f + 1 (f = m KC + c)
+  V ah[RPW], al[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const V* fr = frag + (size_t)(2 * (size_t)mrow[i] * KC) * 64 + lane;
+    ah[i] = fr[0];
+    al[i] = fr[64];
+  }
+  constexpr int GT = (NT + 3) / 4;  // tiles whose operands this wave forms
   epi.init();
   for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
-    const float2* elg[GT];
-    const float2* emg[GT];
+    if (row_blocks) {
+      const int im = (16 * blk * NT) / nl;
+      for (int k = threadIdx.x; k < 16 * cend; k += blockDim.x) emsh[k] = tab.Em[(size_t)min(k, Pp - 1) * nm + im];
+      __syncthreads();
+    }
 #pragma unroll
     for (int tt = 0; tt < GT; ++tt) {
-      const int t = min(w + 4 * tt, NT - 1);
-      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
-      const int im = pix / nl;
-      elg[tt] = tab.El + (pix - im * nl);
-      emg[tt] = tab.Em + im;
-    }
-    auto gen = [&](int c, int slot) {
+      const int t = w + 4 * tt;
+      if (t >= NT) continue;  // wave-uniform
+      const int pw = min(16 * (blk * NT + t) + c16, Q - 1);
+      const int imw = pw / nl;
+      const float2* elw = tab.El + (pw - imw * nl);
+      const float2* emw = tab.Em + imw;
+      for (int c0 = 0; c0 < cend; c0 += 2) {
+        float2 el[8], em[8];
 #pragma unroll
-      for (int tt = 0; tt < GT; ++tt) {
-        if (w + 4 * tt >= NT) continue;  // wave-uniform
-        V bh, bl;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int ant = min(16 * c + 4 * g + u, Pp - 1);  // beyond P: zero columns of Ut
-          const float2 a = cmul(elg[tt][(size_t)ant * nl], emg[tt][(size_t)ant * nm]);
-          T h, l;
-          split_half<BF>(a.x * sB, h, l);
-          bh[2 * u] = h;
-          bl[2 * u] = l;
-          split_half<BF>(a.y * sB, h, l);
-          bh[2 * u + 1] = h;
-          bl[2 * u + 1] = l;
+        for (int k = 0; k < 8; ++k) {
+          const int ant = min(16 * c0 + 16 * (k >> 2) + 4 * g + (k & 3), Pp - 1);  // beyond P: zero columns of Ut
+          el[k] = elw[(size_t)ant * nl];
+          em[k] = row_blocks ? emsh[ant] : emw[(size_t)ant * nm];
         }
-        bsh[slot][w + 4 * tt][0][lane] = bh;
-        bsh[slot][w + 4 * tt][1][lane] = bl;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          V bh, bl;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float2 x = cmul(el[4 * h + u], em[4 * h + u]);
+            T hh, ll;
+            split_half<BF>(x.x * sB, hh, ll);
+            bh[2 * u] = hh;
+            bl[2 * u] = ll;
+            split_half<BF>(x.y * sB, hh, ll);
+            bh[2 * u + 1] = hh;
+            bl[2 * u + 1] = ll;
+          }
+          bsh[c0 + h][t][0][lane] = bh;  // c0 + 1 < CMAX also when cend is odd (CMAX is even)
+          bsh[c0 + h][t][1][lane] = bl;
+        }
       }
-    };
+    }
+    __syncthreads();
     v4f acc[RPW][NT];
 #pragma unroll
     for (int i = 0; i < RPW; ++i)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    gen(0, 0);
-    __syncthreads();
-    for (int c = 0; c < cend; ++c) {
-      if (c + 1 < cend) gen(c + 1, (c + 1) & 1);
+    auto phase = [&](auto pc) {
+      constexpr int P0 = decltype(pc)::value;
+      const int lo = P0 == 0 ? 0 : (mrow[P0 > 0 ? P0 - 1 : 0] >> 1) + 1;
+      const int hi = min(mrow[P0] >> 1, cend - 1);
+      for (int c = lo; c <= hi; ++c) {
+        V bh[NT], bl[NT];
 #pragma unroll
-      for (int i = 0; i < RPW; ++i) {
-        if (mrow[i] < MT && 2 * c <= mrow[i]) {  // wave-uniform
-          const V* fr = frag + ((size_t)(2 * ((size_t)mrow[i] * KC + c))) * 64 + lane;
-          const V ah = fr[0], al = fr[64];
+        for (int t = 0; t < NT; ++t) {
+          bh[t] = bsh[c][t][0][lane];
+          bl[t] = bsh[c][t][1][lane];
+        }
+#pragma unroll
+        for (int i = P0; i < RPW; ++i) {
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
-            const V bh = bsh[c & 1][t][0][lane], bl = bsh[c & 1][t][1][lane];
-            acc[i][t] = Half<BF>::mfma(ah, bh, acc[i][t]);
-            acc[i][t] = Half<BF>::mfma(ah, bl, acc[i][t]);
-            acc[i][t] = Half<BF>::mfma(al, bh, acc[i][t]);
+            acc[i][t] = Half<BF>::mfma(ah[i], bh[t], acc[i][t]);
+            acc[i][t] = Half<BF>::mfma(ah[i], bl[t], acc[i][t]);
+            acc[i][t] = Half<BF>::mfma(al[i], bh[t], acc[i][t]);
           }
+          const V* fr = frag + (size_t)(2 * ((size_t)mrow[i] * KC + (c < last[i] ? c + 1 : 0))) * 64 + lane;
+          ah[i] = fr[0];
+          al[i] = fr[64];
         }
       }
-      __syncthreads();  // slot c & 1 is free again; slot (c + 1) & 1 is complete
-    }
+    };
+    for_each_index(phase, std::make_integer_sequence<int, RPW>{});
+    // the column dot with x = xh + xl, from the chunk and lane positions of
+    // the single-product kernel
     float gp[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int pix = min(16 * (blk * NT + t) + c16, Q - 1);
-      const int im = pix / nl;
-      const float2* el = tab.El + (pix - im * nl);
-      const float2* em = tab.Em + im;
       gp[t] = 0.f;
 #pragma unroll
       for (int i = 0; i < RPW; ++i) {
         const int m = mrow[i];
         if (m < MT) {
-          const int a0i = 8 * m + 2 * g;
-          const float2 a0 = cmul(el[(size_t)a0i * nl], em[(size_t)a0i * nm]);
-          const float2 a1 = cmul(el[(size_t)(a0i + 1) * nl], em[(size_t)(a0i + 1) * nm]);
-          gp[t] += acc[i][t][0] * a0.x + acc[i][t][1] * a0.y + acc[i][t][2] * a1.x + acc[i][t][3] * a1.y;
+          const int ln = c16 + 16 * (2 * (m & 1) + (g >> 1));
+          const V4 xh = *reinterpret_cast<const V4*>(reinterpret_cast<const T*>(&bsh[m >> 1][t][0][ln]) + 4 * (g & 1));
+          const V4 xl = *reinterpret_cast<const V4*>(reinterpret_cast<const T*>(&bsh[m >> 1][t][1][ln]) + 4 * (g & 1));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gp[t] += acc[i][t][r] * ((float)xh[r] + (float)xl[r]);
         }
       }
       gp[t] += __shfl_xor(gp[t], 16, 64);
@@ -772,7 +815,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 #pragma unroll
       for (int t = 0; t < NT; ++t) gsum[w][16 * t + c16] = gp[t];
     }
-    __syncthreads();
+    __syncthreads();  // every wave is done with bsh and emsh, and gsum is complete
     if (threadIdx.x < NT * 16) {
       const int t = threadIdx.x >> 4;
       const int pix = 16 * (blk * NT + t) + (threadIdx.x & 15);
@@ -867,12 +910,6 @@ struct BeamLambdaApprox {
     if (threadIdx.x == 0) part[blk] = m;
   }
 };
-
-// Calls f(integral_constant<int, P>) for P = 0 .. N - 1 in order.
-template <class F, int... Ps>
-__device__ __forceinline__ void for_each_index(F&& f, std::integer_sequence<int, Ps...>) {
-  (f(std::integral_constant<int, Ps>{}), ...);
-}
 
 // Single product on the half MFMA, block-triangular; waves own row tiles
 // m = 4i + w (even i) or 4i + 3 - w (odd i) as in the FP32 kernel, and row
@@ -1158,6 +1195,15 @@ hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const
 // ---- split half precision ----
 int beam_h16_chunks(int P) { return (2 * pad_p(P) + 31) / 32; }
 
+// 16-pixel tiles per workgroup of the split kernel: the hi / lo operands of a
+// block (2 RPW chunks x NT tiles x 2 KiB) stay in LDS, so eight tiles only up
+// to 4 row tiles per wave; two tiles by default (two workgroups per CU up to
+// 9 row tiles per wave)
+__host__ __device__ constexpr bool h16_nt_ok(int nt, int rpw) { return nt == 2 || nt == 4 || (nt == 8 && rpw <= 4); }
+__host__ __device__ inline int h16_nt_or(int nt, int rpw) { return h16_nt_ok(nt, rpw) ? nt : 2; }
+
+bool beam_tiles_offered(bool half, int nt, int rpw) { return half ? h16_nt_ok(nt, rpw) : big_nt_ok(nt, rpw); }
+
 size_t beam_h16_frag_bytes(int P) {
   const int MT = pad_p(P) / 8;
   return (size_t)4 * big_rpw(MT) * beam_h16_chunks(P) * 2 * 64 * 16;
@@ -1168,7 +1214,7 @@ static hipError_t launch_h16(const void* frag, const float* scale, const Tables&
                              hipStream_t st, Stamps ts = {}, int nt = 0) {
   typedef typename Half<BF>::V V;
   const int MT = tab.Pp / 8, KC = beam_h16_chunks(tab.Pp), rpw = big_rpw(MT);
-  nt = big_nt_or(nt, rpw);
+  nt = h16_nt_or(nt, rpw);
   // steering entries scaled towards unit magnitude (|a_p| = P^-1/2): a power of two
   int ex = 0;
   (void)frexpf(sqrtf((float)tab.Pp), &ex);
@@ -1187,8 +1233,8 @@ static hipError_t launch_h16(const void* frag, const float* scale, const Tables&
     H16_RPW(2)
     H16_RPW(3)
     H16_RPW(4)
-    H16_RPW(5)
-    H16_RPW(6)
+    H16_RPW_LARGE(5)
+    H16_RPW_LARGE(6)
     H16_RPW_LARGE(7)
     H16_RPW_LARGE(8)
     H16_RPW_LARGE(9)

@@ -378,6 +378,9 @@ size_t beam_big_frag_floats(int P);
 // gives the largest grid
 int beam_big_grid(int P, int Q, int nt = 0);
 constexpr int kBigTileChoices[3] = {2, 4, 8};
+// tile counts built for rpw row tiles per wave: 2, 4, and 8 up to rpw 6
+// (FP32) or 4 (split half precision, whose block operands stay in LDS)
+bool beam_tiles_offered(bool half, int nt, int rpw);
 hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st, Stamps ts = {});
 // kind: 0 MF (+ threshold), 1 MVDR bound, 2 store (scaled), 3 multipliers with argmin keys
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,

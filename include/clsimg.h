@@ -52,6 +52,8 @@ extern "C" {
 #define CLSIMG_ENOMEM (-3)   /* workspace would exceed the context's HBM budget          */
 #define CLSIMG_EHIP (-4)     /* a HIP runtime call failed                                */
 #define CLSIMG_ENOTSUP (-5)  /* option not available for this problem (see cost below)   */
+#define CLSIMG_EWORKSPACE (-6) /* a device buffer a call needs was missing or too small */
+                               /* (checked before any launch; an internal error)        */
 
 /* bound kinds for clsimg_opts.bound */
 #define CLSIMG_BOUND_MVDR 0  /* gamma = C / (a^H R^-1 a) (+ kappa_b std), Sec. II-D  */
@@ -74,6 +76,21 @@ extern "C" {
                              /* h_i = a_i^H R^-1 a_i; threshold kappa_d std of the MVDR   */
                              /* image (App. A).  Needs P <= 48 and free sets that fit one */
                              /* workgroup (CLSIMG_ENOTSUP otherwise).                     */
+
+/* loop driving the Table I iteration (clsimg_opts.loop); both give the same
+ * iterates and results */
+#define CLSIMG_LOOP_AUTO 0   /* on the device for P <= 48 (continued on the host if the  */
+                             /* free set outgrows one workgroup), host-driven beyond     */
+#define CLSIMG_LOOP_HOST 1   /* host-driven for every P (measurement, tests)             */
+
+/* LSQR engine of the host-driven loop (clsimg_opts.lsqr_engine); every engine
+ * computes the same iterates, an engine that does not fit the problem falls
+ * back to the next one down the list */
+#define CLSIMG_LSQR_AUTO 0        /* the first that fits, in the order below            */
+#define CLSIMG_LSQR_ONE_WG 1      /* one workgroup, free set in LDS (P <= 48)            */
+#define CLSIMG_LSQR_COOP 2        /* one cooperative multi-workgroup kernel (P <= 96)    */
+#define CLSIMG_LSQR_TWO_KERNEL 3  /* two kernels per LSQR step (P <= 96); beyond, the    */
+                                  /* correlation with separate reductions and adjoint    */
 
 /* pixel states in clsimg_solve's `state` output */
 #define CLSIMG_STATE_L 0     /* sigma_i = 0        */
@@ -110,6 +127,13 @@ typedef struct {
   int32_t max_outer;      /* subproblem solves, -1 = 4Q                         */
   int32_t precision;      /* CLSIMG_FP32 | CLSIMG_FP16 | CLSIMG_BF16            */
   int32_t cost;           /* CLSIMG_COST_*                           (LS)       */
+  int32_t loop;           /* CLSIMG_LOOP_*                           (AUTO)     */
+  int32_t lsqr_engine;    /* CLSIMG_LSQR_* of the host-driven loop   (AUTO)     */
+  int32_t hand_over_free; /* device loop, batches and server slots: continue on */
+                          /* the host once |F| exceeds this; 0 = only when F    */
+                          /* outgrows one workgroup                   (0)       */
+  int32_t trace;          /* 1: host-driven loop with one line per Table I step */
+                          /* on stderr                                (0)       */
 } clsimg_opts;
 
 typedef struct {

@@ -19,10 +19,12 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libclsimg.so")
 
 OK, WMAXOUTER, WITNLIM, WCYCLE = 0, 1, 2, 3
-EINVAL, ENOTPD, ENOMEM, EHIP, ENOTSUP = -1, -2, -3, -4, -5
+EINVAL, ENOTPD, ENOMEM, EHIP, ENOTSUP, EWORKSPACE = -1, -2, -3, -4, -5, -6
 BOUND_MVDR, BOUND_MF, BOUND_NONE = 0, 1, 2
 FP32, FP16, BF16 = 0, 1, 2
 COST_LS, COST_PWLS = 0, 1
+LOOP_AUTO, LOOP_HOST = 0, 1
+LSQR_AUTO, LSQR_ONE_WG, LSQR_COOP, LSQR_TWO_KERNEL = 0, 1, 2, 3
 STATE_L, STATE_F, STATE_U = 0, 1, 2
 MAX_P = 288
 
@@ -45,7 +47,9 @@ class COpts(C.Structure):
     _fields_ = [("bound", C.c_int32), ("C", C.c_double), ("kappa_b", C.c_double),
                 ("kappa_d", C.c_double), ("nsamples", C.c_int64), ("atol", C.c_double),
                 ("btol", C.c_double), ("conlim", C.c_double), ("itnlim", C.c_int32),
-                ("max_outer", C.c_int32), ("precision", C.c_int32), ("cost", C.c_int32)]
+                ("max_outer", C.c_int32), ("precision", C.c_int32), ("cost", C.c_int32),
+                ("loop", C.c_int32), ("lsqr_engine", C.c_int32), ("hand_over_free", C.c_int32),
+                ("trace", C.c_int32)]
 
 
 class CStats(C.Structure):
@@ -149,17 +153,23 @@ class Options:
     max_outer: int = -1
     precision: int = FP32
     cost: int = COST_LS
+    loop: int = LOOP_AUTO
+    lsqr_engine: int = LSQR_AUTO
+    hand_over_free: int = 0
+    trace: int = 0
 
     def to_c(self) -> COpts:
         return COpts(self.bound, self.C, self.kappa_b, self.kappa_d, self.nsamples, self.atol,
-                     self.btol, self.conlim, self.itnlim, self.max_outer, self.precision, self.cost)
+                     self.btol, self.conlim, self.itnlim, self.max_outer, self.precision, self.cost,
+                     self.loop, self.lsqr_engine, self.hand_over_free, self.trace)
 
 
 def default_options() -> Options:
     o = COpts()
     lib().clsimg_default_opts(C.byref(o))
     return Options(o.bound, o.C, o.kappa_b, o.kappa_d, o.nsamples, o.atol, o.btol, o.conlim,
-                   o.itnlim, o.max_outer, o.precision, o.cost)
+                   o.itnlim, o.max_outer, o.precision, o.cost, o.loop, o.lsqr_engine, o.hand_over_free,
+                   o.trace)
 
 
 def _ptr(t):

@@ -13,6 +13,7 @@
 #include "../../include/clsimg.h"
 #include "kernels.h"
 #include "request.h"
+#include "workspace.h"
 
 using namespace clsimg;
 
@@ -23,11 +24,6 @@ namespace {
 // partial count
 constexpr int kCandCap = 16384;
 constexpr int kCandAbsParts = 256;
-
-struct DevBuf {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
 
 struct TableKey {
   int P = -1;
@@ -68,12 +64,7 @@ struct clsimg_ctx {
   LsqrState* h_lsqr = nullptr;
   int* h_status = nullptr;
   double* h_norms = nullptr;
-  bool trace = false;  // CLSIMG_TRACE=1: one line per active-set step on stderr
   bool coop = false;   // cooperative launches available (multi-workgroup LSQR kernel)
-  int lsqr_path = 0;   // CLSIMG_LSQR_PATH: 0 auto, 1 one workgroup, 2 cooperative, 3 two kernels/step
-  bool old_beam = false;   // CLSIMG_LDS_BEAM=1: LDS-staged beamformer for the gradient
-  bool beam_prep = false;  // CLSIMG_BEAM_PREP=1: beamformer fragments from a separate pass
-  bool host_loop = false;  // CLSIMG_HOST_LOOP=1: active-set loop driven from the host
   int prec = CLSIMG_FP32;  // arithmetic of the full-grid beamforming products of the current call
   // K covariance blocks: per-block tables and vectors; tables_of() reads the
   // override while a block's operators run
@@ -84,7 +75,6 @@ struct clsimg_ctx {
   size_t h_mnorm_n = 0;
   DevBuf frag_h, hscale;   // half-precision fragments and their scale
   DevBuf mx_abs, mx_lam, mx_cand, mx_count;  // refined multipliers: |W| partials, lam~, candidates
-  int outer_max_f = 1 << 30;  // CLSIMG_OUTER_MAXF: hand over to the host loop beyond this |F|
   void* scratch = nullptr;    // this device's copy of the static workspace (allocation-free calls)
   // device time of the host-driven loop's multiplier kernel (clsimg_kernel_timing)
   bool time_mult = false;
@@ -382,13 +372,9 @@ int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamK
                             nullptr, nullptr, st, last, big_tiles(c, P)));
     return CLSIMG_OK;
   }
-  // fragments built inside the kernel, or prepared by a separate pass
-  const float* fb = c->beam_prep ? P_<float>(c->frag_b) : nullptr;
-  const float2* Uk = c->beam_prep ? nullptr : U;
-  if (c->beam_prep) {
-    HIP_TRY(launch_beam_prep(U, P, P_<float>(c->frag_b), st, first));
-    ts = last;
-  }
+  // fragments built inside the kernel
+  const float* fb = nullptr;
+  const float2* Uk = U;
   switch (kind) {
     case BEAM_MF: HIP_TRY(launch_beam_mf(fb, Uk, P, tab, out, eps, eps_scale, st, ts)); break;
     case BEAM_MVDR: HIP_TRY(launch_beam_mvdr(fb, Uk, P, tab, out, C, kb, st)); break;
@@ -457,8 +443,14 @@ int check_opts(const clsimg_opts* o, int P) {
   }
   if (!(o->kappa_d >= 0.0) || !(o->kappa_b >= 0.0)) return CLSIMG_EINVAL;
   if (!(o->atol >= 0.0) || !(o->btol >= 0.0) || !(o->conlim > 0.0)) return CLSIMG_EINVAL;
+  if (o->loop != CLSIMG_LOOP_AUTO && o->loop != CLSIMG_LOOP_HOST) return CLSIMG_EINVAL;
+  if (o->lsqr_engine < CLSIMG_LSQR_AUTO || o->lsqr_engine > CLSIMG_LSQR_TWO_KERNEL) return CLSIMG_EINVAL;
+  if (o->hand_over_free < 0 || (o->trace != 0 && o->trace != 1)) return CLSIMG_EINVAL;
   return CLSIMG_OK;
 }
+
+// largest free set a device-resident loop keeps before continuing on the host
+int hand_over_limit(const clsimg_opts* o) { return o->hand_over_free > 0 ? o->hand_over_free : (1 << 30); }
 
 }  // namespace
 
@@ -543,7 +535,7 @@ int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* 
   const int nblk = beam_grid_batched(Q, L.tiles);
   if (nblk > L.nkeys) return CLSIMG_EINVAL;
   if (defer) {
-    if (pwls || !rinv || o->bound != CLSIMG_BOUND_MVDR || c->prec != CLSIMG_FP32 || !beam_fits(P) || c->beam_prep)
+    if (pwls || !rinv || o->bound != CLSIMG_BOUND_MVDR || c->prec != CLSIMG_FP32 || !beam_fits(P))
       return CLSIMG_EINVAL;
     const double kb = o->kappa_b != 0.0 ? o->kappa_b / sqrt((double)(o->nsamples - P - 1)) : 0.0;
     *defer->beam = BeamSetItem{Rf, rinv, tab, mf, eps, gamma, eps_scale, o->C, kb, P, nblk};
@@ -604,7 +596,7 @@ int request_setup(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, char* 
   op.conlim = o->conlim;
   op.itnlim = o->itnlim;
   op.max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
-  op.max_f = c->outer_max_f;
+  op.max_f = hand_over_limit(o);
   op.Lw = Lw;
   op.rowscale = rowscale;
   it.U = op.E;
@@ -673,6 +665,10 @@ void clsimg_default_opts(clsimg_opts* o) {
   o->max_outer = -1;
   o->precision = CLSIMG_FP32;
   o->cost = CLSIMG_COST_LS;
+  o->loop = CLSIMG_LOOP_AUTO;
+  o->lsqr_engine = CLSIMG_LSQR_AUTO;
+  o->hand_over_free = 0;
+  o->trace = 0;
 }
 
 int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
@@ -685,21 +681,9 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   if (!c) return CLSIMG_ENOMEM;
   c->device = device;
   c->budget = budget;
-  const char* tr = getenv("CLSIMG_TRACE");
-  c->trace = tr && tr[0] == '1';
   int coop = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess)
     c->coop = coop != 0;
-  const char* lp = getenv("CLSIMG_LSQR_PATH");
-  if (lp) c->lsqr_path = atoi(lp);
-  const char* ob = getenv("CLSIMG_LDS_BEAM");
-  c->old_beam = ob && ob[0] == '1';
-  const char* bp = getenv("CLSIMG_BEAM_PREP");
-  c->beam_prep = bp && bp[0] == '1';
-  const char* hl = getenv("CLSIMG_HOST_LOOP");
-  c->host_loop = hl && hl[0] == '1';
-  const char* mf_ = getenv("CLSIMG_OUTER_MAXF");
-  if (mf_) c->outer_max_f = atoi(mf_);
   void* hp = nullptr;
   // room for the norm partials of the largest array (reduce_blocks grows as P^2)
   const int nnorm = reduce_blocks(CLSIMG_MAX_P);
@@ -768,6 +752,7 @@ const char* clsimg_strerror(int s) {
     case CLSIMG_ENOMEM: return "workspace exceeds the HBM budget or allocation failed";
     case CLSIMG_EHIP: return "HIP runtime error";
     case CLSIMG_ENOTSUP: return "option not available for this problem size";
+    case CLSIMG_EWORKSPACE: return "device workspace missing or too small (internal check)";
     default: return "unknown status";
   }
 }
@@ -989,6 +974,657 @@ int clsimg_adjoint(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, c
   return CLSIMG_OK;
 }
 
+namespace {
+
+// The sets' index lists F and U and their sizes (dec->nF, dec->nU), after
+// checking that the lists and the decision record exist at the sizes the
+// compaction writes.
+int compact(clsimg_ctx* c, const uint8_t* state, int Q, hipStream_t st) {
+  ST_TRY(need_all({{&c->Flist, (size_t)Q * sizeof(int)}, {&c->Ulist, (size_t)Q * sizeof(int)},
+                   {&c->dec, sizeof(SolveDecision)}}));
+  HIP_TRY(launch_compact(state, Q, P_<int>(c->Flist), P_<int>(c->Ulist), P_<SolveDecision>(c->dec), st));
+  return CLSIMG_OK;
+}
+
+// What the phases of clsimg_solve share: set-up (images, bound, data, the
+// starting sets), the device-resident loop (Table I on the device), the
+// host-driven loop (one subproblem per round trip) and the statistics.
+struct SolveRun {
+  clsimg_ctx* c = nullptr;
+  const clsimg_grid* g = nullptr;
+  const clsimg_opts* o = nullptr;
+  hipStream_t st = nullptr;
+  int P = 0, Q = 0, MT = 0, nbeta = 0, nfw = 0, ntiles_Q = 0, max_outer = 0, cand_cap = 0, cand_tile = 0;
+  bool pwls = false, device_loop = false, fused = false, beam_half = false, beam_full_grid = false,
+       beam_big_grid_ok = false;
+  // device buffers
+  float *sigma = nullptr, *mf = nullptr, *gamma = nullptr, *eps = nullptr;
+  uint8_t* state = nullptr;
+  float2 *B0 = nullptr, *Bb = nullptr, *u = nullptr, *E = nullptr;
+  int *Flist = nullptr, *Ulist = nullptr, *done = nullptr, *lerr = nullptr;
+  float *v = nullptr, *w = nullptr, *x = nullptr, *x1 = nullptr, *w1 = nullptr, *vraw = nullptr, *xf = nullptr;
+  float *frag_r = nullptr, *frag_u = nullptr;
+  double *beta_part = nullptr, *alpha_part = nullptr, *bparts[2] = {nullptr, nullptr};
+  uint64_t* keys = nullptr;
+  LsqrState *ls = nullptr, *S2 = nullptr, *Sfin = nullptr;
+  SolveDecision* dec = nullptr;
+  unsigned* bar = nullptr;
+  const int* lsqr_stop = nullptr;
+  const int* grad_stop = nullptr;
+  // PWLS operands (eq. preWLS), else the LS ones
+  const float* lam_scale = nullptr;
+  const float* op_gamma = nullptr;
+  const float* op_eps = nullptr;
+  const float2* op_B0 = nullptr;
+  Stamps mult_stamps;
+  // iteration state
+  int status = CLSIMG_OK, outer = 0, adds = 0, drops = 0, lsqr_total = 0, itnlim_hits = 0, last_added = -1;
+  int nF = 0, nU = 0, batch = 4, i_min = -1, st_min = 0;
+  bool need_solve = true, host_loop = true, stop = false;
+  float lam_min = 0.f, eps_min = 0.f;
+  double margin_lambda = INFINITY, margin_z = INFINITY;
+  double flops = 0.0, b0norm = 0.0, dev_res2 = 0.0, dev_b0n2 = 0.0;
+
+  Tables tab() const { return tables_of(c, g, P); }
+  AdjParams lsqr_adj(const int* stop_flag) const {
+    AdjParams a = adj_params(c, g, P, frag_u, Flist, nF, stop_flag);
+    a.xf = xf;
+    return a;
+  }
+  // the LSQR adjoint of the split-K engine: for large arrays its rows are
+  // split over workgroups, with the correlation's partial buffer (free by
+  // then) as the workspace of the row groups' dots
+  AdjParams lsqr_adj_rows(const int* stop_flag) const {
+    AdjParams a = adj_params(c, g, P, frag_u, Flist, nF, stop_flag);
+    a.rows_part = P_<float>(c->part);
+    a.rows_cap = c->part.bytes / sizeof(float);
+    return a;
+  }
+  LsqrFwdParams fwd_params(int iter, int nalpha2) const {
+    LsqrFwdParams f;
+    f.tab = tab();
+    f.MT = MT;
+    f.P = P;
+    f.Flist = Flist;
+    f.n = nF;
+    f.S = S2;
+    f.Sfinal = Sfin;
+    f.done = done;
+    f.it = iter;
+    f.vraw = vraw;
+    f.vnorm = v;
+    f.alpha_part = alpha_part;
+    f.nalpha = nalpha2;
+    f.beta_in = bparts[iter & 1];
+    f.nbeta_in = iter == 1 ? nbeta : nfw;
+    f.beta_out = bparts[(iter + 1) & 1];
+    f.x0 = x;
+    f.x1 = x1;
+    f.w0 = w;
+    f.w1 = w1;
+    f.xf = xf;
+    f.u = u;
+    f.frag = frag_u;
+    f.ntp = MT * (MT + 1) / 2;
+    return f;
+  }
+};
+
+// Workspace, images, bound and threshold (Sec. II-D, App. A), the data B0 =
+// R - diag(noise), the starting image and sets; the PWLS inputs.
+int solve_setup(SolveRun& r, const clsimg_c32* R, const clsimg_array* a, const float* noise_diag,
+                const float* sigma0, const uint8_t* state0, float* mf_out, float* gamma_out) {
+  clsimg_ctx* c = r.c;
+  const clsimg_opts* o = r.o;
+  hipStream_t st = r.st;
+  const int P = r.P, Q = r.Q;
+  ST_TRY(ensure_workspace(c, P, Q));
+  ST_TRY(ensure(c, c->Flist, (size_t)Q * sizeof(int)));
+  ST_TRY(ensure(c, c->Ulist, (size_t)2 * Q * sizeof(int)));  // two buffers for the device loop
+  ST_TRY(ensure(c, c->ostate, sizeof(OuterState)));
+  for (DevBuf* b : {&c->v, &c->w, &c->x, &c->x1, &c->w1, &c->vraw}) ST_TRY(ensure(c, *b, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure(c, c->lsqr2, 3 * sizeof(LsqrState)));
+  ST_TRY(ensure(c, c->done, sizeof(int)));
+  ST_TRY(ensure(c, c->bar, 2 * sizeof(unsigned)));
+  const int nparts = std::max(std::max(reduce_blocks(P), lsqr_fwd_waves(P)), Q / 32 + 64);
+  ST_TRY(ensure(c, c->bpart0, (size_t)nparts * sizeof(double)));
+  ST_TRY(ensure(c, c->bpart1, (size_t)nparts * sizeof(double)));
+  const size_t nalpha_max = (size_t)(Q / 16 + 64);  // one per 16-pixel tile
+  ST_TRY(ensure(c, c->alpha_part, nalpha_max * sizeof(double)));
+
+  // PWLS runs on the device-resident loop only (P <= 48)
+  r.pwls = o->cost == CLSIMG_COST_PWLS;
+  r.device_loop = beam_fits(P) && outer_fits(P) && o->loop == CLSIMG_LOOP_AUTO && !o->trace;
+  if (r.pwls && !r.device_loop) return CLSIMG_ENOTSUP;
+  if (r.pwls && o->nsamples <= P + 1 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
+  if (r.pwls) {
+    for (DevBuf* b : {&c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv})
+      ST_TRY(ensure(c, *b, (size_t)Q * sizeof(float)));
+    ST_TRY(ensure(c, c->pw_Lw, (size_t)P * P * sizeof(float2)));
+    ST_TRY(ensure(c, c->pw_B0w, (size_t)P * P * sizeof(float2)));
+  }
+  ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
+  if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
+  if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
+  ST_TRY(ensure_tables(c, a, r.g, st));
+
+  r.MT = pad_p(P) / 8;
+  r.fused = r.MT <= 12;  // the two-kernel LSQR step and its free-set cache up to 12 row tiles (P <= 96)
+  r.nbeta = reduce_blocks(P);
+  r.nfw = lsqr_fwd_waves(P);
+  r.ntiles_Q = ntiles_adj(P, Q);
+  r.max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
+  r.beam_full_grid = beam_fits(P);
+  r.beam_big_grid_ok = !beam_fits(P) && beam_big_fits(P);
+  // timing of the multiplier kernel (clsimg_kernel_timing): events bound to its launches
+  r.mult_stamps = c->time_mult ? Stamps{c->tm_ev[0], c->tm_ev[1]} : Stamps{};
+  // reduced precision: the multipliers from one half-precision product, the
+  // decision refined in FP32 over the candidates the rounding bound leaves
+  r.beam_half = c->prec != CLSIMG_FP32;
+  r.cand_cap = std::max(64, std::min(Q / 8, kCandCap));
+  r.cand_tile = adjoint_tile_width(r.MT);
+  if (r.beam_half) {
+    ST_TRY(ensure(c, c->frag_h, std::max(beam_h16_frag_bytes(P), beam_h1_frag_bytes(P))));
+    ST_TRY(ensure(c, c->hscale, sizeof(float)));
+    ST_TRY(ensure(c, c->mx_abs, kCandAbsParts * sizeof(double)));
+    ST_TRY(ensure(c, c->mx_lam, (size_t)Q * sizeof(float)));
+    ST_TRY(ensure(c, c->mx_cand, (size_t)r.cand_cap * sizeof(int)));
+    ST_TRY(ensure(c, c->mx_count, sizeof(int)));
+    const size_t nk = (size_t)std::max(beam_big_grid(P, Q, 2), (r.cand_cap + r.cand_tile - 1) / r.cand_tile) + 1;
+    if (c->keys.bytes < nk * sizeof(uint64_t)) ST_TRY(ensure(c, c->keys, nk * sizeof(uint64_t)));
+    const size_t rows = (size_t)((r.MT + 3) / 4) * 8 * r.cand_cap;  // row groups x K slices x list
+    if (c->part.bytes < rows * sizeof(float)) ST_TRY(ensure(c, c->part, rows * sizeof(float)));
+  }
+  // every buffer the phases launch with, at the sizes their kernels assume
+  const size_t fq = (size_t)Q * sizeof(float), cx = (size_t)P * P * sizeof(float2);
+  ST_TRY(need_all({{&c->B0, cx},
+                   {&c->Bb, cx},
+                   {&c->u, cx},
+                   {&c->E, cx},
+                   {&c->Flist, (size_t)Q * sizeof(int)},
+                   {&c->Ulist, (size_t)2 * Q * sizeof(int)},
+                   {&c->v, fq},
+                   {&c->w, fq},
+                   {&c->x, fq},
+                   {&c->x1, fq},
+                   {&c->w1, fq},
+                   {&c->vraw, fq},
+                   {&c->eps, fq},
+                   {&c->frag_r, (size_t)4 * pad_p(P) * pad_p(P) * sizeof(float)},
+                   {&c->frag_u, (size_t)4 * pad_p(P) * pad_p(P) * sizeof(float)},
+                   {&c->beta_part, (size_t)r.nbeta * sizeof(double)},
+                   {&c->alpha_part, nalpha_max * sizeof(double)},
+                   {&c->bpart0, (size_t)nparts * sizeof(double)},
+                   {&c->bpart1, (size_t)nparts * sizeof(double)},
+                   {&c->keys, (size_t)(std::max(r.ntiles_Q, beam_grid(Q)) + 1) * sizeof(uint64_t)},
+                   {&c->lsqr, sizeof(LsqrState)},
+                   {&c->lsqr2, 3 * sizeof(LsqrState)},
+                   {&c->dec, sizeof(SolveDecision)},
+                   {&c->done, sizeof(int)},
+                   {&c->bar, 2 * sizeof(unsigned)},
+                   {&c->ostate, sizeof(OuterState)}}));
+  if (!mf_out) ST_TRY(need_all({{&c->mf, fq}}));
+  if (!gamma_out) ST_TRY(need_all({{&c->gamma, fq}}));
+  if (r.beam_half)
+    ST_TRY(need_all({{&c->mx_lam, fq}, {&c->mx_cand, (size_t)r.cand_cap * sizeof(int)}, {&c->mx_count, sizeof(int)},
+                     {&c->mx_abs, kCandAbsParts * sizeof(double)}, {&c->hscale, sizeof(float)}}));
+
+  r.mf = mf_out ? mf_out : P_<float>(c->mf);
+  r.gamma = gamma_out ? gamma_out : P_<float>(c->gamma);
+  r.eps = P_<float>(c->eps);
+  r.B0 = P_<float2>(c->B0);
+  r.Bb = P_<float2>(c->Bb);
+  r.u = P_<float2>(c->u);
+  r.E = P_<float2>(c->E);
+  r.Flist = P_<int>(c->Flist);
+  r.Ulist = P_<int>(c->Ulist);
+  r.v = P_<float>(c->v);
+  r.w = P_<float>(c->w);
+  r.x = P_<float>(c->x);
+  r.x1 = P_<float>(c->x1);
+  r.w1 = P_<float>(c->w1);
+  r.vraw = P_<float>(c->vraw);
+  r.xf = P_<float>(c->xf);
+  r.frag_r = P_<float>(c->frag_r);
+  r.frag_u = P_<float>(c->frag_u);
+  r.beta_part = P_<double>(c->beta_part);
+  r.alpha_part = P_<double>(c->alpha_part);
+  r.bparts[0] = P_<double>(c->bpart0);
+  r.bparts[1] = P_<double>(c->bpart1);
+  r.keys = P_<uint64_t>(c->keys);
+  r.ls = P_<LsqrState>(c->lsqr);
+  r.S2 = P_<LsqrState>(c->lsqr2);
+  r.Sfin = r.S2 + 2;
+  r.dec = P_<SolveDecision>(c->dec);
+  r.done = P_<int>(c->done);
+  r.bar = P_<unsigned>(c->bar);
+  r.lerr = reinterpret_cast<int*>(r.bar + 1);
+  r.lsqr_stop = &r.ls->done;
+  r.grad_stop = &r.dec->grad_done;
+
+  const float2* Rf = reinterpret_cast<const float2*>(R);
+  r.flops = beam_flops(P, Q) + (o->bound != CLSIMG_BOUND_NONE ? beam_flops(P, Q) : 0.0);
+  // bounds and threshold (Sec. II-D, App. A)
+  const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
+  if (beam_any(P)) {
+    ST_TRY(beam_full(c, r.g, P, Rf, BEAM_MF, r.mf, r.eps, eps_scale, 0, 0, 1.f, st));
+  } else {
+    HIP_TRY(launch_adjoint_mf(adj_params(c, r.g, P, nullptr, nullptr, Q, nullptr, Rf), r.mf, r.eps, eps_scale,
+                              st));
+  }
+  ST_TRY(compute_bound(c, R, a, r.g, o, r.gamma, st));
+  // data B0 = R - diag(noise), its norm, the starting image and sets
+  HIP_TRY(launch_sub_diag(Rf, noise_diag, P, r.B0, st));
+  ST_TRY(correlate(c, r.g, P, nullptr, nullptr, 0, 0, r.E, r.B0, 0.f, 1.f, nullptr, nullptr, r.beta_part, nullptr,
+                   st));
+  HIP_TRY(hipMemcpyAsync(c->h_norms, r.beta_part, r.nbeta * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(launch_init_state(sigma0, state0, r.sigma, r.state, Q, st));
+  ST_TRY(compact(c, r.state, Q, st));
+  ST_TRY(read_back(c, c->h_dec, r.dec, sizeof(SolveDecision), st));
+  r.b0norm = sqrt(sum_host(c->h_norms, r.nbeta));
+  r.nF = c->h_dec->nF;
+  r.nU = c->h_dec->nU;
+
+  // PWLS inputs (eq. preWLS): Cholesky of R, h = a^H R^-1 a, D = h^2 / C, the
+  // whitened data, bound D gamma and the MVDR-image threshold; the loop then
+  // solves for D sigma
+  r.op_gamma = r.gamma;
+  r.op_eps = r.eps;
+  r.op_B0 = r.B0;
+  if (r.pwls) {
+    if (o->bound != CLSIMG_BOUND_MVDR) {  // the MVDR bound has factorised R already
+      HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
+                                  P_<int>(c->status), st));
+      ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
+      if (*c->h_status != 0) return CLSIMG_ENOTPD;
+    }
+    float* h = P_<float>(c->pw_h);
+    ST_TRY(beam_full(c, r.g, P, P_<const float2>(c->Rinv), BEAM_STORE, h, nullptr, 0.f, 0, 0, 1.f, st));
+    const double kd = o->kappa_d != 0.0 ? o->kappa_d / sqrt((double)(o->nsamples - P - 1)) : 0.0;
+    HIP_TRY(launch_pwls_setup(h, r.gamma, o->C, kd, Q, P_<float>(c->pw_rs), P_<float>(c->pw_g),
+                              P_<float>(c->pw_eps), P_<float>(c->pw_dinv), st));
+    HIP_TRY(launch_pwls_whiten(P_<const double2>(c->Li), r.B0, P, P_<float2>(c->pw_Lw), P_<float2>(c->pw_B0w), st));
+    if (sigma0) HIP_TRY(launch_pwls_scale(r.sigma, P_<const float>(c->pw_dinv), Q, true, st));  // D sigma0
+    r.lam_scale = P_<const float>(c->pw_dinv);
+    r.op_gamma = P_<const float>(c->pw_g);
+    r.op_eps = P_<const float>(c->pw_eps);
+    r.op_B0 = P_<const float2>(c->pw_B0w);
+  }
+  return CLSIMG_OK;
+}
+
+// Table I on the device: one workgroup per outer step, the full-grid
+// multiplier kernel between steps; the host only checks for the end.
+int solve_device_loop(SolveRun& r) {
+  clsimg_ctx* c = r.c;
+  hipStream_t st = r.st;
+  const clsimg_opts* o = r.o;
+  OuterState* ost = P_<OuterState>(c->ostate);
+  HIP_TRY(launch_outer_init(ost, r.dec, st));
+  OuterParams op;
+  op.st = ost;
+  op.Flist = r.Flist;
+  op.Ulist = r.Ulist;
+  op.sigma = r.sigma;
+  op.gamma = r.op_gamma;
+  op.eps = r.op_eps;
+  op.state = r.state;
+  op.B0 = r.op_B0;
+  op.Bb = r.Bb;
+  op.E = r.E;
+  op.keys = r.keys;
+  op.nkeys = beam_grid(r.Q);
+  op.tab = r.tab();
+  op.P = r.P;
+  op.Q = r.Q;
+  op.atol = o->atol;
+  op.btol = o->btol;
+  op.conlim = o->conlim;
+  op.itnlim = o->itnlim;
+  op.max_outer = r.max_outer;
+  op.max_f = hand_over_limit(o);
+  op.Lw = r.pwls ? P_<const float2>(c->pw_Lw) : nullptr;
+  op.rowscale = r.pwls ? P_<const float>(c->pw_rs) : nullptr;
+  int nb = 8;
+  for (;;) {
+    for (int b = 0; b < nb; ++b) {
+      HIP_TRY(launch_outer_step(op, st));
+      HIP_TRY(launch_beam_lambda(nullptr, r.E, r.P, op.tab, &ost->lam_skip, r.state, r.keys, r.lam_scale, st));
+    }
+    ST_TRY(read_back(c, c->h_outer, ost, sizeof(OuterState), st));
+    if (c->h_outer->done) break;
+    nb = std::min(2 * nb, 128);
+  }
+  const OuterState& S = *c->h_outer;
+  r.status = S.status == kStatusMaxOuter ? CLSIMG_WMAXOUTER : (S.status == kStatusCycle ? CLSIMG_WCYCLE : CLSIMG_OK);
+  r.outer = S.outer;
+  r.adds = S.adds;
+  r.drops = S.drops;
+  r.lsqr_total = S.lsqr_total;
+  r.itnlim_hits = S.itnlim_hits;
+  r.last_added = S.last_added;
+  r.margin_lambda = S.margin_lambda;
+  r.margin_z = S.margin_z;
+  r.nF = S.nF;
+  r.nU = S.nU;
+  r.flops += S.psi_flops;
+  // a free set too large for one workgroup: continue on the host from here
+  r.host_loop = S.fallback != 0;
+  r.dev_res2 = S.res2;
+  r.dev_b0n2 = S.b0n2;
+  if (r.pwls) {
+    if (r.host_loop) return CLSIMG_ENOTSUP;  // the host loop has no PWLS path
+    HIP_TRY(launch_pwls_scale(r.sigma, P_<const float>(c->pw_dinv), r.Q, false, st));  // sigma = D^-1 (D sigma)
+  }
+  return CLSIMG_OK;
+}
+
+// The full-grid multipliers of a feasible step (eqs. gls, etaL, etaU) from E
+// and their argmin with the detection test; `fp32_only` takes the FP32
+// kernels also in the reduced-precision modes.
+int host_multipliers(SolveRun& r, bool fp32_only) {
+  clsimg_ctx* c = r.c;
+  hipStream_t st = r.st;
+  const int P = r.P, Q = r.Q;
+  if (r.beam_half && !fp32_only) {
+    const bool bf = c->prec == CLSIMG_BF16;
+    int* count = P_<int>(c->mx_count);
+    HIP_TRY(launch_beam_lambda_refined(r.E, P, bf, r.tab(), r.grad_stop, r.state, c->frag_h.ptr,
+                                       P_<float>(c->hscale), P_<double>(c->mx_abs), kCandAbsParts, r.keys,
+                                       P_<float>(c->mx_lam), P_<int>(c->mx_cand), r.cand_cap, count, st,
+                                       big_tiles(c, P), r.mult_stamps));
+    // the candidates in FP32: Ut fragments of E from the correlation
+    AdjParams ap = adj_params(c, r.g, P, r.frag_r, P_<const int>(c->mx_cand), r.cand_cap, r.grad_stop);
+    ap.rows_part = P_<float>(c->part);
+    ap.rows_cap = c->part.bytes / sizeof(float);
+    ap.n_dev = count;
+    HIP_TRY(launch_adjoint_lambda(ap, r.state, r.keys, st));
+    HIP_TRY(launch_argmin_final(r.keys, (r.cand_cap + r.cand_tile - 1) / r.cand_tile, r.eps, r.state, r.dec, st,
+                                count, r.cand_cap));
+  } else if (r.beam_full_grid) {
+    HIP_TRY(launch_beam_lambda(nullptr, r.E, P, r.tab(), r.grad_stop, r.state, r.keys, nullptr, st));
+    HIP_TRY(launch_argmin_final(r.keys, beam_grid(Q), r.eps, r.state, r.dec, st));
+  } else if (r.beam_big_grid_ok) {
+    HIP_TRY(launch_beam_prep_full(r.E, P, P_<float>(c->frag_b), st));
+    HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), r.tab(), r.grad_stop, nullptr, nullptr, 0.f, 0, 0, 1.f,
+                            r.state, r.keys, st, fp32_only ? Stamps{} : r.mult_stamps, big_tiles(c, P)));
+    HIP_TRY(launch_argmin_final(r.keys, beam_big_grid(P, Q, big_tiles(c, P)), r.eps, r.state, r.dec, st));
+  } else {
+    HIP_TRY(launch_adjoint_lambda(adj_params(c, r.g, P, r.frag_r, nullptr, Q, r.grad_stop), r.state, r.keys, st));
+    HIP_TRY(launch_argmin_final(r.keys, r.ntiles_Q, r.eps, r.state, r.dec, st));
+  }
+  return CLSIMG_OK;
+}
+
+// One subproblem of the host-driven loop (eqs. subproblemLS, bsubproblemLS)
+// by LSQR, the step of Table I and, after a feasible step, the multipliers.
+int host_subproblem(SolveRun& r) {
+  clsimg_ctx* c = r.c;
+  const clsimg_opts* o = r.o;
+  hipStream_t st = r.st;
+  const int P = r.P, Q = r.Q, MT = r.MT;
+  const bool fused = r.fused;
+  if (r.outer >= r.max_outer) {
+    r.status = CLSIMG_WMAXOUTER;
+    r.stop = true;
+    return CLSIMG_OK;
+  }
+  ST_TRY(compact(c, r.state, Q, st));
+  // b = B0 - Psi_U gamma_U  (eq. bsubproblemLS); b = B0 while U is empty
+  const float2* bsub = r.B0;
+  if (r.nU > 0) {
+    ST_TRY(correlate(c, r.g, P, r.Ulist, r.gamma, 1, r.nU, r.Bb, r.B0, -1.f, 1.f, nullptr, nullptr, nullptr, nullptr,
+                     st));
+    bsub = r.Bb;
+  }
+  r.flops += corr_flops(P, r.nU);
+  const int nF = r.nF;
+  if (fused) {
+    // the cache grows geometrically with |F| (a reallocation synchronises the device)
+    size_t cap = 256;
+    while (cap < (size_t)nF) cap *= 2;
+    ST_TRY(ensure(c, c->xf, cap * 2 * pad_p(P) * sizeof(float)));
+    r.xf = P_<float>(c->xf);
+    HIP_TRY(launch_xf(r.tab(), r.Flist, nF, r.xf, st));
+  }
+  const int nalpha = ntiles_adj(P, nF);
+  const int nalpha2 = (nF + adjoint_lsqr2_tile_width(MT, nF) - 1) / adjoint_lsqr2_tile_width(MT, nF);
+  int it = 1;
+  // LSQR engine: one workgroup when the subproblem fits in its LDS (no grid
+  // barriers at all), else one cooperative kernel, else two kernels per
+  // step (P <= 96), else the split-K correlation with separate reductions
+  const int want = o->lsqr_engine;
+  const bool one_cu = fused && (want == CLSIMG_LSQR_AUTO || want == CLSIMG_LSQR_ONE_WG) && lsqr_cu_fits(P, nF);
+  const bool persist = !one_cu && fused && c->coop && (want == CLSIMG_LSQR_AUTO || want == CLSIMG_LSQR_COOP) &&
+                       persist_fits(P, nF);
+  if (nF > 0) {
+    const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
+    if (one_cu) {
+      HIP_TRY(launch_lsqr_setup2(r.S2, r.done, r.bar, r.lerr, o->atol, o->btol, o->conlim, itnlim, st));
+      LsqrCuParams lc;
+      lc.P = P;
+      lc.n = nF;
+      lc.xf = r.xf;
+      lc.B = bsub;
+      lc.x_out = r.x;
+      lc.Sfinal = r.Sfin;
+      lc.done = r.done;
+      lc.atol = o->atol;
+      lc.btol = o->btol;
+      lc.conlim = o->conlim;
+      lc.itnlim = itnlim;
+      HIP_TRY(launch_lsqr_cu(lc, st));
+    } else if (persist) {
+      // the whole LSQR solve in one cooperative kernel
+      HIP_TRY(launch_lsqr_setup2(r.S2, r.done, r.bar, r.lerr, o->atol, o->btol, o->conlim, itnlim, st));
+      LsqrPersistParams lp;
+      lp.MT = MT;
+      lp.P = P;
+      lp.n = nF;
+      lp.ntp = MT * (MT + 1) / 2;
+      lp.xf = r.xf;
+      lp.B = bsub;
+      lp.frag = r.frag_u;
+      lp.pbeta = r.bparts[0];
+      lp.palpha = r.alpha_part;
+      lp.vraw = r.vraw;
+      lp.x_out = r.x;
+      lp.Sfinal = r.Sfin;
+      lp.done = r.done;
+      lp.bar = r.bar;
+      lp.err = r.lerr;
+      lp.atol = o->atol;
+      lp.btol = o->btol;
+      lp.conlim = o->conlim;
+      lp.itnlim = itnlim;
+      HIP_TRY(launch_lsqr_persist(lp, st));
+    } else if (fused) {
+      // beta_1 u_1 = b ; alpha_1 v_1 = Psi_F^H u_1  (eqs. initbeta, initu); then step 1
+      HIP_TRY(launch_lsqr_setup(r.S2, r.done, o->atol, o->btol, o->conlim, itnlim, st));
+      ST_TRY(correlate(c, r.g, P, nullptr, nullptr, 0, 0, r.u, bsub, 0.f, 1.f, nullptr, r.frag_u, r.bparts[1],
+                       nullptr, st));
+      HIP_TRY(launch_adjoint_lsqr2(r.lsqr_adj(r.done), EpiLsqrV2{r.vraw, r.v, r.bparts[1], r.nbeta, r.alpha_part, 1},
+                                   st));
+      HIP_TRY(launch_lsqr_fwd(r.fwd_params(1, nalpha2), st));
+    } else {
+      ST_TRY(correlate(c, r.g, P, nullptr, nullptr, 0, 0, r.u, bsub, 0.f, 1.f, nullptr, r.frag_u, r.beta_part,
+                       nullptr, st));
+      HIP_TRY(launch_adjoint_lsqr(r.lsqr_adj_rows(nullptr), r.v, r.beta_part, r.nbeta, r.alpha_part, 1, st));
+      HIP_TRY(launch_lsqr_init_scalars(r.ls, r.beta_part, r.nbeta, r.alpha_part, nalpha, r.v, r.w, r.x, nF, o->atol,
+                                       o->btol, o->conlim, itnlim, st));
+    }
+  }
+  for (;;) {
+    if (nF > 0 && !persist && !one_cu) {
+      for (int b = 0; b < r.batch; ++b) {
+        // beta u <- Psi_F v - alpha u ; alpha v <- Psi_F^H u - beta v  (eq. lanczos)
+        if (fused) {
+          HIP_TRY(launch_adjoint_lsqr2(r.lsqr_adj(r.done),
+                                       EpiLsqrV2{r.vraw, r.v, r.bparts[(it + 1) & 1], r.nfw, r.alpha_part, 0}, st));
+          ++it;
+          HIP_TRY(launch_lsqr_fwd(r.fwd_params(it, nalpha2), st));
+        } else {
+          ST_TRY(correlate(c, r.g, P, r.Flist, r.v, 0, nF, r.u, r.u, 1.f, 0.f, r.ls, r.frag_u, r.beta_part,
+                           r.lsqr_stop, st));
+          HIP_TRY(launch_adjoint_lsqr(r.lsqr_adj_rows(r.lsqr_stop), r.v, r.beta_part, r.nbeta, r.alpha_part, 0, st));
+          HIP_TRY(launch_lsqr_update(r.ls, r.beta_part, r.nbeta, r.alpha_part, nalpha, r.v, r.w, r.x, nF, st));
+        }
+      }
+    }
+    if (persist || one_cu)
+      HIP_TRY(launch_step(r.done, r.lerr, r.Sfin, r.x, r.x, r.Flist, nF, r.sigma, r.gamma, r.state, r.dec, st));
+    else if (fused)
+      HIP_TRY(launch_step(r.done, nullptr, r.Sfin, r.x, r.x1, r.Flist, nF, r.sigma, r.gamma, r.state, r.dec, st));
+    else
+      HIP_TRY(launch_step(r.lsqr_stop, nullptr, r.ls, r.x, r.x, r.Flist, nF, r.sigma, r.gamma, r.state, r.dec, st));
+    // gradient on the active pixels, only after a feasible subproblem (eq. gls):
+    // E = Psi_F sigma_F - b, then g = Psi^H E on every pixel
+    if (fused) {
+      CorrOsParams cp;
+      cp.MT = MT;
+      cp.P = P;
+      cp.xf = r.xf;
+      cp.n = nF;
+      cp.vals = r.sigma;
+      cp.gidx = r.Flist;
+      cp.out = r.E;
+      cp.B = bsub;
+      cp.cK = 1.f;
+      cp.cB = -1.f;
+      cp.frag = r.frag_r;
+      cp.stop_flag = r.grad_stop;
+      HIP_TRY(launch_corr_os(cp, st));
+    } else {
+      ST_TRY(correlate(c, r.g, P, r.Flist, r.sigma, 1, nF, r.E, bsub, 1.f, -1.f, nullptr, r.frag_r, nullptr,
+                       r.grad_stop, st));
+    }
+    ST_TRY(host_multipliers(r, false));
+    ST_TRY(read_back(c, c->h_dec, r.dec, sizeof(SolveDecision), st));
+    const bool grad = c->h_dec->lsqr_done && c->h_dec->feasible;
+    if (r.mult_stamps.start && grad && (r.beam_half || !r.beam_full_grid)) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, c->tm_ev[0], c->tm_ev[1]));
+      c->tm_ms += ms;
+      ++c->tm_n;
+    }
+    if (r.beam_half && grad && c->h_dec->cand_overflow) {
+      // more candidates than the list holds: this step's multipliers in FP32
+      ST_TRY(host_multipliers(r, true));
+      ST_TRY(read_back(c, c->h_dec, r.dec, sizeof(SolveDecision), st));
+      if (o->trace) fprintf(stderr, "clsimg: outer %d: candidate list full, multipliers in FP32\n", r.outer);
+    }
+    if (c->h_dec->lsqr_done) break;
+    if (persist || one_cu || c->h_dec->lsqr_err) return CLSIMG_EHIP;  // LSQR kernel did not finish
+    r.batch = std::min(r.batch * 2, 64);
+  }
+  const SolveDecision d = *c->h_dec;
+  if (o->trace) {
+    ST_TRY(read_back(c, c->h_lsqr, fused ? r.Sfin : r.ls, sizeof(LsqrState), st));
+    const LsqrState& L = *c->h_lsqr;
+    fprintf(stderr,
+            "clsimg: outer %d nF %d nU %d itn %d istop %d alpha %.3e beta %.3e rnorm %.3e "
+            "arnorm %.3e anorm %.3e acond %.3e xnorm %.3e bnorm %.3e feasible %d ib %d mu %.3e "
+            "i_min %d lam %.4e eps %.4e\n",
+            r.outer, nF, r.nU, L.itn, L.istop, L.alpha, L.beta, L.rnorm, L.arnorm, L.anorm, L.acond, L.xnorm, L.bnorm,
+            d.feasible, d.ib, (double)d.mu_max, d.i_min, (double)d.lam_min, (double)d.eps_min);
+  }
+  r.batch = std::max(2, std::min(64, d.lsqr_itn + 1));
+  ++r.outer;
+  r.lsqr_total += d.lsqr_itn;
+  if (nF > 0) r.flops += beam_flops(P, nF) + d.lsqr_itn * (corr_flops(P, nF) + beam_flops(P, nF));
+  if (d.feasible) r.flops += corr_flops(P, nF) + beam_flops(P, Q);
+  if (nF > 0 && d.lsqr_istop == 7) ++r.itnlim_hits;
+  if (d.feasible) {
+    r.need_solve = false;
+    if (nF > 0) r.margin_z = std::min(r.margin_z, (double)d.margin_z);
+    if (d.i_min < 0) {  // no active pixel left
+      r.stop = true;
+      return CLSIMG_OK;
+    }
+    r.lam_min = d.lam_min;
+    r.eps_min = d.eps_min;
+    r.i_min = d.i_min;
+    r.st_min = d.st_min;
+  } else {
+    ++r.drops;
+    --r.nF;
+    if (d.ib_to == CLSIMG_STATE_U) ++r.nU;
+    r.need_solve = true;
+    if (d.ib == r.last_added && d.mu_max == 0.0f) {
+      r.status = CLSIMG_WCYCLE;
+      r.stop = true;
+      return CLSIMG_OK;
+    }
+  }
+  r.last_added = -1;
+  return CLSIMG_OK;
+}
+
+// Table I driven from the host: subproblems, and after each feasible one the
+// detection test on the most negative multiplier (release into F or stop).
+int solve_host_loop(SolveRun& r) {
+  while (!r.stop) {
+    if (r.need_solve) {
+      ST_TRY(host_subproblem(r));
+      continue;
+    }
+    if (r.eps_min > 0.f) r.margin_lambda = std::min(r.margin_lambda, fabs((double)r.lam_min + r.eps_min) / r.eps_min);
+    if (!(r.lam_min < -r.eps_min)) break;
+    HIP_TRY(launch_set_state(r.state, r.i_min, (uint8_t)CLSIMG_STATE_F, r.st));
+    ++r.adds;
+    ++r.nF;
+    if (r.st_min == CLSIMG_STATE_U) --r.nU;
+    r.last_added = r.i_min;
+    r.need_solve = true;
+  }
+  return CLSIMG_OK;
+}
+
+// Statistics; after the host-driven loop the final residual ||B0 - Psi sigma||_F
+// is formed from the final sets (the device loop keeps that of its last
+// feasible step, which is the final image).
+int solve_stats(SolveRun& r, clsimg_stats* stats) {
+  clsimg_ctx* c = r.c;
+  if (r.status == CLSIMG_OK && r.itnlim_hits) r.status = CLSIMG_WITNLIM;
+  double res2 = r.dev_res2;
+  const double b0n2 = r.dev_b0n2;
+  if (r.host_loop) {
+    ST_TRY(compact(c, r.state, r.Q, r.st));
+    ST_TRY(read_back(c, c->h_dec, r.dec, sizeof(SolveDecision), r.st));
+    r.nF = c->h_dec->nF;
+    r.nU = c->h_dec->nU;
+    ST_TRY(correlate(c, r.g, r.P, r.Ulist, r.gamma, 1, r.nU, r.Bb, r.B0, -1.f, 1.f, nullptr, nullptr, nullptr,
+                     nullptr, r.st));
+    ST_TRY(correlate(c, r.g, r.P, r.Flist, r.sigma, 1, r.nF, r.E, r.Bb, 1.f, -1.f, nullptr, nullptr, r.beta_part,
+                     nullptr, r.st));
+    ST_TRY(read_back(c, c->h_norms, r.beta_part, r.nbeta * sizeof(double), r.st));
+    res2 = sum_host(c->h_norms, r.nbeta);
+    r.flops += corr_flops(r.P, r.nU) + corr_flops(r.P, r.nF);
+  }
+  stats->status = r.status;
+  stats->outer_iters = r.outer;
+  stats->adds = r.adds;
+  stats->drops = r.drops;
+  stats->lsqr_iters_total = r.lsqr_total;
+  stats->lsqr_itnlim_hits = r.itnlim_hits;
+  stats->nF = r.nF;
+  stats->nU = r.nU;
+  if (r.host_loop) {
+    const double rn = sqrt(res2);
+    stats->rel_residual = r.b0norm > 0 ? rn / r.b0norm : 0.0;
+    stats->objective = 0.5 * rn * rn;
+  } else {
+    stats->rel_residual = b0n2 > 0.0 ? sqrt(res2 / b0n2) : 0.0;
+    stats->objective = 0.5 * res2;
+  }
+  stats->min_margin_lambda = r.margin_lambda;
+  stats->min_margin_z = r.margin_z;
+  stats->psi_flops = r.flops;
+  return r.status;
+}
+
+}  // namespace
+
 int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, const clsimg_grid* g,
                  const float* noise_diag, const clsimg_opts* o, const float* sigma0,
                  const uint8_t* state0, float* sigma, uint8_t* state, float* mf_out,
@@ -1001,554 +1637,19 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   if (o->nsamples <= 0 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
   c->prec = o->precision;
   DeviceGuard guard(c->device);
-  hipStream_t st = (hipStream_t)stream;
-  const int P = a->P, Q = g->nl * g->nm;
-  ST_TRY(ensure_workspace(c, P, Q));
-  ST_TRY(ensure(c, c->Flist, (size_t)Q * sizeof(int)));
-  ST_TRY(ensure(c, c->Ulist, (size_t)2 * Q * sizeof(int)));  // two buffers for the device loop
-  ST_TRY(ensure(c, c->ostate, sizeof(OuterState)));
-  ST_TRY(ensure(c, c->v, (size_t)Q * sizeof(float)));
-  ST_TRY(ensure(c, c->w, (size_t)Q * sizeof(float)));
-  ST_TRY(ensure(c, c->x, (size_t)Q * sizeof(float)));
-  ST_TRY(ensure(c, c->x1, (size_t)Q * sizeof(float)));
-  ST_TRY(ensure(c, c->w1, (size_t)Q * sizeof(float)));
-  ST_TRY(ensure(c, c->vraw, (size_t)Q * sizeof(float)));
-  ST_TRY(ensure(c, c->lsqr2, 3 * sizeof(LsqrState)));
-  ST_TRY(ensure(c, c->done, sizeof(int)));
-  ST_TRY(ensure(c, c->bar, 2 * sizeof(unsigned)));
-  {
-    const int nparts = std::max(std::max(reduce_blocks(P), lsqr_fwd_waves(P)), Q / 32 + 64);
-    const size_t nb = (size_t)nparts * sizeof(double);
-    ST_TRY(ensure(c, c->bpart0, nb));
-    ST_TRY(ensure(c, c->bpart1, nb));
-  }
-  ST_TRY(ensure(c, c->alpha_part, (size_t)(Q / 16 + 64) * sizeof(double)));  // one per 16-pixel tile
-
-  // PWLS runs on the device-resident loop only (P <= 48)
-  const bool pwls = o->cost == CLSIMG_COST_PWLS;
-  const bool device_loop = beam_fits(P) && outer_fits(P) && !c->old_beam && !c->host_loop && !c->trace;
-  if (pwls && !device_loop) return CLSIMG_ENOTSUP;
-  if (pwls && o->nsamples <= P + 1 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
-  if (pwls) {
-    for (DevBuf* b : {&c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv})
-      ST_TRY(ensure(c, *b, (size_t)Q * sizeof(float)));
-    ST_TRY(ensure(c, c->pw_Lw, (size_t)P * P * sizeof(float2)));
-    ST_TRY(ensure(c, c->pw_B0w, (size_t)P * P * sizeof(float2)));
-  }
-  ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
-  if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
-  if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
-  ST_TRY(ensure_tables(c, a, g, st));
-  float* mf = mf_out ? mf_out : P_<float>(c->mf);
-  float* gamma = gamma_out ? gamma_out : P_<float>(c->gamma);
-  float* eps = P_<float>(c->eps);
-  const float2* Rf = reinterpret_cast<const float2*>(R);
-  float2* B0 = P_<float2>(c->B0);
-  float2* Bb = P_<float2>(c->Bb);
-  float2* u = P_<float2>(c->u);
-  float2* E = P_<float2>(c->E);
-  int* Flist = P_<int>(c->Flist);
-  int* Ulist = P_<int>(c->Ulist);
-  float* v = P_<float>(c->v);
-  float* w = P_<float>(c->w);
-  float* x = P_<float>(c->x);
-  float* frag_r = P_<float>(c->frag_r);
-  float* frag_u = P_<float>(c->frag_u);
-  double* beta_part = P_<double>(c->beta_part);
-  double* alpha_part = P_<double>(c->alpha_part);
-  uint64_t* keys = P_<uint64_t>(c->keys);
-  LsqrState* ls = P_<LsqrState>(c->lsqr);
-  SolveDecision* dec = P_<SolveDecision>(c->dec);
-  const int* lsqr_stop = &ls->done;
-  const int* grad_stop = &dec->grad_done;
-  const int nbeta = reduce_blocks(P);
-  // fused two-kernel LSQR step for up to 12 row tiles (P <= 96)
-  const int MT = pad_p(P) / 8;
-  const bool fused = MT <= 12;
-  const int nfw = lsqr_fwd_waves(P);
-  LsqrState* S2 = P_<LsqrState>(c->lsqr2);
-  LsqrState* Sfin = S2 + 2;
-  int* done = P_<int>(c->done);
-  float* x1 = P_<float>(c->x1);
-  float* w1 = P_<float>(c->w1);
-  float* vraw = P_<float>(c->vraw);
-  double* bparts[2] = {P_<double>(c->bpart0), P_<double>(c->bpart1)};
-  unsigned* bar = P_<unsigned>(c->bar);
-  int* lerr = reinterpret_cast<int*>(bar + 1);
-  float* xf = P_<float>(c->xf);
-
-  double flops = beam_flops(P, Q) + (o->bound != CLSIMG_BOUND_NONE ? beam_flops(P, Q) : 0.0);
-  // bounds and threshold (Sec. II-D, App. A)
-  const float eps_scale = o->kappa_d != 0.0 ? (float)(o->kappa_d / sqrt((double)o->nsamples)) : 0.f;
-  if (beam_any(P)) {
-    ST_TRY(beam_full(c, g, P, Rf, BEAM_MF, mf, eps, eps_scale, 0, 0, 1.f, st));
-  } else {
-    HIP_TRY(launch_adjoint_mf(adj_params(c, g, P, nullptr, nullptr, Q, nullptr, Rf), mf, eps, eps_scale,
-                              st));
-  }
-  ST_TRY(compute_bound(c, R, a, g, o, gamma, st));
-  // data B0 = R - diag(noise), its norm, the starting image and sets
-  HIP_TRY(launch_sub_diag(Rf, noise_diag, P, B0, st));
-  ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, E, B0, 0.f, 1.f, nullptr, nullptr, beta_part,
-                   nullptr, st));
-  HIP_TRY(hipMemcpyAsync(c->h_norms, beta_part, nbeta * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(launch_init_state(sigma0, state0, sigma, state, Q, st));
-  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
-  ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
-  const double b0norm = sqrt(sum_host(c->h_norms, nbeta));
-  int nF = c->h_dec->nF, nU = c->h_dec->nU;
-  auto lsqr_adj = [&](const int* stop) {
-    AdjParams a = adj_params(c, g, P, frag_u, Flist, nF, stop);
-    a.xf = xf;
-    return a;
-  };
-  // the LSQR adjoint of the split-K engine: for large arrays its rows are split
-  // over workgroups, with the correlation's partial buffer (free by then) as
-  // the workspace of the row groups' dots
-  auto lsqr_adj_rows = [&](const int* stop) {
-    AdjParams a = adj_params(c, g, P, frag_u, Flist, nF, stop);
-    a.rows_part = P_<float>(c->part);
-    a.rows_cap = c->part.bytes / sizeof(float);
-    return a;
-  };
-
-  const int max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
-  int status = CLSIMG_OK;
-  int outer = 0, adds = 0, drops = 0, lsqr_total = 0, itnlim_hits = 0, last_added = -1;
-  bool need_solve = true;
-  float lam_min = 0.f, eps_min = 0.f;
-  int i_min = -1, st_min = 0;
-  double margin_lambda = INFINITY, margin_z = INFINITY;
-  int batch = 4;
-  const int ntiles_Q = ntiles_adj(P, Q);
-  const bool beam_full_grid = beam_fits(P) && !c->old_beam;
-  // timing of the multiplier kernel (clsimg_kernel_timing): events bound to its launches
-  const Stamps mult_stamps = c->time_mult ? Stamps{c->tm_ev[0], c->tm_ev[1]} : Stamps{};
-  // reduced precision: the multipliers from one half-precision product, the
-  // decision refined in FP32 over the candidates the rounding bound leaves
-  const bool beam_half = c->prec != CLSIMG_FP32;
-  const int cand_cap = std::max(64, std::min(Q / 8, kCandCap));
-  const int cand_tile = adjoint_tile_width(MT);
-  if (beam_half) {
-    ST_TRY(ensure(c, c->frag_h, std::max(beam_h16_frag_bytes(P), beam_h1_frag_bytes(P))));
-    ST_TRY(ensure(c, c->hscale, sizeof(float)));
-    ST_TRY(ensure(c, c->mx_abs, kCandAbsParts * sizeof(double)));
-    ST_TRY(ensure(c, c->mx_lam, (size_t)Q * sizeof(float)));
-    ST_TRY(ensure(c, c->mx_cand, (size_t)cand_cap * sizeof(int)));
-    ST_TRY(ensure(c, c->mx_count, sizeof(int)));
-    const size_t nk = (size_t)std::max(beam_big_grid(P, Q, 2), (cand_cap + cand_tile - 1) / cand_tile) + 1;
-    if (c->keys.bytes < nk * sizeof(uint64_t)) ST_TRY(ensure(c, c->keys, nk * sizeof(uint64_t)));
-    keys = P_<uint64_t>(c->keys);
-    const size_t rows = (size_t)((MT + 3) / 4) * 8 * cand_cap;  // row groups x K slices x list
-    if (c->part.bytes < rows * sizeof(float)) ST_TRY(ensure(c, c->part, rows * sizeof(float)));
-  }
-  const bool beam_big_grid_ok = !beam_fits(P) && beam_big_fits(P) && !c->old_beam;
-  bool host_loop = true;
-  double dev_res2 = 0.0, dev_b0n2 = 0.0;  // residual of the device loop's last feasible step
-  // PWLS inputs (eq. preWLS): Cholesky of R, h = a^H R^-1 a, D = h^2 / C, the
-  // whitened data, bound D gamma and the MVDR-image threshold; the loop then
-  // solves for D sigma
-  const float* lam_scale = nullptr;
-  const float* op_gamma = gamma;
-  const float* op_eps = eps;
-  const float2* op_B0 = B0;
-  if (pwls) {
-    if (o->bound != CLSIMG_BOUND_MVDR) {  // the MVDR bound has factorised R already
-      HIP_TRY(launch_chol_inverse(Rf, P, P_<double2>(c->W), P_<double2>(c->Li), P_<float2>(c->Rinv),
-                                  P_<int>(c->status), st));
-      ST_TRY(read_back(c, c->h_status, c->status.ptr, sizeof(int), st));
-      if (*c->h_status != 0) return CLSIMG_ENOTPD;
-    }
-    float* h = P_<float>(c->pw_h);
-    ST_TRY(beam_full(c, g, P, P_<const float2>(c->Rinv), BEAM_STORE, h, nullptr, 0.f, 0, 0, 1.f, st));
-    const double kd = o->kappa_d != 0.0 ? o->kappa_d / sqrt((double)(o->nsamples - P - 1)) : 0.0;
-    HIP_TRY(launch_pwls_setup(h, gamma, o->C, kd, Q, P_<float>(c->pw_rs), P_<float>(c->pw_g),
-                              P_<float>(c->pw_eps), P_<float>(c->pw_dinv), st));
-    HIP_TRY(launch_pwls_whiten(P_<const double2>(c->Li), B0, P, P_<float2>(c->pw_Lw), P_<float2>(c->pw_B0w), st));
-    if (sigma0) HIP_TRY(launch_pwls_scale(sigma, P_<const float>(c->pw_dinv), Q, true, st));  // D sigma0
-    lam_scale = P_<const float>(c->pw_dinv);
-    op_gamma = P_<const float>(c->pw_g);
-    op_eps = P_<const float>(c->pw_eps);
-    op_B0 = P_<const float2>(c->pw_B0w);
-  }
-  if (device_loop) {
-    // Table I on the device: one workgroup per outer step, the full-grid
-    // multiplier kernel between steps; the host only checks for the end
-    OuterState* ost = P_<OuterState>(c->ostate);
-    HIP_TRY(launch_outer_init(ost, dec, st));
-    OuterParams op;
-    op.st = ost;
-    op.Flist = Flist;
-    op.Ulist = Ulist;
-    op.sigma = sigma;
-    op.gamma = op_gamma;
-    op.eps = op_eps;
-    op.state = state;
-    op.B0 = op_B0;
-    op.Bb = Bb;
-    op.E = E;
-    op.keys = keys;
-    op.nkeys = beam_grid(Q);
-    op.tab = tables_of(c, g, P);
-    op.P = P;
-    op.Q = Q;
-    op.atol = o->atol;
-    op.btol = o->btol;
-    op.conlim = o->conlim;
-    op.itnlim = o->itnlim;
-    op.max_outer = max_outer;
-    op.max_f = c->outer_max_f;
-    op.Lw = pwls ? P_<const float2>(c->pw_Lw) : nullptr;
-    op.rowscale = pwls ? P_<const float>(c->pw_rs) : nullptr;
-    int nb = 8;
-    for (;;) {
-      for (int b = 0; b < nb; ++b) {
-        HIP_TRY(launch_outer_step(op, st));
-        HIP_TRY(launch_beam_lambda(nullptr, E, P, op.tab, &ost->lam_skip, state, keys, lam_scale, st));
-      }
-      ST_TRY(read_back(c, c->h_outer, ost, sizeof(OuterState), st));
-      if (c->h_outer->done) break;
-      nb = std::min(2 * nb, 128);
-    }
-    const OuterState& S = *c->h_outer;
-    status = S.status == kStatusMaxOuter ? CLSIMG_WMAXOUTER : (S.status == kStatusCycle ? CLSIMG_WCYCLE : CLSIMG_OK);
-    outer = S.outer;
-    adds = S.adds;
-    drops = S.drops;
-    lsqr_total = S.lsqr_total;
-    itnlim_hits = S.itnlim_hits;
-    last_added = S.last_added;
-    margin_lambda = S.margin_lambda;
-    margin_z = S.margin_z;
-    nF = S.nF;
-    nU = S.nU;
-    flops += S.psi_flops;
-    // a free set too large for one workgroup: continue on the host from here
-    host_loop = S.fallback != 0;
-    dev_res2 = S.res2;
-    dev_b0n2 = S.b0n2;
-    if (pwls) {
-      if (host_loop) return CLSIMG_ENOTSUP;  // the host loop has no PWLS path
-      HIP_TRY(launch_pwls_scale(sigma, P_<const float>(c->pw_dinv), Q, false, st));  // sigma = D^-1 (D sigma)
-    }
-  }
-  for (; host_loop;) {
-    if (need_solve) {
-      if (outer >= max_outer) {
-        status = CLSIMG_WMAXOUTER;
-        break;
-      }
-      HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
-      // b = B0 - Psi_U gamma_U  (eq. bsubproblemLS); b = B0 while U is empty
-      const float2* bsub = B0;
-      if (nU > 0) {
-        ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr,
-                         nullptr, st));
-        bsub = Bb;
-      }
-      flops += corr_flops(P, nU);
-      if (fused) {
-        // the cache grows geometrically with |F| (a reallocation synchronises the device)
-        size_t cap = 256;
-        while (cap < (size_t)nF) cap *= 2;
-        ST_TRY(ensure(c, c->xf, cap * 2 * pad_p(P) * sizeof(float)));
-        xf = P_<float>(c->xf);
-        HIP_TRY(launch_xf(tables_of(c, g, P), Flist, nF, xf, st));
-      }
-      const int nalpha = ntiles_adj(P, nF);
-      const int nalpha2 = (nF + adjoint_lsqr2_tile_width(MT, nF) - 1) / adjoint_lsqr2_tile_width(MT, nF);
-      int it = 1;
-      auto fwd_params = [&](int iter) {
-        LsqrFwdParams f;
-        f.tab = tables_of(c, g, P);
-        f.MT = MT;
-        f.P = P;
-        f.Flist = Flist;
-        f.n = nF;
-        f.S = S2;
-        f.Sfinal = Sfin;
-        f.done = done;
-        f.it = iter;
-        f.vraw = vraw;
-        f.vnorm = v;
-        f.alpha_part = alpha_part;
-        f.nalpha = nalpha2;
-        f.beta_in = bparts[iter & 1];
-        f.nbeta_in = iter == 1 ? nbeta : nfw;
-        f.beta_out = bparts[(iter + 1) & 1];
-        f.x0 = x;
-        f.x1 = x1;
-        f.w0 = w;
-        f.w1 = w1;
-        f.xf = xf;
-        f.u = u;
-        f.frag = frag_u;
-        f.ntp = MT * (MT + 1) / 2;
-        return f;
-      };
-      // LSQR engine: one workgroup when the subproblem fits in its LDS (no grid
-      // barriers at all), else one cooperative kernel, else two kernels per
-      // step (P <= 96), else the split-K correlation with separate reductions
-      const int want = c->lsqr_path;
-      const bool one_cu = fused && (want == 0 || want == 1) && lsqr_cu_fits(P, nF);
-      const bool persist = !one_cu && fused && c->coop && (want == 0 || want == 2) && persist_fits(P, nF);
-      if (nF > 0) {
-        const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
-        if (one_cu) {
-          HIP_TRY(launch_lsqr_setup2(S2, done, bar, lerr, o->atol, o->btol, o->conlim, itnlim, st));
-          LsqrCuParams lc;
-          lc.P = P;
-          lc.n = nF;
-          lc.xf = xf;
-          lc.B = bsub;
-          lc.x_out = x;
-          lc.Sfinal = Sfin;
-          lc.done = done;
-          lc.atol = o->atol;
-          lc.btol = o->btol;
-          lc.conlim = o->conlim;
-          lc.itnlim = itnlim;
-          HIP_TRY(launch_lsqr_cu(lc, st));
-        } else if (persist) {
-          // the whole LSQR solve in one cooperative kernel
-          HIP_TRY(launch_lsqr_setup2(S2, done, bar, lerr, o->atol, o->btol, o->conlim, itnlim, st));
-          LsqrPersistParams lp;
-          lp.MT = MT;
-          lp.P = P;
-          lp.n = nF;
-          lp.ntp = MT * (MT + 1) / 2;
-          lp.xf = xf;
-          lp.B = bsub;
-          lp.frag = frag_u;
-          lp.pbeta = bparts[0];
-          lp.palpha = alpha_part;
-          lp.vraw = vraw;
-          lp.x_out = x;
-          lp.Sfinal = Sfin;
-          lp.done = done;
-          lp.bar = bar;
-          lp.err = lerr;
-          lp.atol = o->atol;
-          lp.btol = o->btol;
-          lp.conlim = o->conlim;
-          lp.itnlim = itnlim;
-          HIP_TRY(launch_lsqr_persist(lp, st));
-        } else if (fused) {
-          // beta_1 u_1 = b ; alpha_1 v_1 = Psi_F^H u_1  (eqs. initbeta, initu); then step 1
-          HIP_TRY(launch_lsqr_setup(S2, done, o->atol, o->btol, o->conlim, itnlim, st));
-          ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, u, bsub, 0.f, 1.f, nullptr, frag_u,
-                           bparts[1], nullptr, st));
-          HIP_TRY(launch_adjoint_lsqr2(lsqr_adj(done), EpiLsqrV2{vraw, v, bparts[1], nbeta, alpha_part, 1},
-                                       st));
-          HIP_TRY(launch_lsqr_fwd(fwd_params(1), st));
-        } else {
-          ST_TRY(correlate(c, g, P, nullptr, nullptr, 0, 0, u, bsub, 0.f, 1.f, nullptr, frag_u, beta_part,
-                           nullptr, st));
-          HIP_TRY(launch_adjoint_lsqr(lsqr_adj_rows(nullptr), v, beta_part, nbeta, alpha_part, 1, st));
-          HIP_TRY(launch_lsqr_init_scalars(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF,
-                                           o->atol, o->btol, o->conlim, itnlim, st));
-        }
-      }
-      for (;;) {
-        if (nF > 0 && !persist && !one_cu) {
-          for (int b = 0; b < batch; ++b) {
-            // beta u <- Psi_F v - alpha u ; alpha v <- Psi_F^H u - beta v  (eq. lanczos)
-            if (fused) {
-              HIP_TRY(launch_adjoint_lsqr2(lsqr_adj(done),
-                                           EpiLsqrV2{vraw, v, bparts[(it + 1) & 1], nfw, alpha_part, 0},
-                                           st));
-              ++it;
-              HIP_TRY(launch_lsqr_fwd(fwd_params(it), st));
-            } else {
-              ST_TRY(correlate(c, g, P, Flist, v, 0, nF, u, u, 1.f, 0.f, ls, frag_u, beta_part,
-                               lsqr_stop, st));
-              HIP_TRY(launch_adjoint_lsqr(lsqr_adj_rows(lsqr_stop), v, beta_part, nbeta, alpha_part, 0, st));
-              HIP_TRY(launch_lsqr_update(ls, beta_part, nbeta, alpha_part, nalpha, v, w, x, nF, st));
-            }
-          }
-        }
-        if (persist || one_cu)
-          HIP_TRY(launch_step(done, lerr, Sfin, x, x, Flist, nF, sigma, gamma, state, dec, st));
-        else if (fused)
-          HIP_TRY(launch_step(done, nullptr, Sfin, x, x1, Flist, nF, sigma, gamma, state, dec, st));
-        else
-          HIP_TRY(launch_step(lsqr_stop, nullptr, ls, x, x, Flist, nF, sigma, gamma, state, dec, st));
-        // gradient on the active pixels, only after a feasible subproblem (eq. gls):
-        // E = Psi_F sigma_F - b, then g = Psi^H E on every pixel
-        if (fused) {
-          CorrOsParams cp;
-          cp.MT = MT;
-          cp.P = P;
-          cp.xf = xf;
-          cp.n = nF;
-          cp.vals = sigma;
-          cp.gidx = Flist;
-          cp.out = E;
-          cp.B = bsub;
-          cp.cK = 1.f;
-          cp.cB = -1.f;
-          cp.frag = frag_r;
-          cp.stop_flag = grad_stop;
-          HIP_TRY(launch_corr_os(cp, st));
-        } else {
-          ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, bsub, 1.f, -1.f, nullptr, frag_r, nullptr,
-                           grad_stop, st));
-        }
-        if (beam_half) {
-          const bool bf = c->prec == CLSIMG_BF16;
-          int* count = P_<int>(c->mx_count);
-          HIP_TRY(launch_beam_lambda_refined(E, P, bf, tables_of(c, g, P), grad_stop, state, c->frag_h.ptr,
-                                             P_<float>(c->hscale), P_<double>(c->mx_abs), kCandAbsParts, keys,
-                                             P_<float>(c->mx_lam), P_<int>(c->mx_cand), cand_cap, count, st,
-                                             big_tiles(c, P), mult_stamps));
-          // the candidates in FP32: Ut fragments of E from the correlation
-          AdjParams ap = adj_params(c, g, P, frag_r, P_<const int>(c->mx_cand), cand_cap, grad_stop);
-          ap.rows_part = P_<float>(c->part);
-          ap.rows_cap = c->part.bytes / sizeof(float);
-          ap.n_dev = count;
-          HIP_TRY(launch_adjoint_lambda(ap, state, keys, st));
-          HIP_TRY(launch_argmin_final(keys, (cand_cap + cand_tile - 1) / cand_tile, eps, state, dec, st, count,
-                                      cand_cap));
-        } else if (!beam_full_grid && beam_big_grid_ok) {
-          HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
-          HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr, 0.f,
-                                  0, 0, 1.f, state, keys, st, mult_stamps, big_tiles(c, P)));
-          HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
-        } else if (beam_full_grid) {
-          if (c->beam_prep) HIP_TRY(launch_beam_prep(E, P, P_<float>(c->frag_b), st));
-          HIP_TRY(launch_beam_lambda(c->beam_prep ? P_<const float>(c->frag_b) : nullptr,
-                                     c->beam_prep ? nullptr : E, P, tables_of(c, g, P), grad_stop, state,
-                                     keys, nullptr, st));
-          HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
-        } else {
-          HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys,
-                                        st));
-          HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
-        }
-        ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
-        if (mult_stamps.start && c->h_dec->lsqr_done && c->h_dec->feasible && (beam_half || !beam_full_grid)) {
-          float ms = 0.f;
-          HIP_TRY(hipEventElapsedTime(&ms, c->tm_ev[0], c->tm_ev[1]));
-          c->tm_ms += ms;
-          ++c->tm_n;
-        }
-        if (beam_half && c->h_dec->lsqr_done && c->h_dec->feasible && c->h_dec->cand_overflow) {
-          // more candidates than the list holds: this step's multipliers in FP32
-          if (beam_full_grid) {
-            HIP_TRY(launch_beam_lambda(nullptr, E, P, tables_of(c, g, P), grad_stop, state, keys, nullptr, st));
-            HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
-          } else if (beam_big_grid_ok) {
-            HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
-            HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tables_of(c, g, P), grad_stop, nullptr, nullptr,
-                                    0.f, 0, 0, 1.f, state, keys, st, {}, big_tiles(c, P)));
-            HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
-          } else {
-            HIP_TRY(launch_adjoint_lambda(adj_params(c, g, P, frag_r, nullptr, Q, grad_stop), state, keys, st));
-            HIP_TRY(launch_argmin_final(keys, ntiles_Q, eps, state, dec, st));
-          }
-          ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
-          if (c->trace) fprintf(stderr, "clsimg: outer %d: candidate list full, multipliers in FP32\n", outer);
-        }
-        if (c->h_dec->lsqr_done) break;
-        if (persist || one_cu || c->h_dec->lsqr_err) return CLSIMG_EHIP;  // LSQR kernel did not finish
-        batch = std::min(batch * 2, 64);
-      }
-      const SolveDecision d = *c->h_dec;
-      if (c->trace) {
-        ST_TRY(read_back(c, c->h_lsqr, fused ? Sfin : ls, sizeof(LsqrState), st));
-        const LsqrState& L = *c->h_lsqr;
-        fprintf(stderr,
-                "clsimg: outer %d nF %d nU %d itn %d istop %d alpha %.3e beta %.3e rnorm %.3e "
-                "arnorm %.3e anorm %.3e acond %.3e xnorm %.3e bnorm %.3e feasible %d ib %d mu %.3e "
-                "i_min %d lam %.4e eps %.4e\n",
-                outer, nF, nU, L.itn, L.istop, L.alpha, L.beta, L.rnorm, L.arnorm, L.anorm, L.acond,
-                L.xnorm, L.bnorm, d.feasible, d.ib, (double)d.mu_max, d.i_min, (double)d.lam_min,
-                (double)d.eps_min);
-      }
-      batch = std::max(2, std::min(64, d.lsqr_itn + 1));
-      ++outer;
-      lsqr_total += d.lsqr_itn;
-      if (nF > 0) flops += beam_flops(P, nF) + d.lsqr_itn * (corr_flops(P, nF) + beam_flops(P, nF));
-      if (d.feasible) flops += corr_flops(P, nF) + beam_flops(P, Q);
-      if (nF > 0 && d.lsqr_istop == 7) ++itnlim_hits;
-      if (d.feasible) {
-        need_solve = false;
-        if (nF > 0) margin_z = std::min(margin_z, (double)d.margin_z);
-        if (d.i_min < 0) break;  // no active pixel left
-        lam_min = d.lam_min;
-        eps_min = d.eps_min;
-        i_min = d.i_min;
-        st_min = d.st_min;
-      } else {
-        ++drops;
-        --nF;
-        if (d.ib_to == CLSIMG_STATE_U) ++nU;
-        need_solve = true;
-        if (d.ib == last_added && d.mu_max == 0.0f) {
-          status = CLSIMG_WCYCLE;
-          break;
-        }
-      }
-      last_added = -1;
-    } else {
-      if (eps_min > 0.f)
-        margin_lambda = std::min(margin_lambda, fabs((double)lam_min + eps_min) / eps_min);
-      if (lam_min < -eps_min) {
-        HIP_TRY(launch_set_state(state, i_min, (uint8_t)CLSIMG_STATE_F, st));
-        ++adds;
-        ++nF;
-        if (st_min == CLSIMG_STATE_U) --nU;
-        last_added = i_min;
-        need_solve = true;
-      } else {
-        break;
-      }
-    }
-  }
-  if (status == CLSIMG_OK && itnlim_hits) status = CLSIMG_WITNLIM;
-  if (!host_loop) {
-    // finished on the device: the residual of the last feasible step (the
-    // final image), as the batched and served solves report it
-    stats->status = status;
-    stats->outer_iters = outer;
-    stats->adds = adds;
-    stats->drops = drops;
-    stats->lsqr_iters_total = lsqr_total;
-    stats->lsqr_itnlim_hits = itnlim_hits;
-    stats->nF = nF;
-    stats->nU = nU;
-    stats->rel_residual = dev_b0n2 > 0.0 ? sqrt(dev_res2 / dev_b0n2) : 0.0;
-    stats->objective = 0.5 * dev_res2;
-    stats->min_margin_lambda = margin_lambda;
-    stats->min_margin_z = margin_z;
-    stats->psi_flops = flops;
-    return status;
-  }
-  // final residual ||B0 - Psi sigma||_F
-  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
-  ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
-  nF = c->h_dec->nF;
-  nU = c->h_dec->nU;
-  ST_TRY(correlate(c, g, P, Ulist, gamma, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr, nullptr,
-                   st));
-  ST_TRY(correlate(c, g, P, Flist, sigma, 1, nF, E, Bb, 1.f, -1.f, nullptr, nullptr, beta_part,
-                   nullptr, st));
-  ST_TRY(read_back(c, c->h_norms, beta_part, nbeta * sizeof(double), st));
-  const double rn = sqrt(sum_host(c->h_norms, nbeta));
-  stats->status = status;
-  stats->outer_iters = outer;
-  stats->adds = adds;
-  stats->drops = drops;
-  stats->lsqr_iters_total = lsqr_total;
-  stats->lsqr_itnlim_hits = itnlim_hits;
-  stats->nF = nF;
-  stats->nU = nU;
-  stats->rel_residual = b0norm > 0 ? rn / b0norm : 0.0;
-  stats->objective = 0.5 * rn * rn;
-  stats->min_margin_lambda = margin_lambda;
-  stats->min_margin_z = margin_z;
-  stats->psi_flops = flops + corr_flops(P, nU) + corr_flops(P, nF);
-  return status;
+  SolveRun r;
+  r.c = c;
+  r.g = g;
+  r.o = o;
+  r.st = (hipStream_t)stream;
+  r.P = a->P;
+  r.Q = g->nl * g->nm;
+  r.sigma = sigma;
+  r.state = state;
+  ST_TRY(solve_setup(r, R, a, noise_diag, sigma0, state0, mf_out, gamma_out));
+  if (r.device_loop) ST_TRY(solve_device_loop(r));
+  if (r.host_loop) ST_TRY(solve_host_loop(r));
+  return solve_stats(r, stats);
 }
 
 // K covariance blocks over one grid (eq. vectRtotal): the host-driven
@@ -1707,7 +1808,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   ST_TRY(read_back(c, c->h_mnorm, beta_part, (size_t)K * nbeta * sizeof(double), st));
   const double b0norm = sqrt(sum_host(c->h_mnorm, K * nbeta));
   HIP_TRY(launch_init_state(nullptr, nullptr, sigma, state, Q, st));
-  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  ST_TRY(compact(c, state, Q, st));
   ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
   int nF = c->h_dec->nF, nU = c->h_dec->nU;
 
@@ -1726,7 +1827,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
         status = CLSIMG_WMAXOUTER;
         break;
       }
-      HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+      ST_TRY(compact(c, state, Q, st));
       // b_k = B0_k - Psi_{U,k} gamma_U  (eq. bsubproblemLS per block)
       ST_TRY(corr(Ulist, gamma, 1, nU, Bbk(0), B0k(0), -1.f, 1.f, nullptr, nullptr, nullptr, nullptr));
       flops += K * corr_flops(P, nU);
@@ -1816,7 +1917,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   }
   if (status == CLSIMG_OK && itnlim_hits) status = CLSIMG_WITNLIM;
   // final residual sum_k ||B0_k - Psi_k sigma||^2
-  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  ST_TRY(compact(c, state, Q, st));
   ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
   nF = c->h_dec->nF;
   nU = c->h_dec->nU;
@@ -1949,7 +2050,7 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
         status = CLSIMG_WMAXOUTER;
         break;
       }
-      HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+      ST_TRY(compact(c, state, Q, st));
       HIP_TRY(launch_offgrid_sets(state, Q, gamma0, offsets, sigma, st));
       ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
       nF = c->h_dec->nF;
@@ -2033,7 +2134,7 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
   }
   if (status == CLSIMG_OK && itnlim_hits) status = CLSIMG_WITNLIM;
   // final sets, upper-set powers and offsets; residual ||B0 - Psi_U gamma0_U - Psi(delta)_F sigma_F||
-  HIP_TRY(launch_compact(state, Q, Flist, Ulist, dec, st));
+  ST_TRY(compact(c, state, Q, st));
   HIP_TRY(launch_offgrid_sets(state, Q, gamma0, offsets, sigma, st));
   ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
   nF = c->h_dec->nF;
@@ -2093,7 +2194,7 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   // the least-squares cost with the MVDR bound (factored below), FP32: the
   // per-request set-up launches become two batched launches
   const bool fused = !pwls && o->bound == CLSIMG_BOUND_MVDR && P <= kCholLdsMaxP &&
-                     o->precision == CLSIMG_FP32 && !c->beam_prep;
+                     o->precision == CLSIMG_FP32;
   bool shared_tables = fused;
   for (int r = 1; r < n && shared_tables; ++r) {
     const clsimg_array &a0 = reqs[0].array, &a = reqs[r].array;

@@ -250,11 +250,14 @@ def _oracle_solve(sc, atol=1e-8, btol=1e-8, noise=True, kappa_d=6.0):
     return res, mf, gamma
 
 
-def _gpu_solve(gpu_lib, ctx, sc, atol=1e-7, btol=1e-7, noise=True, kappa_d=6.0):
+def _gpu_solve(gpu_lib, ctx, sc, atol=1e-7, btol=1e-7, noise=True, kappa_d=6.0, **engine):
+    # engine: loop / lsqr_engine / hand_over_free options (every engine gives the same iterates)
     opts = gpu_lib.default_options()
     opts.nsamples = sc.N
     opts.atol, opts.btol = atol, btol
     opts.kappa_d = kappa_d
+    for k, val in engine.items():
+        setattr(opts, k, val)
     nd = _dev(sc.noise_diag, torch.float32) if noise else None
     sigma, state, mf, gamma, stats = ctx.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc),
                                                opts, noise_diag=nd)
@@ -280,22 +283,14 @@ def test_solve_c0_identical_sets(gpu_lib, ctx, scenes, noise):
 
 
 @pytest.mark.parametrize("host", [False, True])
-def test_solve_ragged_grid(gpu_lib, ctx, host, monkeypatch):
+def test_solve_ragged_grid(gpu_lib, ctx, host):
     # 40 antennas (5 row tiles, padding antennas inside the last tile pair),
     # 37 x 37 pixels: the last 16-pixel tile holds 9 pixels; device loop and
     # host loop
     sc = synth.make_scene("c1", P=40, n=37, seed=41, points=(30, ("loguniform", 0.5, 50.0)), blobs=(1, 5.0, 5.0))
     print(f"case solve ragged P={sc.P} Q={sc.Q} host={host}", flush=True)
     ref, mf_ref, gamma_ref = _oracle_solve(sc)
-    c = ctx
-    if host:
-        monkeypatch.setenv("CLSIMG_HOST_LOOP", "1")
-        c = gpu_lib.Context(0)
-    try:
-        sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, c, sc)
-    finally:
-        if host:
-            c.close()
+    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc, loop=gpu_lib.LOOP_HOST if host else 0)
     print(f"  steps {stats['outer_iters']} / {ref.outer_iters}, nF {stats['nF']}", flush=True)
     _assert_close(mf, mf_ref, what="ragged mf")
     _assert_close(gamma, gamma_ref, what="ragged gamma")
@@ -334,39 +329,28 @@ def test_solve_c1_image_error(gpu_lib, ctx, scenes):
     _assert_close(sigma, ref.sigma, what="solve sigma c1")
 
 
-@pytest.mark.parametrize("path", ["1", "2", "3"])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("name", ["c0", "c1"])
-def test_solve_each_lsqr_engine_matches_oracle(gpu_lib, scenes, name, path, monkeypatch):
+def test_solve_each_lsqr_engine_matches_oracle(gpu_lib, ctx, scenes, name, path):
     # every LSQR engine (one workgroup, one cooperative kernel, two kernels per
     # step) must reproduce the oracle's solve
-    monkeypatch.setenv("CLSIMG_LSQR_PATH", path)
-    monkeypatch.setenv("CLSIMG_HOST_LOOP", "1")
     sc = scenes[name]
     print(f"case solve {name} LSQR engine {path}", flush=True)
-    ctx2 = gpu_lib.Context(0)
-    try:
-        ref, _, _ = _oracle_solve(sc)
-        sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx2, sc)
-    finally:
-        ctx2.close()
+    ref, _, _ = _oracle_solve(sc)
+    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc, loop=gpu_lib.LOOP_HOST, lsqr_engine=path)
     print("gpu stats", stats, flush=True)
     np.testing.assert_array_equal(state, ref.state)
     _assert_close(sigma, ref.sigma, what=f"solve sigma {name} engine {path}")
 
 
 @pytest.mark.parametrize("name,maxf", [("c0", 3), ("c1", 40)])
-def test_solve_device_loop_hands_over_to_host(gpu_lib, scenes, name, maxf, monkeypatch):
+def test_solve_device_loop_hands_over_to_host(gpu_lib, ctx, scenes, name, maxf):
     # the device-resident loop stops when |F| passes maxf and the host loop
     # continues from the same sigma and state; the result must not change
-    monkeypatch.setenv("CLSIMG_OUTER_MAXF", str(maxf))
     sc = scenes[name]
     print(f"case solve {name} device loop handover at |F| > {maxf}", flush=True)
-    ctx2 = gpu_lib.Context(0)
-    try:
-        ref, _, _ = _oracle_solve(sc)
-        sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx2, sc)
-    finally:
-        ctx2.close()
+    ref, _, _ = _oracle_solve(sc)
+    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc, hand_over_free=maxf)
     print("gpu stats", stats, flush=True)
     assert int(np.sum(ref.state == 1)) > maxf  # the handover really happens
     np.testing.assert_array_equal(state, ref.state)
@@ -374,13 +358,12 @@ def test_solve_device_loop_hands_over_to_host(gpu_lib, scenes, name, maxf, monke
     assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
 
 
-@pytest.mark.parametrize("host", ["0", "1"])
+@pytest.mark.parametrize("host", [0, 1])
 @pytest.mark.parametrize("name", ["c0", "c1"])
-def test_solve_tight_bound_uses_upper_set(gpu_lib, scenes, name, host, monkeypatch):
+def test_solve_tight_bound_uses_upper_set(gpu_lib, scenes, name, host):
     # a bias factor C < 1 lowers the MVDR bound until pixels stop at it: the
     # upper set U, b = B0 - Psi_U gamma_U and the moves into and out of U are
     # exercised on the device loop (host=0) and on the host loop (host=1)
-    monkeypatch.setenv("CLSIMG_HOST_LOOP", host)
     sc = scenes[name]
     C = 0.25
     print(f"case solve {name} C={C} host loop {host}", flush=True)
@@ -397,6 +380,7 @@ def test_solve_tight_bound_uses_upper_set(gpu_lib, scenes, name, host, monkeypat
         opts.nsamples = sc.N
         opts.atol = opts.btol = 1e-7
         opts.C = C
+        opts.loop = host
         sigma, state, mf, gamma, stats = ctx2.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts,
                                                     noise_diag=_dev(sc.noise_diag, torch.float32))
     finally:
@@ -437,14 +421,14 @@ def test_solve_pwls_matches_oracle(gpu_lib, ctx, scenes, name):
     assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
 
 
-def test_pwls_without_the_device_loop_is_not_supported(gpu_lib, scenes, monkeypatch):
-    monkeypatch.setenv("CLSIMG_HOST_LOOP", "1")
+def test_pwls_without_the_device_loop_is_not_supported(gpu_lib, scenes):
     sc = scenes["c0"]
     ctx2 = gpu_lib.Context(0)
     try:
         opts = gpu_lib.default_options()
         opts.nsamples = sc.N
         opts.cost = gpu_lib.COST_PWLS
+        opts.loop = gpu_lib.LOOP_HOST
         with pytest.raises(gpu_lib.ClsimgError) as ei:
             ctx2.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts)
         assert ei.value.status == gpu_lib.ENOTSUP

@@ -133,12 +133,12 @@ def test_pwls_requests_equal_their_solves_alone(gpu_lib):
         _same(alone[i], served[i], i)
 
 
-def test_handover_beyond_the_device_capacity(gpu_lib, monkeypatch):
+def test_handover_beyond_the_device_capacity(gpu_lib):
     # a tiny free-set capacity makes every device slot hand its request to the worker
-    monkeypatch.setenv("CLSIMG_OUTER_MAXF", "3")
     scenes = _mixed_scenes(with_large=False)[:3]
     print("case server: free-set capacity 3 (hand-over to the worker)", flush=True)
     opts = _opts(gpu_lib)
+    opts.hand_over_free = 3
     served, info = _serve(gpu_lib, scenes, opts, max_slots=4)
     print("server info", info, flush=True)
     alone = _alone(gpu_lib, scenes, opts)

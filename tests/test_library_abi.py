@@ -101,3 +101,33 @@ def test_entry_points_reject_a_null_context():
     assert lib.clsimg_server_poll(n, 0, n, 0, n) == E
     assert lib.clsimg_server_query(n, n) == E
     assert lib.clsimg_server_destroy(n) == E
+
+
+def test_workspace_check_rejects_missing_or_short_buffers(tmp_path):
+    # the check every entry point makes before its first launch (workspace.h):
+    # a buffer that was never allocated, or is smaller than a kernel assumes,
+    # is an error code and not a memory fault
+    csrc = os.path.join(os.path.dirname(HEADER), "..", "paper_1505_01348_amd", "csrc")
+    src = tmp_path / "ws.cpp"
+    src.write_text("\n".join([
+        '#include "workspace.h"',
+        "#include <stdio.h>",
+        "using namespace clsimg;",
+        "int main() {",
+        "  static char mem[4096];",
+        "  DevBuf none, small, big;",
+        "  small.ptr = mem; small.bytes = 256;",
+        "  big.ptr = mem; big.bytes = 4096;",
+        '  printf("%d\\n", need_all({{&big, 4096}, {&small, 256}}));',
+        '  printf("%d\\n", need_all({{&big, 4096}, {&none, 1}}));',
+        '  printf("%d\\n", need_all({{&small, 257}}));',
+        '  printf("%d\\n", need_all({{nullptr, 0}}));',
+        '  printf("%d\\n", need_all({}));',
+        "  return 0;",
+        "}"]))
+    exe = tmp_path / "ws"
+    subprocess.run(["g++", "-std=c++17", "-I", csrc, "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    E = clsimg.EWORKSPACE
+    assert got == [clsimg.OK, E, E, E, clsimg.OK]
+    assert "workspace" in clsimg.strerror(E)

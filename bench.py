@@ -579,23 +579,33 @@ def batched_sweep(ctx, clsimg, synth, np, torch, opts, sizes, alone_stats):
     sweep = []
     for nbx in sizes:
         breqs = pool[:nbx]
-        ctx.solve_batch(breqs, opts)  # warm-up
-        torch.cuda.synchronize()
-        blat, bflops = [], 0.0
-        tb0 = time.perf_counter()
-        for _ in range(3):
-            t0 = time.perf_counter()
-            stb, resb = ctx.solve_batch(breqs, opts)
+        row = {"requests_per_call": nbx}
+        # the step launches enqueued one by one, then replayed from a captured graph
+        for mode in (0, 1):
+            opts.batch_graph = mode
+            ctx.solve_batch(breqs, opts)  # warm-up (and the capture)
             torch.cuda.synchronize()
-            blat.append(time.perf_counter() - t0)
-            bflops += sum(r[4]["psi_flops"] for r in resb)
-        tbt = time.perf_counter() - tb0
-        same0 = (resb[0][4]["rel_residual"] == alone_stats["rel_residual"] and
-                 resb[0][4]["lsqr_iters_total"] == alone_stats["lsqr_iters_total"])
-        sweep.append({"requests_per_call": nbx, "solves_per_s": round(3 * nbx / tbt, 3),
-                      "ms_per_call_p50": round(float(np.percentile(np.array(blat) * 1e3, 50)), 3),
-                      "psi_tflops_dense_count": round(bflops / tbt / 1e12, 4),
-                      "request0_same_as_alone": bool(same0 and stb >= 0)})
+            blat, bflops = [], 0.0
+            tb0 = time.perf_counter()
+            for _ in range(3):
+                t0 = time.perf_counter()
+                stb, resb = ctx.solve_batch(breqs, opts)
+                torch.cuda.synchronize()
+                blat.append(time.perf_counter() - t0)
+                bflops += sum(r[4]["psi_flops"] for r in resb)
+            tbt = time.perf_counter() - tb0
+            same0 = (resb[0][4]["rel_residual"] == alone_stats["rel_residual"] and
+                     resb[0][4]["lsqr_iters_total"] == alone_stats["lsqr_iters_total"])
+            rec = {"solves_per_s": round(3 * nbx / tbt, 3),
+                   "ms_per_call_p50": round(float(np.percentile(np.array(blat) * 1e3, 50)), 3),
+                   "psi_tflops_dense_count": round(bflops / tbt / 1e12, 4),
+                   "request0_same_as_alone": bool(same0 and stb >= 0)}
+            if mode == 0:
+                row.update(rec)
+            else:
+                row["graph_rounds"] = rec
+        opts.batch_graph = 0
+        sweep.append(row)
         log(f"bench: batched {nbx} per call: {sweep[-1]}")
     return sweep
 

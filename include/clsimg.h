@@ -134,6 +134,9 @@ typedef struct {
                           /* outgrows one workgroup                   (0)       */
   int32_t trace;          /* 1: host-driven loop with one line per Table I step */
                           /* on stderr                                (0)       */
+  int32_t batch_graph;    /* clsimg_solve_batch: 1 replays each round's step    */
+                          /* launches from a captured HIP graph, 0 enqueues     */
+                          /* them one by one (same results)           (0)       */
 } clsimg_opts;
 
 typedef struct {

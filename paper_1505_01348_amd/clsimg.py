@@ -49,7 +49,7 @@ class COpts(C.Structure):
                 ("btol", C.c_double), ("conlim", C.c_double), ("itnlim", C.c_int32),
                 ("max_outer", C.c_int32), ("precision", C.c_int32), ("cost", C.c_int32),
                 ("loop", C.c_int32), ("lsqr_engine", C.c_int32), ("hand_over_free", C.c_int32),
-                ("trace", C.c_int32)]
+                ("trace", C.c_int32), ("batch_graph", C.c_int32)]
 
 
 class CStats(C.Structure):
@@ -157,11 +157,12 @@ class Options:
     lsqr_engine: int = LSQR_AUTO
     hand_over_free: int = 0
     trace: int = 0
+    batch_graph: int = 0
 
     def to_c(self) -> COpts:
         return COpts(self.bound, self.C, self.kappa_b, self.kappa_d, self.nsamples, self.atol,
                      self.btol, self.conlim, self.itnlim, self.max_outer, self.precision, self.cost,
-                     self.loop, self.lsqr_engine, self.hand_over_free, self.trace)
+                     self.loop, self.lsqr_engine, self.hand_over_free, self.trace, self.batch_graph)
 
 
 def default_options() -> Options:
@@ -169,7 +170,7 @@ def default_options() -> Options:
     lib().clsimg_default_opts(C.byref(o))
     return Options(o.bound, o.C, o.kappa_b, o.kappa_d, o.nsamples, o.atol, o.btol, o.conlim,
                    o.itnlim, o.max_outer, o.precision, o.cost, o.loop, o.lsqr_engine, o.hand_over_free,
-                   o.trace)
+                   o.trace, o.batch_graph)
 
 
 def _ptr(t):

@@ -81,6 +81,12 @@ struct clsimg_ctx {
   hipEvent_t tm_ev[2] = {nullptr, nullptr};
   double tm_ms = 0.0;
   int tm_n = 0;
+  // captured round of batched Table I steps (clsimg_opts.batch_graph): its
+  // launch arguments, the capture stream and the executable graph
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t round_exec = nullptr;
+  const void* round_key[2] = {nullptr, nullptr};
+  int round_key_n = 0, round_key_bpr = 0, round_key_P = 0;
 };
 
 namespace {
@@ -446,6 +452,7 @@ int check_opts(const clsimg_opts* o, int P) {
   if (o->loop != CLSIMG_LOOP_AUTO && o->loop != CLSIMG_LOOP_HOST) return CLSIMG_EINVAL;
   if (o->lsqr_engine < CLSIMG_LSQR_AUTO || o->lsqr_engine > CLSIMG_LSQR_TWO_KERNEL) return CLSIMG_EINVAL;
   if (o->hand_over_free < 0 || (o->trace != 0 && o->trace != 1)) return CLSIMG_EINVAL;
+  if (o->batch_graph != 0 && o->batch_graph != 1) return CLSIMG_EINVAL;
   return CLSIMG_OK;
 }
 
@@ -669,6 +676,7 @@ void clsimg_default_opts(clsimg_opts* o) {
   o->lsqr_engine = CLSIMG_LSQR_AUTO;
   o->hand_over_free = 0;
   o->trace = 0;
+  o->batch_graph = 0;
 }
 
 int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
@@ -737,6 +745,8 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   for (hipEvent_t e : c->tm_ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->round_exec) (void)hipGraphExecDestroy(c->round_exec);
+  if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
   delete c;
   return CLSIMG_OK;
 }
@@ -2161,6 +2171,51 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
   return status;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Step pairs in one captured round of a batched solve: the loop replays the
+// round 1, 2, 4 ... 16 times between its looks at the requests' states.
+constexpr int kRoundPairs = 8;
+
+// The captured round (kRoundPairs outer-step and multiplier launches for all
+// requests), built once per (parameter arrays, batch size, P) on a private
+// stream; its kernels read every per-step value from device memory, so one
+// graph serves every round and every call with the same arguments.
+int batch_round_graph(clsimg_ctx* c, const OuterParams* dp, const BeamLamItem* di, int n, int bpr, int P) {
+  if (c->round_exec && c->round_key[0] == dp && c->round_key[1] == di && c->round_key_n == n &&
+      c->round_key_bpr == bpr && c->round_key_P == P)
+    return CLSIMG_OK;
+  if (c->round_exec) {
+    HIP_TRY(hipGraphExecDestroy(c->round_exec));
+    c->round_exec = nullptr;
+  }
+  if (!c->cap_st) HIP_TRY(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < kRoundPairs && e == hipSuccess; ++b) {
+    e = launch_outer_step_batch(dp, n, P, c->cap_st);
+    if (e == hipSuccess) e = launch_beam_lambda_batch(di, n, bpr, P, c->cap_st);
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->cap_st, &graph);
+  if (e == hipSuccess) e = ee;
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->round_exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  HIP_TRY(e);
+  c->round_key[0] = dp;
+  c->round_key[1] = di;
+  c->round_key_n = n;
+  c->round_key_bpr = bpr;
+  c->round_key_P = P;
+  return CLSIMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const clsimg_opts* o, void* stream) {
   if (!c || !reqs || n < 1) return CLSIMG_EINVAL;
   for (int r = 0; r < n; ++r) memset(&reqs[r].stats, 0, sizeof(clsimg_stats));
@@ -2277,11 +2332,16 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   // wait for the upload before the staging is reused for the state read-backs
   HIP_TRY(hipStreamSynchronize(st));
 
+  if (o->batch_graph) ST_TRY(batch_round_graph(c, dp, di, n, bpr, P));
   int nb = 8;
   for (;;) {
-    for (int b = 0; b < nb; ++b) {
-      HIP_TRY(launch_outer_step_batch(dp, n, P, st));
-      HIP_TRY(launch_beam_lambda_batch(di, n, bpr, P, st));
+    if (o->batch_graph) {
+      for (int b = 0; b < nb; b += kRoundPairs) HIP_TRY(hipGraphLaunch(c->round_exec, st));
+    } else {
+      for (int b = 0; b < nb; ++b) {
+        HIP_TRY(launch_outer_step_batch(dp, n, P, st));
+        HIP_TRY(launch_beam_lambda_batch(di, n, bpr, P, st));
+      }
     }
     OuterState* hs = reinterpret_cast<OuterState*>(c->h_batch);
     OuterState* ds = reinterpret_cast<OuterState*>(dbase + off_st);

@@ -208,3 +208,33 @@ def test_half_precision_batch(gpu_lib, prec):
                 assert err <= 1e-5
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["p24", "p48"])
+def test_captured_rounds_equal_enqueued_rounds(gpu_lib, kind):
+    # the batched steps replayed from a captured graph (batch_graph = 1) give
+    # the results of the launches enqueued one by one; two calls in a row reuse
+    # the graph (every replay with the program's own read-backs in between),
+    # a third call with another batch size captures it again
+    scenes = _scenes(kind)
+    print(f"case batch of {len(scenes)} ({kind}) replayed from a graph", flush=True)
+    ctx = gpu_lib.Context(0)
+    try:
+        opts = _opts(gpu_lib, scenes[0])
+        st, eager = ctx.solve_batch([_req(gpu_lib, sc) for sc in scenes], opts)
+        torch.cuda.synchronize()
+        assert st >= 0, st
+        opts.batch_graph = 1
+        for call, subset in enumerate([len(scenes), len(scenes), len(scenes) - 1]):
+            st, res = ctx.solve_batch([_req(gpu_lib, sc) for sc in scenes[:subset]], opts)
+            torch.cuda.synchronize()
+            assert st >= 0, st
+            for i in range(subset):
+                es, est, emf, eg, estats = eager[i]
+                bs, bst, bmf, bg, bstats = res[i]
+                assert torch.equal(est, bst) and torch.equal(es, bs), (call, i)
+                for k in ("status", "outer_iters", "adds", "drops", "lsqr_iters_total", "nF", "nU", "rel_residual"):
+                    assert estats[k] == bstats[k], (call, i, k)
+            print(f"call {call}: {subset} requests equal", flush=True)
+    finally:
+        ctx.close()

@@ -60,14 +60,18 @@ extern "C" {
 #define CLSIMG_BOUND_MF 1    /* gamma = MF dirty image (+ kappa_b std), eq. mfupper  */
 #define CLSIMG_BOUND_NONE 2  /* gamma = +inf: lower bound only, eq. NNLS             */
 
-/* arithmetic of the full-grid beamforming products (dirty image, bound, and
- * the Lagrange multipliers of the host-driven loop); the LSQR subproblems and
- * the device-resident loop (P <= 48) compute in FP32 in every mode */
+/* arithmetic of the full-grid beamforming products.  FP16 / BF16: the dirty
+ * image and the bound take each operand split into high and low halves (three
+ * 16x16x32 products accumulated in FP32, power-of-two scaling keeping FP16 in
+ * range: close to FP32 results, about 2^-16 relative with BF16); the Lagrange
+ * multipliers of each host-driven step take one half-precision product, and
+ * the pixels its rounding bound cannot rule out are evaluated again in FP32,
+ * so the release decision is the FP32 one.  The LSQR subproblems and the
+ * device-resident loop (P <= 48) compute in FP32 in every mode, the Cholesky
+ * factorisation and the LSQR scalars in FP64. */
 #define CLSIMG_FP32 0  /* FP32 MFMA (16x16x4)                                         */
-#define CLSIMG_FP16 1  /* FP16 MFMA (16x16x32), each operand split into high and low  */
-                       /* halves, three products accumulated in FP32; power-of-two    */
-                       /* scaling keeps the operands in range; close to FP32 results  */
-#define CLSIMG_BF16 2  /* the same split with BF16 halves (about 2^-16 relative)      */
+#define CLSIMG_FP16 1  /* FP16 MFMA (16x16x32) with FP32 accumulation                 */
+#define CLSIMG_BF16 2  /* BF16 MFMA (16x16x32) with FP32 accumulation                 */
 
 /* cost function for clsimg_opts.cost */
 #define CLSIMG_COST_LS 0     /* 1/2 ||B0 - Psi sigma||^2, eq. CLS                         */

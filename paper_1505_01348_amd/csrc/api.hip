@@ -41,7 +41,7 @@ struct clsimg_ctx {
   // steering tables of the last (array, grid)
   TableKey key;
   bool tables_valid = false;
-  DevBuf El, Em, pos_d;
+  DevBuf El, Em, ElT, EmT, pos_d;
   double* h_stage = nullptr;  // pinned staging for the antenna positions
   size_t h_stage_bytes = 0;
   hipEvent_t stage_done = nullptr;
@@ -181,6 +181,10 @@ int ensure_tables(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, hi
   HIP_TRY(hipEventRecord(c->stage_done, st));
   HIP_TRY(launch_tables(P_<const double>(c->pos_d), P, a->lambda, g->nl, g->nm, g->l0, g->dl, g->m0,
                         g->dm, P_<float2>(c->El), P_<float2>(c->Em), st));
+  ST_TRY(ensure(c, c->ElT, (size_t)Pp * g->nl * sizeof(float2)));
+  ST_TRY(ensure(c, c->EmT, (size_t)Pp * g->nm * sizeof(float2)));
+  HIP_TRY(launch_tables_t(P_<const float2>(c->El), P_<const float2>(c->Em), Pp, g->nl, g->nm, P_<float2>(c->ElT),
+                          P_<float2>(c->EmT), st));
   c->key.P = P;
   c->key.lambda = a->lambda;
   c->key.grid = *g;
@@ -197,6 +201,10 @@ Tables tables_of(clsimg_ctx* c, const clsimg_grid* g, int P) {
   t.nm = g->nm;
   t.Pp = pad_p(P);
   t.Q = g->nl * g->nm;
+  // the antenna-fastest copies belong to the context's own tables
+  const bool own = !c->tab_El && !c->tab_Em;
+  t.ElT = own ? P_<const float2>(c->ElT) : nullptr;
+  t.EmT = own ? P_<const float2>(c->EmT) : nullptr;
   return t;
 }
 
@@ -727,7 +735,7 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (!c) return CLSIMG_EINVAL;
   DeviceGuard guard(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->batch, &c->batch_params, &c->batch_rinv, &c->part,  &c->beta_part,
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->ElT, &c->EmT, &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->batch, &c->batch_params, &c->batch_rinv, &c->part,  &c->beta_part,
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,

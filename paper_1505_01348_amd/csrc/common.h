@@ -65,6 +65,10 @@ struct Tables {
   const float2* El;  // Pp x nl
   const float2* Em;  // Pp x nm
   int nl, nm, Pp, Q;
+  // the same tables antenna-fastest (nl x Pp, nm x Pp), or null: the
+  // correlation reads 16 consecutive antennas of one pixel per lane group
+  const float2* ElT = nullptr;
+  const float2* EmT = nullptr;
   __device__ __forceinline__ float2 a(int p, int il, int im) const {
     return cmul(El[p * nl + il], Em[p * nm + im]);
   }

@@ -464,6 +464,9 @@ struct CholItem {
 };
 // items: DEVICE array of n; one workgroup each
 hipError_t launch_chol_inverse_batch(const CholItem* items, int n, int P, hipStream_t st);
+// antenna-fastest copies ElT (nl x Pp), EmT (nm x Pp) of the tables
+hipError_t launch_tables_t(const float2* El, const float2* Em, int Pp, int nl, int nm, float2* ElT, float2* EmT,
+                           hipStream_t st);
 hipError_t launch_tables(const double* pos, int P, double lambda, int nl, int nm, double l0,
                          double dl, double m0, double dm, float2* El, float2* Em, hipStream_t st);
 // Steering tables of a batch of geometries in one launch, every entry as

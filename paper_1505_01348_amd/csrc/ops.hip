@@ -488,16 +488,22 @@ __global__ __launch_bounds__(kThreads) void corr_kernel(FwdParams pr) {
     }
   };
   float2 elr[BT], emr[BT], elc[BT], emc[BT];
+  // antenna-fastest tables when present (a lane group's 16 antennas of one
+  // pixel are contiguous), else the pixel-fastest ones (16 lines per pixel)
+  const bool tr = tab.ElT != nullptr;
   auto fetch = [&](int pix) {
     const int im = pix / nl, il = pix - im * nl;
+    const float2* lt = tr ? tab.ElT + (size_t)il * Pp : tab.El + il;
+    const float2* mt = tr ? tab.EmT + (size_t)im * Pp : tab.Em + im;
+    const size_t sl = tr ? 1 : (size_t)nl, sm = tr ? 1 : (size_t)nm;
 #pragma unroll
     for (int i = 0; i < BT; ++i) {
       const bool okr = ar[i] < Pp, okc = ac[i] < Pp;
-      elr[i] = okr ? tab.El[(size_t)ar[i] * nl + il] : make_float2(0.f, 0.f);
-      emr[i] = okr ? tab.Em[(size_t)ar[i] * nm + im] : make_float2(0.f, 0.f);
+      elr[i] = okr ? lt[ar[i] * sl] : make_float2(0.f, 0.f);
+      emr[i] = okr ? mt[ar[i] * sm] : make_float2(0.f, 0.f);
       if (!diag) {
-        elc[i] = okc ? tab.El[(size_t)ac[i] * nl + il] : make_float2(0.f, 0.f);
-        emc[i] = okc ? tab.Em[(size_t)ac[i] * nm + im] : make_float2(0.f, 0.f);
+        elc[i] = okc ? lt[ac[i] * sl] : make_float2(0.f, 0.f);
+        emc[i] = okc ? mt[ac[i] * sm] : make_float2(0.f, 0.f);
       }
     }
   };
@@ -1191,6 +1197,26 @@ hipError_t launch_chol_inverse_batch(const CholItem* items, int n, int P, hipStr
 hipError_t launch_tables_batch(const TableItem* items, int nreq, int total_max, hipStream_t st) {
   const int per = std::max(1, std::min(16, (total_max + kThreads - 1) / kThreads));
   hipLaunchKernelGGL(tables_batch_kernel, dim3(nreq * per), dim3(kThreads), 0, st, items, per);
+  return hipGetLastError();
+}
+
+// Antenna-fastest copies of the steering tables: T[i][p] = E[p][i].
+__global__ __launch_bounds__(kThreads) void tables_t_kernel(const float2* __restrict__ El, const float2* __restrict__ Em,
+                                                          int Pp, int nl, int nm, float2* __restrict__ ElT,
+                                                          float2* __restrict__ EmT) {
+  const int nt = Pp * (nl + nm);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nt; e += gridDim.x * blockDim.x) {
+    const int p = e % Pp, r = e / Pp;  // consecutive threads: consecutive antennas of one pixel row
+    if (r < nl) ElT[e] = El[(size_t)p * nl + r];
+    else EmT[(size_t)(r - nl) * Pp + p] = Em[(size_t)p * nm + (r - nl)];
+  }
+}
+
+hipError_t launch_tables_t(const float2* El, const float2* Em, int Pp, int nl, int nm, float2* ElT, float2* EmT,
+                           hipStream_t st) {
+  int grid = (Pp * (nl + nm) + kThreads - 1) / kThreads;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(tables_t_kernel, dim3(grid), dim3(kThreads), 0, st, El, Em, Pp, nl, nm, ElT, EmT);
   return hipGetLastError();
 }
 

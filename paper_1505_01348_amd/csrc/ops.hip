@@ -448,8 +448,8 @@ __host__ __device__ inline int corr_bt(int P) { return corr_tiles(P) <= 2 ? 2 : 
 __host__ __device__ inline int corr_nblocks(int P) { return (corr_tiles(P) + corr_bt(P) - 1) / corr_bt(P); }
 __host__ __device__ inline int corr_pairs(int P) { return corr_nblocks(P) * (corr_nblocks(P) + 1) / 2; }
 
-template <int BT>
-__global__ __launch_bounds__(kThreads) void corr_kernel(FwdParams pr) {
+template <int BT, bool TR>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void corr_kernel(FwdParams pr) {
   constexpr int NACC = BT * BT * 2;  // v4f accumulators per lane: Re and Im of each tile pair
   __shared__ v4f red[2][NACC][64];
   if (pr.stop_flag && *pr.stop_flag) return;
@@ -476,26 +476,26 @@ __global__ __launch_bounds__(kThreads) void corr_kernel(FwdParams pr) {
   v4f acc[NACC];
 #pragma unroll
   for (int a = 0; a < NACC; ++a) acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
-  // pixel of step s for this lane: k = k0 + 16 s + 4 w + q
+  // pixel of step s for this lane: k = k0 + 16 s + 4 w + q; over the whole
+  // grid (no index list) its (im, il) advance by 16 pixels a step
+  const bool listed = pr.idx != nullptr, walk = !listed && nl >= 16;
   auto pix_of = [&](int k, int& pix, float& v) {
     pix = 0;
     v = 0.f;
     if (k < k1) {
-      int p = pr.idx ? pr.idx[k] : k;
+      int p = listed ? pr.idx[k] : k;
       const bool ok = (unsigned)p < (unsigned)tab.Q;  // invalid index: term dropped
       pix = ok ? p : 0;
       v = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
     }
   };
   float2 elr[BT], emr[BT], elc[BT], emc[BT];
-  // antenna-fastest tables when present (a lane group's 16 antennas of one
-  // pixel are contiguous), else the pixel-fastest ones (16 lines per pixel)
-  const bool tr = tab.ElT != nullptr;
-  auto fetch = [&](int pix) {
-    const int im = pix / nl, il = pix - im * nl;
-    const float2* lt = tr ? tab.ElT + (size_t)il * Pp : tab.El + il;
-    const float2* mt = tr ? tab.EmT + (size_t)im * Pp : tab.Em + im;
-    const size_t sl = tr ? 1 : (size_t)nl, sm = tr ? 1 : (size_t)nm;
+  // TR: antenna-fastest tables (a lane group's 16 antennas of a pixel are
+  // contiguous, fixed offsets from one base per lane), else pixel-fastest
+  auto fetch = [&](int im, int il) {
+    const float2* lt = TR ? tab.ElT + (size_t)il * Pp : tab.El + il;
+    const float2* mt = TR ? tab.EmT + (size_t)im * Pp : tab.Em + im;
+    const size_t sl = TR ? 1 : (size_t)nl, sm = TR ? 1 : (size_t)nm;
 #pragma unroll
     for (int i = 0; i < BT; ++i) {
       const bool okr = ar[i] < Pp, okc = ac[i] < Pp;
@@ -511,7 +511,8 @@ __global__ __launch_bounds__(kThreads) void corr_kernel(FwdParams pr) {
   int pix;
   float v;
   pix_of(kk, pix, v);
-  fetch(pix);
+  int im = pix / nl, il = pix - im * nl;
+  fetch(im, il);
   for (int kb = k0 + 4 * w; kb < k1; kb += 16) {
     float2 A[BT], C[BT];
 #pragma unroll
@@ -523,7 +524,17 @@ __global__ __launch_bounds__(kThreads) void corr_kernel(FwdParams pr) {
     // the next step's pixel and table entries
     kk += 16;
     pix_of(kk, pix, v);
-    fetch(pix);
+    if (walk && kk < k1) {
+      il += 16;
+      while (il >= nl) {
+        il -= nl;
+        ++im;
+      }
+    } else {
+      im = pix / nl;
+      il = pix - im * nl;
+    }
+    fetch(im, il);
     float br[BT], bi[BT], bn[BT];
 #pragma unroll
     for (int j = 0; j < BT; ++j) {
@@ -1155,10 +1166,14 @@ hipError_t launch_forward(const FwdParams& pr, hipStream_t st) {
   const int P = pr.tab.Pp;  // corr_* depend on Pp only
   const int nchunks = (pr.n + pr.chw - 1) / pr.chw;
   const dim3 grid(nchunks, corr_pairs(P), pr.nblk);
-  if (corr_bt(P) == 2)
-    hipLaunchKernelGGL(corr_kernel<2>, grid, dim3(kThreads), 0, st, pr);
-  else
-    hipLaunchKernelGGL(corr_kernel<3>, grid, dim3(kThreads), 0, st, pr);
+  const bool tr = pr.tab.ElT && pr.tab.EmT && pr.nblk == 1;
+  if (corr_bt(P) == 2) {
+    if (tr) hipLaunchKernelGGL((corr_kernel<2, true>), grid, dim3(kThreads), 0, st, pr);
+    else hipLaunchKernelGGL((corr_kernel<2, false>), grid, dim3(kThreads), 0, st, pr);
+  } else {
+    if (tr) hipLaunchKernelGGL((corr_kernel<3, true>), grid, dim3(kThreads), 0, st, pr);
+    else hipLaunchKernelGGL((corr_kernel<3, false>), grid, dim3(kThreads), 0, st, pr);
+  }
   return hipGetLastError();
 }
 

@@ -181,8 +181,8 @@ int ensure_tables(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, hi
   HIP_TRY(hipEventRecord(c->stage_done, st));
   HIP_TRY(launch_tables(P_<const double>(c->pos_d), P, a->lambda, g->nl, g->nm, g->l0, g->dl, g->m0,
                         g->dm, P_<float2>(c->El), P_<float2>(c->Em), st));
-  ST_TRY(ensure(c, c->ElT, (size_t)Pp * g->nl * sizeof(float2)));
-  ST_TRY(ensure(c, c->EmT, (size_t)Pp * g->nm * sizeof(float2)));
+  ST_TRY(ensure(c, c->ElT, (size_t)corr_rows(Pp) * g->nl * sizeof(float2)));
+  ST_TRY(ensure(c, c->EmT, (size_t)corr_rows(Pp) * g->nm * sizeof(float2)));
   HIP_TRY(launch_tables_t(P_<const float2>(c->El), P_<const float2>(c->Em), Pp, g->nl, g->nm, P_<float2>(c->ElT),
                           P_<float2>(c->EmT), st));
   c->key.P = P;

@@ -61,12 +61,23 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // Steering-table view shared by the operator kernels.
+// Correlation tiling (forward operator): 16-antenna tiles, blocks of BT x BT
+// tile pairs, only block pairs on and below the diagonal; corr_rows is the
+// antennas a block row covers in all (the row length of the antenna-fastest
+// tables).  They depend on Pp only.
+__host__ __device__ inline int corr_tiles(int P) { return (pad_p(P) + 15) / 16; }
+__host__ __device__ inline int corr_bt(int P) { return corr_tiles(P) <= 2 ? 2 : 3; }
+__host__ __device__ inline int corr_nblocks(int P) { return (corr_tiles(P) + corr_bt(P) - 1) / corr_bt(P); }
+__host__ __device__ inline int corr_pairs(int P) { return corr_nblocks(P) * (corr_nblocks(P) + 1) / 2; }
+__host__ __device__ inline int corr_rows(int P) { return 16 * corr_bt(P) * corr_nblocks(P); }
+
 struct Tables {
   const float2* El;  // Pp x nl
   const float2* Em;  // Pp x nm
   int nl, nm, Pp, Q;
-  // the same tables antenna-fastest (nl x Pp, nm x Pp), or null: the
-  // correlation reads 16 consecutive antennas of one pixel per lane group
+  // the same tables antenna-fastest (nl x corr_rows(Pp), nm x corr_rows(Pp),
+  // zero beyond Pp), or null: the correlation reads 16 consecutive antennas
+  // of one pixel per lane group
   const float2* ElT = nullptr;
   const float2* EmT = nullptr;
   __device__ __forceinline__ float2 a(int p, int il, int im) const {

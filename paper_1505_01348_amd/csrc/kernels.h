@@ -464,7 +464,7 @@ struct CholItem {
 };
 // items: DEVICE array of n; one workgroup each
 hipError_t launch_chol_inverse_batch(const CholItem* items, int n, int P, hipStream_t st);
-// antenna-fastest copies ElT (nl x Pp), EmT (nm x Pp) of the tables
+// antenna-fastest copies ElT (nl x corr_rows(Pp)), EmT (nm x corr_rows(Pp)) of the tables, zero beyond Pp
 hipError_t launch_tables_t(const float2* El, const float2* Em, int Pp, int nl, int nm, float2* ElT, float2* EmT,
                            hipStream_t st);
 hipError_t launch_tables(const double* pos, int P, double lambda, int nl, int nm, double l0,

@@ -443,12 +443,8 @@ __global__ __launch_bounds__(kThreads) void adjoint_list_kernel(AdjParams pr, Ep
 // accumulators are added in LDS in a fixed order; each workgroup leaves one
 // partial of its block pair: part[(chunk * npairs + pair) * BT^2 * 512 +
 // tile * 512 + {0: Re, 256: Im} + lane * 4 + r] = Y[16 bm + 4q + r][16 bn + c16].
-__host__ __device__ inline int corr_tiles(int P) { return (pad_p(P) + 15) / 16; }
-__host__ __device__ inline int corr_bt(int P) { return corr_tiles(P) <= 2 ? 2 : 3; }
-__host__ __device__ inline int corr_nblocks(int P) { return (corr_tiles(P) + corr_bt(P) - 1) / corr_bt(P); }
-__host__ __device__ inline int corr_pairs(int P) { return corr_nblocks(P) * (corr_nblocks(P) + 1) / 2; }
 
-template <int BT, bool TR>
+template <int BT, bool TR, bool LIST>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void corr_kernel(FwdParams pr) {
   constexpr int NACC = BT * BT * 2;  // v4f accumulators per lane: Re and Im of each tile pair
   __shared__ v4f red[2][NACC][64];
@@ -476,34 +472,49 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   v4f acc[NACC];
 #pragma unroll
   for (int a = 0; a < NACC; ++a) acc[a] = v4f{0.f, 0.f, 0.f, 0.f};
-  // pixel of step s for this lane: k = k0 + 16 s + 4 w + q; over the whole
-  // grid (no index list) its (im, il) advance by 16 pixels a step
-  const bool listed = pr.idx != nullptr, walk = !listed && nl >= 16;
+  // pixel of step s for this lane: k = k0 + 16 s + 4 w + q (LIST: the k-th
+  // entry of the index list); over the whole grid its (im, il) advance by 16
+  // pixels a step, and no load stands between a step's table loads and the
+  // next step's
+  const bool walk = !LIST && nl >= 16;
   auto pix_of = [&](int k, int& pix, float& v) {
     pix = 0;
     v = 0.f;
     if (k < k1) {
-      int p = listed ? pr.idx[k] : k;
+      int p = LIST ? pr.idx[k] : k;
       const bool ok = (unsigned)p < (unsigned)tab.Q;  // invalid index: term dropped
       pix = ok ? p : 0;
       v = ok ? (pr.gather ? pr.vals[pix] : pr.vals[k]) : 0.f;
     }
   };
   float2 elr[BT], emr[BT], elc[BT], emc[BT];
-  // TR: antenna-fastest tables (a lane group's 16 antennas of a pixel are
-  // contiguous, fixed offsets from one base per lane), else pixel-fastest
+  // TR: antenna-fastest tables with rows of corr_rows(Pp) entries, zero
+  // beyond P (a lane group's 16 antennas of a pixel are contiguous, fixed
+  // offsets from one base per lane, no bounds test); else pixel-fastest
+  const int rowT = corr_rows(Pp);
   auto fetch = [&](int im, int il) {
-    const float2* lt = TR ? tab.ElT + (size_t)il * Pp : tab.El + il;
-    const float2* mt = TR ? tab.EmT + (size_t)im * Pp : tab.Em + im;
-    const size_t sl = TR ? 1 : (size_t)nl, sm = TR ? 1 : (size_t)nm;
+    if (TR) {
+      const float2* lt = tab.ElT + (size_t)il * rowT;
+      const float2* mt = tab.EmT + (size_t)im * rowT;
+#pragma unroll
+      for (int i = 0; i < BT; ++i) {
+        elr[i] = lt[ar[i]];
+        emr[i] = mt[ar[i]];
+        if (!diag) {
+          elc[i] = lt[ac[i]];
+          emc[i] = mt[ac[i]];
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < BT; ++i) {
       const bool okr = ar[i] < Pp, okc = ac[i] < Pp;
-      elr[i] = okr ? lt[ar[i] * sl] : make_float2(0.f, 0.f);
-      emr[i] = okr ? mt[ar[i] * sm] : make_float2(0.f, 0.f);
+      elr[i] = okr ? tab.El[(size_t)ar[i] * nl + il] : make_float2(0.f, 0.f);
+      emr[i] = okr ? tab.Em[(size_t)ar[i] * nm + im] : make_float2(0.f, 0.f);
       if (!diag) {
-        elc[i] = okc ? lt[ac[i] * sl] : make_float2(0.f, 0.f);
-        emc[i] = okc ? mt[ac[i] * sm] : make_float2(0.f, 0.f);
+        elc[i] = okc ? tab.El[(size_t)ac[i] * nl + il] : make_float2(0.f, 0.f);
+        emc[i] = okc ? tab.Em[(size_t)ac[i] * nm + im] : make_float2(0.f, 0.f);
       }
     }
   };
@@ -1166,14 +1177,29 @@ hipError_t launch_forward(const FwdParams& pr, hipStream_t st) {
   const int P = pr.tab.Pp;  // corr_* depend on Pp only
   const int nchunks = (pr.n + pr.chw - 1) / pr.chw;
   const dim3 grid(nchunks, corr_pairs(P), pr.nblk);
-  const bool tr = pr.tab.ElT && pr.tab.EmT && pr.nblk == 1;
-  if (corr_bt(P) == 2) {
-    if (tr) hipLaunchKernelGGL((corr_kernel<2, true>), grid, dim3(kThreads), 0, st, pr);
-    else hipLaunchKernelGGL((corr_kernel<2, false>), grid, dim3(kThreads), 0, st, pr);
-  } else {
-    if (tr) hipLaunchKernelGGL((corr_kernel<3, true>), grid, dim3(kThreads), 0, st, pr);
-    else hipLaunchKernelGGL((corr_kernel<3, false>), grid, dim3(kThreads), 0, st, pr);
+  const bool tr = pr.tab.ElT && pr.tab.EmT && pr.nblk == 1, list = pr.idx != nullptr;
+#define CORR_LAUNCH(BT_, TR_, LIST_) hipLaunchKernelGGL((corr_kernel<BT_, TR_, LIST_>), grid, dim3(kThreads), 0, st, pr)
+#define CORR_LIST(BT_, TR_)   \
+  if (list) {                 \
+    CORR_LAUNCH(BT_, TR_, true);  \
+  } else {                    \
+    CORR_LAUNCH(BT_, TR_, false); \
   }
+  if (corr_bt(P) == 2) {
+    if (tr) {
+      CORR_LIST(2, true)
+    } else {
+      CORR_LIST(2, false)
+    }
+  } else {
+    if (tr) {
+      CORR_LIST(3, true)
+    } else {
+      CORR_LIST(3, false)
+    }
+  }
+#undef CORR_LIST
+#undef CORR_LAUNCH
   return hipGetLastError();
 }
 
@@ -1215,21 +1241,23 @@ hipError_t launch_tables_batch(const TableItem* items, int nreq, int total_max, 
   return hipGetLastError();
 }
 
-// Antenna-fastest copies of the steering tables: T[i][p] = E[p][i].
+// Antenna-fastest copies of the steering tables: T[i][p] = E[p][i] for
+// p < Pp, zero up to the row length corr_rows(Pp).
 __global__ __launch_bounds__(kThreads) void tables_t_kernel(const float2* __restrict__ El, const float2* __restrict__ Em,
                                                           int Pp, int nl, int nm, float2* __restrict__ ElT,
                                                           float2* __restrict__ EmT) {
-  const int nt = Pp * (nl + nm);
+  const int rowT = corr_rows(Pp);
+  const int nt = rowT * (nl + nm);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nt; e += gridDim.x * blockDim.x) {
-    const int p = e % Pp, r = e / Pp;  // consecutive threads: consecutive antennas of one pixel row
-    if (r < nl) ElT[e] = El[(size_t)p * nl + r];
-    else EmT[(size_t)(r - nl) * Pp + p] = Em[(size_t)p * nm + (r - nl)];
+    const int p = e % rowT, r = e / rowT;  // consecutive threads: consecutive antennas of one pixel row
+    if (r < nl) ElT[e] = p < Pp ? El[(size_t)p * nl + r] : make_float2(0.f, 0.f);
+    else EmT[(size_t)(r - nl) * rowT + p] = p < Pp ? Em[(size_t)p * nm + (r - nl)] : make_float2(0.f, 0.f);
   }
 }
 
 hipError_t launch_tables_t(const float2* El, const float2* Em, int Pp, int nl, int nm, float2* ElT, float2* EmT,
                            hipStream_t st) {
-  int grid = (Pp * (nl + nm) + kThreads - 1) / kThreads;
+  int grid = (corr_rows(Pp) * (nl + nm) + kThreads - 1) / kThreads;
   if (grid > 1024) grid = 1024;
   hipLaunchKernelGGL(tables_t_kernel, dim3(grid), dim3(kThreads), 0, st, El, Em, Pp, nl, nm, ElT, EmT);
   return hipGetLastError();

@@ -494,15 +494,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   const int rowT = corr_rows(Pp);
   auto fetch = [&](int im, int il) {
     if (TR) {
-      const float2* lt = tab.ElT + (size_t)il * rowT;
-      const float2* mt = tab.EmT + (size_t)im * rowT;
+      // one base per table and block side; tile i at a fixed offset of 16 i entries
+      const float2* lr = tab.ElT + ((size_t)il * rowT + (size_t)ar[0]);
+      const float2* mr = tab.EmT + ((size_t)im * rowT + (size_t)ar[0]);
+      const float2* lc = tab.ElT + ((size_t)il * rowT + (size_t)ac[0]);
+      const float2* mc = tab.EmT + ((size_t)im * rowT + (size_t)ac[0]);
 #pragma unroll
       for (int i = 0; i < BT; ++i) {
-        elr[i] = lt[ar[i]];
-        emr[i] = mt[ar[i]];
+        elr[i] = lr[16 * i];
+        emr[i] = mr[16 * i];
         if (!diag) {
-          elc[i] = lt[ac[i]];
-          emc[i] = mt[ac[i]];
+          elc[i] = lc[16 * i];
+          emc[i] = mc[16 * i];
         }
       }
       return;

@@ -253,7 +253,7 @@ int ensure_workspace(clsimg_ctx* c, int P, int Q) {
   ST_TRY(ensure(c, c->u, cx));
   ST_TRY(ensure(c, c->E, cx));
   ST_TRY(ensure(c, c->Rinv, cx));
-  ST_TRY(ensure(c, c->W, (size_t)2 * P * P * sizeof(double2)));  // L and its transpose (Cholesky beyond 64)
+  ST_TRY(ensure(c, c->W, chol_work_elems(P) * sizeof(double2)));  // Cholesky beyond 64 antennas
   ST_TRY(ensure(c, c->Li, (size_t)P * P * sizeof(double2)));
   ST_TRY(ensure(c, c->lsqr, sizeof(LsqrState)));
   ST_TRY(ensure(c, c->dec, sizeof(SolveDecision)));

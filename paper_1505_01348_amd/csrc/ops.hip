@@ -691,213 +691,323 @@ __global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) 
 }
 
 // ---------------------------------------------------------------------------
-// FP64 Cholesky R = L L^H for arrays beyond the LDS-resident kernel below,
-// in two launches.
+// FP64 Cholesky R = L L^H for arrays beyond the LDS-resident kernel below:
+// a blocked right-looking factorisation of W (row-major; the lower triangle
+// is read and overwritten by L) in panels of kCholNB columns, one launch per
+// panel and one per trailing update, then the inverse.
 //
-// chol_factor_kernel (one workgroup): blocked right-looking factorisation of
-// W (row-major, the lower triangle is read and overwritten by L), panels of
-// kCholNB columns.  A panel's rows are copied into LDS, factored there (one
-// column at a time: pivot, scale, update of the panel's later columns), and
-// written back; the trailing lower triangle then takes the panel's rank-nb
-// update with one global read and write per element.  The factor is also
-// stored transposed (LT[k][i] = L[i][k]) so that columns of L are contiguous
-// for the forward substitution.  status: 0 ok, 1 not positive definite,
-// 2 non-finite entry.
+// chol_convert_kernel (one workgroup): W = R in FP64, status 2 for a
+// non-finite entry, else 0.
+// chol_panel_kernel (one workgroup): the panel's diagonal block is factored
+// in LDS one column at a time (pivot, scale, update of its later columns);
+// every row below it then takes the same steps on its own panel entries in
+// registers (divide by the pivot, subtract from the later entries), no
+// barrier needed.  Status 1 for a pivot that is not positive.  The factor is
+// also stored transposed (LT[k][i] = L[i][k]) so that columns of L are
+// contiguous for the forward substitution.
+// chol_update_kernel (one workgroup per 32 x 32 tile of the trailing lower
+// triangle): W[i][k] -= sum_c L[i][c] conj(L[k][c]) over the panel's
+// columns, the two row blocks of the panel staged in LDS.
+// Each entry sees the operations of the one-workgroup blocked factorisation
+// in the same order.
 //
+// chol_dinv_kernel (one wave per diagonal block of kCholNB rows): D_b, the
+// inverse of the block's lower-triangular factor, by forward substitution
+// (one lane per column), kCholNB x kCholNB row-major, zero above the diagonal
+// and beyond the last row.
 // chol_solve_kernel (one workgroup per column c of the identity): forward
-// substitution L y = e_c (y = column c of L^-1, stored when Li is given), then
-// backward substitution L^H x = y (x = column c of R^-1, rounded to complex64).
-// Each step reads one row of LT or of L, loaded one step ahead.
+// substitution L y = e_c by blocks of kCholNB rows (y_i = -D_i sum_k L_ik y_k,
+// y = column c of L^-1, stored when Li is given), then backward substitution
+// L^H x = y by blocks (x_i = D_i^H (y_i - sum_k L_ki^H x_k), x = column c of
+// R^-1, rounded to complex64).  16 threads share each row's sum (coalesced
+// reads of a row of L or of LT), and the next block row's entries are loaded
+// while one is reduced: two barriers per block row.
 constexpr int kCholNB = 16;
 constexpr int kCholMaxRows = 288;  // the largest array (CLSIMG_MAX_P)
+constexpr int kCholTile = 32;
 
-__global__ __launch_bounds__(1024) void chol_factor_kernel(const float2* __restrict__ R, int P,
-                                                           double2* __restrict__ W, double2* __restrict__ LT,
-                                                           int* __restrict__ status) {
-  constexpr int LDP = kCholNB + 1;  // padded panel rows
-  __shared__ double2 pan[kCholMaxRows * LDP];
+__global__ __launch_bounds__(1024) void chol_convert_kernel(const float2* __restrict__ R, int P,
+                                                            double2* __restrict__ W, int* __restrict__ status) {
   __shared__ int bad;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) bad = 0;
+  if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  for (int e = tid; e < P * P; e += nt) {
+  const int n = P * P, nt = blockDim.x;
+  int e = threadIdx.x;
+  for (; e + 7 * nt < n; e += 8 * nt) {
+    float2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = R[e + k * nt];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (!isfinite(v[k].x) || !isfinite(v[k].y)) bad = 2;
+      W[e + k * nt] = make_double2((double)v[k].x, (double)v[k].y);
+    }
+  }
+  for (; e < n; e += nt) {
     const float2 v = R[e];
     if (!isfinite(v.x) || !isfinite(v.y)) bad = 2;
     W[e] = make_double2((double)v.x, (double)v.y);
   }
   __syncthreads();
-  if (bad) {
-    if (tid == 0) *status = bad;
-    return;
+  if (threadIdx.x == 0) *status = bad;
+}
+
+template <int NB>
+__global__ __launch_bounds__(512) void chol_panel_kernel(double2* __restrict__ W, double2* __restrict__ LT, int P,
+                                                         int j0, int* __restrict__ status) {
+  constexpr int LDP = kCholNB + 1;
+  __shared__ double2 d11[kCholNB * LDP];
+  if (*status != 0) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr int nb = NB;
+  const int rows = P - j0;
+  for (int e = tid; e < nb * nb; e += nt) {
+    const int r = e / nb, c = e - r * nb;
+    d11[r * LDP + c] = W[(size_t)(j0 + r) * P + j0 + c];
   }
-  for (int j0 = 0; j0 < P; j0 += kCholNB) {
-    const int nb = min(kCholNB, P - j0), rows = P - j0;
-    for (int e = tid; e < rows * nb; e += nt) {
-      const int r = e / nb, c = e - r * nb;
-      pan[r * LDP + c] = W[(size_t)(j0 + r) * P + j0 + c];
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    const double d = d11[c * LDP + c].x;  // the same value in every thread: the exit is uniform
+    if (!(d > 0.0)) {
+      if (tid == 0) *status = 1;
+      return;
+    }
+    const double ljj = sqrt(d);
+    if (tid > c && tid < nb) {
+      const double2 v = d11[tid * LDP + c];
+      d11[tid * LDP + c] = make_double2(v.x / ljj, v.y / ljj);
     }
     __syncthreads();
-    for (int c = 0; c < nb; ++c) {
-      const double d = pan[c * LDP + c].x;  // the same value in every thread: the exit is uniform
-      if (!(d > 0.0)) {
-        if (tid == 0) *status = 1;
-        return;
-      }
-      const double ljj = sqrt(d);
-      for (int r = c + 1 + tid; r < rows; r += nt) {
-        const double2 v = pan[r * LDP + c];
-        pan[r * LDP + c] = make_double2(v.x / ljj, v.y / ljj);
-      }
-      __syncthreads();
-      if (tid == 0) pan[c * LDP + c] = make_double2(ljj, 0.0);
-      // later columns of the panel: pan[r][c2] -= pan[r][c] conj(pan[c2][c]), r >= c2 > c
-      const int w = nb - c - 1;
-      for (int e = tid; e < rows * w; e += nt) {
-        const int r = e / w, c2 = c + 1 + e - (e / w) * w;
-        if (r >= c2) {
-          const double2 a = pan[r * LDP + c], b = pan[c2 * LDP + c];
-          double2 x = pan[r * LDP + c2];
-          x.x -= a.x * b.x + a.y * b.y;
-          x.y -= a.y * b.x - a.x * b.y;
-          pan[r * LDP + c2] = x;
-        }
-      }
-      __syncthreads();
-    }
-    // the panel's columns of L, in W and transposed in LT
-    for (int e = tid; e < rows * nb; e += nt) {
-      const int r = e / nb, c = e - r * nb;
-      if (r >= c) {
-        const double2 v = pan[r * LDP + c];
-        W[(size_t)(j0 + r) * P + j0 + c] = v;
-        LT[(size_t)(j0 + c) * P + j0 + r] = v;
+    if (tid == 0) d11[c * LDP + c] = make_double2(ljj, 0.0);
+    // later columns of the block: d11[r][c2] -= d11[r][c] conj(d11[c2][c]), r >= c2 > c
+    if (tid < nb * nb) {
+      const int r = tid / nb, c2 = tid - r * nb;
+      if (c2 > c && r >= c2) {
+        const double2 a = d11[r * LDP + c], bb = d11[c2 * LDP + c];
+        double2 x = d11[r * LDP + c2];
+        x.x -= a.x * bb.x + a.y * bb.y;
+        x.y -= a.y * bb.x - a.x * bb.y;
+        d11[r * LDP + c2] = x;
       }
     }
-    // trailing update W[i][k] -= sum_c L[i][c] conj(L[k][c]), j0 + nb <= k <= i;
-    // threads as 32 x 32 (row phase, column phase): consecutive threads take
-    // consecutive k of one row (coalesced), each thread four elements at a time
-    const int t0 = j0 + nb, m = P - t0;
-    const int ty = tid >> 5, tx = tid & 31;
-    for (int i = t0 + ty; i < P; i += 32) {
-      const int ri = i - j0;
-      for (int k0 = t0 + tx; k0 <= i; k0 += 128) {
-        double2 acc[4];
-        double2 wv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + 32 * u;
-          wv[u] = k <= i ? W[(size_t)i * P + k] : make_double2(0.0, 0.0);
-          acc[u] = make_double2(0.0, 0.0);
-        }
-#pragma unroll 4
-        for (int c = 0; c < nb; ++c) {
-          const double2 a = pan[ri * LDP + c];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int k = min(k0 + 32 * u, P - 1);
-            const double2 b = pan[(k - j0) * LDP + c];
-            acc[u].x += a.x * b.x + a.y * b.y;
-            acc[u].y += a.y * b.x - a.x * b.y;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + 32 * u;
-          if (k <= i) W[(size_t)i * P + k] = make_double2(wv[u].x - acc[u].x, wv[u].y - acc[u].y);
-        }
-      }
-    }
-    (void)m;
     __syncthreads();
   }
-  if (tid == 0) *status = 0;
+  for (int e = tid; e < nb * nb; e += nt) {
+    const int r = e / nb, c = e - r * nb;
+    if (r >= c) {
+      const double2 v = d11[r * LDP + c];
+      W[(size_t)(j0 + r) * P + j0 + c] = v;
+      LT[(size_t)(j0 + c) * P + j0 + r] = v;
+    }
+  }
+  // rows below the block (one per thread: P - nb <= 512): the column steps on
+  // the row's own entries
+  {
+    const int r = nb + tid;
+    if (r >= rows) return;
+    double2 x[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[c] = W[(size_t)(j0 + r) * P + j0 + c];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double ljj = d11[c * LDP + c].x;
+      x[c] = make_double2(x[c].x / ljj, x[c].y / ljj);
+#pragma unroll
+      for (int c2 = c + 1; c2 < NB; ++c2) {
+        const double2 bb = d11[c2 * LDP + c];
+        x[c2].x -= x[c].x * bb.x + x[c].y * bb.y;
+        x[c2].y -= x[c].y * bb.x - x[c].x * bb.y;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      W[(size_t)(j0 + r) * P + j0 + c] = x[c];
+      LT[(size_t)(j0 + c) * P + j0 + r] = x[c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void chol_update_kernel(double2* __restrict__ W, int P, int j0, int nb,
+                                                          const int* __restrict__ status) {
+  constexpr int LDP = kCholNB + 1;
+  __shared__ double2 li[kCholTile * LDP], lk[kCholTile * LDP];
+  if (*status != 0) return;
+  const int t0 = j0 + nb;
+  // this workgroup's tile (ti, tk), tk <= ti, in row-major order of the lower triangle
+  int ti = 0, b = blockIdx.x;
+  while (b > ti) {
+    b -= ti + 1;
+    ++ti;
+  }
+  const int tk = b;
+  const int i0 = t0 + kCholTile * ti, k0 = t0 + kCholTile * tk;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kCholTile * kCholNB; e += blockDim.x) {
+    const int r = e / kCholNB, c = e - r * kCholNB;
+    li[r * LDP + c] = (i0 + r < P && c < nb) ? W[(size_t)(i0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
+    lk[r * LDP + c] = (k0 + r < P && c < nb) ? W[(size_t)(k0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  // thread: row i0 + (tid >> 3), columns k0 + (tid & 7) + 8 u
+  const int ri = tid >> 3, i = i0 + ri;
+  if (i >= P) return;
+  double2 wv[4], acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = k0 + (tid & 7) + 8 * u;
+    wv[u] = k <= i ? W[(size_t)i * P + k] : make_double2(0.0, 0.0);
+    acc[u] = make_double2(0.0, 0.0);
+  }
+  for (int c = 0; c < nb; ++c) {
+    const double2 a = li[ri * LDP + c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 bb = lk[((tid & 7) + 8 * u) * LDP + c];
+      acc[u].x += a.x * bb.x + a.y * bb.y;
+      acc[u].y += a.y * bb.x - a.x * bb.y;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = k0 + (tid & 7) + 8 * u;
+    if (k <= i) W[(size_t)i * P + k] = make_double2(wv[u].x - acc[u].x, wv[u].y - acc[u].y);
+  }
+}
+
+// sum over the 16 lanes of a row group (lanes 16 g .. 16 g + 15 of a wave)
+__device__ inline double2 chol_sum16(double2 v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 16);
+    v.y += __shfl_xor(v.y, o, 16);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(64) void chol_dinv_kernel(const double2* __restrict__ L, int P,
+                                                       const int* __restrict__ status, double2* __restrict__ D) {
+  constexpr int NB = kCholNB, LDP = NB + 1;
+  __shared__ double2 a[NB * LDP];
+  if (*status != 0) return;
+  const int b = blockIdx.x, i0 = b * NB, n = min(NB, P - i0), tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int r = e / NB, k = e - r * NB;
+    a[r * LDP + k] = (r < n && k <= r) ? L[(size_t)(i0 + r) * P + i0 + k] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (tid >= NB) return;
+  const int cc = tid;
+  double2 x[NB];  // column cc of the block's inverse
+#pragma unroll
+  for (int r = 0; r < NB; ++r) x[r] = make_double2(r == cc ? 1.0 : 0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k < n) {
+      const double lkk = a[k * LDP + k].x;
+      x[k] = make_double2(x[k].x / lkk, x[k].y / lkk);
+#pragma unroll
+      for (int r = k + 1; r < NB; ++r) {
+        const double2 l = a[r * LDP + k];
+        x[r].x -= l.x * x[k].x - l.y * x[k].y;
+        x[r].y -= l.x * x[k].y + l.y * x[k].x;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r) D[(size_t)b * NB * NB + r * NB + cc] = (r < n && cc < n) ? x[r] : make_double2(0.0, 0.0);
 }
 
 __global__ __launch_bounds__(256) void chol_solve_kernel(const double2* __restrict__ L, const double2* __restrict__ LT,
-                                                         int P, const int* __restrict__ status,
-                                                         double2* __restrict__ Li, float2* __restrict__ Rinv) {
+                                                         const double2* __restrict__ D, int P,
+                                                         const int* __restrict__ status, double2* __restrict__ Li,
+                                                         float2* __restrict__ Rinv) {
+  constexpr int NB = kCholNB, MB = kCholMaxRows / kCholNB;
   __shared__ double2 y[kCholMaxRows];
+  __shared__ double2 t[NB];
   if (*status != 0) return;
-  const int c = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < P; i += nt) y[i] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+  const int c = blockIdx.x, tid = threadIdx.x, r = tid >> 4, q = tid & 15;
+  const int nbk = (P + NB - 1) / NB, jc = c / NB;
+  // block jc of y: column (c - NB jc) of D_jc; above it zero
+  for (int i = tid; i < nbk * NB; i += blockDim.x)
+    y[i] = i / NB == jc ? D[(size_t)jc * NB * NB + (i - jc * NB) * NB + (c - jc * NB)] : make_double2(0.0, 0.0);
+  // forward, block rows i > jc: y_i = -D_i sum_{k in blocks jc .. i-1} L_ik y_k.  Thread (r, q) sums
+  // L[i NB + r][jc NB + q + NB m] y[jc NB + q + NB m] over m; the next block row's entries are
+  // loaded while this one is reduced.
+  double2 nxt[MB];
+  auto load_fwd = [&](int i) {
+    const int row = i * NB + r, cnt = i - jc;
+    const double2* lr = L + (size_t)min(row, P - 1) * P + jc * NB + q;
+#pragma unroll
+    for (int m = 0; m < MB; ++m) nxt[m] = (m < cnt && row < P) ? lr[m * NB] : make_double2(0.0, 0.0);
+  };
+  if (jc + 1 < nbk) load_fwd(jc + 1);
   __syncthreads();
-  // forward: for k = c .. P-1: y_k /= L_kk; y_i -= L_ik y_k (i > k), column k of L = row k of LT
-  double2 nxt[2];
-  double npiv = LT[(size_t)c * P + c].x;
+  for (int i = jc + 1; i < nbk; ++i) {
+    double2 lv[MB];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int i = c + tid + h * nt;
-    nxt[h] = i < P ? LT[(size_t)c * P + i] : make_double2(0.0, 0.0);
-  }
-  for (int k = c; k < P; ++k) {
-    // thread (tid, h) holds L[k + tid + h nt][k]
-    double2 col[2] = {nxt[0], nxt[1]};
-    const double lkk = npiv;
-    if (k + 1 < P) {
-      npiv = LT[(size_t)(k + 1) * P + k + 1].x;
+    for (int m = 0; m < MB; ++m) lv[m] = nxt[m];
+    if (i + 1 < nbk) load_fwd(i + 1);
+    const int cnt = i - jc;
+    double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = k + 1 + tid + h * nt;
-        nxt[h] = i < P ? LT[(size_t)(k + 1) * P + i] : make_double2(0.0, 0.0);
+    for (int m = 0; m < MB; ++m)
+      if (m < cnt) {
+        const double2 v = y[jc * NB + q + m * NB];
+        acc.x += lv[m].x * v.x - lv[m].y * v.y;
+        acc.y += lv[m].x * v.y + lv[m].y * v.x;
       }
-    }
-    const double2 yk0 = y[k];
-    const double2 yk = make_double2(yk0.x / lkk, yk0.y / lkk);
-    __syncthreads();  // every thread has read y[k]
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = k + tid + h * nt;
-      if (i == k) {
-        y[k] = yk;
-      } else if (i < P) {
-        const double2 l = col[h];
-        double2 v = y[i];
-        v.x -= l.x * yk.x - l.y * yk.y;
-        v.y -= l.x * yk.y + l.y * yk.x;
-        y[i] = v;
-      }
-    }
+    acc = chol_sum16(acc);
+    if (q == 0) t[r] = make_double2(-acc.x, -acc.y);
+    __syncthreads();
+    const double2 d = D[(size_t)i * NB * NB + r * NB + q], tq = t[q];
+    double2 p = make_double2(d.x * tq.x - d.y * tq.y, d.x * tq.y + d.y * tq.x);
+    p = chol_sum16(p);
+    if (q == 0) y[i * NB + r] = p;
     __syncthreads();
   }
   if (Li)
-    for (int i = tid; i < P; i += nt) Li[(size_t)i * P + c] = y[i];
-  // backward: for k = P-1 .. 0: x_k = y_k / L_kk; y_i -= conj(L_ki) x_k (i < k), row k of L
-  npiv = L[(size_t)(P - 1) * P + P - 1].x;
+    for (int i = tid; i < P; i += blockDim.x) Li[(size_t)i * P + c] = y[i];
+  // backward, block rows i = nbk-1 .. 0: x_i = D_i^H (y_i - sum_{k >= (i+1) NB} conj(L_ki) x_k), x
+  // overwriting y; conj(L[k][i NB + r]) is entry k of row i NB + r of LT
+  auto load_bwd = [&](int i) {
+    const int row = i * NB + r, k0 = (i + 1) * NB + q;
+    const double2* lr = LT + (size_t)min(row, P - 1) * P;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int i = tid + h * nt;
-    nxt[h] = i < P - 1 ? L[(size_t)(P - 1) * P + i] : make_double2(0.0, 0.0);
-  }
-  for (int k = P - 1; k >= 0; --k) {
-    double2 row[2] = {nxt[0], nxt[1]};
-    const double lkk = npiv;
-    if (k > 0) {
-      npiv = L[(size_t)(k - 1) * P + k - 1].x;
+    for (int m = 0; m < MB; ++m) {
+      const int k = k0 + m * NB;
+      nxt[m] = (k < P && row < P) ? lr[k] : make_double2(0.0, 0.0);
+    }
+  };
+  load_bwd(nbk - 1);
+  for (int i = nbk - 1; i >= 0; --i) {
+    double2 lv[MB];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = tid + h * nt;
-        nxt[h] = i < k - 1 ? L[(size_t)(k - 1) * P + i] : make_double2(0.0, 0.0);
+    for (int m = 0; m < MB; ++m) lv[m] = nxt[m];
+    if (i > 0) load_bwd(i - 1);
+    const int k0 = (i + 1) * NB + q;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const int k = k0 + m * NB;
+      if (k < P) {
+        const double2 v = y[k];  // conj(l) v
+        acc.x += lv[m].x * v.x + lv[m].y * v.y;
+        acc.y += lv[m].x * v.y - lv[m].y * v.x;
       }
     }
-    const double2 yk0 = y[k];
-    const double2 xk = make_double2(yk0.x / lkk, yk0.y / lkk);
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = tid + h * nt;
-      if (i == k) {
-        y[k] = xk;
-      } else if (i < k) {
-        const double2 l = row[h];  // conj(L_ki) x_k
-        double2 v = y[i];
-        v.x -= l.x * xk.x + l.y * xk.y;
-        v.y -= l.x * xk.y - l.y * xk.x;
-        y[i] = v;
-      }
+    acc = chol_sum16(acc);
+    if (q == 0) {
+      const double2 yi = y[i * NB + r];
+      t[r] = make_double2(yi.x - acc.x, yi.y - acc.y);
     }
     __syncthreads();
+    const double2 d = D[(size_t)i * NB * NB + q * NB + r], tq = t[q];  // conj(D[q][r]) t_q
+    double2 p = make_double2(d.x * tq.x + d.y * tq.y, d.x * tq.y - d.y * tq.x);
+    p = chol_sum16(p);
+    if (q == 0) y[i * NB + r] = p;
+    __syncthreads();
   }
-  for (int i = tid; i < P; i += nt) Rinv[(size_t)i * P + c] = make_float2((float)y[i].x, (float)y[i].y);
+  for (int i = tid; i < P; i += blockDim.x) Rinv[(size_t)i * P + c] = make_float2((float)y[i].x, (float)y[i].y);
 }
 
 // The same factorisation and inverse with both triangles resident in LDS
@@ -1216,6 +1326,11 @@ hipError_t launch_reduce(const RedParams& pr, hipStream_t st) {
   return hipGetLastError();
 }
 
+size_t chol_work_elems(int P) {
+  const size_t nbk = (size_t)(P + kCholNB - 1) / kCholNB;
+  return (size_t)2 * P * P + nbk * kCholNB * kCholNB;
+}
+
 hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, float2* Rinv,
                                int* status, hipStream_t st) {
   if (P <= kCholLdsMaxP) {
@@ -1223,11 +1338,34 @@ hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, 
     hipLaunchKernelGGL(chol_inverse_lds_kernel, dim3(1), dim3(256), 0, st, one, (const CholItem*)nullptr, P);
   } else {
     if (P > kCholMaxRows) return hipErrorInvalidValue;
-    // W holds two P x P FP64 matrices: L (row-major) and its transpose
+    // W holds two P x P FP64 matrices, L (row-major) and its transpose, then the inverses of the
+    // diagonal blocks (chol_work_elems)
     double2* LT = W + (size_t)P * P;
-    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(1024), 0, st, R, P, W, LT, status);
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(P), dim3(256), 0, st, (const double2*)W, (const double2*)LT, P,
-                       (const int*)status, Li, Rinv);
+    hipLaunchKernelGGL(chol_convert_kernel, dim3(1), dim3(1024), 0, st, R, P, W, status);
+    for (int j0 = 0; j0 < P; j0 += kCholNB) {
+      const int nb = std::min(kCholNB, P - j0), m = P - j0 - nb;
+      switch (nb) {  // panel width: 16, or the last panel's remainder
+#define CHOL_PANEL(N)                                                                             \
+  case N:                                                                                         \
+    hipLaunchKernelGGL(chol_panel_kernel<N>, dim3(1), dim3(512), 0, st, W, LT, P, j0, status);    \
+    break;
+        CHOL_PANEL(1) CHOL_PANEL(2) CHOL_PANEL(3) CHOL_PANEL(4) CHOL_PANEL(5) CHOL_PANEL(6) CHOL_PANEL(7)
+        CHOL_PANEL(8) CHOL_PANEL(9) CHOL_PANEL(10) CHOL_PANEL(11) CHOL_PANEL(12) CHOL_PANEL(13)
+        CHOL_PANEL(14) CHOL_PANEL(15) CHOL_PANEL(16)
+#undef CHOL_PANEL
+        default: return hipErrorInvalidValue;
+      }
+      if (m > 0) {
+        const int T = (m + kCholTile - 1) / kCholTile;
+        hipLaunchKernelGGL(chol_update_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, st, W, P, j0, nb,
+                           (const int*)status);
+      }
+    }
+    double2* D = LT + (size_t)P * P;
+    hipLaunchKernelGGL(chol_dinv_kernel, dim3((P + kCholNB - 1) / kCholNB), dim3(64), 0, st, (const double2*)W, P,
+                       (const int*)status, D);
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(P), dim3(256), 0, st, (const double2*)W, (const double2*)LT,
+                       (const double2*)D, P, (const int*)status, Li, Rinv);
   }
   return hipGetLastError();
 }

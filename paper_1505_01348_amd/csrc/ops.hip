@@ -692,29 +692,27 @@ __global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) 
 
 // ---------------------------------------------------------------------------
 // FP64 Cholesky R = L L^H for arrays beyond the LDS-resident kernel below:
-// a blocked right-looking factorisation of W (row-major; the lower triangle
-// is read and overwritten by L) in panels of kCholNB columns, one launch per
-// panel and one per trailing update, then the inverse.
+// a blocked right-looking factorisation in panels of kCholNB columns.  W holds
+// L row-major, LT its transpose, D the inverses D_b of the diagonal blocks
+// L_bb (kCholNB x kCholNB row-major, zero above the diagonal and beyond the
+// array).  One launch per panel:
 //
-// chol_convert_kernel (one workgroup): W = R in FP64, status 2 for a
-// non-finite entry, else 0.
-// chol_panel_kernel (one workgroup): the panel's diagonal block is factored
-// in LDS one column at a time (pivot, scale, update of its later columns);
-// every row below it then takes the same steps on its own panel entries in
-// registers (divide by the pivot, subtract from the later entries), no
-// barrier needed.  Status 1 for a pivot that is not positive.  The factor is
-// also stored transposed (LT[k][i] = L[i][k]) so that columns of L are
-// contiguous for the forward substitution.
-// chol_update_kernel (one workgroup per 32 x 32 tile of the trailing lower
-// triangle): W[i][k] -= sum_c L[i][c] conj(L[k][c]) over the panel's
-// columns, the two row blocks of the panel staged in LDS.
-// Each entry sees the operations of the one-workgroup blocked factorisation
-// in the same order.
+// chol_convert_kernel (one workgroup): W = R in FP64 and the first diagonal
+// block factored (status 2 for a non-finite entry, 1 for a pivot that is not
+// positive, else 0).
+// chol_update_kernel (panel j; one workgroup per 32 x 32 tile of the trailing
+// lower triangle): the panel's rows below its diagonal block,
+// L_ij = A_ij L_jj^-H = A_ij D_j^H, formed in LDS for the tile's two row
+// blocks (the diagonal tiles record them in LT), then
+// W[i][k] -= sum_c L[i][c] conj(L[k][c]) over the panel's columns; the
+// workgroup of the first tile, which holds the whole next diagonal block once
+// updated, factors it (chol_block) and stores L_bb and D_b.
+// chol_lower_kernel: the rows of L below the diagonal blocks copied from LT
+// into W (the update launches read the panel's entries of W while it is
+// formed, so they do not overwrite them).
+// A diagonal block is factored in LDS one column at a time (chol_block); its
+// inverse by forward substitution, one thread per column.
 //
-// chol_dinv_kernel (one wave per diagonal block of kCholNB rows): D_b, the
-// inverse of the block's lower-triangular factor, by forward substitution
-// (one lane per column), kCholNB x kCholNB row-major, zero above the diagonal
-// and beyond the last row.
 // chol_solve_kernel (one workgroup per column c of the identity): forward
 // substitution L y = e_c by blocks of kCholNB rows (y_i = -D_i sum_k L_ik y_k,
 // y = column c of L^-1, stored when Li is given), then backward substitution
@@ -726,14 +724,96 @@ constexpr int kCholNB = 16;
 constexpr int kCholMaxRows = 288;  // the largest array (CLSIMG_MAX_P)
 constexpr int kCholTile = 32;
 
-__global__ __launch_bounds__(1024) void chol_convert_kernel(const float2* __restrict__ R, int P,
-                                                            double2* __restrict__ W, int* __restrict__ status) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
+// Factor the n x n block in a (kCholNB rows of kCholNB + 1, lower triangle)
+// in place; rl[c] = 1 / L_cc.  Every thread of the workgroup calls it
+// (blockDim >= kCholNB^2, after a barrier that made a visible); false, in
+// every thread, for a pivot that is not positive.  Column c's step subtracts
+// a[r][c] conj(a[c2][c]) / a[c][c] from the later columns (r >= c2 > c) while
+// column c itself stays unscaled, so a step reads only what the previous one
+// wrote (one barrier per column); the columns are scaled by 1 / sqrt(pivot) at
+// the end.
+__device__ __forceinline__ bool chol_block(double2* a, double* rl, int n) {
+  constexpr int NB = kCholNB, LDP = NB + 1;
+  const int tid = threadIdx.x, r = tid / NB, c2 = tid - r * NB;
+  const bool mine = tid < NB * NB && r < n && c2 <= r;
+  for (int c = 0; c < n; ++c) {
+    const double d = a[c * LDP + c].x;  // the same value in every thread: the exit is uniform
+    if (!(d > 0.0)) return false;
+    if (mine && c2 > c) {
+      const double rd = 1.0 / d;
+      const double2 x = a[r * LDP + c], b = a[c2 * LDP + c];
+      double2 v = a[r * LDP + c2];
+      v.x -= (x.x * b.x + x.y * b.y) * rd;
+      v.y -= (x.y * b.x - x.x * b.y) * rd;
+      a[r * LDP + c2] = v;
+    }
+    __syncthreads();
+  }
+  double2 v = make_double2(0.0, 0.0);
+  double ljj = 1.0;
+  if (mine) {
+    ljj = sqrt(a[c2 * LDP + c2].x);
+    v = a[r * LDP + c2];
+  }
   __syncthreads();
-  const int n = P * P, nt = blockDim.x;
-  int e = threadIdx.x;
-  for (; e + 7 * nt < n; e += 8 * nt) {
+  if (mine) {
+    a[r * LDP + c2] = r == c2 ? make_double2(ljj, 0.0) : make_double2(v.x / ljj, v.y / ljj);
+    if (r == c2) rl[c2] = 1.0 / ljj;
+  }
+  __syncthreads();
+  return true;
+}
+
+// After chol_block: L_bb to W and LT at (b0, b0), D_b = L_bb^-1 to Db.
+__device__ __forceinline__ void chol_block_store(const double2* a, const double* rl, int n, int b0, int P,
+                                                 double2* __restrict__ W, double2* __restrict__ LT,
+                                                 double2* __restrict__ Db) {
+  constexpr int NB = kCholNB, LDP = NB + 1;
+  const int tid = threadIdx.x;
+  if (tid < NB * NB) {
+    const int r = tid / NB, c = tid - r * NB;
+    if (r < n && c <= r) {
+      const double2 v = a[r * LDP + c];
+      W[(size_t)(b0 + r) * P + b0 + c] = v;
+      LT[(size_t)(b0 + c) * P + b0 + r] = v;
+    }
+  }
+  if (tid < NB) {  // column cc of the inverse
+    const int cc = tid;
+    double2 x[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) x[r] = make_double2(r == cc ? 1.0 : 0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (k < n) {
+        const double q = rl[k];
+        x[k] = make_double2(x[k].x * q, x[k].y * q);
+#pragma unroll
+        for (int r = k + 1; r < NB; ++r) {
+          const double2 l = a[r * LDP + k];
+          x[r].x -= l.x * x[k].x - l.y * x[k].y;
+          x[r].y -= l.x * x[k].y + l.y * x[k].x;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) Db[r * NB + cc] = (r < n && cc < n) ? x[r] : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(1024) void chol_convert_kernel(const float2* __restrict__ R, int P,
+                                                            double2* __restrict__ W, double2* __restrict__ LT,
+                                                            double2* __restrict__ D, int* __restrict__ status) {
+  constexpr int NB = kCholNB, LDP = NB + 1;
+  __shared__ int bad;
+  __shared__ double2 a[NB * LDP];
+  __shared__ double rl[NB];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  const int n2 = P * P;
+  int e = tid;
+  for (; e + 7 * nt < n2; e += 8 * nt) {
     float2 v[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = R[e + k * nt];
@@ -743,96 +823,39 @@ __global__ __launch_bounds__(1024) void chol_convert_kernel(const float2* __rest
       W[e + k * nt] = make_double2((double)v[k].x, (double)v[k].y);
     }
   }
-  for (; e < n; e += nt) {
+  for (; e < n2; e += nt) {
     const float2 v = R[e];
     if (!isfinite(v.x) || !isfinite(v.y)) bad = 2;
     W[e] = make_double2((double)v.x, (double)v.y);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) *status = bad;
-}
-
-template <int NB>
-__global__ __launch_bounds__(512) void chol_panel_kernel(double2* __restrict__ W, double2* __restrict__ LT, int P,
-                                                         int j0, int* __restrict__ status) {
-  constexpr int LDP = kCholNB + 1;
-  __shared__ double2 d11[kCholNB * LDP];
-  if (*status != 0) return;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  constexpr int nb = NB;
-  const int rows = P - j0;
-  for (int e = tid; e < nb * nb; e += nt) {
-    const int r = e / nb, c = e - r * nb;
-    d11[r * LDP + c] = W[(size_t)(j0 + r) * P + j0 + c];
+  // the first diagonal block, from R
+  const int n = min(NB, P);
+  if (tid < NB * NB) {
+    const int r = tid / NB, c = tid - r * NB;
+    const float2 v = (r < n && c <= r) ? R[r * P + c] : make_float2(0.f, 0.f);
+    a[r * LDP + c] = make_double2((double)v.x, (double)v.y);
   }
   __syncthreads();
-  for (int c = 0; c < nb; ++c) {
-    const double d = d11[c * LDP + c].x;  // the same value in every thread: the exit is uniform
-    if (!(d > 0.0)) {
-      if (tid == 0) *status = 1;
-      return;
-    }
-    const double ljj = sqrt(d);
-    if (tid > c && tid < nb) {
-      const double2 v = d11[tid * LDP + c];
-      d11[tid * LDP + c] = make_double2(v.x / ljj, v.y / ljj);
-    }
-    __syncthreads();
-    if (tid == 0) d11[c * LDP + c] = make_double2(ljj, 0.0);
-    // later columns of the block: d11[r][c2] -= d11[r][c] conj(d11[c2][c]), r >= c2 > c
-    if (tid < nb * nb) {
-      const int r = tid / nb, c2 = tid - r * nb;
-      if (c2 > c && r >= c2) {
-        const double2 a = d11[r * LDP + c], bb = d11[c2 * LDP + c];
-        double2 x = d11[r * LDP + c2];
-        x.x -= a.x * bb.x + a.y * bb.y;
-        x.y -= a.y * bb.x - a.x * bb.y;
-        d11[r * LDP + c2] = x;
-      }
-    }
-    __syncthreads();
+  if (bad) {
+    if (tid == 0) *status = bad;
+    return;
   }
-  for (int e = tid; e < nb * nb; e += nt) {
-    const int r = e / nb, c = e - r * nb;
-    if (r >= c) {
-      const double2 v = d11[r * LDP + c];
-      W[(size_t)(j0 + r) * P + j0 + c] = v;
-      LT[(size_t)(j0 + c) * P + j0 + r] = v;
-    }
+  if (!chol_block(a, rl, n)) {
+    if (tid == 0) *status = 1;
+    return;
   }
-  // rows below the block (one per thread: P - nb <= 512): the column steps on
-  // the row's own entries
-  {
-    const int r = nb + tid;
-    if (r >= rows) return;
-    double2 x[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) x[c] = W[(size_t)(j0 + r) * P + j0 + c];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const double ljj = d11[c * LDP + c].x;
-      x[c] = make_double2(x[c].x / ljj, x[c].y / ljj);
-#pragma unroll
-      for (int c2 = c + 1; c2 < NB; ++c2) {
-        const double2 bb = d11[c2 * LDP + c];
-        x[c2].x -= x[c].x * bb.x + x[c].y * bb.y;
-        x[c2].y -= x[c].y * bb.x - x[c].x * bb.y;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      W[(size_t)(j0 + r) * P + j0 + c] = x[c];
-      LT[(size_t)(j0 + c) * P + j0 + r] = x[c];
-    }
-  }
+  chol_block_store(a, rl, n, 0, P, W, LT, D);
+  if (tid == 0) *status = 0;
 }
 
-__global__ __launch_bounds__(256) void chol_update_kernel(double2* __restrict__ W, int P, int j0, int nb,
-                                                          const int* __restrict__ status) {
-  constexpr int LDP = kCholNB + 1;
-  __shared__ double2 li[kCholTile * LDP], lk[kCholTile * LDP];
+__global__ __launch_bounds__(256) void chol_update_kernel(double2* __restrict__ W, double2* __restrict__ LT,
+                                                          double2* __restrict__ D, int P, int j0,
+                                                          int* __restrict__ status) {
+  constexpr int NB = kCholNB, LDP = NB + 1, T = kCholTile;
+  __shared__ double2 ai[T * LDP], ak[T * LDP], li[T * LDP], lk[T * LDP], dj[NB * NB], a[NB * LDP];
+  __shared__ double rl[NB];
   if (*status != 0) return;
-  const int t0 = j0 + nb;
+  const int t0 = j0 + NB;
   // this workgroup's tile (ti, tk), tk <= ti, in row-major order of the lower triangle
   int ti = 0, b = blockIdx.x;
   while (b > ti) {
@@ -840,37 +863,87 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double2* __restrict__ 
     ++ti;
   }
   const int tk = b;
-  const int i0 = t0 + kCholTile * ti, k0 = t0 + kCholTile * tk;
+  const int i0 = t0 + T * ti, k0 = t0 + T * tk;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kCholTile * kCholNB; e += blockDim.x) {
-    const int r = e / kCholNB, c = e - r * kCholNB;
-    li[r * LDP + c] = (i0 + r < P && c < nb) ? W[(size_t)(i0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
-    lk[r * LDP + c] = (k0 + r < P && c < nb) ? W[(size_t)(k0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
+  dj[tid] = D[(size_t)(j0 / NB) * NB * NB + tid];  // 256 threads = NB * NB
+  for (int e = tid; e < T * NB; e += blockDim.x) {
+    const int r = e / NB, c = e - r * NB;
+    ai[r * LDP + c] = i0 + r < P ? W[(size_t)(i0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
+    ak[r * LDP + c] = k0 + r < P ? W[(size_t)(k0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
+  }
+  // this thread's trailing entries: row i0 + (tid >> 3), columns k0 + (tid & 7) + 8 u
+  const int ri = tid >> 3, i = i0 + ri;
+  double2 wv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = k0 + (tid & 7) + 8 * u;
+    wv[u] = (i < P && k <= i) ? W[(size_t)i * P + k] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  // thread: row i0 + (tid >> 3), columns k0 + (tid & 7) + 8 u
-  const int ri = tid >> 3, i = i0 + ri;
-  if (i >= P) return;
-  double2 wv[4], acc[4];
+  // the panel's rows of L: l[r][c] = sum_{c1 <= c} a[r][c1] conj(D_j[c][c1])
+  for (int e = tid; e < T * NB; e += blockDim.x) {
+    const int r = e / NB, c = e - r * NB;
+    double2 si = make_double2(0.0, 0.0), sk = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int k = k0 + (tid & 7) + 8 * u;
-    wv[u] = k <= i ? W[(size_t)i * P + k] : make_double2(0.0, 0.0);
-    acc[u] = make_double2(0.0, 0.0);
+    for (int c1 = 0; c1 < NB; ++c1)
+      if (c1 <= c) {
+        const double2 d = dj[c * NB + c1], x = ai[r * LDP + c1], y = ak[r * LDP + c1];
+        si.x += x.x * d.x + x.y * d.y;
+        si.y += x.y * d.x - x.x * d.y;
+        sk.x += y.x * d.x + y.y * d.y;
+        sk.y += y.y * d.x - y.x * d.y;
+      }
+    li[r * LDP + c] = si;
+    lk[r * LDP + c] = sk;
   }
-  for (int c = 0; c < nb; ++c) {
-    const double2 a = li[ri * LDP + c];
+  __syncthreads();
+  if (ti == tk)  // the tile's rows of the panel, recorded transposed
+    for (int e = tid; e < T * NB; e += blockDim.x) {
+      const int c = e / T, r = e - c * T;
+      if (i0 + r < P) LT[(size_t)(j0 + c) * P + i0 + r] = li[r * LDP + c];
+    }
+  double2 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = make_double2(0.0, 0.0);
+#pragma unroll 4
+  for (int c = 0; c < NB; ++c) {
+    const double2 x = li[ri * LDP + c];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double2 bb = lk[((tid & 7) + 8 * u) * LDP + c];
-      acc[u].x += a.x * bb.x + a.y * bb.y;
-      acc[u].y += a.y * bb.x - a.x * bb.y;
+      const double2 y = lk[((tid & 7) + 8 * u) * LDP + c];
+      acc[u].x += x.x * y.x + x.y * y.y;
+      acc[u].y += x.y * y.x - x.x * y.y;
     }
   }
+  const bool first = ti == 0 && tk == 0;  // holds the next diagonal block (rows and columns t0 .. t0 + NB - 1)
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int k = k0 + (tid & 7) + 8 * u;
-    if (k <= i) W[(size_t)i * P + k] = make_double2(wv[u].x - acc[u].x, wv[u].y - acc[u].y);
+    const int kc = (tid & 7) + 8 * u, k = k0 + kc;
+    const double2 v = make_double2(wv[u].x - acc[u].x, wv[u].y - acc[u].y);
+    if (first && ri < NB && kc < NB)
+      a[ri * LDP + kc] = (i < P && k <= i) ? v : make_double2(0.0, 0.0);
+    else if (i < P && k <= i)
+      W[(size_t)i * P + k] = v;
+  }
+  if (first) {
+    const int n = min(NB, P - t0);
+    __syncthreads();
+    if (!chol_block(a, rl, n)) {
+      if (tid == 0) *status = 1;
+      return;
+    }
+    chol_block_store(a, rl, n, t0, P, W, LT, D + (size_t)(t0 / NB) * NB * NB);
+  }
+}
+
+__global__ __launch_bounds__(256) void chol_lower_kernel(double2* __restrict__ W, const double2* __restrict__ LT,
+                                                         int P, const int* __restrict__ status) {
+  constexpr int NB = kCholNB;
+  if (*status != 0) return;
+  const int bi = blockIdx.x + 1, r0 = bi * NB, n = min(NB, P - r0);
+  for (int e = threadIdx.x; e < r0 * NB; e += blockDim.x) {
+    const int k = e / NB, r = e - k * NB;
+    if (r < n) W[(size_t)(r0 + r) * P + k] = LT[(size_t)k * P + r0 + r];
   }
 }
 
@@ -882,39 +955,6 @@ __device__ inline double2 chol_sum16(double2 v) {
     v.y += __shfl_xor(v.y, o, 16);
   }
   return v;
-}
-
-__global__ __launch_bounds__(64) void chol_dinv_kernel(const double2* __restrict__ L, int P,
-                                                       const int* __restrict__ status, double2* __restrict__ D) {
-  constexpr int NB = kCholNB, LDP = NB + 1;
-  __shared__ double2 a[NB * LDP];
-  if (*status != 0) return;
-  const int b = blockIdx.x, i0 = b * NB, n = min(NB, P - i0), tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int r = e / NB, k = e - r * NB;
-    a[r * LDP + k] = (r < n && k <= r) ? L[(size_t)(i0 + r) * P + i0 + k] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  if (tid >= NB) return;
-  const int cc = tid;
-  double2 x[NB];  // column cc of the block's inverse
-#pragma unroll
-  for (int r = 0; r < NB; ++r) x[r] = make_double2(r == cc ? 1.0 : 0.0, 0.0);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (k < n) {
-      const double lkk = a[k * LDP + k].x;
-      x[k] = make_double2(x[k].x / lkk, x[k].y / lkk);
-#pragma unroll
-      for (int r = k + 1; r < NB; ++r) {
-        const double2 l = a[r * LDP + k];
-        x[r].x -= l.x * x[k].x - l.y * x[k].y;
-        x[r].y -= l.x * x[k].y + l.y * x[k].x;
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NB; ++r) D[(size_t)b * NB * NB + r * NB + cc] = (r < n && cc < n) ? x[r] : make_double2(0.0, 0.0);
 }
 
 __global__ __launch_bounds__(256) void chol_solve_kernel(const double2* __restrict__ L, const double2* __restrict__ LT,
@@ -1341,29 +1381,15 @@ hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, 
     // W holds two P x P FP64 matrices, L (row-major) and its transpose, then the inverses of the
     // diagonal blocks (chol_work_elems)
     double2* LT = W + (size_t)P * P;
-    hipLaunchKernelGGL(chol_convert_kernel, dim3(1), dim3(1024), 0, st, R, P, W, status);
-    for (int j0 = 0; j0 < P; j0 += kCholNB) {
-      const int nb = std::min(kCholNB, P - j0), m = P - j0 - nb;
-      switch (nb) {  // panel width: 16, or the last panel's remainder
-#define CHOL_PANEL(N)                                                                             \
-  case N:                                                                                         \
-    hipLaunchKernelGGL(chol_panel_kernel<N>, dim3(1), dim3(512), 0, st, W, LT, P, j0, status);    \
-    break;
-        CHOL_PANEL(1) CHOL_PANEL(2) CHOL_PANEL(3) CHOL_PANEL(4) CHOL_PANEL(5) CHOL_PANEL(6) CHOL_PANEL(7)
-        CHOL_PANEL(8) CHOL_PANEL(9) CHOL_PANEL(10) CHOL_PANEL(11) CHOL_PANEL(12) CHOL_PANEL(13)
-        CHOL_PANEL(14) CHOL_PANEL(15) CHOL_PANEL(16)
-#undef CHOL_PANEL
-        default: return hipErrorInvalidValue;
-      }
-      if (m > 0) {
-        const int T = (m + kCholTile - 1) / kCholTile;
-        hipLaunchKernelGGL(chol_update_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, st, W, P, j0, nb,
-                           (const int*)status);
-      }
-    }
     double2* D = LT + (size_t)P * P;
-    hipLaunchKernelGGL(chol_dinv_kernel, dim3((P + kCholNB - 1) / kCholNB), dim3(64), 0, st, (const double2*)W, P,
-                       (const int*)status, D);
+    const int nbk = (P + kCholNB - 1) / kCholNB;
+    hipLaunchKernelGGL(chol_convert_kernel, dim3(1), dim3(1024), 0, st, R, P, W, LT, D, status);
+    for (int j0 = 0; j0 + kCholNB < P; j0 += kCholNB) {
+      const int T = (P - j0 - kCholNB + kCholTile - 1) / kCholTile;
+      hipLaunchKernelGGL(chol_update_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, st, W, LT, D, P, j0, status);
+    }
+    hipLaunchKernelGGL(chol_lower_kernel, dim3(nbk - 1), dim3(256), 0, st, W, (const double2*)LT, P,
+                       (const int*)status);
     hipLaunchKernelGGL(chol_solve_kernel, dim3(P), dim3(256), 0, st, (const double2*)W, (const double2*)LT,
                        (const double2*)D, P, (const int*)status, Li, Rinv);
   }

@@ -78,8 +78,10 @@ extern "C" {
 #define CLSIMG_COST_PWLS 1   /* preconditioned weighted LS, eq. preWLS: R^-1/2 weighting  */
                              /* on both sides, variable D sigma with D_i = h_i^2 / C,     */
                              /* h_i = a_i^H R^-1 a_i; threshold kappa_d std of the MVDR   */
-                             /* image (App. A).  Needs P <= 48 and free sets that fit one */
-                             /* workgroup (CLSIMG_ENOTSUP otherwise).                     */
+                             /* image (App. A).  Needs P <= 96 (CLSIMG_ENOTSUP beyond):    */
+                             /* the device-resident loop up to 48, the host-driven loop   */
+                             /* (whitened steering rows of the free set) beyond, or when  */
+                             /* the free set outgrows one workgroup.                      */
 
 /* loop driving the Table I iteration (clsimg_opts.loop); both give the same
  * iterates and results */

@@ -53,6 +53,7 @@ struct clsimg_ctx {
   DevBuf lsqr2, done, x1, w1, vraw, bpart0, bpart1, xf, bar;  // fused LSQR step
   DevBuf ostate;                                                // device-resident outer loop
   DevBuf pw_h, pw_rs, pw_g, pw_eps, pw_dinv, pw_Lw, pw_B0w;      // PWLS inputs
+  DevBuf pw_T, pw_Bw, pw_Eh, pw_nrm;  // PWLS on the host-driven loop: products with L^-1, whitened b and E
   DevBuf batch, batch_params, batch_rinv;                       // batched solve workspace
   // autotuned 16-pixel tiles per workgroup of the GEMM-shaped beamformers, by
   // precision (FP32, FP16, BF16) and row tiles per wave; 0: the default
@@ -701,8 +702,8 @@ int clsimg_create(clsimg_ctx** out, int32_t device, size_t budget) {
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess)
     c->coop = coop != 0;
   void* hp = nullptr;
-  // room for the norm partials of the largest array (reduce_blocks grows as P^2)
-  const int nnorm = reduce_blocks(CLSIMG_MAX_P);
+  // room for the norm partials of the largest array (reduce_blocks grows as P^2), or one per row
+  const int nnorm = std::max(reduce_blocks(CLSIMG_MAX_P), CLSIMG_MAX_P);
   const size_t hbytes =
       sizeof(SolveDecision) + sizeof(LsqrState) + 4 * sizeof(int) + nnorm * sizeof(double) + sizeof(OuterState);
   if (hipHostMalloc(&hp, hbytes, hipHostMallocDefault) != hipSuccess ||
@@ -735,7 +736,7 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (!c) return CLSIMG_EINVAL;
   DeviceGuard guard(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->ElT, &c->EmT, &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->batch, &c->batch_params, &c->batch_rinv, &c->part,  &c->beta_part,
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->ElT, &c->EmT, &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->pw_T, &c->pw_Bw, &c->pw_Eh, &c->pw_nrm, &c->batch, &c->batch_params, &c->batch_rinv, &c->part,  &c->beta_part,
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
@@ -1110,16 +1111,21 @@ int solve_setup(SolveRun& r, const clsimg_c32* R, const clsimg_array* a, const f
   const size_t nalpha_max = (size_t)(Q / 16 + 64);  // one per 16-pixel tile
   ST_TRY(ensure(c, c->alpha_part, nalpha_max * sizeof(double)));
 
-  // PWLS runs on the device-resident loop only (P <= 48)
+  // PWLS: on the device-resident loop, or on the host-driven loop with the
+  // whitened steering rows in the free-set cache (up to 12 row tiles, P <= 96)
   r.pwls = o->cost == CLSIMG_COST_PWLS;
   r.device_loop = beam_fits(P) && outer_fits(P) && o->loop == CLSIMG_LOOP_AUTO && !o->trace;
-  if (r.pwls && !r.device_loop) return CLSIMG_ENOTSUP;
+  if (r.pwls && pad_p(P) / 8 > 12) return CLSIMG_ENOTSUP;
   if (r.pwls && o->nsamples <= P + 1 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
   if (r.pwls) {
     for (DevBuf* b : {&c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv})
       ST_TRY(ensure(c, *b, (size_t)Q * sizeof(float)));
     ST_TRY(ensure(c, c->pw_Lw, (size_t)P * P * sizeof(float2)));
     ST_TRY(ensure(c, c->pw_B0w, (size_t)P * P * sizeof(float2)));
+    ST_TRY(ensure(c, c->pw_T, (size_t)P * P * sizeof(double2)));
+    ST_TRY(ensure(c, c->pw_Bw, (size_t)P * P * sizeof(float2)));
+    ST_TRY(ensure(c, c->pw_Eh, (size_t)P * P * sizeof(float2)));
+    ST_TRY(ensure(c, c->pw_nrm, (size_t)P * sizeof(double)));
   }
   ST_TRY(ensure(c, c->eps, (size_t)Q * sizeof(float)));
   if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
@@ -1186,6 +1192,11 @@ int solve_setup(SolveRun& r, const clsimg_c32* R, const clsimg_array* a, const f
   if (r.beam_half)
     ST_TRY(need_all({{&c->mx_lam, fq}, {&c->mx_cand, (size_t)r.cand_cap * sizeof(int)}, {&c->mx_count, sizeof(int)},
                      {&c->mx_abs, kCandAbsParts * sizeof(double)}, {&c->hscale, sizeof(float)}}));
+  if (r.pwls)
+    ST_TRY(need_all({{&c->pw_h, fq}, {&c->pw_rs, fq}, {&c->pw_g, fq}, {&c->pw_eps, fq}, {&c->pw_dinv, fq},
+                     {&c->pw_Lw, cx}, {&c->pw_B0w, cx}, {&c->pw_T, (size_t)P * P * sizeof(double2)},
+                     {&c->pw_Bw, cx}, {&c->pw_Eh, cx}, {&c->pw_nrm, (size_t)P * sizeof(double)},
+                     {&c->Li, (size_t)P * P * sizeof(double2)}}));
 
   r.mf = mf_out ? mf_out : P_<float>(c->mf);
   r.gamma = gamma_out ? gamma_out : P_<float>(c->gamma);
@@ -1261,7 +1272,18 @@ int solve_setup(SolveRun& r, const clsimg_c32* R, const clsimg_array* a, const f
     const double kd = o->kappa_d != 0.0 ? o->kappa_d / sqrt((double)(o->nsamples - P - 1)) : 0.0;
     HIP_TRY(launch_pwls_setup(h, r.gamma, o->C, kd, Q, P_<float>(c->pw_rs), P_<float>(c->pw_g),
                               P_<float>(c->pw_eps), P_<float>(c->pw_dinv), st));
-    HIP_TRY(launch_pwls_whiten(P_<const double2>(c->Li), r.B0, P, P_<float2>(c->pw_Lw), P_<float2>(c->pw_B0w), st));
+    const double2* Li = P_<const double2>(c->Li);
+    if (P <= 48) {  // L^-1 in FP32 for the device loop, and the whitened data
+      HIP_TRY(launch_pwls_whiten(Li, r.B0, P, P_<float2>(c->pw_Lw), P_<float2>(c->pw_B0w), st));
+      HIP_TRY(launch_pwls_sandwich(Li, r.B0, P, false, P_<double2>(c->pw_T), P_<float2>(c->pw_Bw),
+                                   P_<double>(c->pw_nrm), st));  // its norm only
+    } else {
+      HIP_TRY(launch_pwls_sandwich(Li, r.B0, P, false, P_<double2>(c->pw_T), P_<float2>(c->pw_B0w),
+                                   P_<double>(c->pw_nrm), st));
+    }
+    // the host-driven loop reports the residual relative to the whitened data
+    ST_TRY(read_back(c, c->h_norms, c->pw_nrm.ptr, (size_t)P * sizeof(double), st));
+    r.b0norm = sqrt(sum_host(c->h_norms, P));
     if (sigma0) HIP_TRY(launch_pwls_scale(r.sigma, P_<const float>(c->pw_dinv), Q, true, st));  // D sigma0
     r.lam_scale = P_<const float>(c->pw_dinv);
     r.op_gamma = P_<const float>(c->pw_g);
@@ -1330,10 +1352,6 @@ int solve_device_loop(SolveRun& r) {
   r.host_loop = S.fallback != 0;
   r.dev_res2 = S.res2;
   r.dev_b0n2 = S.b0n2;
-  if (r.pwls) {
-    if (r.host_loop) return CLSIMG_ENOTSUP;  // the host loop has no PWLS path
-    HIP_TRY(launch_pwls_scale(r.sigma, P_<const float>(c->pw_dinv), r.Q, false, st));  // sigma = D^-1 (D sigma)
-  }
   return CLSIMG_OK;
 }
 
@@ -1344,6 +1362,7 @@ int host_multipliers(SolveRun& r, bool fp32_only) {
   clsimg_ctx* c = r.c;
   hipStream_t st = r.st;
   const int P = r.P, Q = r.Q;
+  if (r.pwls) fp32_only = true;  // PWLS: the multipliers in FP32, scaled by 1 / D_i
   if (r.beam_half && !fp32_only) {
     const bool bf = c->prec == CLSIMG_BF16;
     int* count = P_<int>(c->mx_count);
@@ -1360,14 +1379,16 @@ int host_multipliers(SolveRun& r, bool fp32_only) {
     HIP_TRY(launch_argmin_final(r.keys, (r.cand_cap + r.cand_tile - 1) / r.cand_tile, r.eps, r.state, r.dec, st,
                                 count, r.cand_cap));
   } else if (r.beam_full_grid) {
-    HIP_TRY(launch_beam_lambda(nullptr, r.E, P, r.tab(), r.grad_stop, r.state, r.keys, nullptr, st));
-    HIP_TRY(launch_argmin_final(r.keys, beam_grid(Q), r.eps, r.state, r.dec, st));
+    HIP_TRY(launch_beam_lambda(nullptr, r.E, P, r.tab(), r.grad_stop, r.state, r.keys, r.lam_scale, st));
+    HIP_TRY(launch_argmin_final(r.keys, beam_grid(Q), r.op_eps, r.state, r.dec, st));
   } else if (r.beam_big_grid_ok) {
     HIP_TRY(launch_beam_prep_full(r.E, P, P_<float>(c->frag_b), st));
     HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), r.tab(), r.grad_stop, nullptr, nullptr, 0.f, 0, 0, 1.f,
-                            r.state, r.keys, st, fp32_only ? Stamps{} : r.mult_stamps, big_tiles(c, P)));
-    HIP_TRY(launch_argmin_final(r.keys, beam_big_grid(P, Q, big_tiles(c, P)), r.eps, r.state, r.dec, st));
+                            r.state, r.keys, st, fp32_only ? Stamps{} : r.mult_stamps, big_tiles(c, P),
+                            r.lam_scale));
+    HIP_TRY(launch_argmin_final(r.keys, beam_big_grid(P, Q, big_tiles(c, P)), r.op_eps, r.state, r.dec, st));
   } else {
+    if (r.pwls) return CLSIMG_ENOTSUP;
     HIP_TRY(launch_adjoint_lambda(adj_params(c, r.g, P, r.frag_r, nullptr, Q, r.grad_stop), r.state, r.keys, st));
     HIP_TRY(launch_argmin_final(r.keys, r.ntiles_Q, r.eps, r.state, r.dec, st));
   }
@@ -1396,6 +1417,19 @@ int host_subproblem(SolveRun& r) {
     bsub = r.Bb;
   }
   r.flops += corr_flops(P, r.nU);
+  // PWLS (eq. preWLS): the subproblem in whitened variables, L^-1 b L^-H with
+  // the bound D gamma for D sigma (sum_U gamma_i a_i a_i^H whitens to the
+  // same terms with D gamma and the whitened rows)
+  const double2* Li = P_<const double2>(c->Li);
+  if (r.pwls) {
+    if (!fused) return CLSIMG_ENOTSUP;
+    if (r.nU > 0) {
+      HIP_TRY(launch_pwls_sandwich(Li, bsub, P, false, P_<double2>(c->pw_T), P_<float2>(c->pw_Bw), nullptr, st));
+      bsub = P_<const float2>(c->pw_Bw);
+    } else {
+      bsub = r.op_B0;
+    }
+  }
   const int nF = r.nF;
   if (fused) {
     // the cache grows geometrically with |F| (a reallocation synchronises the device)
@@ -1404,6 +1438,7 @@ int host_subproblem(SolveRun& r) {
     ST_TRY(ensure(c, c->xf, cap * 2 * pad_p(P) * sizeof(float)));
     r.xf = P_<float>(c->xf);
     HIP_TRY(launch_xf(r.tab(), r.Flist, nF, r.xf, st));
+    if (r.pwls) HIP_TRY(launch_pwls_xf_whiten(Li, P, r.Flist, nF, P_<const float>(c->pw_rs), r.xf, st));
   }
   const int nalpha = ntiles_adj(P, nF);
   const int nalpha2 = (nF + adjoint_lsqr2_tile_width(MT, nF) - 1) / adjoint_lsqr2_tile_width(MT, nF);
@@ -1490,11 +1525,12 @@ int host_subproblem(SolveRun& r) {
       }
     }
     if (persist || one_cu)
-      HIP_TRY(launch_step(r.done, r.lerr, r.Sfin, r.x, r.x, r.Flist, nF, r.sigma, r.gamma, r.state, r.dec, st));
+      HIP_TRY(launch_step(r.done, r.lerr, r.Sfin, r.x, r.x, r.Flist, nF, r.sigma, r.op_gamma, r.state, r.dec, st));
     else if (fused)
-      HIP_TRY(launch_step(r.done, nullptr, r.Sfin, r.x, r.x1, r.Flist, nF, r.sigma, r.gamma, r.state, r.dec, st));
+      HIP_TRY(launch_step(r.done, nullptr, r.Sfin, r.x, r.x1, r.Flist, nF, r.sigma, r.op_gamma, r.state, r.dec, st));
     else
-      HIP_TRY(launch_step(r.lsqr_stop, nullptr, r.ls, r.x, r.x, r.Flist, nF, r.sigma, r.gamma, r.state, r.dec, st));
+      HIP_TRY(launch_step(r.lsqr_stop, nullptr, r.ls, r.x, r.x, r.Flist, nF, r.sigma, r.op_gamma, r.state, r.dec,
+                          st));
     // gradient on the active pixels, only after a feasible subproblem (eq. gls):
     // E = Psi_F sigma_F - b, then g = Psi^H E on every pixel
     if (fused) {
@@ -1505,13 +1541,16 @@ int host_subproblem(SolveRun& r) {
       cp.n = nF;
       cp.vals = r.sigma;
       cp.gidx = r.Flist;
-      cp.out = r.E;
+      cp.out = r.pwls ? P_<float2>(c->pw_Eh) : r.E;
       cp.B = bsub;
       cp.cK = 1.f;
       cp.cB = -1.f;
       cp.frag = r.frag_r;
       cp.stop_flag = r.grad_stop;
       HIP_TRY(launch_corr_os(cp, st));
+      // PWLS: the multiplier of pixel i is a_i^H (L^-H E L^-1) a_i / D_i
+      if (r.pwls)
+        HIP_TRY(launch_pwls_sandwich(Li, P_<const float2>(c->pw_Eh), P, true, P_<double2>(c->pw_T), r.E, nullptr, st));
     } else {
       ST_TRY(correlate(c, r.g, P, r.Flist, r.sigma, 1, nF, r.E, bsub, 1.f, -1.f, nullptr, r.frag_r, nullptr,
                        r.grad_stop, st));
@@ -1615,8 +1654,15 @@ int solve_stats(SolveRun& r, clsimg_stats* stats) {
                      nullptr, r.st));
     ST_TRY(correlate(c, r.g, r.P, r.Flist, r.sigma, 1, r.nF, r.E, r.Bb, 1.f, -1.f, nullptr, nullptr, r.beta_part,
                      nullptr, r.st));
-    ST_TRY(read_back(c, c->h_norms, r.beta_part, r.nbeta * sizeof(double), r.st));
-    res2 = sum_host(c->h_norms, r.nbeta);
+    if (r.pwls) {  // PWLS: the residual of the whitened problem, L^-1 (Psi sigma - b) L^-H
+      HIP_TRY(launch_pwls_sandwich(P_<const double2>(c->Li), r.E, r.P, false, P_<double2>(c->pw_T),
+                                   P_<float2>(c->pw_Eh), P_<double>(c->pw_nrm), r.st));
+      ST_TRY(read_back(c, c->h_norms, c->pw_nrm.ptr, (size_t)r.P * sizeof(double), r.st));
+      res2 = sum_host(c->h_norms, r.P);
+    } else {
+      ST_TRY(read_back(c, c->h_norms, r.beta_part, r.nbeta * sizeof(double), r.st));
+      res2 = sum_host(c->h_norms, r.nbeta);
+    }
     r.flops += corr_flops(r.P, r.nU) + corr_flops(r.P, r.nF);
   }
   stats->status = r.status;
@@ -1667,6 +1713,8 @@ int clsimg_solve(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array* a, cons
   ST_TRY(solve_setup(r, R, a, noise_diag, sigma0, state0, mf_out, gamma_out));
   if (r.device_loop) ST_TRY(solve_device_loop(r));
   if (r.host_loop) ST_TRY(solve_host_loop(r));
+  // PWLS solves for D sigma: sigma = D^-1 (D sigma)
+  if (r.pwls) HIP_TRY(launch_pwls_scale(r.sigma, P_<const float>(c->pw_dinv), r.Q, false, r.st));
   return solve_stats(r, stats);
 }
 

@@ -1183,12 +1183,12 @@ static hipError_t launch_big(const float* frag, const Tables& tab, const int* sk
 
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
-                           hipStream_t st, Stamps ts, int nt) {
+                           hipStream_t st, Stamps ts, int nt, const float* lam_scale) {
   switch (kind) {
     case 0: return launch_big(frag, tab, skip, BeamMF{out, eps, eps_scale}, st, ts, nt);
     case 1: return launch_big(frag, tab, skip, BeamMVDR{out, C, kb}, st, ts, nt);
     case 2: return launch_big(frag, tab, skip, BeamStore{out, scale}, st, ts, nt);
-    default: return launch_big(frag, tab, skip, BeamLambda{state, part, nullptr, 0}, st, ts, nt);
+    default: return launch_big(frag, tab, skip, BeamLambda{state, part, lam_scale, 0}, st, ts, nt);
   }
 }
 

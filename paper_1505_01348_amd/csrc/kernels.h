@@ -383,9 +383,10 @@ constexpr int kBigTileChoices[3] = {2, 4, 8};
 bool beam_tiles_offered(bool half, int nt, int rpw);
 hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_t st, Stamps ts = {});
 // kind: 0 MF (+ threshold), 1 MVDR bound, 2 store (scaled), 3 multipliers with argmin keys
+// lam_scale (kind 3, optional): positive per-pixel factor of the multipliers (PWLS: 1 / D_i)
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
-                           hipStream_t st, Stamps ts = {}, int nt = 0);
+                           hipStream_t st, Stamps ts = {}, int nt = 0, const float* lam_scale = nullptr);
 // the same full-grid products in split half precision (FP16 with power-of-two
 // scaling, or BF16): fragments and scale prepared by launch_beam_prep_h16
 int beam_h16_chunks(int P);
@@ -554,6 +555,13 @@ hipError_t launch_pwls_setup(const float* h, const float* gamma, double C, doubl
                              float* gamma_pw, float* eps_pw, float* dinv, hipStream_t st);
 hipError_t launch_pwls_whiten(const double2* Li, const float2* B0, int P, float2* Lw, float2* B0w, hipStream_t st);
 hipError_t launch_pwls_scale(float* x, const float* s, int n, bool divide, hipStream_t st);
+// out = L^-1 herm(X) L^-H (colour false) or L^-H herm(X) L^-1 (colour true), FP64
+// temporary T (P x P); norm2 (optional): per row of out, its squared norm
+hipError_t launch_pwls_sandwich(const double2* Li, const float2* X, int P, bool colour, double2* T, float2* out,
+                                double* norm2, hipStream_t st);
+// xf rows (xf_kernel layout) whitened in place: rowscale[F[k]] L^-1 x_k
+hipError_t launch_pwls_xf_whiten(const double2* Li, int P, const int* Flist, int n, const float* rowscale, float* xf,
+                                 hipStream_t st);
 hipError_t launch_outer_init(OuterState* st, const SolveDecision* dec, hipStream_t s);
 // Fresh state of a batch of requests in one launch: B0 = R - diag(noise),
 // sigma = 0, every pixel at its lower bound, a fresh outer state.

@@ -24,6 +24,7 @@
 // the multiplier kernel as L^-H E L^-1 with a per-pixel factor 1 / D_i.
 #include <algorithm>
 
+#include "../../include/clsimg.h"
 #include "lsqr_cu.h"
 
 namespace clsimg {
@@ -610,6 +611,105 @@ __global__ __launch_bounds__(1024) void pwls_whiten_kernel(const double2* __rest
     }
     B0w[e] = make_float2((float)re, (float)im);
   }
+}
+
+// ---- PWLS on the host-driven loop (any P up to the Cholesky limit) ----
+// out = M herm(X) M^H with M = L^-1 (whiten) or M = L^-H (colour), in two
+// passes through an FP64 P x P temporary T: pass 1 T = M herm(X) (one
+// workgroup per row of T), pass 2 out = T M^H (one workgroup per row of out,
+// optionally that row's squared Frobenius norm in FP64).  L^-1 (Li, FP64,
+// lower triangular, row-major) supplies both factors: for the whitening
+// M[p][r] = Li[p][r] (r <= p) and M^H[r][q] = conj(Li[q][r]) (r <= q); for the
+// colouring M[p][r] = conj(Li[r][p]) (r >= p) and M^H[r][q] = Li[r][q] (r >= q).
+__global__ __launch_bounds__(256) void pwls_sandwich_left_kernel(const double2* __restrict__ Li,
+                                                                 const float2* __restrict__ X, int P, int colour,
+                                                                 double2* __restrict__ T) {
+  const int p = blockIdx.x;
+  for (int q = threadIdx.x; q < P; q += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    const int r0 = colour ? p : 0, r1 = colour ? P - 1 : p;
+    for (int r = r0; r <= r1; ++r) {
+      double2 m = colour ? Li[(size_t)r * P + p] : Li[(size_t)p * P + r];
+      if (colour) m.y = -m.y;
+      const float2 x = X[(size_t)r * P + q], y = X[(size_t)q * P + r];  // herm(X)[r][q]
+      const double br = 0.5 * ((double)x.x + y.x), bi = 0.5 * ((double)x.y - y.y);
+      re += m.x * br - m.y * bi;
+      im += m.x * bi + m.y * br;
+    }
+    T[(size_t)p * P + q] = make_double2(re, im);
+  }
+}
+
+__global__ __launch_bounds__(256) void pwls_sandwich_right_kernel(const double2* __restrict__ Li,
+                                                                  const double2* __restrict__ T, int P, int colour,
+                                                                  float2* __restrict__ out, double* __restrict__ norm2) {
+  __shared__ double part[256];
+  const int p = blockIdx.x;
+  double nn = 0.0;
+  for (int q = threadIdx.x; q < P; q += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    const int r0 = colour ? q : 0, r1 = colour ? P - 1 : q;
+    for (int r = r0; r <= r1; ++r) {
+      double2 m = colour ? Li[(size_t)r * P + q] : Li[(size_t)q * P + r];
+      if (!colour) m.y = -m.y;
+      const double2 t = T[(size_t)p * P + r];
+      re += t.x * m.x - t.y * m.y;
+      im += t.x * m.y + t.y * m.x;
+    }
+    const float2 o = make_float2((float)re, (float)im);
+    out[(size_t)p * P + q] = o;
+    nn += (double)o.x * o.x + (double)o.y * o.y;
+  }
+  if (!norm2) return;
+  part[threadIdx.x] = nn;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norm2[p] = part[0];
+}
+
+// The free set's steering rows whitened in place: x_k <- rowscale[F[k]] L^-1 x_k
+// (xf layout: 2 Pp floats per pixel, padding antennas zero); one workgroup
+// per row.
+__global__ __launch_bounds__(128) void pwls_xf_whiten_kernel(const double2* __restrict__ Li, int P, int Pp,
+                                                             const int* __restrict__ Flist, int n,
+                                                             const float* __restrict__ rowscale,
+                                                             float* __restrict__ xf) {
+  __shared__ float2 x[CLSIMG_MAX_P];
+  const int k = blockIdx.x;
+  float2* row = reinterpret_cast<float2*>(xf + (size_t)k * 2 * Pp);
+  for (int r = threadIdx.x; r < P; r += blockDim.x) x[r] = row[r];
+  __syncthreads();
+  const double sc = (double)rowscale[Flist[k]];
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int r = 0; r <= p; ++r) {
+      const double2 l = Li[(size_t)p * P + r];
+      const float2 v = x[r];
+      re += l.x * v.x - l.y * v.y;
+      im += l.x * v.y + l.y * v.x;
+    }
+    row[p] = make_float2((float)(sc * re), (float)(sc * im));
+  }
+}
+
+hipError_t launch_pwls_sandwich(const double2* Li, const float2* X, int P, bool colour, double2* T, float2* out,
+                                double* norm2, hipStream_t st) {
+  if (P < 1 || P > CLSIMG_MAX_P) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pwls_sandwich_left_kernel, dim3(P), dim3(128), 0, st, Li, X, P, colour ? 1 : 0, T);
+  hipLaunchKernelGGL(pwls_sandwich_right_kernel, dim3(P), dim3(128), 0, st, Li, (const double2*)T, P,
+                     colour ? 1 : 0, out, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pwls_xf_whiten(const double2* Li, int P, const int* Flist, int n, const float* rowscale, float* xf,
+                                 hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (P < 1 || P > CLSIMG_MAX_P) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pwls_xf_whiten_kernel, dim3(n), dim3(128), 0, st, Li, P, pad_p(P), Flist, n, rowscale, xf);
+  return hipGetLastError();
 }
 
 // x[i] *= s[i] (mul) or x[i] /= s[i]

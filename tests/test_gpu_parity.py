@@ -393,42 +393,71 @@ def test_solve_tight_bound_uses_upper_set(gpu_lib, scenes, name, host):
     assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
 
 
-@pytest.mark.parametrize("name", ["c0", "c1"])
-def test_solve_pwls_matches_oracle(gpu_lib, ctx, scenes, name):
+def _pwls_case(gpu_lib, ctx, sc, what, C=1.0, **optfields):
     # preconditioned weighted LS (eq. preWLS) with the MVDR bound and the
     # MVDR-image threshold, against the oracle's PWLS solve
-    sc = scenes[name]
-    print(f"case PWLS solve {name}", flush=True)
+    print(f"case PWLS solve {what} (P={sc.P}, Q={sc.Q}) C={C} {optfields}", flush=True)
     R = sc.R_hat32_c128
     A = oracle.steering(sc.pos, sc.lam, sc.grid)
-    gamma = oracle.upper_bound(A, R)
-    _, h = oracle.pwls_scaling(A, R)
+    gamma = oracle.upper_bound(A, R, C=C)
+    _, h = oracle.pwls_scaling(A, R, C)
     eps = oracle.pwls_threshold(h, 6.0, sc.N, sc.P)
     nd = np.asarray(sc.noise_diag, np.float32).astype(np.float64)
-    ref = oracle.solve_pwls(A, R, R - np.diag(nd), gamma, eps, atol=1e-8, btol=1e-8)
+    ref = oracle.solve_pwls(A, R, R - np.diag(nd), gamma, eps, C=C, atol=1e-8, btol=1e-8)
     opts = gpu_lib.default_options()
     opts.nsamples = sc.N
     opts.atol = opts.btol = 1e-7
     opts.cost = gpu_lib.COST_PWLS
+    opts.C = C
+    for k, v in optfields.items():
+        setattr(opts, k, v)
     sigma, state, mf, gam, stats = ctx.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts,
                                              noise_diag=_dev(sc.noise_diag, torch.float32))
     print("gpu stats", stats, "oracle outer", ref.outer_iters, "adds", ref.adds, "drops", ref.drops, flush=True)
     state, sigma = state.cpu().numpy(), sigma.cpu().numpy()
     print("state mismatches", int(np.sum(state != ref.state)), flush=True)
+    assert ref.adds > 0
     np.testing.assert_array_equal(state, ref.state)
-    _assert_close(sigma, ref.sigma, what=f"PWLS sigma {name}")
-    _assert_close(gam.cpu().numpy(), gamma, what=f"PWLS gamma {name}")
+    _assert_close(sigma, ref.sigma, what=f"PWLS sigma {what}")
+    _assert_close(gam.cpu().numpy(), gamma, what=f"PWLS gamma {what}")
     assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
+    print("oracle U", int(np.sum(ref.state == 2)), flush=True)
+    return stats, ref
 
 
-def test_pwls_without_the_device_loop_is_not_supported(gpu_lib, scenes):
-    sc = scenes["c0"]
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_solve_pwls_matches_oracle(gpu_lib, ctx, scenes, name):
+    _pwls_case(gpu_lib, ctx, scenes[name], name)
+
+
+def test_solve_pwls_on_the_host_loop_matches_oracle(gpu_lib, ctx, scenes):
+    # the host-driven loop: the whitened steering rows of the free set in the
+    # cache of the two-kernel LSQR, E coloured back for the multipliers
+    _pwls_case(gpu_lib, ctx, scenes["c0"], "c0 host loop", loop=gpu_lib.LOOP_HOST)
+
+
+def test_solve_pwls_hand_over_matches_oracle(gpu_lib, ctx, scenes):
+    # the device loop hands the PWLS solve over to the host loop part way
+    stats, _ = _pwls_case(gpu_lib, ctx, scenes["c1"], "c1 hand-over", hand_over_free=4)
+    assert stats["nF"] > 4
+
+
+@pytest.mark.parametrize("P,n,pts,C", [(72, 36, 12, 1.0), (96, 40, 12, 1.0), (96, 40, 30, 0.25)])
+def test_solve_pwls_beyond_48_antennas_matches_oracle(gpu_lib, ctx, P, n, pts, C):
+    # C = 0.25 moves pixels into U and drops them there (b whitened every step)
+    sc = synth.make_scene("c2", P=P, n=n, seed=400 + P, points=(pts, ("powerlaw", 0.5, 500.0)))
+    _, ref = _pwls_case(gpu_lib, ctx, sc, f"P={P}", C=C)
+    if C < 1.0:
+        assert int(np.sum(ref.state == 2)) > 0 and ref.drops > 0
+
+
+def test_pwls_beyond_96_antennas_is_not_supported(gpu_lib):
+    sc = synth.make_scene("c2", P=104, n=16, seed=12)
     ctx2 = gpu_lib.Context(0)
     try:
         opts = gpu_lib.default_options()
         opts.nsamples = sc.N
         opts.cost = gpu_lib.COST_PWLS
-        opts.loop = gpu_lib.LOOP_HOST
         with pytest.raises(gpu_lib.ClsimgError) as ei:
             ctx2.solve(_dev(sc.R_hat32, torch.complex64), _geo(gpu_lib, sc), opts)
         assert ei.value.status == gpu_lib.ENOTSUP

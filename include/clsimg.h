@@ -364,8 +364,9 @@ int clsimg_solve_multi(clsimg_ctx* ctx, int32_t K, const clsimg_block* blocks, c
  * (delta_l, delta_m) per pixel, zero outside F; sigma holds the powers at the
  * shifted positions.  0 <= rounds <= 16 (0: the plain subproblem, with the
  * free steering vectors formed directly in FP64 rather than from the tables).
- * P <= 48, LS cost, free sets within the one-workgroup LSQR (else
- * CLSIMG_ENOTSUP).  Other arguments as clsimg_solve (no starting image);
+ * P <= 96 and the LS cost; LSQR in one workgroup, or for free sets beyond
+ * its LDS in one cooperative kernel (CLSIMG_ENOTSUP where neither holds the
+ * free set).  Other arguments as clsimg_solve (no starting image);
  * synchronises `stream`. */
 int clsimg_solve_offgrid(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_array* array, const clsimg_grid* grid,
                          const float* noise_diag, const clsimg_opts* opts, int32_t rounds, float* sigma,

@@ -1637,6 +1637,37 @@ int solve_host_loop(SolveRun& r) {
   return CLSIMG_OK;
 }
 
+// The two-kernel LSQR over the free-set cache r.xf (P <= 96) run to the end
+// on its own: steps enqueued in growing batches with the done flag read back
+// between them; the solution left in r.x.
+int lsqr_fused_solve(SolveRun& r, const float2* bsub, int itnlim) {
+  clsimg_ctx* c = r.c;
+  const clsimg_opts* o = r.o;
+  hipStream_t st = r.st;
+  const int nF = r.nF, tw = adjoint_lsqr2_tile_width(r.MT, nF);
+  const int nalpha2 = (nF + tw - 1) / tw;
+  HIP_TRY(launch_lsqr_setup(r.S2, r.done, o->atol, o->btol, o->conlim, itnlim, st));
+  ST_TRY(correlate(c, r.g, r.P, nullptr, nullptr, 0, 0, r.u, bsub, 0.f, 1.f, nullptr, r.frag_u, r.bparts[1], nullptr,
+                   st));
+  HIP_TRY(launch_adjoint_lsqr2(r.lsqr_adj(r.done), EpiLsqrV2{r.vraw, r.v, r.bparts[1], r.nbeta, r.alpha_part, 1}, st));
+  int it = 1, batch = 4;
+  HIP_TRY(launch_lsqr_fwd(r.fwd_params(1, nalpha2), st));
+  for (;;) {
+    ST_TRY(read_back(c, c->h_status, r.done, sizeof(int), st));
+    if (*c->h_status) break;
+    if (it > itnlim + 256) return CLSIMG_EHIP;  // LSQR stops itself at itnlim
+    for (int b = 0; b < batch; ++b) {
+      HIP_TRY(launch_adjoint_lsqr2(r.lsqr_adj(r.done),
+                                   EpiLsqrV2{r.vraw, r.v, r.bparts[(it + 1) & 1], r.nfw, r.alpha_part, 0}, st));
+      ++it;
+      HIP_TRY(launch_lsqr_fwd(r.fwd_params(it, nalpha2), st));
+    }
+    batch = std::min(batch * 2, 64);
+  }
+  HIP_TRY(launch_lsqr_pick(r.Sfin, r.x1, r.x, nF, st));
+  return CLSIMG_OK;
+}
+
 // Statistics; after the host-driven loop the final residual ||B0 - Psi sigma||_F
 // is formed from the final sets (the device loop keeps that of its last
 // feasible step, which is the final image).
@@ -2025,7 +2056,9 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
   ST_TRY(check_opts(o, a->P));
   if (o->nsamples <= 0 && o->kappa_d != 0.0) return CLSIMG_EINVAL;
   const int P = a->P, Q = g->nl * g->nm, Pp = pad_p(P), MT = Pp / 8;
-  if (o->cost != CLSIMG_COST_LS || !beam_fits(P)) return CLSIMG_ENOTSUP;
+  // the shifted steering rows live in the free-set cache of the LSQR engines
+  // that read it (up to 12 row tiles, P <= 96)
+  if (o->cost != CLSIMG_COST_LS || MT > 12 || !beam_any(P)) return CLSIMG_ENOTSUP;
   c->prec = o->precision;
   DeviceGuard guard(c->device);
   hipStream_t st = (hipStream_t)stream;
@@ -2042,6 +2075,12 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
   ST_TRY(ensure(c, c->xf, (size_t)Q * 2 * Pp * sizeof(float)));
   if (!mf_out) ST_TRY(ensure(c, c->mf, (size_t)Q * sizeof(float)));
   if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
+  // the cooperative and the two-kernel LSQR (free sets beyond one workgroup)
+  const int nparts = std::max(std::max(reduce_blocks(P), lsqr_fwd_waves(P)), Q / 32 + 64);
+  ST_TRY(ensure(c, c->bpart0, (size_t)nparts * sizeof(double)));
+  ST_TRY(ensure(c, c->bpart1, (size_t)nparts * sizeof(double)));
+  ST_TRY(ensure(c, c->alpha_part, (size_t)(Q / 16 + 64) * sizeof(double)));
+  for (DevBuf* b : {&c->v, &c->w, &c->x1, &c->w1, &c->vraw}) ST_TRY(ensure(c, *b, (size_t)Q * sizeof(float)));
   ST_TRY(ensure_tables(c, a, g, st));
   float* mf = mf_out ? mf_out : P_<float>(c->mf);
   float* gamma = gamma_out ? gamma_out : P_<float>(c->gamma);  // bounds in use (free pixels shifted)
@@ -2103,6 +2142,33 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
     return launch_corr_os(cp, st);
   };
 
+  // the two-kernel LSQR's operands (its steering rows: the shifted cache)
+  SolveRun fr;
+  fr.c = c;
+  fr.g = g;
+  fr.o = o;
+  fr.st = st;
+  fr.P = P;
+  fr.Q = Q;
+  fr.MT = MT;
+  fr.nbeta = reduce_blocks(P);
+  fr.nfw = lsqr_fwd_waves(P);
+  fr.Flist = Flist;
+  fr.xf = xf;
+  fr.u = P_<float2>(c->u);
+  fr.v = P_<float>(c->v);
+  fr.w = P_<float>(c->w);
+  fr.x = x;
+  fr.x1 = P_<float>(c->x1);
+  fr.w1 = P_<float>(c->w1);
+  fr.vraw = P_<float>(c->vraw);
+  fr.frag_u = P_<float>(c->frag_u);
+  fr.alpha_part = P_<double>(c->alpha_part);
+  fr.bparts[0] = P_<double>(c->bpart0);
+  fr.bparts[1] = P_<double>(c->bpart1);
+  fr.S2 = S2;
+  fr.Sfin = Sfin;
+  fr.done = done;
   const int max_outer = o->max_outer < 0 ? 4 * Q : o->max_outer;
   int status = CLSIMG_OK;
   int outer = 0, adds = 0, drops = 0, lsqr_total = 0, itnlim_hits = 0, last_added = -1, nF = 0, nU = 0;
@@ -2121,7 +2187,11 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
       ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
       nF = c->h_dec->nF;
       nU = c->h_dec->nU;
-      if (nF > 0 && !lsqr_cu_fits(P, nF)) return CLSIMG_ENOTSUP;  // beyond the one-workgroup LSQR
+      // LSQR in one workgroup when the subproblem fits its LDS, else in one
+      // cooperative kernel, else two kernels per step
+      const bool one_cu = lsqr_cu_fits(P, nF);
+      const bool persist = !one_cu && c->coop && persist_fits(P, nF);
+      fr.nF = nF;
       // b = B0 - Psi_U gamma0_U on the grid (eq. bsubproblemLS)
       ST_TRY(correlate(c, g, P, Ulist, gamma0, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr, nullptr, st));
       flops += corr_flops(P, nU);
@@ -2129,7 +2199,7 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
       for (int t = 0; t <= rounds; ++t) {
         HIP_TRY(xf_off(nF));
         HIP_TRY(launch_lsqr_setup2(S2, done, bar, lerr, o->atol, o->btol, o->conlim, itnlim, st));
-        if (nF > 0) {
+        if (nF > 0 && one_cu) {
           LsqrCuParams lc;
           lc.P = P;
           lc.n = nF;
@@ -2143,6 +2213,30 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
           lc.conlim = o->conlim;
           lc.itnlim = itnlim;
           HIP_TRY(launch_lsqr_cu(lc, st));
+        } else if (nF > 0 && persist) {
+          LsqrPersistParams lp;
+          lp.MT = MT;
+          lp.P = P;
+          lp.n = nF;
+          lp.ntp = MT * (MT + 1) / 2;
+          lp.xf = xf;
+          lp.B = Bb;
+          lp.frag = P_<float>(c->frag_u);
+          lp.pbeta = P_<double>(c->bpart0);
+          lp.palpha = P_<double>(c->alpha_part);
+          lp.vraw = P_<float>(c->vraw);
+          lp.x_out = x;
+          lp.Sfinal = Sfin;
+          lp.done = done;
+          lp.bar = bar;
+          lp.err = lerr;
+          lp.atol = o->atol;
+          lp.btol = o->btol;
+          lp.conlim = o->conlim;
+          lp.itnlim = itnlim;
+          HIP_TRY(launch_lsqr_persist(lp, st));
+        } else if (nF > 0) {
+          ST_TRY(lsqr_fused_solve(fr, Bb, itnlim));
         }
         if (t == rounds) break;
         ST_TRY(read_back(c, c->h_lsqr, Sfin, sizeof(LsqrState), st));
@@ -2159,8 +2253,15 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
       HIP_TRY(launch_step(done, lerr, Sfin, x, x, Flist, nF, sigma, gamma, state, dec, st));
       // gradient after a feasible subproblem: E = Psi(delta)_F sigma_F - b, multipliers on the grid
       HIP_TRY(corr_xf(nF, sigma, Flist, grad_stop));
-      HIP_TRY(launch_beam_lambda(nullptr, E, P, tab, grad_stop, state, keys, nullptr, st));
-      HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
+      if (beam_fits(P)) {
+        HIP_TRY(launch_beam_lambda(nullptr, E, P, tab, grad_stop, state, keys, nullptr, st));
+        HIP_TRY(launch_argmin_final(keys, beam_grid(Q), eps, state, dec, st));
+      } else {
+        HIP_TRY(launch_beam_prep_full(E, P, P_<float>(c->frag_b), st));
+        HIP_TRY(launch_beam_big(3, P_<const float>(c->frag_b), tab, grad_stop, nullptr, nullptr, 0.f, 0, 0, 1.f, state,
+                                keys, st, Stamps{}, big_tiles(c, P)));
+        HIP_TRY(launch_argmin_final(keys, beam_big_grid(P, Q, big_tiles(c, P)), eps, state, dec, st));
+      }
       ST_TRY(read_back(c, c->h_dec, dec, sizeof(SolveDecision), st));
       const SolveDecision d = *c->h_dec;
       if (nF > 0 && !d.lsqr_done) return CLSIMG_EHIP;  // the LSQR kernel did not finish

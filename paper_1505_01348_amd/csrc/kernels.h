@@ -445,6 +445,8 @@ int lsqr_fwd_waves(int P);
 hipError_t launch_corr_os(const CorrOsParams& pr, hipStream_t st);
 hipError_t launch_xf(const Tables& tab, const int* Flist, int n, float* xf, hipStream_t st);
 hipError_t launch_lsqr_fwd(const LsqrFwdParams& pr, hipStream_t st);
+// x0 <- x1 when the finished two-kernel LSQR (state S) ended on an odd step
+hipError_t launch_lsqr_pick(const LsqrState* S, const float* x1, float* x0, int n, hipStream_t st);
 hipError_t launch_lsqr_setup(LsqrState* S0, int* done, double atol, double btol, double conlim,
                              int itnlim, hipStream_t st);
 void forward_plan(int P, int n, int* chw, int* nchunks);

@@ -296,6 +296,20 @@ hipError_t launch_lsqr_setup(LsqrState* S0, int* done, double atol, double btol,
   return hipGetLastError();
 }
 
+// the two-kernel LSQR leaves x_itn in x[itn & 1]: x0 <- x1 when itn is odd
+__global__ void lsqr_pick_kernel(const LsqrState* __restrict__ S, const float* __restrict__ x1, float* __restrict__ x0,
+                                 int n) {
+  if (!(S->itn & 1)) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x0[i] = x1[i];
+}
+
+hipError_t launch_lsqr_pick(const LsqrState* S, const float* x1, float* x0, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int g = std::min((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(lsqr_pick_kernel, dim3(g), dim3(256), 0, st, S, x1, x0, n);
+  return hipGetLastError();
+}
+
 int lsqr_fwd_waves(int P) {
   const int MT = pad_p(P) / 8;
   const int ntp = MT * (MT + 1) / 2;

@@ -54,6 +54,7 @@ struct clsimg_ctx {
   DevBuf ostate;                                                // device-resident outer loop
   DevBuf pw_h, pw_rs, pw_g, pw_eps, pw_dinv, pw_Lw, pw_B0w;      // PWLS inputs
   DevBuf pw_T, pw_Bw, pw_Eh, pw_nrm;  // PWLS on the host-driven loop: products with L^-1, whitened b and E
+  DevBuf cpart;                       // per-chunk counts of the compaction
   DevBuf batch, batch_params, batch_rinv;                       // batched solve workspace
   // autotuned 16-pixel tiles per workgroup of the GEMM-shaped beamformers, by
   // precision (FP32, FP16, BF16) and row tiles per wave; 0: the default
@@ -736,7 +737,7 @@ int clsimg_destroy(clsimg_ctx* c) {
   if (!c) return CLSIMG_EINVAL;
   DeviceGuard guard(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->ElT, &c->EmT, &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->pw_T, &c->pw_Bw, &c->pw_Eh, &c->pw_nrm, &c->batch, &c->batch_params, &c->batch_rinv, &c->part,  &c->beta_part,
+  DevBuf* bufs[] = {&c->El,   &c->Em,    &c->ElT, &c->EmT, &c->pos_d,    &c->frag_r, &c->frag_u, &c->frag_b, &c->ostate, &c->pw_h, &c->pw_rs, &c->pw_g, &c->pw_eps, &c->pw_dinv, &c->pw_Lw, &c->pw_B0w, &c->pw_T, &c->pw_Bw, &c->pw_Eh, &c->pw_nrm, &c->cpart, &c->batch, &c->batch_params, &c->batch_rinv, &c->part,  &c->beta_part,
                     &c->alpha_part, &c->keys, &c->B0, &c->Bb,   &c->u,     &c->E,
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
@@ -999,9 +1000,12 @@ namespace {
 // checking that the lists and the decision record exist at the sizes the
 // compaction writes.
 int compact(clsimg_ctx* c, const uint8_t* state, int Q, hipStream_t st) {
+  const size_t np = (size_t)compact_parts(Q) * sizeof(int);
+  if (c->cpart.bytes < np) ST_TRY(ensure(c, c->cpart, np));
   ST_TRY(need_all({{&c->Flist, (size_t)Q * sizeof(int)}, {&c->Ulist, (size_t)Q * sizeof(int)},
-                   {&c->dec, sizeof(SolveDecision)}}));
-  HIP_TRY(launch_compact(state, Q, P_<int>(c->Flist), P_<int>(c->Ulist), P_<SolveDecision>(c->dec), st));
+                   {&c->dec, sizeof(SolveDecision)}, {&c->cpart, np}}));
+  HIP_TRY(launch_compact(state, Q, P_<int>(c->Flist), P_<int>(c->Ulist), P_<SolveDecision>(c->dec),
+                         P_<int>(c->cpart), st));
   return CLSIMG_OK;
 }
 

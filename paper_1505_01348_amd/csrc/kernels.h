@@ -503,7 +503,9 @@ struct SolveDecision {
   int cand_overflow;     // refined multipliers: more candidates than the list holds
 };
 
-hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec,
+// sorted lists of F and U and their sizes (dec->nF, dec->nU); part: compact_parts(Q) ints
+int compact_parts(int Q);
+hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec, int* part,
                           hipStream_t st);
 
 // ---- device-resident outer iteration (outer.hip) ----

@@ -405,9 +405,144 @@ __global__ void init_state_kernel(const float* __restrict__ sigma0, const uint8_
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec,
+// ---- compaction over many workgroups: chunks of kCmpChunk states ----
+// compact_count_kernel: the F and U counts of each chunk (part[2b], part[2b+1]);
+// compact_write_kernel: each chunk's offsets from the counts of the chunks
+// before it, a scan inside the chunk, and its entries of the sorted lists; the
+// last chunk writes the totals.
+constexpr int kCmpThreads = 256, kCmpChunk = kCmpThreads * 16;
+
+// sixteen states from i0 (past Q: 0, the lower set), as four words
+__device__ inline uint4 cmp_load(const uint8_t* __restrict__ state, int Q, int i0, bool vec) {
+  if (vec && i0 + 16 <= Q) return *reinterpret_cast<const uint4*>(state + i0);
+  uint32_t ws[4] = {0u, 0u, 0u, 0u};
+  for (int k = 0; k < 16 && i0 + k < Q; ++k) ws[k >> 2] |= (uint32_t)state[i0 + k] << (8 * (k & 3));
+  return make_uint4(ws[0], ws[1], ws[2], ws[3]);
+}
+
+// states are 0, 1 or 2: byte b is 1 when its bit 0 is set and bit 1 clear, 2
+// when bit 1 is set and bit 0 clear (four bytes per popcount)
+__device__ inline void cmp_count(uint4 v, int& cf, int& cu) {
+  const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+  cf = 0;
+  cu = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cf += __popc(x[q] & ~(x[q] >> 1) & 0x01010101u);
+    cu += __popc((x[q] >> 1) & ~x[q] & 0x01010101u);
+  }
+}
+
+__global__ __launch_bounds__(kCmpThreads) void compact_count_kernel(const uint8_t* __restrict__ state, int Q,
+                                                                    int* __restrict__ part) {
+  __shared__ int sf[kCmpThreads / 64], su[kCmpThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool vec = (reinterpret_cast<uintptr_t>(state) & 15) == 0;
+  int cf, cu;
+  cmp_count(cmp_load(state, Q, blockIdx.x * kCmpChunk + 16 * tid, vec), cf, cu);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    cf += __shfl_xor(cf, o, 64);
+    cu += __shfl_xor(cu, o, 64);
+  }
+  if (lane == 0) {
+    sf[w] = cf;
+    su[w] = cu;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int tf = 0, tu = 0;
+#pragma unroll
+    for (int k = 0; k < kCmpThreads / 64; ++k) {
+      tf += sf[k];
+      tu += su[k];
+    }
+    part[2 * blockIdx.x] = tf;
+    part[2 * blockIdx.x + 1] = tu;
+  }
+}
+
+__global__ __launch_bounds__(kCmpThreads) void compact_write_kernel(const uint8_t* __restrict__ state, int Q,
+                                                                    const int* __restrict__ part,
+                                                                    int* __restrict__ Flist, int* __restrict__ Ulist,
+                                                                    SolveDecision* dec) {
+  constexpr int NW = kCmpThreads / 64;
+  __shared__ int wf[NW], wu[NW], base[2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, b = blockIdx.x;
+  const bool vec = (reinterpret_cast<uintptr_t>(state) & 15) == 0;
+  const int i0 = b * kCmpChunk + 16 * tid;
+  const uint4 v = cmp_load(state, Q, i0, vec);
+  if (w == 0) {  // the chunks before this one
+    int pf = 0, pu = 0;
+    for (int k = lane; k < b; k += 64) {
+      pf += part[2 * k];
+      pu += part[2 * k + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      pf += __shfl_xor(pf, o, 64);
+      pu += __shfl_xor(pu, o, 64);
+    }
+    if (lane == 0) {
+      base[0] = pf;
+      base[1] = pu;
+    }
+  }
+  int cf, cu;
+  cmp_count(v, cf, cu);
+  int sf = cf, su = cu;  // inclusive scan over the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int tf = __shfl_up(sf, o, 64), tu = __shfl_up(su, o, 64);
+    if (lane >= o) {
+      sf += tf;
+      su += tu;
+    }
+  }
+  if (lane == 63) {
+    wf[w] = sf;
+    wu[w] = su;
+  }
+  __syncthreads();
+  int pf = base[0], pu = base[1], tf = 0, tu = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    if (k < w) {
+      pf += wf[k];
+      pu += wu[k];
+    }
+    tf += wf[k];
+    tu += wu[k];
+  }
+  int of = pf + sf - cf, ou = pu + su - cu;
+  if (cf + cu > 0) {
+    const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t sv = (x[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+      if (sv == 1) Flist[of++] = i0 + k;
+      else if (sv == 2) Ulist[ou++] = i0 + k;
+    }
+  }
+  if (b == gridDim.x - 1 && tid == 0) {
+    dec->nF = base[0] + tf;
+    dec->nU = base[1] + tu;
+  }
+}
+
+int compact_parts(int Q) { return 2 * ((Q + kCmpChunk - 1) / kCmpChunk); }
+
+hipError_t launch_compact(const uint8_t* state, int Q, int* Flist, int* Ulist, SolveDecision* dec, int* part,
                           hipStream_t st) {
-  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kCtl), 0, st, state, Q, Flist, Ulist, dec);
+  if (Q <= 0) return hipErrorInvalidValue;
+  const int nb = (Q + kCmpChunk - 1) / kCmpChunk;
+  if (nb == 1) {
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kCtl), 0, st, state, Q, Flist, Ulist, dec);
+  } else {
+    hipLaunchKernelGGL(compact_count_kernel, dim3(nb), dim3(kCmpThreads), 0, st, state, Q, part);
+    hipLaunchKernelGGL(compact_write_kernel, dim3(nb), dim3(kCmpThreads), 0, st, state, Q, (const int*)part, Flist,
+                       Ulist, dec);
+  }
   return hipGetLastError();
 }
 

@@ -76,6 +76,8 @@ struct clsimg_ctx {
   double* h_mnorm = nullptr;  // pinned: the blocks' norm partials
   size_t h_mnorm_n = 0;
   DevBuf frag_h, hscale;   // half-precision fragments and their scale
+  DevBuf h1_xc;            // half-precision steering operands of every pixel tile (beam_h1_kernel)
+  int h1_xc_kind = 0;      // what h1_xc holds for the current tables: 0 nothing, 1 FP16, 2 BF16
   DevBuf mx_abs, mx_lam, mx_cand, mx_count;  // refined multipliers: |W| partials, lam~, candidates
   void* scratch = nullptr;    // this device's copy of the static workspace (allocation-free calls)
   // device time of the host-driven loop's multiplier kernel (clsimg_kernel_timing)
@@ -192,7 +194,22 @@ int ensure_tables(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, hi
   c->key.grid = *g;
   c->key.pos.assign(a->pos_xy, a->pos_xy + 2 * P);
   c->tables_valid = true;
+  c->h1_xc_kind = 0;  // formed from the previous tables
   return CLSIMG_OK;
+}
+
+// The multiplier kernel's half-precision steering operands for the current
+// tables (formed once per geometry and precision, Q x 2Pp halves), or null
+// when the context's budget has no room for them (the kernel then forms them
+// from the tables in every launch) or the tables are not the context's own.
+const void* h1_operands(clsimg_ctx* c, const Tables& tab, int P, bool bf, hipStream_t st) {
+  if (c->tab_El || c->tab_Em || !c->tables_valid) return nullptr;
+  const int kind = bf ? 2 : 1;
+  if (c->h1_xc_kind == kind) return c->h1_xc.ptr;
+  if (ensure(c, c->h1_xc, beam_h1_xcache_bytes(P, tab.Q)) != CLSIMG_OK) return nullptr;
+  if (launch_h1_xcache(tab, bf, c->h1_xc.ptr, st) != hipSuccess) return nullptr;
+  c->h1_xc_kind = kind;
+  return c->h1_xc.ptr;
 }
 
 Tables tables_of(clsimg_ctx* c, const clsimg_grid* g, int P) {
@@ -374,7 +391,7 @@ int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamK
   if (c->prec != CLSIMG_FP32) {  // split half precision, GEMM-shaped kernel for every P
     const bool bf = c->prec == CLSIMG_BF16;
     ST_TRY(ensure(c, c->frag_h, beam_h16_frag_bytes(P)));
-    ST_TRY(ensure(c, c->hscale, sizeof(float)));
+    ST_TRY(ensure(c, c->hscale, kHalfScaleFloats * sizeof(float)));
     HIP_TRY(launch_beam_prep_h16(U, P, bf, c->frag_h.ptr, P_<float>(c->hscale), st, first));
     const int k = kind == BEAM_MF ? 0 : (kind == BEAM_MVDR ? 1 : 2);
     HIP_TRY(launch_beam_h16(k, bf, c->frag_h.ptr, P_<const float>(c->hscale), tab, nullptr, out, eps, eps_scale, C,
@@ -742,7 +759,7 @@ int clsimg_destroy(clsimg_ctx* c) {
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
                     &c->dec,  &c->status, &c->lsqr2, &c->done, &c->x1, &c->w1, &c->vraw,
-                    &c->bpart0, &c->bpart1, &c->xf, &c->bar, &c->frag_h, &c->hscale,
+                    &c->bpart0, &c->bpart1, &c->xf, &c->bar, &c->frag_h, &c->hscale, &c->h1_xc,
                     &c->mx_abs, &c->mx_lam, &c->mx_cand, &c->mx_count,
                     &c->mb_tab, &c->mb_B0, &c->mb_Bb, &c->mb_u, &c->mb_E, &c->mb_frag, &c->mb_acc, &c->mb_acc2,
                     &c->mb_gpart};
@@ -913,7 +930,7 @@ int clsimg_dirty_image_noalloc(clsimg_ctx* c, const clsimg_c32* R, const clsimg_
   size_t fb = 0;
   if (precision != CLSIMG_FP32) fb = beam_h16_frag_bytes(P);
   else if (!beam_fits(P)) fb = beam_big_frag_floats(P) * sizeof(float);
-  const size_t o_fr = take(fb), o_sc = take(sizeof(float));
+  const size_t o_fr = take(fb), o_sc = take(kHalfScaleFloats * sizeof(float));
   if (off > kNoAllocBytes) return CLSIMG_ENOMEM;
   c->prec = precision;
   DeviceGuard guard(c->device);
@@ -1153,7 +1170,7 @@ int solve_setup(SolveRun& r, const clsimg_c32* R, const clsimg_array* a, const f
   r.cand_tile = adjoint_tile_width(r.MT);
   if (r.beam_half) {
     ST_TRY(ensure(c, c->frag_h, std::max(beam_h16_frag_bytes(P), beam_h1_frag_bytes(P))));
-    ST_TRY(ensure(c, c->hscale, sizeof(float)));
+    ST_TRY(ensure(c, c->hscale, kHalfScaleFloats * sizeof(float)));
     ST_TRY(ensure(c, c->mx_abs, kCandAbsParts * sizeof(double)));
     ST_TRY(ensure(c, c->mx_lam, (size_t)Q * sizeof(float)));
     ST_TRY(ensure(c, c->mx_cand, (size_t)r.cand_cap * sizeof(int)));
@@ -1195,7 +1212,7 @@ int solve_setup(SolveRun& r, const clsimg_c32* R, const clsimg_array* a, const f
   if (!gamma_out) ST_TRY(need_all({{&c->gamma, fq}}));
   if (r.beam_half)
     ST_TRY(need_all({{&c->mx_lam, fq}, {&c->mx_cand, (size_t)r.cand_cap * sizeof(int)}, {&c->mx_count, sizeof(int)},
-                     {&c->mx_abs, kCandAbsParts * sizeof(double)}, {&c->hscale, sizeof(float)}}));
+                     {&c->mx_abs, kCandAbsParts * sizeof(double)}, {&c->hscale, kHalfScaleFloats * sizeof(float)}}));
   if (r.pwls)
     ST_TRY(need_all({{&c->pw_h, fq}, {&c->pw_rs, fq}, {&c->pw_g, fq}, {&c->pw_eps, fq}, {&c->pw_dinv, fq},
                      {&c->pw_Lw, cx}, {&c->pw_B0w, cx}, {&c->pw_T, (size_t)P * P * sizeof(double2)},
@@ -1370,10 +1387,11 @@ int host_multipliers(SolveRun& r, bool fp32_only) {
   if (r.beam_half && !fp32_only) {
     const bool bf = c->prec == CLSIMG_BF16;
     int* count = P_<int>(c->mx_count);
-    HIP_TRY(launch_beam_lambda_refined(r.E, P, bf, r.tab(), r.grad_stop, r.state, c->frag_h.ptr,
+    const Tables tab = r.tab();
+    HIP_TRY(launch_beam_lambda_refined(r.E, P, bf, tab, r.grad_stop, r.state, c->frag_h.ptr,
                                        P_<float>(c->hscale), P_<double>(c->mx_abs), kCandAbsParts, r.keys,
                                        P_<float>(c->mx_lam), P_<int>(c->mx_cand), r.cand_cap, count, st,
-                                       big_tiles(c, P), r.mult_stamps));
+                                       big_tiles(c, P), r.mult_stamps, h1_operands(c, tab, P, bf, st)));
     // the candidates in FP32: Ut fragments of E from the correlation
     AdjParams ap = adj_params(c, r.g, P, r.frag_r, P_<const int>(c->mx_cand), r.cand_cap, r.grad_stop);
     ap.rows_part = P_<float>(c->part);
@@ -1817,7 +1835,7 @@ int clsimg_solve_multi(clsimg_ctx* c, int32_t K, const clsimg_block* blocks, con
   if (!gamma_out) ST_TRY(ensure(c, c->gamma, (size_t)Q * sizeof(float)));
   if (c->prec != CLSIMG_FP32) {
     ST_TRY(ensure(c, c->frag_h, beam_h16_frag_bytes(P)));
-    ST_TRY(ensure(c, c->hscale, sizeof(float)));
+    ST_TRY(ensure(c, c->hscale, kHalfScaleFloats * sizeof(float)));
   }
   if ((size_t)K * nbeta > c->h_mnorm_n) {
     HIP_TRY(hipStreamSynchronize(st));

@@ -387,8 +387,12 @@ hipError_t launch_beam_prep_full(const float2* U, int P, float* frag, hipStream_
 hipError_t launch_beam_big(int kind, const float* frag, const Tables& tab, const int* skip, float* out, float* eps,
                            float eps_scale, double C, double kb, float scale, const uint8_t* state, uint64_t* part,
                            hipStream_t st, Stamps ts = {}, int nt = 0, const float* lam_scale = nullptr);
+// the FP16 scale buffer (`scale` below): the scale, then the partial maxima it is formed from
+constexpr int kHalfScaleParts = 64;
+constexpr int kHalfScaleFloats = 1 + kHalfScaleParts;
 // the same full-grid products in split half precision (FP16 with power-of-two
-// scaling, or BF16): fragments and scale prepared by launch_beam_prep_h16
+// scaling, or BF16): fragments and scale (kHalfScaleFloats floats) prepared by
+// launch_beam_prep_h16
 int beam_h16_chunks(int P);
 size_t beam_h16_frag_bytes(int P);
 hipError_t launch_beam_prep_h16(const float2* U, int P, bool bf16, void* frag, float* scale, hipStream_t st,
@@ -404,14 +408,19 @@ hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* s
 // product of the block-triangular Ut of E (lam[] and one argmin key per
 // workgroup in keys[]), then the pixels within twice the rounding bound of
 // the approximate minimum are listed in cand[] (*count of them, possibly more
-// than cap) for an FP32 evaluation.  frag: beam_h1_frag_bytes(P); scale: one
-// float (FP16); absum: nabs doubles; keys: beam_big_grid(P, Q, nt) entries.
+// than cap) for an FP32 evaluation.  frag: beam_h1_frag_bytes(P); scale:
+// kHalfScaleFloats floats (FP16); absum: nabs doubles; keys: beam_big_grid(P, Q, nt) entries.
 size_t beam_h1_frag_bytes(int P);
 double beam_h1_delta_coef(int P, bool bf16);
+// xcache (optional): the half-precision steering operands of every pixel tile
+// (launch_h1_xcache, beam_h1_xcache_bytes(P, Q) bytes), read instead of formed
+// from the tables in every launch
 hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,
                                       const uint8_t* state, void* frag, float* scale, double* absum, int nabs,
                                       uint64_t* keys, float* lam, int* cand, int cap, int* count, hipStream_t st,
-                                      int nt, Stamps ts = {});
+                                      int nt, Stamps ts = {}, const void* xcache = nullptr);
+size_t beam_h1_xcache_bytes(int P, int Q);
+hipError_t launch_h1_xcache(const Tables& tab, bool bf16, void* xc, hipStream_t st);
 hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
                                   float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
                                   float* hscale, hipStream_t st, int nt = 0);

@@ -76,8 +76,6 @@ struct clsimg_ctx {
   double* h_mnorm = nullptr;  // pinned: the blocks' norm partials
   size_t h_mnorm_n = 0;
   DevBuf frag_h, hscale;   // half-precision fragments and their scale
-  DevBuf h1_xc;            // half-precision steering operands of every pixel tile (beam_h1_kernel)
-  int h1_xc_kind = 0;      // what h1_xc holds for the current tables: 0 nothing, 1 FP16, 2 BF16
   DevBuf mx_abs, mx_lam, mx_cand, mx_count;  // refined multipliers: |W| partials, lam~, candidates
   void* scratch = nullptr;    // this device's copy of the static workspace (allocation-free calls)
   // device time of the host-driven loop's multiplier kernel (clsimg_kernel_timing)
@@ -194,22 +192,7 @@ int ensure_tables(clsimg_ctx* c, const clsimg_array* a, const clsimg_grid* g, hi
   c->key.grid = *g;
   c->key.pos.assign(a->pos_xy, a->pos_xy + 2 * P);
   c->tables_valid = true;
-  c->h1_xc_kind = 0;  // formed from the previous tables
   return CLSIMG_OK;
-}
-
-// The multiplier kernel's half-precision steering operands for the current
-// tables (formed once per geometry and precision, Q x 2Pp halves), or null
-// when the context's budget has no room for them (the kernel then forms them
-// from the tables in every launch) or the tables are not the context's own.
-const void* h1_operands(clsimg_ctx* c, const Tables& tab, int P, bool bf, hipStream_t st) {
-  if (c->tab_El || c->tab_Em || !c->tables_valid) return nullptr;
-  const int kind = bf ? 2 : 1;
-  if (c->h1_xc_kind == kind) return c->h1_xc.ptr;
-  if (ensure(c, c->h1_xc, beam_h1_xcache_bytes(P, tab.Q)) != CLSIMG_OK) return nullptr;
-  if (launch_h1_xcache(tab, bf, c->h1_xc.ptr, st) != hipSuccess) return nullptr;
-  c->h1_xc_kind = kind;
-  return c->h1_xc.ptr;
 }
 
 Tables tables_of(clsimg_ctx* c, const clsimg_grid* g, int P) {
@@ -759,7 +742,7 @@ int clsimg_destroy(clsimg_ctx* c) {
                     &c->Rinv, &c->W,     &c->Li,     &c->Flist,  &c->Ulist, &c->v,
                     &c->w,    &c->x,     &c->eps,    &c->mf,     &c->gamma, &c->lsqr,
                     &c->dec,  &c->status, &c->lsqr2, &c->done, &c->x1, &c->w1, &c->vraw,
-                    &c->bpart0, &c->bpart1, &c->xf, &c->bar, &c->frag_h, &c->hscale, &c->h1_xc,
+                    &c->bpart0, &c->bpart1, &c->xf, &c->bar, &c->frag_h, &c->hscale,
                     &c->mx_abs, &c->mx_lam, &c->mx_cand, &c->mx_count,
                     &c->mb_tab, &c->mb_B0, &c->mb_Bb, &c->mb_u, &c->mb_E, &c->mb_frag, &c->mb_acc, &c->mb_acc2,
                     &c->mb_gpart};
@@ -1387,11 +1370,10 @@ int host_multipliers(SolveRun& r, bool fp32_only) {
   if (r.beam_half && !fp32_only) {
     const bool bf = c->prec == CLSIMG_BF16;
     int* count = P_<int>(c->mx_count);
-    const Tables tab = r.tab();
-    HIP_TRY(launch_beam_lambda_refined(r.E, P, bf, tab, r.grad_stop, r.state, c->frag_h.ptr,
+    HIP_TRY(launch_beam_lambda_refined(r.E, P, bf, r.tab(), r.grad_stop, r.state, c->frag_h.ptr,
                                        P_<float>(c->hscale), P_<double>(c->mx_abs), kCandAbsParts, r.keys,
                                        P_<float>(c->mx_lam), P_<int>(c->mx_cand), r.cand_cap, count, st,
-                                       big_tiles(c, P), r.mult_stamps, h1_operands(c, tab, P, bf, st)));
+                                       big_tiles(c, P), r.mult_stamps));
     // the candidates in FP32: Ut fragments of E from the correlation
     AdjParams ap = adj_params(c, r.g, P, r.frag_r, P_<const int>(c->mx_cand), r.cand_cap, r.grad_stop);
     ap.rows_part = P_<float>(c->part);

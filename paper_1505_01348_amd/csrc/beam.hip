@@ -932,10 +932,10 @@ struct BeamLambdaApprox {
 // its MFMAs of chunk c, in a fixed order, so the waits count exactly), and
 // the column dot takes the same rounded steering components back from LDS:
 // lam~ = x~^T W~ x~, every operand rounded once.
-template <int RPW, bool BF, bool XC, class Epi>
+template <int RPW, bool BF, class Epi>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void beam_h1_kernel(
     const typename Half<BF>::V* __restrict__ frag, int MT, int KC, const float* __restrict__ scale, float sB,
-    Tables tab, const typename Half<BF>::V* __restrict__ xc, const int* skip, Epi epi) {
+    Tables tab, const int* skip, Epi epi) {
   typedef typename Half<BF>::V V;
   typedef typename Half<BF>::T T;
   typedef T V4 __attribute__((ext_vector_type(4)));
@@ -966,24 +966,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
   for (int i = 0; i < RPW; ++i) a[i] = frag[(size_t)mrow[i] * KC * 64 + lane];
   epi.init();
   for (int blk = blockIdx.x; blk * NT < ntiles; blk += gridDim.x) {
-    if (XC) {  // the tile's operands from the cache (h1_xcache_kernel), XR chunks per round
-      constexpr int XR = 4;
-      const V* xw = xc + (size_t)(blk * NT + w) * KC * 64 + lane;
-      for (int c0 = 0; c0 < cend; c0 += XR) {
-        V xv[XR];
-#pragma unroll
-        for (int k = 0; k < XR; ++k)
-          if (c0 + k < cend) xv[k] = xw[(c0 + k) * 64];
-#pragma unroll
-        for (int k = 0; k < XR; ++k)
-          if (c0 + k < cend) bsh[c0 + k][w][lane] = xv[k];
-      }
-    } else if (row_blocks) {
+    if (row_blocks) {
       const int im = (16 * blk * NT) / nl;
       for (int k = threadIdx.x; k < 16 * cend; k += blockDim.x) emsh[k] = tab.Em[(size_t)min(k, Pp - 1) * nm + im];
       __syncthreads();
     }
-    if (!XC) {
+    {
       const int pw = min(16 * (blk * NT + w) + c16, Q - 1);
       const int imw = pw / nl;
       const float2* elw = tab.El + (pw - imw * nl);
@@ -1067,37 +1055,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     __syncthreads();
   }
   epi.finish(blockIdx.x);
-}
-
-// The operands of beam_h1_kernel for every pixel tile, formed from the tables
-// once per geometry and precision: entry ((tile KC + c) 64 + lane) holds what
-// the kernel would place in bsh[c][.][lane] for that tile (antennas 16 c +
-// 4 g + u, u = 0 .. 3, of pixel 16 tile + c16, scaled by sB; pixels past Q
-// repeat the last one).  Q x 2Pp halves, read once per launch instead of
-// formed again from the tables.
-template <bool BF>
-__global__ __launch_bounds__(256) void h1_xcache_kernel(Tables tab, int KC, int ntiles, float sB,
-                                                        typename Half<BF>::V* __restrict__ xc) {
-  typedef typename Half<BF>::V V;
-  typedef typename Half<BF>::T T;
-  const int Q = tab.Q, nl = tab.nl, nm = tab.nm, Pp = tab.Pp;
-  const size_t total = (size_t)ntiles * KC * 64;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const int lane = (int)(e & 63), c16 = lane & 15, g = lane >> 4;
-    const size_t tc = e >> 6;
-    const int c = (int)(tc % KC), tile = (int)(tc / KC);
-    const int pw = min(16 * tile + c16, Q - 1);
-    const int im = pw / nl, il = pw - im * nl;
-    V bh;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ant = min(16 * c + 4 * g + u, Pp - 1);
-      const float2 x = cmul(tab.El[(size_t)ant * nl + il], tab.Em[(size_t)ant * nm + im]);
-      bh[2 * u] = (T)(x.x * sB);
-      bh[2 * u + 1] = (T)(x.y * sB);
-    }
-    xc[e] = bh;
-  }
 }
 
 // Candidates of the FP32 refinement: every workgroup reduces the argmin keys
@@ -1340,22 +1297,6 @@ static float h1_sB(int Pp, bool bf16) {
   return bf16 ? 1.f : ldexpf(1.f, ex - 1);
 }
 
-size_t beam_h1_xcache_bytes(int P, int Q) {
-  const int ntiles = ((Q + 15) / 16 + 3) & ~3;  // whole blocks of four tiles
-  return (size_t)ntiles * beam_h16_chunks(P) * 64 * 16;
-}
-
-hipError_t launch_h1_xcache(const Tables& tab, bool bf16, void* xc, hipStream_t st) {
-  const int KC = beam_h16_chunks(tab.Pp), ntiles = ((tab.Q + 15) / 16 + 3) & ~3;
-  const float sB = h1_sB(tab.Pp, bf16);
-  const dim3 g(4096), b(256);
-  if (bf16)
-    hipLaunchKernelGGL(h1_xcache_kernel<true>, g, b, 0, st, tab, KC, ntiles, sB, static_cast<v8b*>(xc));
-  else
-    hipLaunchKernelGGL(h1_xcache_kernel<false>, g, b, 0, st, tab, KC, ntiles, sB, static_cast<v8h*>(xc));
-  return hipGetLastError();
-}
-
 size_t beam_h1_frag_bytes(int P) {
   const int MT = pad_p(P) / 8;
   return (size_t)4 * big_rpw(MT) * beam_h16_chunks(P) * 64 * 16;
@@ -1375,7 +1316,7 @@ double beam_h1_delta_coef(int P, bool bf16) {
 hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,
                                       const uint8_t* state, void* frag, float* scale, double* absum, int nabs,
                                       uint64_t* keys, float* lam, int* cand, int cap, int* count, hipStream_t st,
-                                      int nt, Stamps ts, const void* xcache) {
+                                      int nt, Stamps ts) {
   const int MT = pad_p(P) / 8, KC = beam_h16_chunks(P), rpw = big_rpw(MT);
   if (!bf16) launch_half_scale(E, P * P, scale, st);
   if (bf16)
@@ -1392,19 +1333,14 @@ hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const T
   const dim3 g(beam_big_grid(tab.Pp, tab.Q, nt)), b(256);
   const BeamLambdaApprox epi{state, keys, lam, 0};
   const float* sc = bf16 ? nullptr : scale;
-#define H1_LAUNCH(R, BFV, XCV, VT)                                                                              \
-  hipExtLaunchKernelGGL((beam_h1_kernel<R, BFV, XCV, BeamLambdaApprox>), g, b, 0, st, ts.start, ts.stop, 0,     \
-                        static_cast<const VT*>(frag), MT, KC, sc, sB, tab, static_cast<const VT*>(xcache), skip,  \
-                        epi)
 #define H1_RPW(R)                                                                                              \
   case R:                                                                                                      \
-    if (bf16) {                                                                                                \
-      if (xcache) H1_LAUNCH(R, true, true, v8b);                                                               \
-      else H1_LAUNCH(R, true, false, v8b);                                                                     \
-    } else {                                                                                                   \
-      if (xcache) H1_LAUNCH(R, false, true, v8h);                                                              \
-      else H1_LAUNCH(R, false, false, v8h);                                                                    \
-    }                                                                                                          \
+    if (bf16)                                                                                                  \
+      hipExtLaunchKernelGGL((beam_h1_kernel<R, true, BeamLambdaApprox>), g, b, 0, st, ts.start, ts.stop, 0,     \
+                            static_cast<const v8b*>(frag), MT, KC, sc, sB, tab, skip, epi);                    \
+    else                                                                                                       \
+      hipExtLaunchKernelGGL((beam_h1_kernel<R, false, BeamLambdaApprox>), g, b, 0, st, ts.start, ts.stop, 0,    \
+                            static_cast<const v8h*>(frag), MT, KC, sc, sB, tab, skip, epi);                    \
     break;
   switch (rpw) {
     H1_RPW(1)
@@ -1419,7 +1355,6 @@ hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const T
     default: return hipErrorInvalidValue;
   }
 #undef H1_RPW
-#undef H1_LAUNCH
   hipLaunchKernelGGL(beam_cand_kernel, dim3(256), dim3(256), 0, st, (const uint64_t*)keys, (int)g.x,
                      (const double*)absum, nabs, beam_h1_delta_coef(P, bf16), (const float*)lam, tab.Q, skip, cand,
                      cap, count);

@@ -412,15 +412,10 @@ hipError_t launch_beam_h16(int kind, bool bf16, const void* frag, const float* s
 // kHalfScaleFloats floats (FP16); absum: nabs doubles; keys: beam_big_grid(P, Q, nt) entries.
 size_t beam_h1_frag_bytes(int P);
 double beam_h1_delta_coef(int P, bool bf16);
-// xcache (optional): the half-precision steering operands of every pixel tile
-// (launch_h1_xcache, beam_h1_xcache_bytes(P, Q) bytes), read instead of formed
-// from the tables in every launch
 hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const Tables& tab, const int* skip,
                                       const uint8_t* state, void* frag, float* scale, double* absum, int nabs,
                                       uint64_t* keys, float* lam, int* cand, int cap, int* count, hipStream_t st,
-                                      int nt, Stamps ts = {}, const void* xcache = nullptr);
-size_t beam_h1_xcache_bytes(int P, int Q);
-hipError_t launch_h1_xcache(const Tables& tab, bool bf16, void* xc, hipStream_t st);
+                                      int nt, Stamps ts = {});
 hipError_t launch_beam_accumulate(const float2* U, int P, const Tables& tab, const int* skip, float* sum,
                                   float* sumsq, float scale, int first, int prec, float* frag_big, void* frag_half,
                                   float* hscale, hipStream_t st, int nt = 0);

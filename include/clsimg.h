@@ -301,7 +301,7 @@ typedef struct {
 
 /* Batched solve (Sec. III, Table I, with LSQR of Sec. IV-A) of n independent
  * imaging problems -- frequency channels, time slices, observations -- with
- * the same antenna count P <= 48 and the same options.  Every outer step of
+ * the same antenna count P and the same options.  For P <= 48 every outer step of
  * all requests runs in one kernel launch (one workgroup per request) and the
  * Lagrange multipliers of all requests in another, so the requests share the
  * GPU instead of queueing; each request's result is identical to what
@@ -310,11 +310,15 @@ typedef struct {
  * FP32, the set-up of all requests (R^-1, steering tables, initial state,
  * dirty images and bounds) also runs as a few batched launches.  When every
  * request has the same array and grid, they all read one copy of the
- * steering tables.  Returns CLSIMG_OK when every request ended with
- * CLSIMG_OK, its first negative code if a request failed, CLSIMG_ENOTSUP if a
- * free set outgrew one workgroup (no host fallback in a batch), else the
- * largest warning code; per-request codes are in reqs[i].stats.status.
- * `reqs` is host memory (n entries); n >= 1. */
+ * steering tables.  A request whose free set outgrows one workgroup (or
+ * passes hand_over_free) is then solved again alone, as clsimg_solve does
+ * (the device loop hands it to the host-driven loop at the same step).
+ * Beyond 48 antennas the requests are solved one after another on the
+ * host-driven loop.  Either way each result is that of the request's solve
+ * alone.  Returns CLSIMG_OK when every request ended with CLSIMG_OK, its
+ * first negative code if a request failed, else the largest warning code;
+ * per-request codes are in reqs[i].stats.status.  `reqs` is host memory
+ * (n entries); n >= 1. */
 int clsimg_solve_batch(clsimg_ctx* ctx, int32_t n, clsimg_request* reqs, const clsimg_opts* opts, void* stream);
 
 /* ---- K covariance blocks over one pixel grid ---------------------------

@@ -2377,8 +2377,53 @@ int batch_round_graph(clsimg_ctx* c, const OuterParams* dp, const BeamLamItem* d
 
 extern "C" {
 
+namespace {
+// one request solved alone, as clsimg_solve does it; the worse of two codes
+int solve_request_alone(clsimg_ctx* c, clsimg_request& q, const clsimg_opts* o, void* stream) {
+  return clsimg_solve(c, q.R, &q.array, &q.grid, q.noise_diag, o, nullptr, nullptr, q.sigma, q.state, q.mf, q.gamma,
+                      &q.stats, stream);
+}
+int worse_status(int worst, int status) {
+  if (status < 0) return worst < 0 ? worst : status;
+  return (worst >= 0 && status > worst) ? status : worst;
+}
+int solve_batch_device(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const clsimg_opts* o, void* stream);
+}  // namespace
+
 int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const clsimg_opts* o, void* stream) {
   if (!c || !reqs || n < 1) return CLSIMG_EINVAL;
+  for (int r = 0; r < n; ++r) memset(&reqs[r].stats, 0, sizeof(clsimg_stats));
+  const int P = reqs[0].array.P;
+  ST_TRY(check_opts(o, P));
+  for (int r = 0; r < n; ++r) {
+    if (!reqs[r].R || !reqs[r].sigma || !reqs[r].state || reqs[r].array.P != P) return CLSIMG_EINVAL;
+    ST_TRY(check_geometry(&reqs[r].array, &reqs[r].grid));
+  }
+  if (!request_on_device(P)) {
+    // beyond the device-resident loop: the requests one after another on the
+    // host-driven loop, each exactly its solve alone
+    int worst = CLSIMG_OK;
+    for (int r = 0; r < n; ++r) worst = worse_status(worst, solve_request_alone(c, reqs[r], o, stream));
+    return worst;
+  }
+  const int st = solve_batch_device(c, n, reqs, o, stream);
+  int handed = 0;
+  for (int r = 0; r < n; ++r) handed += reqs[r].stats.status == CLSIMG_ENOTSUP;
+  if (st < 0 && !(st == CLSIMG_ENOTSUP && handed)) return st;
+  // a request whose free set outgrew the device loop (or passed hand_over_free)
+  // is solved again alone: the device loop hands it over to the host loop at
+  // the same step
+  int worst = CLSIMG_OK;
+  for (int r = 0; r < n; ++r) {
+    const int status = reqs[r].stats.status == CLSIMG_ENOTSUP ? solve_request_alone(c, reqs[r], o, stream)
+                                                               : reqs[r].stats.status;
+    worst = worse_status(worst, status);
+  }
+  return worst;
+}
+
+namespace {
+int solve_batch_device(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const clsimg_opts* o, void* stream) {
   for (int r = 0; r < n; ++r) memset(&reqs[r].stats, 0, sizeof(clsimg_stats));
   const int P = reqs[0].array.P;
   ST_TRY(check_opts(o, P));
@@ -2516,12 +2561,9 @@ int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
   }
   const OuterState* hs = reinterpret_cast<const OuterState*>(c->h_batch);
   int worst = CLSIMG_OK;
-  for (int r = 0; r < n; ++r) {
-    const int status = request_finish(reqs[r], o, slice(r), L, hs[r], st);
-    if (status < 0) worst = (worst < 0) ? worst : status;
-    else if (worst >= 0 && status > worst) worst = status;
-  }
+  for (int r = 0; r < n; ++r) worst = worse_status(worst, request_finish(reqs[r], o, slice(r), L, hs[r], st));
   return worst;
 }
+}  // namespace
 
 }  // extern "C"

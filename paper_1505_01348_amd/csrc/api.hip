@@ -1523,8 +1523,13 @@ int host_subproblem(SolveRun& r) {
         } else {
           ST_TRY(correlate(c, r.g, P, r.Flist, r.v, 0, nF, r.u, r.u, 1.f, 0.f, r.ls, r.frag_u, r.beta_part,
                            r.lsqr_stop, st));
-          HIP_TRY(launch_adjoint_lsqr(r.lsqr_adj_rows(r.lsqr_stop), r.v, r.beta_part, r.nbeta, r.alpha_part, 0, st));
-          HIP_TRY(launch_lsqr_update(r.ls, r.beta_part, r.nbeta, r.alpha_part, nalpha, r.v, r.w, r.x, nF, st));
+          const AdjParams ap = r.lsqr_adj_rows(r.lsqr_stop);
+          if (adjoint_lsqr_fuses(ap)) {  // the whole list in one epilogue workgroup: the step there too
+            HIP_TRY(launch_adjoint_lsqr_step(ap, r.v, r.beta_part, r.nbeta, r.alpha_part, r.ls, r.w, r.x, st));
+          } else {
+            HIP_TRY(launch_adjoint_lsqr(ap, r.v, r.beta_part, r.nbeta, r.alpha_part, 0, st));
+            HIP_TRY(launch_lsqr_update(r.ls, r.beta_part, r.nbeta, r.alpha_part, nalpha, r.v, r.w, r.x, nF, st));
+          }
         }
       }
     }

@@ -180,40 +180,121 @@ struct EpiLambda {
   }
 };
 
+// One LSQR step's rotation and scalars (Sec. IV-A, Paige and Saunders'
+// recurrences) from beta^2 and alpha^2; sc = {1 / alpha (v scale), 1 / rho,
+// phi, theta / rho, c}.  One thread.
+__device__ inline void lsqr_scalars(LsqrState* s, double b2, double a2, double* sc) {
+  const double beta = sqrt(b2);
+  const double alpha = sqrt(a2);
+  const double alpha_old = s->alpha;
+  s->anorm2 += alpha_old * alpha_old + beta * beta;
+  const double rho = hypot(s->rhobar, beta);
+  const double c = s->rhobar / rho, sn = beta / rho;
+  const double theta = sn * alpha;
+  s->rhobar = -c * alpha;
+  const double phi = c * s->phibar;
+  s->phibar = sn * s->phibar;
+  s->alpha = alpha;
+  s->beta = beta;
+  sc[0] = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  sc[1] = 1.0 / rho;
+  sc[2] = phi;
+  sc[3] = theta / rho;
+  sc[4] = c;
+}
+
+// The step's estimates and stopping rule from ||d_k||^2 and ||x||^2.  One thread.
+__device__ inline void lsqr_close(LsqrState* s, double dd, double xx, double c) {
+  s->ddnorm += dd;
+  s->rnorm = s->phibar;
+  s->arnorm = s->phibar * s->alpha * fabs(c);
+  s->anorm = sqrt(s->anorm2);
+  s->acond = s->anorm * sqrt(s->ddnorm);
+  s->xnorm = sqrt(xx);
+  s->itn += 1;
+  int istop = 0;
+  if (s->rnorm <= s->btol * s->bnorm + s->atol * s->anorm * s->xnorm) istop = 1;
+  else if (s->arnorm <= s->atol * s->anorm * s->rnorm) istop = 2;
+  else if (s->acond >= s->conlim) istop = 3;
+  else if (s->alpha == 0.0 || s->beta == 0.0) istop = 4;
+  else if (s->itn >= s->itnlim) istop = 7;
+  s->istop = istop;
+  s->done = istop != 0;
+}
+
+// The vector part of a step for entry k: v scaled, x += phi w / rho,
+// w = v - (theta / rho) w; adds |d_k|^2 and x_k^2 to dd and xx.
+__device__ inline void lsqr_vectors(const double* sc, float vraw, float* v, float* w, float* x, int k, double& dd,
+                                    double& xx) {
+  const double vk = (double)vraw * sc[0];
+  const double wk = (double)w[k];
+  const double dk = wk * sc[1];
+  dd += dk * dk;
+  const float xk = (float)((double)x[k] + sc[2] * dk);
+  x[k] = xk;
+  xx += (double)xk * xk;
+  const float vf = (float)vk;
+  v[k] = vf;
+  w[k] = (float)((double)vf - sc[3] * wk);
+}
+
 // LSQR: v <- Psi_F^H u / beta - beta v   (or Psi_F^H u / beta at the start),
-// with u held unnormalised; per-tile partial sums of v^2.
+// with u held unnormalised; per-tile partial sums of v^2.  With ls set (the
+// whole list in one workgroup, not the first step) the workgroup also takes
+// the step of lsqr_update_kernel: the same sums in the same order, so the
+// iterates are those of the separate launch.
 struct EpiLsqrV {
   float* v;
   const double* beta_part;
   int nbeta;
   double* alpha_part;
   int first;
+  LsqrState* ls = nullptr;
+  float* w = nullptr;
+  float* x = nullptr;
   using Ctx = NoCtx;
   using Pre = NoCtx;
   __device__ Ctx init() const { return {}; }
   __device__ Pre prefetch(int, bool) const { return {}; }
   __device__ void operator()(int tile, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
     __shared__ double sh[8];
-    __shared__ double sbeta;
+    __shared__ double sbeta, sb2;
+    __shared__ double sc[5];
     if (threadIdx.x < 64) {  // wave 0, the same order as the LSQR scalar kernels
       const double s = wave_sum_parts(beta_part, nbeta);
-      if (threadIdx.x == 0) sbeta = sqrt(s);
+      if (threadIdx.x == 0) {
+        sb2 = s;
+        sbeta = sqrt(s);
+      }
     }
     __syncthreads();
     const double beta = sbeta;
     double vr2 = 0.0;
+    float vf = 0.f;
     if (ok) {
       double vr = beta > 0.0 ? (double)g / beta : 0.0;
       if (!first) vr -= beta * (double)v[col];
-      const float vf = (float)vr;
+      vf = (float)vr;
       v[col] = vf;
       vr2 = (double)vf * vf;
     }
     const double tot = block_sum_d(vr2, sh);
-    if (threadIdx.x == 0) alpha_part[tile] = tot;
+    if (!ls) {
+      if (threadIdx.x == 0) alpha_part[tile] = tot;
+      return;
+    }
+    if (threadIdx.x == 0) {
+      alpha_part[tile] = tot;
+      lsqr_scalars(ls, sb2, tot, sc);
+    }
+    __syncthreads();
+    double dd = 0.0, xx = 0.0;
+    if (ok) lsqr_vectors(sc, vf, v, w, x, col, dd, xx);
+    dd = block_sum_d(dd, sh);
+    xx = block_sum_d(xx, sh);
+    if (threadIdx.x == 0) lsqr_close(ls, dd, xx, sc[4]);
   }
 };
-
 
 // LSQR (fused form): v_raw <- Psi_F^H u / beta - beta v_it (or Psi_F^H u / beta
 // at the start); beta from the per-wave partials of the correlation kernel.
@@ -307,6 +388,11 @@ hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint
                                  hipStream_t st);
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
                                double* alpha_part, int init, hipStream_t st);
+// The step of lsqr_update_kernel folded into the adjoint's epilogue: the list
+// must fit one epilogue workgroup (adjoint_lsqr_fuses); v, w, x as there
+bool adjoint_lsqr_fuses(const AdjParams& pr);
+hipError_t launch_adjoint_lsqr_step(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
+                                    double* alpha_part, LsqrState* ls, float* w, float* x, hipStream_t st);
 hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipStream_t st);
 // the column dots of each of pr.nblk blocks apart: out[k * stride + col], one block per workgroup row
 hipError_t launch_adjoint_store_blocks(const AdjParams& pr, float* out, size_t stride, hipStream_t st);

@@ -243,11 +243,20 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams pr, Epi epi
 // reduction's fragments: real row 2p + s is component s of antenna p.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, float* __restrict__ part) {
-  if (pr.stop_flag && *pr.stop_flag) return;
   __shared__ float gs[4][NT * 16];
   const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
   const int MT = pr.MT, KS = pr.KS, stride = pr.n;  // partials: one row of pr.n per (slice, row group)
-  const int n = pr.n_dev ? min(*pr.n_dev, pr.n) : pr.n;
+  // the flags, the list length and the first group's pixels in one round trip
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
+  const int ndev = pr.n_dev ? *pr.n_dev : pr.n;
+  int pix0[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = max(0, min(16 * (blockIdx.x * NT + t) + c16, pr.n - 1));
+    pix0[t] = (pr.idx && pr.n > 0) ? pr.idx[col] : col;
+  }
+  if (stop) return;
+  const int n = min(ndev, pr.n);
   const int mt = 4 * blockIdx.y + w;
   const bool live_row = mt < MT;
   const int mtc = live_row ? mt : MT - 1;  // loads stay in bounds; the dot leaves it out
@@ -263,10 +272,18 @@ __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, fl
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int col = 16 * (xb * NT + t) + c16;
-      int pix = col < n ? (pr.idx ? pr.idx[col] : col) : 0;
+      int pix = col < n ? (xb == (int)blockIdx.x ? pix0[t] : (pr.idx ? pr.idx[col] : col)) : 0;
       if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;
       im[t] = pix / tab.nl;
       il[t] = pix - im[t] * tab.nl;
+    }
+    // the column dot's steering entries (antennas 8mt + 2q, 8mt + 2q + 1), loaded with the K loop's
+    float2 ad0[NT], ad1[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int pa = 8 * mtc + 2 * q;
+      ad0[t] = tab.a(pa, il[t], im[t]);
+      ad1[t] = tab.a(pa + 1, il[t], im[t]);
     }
     // B operand of chunk kc: real row 4kc + q = component q & 1 of antenna 2kc + (q >> 1)
     const float2* elp[NT];
@@ -279,31 +296,50 @@ __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, fl
     v4f acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int kf = k0 < k1 ? k0 : 0;
-    float fa = fw[(size_t)kf * 64];
-    float2 te[NT], tm[NT];
+    constexpr int KALL = 24;  // one tile and a short slice: every load of the slice issued at once
+    if (NT == 1 && k1 - k0 <= KALL) {
+      float fa[KALL];
+      float2 te[KALL], tm[KALL];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      te[t] = elp[t][kf * sl];
-      tm[t] = emp[t][kf * sm];
-    }
-    for (int kc = k0; kc < k1; ++kc) {
-      const float a = fa;
-      float b[NT];
+      for (int j = 0; j < KALL; ++j)
+        if (k0 + j < k1) {
+          fa[j] = fw[(size_t)(k0 + j) * 64];
+          te[j] = elp[0][(k0 + j) * sl];
+          tm[j] = emp[0][(k0 + j) * sm];
+        }
+#pragma unroll
+      for (int j = 0; j < KALL; ++j)
+        if (k0 + j < k1) {
+          const float2 x = cmul(te[j], tm[j]);
+          acc[0] = mfma16x16x4(fa[j], (q & 1) ? x.y : x.x, acc[0]);
+        }
+    } else {
+      const int kf = k0 < k1 ? k0 : 0;
+      float fa = fw[(size_t)kf * 64];
+      float2 te[NT], tm[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const float2 x = cmul(te[t], tm[t]);
-        b[t] = (q & 1) ? x.y : x.x;
+        te[t] = elp[t][kf * sl];
+        tm[t] = emp[t][kf * sm];
       }
-      const int kn = kc + 1 < k1 ? kc + 1 : kc;
-      fa = fw[(size_t)kn * 64];
+      for (int kc = k0; kc < k1; ++kc) {
+        const float a = fa;
+        float b[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        te[t] = elp[t][kn * sl];
-        tm[t] = emp[t][kn * sm];
+        for (int t = 0; t < NT; ++t) {
+          const float2 x = cmul(te[t], tm[t]);
+          b[t] = (q & 1) ? x.y : x.x;
+        }
+        const int kn = kc + 1 < k1 ? kc + 1 : kc;
+        fa = fw[(size_t)kn * 64];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          te[t] = elp[t][kn * sl];
+          tm[t] = emp[t][kn * sm];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(a, b[t], acc[t]);
       }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(a, b[t], acc[t]);
     }
     // accumulator element r of lane (c16, q): real row 16mt + 4q + r, i.e.
     // antenna 8mt + 2q + (r >> 1), component r & 1
@@ -312,8 +348,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_rows_kernel(AdjParams pr, fl
     for (int t = 0; t < NT; ++t) {
       gp[t] = 0.f;
       if (live_row) {
-        const float2 a0 = tab.a(8 * mt + 2 * q, il[t], im[t]);
-        const float2 a1 = tab.a(8 * mt + 2 * q + 1, il[t], im[t]);
+        const float2 a0 = ad0[t], a1 = ad1[t];
         gp[t] = acc[t][0] * a0.x + acc[t][1] * a0.y + acc[t][2] * a1.x + acc[t][3] * a1.y;
       }
       gp[t] += __shfl_xor(gp[t], 16, 64);
@@ -347,7 +382,16 @@ __global__ __launch_bounds__(64) void adjoint_rows_finish_kernel(AdjParams pr, c
   float g = 0.f;
   int pix = 0;
   if (ok) {
-    for (int y = 0; y < ngroups; ++y) g += part[(size_t)y * pr.n + col];
+    // eight partials loaded at a time, added in group order
+    int y = 0;
+    for (; y + 8 <= ngroups; y += 8) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = part[(size_t)(y + k) * pr.n + col];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) g += v[k];
+    }
+    for (; y < ngroups; ++y) g += part[(size_t)y * pr.n + col];
     pix = pr.idx ? pr.idx[col] : col;
     if ((unsigned)pix >= (unsigned)pr.tab.Q) {  // invalid pixel index: NaN output
       pix = 0;
@@ -1214,10 +1258,11 @@ hipError_t launch_adjoint_epi(const AdjParams& pr, const Epi& epi, hipStream_t s
   }
   const int ngroups = (pr.MT + 3) / 4;
   // a list built on the device (usually short): one tile per workgroup, at
-  // most 64 workgroups along the list, the most K slices
+  // most 16 workgroups along the list (striding over longer lists), the most
+  // K slices
   const int nt = pr.n_dev ? 1 : (pr.n <= 16 ? 1 : (pr.n <= 32 ? 2 : 4));
   const int xt0 = (pr.n + 16 * nt - 1) / (16 * nt);
-  const int xt = pr.n_dev ? std::min(xt0, 64) : xt0;
+  const int xt = pr.n_dev ? std::min(xt0, 16) : xt0;
   // K slices: about 256 workgroups in all, at least 16 chunks per slice
   int ksl = pr.n_dev ? 8 : (256 + xt * ngroups - 1) / (xt * ngroups);
   ksl = std::max(1, std::min(ksl, std::min(8, pr.KS / 16)));
@@ -1299,6 +1344,20 @@ hipError_t launch_adjoint_lambda(const AdjParams& pr, const uint8_t* state, uint
 hipError_t launch_adjoint_lsqr(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
                                double* alpha_part, int init, hipStream_t st) {
   return launch_adjoint_epi(pr, EpiLsqrV{v, beta_part, nbeta, alpha_part, init}, st);
+}
+// both adjoint paths put the epilogue of tiles of adjoint_tile_width(MT)
+// pixels in one workgroup each
+bool adjoint_lsqr_fuses(const AdjParams& pr) {
+  return !pr.n_dev && !pr.blk_grid && pr.nblk == 1 && pr.n >= 1 && pr.n <= adjoint_tile_width(pr.MT);
+}
+hipError_t launch_adjoint_lsqr_step(const AdjParams& pr, float* v, const double* beta_part, int nbeta,
+                                    double* alpha_part, LsqrState* ls, float* w, float* x, hipStream_t st) {
+  if (!adjoint_lsqr_fuses(pr)) return hipErrorInvalidValue;
+  EpiLsqrV e{v, beta_part, nbeta, alpha_part, 0};
+  e.ls = ls;
+  e.w = w;
+  e.x = x;
+  return launch_adjoint_epi(pr, e, st);
 }
 hipError_t launch_adjoint_store_blocks(const AdjParams& pr, float* out, size_t stride, hipStream_t st) {
   AdjParams p = pr;

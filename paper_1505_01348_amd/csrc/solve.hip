@@ -168,60 +168,13 @@ __global__ __launch_bounds__(kCtl) void lsqr_update_kernel(LsqrState* s, const d
     b2 = wave_sum_parts(beta_part, nbeta);
     a2 = wave_sum_parts(alpha_part, nalpha);
   }
-  if (threadIdx.x == 0) {
-    const double beta = sqrt(b2);
-    const double alpha = sqrt(a2);
-    const double alpha_old = s->alpha;
-    s->anorm2 += alpha_old * alpha_old + beta * beta;
-    const double rho = hypot(s->rhobar, beta);
-    const double c = s->rhobar / rho, sn = beta / rho;
-    const double theta = sn * alpha;
-    s->rhobar = -c * alpha;
-    const double phi = c * s->phibar;
-    s->phibar = sn * s->phibar;
-    s->alpha = alpha;
-    s->beta = beta;
-    sc[0] = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v scale
-    sc[1] = 1.0 / rho;                         // dk = w / rho
-    sc[2] = phi;                               // x += phi dk
-    sc[3] = theta / rho;                       // w = v - (theta/rho) w
-    sc[4] = c;
-  }
+  if (threadIdx.x == 0) lsqr_scalars(s, b2, a2, sc);
   __syncthreads();
-  const double iv = sc[0], ir = sc[1], phi = sc[2], tr = sc[3];
   double dd = 0.0, xx = 0.0;
-  for (int k = threadIdx.x; k < n; k += kCtl) {
-    const double vk = (double)v[k] * iv;
-    const double wk = (double)w[k];
-    const double dk = wk * ir;
-    dd += dk * dk;
-    const float xk = (float)((double)x[k] + phi * dk);
-    x[k] = xk;
-    xx += (double)xk * xk;
-    const float vf = (float)vk;
-    v[k] = vf;
-    w[k] = (float)((double)vf - tr * wk);
-  }
+  for (int k = threadIdx.x; k < n; k += kCtl) lsqr_vectors(sc, v[k], v, w, x, k, dd, xx);
   dd = block_sum_d(dd, red_d);
   xx = block_sum_d(xx, red_x);
-  if (threadIdx.x == 0) {
-    s->ddnorm += dd;
-    const double c = sc[4];
-    s->rnorm = s->phibar;
-    s->arnorm = s->phibar * s->alpha * fabs(c);
-    s->anorm = sqrt(s->anorm2);
-    s->acond = s->anorm * sqrt(s->ddnorm);
-    s->xnorm = sqrt(xx);
-    s->itn += 1;
-    int istop = 0;
-    if (s->rnorm <= s->btol * s->bnorm + s->atol * s->anorm * s->xnorm) istop = 1;
-    else if (s->arnorm <= s->atol * s->anorm * s->rnorm) istop = 2;
-    else if (s->acond >= s->conlim) istop = 3;
-    else if (s->alpha == 0.0 || s->beta == 0.0) istop = 4;
-    else if (s->itn >= s->itnlim) istop = 7;
-    s->istop = istop;
-    s->done = istop != 0;
-  }
+  if (threadIdx.x == 0) lsqr_close(s, dd, xx, sc[4]);
 }
 
 // ---------------------------------------------------------------------------

@@ -271,9 +271,10 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
   int chw = 16, nchunks = 0;
   forward_plan(P, n, &chw, &nchunks);
   const int MT = pad_p(P) / 8;
-  if ((size_t)nchunks * forward_part_floats(P) > c->part.bytes / sizeof(float)) return CLSIMG_EINVAL;
+  const bool small = corr_small_fits(n, 1);  // a short list: one launch straight into the output
+  if (!small && (size_t)nchunks * forward_part_floats(P) > c->part.bytes / sizeof(float)) return CLSIMG_EINVAL;
+  FwdParams f;
   if (n > 0) {
-    FwdParams f;
     f.tab = tables_of(c, g, P);
     f.MT = MT;
     f.idx = idx;
@@ -283,7 +284,7 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
     f.chw = chw;
     f.part = P_<float>(c->part);
     f.stop_flag = stop;
-    HIP_TRY(launch_forward(f, st));
+    if (!small) HIP_TRY(launch_forward(f, st));
   }
   RedParams r;
   r.part = P_<const float>(c->part);
@@ -298,7 +299,8 @@ int correlate(clsimg_ctx* c, const clsimg_grid* g, int P, const int* idx, const 
   r.frag = frag;
   r.norm_part = norm_part;
   r.stop_flag = stop;
-  HIP_TRY(launch_reduce(r, st));
+  if (small) HIP_TRY(launch_corr_small(f, r, st));
+  else HIP_TRY(launch_reduce(r, st));
   return CLSIMG_OK;
 }
 

@@ -545,6 +545,10 @@ size_t forward_part_floats(int P);   // floats of one chunk's partials
 hipError_t launch_forward(const FwdParams& pr, hipStream_t st);
 int reduce_blocks(int P);
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st);
+// a short list (corr_small_fits) in one launch: the output of launch_forward
+// followed by launch_reduce, without the partial tiles (f.part unused)
+bool corr_small_fits(int n, int nblk);
+hipError_t launch_corr_small(const FwdParams& f, const RedParams& pr, hipStream_t st);
 // W: chol_work_elems(P) FP64 complex entries (unused for P <= kCholLdsMaxP)
 size_t chol_work_elems(int P);
 hipError_t launch_chol_inverse(const float2* R, int P, double2* W, double2* Li, float2* Rinv,

@@ -656,51 +656,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 // common.h) and the workgroup's sum |out|^2 in norm_part[blockIdx.x].  out may
 // alias B.  Partials are read at the block pair and tile of the correlation.
 constexpr int kRedGroups = 4;  // thread groups summing interleaved chunks
-__global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) {
-  __shared__ double sh[4 * kRedGroups];
-  __shared__ float2 gsum[kRedGroups - 1][256];
-  if (pr.stop_flag && *pr.stop_flag) return;
-  {  // covariance block blockIdx.y
-    const size_t kb = blockIdx.y;
-    pr.part += kb * pr.part_stride;
-    pr.out += kb * pr.out_stride;
-    if (pr.B) pr.B += kb * pr.B_stride;
-    if (pr.frag) pr.frag += kb * pr.frag_stride;
-    if (pr.norm_part) pr.norm_part += kb * pr.norm_stride;
-  }
-  const int P = pr.P, Pp = pad_p(P), BT = corr_bt(P), npairs = corr_pairs(P);
-  int bm = 0, bn = blockIdx.x;  // tile pair (bm >= bn)
-  while (bn > bm) {
-    bn -= bm + 1;
-    ++bm;
-  }
-  const int BM = bm / BT, BN = bn / BT;
-  const int pair = BM * (BM + 1) / 2 + BN, tile = (bm - BT * BM) * BT + (bn - BT * BN);
-  const int t = threadIdx.x & 255, grp = threadIdx.x >> 8, lane = t >> 2, r = t & 3;
-  const int row = 4 * (lane >> 4) + r, col = lane & 15;
+// The output of one tile pair from its sum y = Y_pq (writer threads only):
+// out = cK Y + cB B on the tile's lower part and mirrored, the fragments of
+// out, and the workgroup's share of |out|^2 (every thread of the workgroup
+// calls it: the norm is a block sum).
+template <int NW>
+__device__ __forceinline__ void red_store(const RedParams& pr, int bm, int bn, int row, int col, bool writer,
+                                          float yr, float yi, double (&sh)[NW]) {
+  const int P = pr.P, Pp = pad_p(P);
   const int p = 16 * bm + row, qq = 16 * bn + col;
-  // group g sums chunks g, g + G, ...; the group sums are added in group order
-  float yr = 0.f, yi = 0.f;
-  for (int c = grp; c < pr.nchunks; c += kRedGroups) {
-    const float* src = pr.part + ((size_t)c * npairs + pair) * (size_t)(BT * BT * 512) + (size_t)tile * 512;
-    yr += src[t];
-    yi += src[256 + t];
-  }
-  if (grp > 0) gsum[grp - 1][t] = make_float2(yr, yi);
-  __syncthreads();
-  if (grp == 0) {
-#pragma unroll
-    for (int g = 0; g < kRedGroups - 1; ++g) {
-      yr += gsum[g][t].x;
-      yi += gsum[g][t].y;
-    }
-  }
   float cB = pr.cB;
   if (pr.lsqr) cB = (float)(-pr.lsqr->alpha / pr.lsqr->beta);
-  // group 0 writes; the diagonal tile: its lower triangle, mirrored
-  const bool lower = grp == 0 && (bm != bn || row >= col);
+  // the diagonal tile: its lower triangle, mirrored
+  const bool lower = writer && (bm != bn || row >= col);
   double nrm = 0.0;
-  const int KS = pad_p(P) / 2;
+  const int KS = Pp / 2;
   auto put = [&](int a, int b, float2 y) {  // out[a][b] from Y_ab = y
     float2 o = make_float2(0.f, 0.f);
     if (a < P && b < P) {
@@ -732,6 +702,96 @@ __global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) 
     const double tot = block_sum_d(nrm, sh);
     if (threadIdx.x == 0) pr.norm_part[blockIdx.x] = tot;
   }
+}
+
+__device__ __forceinline__ void red_pair(int b, int& bm, int& bn) {  // tile pair b, bm >= bn
+  bm = 0;
+  bn = b;
+  while (bn > bm) {
+    bn -= bm + 1;
+    ++bm;
+  }
+}
+
+__global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) {
+  __shared__ double sh[4 * kRedGroups];
+  __shared__ float2 gsum[kRedGroups - 1][256];
+  if (pr.stop_flag && *pr.stop_flag) return;
+  {  // covariance block blockIdx.y
+    const size_t kb = blockIdx.y;
+    pr.part += kb * pr.part_stride;
+    pr.out += kb * pr.out_stride;
+    if (pr.B) pr.B += kb * pr.B_stride;
+    if (pr.frag) pr.frag += kb * pr.frag_stride;
+    if (pr.norm_part) pr.norm_part += kb * pr.norm_stride;
+  }
+  const int P = pr.P, BT = corr_bt(P), npairs = corr_pairs(P);
+  int bm, bn;  // tile pair (bm >= bn)
+  red_pair(blockIdx.x, bm, bn);
+  const int BM = bm / BT, BN = bn / BT;
+  const int pair = BM * (BM + 1) / 2 + BN, tile = (bm - BT * BM) * BT + (bn - BT * BN);
+  const int t = threadIdx.x & 255, grp = threadIdx.x >> 8, lane = t >> 2, r = t & 3;
+  const int row = 4 * (lane >> 4) + r, col = lane & 15;
+  // group g sums chunks g, g + G, ...; the group sums are added in group order
+  float yr = 0.f, yi = 0.f;
+  for (int c = grp; c < pr.nchunks; c += kRedGroups) {
+    const float* src = pr.part + ((size_t)c * npairs + pair) * (size_t)(BT * BT * 512) + (size_t)tile * 512;
+    yr += src[t];
+    yi += src[256 + t];
+  }
+  if (grp > 0) gsum[grp - 1][t] = make_float2(yr, yi);
+  __syncthreads();
+  if (grp == 0) {
+#pragma unroll
+    for (int g = 0; g < kRedGroups - 1; ++g) {
+      yr += gsum[g][t].x;
+      yi += gsum[g][t].y;
+    }
+  }
+  // group 0 writes
+  red_store(pr, bm, bn, row, col, grp == 0, yr, yi, sh);
+}
+
+// The correlation of a short list (n <= kCorrSmall pixels) straight into the
+// output: one workgroup per 16 x 16 tile pair (the tiles of reduce_kernel,
+// the same output, fragments and norm partials), the list's steering entries
+// at the pair's 16 + 16 antennas and its weights staged in LDS, then
+// Y_pq = sum_k v_k a_k[p] conj(a_k[q]) by one thread per entry.  No partial
+// tiles and no second launch.
+constexpr int kCorrSmall = 32;
+__global__ __launch_bounds__(256) void corr_small_kernel(FwdParams f, RedParams pr) {
+  __shared__ float2 sa[kCorrSmall][32];
+  __shared__ float sv[kCorrSmall];
+  __shared__ double sh[4];
+  if (pr.stop_flag && *pr.stop_flag) return;
+  const Tables& tab = f.tab;
+  const int Pp = pad_p(pr.P), n = f.n;
+  int bm, bn;
+  red_pair(blockIdx.x, bm, bn);
+  const int t = threadIdx.x, lane = t >> 2, r = t & 3;
+  const int row = 4 * (lane >> 4) + r, col = lane & 15;
+  for (int e = t; e < n * 32; e += blockDim.x) {
+    const int k = e >> 5, j = e & 31;
+    int pix = f.idx ? f.idx[k] : k;
+    if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;  // an invalid index reads in bounds
+    const int ant = min(j < 16 ? 16 * bm + j : 16 * bn + j - 16, Pp - 1);
+    const int im = pix / tab.nl;
+    sa[k][j] = tab.a(ant, pix - im * tab.nl, im);
+  }
+  for (int k = t; k < n; k += blockDim.x) {
+    int pix = f.idx ? f.idx[k] : k;
+    if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;
+    sv[k] = f.gather ? f.vals[pix] : f.vals[k];
+  }
+  __syncthreads();
+  float yr = 0.f, yi = 0.f;
+  for (int k = 0; k < n; ++k) {
+    const float2 a = sa[k][row], b = sa[k][16 + col];
+    const float v = sv[k];
+    yr += v * (a.x * b.x + a.y * b.y);
+    yi += v * (a.y * b.x - a.x * b.y);
+  }
+  red_store(pr, bm, bn, row, col, true, yr, yi, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1422,6 +1482,14 @@ int reduce_blocks(int P) {
 
 hipError_t launch_reduce(const RedParams& pr, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(reduce_blocks(pr.P), pr.nblk), dim3(256 * kRedGroups), 0, st, pr);
+  return hipGetLastError();
+}
+
+bool corr_small_fits(int n, int nblk) { return n >= 1 && n <= kCorrSmall && nblk == 1; }
+
+hipError_t launch_corr_small(const FwdParams& f, const RedParams& pr, hipStream_t st) {
+  if (!corr_small_fits(f.n, pr.nblk) || f.nblk != 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(corr_small_kernel, dim3(reduce_blocks(pr.P)), dim3(256), 0, st, f, pr);
   return hipGetLastError();
 }
 

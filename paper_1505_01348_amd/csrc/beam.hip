@@ -1070,20 +1070,43 @@ __global__ __launch_bounds__(256) void beam_cand_kernel(const uint64_t* __restri
   __shared__ uint64_t shk[4];
   __shared__ double shs[4];
   if (skip && *skip) return;
+  // this thread's first four multipliers, the keys and the partials, all
+  // requested before the reductions
+  constexpr int L4 = 4;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  float l4[L4];
+#pragma unroll
+  for (int u = 0; u < L4; ++u) l4[u] = i0 + u * stride < Q ? lam[i0 + u * stride] : 0.f;
   uint64_t m = ~0ull;
-  for (int i = threadIdx.x; i < nkeys; i += blockDim.x) m = keys[i] < m ? keys[i] : m;
-  m = block_min_u64(m, shk);
+  int i = threadIdx.x;
+  for (; i + 3 * (int)blockDim.x < nkeys; i += 4 * blockDim.x) {
+    uint64_t k4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k4[u] = keys[i + u * blockDim.x];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m = k4[u] < m ? k4[u] : m;
+  }
+  for (; i < nkeys; i += blockDim.x) m = keys[i] < m ? keys[i] : m;
   double sa = 0.0;
-  for (int i = threadIdx.x; i < nabs; i += blockDim.x) sa += absum[i];
+  for (int j = threadIdx.x; j < nabs; j += blockDim.x) sa += absum[j];
+  m = block_min_u64(m, shk);
   const double S = block_sum_d(sa, shs);
   if (m == ~0ull) return;  // no active pixel
   const double lmin = (double)from_ordered_bits((uint32_t)(m >> 32));
   const double thr = lmin + 2.0 * coef * S;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Q; i += gridDim.x * blockDim.x) {
-    const float l = lam[i];
+#pragma unroll
+  for (int u = 0; u < L4; ++u) {
+    const int ii = i0 + u * stride;
+    if (ii < Q && (double)l4[u] <= thr) {
+      const int k = atomicAdd(count, 1);
+      if (k < cap) cand[k] = ii;
+    }
+  }
+  for (int ii = i0 + L4 * stride; ii < Q; ii += stride) {
+    const float l = lam[ii];
     if ((double)l <= thr) {
       const int k = atomicAdd(count, 1);
-      if (k < cap) cand[k] = i;
+      if (k < cap) cand[k] = ii;
     }
   }
 }

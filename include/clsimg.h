@@ -301,7 +301,8 @@ typedef struct {
 
 /* Batched solve (Sec. III, Table I, with LSQR of Sec. IV-A) of n independent
  * imaging problems -- frequency channels, time slices, observations -- with
- * the same antenna count P and the same options.  For P <= 48 every outer step of
+ * the same options.  Requests with different antenna counts run as one batch
+ * per count, in order of first appearance.  For P <= 48 every outer step of
  * all requests runs in one kernel launch (one workgroup per request) and the
  * Lagrange multipliers of all requests in another, so the requests share the
  * GPU instead of queueing; each request's result is identical to what

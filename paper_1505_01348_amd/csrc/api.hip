@@ -2400,11 +2400,32 @@ int solve_batch_device(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const cls
 int clsimg_solve_batch(clsimg_ctx* c, int32_t n, clsimg_request* reqs, const clsimg_opts* o, void* stream) {
   if (!c || !reqs || n < 1) return CLSIMG_EINVAL;
   for (int r = 0; r < n; ++r) memset(&reqs[r].stats, 0, sizeof(clsimg_stats));
-  const int P = reqs[0].array.P;
-  ST_TRY(check_opts(o, P));
   for (int r = 0; r < n; ++r) {
-    if (!reqs[r].R || !reqs[r].sigma || !reqs[r].state || reqs[r].array.P != P) return CLSIMG_EINVAL;
+    if (!reqs[r].R || !reqs[r].sigma || !reqs[r].state) return CLSIMG_EINVAL;
+    ST_TRY(check_opts(o, reqs[r].array.P));
     ST_TRY(check_geometry(&reqs[r].array, &reqs[r].grid));
+  }
+  const int P = reqs[0].array.P;
+  bool one_p = true;
+  for (int r = 1; r < n; ++r) one_p = one_p && reqs[r].array.P == P;
+  if (!one_p) {
+    // several array sizes: one batch per size, in order of first appearance
+    std::vector<int> sizes;
+    for (int r = 0; r < n; ++r)
+      if (std::find(sizes.begin(), sizes.end(), reqs[r].array.P) == sizes.end()) sizes.push_back(reqs[r].array.P);
+    int worst = CLSIMG_OK;
+    std::vector<clsimg_request> group;
+    for (int sz : sizes) {
+      group.clear();
+      for (int r = 0; r < n; ++r)
+        if (reqs[r].array.P == sz) group.push_back(reqs[r]);
+      const int st = clsimg_solve_batch(c, (int32_t)group.size(), group.data(), o, stream);
+      for (int r = 0, k = 0; r < n; ++r)
+        if (reqs[r].array.P == sz) reqs[r].stats = group[k++].stats;
+      if (st < 0 && st != CLSIMG_ENOTSUP && st != CLSIMG_ENOTPD) return st;  // a call-level failure
+      worst = worse_status(worst, st);
+    }
+    return worst;
   }
   if (!request_on_device(P)) {
     // beyond the device-resident loop: the requests one after another on the

@@ -282,12 +282,13 @@ def test_solve_c0_identical_sets(gpu_lib, ctx, scenes, noise):
     assert abs(stats["rel_residual"] - ref.rel_residual) <= 1e-5 * max(ref.rel_residual, 1e-12) + 1e-7
 
 
-@pytest.mark.parametrize("host", [False, True])
-def test_solve_ragged_grid(gpu_lib, ctx, host):
+@pytest.mark.parametrize("host,n", [(False, 37), (True, 37), (True, 101)])
+def test_solve_ragged_grid(gpu_lib, ctx, host, n):
     # 40 antennas (5 row tiles, padding antennas inside the last tile pair),
     # 37 x 37 pixels: the last 16-pixel tile holds 9 pixels; device loop and
-    # host loop
-    sc = synth.make_scene("c1", P=40, n=37, seed=41, points=(30, ("loguniform", 0.5, 50.0)), blobs=(1, 5.0, 5.0))
+    # host loop.  101 x 101 pixels: the host loop's set compaction over two
+    # whole chunks of 4096 states and a ragged third
+    sc = synth.make_scene("c1", P=40, n=n, seed=41, points=(30, ("loguniform", 0.5, 50.0)), blobs=(1, 5.0, 5.0))
     print(f"case solve ragged P={sc.P} Q={sc.Q} host={host}", flush=True)
     ref, mf_ref, gamma_ref = _oracle_solve(sc)
     sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc, loop=gpu_lib.LOOP_HOST if host else 0)

@@ -391,8 +391,8 @@ int clsimg_solve_offgrid(clsimg_ctx* ctx, const clsimg_c32* R, const clsimg_arra
  * device, overlapping with the batch.  Every request's outputs equal those of
  * clsimg_solve for it alone.  The server owns one context and stream for the
  * batch, one per worker, the arena and the worker threads; submit / poll / query / destroy must be called from
- * one host thread.  Per-request PWLS (CLSIMG_COST_PWLS) requires P <= 48
- * (otherwise the request completes at once with status CLSIMG_ENOTSUP). */
+ * one host thread.  With CLSIMG_COST_PWLS the workers' solves take P <= 96
+ * (beyond, the request completes with status CLSIMG_ENOTSUP, as clsimg_solve). */
 typedef struct clsimg_server clsimg_server;
 
 typedef struct {

@@ -278,7 +278,7 @@ int run_round(clsimg_server* s) {
       keep.push_back(sl);
       continue;
     }
-    if (S.fallback && s->opts.cost != CLSIMG_COST_PWLS) {
+    if (S.fallback) {
       // beyond the on-chip capacity: the worker solves it as clsimg_solve would
       s->arena.give(sl.off, sl.bytes);
       to_worker(s, sl.job);
@@ -396,11 +396,7 @@ int clsimg_server_submit(clsimg_server* s, clsimg_request* q, int64_t* ticket) {
   const bool device = request_on_device(a->P) && beam_grid(Q) <= kKeysPerReq &&
                       layout_for(s, *q).bytes <= s->arena.bytes;
   if (!device) {
-    if (pwls) {  // PWLS exists on the device loop only
-      finish_now(s, j, CLSIMG_ENOTSUP);
-    } else {
-      to_worker(s, j);
-    }
+    to_worker(s, j);  // clsimg_solve on a worker (PWLS up to 96 antennas, else CLSIMG_ENOTSUP)
   } else {
     s->pending.push_back(j);
   }

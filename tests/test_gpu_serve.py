@@ -124,10 +124,13 @@ def test_admission_waits_for_arena_space(gpu_lib):
 
 
 def test_pwls_requests_equal_their_solves_alone(gpu_lib):
+    # device slots for 24 and 48 antennas, a worker for the 96-antenna request
     scenes = _mixed_scenes(with_large=False)[:4]
+    scenes.insert(2, synth.make_scene("c2", n=24, seed=779, points=(8, ("powerlaw", 0.5, 500.0))))
     print("case server: PWLS cost", flush=True)
     opts = _opts(gpu_lib, cost=1)
-    served, _ = _serve(gpu_lib, scenes, opts, max_slots=4)
+    served, info = _serve(gpu_lib, scenes, opts, max_slots=4, workers=1)
+    assert info["admitted"] == len(scenes) - 1
     alone = _alone(gpu_lib, scenes, opts)
     for i in range(len(scenes)):
         _same(alone[i], served[i], i)

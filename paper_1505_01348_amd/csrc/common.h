@@ -161,6 +161,28 @@ __device__ inline double block_sum_d(double v, double (&sh)[NW]) {
   for (int i = 0; i < nw; ++i) s += sh[i];
   return s;
 }
+// Two sums at once through one pair of barriers (NS = 2 slots per wave).
+template <int NS>
+__device__ inline void block_sum_d2(double& a, double& b, double (&sh)[NS]) {
+  constexpr int NW = NS / 2;
+  a = wave_sum_d(a);
+  b = wave_sum_d(b);
+  const int w = threadIdx.x >> 6;
+  const int nw = min((int)(blockDim.x >> 6), NW);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0 && w < NW) {
+    sh[w] = a;
+    sh[NW + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    sa += sh[i];
+    sb += sh[NW + i];
+  }
+  a = sa;
+  b = sb;
+}
 template <int NW>
 __device__ inline uint64_t block_min_u64(uint64_t v, uint64_t (&sh)[NW]) {
   v = wave_min_u64(v);

@@ -312,8 +312,9 @@ struct EpiLsqrV2 {
     float v;
   };
   // beta_{it+1} from the correlation's per-wave partials, once per block
+  // (LDS slots for up to 16 waves: also run by the 12-wave list kernel)
   __device__ Ctx init() const {
-    __shared__ double sh[4];
+    __shared__ double sh[16];
     double b2 = 0.0;
     for (int i = threadIdx.x; i < nbeta; i += blockDim.x) b2 += beta_part[i];
     return {sqrt(block_sum_d(b2, sh))};
@@ -321,7 +322,7 @@ struct EpiLsqrV2 {
   __device__ Pre prefetch(int col, bool ok) const { return {(ok && !first) ? vnorm[col] : 0.f}; }
   __device__ void operator()(int tile, int col, int, float g, bool ok, const Ctx& cx,
                              const Pre& pf) const {
-    __shared__ double sh2[4];
+    __shared__ double sh2[16];
     const double beta = cx.beta;
     double vr2 = 0.0;
     if (ok) {

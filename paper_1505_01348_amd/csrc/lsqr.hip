@@ -18,19 +18,15 @@
 // w_j in w[j & 1], the state after step j in S[(j + 1) & 1].
 //
 // The correlation is output-stationary: one wave owns one 16 x 16 tile
-// (mt <= nt) of G = X_F diag(v) X_F^T, the workgroup stages the real-embedded
-// steering vectors of a chunk of free pixels in LDS, and the Hermitian mirror
-// of each off-diagonal tile is written by the same wave.  No partial sums, no
-// reduction kernel.  The steering vectors of the free set are generated once
+// (mt <= nt) of G = X_F diag(v) X_F^T, loads its two 16-row slices of the
+// real-embedded steering vectors and the weights straight into registers
+// (64 pixels at a time, the next 64 in flight while the current ones
+// multiply), and writes the Hermitian mirror of an off-diagonal tile itself.
+// No LDS, no partial sums, no reduction kernel.  The steering vectors of the free set are generated once
 // per subproblem (xf_kernel, 2Pp x |F| floats) and read by every LSQR step.
 #include "os_tiles.h"
 
 namespace clsimg {
-
-constexpr int kXs = 24576;  // LDS floats of staged steering entries (96 KiB)
-
-__host__ __device__ inline int os_row_stride(int Pp) { return 2 * Pp + 16; }
-__host__ __device__ inline int os_chunk(int Pp) { return (kXs / os_row_stride(Pp)) & ~15; }
 
 // X_F[k][2p + s] = Re/Im a_{Flist[k]}[p]  (pixel-major, 2Pp floats per pixel)
 __global__ void xf_kernel(Tables tab, const int* __restrict__ Flist, int n, float* __restrict__ xf) {
@@ -42,46 +38,61 @@ __global__ void xf_kernel(Tables tab, const int* __restrict__ Flist, int n, floa
   }
 }
 
-// Stage a chunk of X_F rows and weights in LDS and accumulate the tile.
-__device__ inline v4f os_accumulate(const float* __restrict__ xf, int n, int Pp, const float* vals,
-                                    const int* gidx, double scale, bool active, int mt, int nt,
-                                    float* xs, float* vs) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int c16 = lane & 15, q = lane >> 4;
-  const int RS = os_row_stride(Pp), CH = os_chunk(Pp);
-  const int r4 = Pp / 2;  // float4s per pixel row
+// Operands of one wave's tile for 16 k steps (64 pixels) straight from X_F:
+// at step s lane (c16, q) takes pixel k0 + 4 s + q, rows 16 mt + c16 and
+// 16 nt + c16 of its real-embedded steering vector, and its weight (zero
+// past the list; the pixel index is clamped into it, so every load stays in
+// X_F).  n >= 1.
+constexpr int kOsSteps = 16;
+
+struct OsOps {
+  float a[kOsSteps], b[kOsSteps], v[kOsSteps];
+};
+
+__device__ inline void os_load(const float* __restrict__ xf, int n, int Pp, const float* __restrict__ vals,
+                               const int* __restrict__ gidx, int k0, int mt, int nt, OsOps& o) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, q = lane >> 4;
+  // the gathered weights' indices first: a wait for them then leaves the
+  // operand loads issued after them in flight
+  int wi[kOsSteps];
+#pragma unroll
+  for (int s = 0; s < kOsSteps; ++s) wi[s] = min(k0 + 4 * s + q, n - 1);
+  if (gidx) {
+#pragma unroll
+    for (int s = 0; s < kOsSteps; ++s) wi[s] = gidx[wi[s]];
+  }
+#pragma unroll
+  for (int s = 0; s < kOsSteps; ++s) {
+    const float* row = xf + (size_t)min(k0 + 4 * s + q, n - 1) * 2 * Pp;
+    o.a[s] = row[16 * mt + c16];
+    o.b[s] = row[16 * nt + c16];
+  }
+#pragma unroll
+  for (int s = 0; s < kOsSteps; ++s) {
+    const float w = vals[wi[s]];
+    o.v[s] = k0 + 4 * s + q < n ? w : 0.f;
+  }
+}
+
+__device__ inline void os_mma(const OsOps& o, v4f (&acc)[4]) {
+#pragma unroll
+  for (int s = 0; s < kOsSteps; ++s) acc[s & 3] = mfma16x16x4(o.a[s] * o.v[s], o.b[s], acc[s & 3]);
+}
+
+// The tile sum over the whole list, the operands of the next 64 pixels
+// loaded while the current ones multiply; `o` holds the first 64 (loaded by
+// the caller, so that their round trip overlaps the caller's other work).
+__device__ inline v4f os_accumulate(const float* __restrict__ xf, int n, int Pp, const float* __restrict__ vals,
+                                    const int* __restrict__ gidx, int mt, int nt, OsOps& o) {
   v4f acc[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int c0 = 0; c0 < n; c0 += CH) {
-    const int cn = min(CH, n - c0);
-    const int cn16 = (cn + 15) & ~15;
-    __syncthreads();
-    for (int e = tid; e < cn16 * r4; e += kThreads) {
-      const int k = e / r4, j = e - k * r4;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (k < cn) v = *reinterpret_cast<const float4*>(xf + (size_t)(c0 + k) * 2 * Pp + 4 * j);
-      *reinterpret_cast<float4*>(xs + k * RS + 4 * j) = v;
-    }
-    for (int k = tid; k < cn16; k += kThreads) {
-      float wv = 0.f;
-      if (k < cn) wv = (float)((double)(gidx ? vals[gidx[c0 + k]] : vals[c0 + k]) * scale);
-      vs[k] = wv;
-    }
-    __syncthreads();
-    if (active) {
-      for (int kk = 0; kk < cn16; kk += 16) {
-        float a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = kk + 4 * u + q;
-          a[u] = xs[k * RS + 16 * mt + c16] * vs[k];
-          b[u] = xs[k * RS + 16 * nt + c16];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = mfma16x16x4(a[u], b[u], acc[u]);
-      }
-    }
+  for (int k0 = 0; k0 < n; k0 += 4 * kOsSteps) {
+    const bool more = k0 + 4 * kOsSteps < n;
+    OsOps nx;
+    if (more) os_load(xf, n, Pp, vals, gidx, k0 + 4 * kOsSteps, mt, nt, nx);
+    os_mma(o, acc);
+    if (more) o = nx;
   }
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
@@ -98,9 +109,7 @@ __device__ inline double os_write(v4f acc, const OsSlots& sl, const float2* Bold
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
-  __shared__ float xs[kXs];
-  __shared__ float vs[kXs / 16];
-  __shared__ double red_a[4], red_b[4], red_d[4], red_x[4];
+  __shared__ double red_ab[8], red_dx[8];
   __shared__ double sc[8];
   __shared__ LsqrState sS;
   __shared__ int s_done;
@@ -138,11 +147,14 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
       xp0 = x_prev[tid];
     }
   }
+  // the tile's operands for the first 64 free pixels (v_raw unscaled: the
+  // sum is scaled by 1 / alpha at the end)
+  OsOps ops;
+  if (active && n > 0) os_load(pr.xf, n, Pp, pr.vraw, nullptr, 0, mt, nt, ops);
   if (was_done) return;  // uniform: a finished solve
 
   // ---- finish LSQR step it-1 (every workgroup, identical arithmetic) ----
-  a2 = block_sum_d(a2, red_a);
-  b2 = block_sum_d(b2, red_b);
+  block_sum_d2(a2, b2, red_ab);
   if (tid == 0) {
     const double alpha = sqrt(a2), beta = sqrt(b2);
     sc[0] = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v = v_raw / alpha
@@ -183,8 +195,7 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
       }
     }
   }
-  dd = block_sum_d(dd, red_d);
-  xx = block_sum_d(xx, red_x);
+  block_sum_d2(dd, xx, red_dx);
   if (tid == 0) {
     LsqrState S = sS;  // tolerances and limits travel with the state
     const double alpha = sqrt(a2), beta = sqrt(b2);
@@ -239,8 +250,9 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
   }
 
   // ---- u_{it+1} = Psi_F v_it - (alpha/beta) u_it ----
-  const v4f acc = os_accumulate(pr.xf, n, Pp, pr.vraw, nullptr, iv, active, mt, nt, xs, vs);
-  double nrm = os_write(acc, sl, uold, P, Pp, 1.f, (float)sc[7], pr.u, pr.frag);
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+  if (active) acc = os_accumulate(pr.xf, n, Pp, pr.vraw, nullptr, mt, nt, ops);
+  double nrm = os_write(acc, sl, uold, P, Pp, (float)iv, (float)sc[7], pr.u, pr.frag);
   nrm = wave_sum_d(nrm);
   if (lane == 0) pr.beta_out[tp] = nrm;
 }
@@ -248,8 +260,6 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
 // Plain output-stationary correlation over the free set:
 //   out = cK * sum_k vals[gidx ? gidx[k] : k] a_k a_k^H + cB * B,  Ut fragments of out.
 __global__ __launch_bounds__(kThreads) void corr_os_kernel(CorrOsParams pr) {
-  __shared__ float xs[kXs];
-  __shared__ float vs[kXs / 16];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c16 = lane & 15, q = lane >> 4;
   const int MT = pr.MT, P = pr.P, Pp = 8 * MT;
@@ -261,8 +271,12 @@ __global__ __launch_bounds__(kThreads) void corr_os_kernel(CorrOsParams pr) {
   const int stop = pr.stop_flag ? *pr.stop_flag : 0;
   float2 bold[4];
   os_prefetch(sl, pr.B, P, bold);
+  OsOps ops;
+  const bool go = active && pr.n > 0;
+  if (go) os_load(pr.xf, pr.n, Pp, pr.vals, pr.gidx, 0, mt, nt, ops);
   if (stop) return;
-  const v4f acc = os_accumulate(pr.xf, pr.n, Pp, pr.vals, pr.gidx, 1.0, active, mt, nt, xs, vs);
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+  if (go) acc = os_accumulate(pr.xf, pr.n, Pp, pr.vals, pr.gidx, mt, nt, ops);
   (void)os_write(acc, sl, bold, P, Pp, pr.cK, pr.cB, pr.out, pr.frag);
 }
 

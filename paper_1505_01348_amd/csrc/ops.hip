@@ -404,61 +404,60 @@ __global__ __launch_bounds__(64) void adjoint_rows_finish_kernel(AdjParams pr, c
 
 // ---------------------------------------------------------------------------
 // Beamforming of a free list for 7..12 row tiles (LSQR adjoint): one 16-pixel
-// tile per workgroup; wave w takes row tiles w, w + 4, w + 8 over the whole K
-// and issues every fragment load (Ut fragments prepared by the correlation)
-// and every load of its pixel's column of X_F before the first MFMA, so that
-// the K loop costs one round trip to memory instead of staged LDS chunks.  The
-// waves' column dots meet in LDS.  Row tiles past MT are loaded clamped and
-// left out of the dot.
+// tile per workgroup of MT waves, wave m taking row tile m over the whole K.
+// A wave may hold at most 63 loads in flight, so each issues only its KS
+// fragment loads (Ut fragments prepared by the correlation) and one float4 of
+// the tile's 16 columns of X_F, which the workgroup stages in LDS; the K loop
+// then waits on one round trip to memory.  The waves' column dots meet in
+// LDS and are added in row-tile order.
+constexpr int kListThreads = 768;
+
 template <int MT, class Epi>
-__global__ __launch_bounds__(kThreads) void adjoint_list_kernel(AdjParams pr, Epi epi) {
-  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
-  const typename Epi::Ctx cx = epi.init();
-  if (stop) return;
-  constexpr int KS = 4 * MT, RPW = (MT + 3) / 4, Pp = 8 * MT;
-  __shared__ float gsh[4][16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+__global__ __launch_bounds__(kListThreads) void adjoint_list_kernel(AdjParams pr, Epi epi) {
+  constexpr int KS = 4 * MT, Pp = 8 * MT, RS = 2 * Pp + 4;  // LDS row stride: 2-way banks at most
+  __shared__ float xs[16 * RS];
+  __shared__ float gsh[MT][16];
+  const int tid = threadIdx.x, lane = tid & 63, m = tid >> 6;
   const int c16 = lane & 15, q = lane >> 4;
   const int tile = blockIdx.x, n = pr.n;
-  const float* xc = pr.xf + (size_t)min(16 * tile + c16, n - 1) * 2 * Pp;
-  float b[KS];
+  const int col = 16 * tile + tid;
+  // the stop flag, every operand and the epilogue's inputs are requested
+  // together (all in bounds whether or not the flag is set)
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
+  const float* fm = pr.frag + (size_t)m * KS * 64 + lane;
+  float a[KS];
 #pragma unroll
-  for (int k = 0; k < KS; ++k) b[k] = xc[4 * k + q];
-  float a[RPW][KS];
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const float* fm = pr.frag + (size_t)min(w + 4 * i, MT - 1) * KS * 64 + lane;
-#pragma unroll
-    for (int k = 0; k < KS; ++k) a[i][k] = fm[k * 64];
+  for (int k = 0; k < KS; ++k) a[k] = fm[k * 64];
+  {  // 16 columns x 2Pp floats = 64 MT float4s: one per thread
+    const int r = tid / (Pp / 2), j = tid - r * (Pp / 2);
+    const float4 x = *reinterpret_cast<const float4*>(pr.xf + (size_t)min(16 * tile + r, n - 1) * 2 * Pp + 4 * j);
+    float* d = xs + r * RS + 4 * j;
+    d[0] = x.x;
+    d[1] = x.y;
+    d[2] = x.z;
+    d[3] = x.w;
   }
-  v4f acc[RPW];
+  const typename Epi::Pre pf = epi.prefetch(col, tid < 16 && col < n);
+  const typename Epi::Ctx cx = epi.init();
+  if (stop) return;
+  __syncthreads();  // xs complete
+  const float* xc = xs + c16 * RS;
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < KS; ++k) acc[i] = mfma16x16x4(a[i][k], b[k], acc[i]);
-  }
-  // column dot: accumulator element r of row tile m is row 16m + 4q + r
-  float gp = 0.f;
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int m = w + 4 * i;
-    if (m < MT) {
-      const float4 x = *reinterpret_cast<const float4*>(xc + 16 * m + 4 * q);
-      gp += x.x * acc[i][0] + x.y * acc[i][1] + x.z * acc[i][2] + x.w * acc[i][3];
-    }
-  }
+  for (int k = 0; k < KS; ++k) acc = mfma16x16x4(a[k], xc[4 * k + q], acc);
+  // column dot: accumulator element r is row 16 m + 4 q + r
+  const float4 xr = *reinterpret_cast<const float4*>(xc + 16 * m + 4 * q);
+  float gp = xr.x * acc[0] + xr.y * acc[1] + xr.z * acc[2] + xr.w * acc[3];
   gp += __shfl_xor(gp, 16, 64);
   gp += __shfl_xor(gp, 32, 64);
-  if (q == 0) gsh[w][c16] = gp;
+  if (q == 0) gsh[m][c16] = gp;
   __syncthreads();
-  const int col = 16 * tile + tid;
-  const typename Epi::Pre pf = epi.prefetch(col, tid < 16 && col < n);
   float g = 0.f;
   bool ok = false;
   int pix = 0;
   if (tid < 16) {
-    g = (gsh[0][tid] + gsh[1][tid]) + (gsh[2][tid] + gsh[3][tid]);
+#pragma unroll
+    for (int i = 0; i < MT; ++i) g += gsh[i][tid];
     ok = col < n;
     if (ok) {
       pix = pr.idx ? pr.idx[col] : col;
@@ -1362,13 +1361,14 @@ hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipSt
   if (pr.MT > 6 && pr.MT <= 12) {
     const dim3 g((pr.n + 15) / 16), b(kThreads);
     if (pr.xf && pr.frag && !pr.U) {
+      const dim3 bl(64 * pr.MT);  // one wave per row tile
       switch (pr.MT) {
-        case 7: hipLaunchKernelGGL((adjoint_list_kernel<7, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
-        case 8: hipLaunchKernelGGL((adjoint_list_kernel<8, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
-        case 9: hipLaunchKernelGGL((adjoint_list_kernel<9, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
-        case 10: hipLaunchKernelGGL((adjoint_list_kernel<10, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
-        case 11: hipLaunchKernelGGL((adjoint_list_kernel<11, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
-        default: hipLaunchKernelGGL((adjoint_list_kernel<12, EpiLsqrV2>), g, b, 0, st, pr, epi); break;
+        case 7: hipLaunchKernelGGL((adjoint_list_kernel<7, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
+        case 8: hipLaunchKernelGGL((adjoint_list_kernel<8, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
+        case 9: hipLaunchKernelGGL((adjoint_list_kernel<9, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
+        case 10: hipLaunchKernelGGL((adjoint_list_kernel<10, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
+        case 11: hipLaunchKernelGGL((adjoint_list_kernel<11, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
+        default: hipLaunchKernelGGL((adjoint_list_kernel<12, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
       }
     } else {
       hipLaunchKernelGGL((adjoint_kernel<3, 1, 4, EpiLsqrV2>), g, b, 0, st, pr, epi);

@@ -108,10 +108,14 @@ __device__ inline double os_write(v4f acc, const OsSlots& sl, const float2* Bold
 }
 
 // ---------------------------------------------------------------------------
+// Wave 0 of every workgroup finishes step it-1 (its lanes hold the same
+// scalars, wave sums on the VALU, so only the finished flag and two scalars
+// cross to the other waves, through one barrier); the other waves meanwhile
+// form their tiles of Psi_F v_raw, which is scaled by 1 / alpha afterwards.
+constexpr int kFwdVecPre = 4;  // vector entries per lane of wave 0 loaded at launch (n <= 256)
+
 __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
-  __shared__ double red_ab[8], red_dx[8];
-  __shared__ double sc[8];
-  __shared__ LsqrState sS;
+  __shared__ double sc[2];
   __shared__ int s_done;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c16 = lane & 15, q = lane >> 4;
@@ -131,129 +135,129 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
   if (active) tri_tile(tp, MT, mt, nt);
   const OsSlots sl = os_slots(mt, nt, c16, q, P, active);
 
-  // ---- every independent load first: flag, state, partials, old u, vectors ----
+  // ---- every independent load first: flag, old u, the tile's operands and,
+  // in wave 0, the state, the partials and the vectors ----
   const int was_done = *pr.done;
-  if (tid == 0) sS = *Sprev;
-  double a2 = 0.0, b2 = 0.0;
-  for (int i = tid; i < pr.nalpha; i += kThreads) a2 += pr.alpha_part[i];
-  for (int i = tid; i < pr.nbeta_in; i += kThreads) b2 += pr.beta_in[i];
   float2 uold[4];
   os_prefetch(sl, pr.u, P, uold);
-  float vr0 = 0.f, wp0 = 0.f, xp0 = 0.f;
-  if (tid < n) {
-    vr0 = pr.vraw[tid];
-    if (!first) {
-      wp0 = w_prev[tid];
-      xp0 = x_prev[tid];
-    }
-  }
-  // the tile's operands for the first 64 free pixels (v_raw unscaled: the
-  // sum is scaled by 1 / alpha at the end)
   OsOps ops;
   if (active && n > 0) os_load(pr.xf, n, Pp, pr.vraw, nullptr, 0, mt, nt, ops);
+  if (w == 0) {
+    LsqrState S = *Sprev;  // tolerances and limits travel with the state
+    double a2 = 0.0, b2 = 0.0;
+    for (int i = lane; i < pr.nalpha; i += 64) a2 += pr.alpha_part[i];
+    for (int i = lane; i < pr.nbeta_in; i += 64) b2 += pr.beta_in[i];
+    float vr0[kFwdVecPre], wp0[kFwdVecPre], xp0[kFwdVecPre];
+#pragma unroll
+    for (int j = 0; j < kFwdVecPre; ++j) {
+      const int k = lane + 64 * j;
+      vr0[j] = wp0[j] = xp0[j] = 0.f;
+      if (k < n) {
+        vr0[j] = pr.vraw[k];
+        if (!first) {
+          wp0[j] = w_prev[k];
+          xp0[j] = x_prev[k];
+        }
+      }
+    }
+    if (!was_done) {
+      // ---- finish LSQR step it-1 (every workgroup, identical arithmetic) ----
+      a2 = wave_sum_dpp_d(a2);
+      b2 = wave_sum_dpp_d(b2);
+      const double alpha = sqrt(a2), beta = sqrt(b2);
+      const double iv = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v = v_raw / alpha
+      double ir = 0.0, phi = 0.0, tr = 0.0, c = 0.0, sn = 0.0;
+      if (!first) {
+        const double rho = hypot(S.rhobar, beta);
+        c = S.rhobar / rho;
+        sn = beta / rho;
+        ir = 1.0 / rho;         // d = w / rho
+        phi = c * S.phibar;
+        tr = sn * alpha / rho;  // theta / rho
+      }
+      double dd = 0.0, xx = 0.0;
+      for (int j = 0, k = lane; k < n; ++j, k += 64) {
+        const bool pre = j < kFwdVecPre;
+        const float vf = (float)((double)(pre ? vr0[j] : pr.vraw[k]) * iv);
+        if (first) {
+          if (wg0) {
+            pr.vnorm[k] = vf;
+            w_cur[k] = vf;
+            x_cur[k] = 0.f;
+          }
+        } else {
+          const double wk = (double)(pre ? wp0[j] : w_prev[k]);
+          const double dk = wk * ir;
+          dd += dk * dk;
+          const float xk = (float)((double)(pre ? xp0[j] : x_prev[k]) + phi * dk);
+          xx += (double)xk * xk;
+          if (wg0) {
+            pr.vnorm[k] = vf;
+            x_cur[k] = xk;
+            w_cur[k] = (float)((double)vf - tr * wk);
+          }
+        }
+      }
+      dd = wave_sum_dpp_d(dd);
+      xx = wave_sum_dpp_d(xx);
+      if (first) {
+        S.alpha = alpha;
+        S.beta = beta;
+        S.rhobar = alpha;
+        S.phibar = beta;
+        S.bnorm = beta;
+        S.anorm2 = 0.0;
+        S.ddnorm = 0.0;
+        S.rnorm = beta;
+        S.arnorm = alpha * beta;
+        S.anorm = S.acond = S.xnorm = 0.0;
+        S.itn = 0;
+        S.istop = (n == 0 || alpha == 0.0 || beta == 0.0) ? 4 : 0;
+      } else {
+        S.anorm2 += S.alpha * S.alpha + beta * beta;
+        S.rhobar = -c * alpha;
+        S.phibar = sn * S.phibar;
+        S.alpha = alpha;
+        S.beta = beta;
+        S.ddnorm += dd;
+        S.rnorm = S.phibar;
+        S.arnorm = S.phibar * alpha * fabs(c);
+        S.anorm = sqrt(S.anorm2);
+        S.acond = S.anorm * sqrt(S.ddnorm);
+        S.xnorm = sqrt(xx);
+        S.itn = it - 1;
+        int istop = 0;
+        if (S.rnorm <= S.btol * S.bnorm + S.atol * S.anorm * S.xnorm) istop = 1;
+        else if (S.arnorm <= S.atol * S.anorm * S.rnorm) istop = 2;
+        else if (S.acond >= S.conlim) istop = 3;
+        else if (alpha == 0.0 || beta == 0.0) istop = 4;
+        else if (S.itn >= S.itnlim) istop = 7;
+        S.istop = istop;
+      }
+      S.done = S.istop != 0;
+      if (lane == 0) {
+        if (wg0) {
+          *Scur = S;
+          if (S.done) *pr.Sfinal = S;
+        }
+        s_done = S.done;
+        sc[0] = iv;
+        sc[1] = alpha > 0.0 && beta > 0.0 ? -alpha / beta : 0.0;
+      }
+    }
+  }
   if (was_done) return;  // uniform: a finished solve
-
-  // ---- finish LSQR step it-1 (every workgroup, identical arithmetic) ----
-  block_sum_d2(a2, b2, red_ab);
-  if (tid == 0) {
-    const double alpha = sqrt(a2), beta = sqrt(b2);
-    sc[0] = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v = v_raw / alpha
-    if (first) {
-      sc[1] = sc[2] = sc[3] = 0.0;
-    } else {
-      const double rho = hypot(sS.rhobar, beta);
-      const double c = sS.rhobar / rho, sn = beta / rho;
-      sc[1] = 1.0 / rho;          // d = w / rho
-      sc[2] = c * sS.phibar;      // phi
-      sc[3] = sn * alpha / rho;   // theta / rho
-      sc[4] = c;
-      sc[5] = sn;
-    }
-  }
-  __syncthreads();
-  const double iv = sc[0], ir = sc[1], phi = sc[2], tr = sc[3];
-  double dd = 0.0, xx = 0.0;
-  for (int k = tid; k < n; k += kThreads) {
-    const bool pre = k == tid;
-    const float vf = (float)((double)(pre ? vr0 : pr.vraw[k]) * iv);
-    if (first) {
-      if (wg0) {
-        pr.vnorm[k] = vf;
-        w_cur[k] = vf;
-        x_cur[k] = 0.f;
-      }
-    } else {
-      const double wk = (double)(pre ? wp0 : w_prev[k]);
-      const double dk = wk * ir;
-      dd += dk * dk;
-      const float xk = (float)((double)(pre ? xp0 : x_prev[k]) + phi * dk);
-      xx += (double)xk * xk;
-      if (wg0) {
-        pr.vnorm[k] = vf;
-        x_cur[k] = xk;
-        w_cur[k] = (float)((double)vf - tr * wk);
-      }
-    }
-  }
-  block_sum_d2(dd, xx, red_dx);
-  if (tid == 0) {
-    LsqrState S = sS;  // tolerances and limits travel with the state
-    const double alpha = sqrt(a2), beta = sqrt(b2);
-    if (first) {
-      S.alpha = alpha;
-      S.beta = beta;
-      S.rhobar = alpha;
-      S.phibar = beta;
-      S.bnorm = beta;
-      S.anorm2 = 0.0;
-      S.ddnorm = 0.0;
-      S.rnorm = beta;
-      S.arnorm = alpha * beta;
-      S.anorm = S.acond = S.xnorm = 0.0;
-      S.itn = 0;
-      S.istop = (n == 0 || alpha == 0.0 || beta == 0.0) ? 4 : 0;
-    } else {
-      const double c = sc[4], sn = sc[5];
-      S.anorm2 += S.alpha * S.alpha + beta * beta;
-      S.rhobar = -c * alpha;
-      S.phibar = sn * S.phibar;
-      S.alpha = alpha;
-      S.beta = beta;
-      S.ddnorm += dd;
-      S.rnorm = S.phibar;
-      S.arnorm = S.phibar * alpha * fabs(c);
-      S.anorm = sqrt(S.anorm2);
-      S.acond = S.anorm * sqrt(S.ddnorm);
-      S.xnorm = sqrt(xx);
-      S.itn = it - 1;
-      int istop = 0;
-      if (S.rnorm <= S.btol * S.bnorm + S.atol * S.anorm * S.xnorm) istop = 1;
-      else if (S.arnorm <= S.atol * S.anorm * S.rnorm) istop = 2;
-      else if (S.acond >= S.conlim) istop = 3;
-      else if (alpha == 0.0 || beta == 0.0) istop = 4;
-      else if (S.itn >= S.itnlim) istop = 7;
-      S.istop = istop;
-    }
-    S.done = S.istop != 0;
-    s_done = S.done;
-    if (wg0) {
-      *Scur = S;
-      if (S.done) *pr.Sfinal = S;
-    }
-    sc[7] = alpha > 0.0 && beta > 0.0 ? -alpha / beta : 0.0;
-  }
-  __syncthreads();
+  // ---- u_{it+1} = Psi_F v_it - (alpha/beta) u_it ----
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+  if (active) acc = os_accumulate(pr.xf, n, Pp, pr.vraw, nullptr, mt, nt, ops);
+  __syncthreads();  // wave 0's scalars
   if (s_done) {
     // the final iterate x_{itn} stays in x[itn & 1]; the state went to Sfinal
     if (wg0 && tid == 0) *pr.done = 1;
     return;
   }
-
-  // ---- u_{it+1} = Psi_F v_it - (alpha/beta) u_it ----
-  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
-  if (active) acc = os_accumulate(pr.xf, n, Pp, pr.vraw, nullptr, mt, nt, ops);
-  double nrm = os_write(acc, sl, uold, P, Pp, (float)iv, (float)sc[7], pr.u, pr.frag);
-  nrm = wave_sum_d(nrm);
+  double nrm = os_write(acc, sl, uold, P, Pp, (float)sc[0], (float)sc[1], pr.u, pr.frag);
+  nrm = wave_sum_dpp_d(nrm);
   if (lane == 0) pr.beta_out[tp] = nrm;
 }
 

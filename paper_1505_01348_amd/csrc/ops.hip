@@ -403,24 +403,27 @@ __global__ __launch_bounds__(64) void adjoint_rows_finish_kernel(AdjParams pr, c
 }
 
 // ---------------------------------------------------------------------------
-// Beamforming of a free list for 7..12 row tiles (LSQR adjoint): one 16-pixel
-// tile per workgroup of MT waves, wave m taking row tile m over the whole K.
-// A wave may hold at most 63 loads in flight, so each issues only its KS
-// fragment loads (Ut fragments prepared by the correlation) and one float4 of
-// the tile's 16 columns of X_F, which the workgroup stages in LDS; the K loop
-// then waits on one round trip to memory.  The waves' column dots meet in
-// LDS and are added in row-tile order.
+// Beamforming of a free list for 7..12 row tiles (LSQR adjoint,
+// v_raw = Psi_F^H u / beta - beta v with the ||v_raw||^2 partial of the
+// tile): one 16-pixel tile per workgroup of MT waves, wave m taking row tile
+// m over the whole K.  A wave may hold at most 63 loads in flight, so each
+// issues only its KS fragment loads (Ut fragments prepared by the
+// correlation) and one float4 of the tile's 16 columns of X_F, which the
+// workgroup stages in LDS; the K loop then waits on one round trip to memory.
+// The waves' column dots meet in LDS, and wave 0 adds them in row-tile order
+// and runs the epilogue alone (wave sums on the VALU, no further barrier).
 constexpr int kListThreads = 768;
 
-template <int MT, class Epi>
-__global__ __launch_bounds__(kListThreads) void adjoint_list_kernel(AdjParams pr, Epi epi) {
+template <int MT>
+__global__ __launch_bounds__(kListThreads) void adjoint_list_kernel(AdjParams pr, EpiLsqrV2 epi) {
   constexpr int KS = 4 * MT, Pp = 8 * MT, RS = 2 * Pp + 4;  // LDS row stride: 2-way banks at most
+  constexpr int kBetaPre = 2;  // ||u||^2 partials per lane of wave 0 loaded at launch
   __shared__ float xs[16 * RS];
   __shared__ float gsh[MT][16];
   const int tid = threadIdx.x, lane = tid & 63, m = tid >> 6;
   const int c16 = lane & 15, q = lane >> 4;
   const int tile = blockIdx.x, n = pr.n;
-  const int col = 16 * tile + tid;
+  const int col = 16 * tile + lane;
   // the stop flag, every operand and the epilogue's inputs are requested
   // together (all in bounds whether or not the flag is set)
   const int stop = pr.stop_flag ? *pr.stop_flag : 0;
@@ -437,8 +440,16 @@ __global__ __launch_bounds__(kListThreads) void adjoint_list_kernel(AdjParams pr
     d[2] = x.z;
     d[3] = x.w;
   }
-  const typename Epi::Pre pf = epi.prefetch(col, tid < 16 && col < n);
-  const typename Epi::Ctx cx = epi.init();
+  // wave 0 runs the epilogue: beta_{it+1} from the correlation's partials and
+  // v_it of its 16 columns
+  double bp[kBetaPre] = {0.0, 0.0};
+  float vold = 0.f;
+  if (m == 0) {
+#pragma unroll
+    for (int j = 0; j < kBetaPre; ++j)
+      if (lane + 64 * j < epi.nbeta) bp[j] = epi.beta_part[lane + 64 * j];
+    if (lane < 16 && col < n && !epi.first) vold = epi.vnorm[col];
+  }
   if (stop) return;
   __syncthreads();  // xs complete
   const float* xc = xs + c16 * RS;
@@ -452,22 +463,25 @@ __global__ __launch_bounds__(kListThreads) void adjoint_list_kernel(AdjParams pr
   gp += __shfl_xor(gp, 32, 64);
   if (q == 0) gsh[m][c16] = gp;
   __syncthreads();
-  float g = 0.f;
-  bool ok = false;
-  int pix = 0;
-  if (tid < 16) {
+  if (m != 0) return;
+  double b2 = bp[0] + bp[1];
+  for (int i = lane + 64 * kBetaPre; i < epi.nbeta; i += 64) b2 += epi.beta_part[i];
+  const double beta = sqrt(wave_sum_dpp_d(b2));
+  double vr2 = 0.0;
+  if (lane < 16 && col < n) {
+    float g = 0.f;
 #pragma unroll
-    for (int i = 0; i < MT; ++i) g += gsh[i][tid];
-    ok = col < n;
-    if (ok) {
-      pix = pr.idx ? pr.idx[col] : col;
-      if ((unsigned)pix >= (unsigned)pr.tab.Q) {  // invalid pixel index: NaN output
-        pix = 0;
-        g = __builtin_nanf("");
-      }
-    }
+    for (int i = 0; i < MT; ++i) g += gsh[i][lane];
+    const int pix = pr.idx ? pr.idx[col] : col;
+    if ((unsigned)pix >= (unsigned)pr.tab.Q) g = __builtin_nanf("");  // invalid pixel index: NaN output
+    double vr = beta > 0.0 ? (double)g / beta : 0.0;
+    if (!epi.first) vr -= beta * (double)vold;
+    const float vf = (float)vr;
+    epi.vraw[col] = vf;
+    vr2 = (double)vf * vf;
   }
-  epi(tile, col, pix, g, ok, cx, pf);
+  vr2 = wave_sum_dpp_d(vr2);
+  if (lane == 0) epi.alpha_part[tile] = vr2;
 }
 
 // ---------------------------------------------------------------------------
@@ -1363,12 +1377,12 @@ hipError_t launch_adjoint_lsqr2(const AdjParams& pr, const EpiLsqrV2& epi, hipSt
     if (pr.xf && pr.frag && !pr.U) {
       const dim3 bl(64 * pr.MT);  // one wave per row tile
       switch (pr.MT) {
-        case 7: hipLaunchKernelGGL((adjoint_list_kernel<7, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
-        case 8: hipLaunchKernelGGL((adjoint_list_kernel<8, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
-        case 9: hipLaunchKernelGGL((adjoint_list_kernel<9, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
-        case 10: hipLaunchKernelGGL((adjoint_list_kernel<10, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
-        case 11: hipLaunchKernelGGL((adjoint_list_kernel<11, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
-        default: hipLaunchKernelGGL((adjoint_list_kernel<12, EpiLsqrV2>), g, bl, 0, st, pr, epi); break;
+        case 7: hipLaunchKernelGGL((adjoint_list_kernel<7>), g, bl, 0, st, pr, epi); break;
+        case 8: hipLaunchKernelGGL((adjoint_list_kernel<8>), g, bl, 0, st, pr, epi); break;
+        case 9: hipLaunchKernelGGL((adjoint_list_kernel<9>), g, bl, 0, st, pr, epi); break;
+        case 10: hipLaunchKernelGGL((adjoint_list_kernel<10>), g, bl, 0, st, pr, epi); break;
+        case 11: hipLaunchKernelGGL((adjoint_list_kernel<11>), g, bl, 0, st, pr, epi); break;
+        default: hipLaunchKernelGGL((adjoint_list_kernel<12>), g, bl, 0, st, pr, epi); break;
       }
     } else {
       hipLaunchKernelGGL((adjoint_kernel<3, 1, 4, EpiLsqrV2>), g, b, 0, st, pr, epi);

@@ -912,6 +912,39 @@ def headline_bench(args, clsimg, synth, np, torch):
           "us_per_lsqr_iteration_bound": round(r1["total"] / 20 * 1e6 / max(r1["stats"]["lsqr_iters_total"], 1), 3)}
     c1["full_grid_48"] = full_grid_ops(ctx, clsimg, np, torch, s1)
     result["c1"] = c1
+
+    # the 96-antenna workload: complete solves (Table I driven from the host,
+    # the free-set LSQR in two launches per iteration), in the headline's
+    # precision and in FP32
+    s2 = synth.make_scene("c2")
+    g2 = clsimg.Geometry(s2.pos, s2.lam, s2.grid)
+    R2 = torch.as_tensor(s2.R_hat32).cuda()
+    nd2 = torch.as_tensor(s2.noise_diag.astype(np.float32)).cuda()
+    c2_runs = {}
+    for pname in dict.fromkeys([args.precision, "fp32"]):
+        o2 = clsimg.default_options()
+        o2.nsamples = s2.N
+        o2.atol = o2.btol = args.tol
+        o2.precision = PRECISIONS[pname]
+        c2_runs[pname] = time_solves(ctx, R2, g2, o2, nd2, 10, 2, torch, f"c2 complete solves, {pname}")
+    r2 = c2_runs[args.precision]
+    l2 = np.array(r2["lat"]) * 1e3
+    c2 = {"workload": f"c2: {WORKLOADS['c2']}", "precision": args.precision,
+          "solves_per_s": round(10 / r2["total"], 3),
+          "p50_ms": round(float(np.percentile(l2, 50)), 3), "p99_ms": round(float(np.percentile(l2, 99)), 3),
+          "psi_tflops_dense_count": round(r2["flops"] / r2["total"] / 1e12, 4),
+          "solve": {k: r2["stats"][k] for k in ("status", "outer_iters", "adds", "drops", "lsqr_iters_total", "nF",
+                                                "nU", "rel_residual")},
+          "dominant_kernels": "lsqr_fwd_kernel + adjoint_list_kernel<12> (the two launches of each LSQR "
+                              "iteration over the free set)",
+          "us_per_lsqr_iteration_bound": round(r2["total"] / 10 * 1e6 / max(r2["stats"]["lsqr_iters_total"], 1), 3)}
+    if args.precision != "fp32":
+        r32 = c2_runs["fp32"]
+        c2["fp32"] = {"solves_per_s": round(10 / r32["total"], 3),
+                      "rel_residual": r32["stats"]["rel_residual"],
+                      "same_sets": bool(np.array_equal(r2["state"].cpu().numpy(), r32["state"].cpu().numpy()))}
+    result["c2"] = c2
+    del R2
     sizes = sorted({int(x) for x in str(args.batched_extra).split(",") if int(x) > 1})
     if sizes:
         result["batched_c1"] = batched_sweep(ctx, clsimg, synth, np, torch, o1, sizes, r1["stats"])
@@ -942,6 +975,13 @@ def headline_bench(args, clsimg, synth, np, torch):
         c1["parity"] = parity_of(r1["sigma"], r1["state"], ref1)
         c1["cpu_baseline"] = {"value": round(1.0 / t1, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
                               "sample": f"1 complete FP64 oracle solve ({t1:.1f} s)"}
+        t0 = time.perf_counter()
+        ref2 = oracle_solve(s2)
+        t2 = time.perf_counter() - t0
+        c2["parity"] = parity_of(r2["sigma"], r2["state"], ref2)
+        c2["cpu_baseline"] = {"value": round(1.0 / t2, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
+                              "sample": f"1 complete FP64 oracle solve ({t2:.1f} s)"}
+        log(f"cpu baseline: c2 oracle solve {t2:.1f} s")
         s0 = synth.make_scene("c0")
         with threadpoolctl.threadpool_limits(1):
             runs, t0c = 0, 0.0

@@ -20,7 +20,7 @@
 // The correlation is output-stationary: one wave owns one 16 x 16 tile
 // (mt <= nt) of G = X_F diag(v) X_F^T, loads its two 16-row slices of the
 // real-embedded steering vectors and the weights straight into registers
-// (64 pixels at a time, the next 64 in flight while the current ones
+// (128 pixels at a time, the next 128 in flight while the current ones
 // multiply), and writes the Hermitian mirror of an off-diagonal tile itself.
 // No LDS, no partial sums, no reduction kernel.  The steering vectors of the free set are generated once
 // per subproblem (xf_kernel, 2Pp x |F| floats) and read by every LSQR step.
@@ -38,12 +38,12 @@ __global__ void xf_kernel(Tables tab, const int* __restrict__ Flist, int n, floa
   }
 }
 
-// Operands of one wave's tile for 16 k steps (64 pixels) straight from X_F:
+// Operands of one wave's tile for 32 k steps (128 pixels) straight from X_F:
 // at step s lane (c16, q) takes pixel k0 + 4 s + q, rows 16 mt + c16 and
 // 16 nt + c16 of its real-embedded steering vector, and its weight (zero
 // past the list; the pixel index is clamped into it, so every load stays in
 // X_F).  n >= 1.
-constexpr int kOsSteps = 16;
+constexpr int kOsSteps = 32;
 
 struct OsOps {
   float a[kOsSteps], b[kOsSteps], v[kOsSteps];
@@ -79,8 +79,8 @@ __device__ inline void os_mma(const OsOps& o, v4f (&acc)[4]) {
   for (int s = 0; s < kOsSteps; ++s) acc[s & 3] = mfma16x16x4(o.a[s] * o.v[s], o.b[s], acc[s & 3]);
 }
 
-// The tile sum over the whole list, the operands of the next 64 pixels
-// loaded while the current ones multiply; `o` holds the first 64 (loaded by
+// The tile sum over the whole list, the operands of the next 128 pixels
+// loaded while the current ones multiply; `o` holds the first 128 (loaded by
 // the caller, so that their round trip overlaps the caller's other work).
 __device__ inline v4f os_accumulate(const float* __restrict__ xf, int n, int Pp, const float* __restrict__ vals,
                                     const int* __restrict__ gidx, int mt, int nt, OsOps& o) {
@@ -135,19 +135,20 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
   if (active) tri_tile(tp, MT, mt, nt);
   const OsSlots sl = os_slots(mt, nt, c16, q, P, active);
 
-  // ---- every independent load first: flag, old u, the tile's operands and,
-  // in wave 0, the state, the partials and the vectors ----
+  // ---- every independent load first: flag; in wave 0 the state, the
+  // partials and the vectors (ahead of the operands, which may fill the
+  // wave's loads in flight); old u and the tile's operands ----
   const int was_done = *pr.done;
-  float2 uold[4];
-  os_prefetch(sl, pr.u, P, uold);
-  OsOps ops;
-  if (active && n > 0) os_load(pr.xf, n, Pp, pr.vraw, nullptr, 0, mt, nt, ops);
+  LsqrState S;
+  double ap[2] = {0.0, 0.0}, bp[2] = {0.0, 0.0};
+  float vr0[kFwdVecPre], wp0[kFwdVecPre], xp0[kFwdVecPre];
   if (w == 0) {
-    LsqrState S = *Sprev;  // tolerances and limits travel with the state
-    double a2 = 0.0, b2 = 0.0;
-    for (int i = lane; i < pr.nalpha; i += 64) a2 += pr.alpha_part[i];
-    for (int i = lane; i < pr.nbeta_in; i += 64) b2 += pr.beta_in[i];
-    float vr0[kFwdVecPre], wp0[kFwdVecPre], xp0[kFwdVecPre];
+    S = *Sprev;  // tolerances and limits travel with the state
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (lane + 64 * j < pr.nalpha) ap[j] = pr.alpha_part[lane + 64 * j];
+      if (lane + 64 * j < pr.nbeta_in) bp[j] = pr.beta_in[lane + 64 * j];
+    }
 #pragma unroll
     for (int j = 0; j < kFwdVecPre; ++j) {
       const int k = lane + 64 * j;
@@ -160,8 +161,17 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
         }
       }
     }
+  }
+  float2 uold[4];
+  os_prefetch(sl, pr.u, P, uold);
+  OsOps ops;
+  if (active && n > 0) os_load(pr.xf, n, Pp, pr.vraw, nullptr, 0, mt, nt, ops);
+  if (w == 0) {
     if (!was_done) {
       // ---- finish LSQR step it-1 (every workgroup, identical arithmetic) ----
+      double a2 = ap[0] + ap[1], b2 = bp[0] + bp[1];
+      for (int i = lane + 128; i < pr.nalpha; i += 64) a2 += pr.alpha_part[i];
+      for (int i = lane + 128; i < pr.nbeta_in; i += 64) b2 += pr.beta_in[i];
       a2 = wave_sum_dpp_d(a2);
       b2 = wave_sum_dpp_d(b2);
       const double alpha = sqrt(a2), beta = sqrt(b2);

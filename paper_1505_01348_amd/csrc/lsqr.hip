@@ -10,18 +10,19 @@
 //   adjoint_kernel<EpiLsqrV2>(it):
 //                         v_raw = Psi_F^H u_{it+1} / beta_{it+1} - beta_{it+1} v_it
 //                         with ||v_raw||^2 partials.
-// Every workgroup of lsqr_fwd_kernel evaluates the scalar recurrence and the
-// stopping tests itself from the same inputs in the same order, so all of them
-// agree bit for bit without a grid barrier; workgroup 0 alone writes the
-// vectors and the state.  Scalars and vectors whose old and new values are
+// Every workgroup of lsqr_fwd_kernel forms alpha and beta itself from the same
+// partials in the same order, so all of them agree bit for bit without a grid
+// barrier; workgroup 0 alone completes the rotation, writes the vectors and
+// the state and takes the stopping decision, which the following launches
+// read from the done flag.  Scalars and vectors whose old and new values are
 // both live are double-buffered by iteration parity: x_j lives in x[j & 1],
 // w_j in w[j & 1], the state after step j in S[(j + 1) & 1].
 //
 // The correlation is output-stationary: one wave owns one 16 x 16 tile
 // (mt <= nt) of G = X_F diag(v) X_F^T, loads its two 16-row slices of the
 // real-embedded steering vectors and the weights straight into registers
-// (128 pixels at a time, the next 128 in flight while the current ones
-// multiply), and writes the Hermitian mirror of an off-diagonal tile itself.
+// (128 pixels at a time, the first 128 requested at launch), and writes the
+// Hermitian mirror of an off-diagonal tile itself.
 // No LDS, no partial sums, no reduction kernel.  The steering vectors of the free set are generated once
 // per subproblem (xf_kernel, 2Pp x |F| floats) and read by every LSQR step.
 #include "os_tiles.h"
@@ -79,20 +80,18 @@ __device__ inline void os_mma(const OsOps& o, v4f (&acc)[4]) {
   for (int s = 0; s < kOsSteps; ++s) acc[s & 3] = mfma16x16x4(o.a[s] * o.v[s], o.b[s], acc[s & 3]);
 }
 
-// The tile sum over the whole list, the operands of the next 128 pixels
-// loaded while the current ones multiply; `o` holds the first 128 (loaded by
-// the caller, so that their round trip overlaps the caller's other work).
+// The tile sum over the whole list; `o` holds the operands of the first 128
+// pixels (loaded by the caller, so that their round trip overlaps the
+// caller's other work), later chunks are loaded here one after another.
 __device__ inline v4f os_accumulate(const float* __restrict__ xf, int n, int Pp, const float* __restrict__ vals,
                                     const int* __restrict__ gidx, int mt, int nt, OsOps& o) {
   v4f acc[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < n; k0 += 4 * kOsSteps) {
-    const bool more = k0 + 4 * kOsSteps < n;
-    OsOps nx;
-    if (more) os_load(xf, n, Pp, vals, gidx, k0 + 4 * kOsSteps, mt, nt, nx);
+  os_mma(o, acc);
+  for (int k0 = 4 * kOsSteps; k0 < n; k0 += 4 * kOsSteps) {
+    os_load(xf, n, Pp, vals, gidx, k0, mt, nt, o);
     os_mma(o, acc);
-    if (more) o = nx;
   }
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
@@ -108,47 +107,42 @@ __device__ inline double os_write(v4f acc, const OsSlots& sl, const float2* Bold
 }
 
 // ---------------------------------------------------------------------------
-// Wave 0 of every workgroup finishes step it-1 (its lanes hold the same
-// scalars, wave sums on the VALU, so only the finished flag and two scalars
-// cross to the other waves, through one barrier); the other waves meanwhile
-// form their tiles of Psi_F v_raw, which is scaled by 1 / alpha afterwards.
+// Each workgroup has five waves.  Wave 0 starts finishing step it-1 (its
+// lanes hold the same scalars, wave sums on the VALU): as soon as alpha and
+// beta are known it hands 1 / alpha and -alpha / beta to the tile waves
+// through one barrier; in workgroup 0 it then completes the rotation, the
+// vector updates and the stopping tests while they write.  Waves 1-4 each own one tile of Psi_F v_raw (formed
+// before the barrier, scaled by 1 / alpha after it).  The tile waves write u,
+// its fragments and norm partials also in the step where the tests stop the
+// solve: nothing reads them after that (the next kernels see the flag).
 constexpr int kFwdVecPre = 4;  // vector entries per lane of wave 0 loaded at launch (n <= 256)
+constexpr int kFwdThreads = 320;
 
-__global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
+__global__ __launch_bounds__(kFwdThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
   __shared__ double sc[2];
-  __shared__ int s_done;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c16 = lane & 15, q = lane >> 4;
   const int it = pr.it, n = pr.n;
   const bool first = (it == 1);
   const bool wg0 = (blockIdx.x == 0);
-  LsqrState* Sprev = pr.S + ((it - 1) & 1);
-  LsqrState* Scur = pr.S + (it & 1);
-  float* x_prev = (it & 1) ? pr.x1 : pr.x0;  // x_{it-2}
-  float* x_cur = (it & 1) ? pr.x0 : pr.x1;   // x_{it-1}
-  float* w_prev = (it & 1) ? pr.w0 : pr.w1;  // w_{it-1}
-  float* w_cur = (it & 1) ? pr.w1 : pr.w0;   // w_it
   const int MT = pr.MT, P = pr.P, Pp = 8 * MT;
-  const int tp = blockIdx.x * 4 + w;
-  const bool active = tp < pr.ntp;
-  int mt = 0, nt = 0;
-  if (active) tri_tile(tp, MT, mt, nt);
-  const OsSlots sl = os_slots(mt, nt, c16, q, P, active);
-
-  // ---- every independent load first: flag; in wave 0 the state, the
-  // partials and the vectors (ahead of the operands, which may fill the
-  // wave's loads in flight); old u and the tile's operands ----
   const int was_done = *pr.done;
-  LsqrState S;
-  double ap[2] = {0.0, 0.0}, bp[2] = {0.0, 0.0};
-  float vr0[kFwdVecPre], wp0[kFwdVecPre], xp0[kFwdVecPre];
   if (w == 0) {
-    S = *Sprev;  // tolerances and limits travel with the state
+    LsqrState* Sprev = pr.S + ((it - 1) & 1);
+    LsqrState* Scur = pr.S + (it & 1);
+    float* x_prev = (it & 1) ? pr.x1 : pr.x0;  // x_{it-2}
+    float* x_cur = (it & 1) ? pr.x0 : pr.x1;   // x_{it-1}
+    float* w_prev = (it & 1) ? pr.w0 : pr.w1;  // w_{it-1}
+    float* w_cur = (it & 1) ? pr.w1 : pr.w0;   // w_it
+    // ---- every load first: state, partials, vectors ----
+    LsqrState S = *Sprev;  // tolerances and limits travel with the state
+    double ap[2] = {0.0, 0.0}, bp[2] = {0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (lane + 64 * j < pr.nalpha) ap[j] = pr.alpha_part[lane + 64 * j];
       if (lane + 64 * j < pr.nbeta_in) bp[j] = pr.beta_in[lane + 64 * j];
     }
+    float vr0[kFwdVecPre], wp0[kFwdVecPre], xp0[kFwdVecPre];
 #pragma unroll
     for (int j = 0; j < kFwdVecPre; ++j) {
       const int k = lane + 64 * j;
@@ -161,111 +155,109 @@ __global__ __launch_bounds__(kThreads) void lsqr_fwd_kernel(LsqrFwdParams pr) {
         }
       }
     }
+    if (was_done) return;  // uniform: a finished solve
+    // ---- finish LSQR step it-1 (every workgroup, identical arithmetic) ----
+    double a2 = ap[0] + ap[1], b2 = bp[0] + bp[1];
+    for (int i = lane + 128; i < pr.nalpha; i += 64) a2 += pr.alpha_part[i];
+    for (int i = lane + 128; i < pr.nbeta_in; i += 64) b2 += pr.beta_in[i];
+    a2 = wave_sum_dpp_d(a2);
+    b2 = wave_sum_dpp_d(b2);
+    const double alpha = sqrt(a2), beta = sqrt(b2);
+    const double iv = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v = v_raw / alpha
+    if (lane == 0) {
+      sc[0] = iv;
+      sc[1] = alpha > 0.0 && beta > 0.0 ? -alpha / beta : 0.0;
+    }
+    __syncthreads();  // the tile waves' scalars
+    if (!wg0) return;  // the vectors, the state and the flag are workgroup 0's
+    double ir = 0.0, phi = 0.0, tr = 0.0, c = 0.0, sn = 0.0;
+    if (!first) {
+      const double rho = hypot(S.rhobar, beta);
+      c = S.rhobar / rho;
+      sn = beta / rho;
+      ir = 1.0 / rho;         // d = w / rho
+      phi = c * S.phibar;
+      tr = sn * alpha / rho;  // theta / rho
+    }
+    double dd = 0.0, xx = 0.0;
+    for (int j = 0, k = lane; k < n; ++j, k += 64) {
+      const bool pre = j < kFwdVecPre;
+      const float vf = (float)((double)(pre ? vr0[j] : pr.vraw[k]) * iv);
+      pr.vnorm[k] = vf;
+      if (first) {
+        w_cur[k] = vf;
+        x_cur[k] = 0.f;
+      } else {
+        const double wk = (double)(pre ? wp0[j] : w_prev[k]);
+        const double dk = wk * ir;
+        dd += dk * dk;
+        const float xk = (float)((double)(pre ? xp0[j] : x_prev[k]) + phi * dk);
+        xx += (double)xk * xk;
+        x_cur[k] = xk;
+        w_cur[k] = (float)((double)vf - tr * wk);
+      }
+    }
+    dd = wave_sum_dpp_d(dd);
+    xx = wave_sum_dpp_d(xx);
+    if (first) {
+      S.alpha = alpha;
+      S.beta = beta;
+      S.rhobar = alpha;
+      S.phibar = beta;
+      S.bnorm = beta;
+      S.anorm2 = 0.0;
+      S.ddnorm = 0.0;
+      S.rnorm = beta;
+      S.arnorm = alpha * beta;
+      S.anorm = S.acond = S.xnorm = 0.0;
+      S.itn = 0;
+      S.istop = (n == 0 || alpha == 0.0 || beta == 0.0) ? 4 : 0;
+    } else {
+      S.anorm2 += S.alpha * S.alpha + beta * beta;
+      S.rhobar = -c * alpha;
+      S.phibar = sn * S.phibar;
+      S.alpha = alpha;
+      S.beta = beta;
+      S.ddnorm += dd;
+      S.rnorm = S.phibar;
+      S.arnorm = S.phibar * alpha * fabs(c);
+      S.anorm = sqrt(S.anorm2);
+      S.acond = S.anorm * sqrt(S.ddnorm);
+      S.xnorm = sqrt(xx);
+      S.itn = it - 1;
+      int istop = 0;
+      if (S.rnorm <= S.btol * S.bnorm + S.atol * S.anorm * S.xnorm) istop = 1;
+      else if (S.arnorm <= S.atol * S.anorm * S.rnorm) istop = 2;
+      else if (S.acond >= S.conlim) istop = 3;
+      else if (alpha == 0.0 || beta == 0.0) istop = 4;
+      else if (S.itn >= S.itnlim) istop = 7;
+      S.istop = istop;
+    }
+    S.done = S.istop != 0;
+    if (lane == 0) {
+      *Scur = S;
+      if (S.done) {
+        // the final iterate x_{itn} stays in x[itn & 1]
+        *pr.Sfinal = S;
+        *pr.done = 1;
+      }
+    }
+    return;
   }
+  // ---- tile waves: u_{it+1} = Psi_F v_it - (alpha/beta) u_it ----
+  const int tp = blockIdx.x * 4 + (w - 1);
+  const bool active = tp < pr.ntp;
+  int mt = 0, nt = 0;
+  if (active) tri_tile(tp, MT, mt, nt);
+  const OsSlots sl = os_slots(mt, nt, c16, q, P, active);
   float2 uold[4];
   os_prefetch(sl, pr.u, P, uold);
   OsOps ops;
   if (active && n > 0) os_load(pr.xf, n, Pp, pr.vraw, nullptr, 0, mt, nt, ops);
-  if (w == 0) {
-    if (!was_done) {
-      // ---- finish LSQR step it-1 (every workgroup, identical arithmetic) ----
-      double a2 = ap[0] + ap[1], b2 = bp[0] + bp[1];
-      for (int i = lane + 128; i < pr.nalpha; i += 64) a2 += pr.alpha_part[i];
-      for (int i = lane + 128; i < pr.nbeta_in; i += 64) b2 += pr.beta_in[i];
-      a2 = wave_sum_dpp_d(a2);
-      b2 = wave_sum_dpp_d(b2);
-      const double alpha = sqrt(a2), beta = sqrt(b2);
-      const double iv = alpha > 0.0 ? 1.0 / alpha : 0.0;  // v = v_raw / alpha
-      double ir = 0.0, phi = 0.0, tr = 0.0, c = 0.0, sn = 0.0;
-      if (!first) {
-        const double rho = hypot(S.rhobar, beta);
-        c = S.rhobar / rho;
-        sn = beta / rho;
-        ir = 1.0 / rho;         // d = w / rho
-        phi = c * S.phibar;
-        tr = sn * alpha / rho;  // theta / rho
-      }
-      double dd = 0.0, xx = 0.0;
-      for (int j = 0, k = lane; k < n; ++j, k += 64) {
-        const bool pre = j < kFwdVecPre;
-        const float vf = (float)((double)(pre ? vr0[j] : pr.vraw[k]) * iv);
-        if (first) {
-          if (wg0) {
-            pr.vnorm[k] = vf;
-            w_cur[k] = vf;
-            x_cur[k] = 0.f;
-          }
-        } else {
-          const double wk = (double)(pre ? wp0[j] : w_prev[k]);
-          const double dk = wk * ir;
-          dd += dk * dk;
-          const float xk = (float)((double)(pre ? xp0[j] : x_prev[k]) + phi * dk);
-          xx += (double)xk * xk;
-          if (wg0) {
-            pr.vnorm[k] = vf;
-            x_cur[k] = xk;
-            w_cur[k] = (float)((double)vf - tr * wk);
-          }
-        }
-      }
-      dd = wave_sum_dpp_d(dd);
-      xx = wave_sum_dpp_d(xx);
-      if (first) {
-        S.alpha = alpha;
-        S.beta = beta;
-        S.rhobar = alpha;
-        S.phibar = beta;
-        S.bnorm = beta;
-        S.anorm2 = 0.0;
-        S.ddnorm = 0.0;
-        S.rnorm = beta;
-        S.arnorm = alpha * beta;
-        S.anorm = S.acond = S.xnorm = 0.0;
-        S.itn = 0;
-        S.istop = (n == 0 || alpha == 0.0 || beta == 0.0) ? 4 : 0;
-      } else {
-        S.anorm2 += S.alpha * S.alpha + beta * beta;
-        S.rhobar = -c * alpha;
-        S.phibar = sn * S.phibar;
-        S.alpha = alpha;
-        S.beta = beta;
-        S.ddnorm += dd;
-        S.rnorm = S.phibar;
-        S.arnorm = S.phibar * alpha * fabs(c);
-        S.anorm = sqrt(S.anorm2);
-        S.acond = S.anorm * sqrt(S.ddnorm);
-        S.xnorm = sqrt(xx);
-        S.itn = it - 1;
-        int istop = 0;
-        if (S.rnorm <= S.btol * S.bnorm + S.atol * S.anorm * S.xnorm) istop = 1;
-        else if (S.arnorm <= S.atol * S.anorm * S.rnorm) istop = 2;
-        else if (S.acond >= S.conlim) istop = 3;
-        else if (alpha == 0.0 || beta == 0.0) istop = 4;
-        else if (S.itn >= S.itnlim) istop = 7;
-        S.istop = istop;
-      }
-      S.done = S.istop != 0;
-      if (lane == 0) {
-        if (wg0) {
-          *Scur = S;
-          if (S.done) *pr.Sfinal = S;
-        }
-        s_done = S.done;
-        sc[0] = iv;
-        sc[1] = alpha > 0.0 && beta > 0.0 ? -alpha / beta : 0.0;
-      }
-    }
-  }
   if (was_done) return;  // uniform: a finished solve
-  // ---- u_{it+1} = Psi_F v_it - (alpha/beta) u_it ----
   v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
   if (active) acc = os_accumulate(pr.xf, n, Pp, pr.vraw, nullptr, mt, nt, ops);
   __syncthreads();  // wave 0's scalars
-  if (s_done) {
-    // the final iterate x_{itn} stays in x[itn & 1]; the state went to Sfinal
-    if (wg0 && tid == 0) *pr.done = 1;
-    return;
-  }
   double nrm = os_write(acc, sl, uold, P, Pp, (float)sc[0], (float)sc[1], pr.u, pr.frag);
   nrm = wave_sum_dpp_d(nrm);
   if (lane == 0) pr.beta_out[tp] = nrm;
@@ -346,7 +338,7 @@ int lsqr_fwd_waves(int P) {
 
 hipError_t launch_lsqr_fwd(const LsqrFwdParams& pr, hipStream_t st) {
   const int blocks = (pr.ntp + 3) / 4;
-  hipLaunchKernelGGL(lsqr_fwd_kernel, dim3(blocks), dim3(kThreads), 0, st, pr);
+  hipLaunchKernelGGL(lsqr_fwd_kernel, dim3(blocks), dim3(kFwdThreads), 0, st, pr);
   return hipGetLastError();
 }
 

@@ -451,6 +451,12 @@ __global__ __launch_bounds__(kListThreads) void adjoint_list_kernel(AdjParams pr
     if (lane < 16 && col < n && !epi.first) vold = epi.vnorm[col];
   }
   if (stop) return;
+  double beta = 0.0;
+  if (m == 0) {  // while the other waves' operands arrive
+    double b2 = bp[0] + bp[1];
+    for (int i = lane + 64 * kBetaPre; i < epi.nbeta; i += 64) b2 += epi.beta_part[i];
+    beta = sqrt(wave_sum_dpp_d(b2));
+  }
   __syncthreads();  // xs complete
   const float* xc = xs + c16 * RS;
   v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
@@ -464,9 +470,6 @@ __global__ __launch_bounds__(kListThreads) void adjoint_list_kernel(AdjParams pr
   if (q == 0) gsh[m][c16] = gp;
   __syncthreads();
   if (m != 0) return;
-  double b2 = bp[0] + bp[1];
-  for (int i = lane + 64 * kBetaPre; i < epi.nbeta; i += 64) b2 += epi.beta_part[i];
-  const double beta = sqrt(wave_sum_dpp_d(b2));
   double vr2 = 0.0;
   if (lane < 16 && col < n) {
     float g = 0.f;

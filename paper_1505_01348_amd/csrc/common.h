@@ -126,13 +126,13 @@ __device__ __forceinline__ double wave_sum_dpp_d(double v) {
                           __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 // Sum of n doubles by one full wave in a fixed order: lane l adds p[l],
-// p[l + 64], ... in turn, then an xor butterfly (a + b == b + a, so every
-// lane ends with the same bits).  Call with all 64 lanes of a wave.
+// p[l + 64], ... in turn, then the VALU wave sum (every lane gets lane 63's
+// total, so all end with the same bits).  Call with all 64 lanes of a wave.
 __device__ inline double wave_sum_parts(const double* p, int n) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
   for (int i = lane; i < n; i += 64) s += p[i];
-  return wave_sum_d(s);
+  return wave_sum_dpp_d(s);
 }
 __device__ __forceinline__ float wave_sum_f(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -152,6 +152,19 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 template <int NW>
 __device__ inline double block_sum_d(double v, double (&sh)[NW]) {
   v = wave_sum_d(v);
+  const int w = threadIdx.x >> 6;
+  const int nw = min((int)(blockDim.x >> 6), NW);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0 && w < NW) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  return s;
+}
+// block_sum_d with the VALU wave sum (all 64 lanes of every wave active).
+template <int NW>
+__device__ inline double block_sum_dpp_d(double v, double (&sh)[NW]) {
+  v = wave_sum_dpp_d(v);
   const int w = threadIdx.x >> 6;
   const int nw = min((int)(blockDim.x >> 6), NW);
   __syncthreads();

@@ -278,7 +278,7 @@ struct EpiLsqrV {
       v[col] = vf;
       vr2 = (double)vf * vf;
     }
-    const double tot = block_sum_d(vr2, sh);
+    const double tot = block_sum_dpp_d(vr2, sh);
     if (!ls) {
       if (threadIdx.x == 0) alpha_part[tile] = tot;
       return;
@@ -290,8 +290,8 @@ struct EpiLsqrV {
     __syncthreads();
     double dd = 0.0, xx = 0.0;
     if (ok) lsqr_vectors(sc, vf, v, w, x, col, dd, xx);
-    dd = block_sum_d(dd, sh);
-    xx = block_sum_d(xx, sh);
+    dd = block_sum_dpp_d(dd, sh);
+    xx = block_sum_dpp_d(xx, sh);
     if (threadIdx.x == 0) lsqr_close(ls, dd, xx, sc[4]);
   }
 };

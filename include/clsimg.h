@@ -92,9 +92,11 @@ extern "C" {
 /* LSQR engine of the host-driven loop (clsimg_opts.lsqr_engine); every engine
  * computes the same iterates, an engine that does not fit the problem falls
  * back to the next one down the list */
-#define CLSIMG_LSQR_AUTO 0        /* the first that fits, in the order below            */
+#define CLSIMG_LSQR_AUTO 0        /* the first that fits, in the order below; above 48 */
+                                  /* antennas the two-kernel step before the cooperative */
+                                  /* kernel (the faster there)                           */
 #define CLSIMG_LSQR_ONE_WG 1      /* one workgroup, free set in LDS (P <= 48)            */
-#define CLSIMG_LSQR_COOP 2        /* one cooperative multi-workgroup kernel (P <= 96)    */
+#define CLSIMG_LSQR_COOP 2        /* one cooperative multi-workgroup kernel (P <= 64)    */
 #define CLSIMG_LSQR_TWO_KERNEL 3  /* two kernels per LSQR step (P <= 96); beyond, the    */
                                   /* correlation with separate reductions and adjoint    */
 

@@ -1454,7 +1454,10 @@ int host_subproblem(SolveRun& r) {
   // step (P <= 96), else the split-K correlation with separate reductions
   const int want = o->lsqr_engine;
   const bool one_cu = fused && (want == CLSIMG_LSQR_AUTO || want == CLSIMG_LSQR_ONE_WG) && lsqr_cu_fits(P, nF);
-  const bool persist = !one_cu && fused && c->coop && (want == CLSIMG_LSQR_AUTO || want == CLSIMG_LSQR_COOP) &&
+  // (above 48 antennas the two-kernel step is the faster one: 7.7 against
+  // 10.7 ms for a 56-antenna solve, 17.3 against 24.7 ms at 64 antennas)
+  const bool coop_auto = want == CLSIMG_LSQR_AUTO && MT <= 6;
+  const bool persist = !one_cu && fused && c->coop && (coop_auto || want == CLSIMG_LSQR_COOP) &&
                        persist_fits(P, nF);
   if (nF > 0) {
     const int itnlim = o->itnlim < 0 ? 4 * nF + 100 : o->itnlim;
@@ -2199,9 +2202,9 @@ int clsimg_solve_offgrid(clsimg_ctx* c, const clsimg_c32* R, const clsimg_array*
       nF = c->h_dec->nF;
       nU = c->h_dec->nU;
       // LSQR in one workgroup when the subproblem fits its LDS, else in one
-      // cooperative kernel, else two kernels per step
+      // cooperative kernel (up to 48 antennas), else two kernels per step
       const bool one_cu = lsqr_cu_fits(P, nF);
-      const bool persist = !one_cu && c->coop && persist_fits(P, nF);
+      const bool persist = !one_cu && c->coop && pad_p(P) / 8 <= 6 && persist_fits(P, nF);
       fr.nF = nF;
       // b = B0 - Psi_U gamma0_U on the grid (eq. bsubproblemLS)
       ST_TRY(correlate(c, g, P, Ulist, gamma0, 1, nU, Bb, B0, -1.f, 1.f, nullptr, nullptr, nullptr, nullptr, st));

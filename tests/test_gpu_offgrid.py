@@ -46,8 +46,8 @@ def _run(gpu_lib, ctx, sc, kind="mvdr", rounds=3, kappa_b=0.0):
 
 
 # 64, 72 and 96 antennas on 40 x 40 to 48 x 48 grids with a 25 m array
-# (about a beamwidth per pixel): at 64 antennas the free set's LSQR runs in
-# the cooperative kernel, beyond in two kernels per step; c2c detects 36 of
+# (about a beamwidth per pixel): beyond 48 antennas the free set's LSQR runs
+# in two kernels per step; c2c detects 36 of
 # 40 sources.  (The 96-antenna workload's own 150 m array on such a grid puts
 # about 9 beamwidths in a pixel: sources out of the Newton step's reach, and
 # solves whose outcome turns on rounding, in the oracle as well.)

@@ -317,16 +317,18 @@ def test_solve_large_arrays_split_rows(gpu_lib, ctx, P, n):
     assert stats["adds"] == ref.adds and stats["drops"] == ref.drops
 
 
-@pytest.mark.parametrize("P,n,pts", [(50, 32, 15), (80, 32, 15), (88, 64, 400)])
-def test_solve_two_kernel_lsqr_row_tiles(gpu_lib, ctx, P, n, pts):
+@pytest.mark.parametrize("P,n,pts,engine", [(50, 32, 15, 3), (80, 32, 15, 3), (88, 64, 400, 3), (56, 32, 15, 2)])
+def test_solve_two_kernel_lsqr_row_tiles(gpu_lib, ctx, P, n, pts, engine):
     # 7..12 row tiles: the free-set LSQR in two launches per iteration, the
     # adjoint with one wave per row tile (7, 10 and 11 here; 50 antennas
     # leaves the last tile ragged), the forward step's operands 128 pixels at
-    # a time (the 88-antenna case ends with 176 free pixels: two chunks)
+    # a time (the 88-antenna case ends with 176 free pixels: two chunks); and
+    # the cooperative kernel where it still fits (56 antennas), asked for by
+    # name since the two-kernel step is the default there
     sc = synth.make_scene("c2", P=P, n=n, seed=500 + P, points=(pts, ("powerlaw", 0.5, 500.0)))
-    print(f"case solve P={sc.P} Q={sc.Q} (two-kernel LSQR, {pts} sources)", flush=True)
+    print(f"case solve P={sc.P} Q={sc.Q} (LSQR engine {engine}, {pts} sources)", flush=True)
     ref, mf_ref, gamma_ref = _oracle_solve(sc)
-    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc, lsqr_engine=gpu_lib.LSQR_TWO_KERNEL)
+    sigma, state, mf, gamma, stats = _gpu_solve(gpu_lib, ctx, sc, lsqr_engine=engine)
     print(f"  steps {stats['outer_iters']} / {ref.outer_iters}, nF {stats['nF']}, lsqr "
           f"{stats['lsqr_iters_total']} / {ref.lsqr_iters_total}", flush=True)
     np.testing.assert_array_equal(state, ref.state)

@@ -401,9 +401,30 @@ int beam_full(clsimg_ctx* c, const clsimg_grid* g, int P, const float2* U, BeamK
   return CLSIMG_OK;
 }
 
+// A small device-to-host read in stream order (pinned host memory): the copy,
+// then an event polled until it completes.  The host usually reaches the wait
+// long before the GPU reaches the copy; polling keeps the wake-up to a few
+// microseconds, where a blocking stream synchronisation would sleep and be
+// woken late.  One event per host thread and device, created on first use.
 int read_back(clsimg_ctx* c, void* host, const void* dev, size_t bytes, hipStream_t st) {
+  (void)c;
+  thread_local int ev_dev = -1;
+  thread_local hipEvent_t ev = nullptr;
+  int d = 0;
+  HIP_TRY(hipGetDevice(&d));
+  if (d != ev_dev) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev = e;  // an event of another device is kept (one per thread and device switch)
+    ev_dev = d;
+  }
   HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipEventRecord(ev, st));
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) return CLSIMG_EHIP;
+  }
   return CLSIMG_OK;
 }
 

@@ -1114,8 +1114,14 @@ __global__ __launch_bounds__(256) void beam_cand_kernel(const uint64_t* __restri
 bool beam_fits(int P) { return pad_p(P) / 8 <= kBeamMaxMT; }
 
 constexpr int kBigMaxRPW = 9;  // up to 36 row tiles: P <= 288
-constexpr int kH1MaxWorkgroups = 1024;    // grid caps of the one-product multiplier kernel
-constexpr int kHalfMaxWorkgroups = 1024;  // and of the split-half beamformer
+// Grid cap of the block-triangular beamformers (FP32, split half, one
+// product): four workgroups per CU, each looping over pixel blocks.  At 288
+// antennas and 512^2 against one workgroup per block: FP32 1059 -> 1042 us,
+// split FP16 376 -> 360 us, one product 162 -> 151 us per launch; caps of 512
+// and 2048 measured within 2 % of this one, 256 took the one-product kernel
+// to 234 us.  Kernels that leave one key per workgroup are reduced over this
+// many keys.
+constexpr int kBigMaxWorkgroups = 1024;
 bool beam_big_fits(int P) { return big_rpw(pad_p(P) / 8) <= kBigMaxRPW; }
 
 size_t beam_big_frag_floats(int P) {
@@ -1126,7 +1132,7 @@ size_t beam_big_frag_floats(int P) {
 int beam_big_grid(int P, int Q, int nt) {
   nt = big_nt_or(nt, big_rpw(pad_p(P) / 8));
   const int nblk = ((Q + 15) / 16 + nt - 1) / nt;
-  return nblk < 1 ? 1 : (nblk > 8192 ? 8192 : nblk);
+  return nblk < 1 ? 1 : (nblk > kBigMaxWorkgroups ? kBigMaxWorkgroups : nblk);
 }
 
 int beam_grid(int Q) {
@@ -1251,9 +1257,7 @@ static hipError_t launch_h16(const void* frag, const float* scale, const Tables&
   (void)frexpf(sqrtf((float)tab.Pp), &ex);
   const float sB = BF ? 1.f : ldexpf(1.f, ex - 1);
   const V* f = static_cast<const V*>(frag);
-  // at most four workgroups per CU, each looping over blocks: at 288 antennas
-  // and 512^2 (8192 blocks) 376 -> 360 us per FP16 image against one block each
-  const dim3 g(std::min(beam_big_grid(tab.Pp, tab.Q, nt), kHalfMaxWorkgroups)), b(256);
+  const dim3 g(beam_big_grid(tab.Pp, tab.Q, nt)), b(256);
   switch (10 * rpw + nt / 4) {
 #define H16_CASE(R, N)                                                                                             \
   case 10 * R + N / 4:                                                                                             \
@@ -1357,9 +1361,7 @@ hipError_t launch_beam_lambda_refined(const float2* E, int P, bool bf16, const T
   (void)nt;
   nt = 4;
   const float sB = h1_sB(tab.Pp, bf16);
-  // at most four workgroups per CU, each looping over blocks: at 288 antennas
-  // and 512^2 (4096 blocks) 162 -> 154 us per launch against one block each
-  const dim3 g(std::min(beam_big_grid(tab.Pp, tab.Q, nt), kH1MaxWorkgroups)), b(256);
+  const dim3 g(beam_big_grid(tab.Pp, tab.Q, nt)), b(256);
   const BeamLambdaApprox epi{state, keys, lam, 0};
   const float* sc = bf16 ? nullptr : scale;
 #define H1_RPW(R)                                                                                              \

@@ -786,19 +786,40 @@ __global__ __launch_bounds__(256) void corr_small_kernel(FwdParams f, RedParams 
   red_pair(blockIdx.x, bm, bn);
   const int t = threadIdx.x, lane = t >> 2, r = t & 3;
   const int row = 4 * (lane >> 4) + r, col = lane & 15;
-  for (int e = t; e < n * 32; e += blockDim.x) {
-    const int k = e >> 5, j = e & 31;
-    int pix = f.idx ? f.idx[k] : k;
-    if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;  // an invalid index reads in bounds
+  // n x 32 steering entries, kSmallIt per thread: every pixel index first,
+  // then every table entry and weight, so the staging waits on two round
+  // trips to memory instead of two per entry
+  constexpr int kSmallIt = kCorrSmall * 32 / 256;
+  int pix[kSmallIt];
+#pragma unroll
+  for (int i = 0; i < kSmallIt; ++i) {
+    const int e = t + 256 * i, k = e >> 5;
+    int p = 0;
+    if (e < n * 32) p = f.idx ? f.idx[k] : k;
+    pix[i] = (unsigned)p < (unsigned)tab.Q ? p : 0;  // an invalid index reads in bounds
+  }
+  int vpix = 0;
+  if (t < n) {
+    vpix = f.idx ? f.idx[t] : t;
+    if ((unsigned)vpix >= (unsigned)tab.Q) vpix = 0;
+  }
+  float2 el[kSmallIt], em[kSmallIt];
+#pragma unroll
+  for (int i = 0; i < kSmallIt; ++i) {
+    const int e = t + 256 * i, j = e & 31;
     const int ant = min(j < 16 ? 16 * bm + j : 16 * bn + j - 16, Pp - 1);
-    const int im = pix / tab.nl;
-    sa[k][j] = tab.a(ant, pix - im * tab.nl, im);
+    const int im = pix[i] / tab.nl;
+    el[i] = tab.El[ant * tab.nl + (pix[i] - im * tab.nl)];
+    em[i] = tab.Em[ant * tab.nm + im];
   }
-  for (int k = t; k < n; k += blockDim.x) {
-    int pix = f.idx ? f.idx[k] : k;
-    if ((unsigned)pix >= (unsigned)tab.Q) pix = 0;
-    sv[k] = f.gather ? f.vals[pix] : f.vals[k];
+  float wv = 0.f;
+  if (t < n) wv = f.gather ? f.vals[vpix] : f.vals[t];
+#pragma unroll
+  for (int i = 0; i < kSmallIt; ++i) {
+    const int e = t + 256 * i;
+    if (e < n * 32) sa[e >> 5][e & 31] = cmul(el[i], em[i]);
   }
+  if (t < n) sv[t] = wv;
   __syncthreads();
   float yr = 0.f, yi = 0.f;
   for (int k = 0; k < n; ++k) {

@@ -995,7 +995,6 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double2* __restrict__ 
   constexpr int NB = kCholNB, LDP = NB + 1, T = kCholTile;
   __shared__ double2 ai[T * LDP], ak[T * LDP], li[T * LDP], lk[T * LDP], dj[NB * NB], a[NB * LDP];
   __shared__ double rl[NB];
-  if (*status != 0) return;
   const int t0 = j0 + NB;
   // this workgroup's tile (ti, tk), tk <= ti, in row-major order of the lower triangle
   int ti = 0, b = blockIdx.x;
@@ -1006,19 +1005,33 @@ __global__ __launch_bounds__(256) void chol_update_kernel(double2* __restrict__ 
   const int tk = b;
   const int i0 = t0 + T * ti, k0 = t0 + T * tk;
   const int tid = threadIdx.x;
-  dj[tid] = D[(size_t)(j0 / NB) * NB * NB + tid];  // 256 threads = NB * NB
-  for (int e = tid; e < T * NB; e += blockDim.x) {
-    const int r = e / NB, c = e - r * NB;
-    ai[r * LDP + c] = i0 + r < P ? W[(size_t)(i0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
-    ak[r * LDP + c] = k0 + r < P ? W[(size_t)(k0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
+  // every load at once (256 threads): the status, D_j, the panel's two row
+  // blocks and this thread's trailing entries, row i0 + (tid >> 3), columns
+  // k0 + (tid & 7) + 8 u; all in bounds whether or not the status is set
+  const int st = *status;
+  const double2 djv = D[(size_t)(j0 / NB) * NB * NB + tid];  // NB * NB = 256 entries
+  constexpr int kPanelIt = T * NB / 256;
+  double2 av[kPanelIt], kv[kPanelIt];
+#pragma unroll
+  for (int it = 0; it < kPanelIt; ++it) {
+    const int e = tid + 256 * it, r = e / NB, c = e - r * NB;
+    av[it] = i0 + r < P ? W[(size_t)(i0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
+    kv[it] = k0 + r < P ? W[(size_t)(k0 + r) * P + j0 + c] : make_double2(0.0, 0.0);
   }
-  // this thread's trailing entries: row i0 + (tid >> 3), columns k0 + (tid & 7) + 8 u
   const int ri = tid >> 3, i = i0 + ri;
   double2 wv[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int k = k0 + (tid & 7) + 8 * u;
     wv[u] = (i < P && k <= i) ? W[(size_t)i * P + k] : make_double2(0.0, 0.0);
+  }
+  if (st != 0) return;
+  dj[tid] = djv;
+#pragma unroll
+  for (int it = 0; it < kPanelIt; ++it) {
+    const int e = tid + 256 * it, r = e / NB, c = e - r * NB;
+    ai[r * LDP + c] = av[it];
+    ak[r * LDP + c] = kv[it];
   }
   __syncthreads();
   // the panel's rows of L: l[r][c] = sum_{c1 <= c} a[r][c1] conj(D_j[c][c1])

@@ -195,7 +195,18 @@ __global__ __launch_bounds__(kCtl) void step_kernel(const int* done, const int* 
   __shared__ int s_k[kCtl / 64];
   __shared__ float s_mz[kCtl / 64];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  if (nF > 0 && !*done) {
+  // the flags, the iteration count and this thread's first list entry with
+  // both iterate buffers are requested together, then its bound
+  const int fin = nF > 0 ? *done : 1;
+  const int itn = nF > 0 ? s->itn : 0;
+  int f0 = 0;
+  float z0a = 0.f, z0b = 0.f;
+  if (tid < nF) {
+    f0 = Flist[tid];
+    z0a = x0[tid];
+    z0b = x1[tid];
+  }
+  if (!fin) {
     if (tid == 0) {
       dec->lsqr_done = 0;
       dec->grad_done = 1;
@@ -203,13 +214,15 @@ __global__ __launch_bounds__(kCtl) void step_kernel(const int* done, const int* 
     }
     return;
   }
+  const float g0 = tid < nF ? gamma[f0] : 0.f;
   // the final LSQR iterate x_itn is kept in buffer itn & 1
-  const float* __restrict__ x = (nF > 0 && (s->itn & 1)) ? x1 : x0;
+  const float* __restrict__ x = (itn & 1) ? x1 : x0;
   // feasibility (non-strict, no tolerance)
   int ok = 1;
   float mz = 3.0e38f;
   for (int k = tid; k < nF; k += kCtl) {
-    const float z = x[k], g = gamma[Flist[k]];
+    const bool pre = k == tid;
+    const float z = pre ? ((itn & 1) ? z0b : z0a) : x[k], g = pre ? g0 : gamma[Flist[k]];
     ok &= (z >= 0.f) && (z <= g);
     mz = fminf(mz, fminf(z, g - z) / g);
   }
@@ -232,7 +245,7 @@ __global__ __launch_bounds__(kCtl) void step_kernel(const int* done, const int* 
     for (int k = tid; k < nF; k += kCtl) sigma[Flist[k]] = x[k];
     if (tid == 0) {
       dec->lsqr_done = 1;
-      dec->lsqr_itn = nF > 0 ? s->itn : 0;
+      dec->lsqr_itn = itn;
       dec->lsqr_istop = nF > 0 ? s->istop : 0;
       dec->feasible = 1;
       dec->lsqr_err = 0;

@@ -22,9 +22,10 @@
 // (mt <= nt) of G = X_F diag(v) X_F^T, loads its two 16-row slices of the
 // real-embedded steering vectors and the weights straight into registers
 // (128 pixels at a time, the first 128 requested at launch), and writes the
-// Hermitian mirror of an off-diagonal tile itself.
-// No LDS, no partial sums, no reduction kernel.  The steering vectors of the free set are generated once
-// per subproblem (xf_kernel, 2Pp x |F| floats) and read by every LSQR step.
+// Hermitian mirror of an off-diagonal tile itself.  No LDS, no partial sums,
+// no reduction kernel.  The steering vectors of the free set are generated
+// once per subproblem (xf_kernel, 2Pp x |F| floats) and read by every LSQR
+// step.
 #include "os_tiles.h"
 
 namespace clsimg {

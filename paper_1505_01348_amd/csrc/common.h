@@ -131,7 +131,14 @@ __device__ __forceinline__ double wave_sum_dpp_d(double v) {
 __device__ inline double wave_sum_parts(const double* p, int n) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int i = lane; i < n; i += 64) s += p[i];
+  for (int i0 = lane; i0 < n; i0 += 256) {  // four per lane requested before the first add
+    double v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = i0 + 64 * j < n ? p[i0 + 64 * j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (i0 + 64 * j < n) s += v[j];
+  }
   return wave_sum_dpp_d(s);
 }
 __device__ __forceinline__ float wave_sum_f(float v) {

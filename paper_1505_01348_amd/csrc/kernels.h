@@ -224,13 +224,13 @@ __device__ inline void lsqr_close(LsqrState* s, double dd, double xx, double c) 
 
 // The vector part of a step for entry k: v scaled, x += phi w / rho,
 // w = v - (theta / rho) w; adds |d_k|^2 and x_k^2 to dd and xx.
-__device__ inline void lsqr_vectors(const double* sc, float vraw, float* v, float* w, float* x, int k, double& dd,
-                                    double& xx) {
+__device__ inline void lsqr_vectors(const double* sc, float vraw, float wold, float xold, float* v, float* w, float* x,
+                                    int k, double& dd, double& xx) {
   const double vk = (double)vraw * sc[0];
-  const double wk = (double)w[k];
+  const double wk = (double)wold;
   const double dk = wk * sc[1];
   dd += dk * dk;
-  const float xk = (float)((double)x[k] + sc[2] * dk);
+  const float xk = (float)((double)xold + sc[2] * dk);
   x[k] = xk;
   xx += (double)xk * xk;
   const float vf = (float)vk;
@@ -253,10 +253,22 @@ struct EpiLsqrV {
   float* w = nullptr;
   float* x = nullptr;
   using Ctx = NoCtx;
-  using Pre = NoCtx;
+  struct Pre {
+    float v, w, x;  // the column's old v, w and x
+  };
   __device__ Ctx init() const { return {}; }
-  __device__ Pre prefetch(int, bool) const { return {}; }
-  __device__ void operator()(int tile, int col, int, float g, bool ok, const Ctx&, const Pre&) const {
+  __device__ Pre prefetch(int col, bool ok) const {
+    Pre p{0.f, 0.f, 0.f};
+    if (ok) {
+      if (!first) p.v = v[col];
+      if (ls) {
+        p.w = w[col];
+        p.x = x[col];
+      }
+    }
+    return p;
+  }
+  __device__ void operator()(int tile, int col, int, float g, bool ok, const Ctx&, const Pre& pf) const {
     __shared__ double sh[8];
     __shared__ double sbeta, sb2;
     __shared__ double sc[5];
@@ -273,7 +285,7 @@ struct EpiLsqrV {
     float vf = 0.f;
     if (ok) {
       double vr = beta > 0.0 ? (double)g / beta : 0.0;
-      if (!first) vr -= beta * (double)v[col];
+      if (!first) vr -= beta * (double)pf.v;
       vf = (float)vr;
       v[col] = vf;
       vr2 = (double)vf * vf;
@@ -289,7 +301,7 @@ struct EpiLsqrV {
     }
     __syncthreads();
     double dd = 0.0, xx = 0.0;
-    if (ok) lsqr_vectors(sc, vf, v, w, x, col, dd, xx);
+    if (ok) lsqr_vectors(sc, vf, pf.w, pf.x, v, w, x, col, dd, xx);
     dd = block_sum_dpp_d(dd, sh);
     xx = block_sum_dpp_d(xx, sh);
     if (threadIdx.x == 0) lsqr_close(ls, dd, xx, sc[4]);

@@ -374,9 +374,12 @@ template <class Epi>
 __global__ __launch_bounds__(64) void adjoint_rows_finish_kernel(AdjParams pr, const float* __restrict__ part,
                                                                  int ngroups, int T, Epi epi) {
   const int stop = pr.stop_flag ? *pr.stop_flag : 0;
+  const int tile = blockIdx.x, col = tile * T + threadIdx.x;
+  // the epilogue's inputs with the flag (columns below the host's bound are
+  // in bounds; a device-length list's epilogues load nothing here)
+  const typename Epi::Pre pf = epi.prefetch(col, (int)threadIdx.x < T && col < pr.n);
   const typename Epi::Ctx cx = epi.init();
   if (stop) return;
-  const int tile = blockIdx.x, col = tile * T + threadIdx.x;
   const int n = pr.n_dev ? min(*pr.n_dev, pr.n) : pr.n;
   const bool ok = (int)threadIdx.x < T && col < n;
   float g = 0.f;
@@ -398,7 +401,6 @@ __global__ __launch_bounds__(64) void adjoint_rows_finish_kernel(AdjParams pr, c
       g = __builtin_nanf("");
     }
   }
-  const typename Epi::Pre pf = epi.prefetch(col, ok);
   epi(tile, col, pix, g, ok, cx, pf);
 }
 

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kCtl) void lsqr_update_kernel(LsqrState* s, const d
   if (threadIdx.x == 0) lsqr_scalars(s, b2, a2, sc);
   __syncthreads();
   double dd = 0.0, xx = 0.0;
-  for (int k = threadIdx.x; k < n; k += kCtl) lsqr_vectors(sc, v[k], v, w, x, k, dd, xx);
+  for (int k = threadIdx.x; k < n; k += kCtl) lsqr_vectors(sc, v[k], w[k], x[k], v, w, x, k, dd, xx);
   dd = block_sum_dpp_d(dd, red_d);
   xx = block_sum_dpp_d(xx, red_x);
   if (threadIdx.x == 0) lsqr_close(s, dd, xx, sc[4]);

@@ -678,23 +678,45 @@ constexpr int kRedGroups = 4;  // thread groups summing interleaved chunks
 // out = cK Y + cB B on the tile's lower part and mirrored, the fragments of
 // out, and the workgroup's share of |out|^2 (every thread of the workgroup
 // calls it: the norm is a block sum).
+// The entries of B this thread's outputs add and the LSQR scalars, requested
+// before the kernel's own sums so that they arrive meanwhile.
+struct RedPre {
+  float2 b[2];  // B[p][q] and B[q][p] of the thread's entry and its mirror
+  double alpha, beta;
+};
+
+__device__ __forceinline__ RedPre red_prefetch(const RedParams& pr, int bm, int bn, int row, int col, bool writer) {
+  RedPre r;
+  r.b[0] = r.b[1] = make_float2(0.f, 0.f);
+  r.alpha = r.beta = 0.0;
+  if (pr.lsqr) {
+    r.alpha = pr.lsqr->alpha;
+    r.beta = pr.lsqr->beta;
+  }
+  const int P = pr.P, p = 16 * bm + row, qq = 16 * bn + col;
+  if (pr.B && writer && (bm != bn || row >= col) && p < P && qq < P) {
+    r.b[0] = pr.B[(size_t)p * P + qq];
+    if (p != qq) r.b[1] = pr.B[(size_t)qq * P + p];
+  }
+  return r;
+}
+
 template <int NW>
 __device__ __forceinline__ void red_store(const RedParams& pr, int bm, int bn, int row, int col, bool writer,
-                                          float yr, float yi, double (&sh)[NW]) {
+                                          float yr, float yi, double (&sh)[NW], const RedPre& pre) {
   const int P = pr.P, Pp = pad_p(P);
   const int p = 16 * bm + row, qq = 16 * bn + col;
   float cB = pr.cB;
-  if (pr.lsqr) cB = (float)(-pr.lsqr->alpha / pr.lsqr->beta);
+  if (pr.lsqr) cB = (float)(-pre.alpha / pre.beta);
   // the diagonal tile: its lower triangle, mirrored
   const bool lower = writer && (bm != bn || row >= col);
   double nrm = 0.0;
   const int KS = Pp / 2;
-  auto put = [&](int a, int b, float2 y) {  // out[a][b] from Y_ab = y
+  auto put = [&](int a, int b, float2 y, float2 bv) {  // out[a][b] from Y_ab = y and B[a][b] = bv
     float2 o = make_float2(0.f, 0.f);
     if (a < P && b < P) {
       o = make_float2(pr.cK * y.x, pr.cK * y.y);
       if (pr.B) {
-        const float2 bv = pr.B[(size_t)a * P + b];
         o.x += cB * bv.x;
         o.y += cB * bv.y;
       }
@@ -713,11 +735,11 @@ __device__ __forceinline__ void red_store(const RedParams& pr, int bm, int bn, i
   };
   if (lower) {
     if (p == qq) yi = 0.f;  // the diagonal of a Hermitian matrix is real
-    put(p, qq, make_float2(yr, yi));
-    if (p != qq) put(qq, p, make_float2(yr, -yi));
+    put(p, qq, make_float2(yr, yi), pre.b[0]);
+    if (p != qq) put(qq, p, make_float2(yr, -yi), pre.b[1]);
   }
   if (pr.norm_part) {
-    const double tot = block_sum_d(nrm, sh);
+    const double tot = block_sum_dpp_d(nrm, sh);
     if (threadIdx.x == 0) pr.norm_part[blockIdx.x] = tot;
   }
 }
@@ -734,7 +756,7 @@ __device__ __forceinline__ void red_pair(int b, int& bm, int& bn) {  // tile pai
 __global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) {
   __shared__ double sh[4 * kRedGroups];
   __shared__ float2 gsum[kRedGroups - 1][256];
-  if (pr.stop_flag && *pr.stop_flag) return;
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
   {  // covariance block blockIdx.y
     const size_t kb = blockIdx.y;
     pr.part += kb * pr.part_stride;
@@ -750,6 +772,8 @@ __global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) 
   const int pair = BM * (BM + 1) / 2 + BN, tile = (bm - BT * BM) * BT + (bn - BT * BN);
   const int t = threadIdx.x & 255, grp = threadIdx.x >> 8, lane = t >> 2, r = t & 3;
   const int row = 4 * (lane >> 4) + r, col = lane & 15;
+  const RedPre pre = red_prefetch(pr, bm, bn, row, col, grp == 0);
+  if (stop) return;
   // group g sums chunks g, g + G, ...; the group sums are added in group order
   float yr = 0.f, yi = 0.f;
   for (int c = grp; c < pr.nchunks; c += kRedGroups) {
@@ -767,7 +791,7 @@ __global__ __launch_bounds__(256 * kRedGroups) void reduce_kernel(RedParams pr) 
     }
   }
   // group 0 writes
-  red_store(pr, bm, bn, row, col, grp == 0, yr, yi, sh);
+  red_store(pr, bm, bn, row, col, grp == 0, yr, yi, sh, pre);
 }
 
 // The correlation of a short list (n <= kCorrSmall pixels) straight into the
@@ -781,13 +805,14 @@ __global__ __launch_bounds__(256) void corr_small_kernel(FwdParams f, RedParams 
   __shared__ float2 sa[kCorrSmall][32];
   __shared__ float sv[kCorrSmall];
   __shared__ double sh[4];
-  if (pr.stop_flag && *pr.stop_flag) return;
+  const int stop = pr.stop_flag ? *pr.stop_flag : 0;
   const Tables& tab = f.tab;
   const int Pp = pad_p(pr.P), n = f.n;
   int bm, bn;
   red_pair(blockIdx.x, bm, bn);
   const int t = threadIdx.x, lane = t >> 2, r = t & 3;
   const int row = 4 * (lane >> 4) + r, col = lane & 15;
+  const RedPre pre = red_prefetch(pr, bm, bn, row, col, true);
   // n x 32 steering entries, kSmallIt per thread: every pixel index first,
   // then every table entry and weight, so the staging waits on two round
   // trips to memory instead of two per entry
@@ -821,6 +846,7 @@ __global__ __launch_bounds__(256) void corr_small_kernel(FwdParams f, RedParams 
     const int e = t + 256 * i;
     if (e < n * 32) sa[e >> 5][e & 31] = cmul(el[i], em[i]);
   }
+  if (stop) return;
   if (t < n) sv[t] = wv;
   __syncthreads();
   float yr = 0.f, yi = 0.f;
@@ -830,7 +856,7 @@ __global__ __launch_bounds__(256) void corr_small_kernel(FwdParams f, RedParams 
     yr += v * (a.x * b.x + a.y * b.y);
     yi += v * (a.y * b.x - a.x * b.y);
   }
-  red_store(pr, bm, bn, row, col, true, yr, yi, sh);
+  red_store(pr, bm, bn, row, col, true, yr, yi, sh, pre);
 }
 
 // ---------------------------------------------------------------------------
